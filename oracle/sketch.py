@@ -1,0 +1,104 @@
+"""The two sketches Y = A Omega (m x s) and W = Psi A (l x n) (Section 4.1,
+eq. Y=AOmegaW=PsiA), formed by linear updates over column blocks of A
+(Section 4, opening, and Section 5.3: the sketches are updated as data
+arrive, without revisiting A).
+
+For an update that adds H to the columns J of A (A[:, J] += H):
+    Y      += H Omega[J, :]
+    W[:, J] += Psi H
+Both are plain Hamilton products (``quaternion.hamilton``) in FP64.
+
+Low-precision emulation: when the sketch runs on low-precision operands, the
+oracle forms the exact operand values the device uses (``lowprec``) and then
+computes the same products in FP64, so that any difference from the device
+is the device's accumulation error alone.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import embeddings, lowprec, quaternion as qt
+
+
+class SketchConfig:
+    """m, n: A in Q^{m x n}; k, l: sketch sizes (paper s, l), r <= s <= l
+    (Section 4.1); embedding 'gaussian' or 'rademacher'; dtype of the sketch
+    operands 'f64' | 'f32' | 'bf16' | 'fp8'; terms: number of bf16 terms of
+    the residual split of the data (bf16 only); fp8_block: tile edge of the
+    power-of-two fp8 scales; fp8_residual: add the exact FP32 residual of
+    the fp8 quantisation as a second term."""
+
+    def __init__(self, m, n, k, l, seed=0, embedding="gaussian", dtype="f64",
+                 terms=1, fp8_block=32, fp8_residual=True):
+        if not (1 <= k <= l <= min(m, n)):
+            raise ValueError("need 1 <= k <= l <= min(m, n)")
+        self.m, self.n, self.k, self.l = int(m), int(n), int(k), int(l)
+        self.seed = int(seed)
+        self.embedding = embedding
+        self.dtype = dtype
+        self.terms = int(terms)
+        self.fp8_block = int(fp8_block)
+        self.fp8_residual = bool(fp8_residual)
+
+
+def data_operand(block, cfg):
+    """The value of a block of A that the sketch multiplies, per the operand
+    format: FP64/FP32 data as given; bf16: sum of the split terms; fp8: the
+    dequantised block (plus the exact residual when enabled)."""
+    block = qt.as_planes(block)
+    if cfg.dtype in ("f64", "f32"):
+        return block
+    if cfg.dtype == "bf16":
+        return sum(lowprec.split_bf16(block, cfg.terms))
+    if cfg.dtype == "fp8":
+        out = np.empty_like(block)
+        for p in range(4):
+            deq, _ = lowprec.quantize_e4m3_blocks(block[p], cfg.fp8_block, cfg.fp8_block)
+            out[p] = deq + (block[p] - deq if cfg.fp8_residual else 0.0)
+        return out
+    raise ValueError(cfg.dtype)
+
+
+class Sketch:
+    """Streaming state (Y, W) of the one-pass algorithm."""
+
+    def __init__(self, cfg: SketchConfig):
+        self.cfg = cfg
+        self.Y = qt.zeros(cfg.m, cfg.k)
+        self.W = qt.zeros(cfg.l, cfg.n)
+        self.columns_seen = 0
+        self._psi = None
+
+    def psi(self):
+        """Psi (l x m) as the sketch uses it (rounded to the operand dtype)."""
+        if self._psi is None:
+            c = self.cfg
+            self._psi = embeddings.psi(c.embedding, c.l, np.arange(c.m), c.seed, c.dtype)
+        return self._psi
+
+    def omega_rows(self, col0, ncols):
+        c = self.cfg
+        return embeddings.omega(c.embedding, np.arange(col0, col0 + ncols), c.k, c.seed, c.dtype)
+
+    def update(self, col0, block):
+        """A[:, col0:col0+ncols] += block (a linear update), so
+        Y += block Omega[J, :] and W[:, J] += Psi block."""
+        block = qt.as_planes(block)
+        c = self.cfg
+        ncols = block.shape[2]
+        if block.shape[1] != c.m or col0 < 0 or col0 + ncols > c.n:
+            raise ValueError("block out of range")
+        a = data_operand(block, c)
+        self.Y += qt.hamilton(a, self.omega_rows(col0, ncols))
+        self.W[:, :, col0:col0 + ncols] += qt.hamilton(self.psi(), a)
+        self.columns_seen += ncols
+
+
+def sketch_matrix(a, cfg, block_cols=None):
+    """Sketch a whole matrix by streaming it in column blocks."""
+    a = qt.as_planes(a)
+    s = Sketch(cfg)
+    bc = block_cols or a.shape[2]
+    for c0 in range(0, a.shape[2], bc):
+        s.update(c0, a[:, :, c0:c0 + bc])
+    return s
