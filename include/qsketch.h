@@ -1,0 +1,172 @@
+/*
+ * qsketch: one-pass randomized quaternion low-rank approximation on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: C. Chang and Y. Yang, "Randomized large-scale quaternion matrix
+ * approximation: practical rangefinders and one-pass algorithm",
+ * arXiv:2404.14783.  For A in Q^{m x n} and sketch sizes r <= k <= l <=
+ * min(m, n) (the paper's s is k here; Section 4.1), two independent random
+ * test matrices Omega (n x k) and Psi (l x m) give the sketches
+ *     Y = A Omega  (m x k)   and   W = Psi A  (l x n)        (Section 4.1)
+ * formed by linear updates of column blocks, so that A is read once and never
+ * stored (Section 4, opening; Section 5.3).  A rangefinder maps Y to Q (the
+ * paper's H, Algs. 1 and 3) and the core solve gives X = (Psi Q)^dagger W
+ * (Alg. 4, through Alg. 2), so that A ~ Q X.
+ *
+ * Conventions for every entry point:
+ *  - A quaternion matrix M = M_w + M_x i + M_y j + M_z k is passed as four
+ *    real planes {w, x, y, z}, each column-major with a leading dimension:
+ *    element (r, c) of plane p is planes[p][r + c * ld].
+ *  - Matrix pointers are HIP device pointers on the device that was current
+ *    when qsketch_init ran.  Sizes and scalars are host values.
+ *  - Calls are stream-ordered on the stream given to qsketch_init and return
+ *    before the GPU has finished, except where stated.  The caller keeps every
+ *    buffer alive until the stream has passed the call.
+ *  - The caller owns its inputs and outputs; the context owns the sketches and
+ *    all workspace, allocated in qsketch_init (update and finalize allocate
+ *    nothing).
+ *  - On QSK_E_ARG nothing has happened.  A HIP failure returns QSK_E_HIP and
+ *    poisons the context: every later call except qsketch_destroy,
+ *    qsketch_last_error and qsketch_strerror returns QSK_E_STATE.
+ *  - One context belongs to one stream; calls on one context must not
+ *    overlap (the API is not re-entrant per context).
+ */
+#ifndef QSKETCH_H
+#define QSKETCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qsk_ctx qsk_ctx;
+
+typedef enum {
+  QSK_OK = 0,
+  QSK_E_ARG = 1,          /* invalid argument; no side effects */
+  QSK_E_STATE = 2,        /* context poisoned or destroyed */
+  QSK_E_NOMEM = 3,        /* device allocation failed in qsketch_init */
+  QSK_E_HIP = 4,          /* a HIP runtime call failed; context poisoned */
+  QSK_E_NUMERIC = 5,      /* no Q/X could be formed (e.g. Y == 0) */
+  QSK_E_UNSUPPORTED = 6   /* valid but not implemented combination */
+} qsk_status;
+
+/* Element formats.  input_dtype: the planes passed to qsketch_update.
+   sketch_dtype: the operands of the sketch products:
+     QSK_F64  FP64 data and test matrices, FP64 accumulation, FP64 Y/W;
+     QSK_F32  FP32 data, test matrices rounded to FP32, FP32 matrix-core
+              products with FP32 accumulation, FP32 Y/W;
+     QSK_BF16 data split into split_terms bf16 terms (hi, mid, lo: each term
+              rounds what the previous ones left), test matrices rounded to
+              bf16 once from their FP64 value, FP32 accumulation, FP32 Y/W;
+     QSK_FP8_E4M3 data quantised to OCP fp8 e4m3 with a power-of-two scale per
+              32 x 32 tile of each plane, optionally plus the exact FP32
+              residual as a second term (split_terms = 2), test matrices
+              rounded to e4m3 once from their FP64 value, FP32 accumulation. */
+typedef enum { QSK_F64 = 0, QSK_F32 = 1, QSK_BF16 = 2, QSK_FP8_E4M3 = 3 } qsk_dtype;
+
+/* Test-matrix distributions: quaternion standard Gaussian, all four
+   components i.i.d. N(0,1) (Def. 4.1); quaternion Rademacher, components
+   i.i.d. +-1 (a centred unit-variance sub-Gaussian matrix, Def. 4.2). */
+typedef enum { QSK_GAUSSIAN = 0, QSK_RADEMACHER = 1 } qsk_embedding;
+
+/* Rangefinders (Section 3): pseudo-QR with correction steps (Alg. 1,
+   non-orthonormal, well conditioned) and pseudo-SVD (Alg. 3, orthonormal). */
+typedef enum { QSK_PSEUDO_QR = 0, QSK_PSEUDO_SVD = 1 } qsk_rangefinder;
+
+/* Report flags (numeric events are flags, not errors). */
+enum {
+  QSK_FLAG_CHOL_FALLBACK = 1,   /* Gram Cholesky broke down: shifted 3-pass CholeskyQR used */
+  QSK_FLAG_RANK_DEFICIENT = 2,  /* Q*Q (or (Psi Q)*(Psi Q)) singular: corrections skipped */
+  QSK_FLAG_NONFINITE = 4,       /* a non-finite value met in the sketches */
+  QSK_FLAG_BAD_PAIRS = 8        /* pseudo-SVD repaired t_bad > 0 singular pairs */
+};
+
+typedef struct {
+  int64_t m, n;            /* A in Q^{m x n}; 1 <= m, n < 2^31 */
+  int32_t k, l;            /* sketch sizes, 1 <= k <= l <= min(m, n), k <= 256, l <= 1024 */
+  uint64_t seed;           /* Philox4x32-10 key (seed mod 2^32, seed >> 32) */
+  int32_t embedding;       /* qsk_embedding */
+  int32_t input_dtype;     /* QSK_F64 | QSK_F32 | QSK_BF16 */
+  int32_t sketch_dtype;    /* qsk_dtype, see above */
+  int32_t pure;            /* 1: A has no real part; planes[0] is ignored (may be NULL) */
+  int32_t split_terms;     /* BF16: 1..3; FP8: 1 or 2 (2 = add FP32 residual term) */
+  int32_t n_correction;    /* pseudo-QR correction steps, 0..8 (paper: "often 3") */
+  int32_t n_power;         /* power iterates per correction step for eps (paper: 2-3) */
+  int64_t max_block_cols;  /* largest ncols of one update; 0 means n */
+} qsk_config;
+
+typedef struct {
+  double kappa;            /* kappa(Q) = sigma_max / sigma_min of the returned Q */
+  double kappa_initial;    /* pseudo-QR: kappa of the raw factor before correction (inf if singular) */
+  double eps[8];           /* pseudo-QR: eps of each correction step */
+  int32_t n_eps;
+  int32_t t_bad;           /* pseudo-SVD: number of repaired pairs */
+  int32_t flags;           /* QSK_FLAG_* */
+  int32_t passes;          /* CholeskyQR passes used on Y */
+  int64_t columns_seen;    /* total columns passed to qsketch_update */
+  double orth_defect;      /* ||Q*Q - I||_max (pseudo-SVD; 0 for pseudo-QR) */
+} qsk_report;
+
+/* Fill cfg with defaults: k, l, m, n zero (must be set), seed 0, Gaussian,
+   FP64 in and out, split_terms 1, n_correction 3, n_power 3. */
+void qsketch_config_default(qsk_config *cfg);
+
+/* Validate cfg, allocate Y, W (zeroed) and all workspace on the current
+   device, bind the context to hip_stream (a hipStream_t; NULL = default
+   stream).  Synchronous.  Returns QSK_E_ARG for an invalid cfg,
+   QSK_E_NOMEM if device memory is short. */
+qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out);
+
+/* Linear update A[:, col0 : col0 + ncols) += H (Section 4, opening), where
+   H is the m x ncols quaternion block in planes[0..3] (input_dtype, column-
+   major, leading dimension ld >= m):
+       Y += H Omega[col0 : col0 + ncols, :],   W[:, col0 : col0 + ncols] += Psi H.
+   Overlapping or repeated column ranges are legal (the update is linear).
+   Requires 0 <= col0, 1 <= ncols <= max_block_cols, col0 + ncols <= n. */
+qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols,
+                          const void *const planes[4], int64_t ld);
+
+/* QB stage (Alg. 4) on the current sketches, in FP64 on the device:
+   Q = F(Y) with F the chosen rangefinder (Alg. 1 or Alg. 3), then
+   X = (Psi Q)^dagger W by least squares (Alg. 2), with Psi regenerated to the
+   exact values that formed W.  Q: m x k FP64 planes (ldq >= m); X: k x n FP64
+   planes (ldx >= k).  Non-destructive: may be called again (either
+   rangefinder) and interleaved with further updates.  Synchronises the stream
+   before returning (to read the report); report may be NULL. */
+qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf,
+                            double *const Q[4], int64_t ldq,
+                            double *const X[4], int64_t ldx,
+                            qsk_report *report);
+
+/* Copy the current sketches out (Y: m x k, W: l x n) as FP64 planes, for
+   tests and checkpoints.  Y or W may be NULL to skip it. */
+qsk_status qsketch_sketches(qsk_ctx *ctx, double *const Y[4], int64_t ldy,
+                            double *const W[4], int64_t ldw);
+
+/* Y = 0, W = 0, columns_seen = 0 (stream-ordered). */
+qsk_status qsketch_reset(qsk_ctx *ctx);
+
+/* Relative error ||A - Q X||_F / ||A||_F (Section 5.1) of an approximation,
+   with A given as planes in input_dtype format of ctx (ld >= m) and Q, X as
+   FP64 planes from qsketch_finalize.  A measurement pass, not part of the
+   one-pass method (it reads A again).  Synchronous; result in *err. */
+qsk_status qsketch_rel_error(qsk_ctx *ctx, const void *const A[4], int64_t lda,
+                             double *const Q[4], int64_t ldq,
+                             double *const X[4], int64_t ldx, double *err);
+
+/* Stream (hipStream_t) of the context. */
+void *qsketch_stream(const qsk_ctx *ctx);
+
+/* Free everything.  Always valid, also on a poisoned context; NULL is a no-op. */
+void qsketch_destroy(qsk_ctx *ctx);
+
+const char *qsketch_strerror(qsk_status s);
+const char *qsketch_last_error(const qsk_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSKETCH_H */

@@ -1,0 +1,245 @@
+"""Python binding of the qsketch C ABI (include/qsketch.h).
+
+Argument marshalling only: every step of the sketch and of the QB stage runs in
+the HIP kernels of ``libqsketch.so``; PyTorch supplies device memory and the
+stream.  The library must have been built (``paper_2404_14783_amd.build``);
+importing this module fails loudly if it is missing.
+
+Quaternion matrices are torch tensors of shape (4, rows, cols) (planes w, x,
+y, z), or (3, rows, cols) for a pure quaternion (planes x, y, z), whose planes
+are column-major: ``t.stride(1) == 1``.  ``qempty`` and ``to_colmajor`` make
+such tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqsketch.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "qsketch.h")
+
+QSK_OK, QSK_E_ARG, QSK_E_STATE, QSK_E_NOMEM, QSK_E_HIP, QSK_E_NUMERIC, QSK_E_UNSUPPORTED = range(7)
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
+EMBEDDINGS = {"gaussian": 0, "rademacher": 1}
+RANGEFINDERS = {"pseudo_qr": 0, "pseudo_svd": 1}
+FLAG_NAMES = {1: "chol_fallback", 2: "rank_deficient", 4: "nonfinite", 8: "bad_pairs"}
+TORCH_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
+
+
+class QskConfig(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+        ("k", ctypes.c_int32), ("l", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("embedding", ctypes.c_int32), ("input_dtype", ctypes.c_int32),
+        ("sketch_dtype", ctypes.c_int32), ("pure", ctypes.c_int32),
+        ("split_terms", ctypes.c_int32), ("n_correction", ctypes.c_int32),
+        ("n_power", ctypes.c_int32), ("max_block_cols", ctypes.c_int64),
+    ]
+
+
+class QskReport(ctypes.Structure):
+    _fields_ = [
+        ("kappa", ctypes.c_double), ("kappa_initial", ctypes.c_double),
+        ("eps", ctypes.c_double * 8), ("n_eps", ctypes.c_int32),
+        ("t_bad", ctypes.c_int32), ("flags", ctypes.c_int32), ("passes", ctypes.c_int32),
+        ("columns_seen", ctypes.c_int64), ("orth_defect", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {
+            "kappa": self.kappa, "kappa_initial": self.kappa_initial,
+            "eps": [self.eps[i] for i in range(self.n_eps)], "t_bad": self.t_bad,
+            "flags": [v for b, v in FLAG_NAMES.items() if self.flags & b],
+            "passes": self.passes, "columns_seen": self.columns_seen,
+            "orth_defect": self.orth_defect,
+        }
+
+
+_P4 = ctypes.c_void_p * 4
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"qsketch: {LIB_PATH} is not built; run `python -m paper_2404_14783_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.qsketch_config_default.argtypes = [ctypes.POINTER(QskConfig)]
+    lib.qsketch_config_default.restype = None
+    lib.qsketch_init.argtypes = [ctypes.POINTER(QskConfig), vp, ctypes.POINTER(vp)]
+    lib.qsketch_init.restype = i32
+    lib.qsketch_update.argtypes = [vp, i64, i64, _P4, i64]
+    lib.qsketch_update.restype = i32
+    lib.qsketch_finalize.argtypes = [vp, i32, _P4, i64, _P4, i64, ctypes.POINTER(QskReport)]
+    lib.qsketch_finalize.restype = i32
+    lib.qsketch_sketches.argtypes = [vp, _P4, i64, _P4, i64]
+    lib.qsketch_sketches.restype = i32
+    lib.qsketch_reset.argtypes = [vp]
+    lib.qsketch_reset.restype = i32
+    lib.qsketch_rel_error.argtypes = [vp, _P4, i64, _P4, i64, _P4, i64, ctypes.POINTER(ctypes.c_double)]
+    lib.qsketch_rel_error.restype = i32
+    lib.qsketch_stream.argtypes = [vp]
+    lib.qsketch_stream.restype = vp
+    lib.qsketch_destroy.argtypes = [vp]
+    lib.qsketch_destroy.restype = None
+    lib.qsketch_strerror.argtypes = [i32]
+    lib.qsketch_strerror.restype = ctypes.c_char_p
+    lib.qsketch_last_error.argtypes = [vp]
+    lib.qsketch_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def header_functions():
+    """Names of the functions declared in include/qsketch.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(qsketch_[a-z_]+)\s*\(", text)))
+
+
+class QSketchError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"qsketch status {status}: {msg}")
+        self.status = status
+
+
+def qempty(planes, rows, cols, dtype, device):
+    """Tensor (planes, rows, cols) with column-major planes."""
+    return torch.empty((planes, cols, rows), dtype=dtype, device=device).transpose(1, 2)
+
+
+def qzeros(planes, rows, cols, dtype, device):
+    return torch.zeros((planes, cols, rows), dtype=dtype, device=device).transpose(1, 2)
+
+
+def to_colmajor(t):
+    """Copy of a (P, rows, cols) tensor with column-major planes (no copy if it has them)."""
+    if t.stride(1) == 1 and t.stride(2) >= t.shape[1]:
+        return t
+    return t.transpose(1, 2).contiguous().transpose(1, 2)
+
+
+def _plane_ptrs(t, pure):
+    if t.dim() != 3 or t.stride(1) != 1:
+        raise ValueError("quaternion tensor must be (P, rows, cols) with column-major planes")
+    ld = t.stride(2) if t.shape[2] > 1 else max(t.shape[1], 1)
+    if pure:
+        if t.shape[0] != 3:
+            raise ValueError("pure quaternion input must have 3 planes (x, y, z)")
+        ptrs = [None] + [t[p].data_ptr() for p in range(3)]
+    else:
+        if t.shape[0] != 4:
+            raise ValueError("quaternion input must have 4 planes (w, x, y, z)")
+        ptrs = [t[p].data_ptr() for p in range(4)]
+    return _P4(*ptrs), ld
+
+
+class Sketcher:
+    """One-pass sketch state (Y, W) of A in Q^{m x n}, on the current CUDA
+    (HIP) device and stream."""
+
+    def __init__(self, m, n, k, l, seed=0, embedding="gaussian", input_dtype="f64",
+                 sketch_dtype="f64", pure=False, split_terms=1, n_correction=3, n_power=3,
+                 max_block_cols=0, stream=None):
+        lib = _load()
+        cfg = QskConfig()
+        lib.qsketch_config_default(ctypes.byref(cfg))
+        cfg.m, cfg.n, cfg.k, cfg.l = int(m), int(n), int(k), int(l)
+        cfg.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+        cfg.embedding = EMBEDDINGS[embedding]
+        cfg.input_dtype = DTYPES[input_dtype]
+        cfg.sketch_dtype = DTYPES[sketch_dtype]
+        cfg.pure = 1 if pure else 0
+        cfg.split_terms = int(split_terms)
+        cfg.n_correction = int(n_correction)
+        cfg.n_power = int(n_power)
+        cfg.max_block_cols = int(max_block_cols)
+        self.m, self.n, self.k, self.l = cfg.m, cfg.n, cfg.k, cfg.l
+        self.pure = bool(pure)
+        self.input_dtype = input_dtype
+        self.sketch_dtype = sketch_dtype
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._ctx = ctypes.c_void_p()
+        st = lib.qsketch_init(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
+                              ctypes.byref(self._ctx))
+        if st != QSK_OK:
+            raise QSketchError(st, lib.qsketch_strerror(st).decode())
+        self._lib = lib
+
+    def _check(self, st):
+        if st != QSK_OK:
+            msg = self._lib.qsketch_last_error(self._ctx).decode() or self._lib.qsketch_strerror(st).decode()
+            raise QSketchError(st, msg)
+
+    def update(self, col0, block):
+        """A[:, col0 : col0 + ncols] += block (planes column-major, input dtype)."""
+        if block.dtype != TORCH_DTYPE[self.input_dtype]:
+            raise TypeError(f"block dtype {block.dtype} != input dtype {self.input_dtype}")
+        ptrs, ld = _plane_ptrs(block, self.pure)
+        self._check(self._lib.qsketch_update(self._ctx, int(col0), int(block.shape[2]), ptrs, ld))
+
+    def finalize(self, rangefinder="pseudo_qr", q=None, x=None):
+        """QB stage: returns (Q, X, report) with Q (4, m, k) and X (4, k, n) FP64."""
+        if q is None:
+            q = qempty(4, self.m, self.k, torch.float64, self.device)
+        if x is None:
+            x = qempty(4, self.k, self.n, torch.float64, self.device)
+        qp, ldq = _plane_ptrs(q, False)
+        xp, ldx = _plane_ptrs(x, False)
+        rep = QskReport()
+        self._check(self._lib.qsketch_finalize(self._ctx, RANGEFINDERS[rangefinder], qp, ldq, xp, ldx,
+                                               ctypes.byref(rep)))
+        return q, x, rep.as_dict()
+
+    def sketches(self):
+        y = qempty(4, self.m, self.k, torch.float64, self.device)
+        w = qempty(4, self.l, self.n, torch.float64, self.device)
+        yp, ldy = _plane_ptrs(y, False)
+        wp, ldw = _plane_ptrs(w, False)
+        self._check(self._lib.qsketch_sketches(self._ctx, yp, ldy, wp, ldw))
+        return y, w
+
+    def reset(self):
+        self._check(self._lib.qsketch_reset(self._ctx))
+
+    def rel_error(self, a, q, x):
+        ap, lda = _plane_ptrs(a, self.pure)
+        qp, ldq = _plane_ptrs(q, False)
+        xp, ldx = _plane_ptrs(x, False)
+        out = ctypes.c_double()
+        self._check(self._lib.qsketch_rel_error(self._ctx, ap, lda, qp, ldq, xp, ldx, ctypes.byref(out)))
+        return out.value
+
+    def close(self):
+        if self._ctx:
+            self._lib.qsketch_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def config_status(**kw):
+    """Run qsketch_init's validation on a configuration without a device:
+    returns the status for configurations rejected before any HIP call."""
+    lib = _load()
+    cfg = QskConfig()
+    lib.qsketch_config_default(ctypes.byref(cfg))
+    for k, v in kw.items():
+        setattr(cfg, k, v)
+    ctx = ctypes.c_void_p()
+    st = lib.qsketch_init(ctypes.byref(cfg), None, ctypes.byref(ctx))
+    if st == QSK_OK:
+        lib.qsketch_destroy(ctx)
+    return st

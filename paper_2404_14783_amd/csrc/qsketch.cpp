@@ -1,0 +1,456 @@
+// Host runtime behind the C ABI of include/qsketch.h: context, workspace,
+// stream-ordered launches of the sketch update and of the FP64 QB stage.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/qsketch.h"
+#include "qsk_kernels.hpp"
+
+namespace {
+
+using qsk::SmallStatus;
+
+struct Buf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct qsk_ctx {
+  qsk_config cfg{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool poisoned = false;
+  std::string last_error;
+  int mode = 0;            // qsk::MODE_*
+  size_t ts = 8;           // bytes per Y/W element
+  int64_t maxcols = 0;
+  int64_t columns_seen = 0;
+  uint32_t k0 = 0, k1 = 0;
+  // sketches
+  void *y = nullptr, *w = nullptr;
+  // finalize workspace (FP64)
+  double *u[2] = {nullptr, nullptr};   // m x k planar, two alternating buffers
+  double *small = nullptr;             // k x k AoS matrices
+  double *work = nullptr;              // driver scratch
+  double *partials = nullptr;
+  int64_t partial_elems = 0;
+  double *pbuf = nullptr, *p1buf = nullptr, *sbuf = nullptr;   // l x k planar each
+  double *err_acc = nullptr;
+  SmallStatus *status = nullptr;
+  void *w_scratch = nullptr;           // split-K partials of the matrix-core W kernel
+  int64_t w_scratch_bytes = 0;
+  int use_mfma = 1;
+};
+
+namespace {
+
+const char *status_str(qsk_status s) {
+  switch (s) {
+    case QSK_OK: return "ok";
+    case QSK_E_ARG: return "invalid argument";
+    case QSK_E_STATE: return "context poisoned or destroyed";
+    case QSK_E_NOMEM: return "device memory allocation failed";
+    case QSK_E_HIP: return "HIP runtime error";
+    case QSK_E_NUMERIC: return "numerical failure: no Q/X could be formed";
+    case QSK_E_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+qsk_status fail_arg(qsk_ctx *c, const char *msg) {
+  if (c) c->last_error = msg;
+  return QSK_E_ARG;
+}
+
+qsk_status hip_fail(qsk_ctx *c, hipError_t e, const char *where) {
+  c->poisoned = true;
+  c->last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return QSK_E_HIP;
+}
+
+#define HIPCHK(ctx, expr)                                   \
+  do {                                                      \
+    hipError_t e_ = (expr);                                 \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr); \
+  } while (0)
+
+void free_all(qsk_ctx *c) {
+  void *ptrs[] = {c->y, c->w, c->u[0], c->u[1], c->small, c->work, c->partials, c->pbuf,
+                  c->p1buf, c->sbuf, c->err_acc, c->status, c->w_scratch};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  c->y = c->w = nullptr;
+  c->u[0] = c->u[1] = nullptr;
+  c->small = c->work = c->partials = c->pbuf = c->p1buf = c->sbuf = c->err_acc = nullptr;
+  c->status = nullptr;
+  c->w_scratch = nullptr;
+}
+
+bool alloc(void **p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
+// Offsets of the k x k matrices inside ctx->small.
+enum SmallSlot { S_G1 = 0, S_GU, S_R, S_T, S_RPROD, S_RTMP, S_G0, S_TMP, S_C, S_F, S_GP, S_RP,
+                 S_TP1, S_TP2, S_TPT, S_Z, S_COUNT };
+
+double *slot(qsk_ctx *c, int s) { return c->small + (size_t)s * c->cfg.k * c->cfg.k * 4; }
+
+}  // namespace
+
+extern "C" {
+
+void qsketch_config_default(qsk_config *cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->embedding = QSK_GAUSSIAN;
+  cfg->input_dtype = QSK_F64;
+  cfg->sketch_dtype = QSK_F64;
+  cfg->split_terms = 1;
+  cfg->n_correction = 3;
+  cfg->n_power = 3;
+}
+
+const char *qsketch_strerror(qsk_status s) { return status_str(s); }
+
+const char *qsketch_last_error(const qsk_ctx *ctx) {
+  if (!ctx) return "null context";
+  return ctx->last_error.c_str();
+}
+
+void *qsketch_stream(const qsk_ctx *ctx) { return ctx ? (void *)ctx->stream : nullptr; }
+
+qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) {
+  if (!cfg || !out) return QSK_E_ARG;
+  *out = nullptr;
+  const qsk_config &c = *cfg;
+  if (c.m < 1 || c.n < 1 || c.m >= (1ll << 31) || c.n >= (1ll << 31)) return QSK_E_ARG;
+  if (c.k < 1 || c.l < c.k || c.l > c.m || c.l > c.n || c.k > 256 || c.l > 1024) return QSK_E_ARG;
+  if (c.embedding != QSK_GAUSSIAN && c.embedding != QSK_RADEMACHER) return QSK_E_ARG;
+  if (c.input_dtype < QSK_F64 || c.input_dtype > QSK_BF16) return QSK_E_ARG;
+  if (c.sketch_dtype < QSK_F64 || c.sketch_dtype > QSK_FP8_E4M3) return QSK_E_ARG;
+  if (c.n_correction < 0 || c.n_correction > 8 || c.n_power < 1 || c.n_power > 64) return QSK_E_ARG;
+  if (c.max_block_cols < 0) return QSK_E_ARG;
+  if (c.sketch_dtype == QSK_BF16 && (c.split_terms < 1 || c.split_terms > 3)) return QSK_E_ARG;
+  if (c.sketch_dtype == QSK_FP8_E4M3) return QSK_E_UNSUPPORTED;
+  if (c.sketch_dtype != QSK_F64 && c.input_dtype == QSK_F64) return QSK_E_UNSUPPORTED;
+
+  qsk_ctx *ctx = new (std::nothrow) qsk_ctx;
+  if (!ctx) return QSK_E_NOMEM;
+  ctx->cfg = c;
+  if (ctx->cfg.max_block_cols == 0 || ctx->cfg.max_block_cols > c.n) ctx->cfg.max_block_cols = c.n;
+  if (ctx->cfg.sketch_dtype != QSK_BF16) ctx->cfg.split_terms = 1;
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->mode = c.sketch_dtype;     // MODE_* and QSK dtypes share the numbering
+  ctx->ts = c.sketch_dtype == QSK_F64 ? 8 : 4;
+  ctx->k0 = (uint32_t)(c.seed & 0xFFFFFFFFull);
+  ctx->k1 = (uint32_t)(c.seed >> 32);
+  const char *env = std::getenv("QSK_NO_MFMA");
+  ctx->use_mfma = (env && env[0] == '1') ? 0 : 1;
+  (void)hipGetDevice(&ctx->device);
+
+  const int64_t m = c.m, n = c.n, k = c.k, l = c.l;
+  const size_t kk = (size_t)k * k * 4;
+  bool ok = true;
+  ok = ok && alloc(&ctx->y, 4 * (size_t)m * k * ctx->ts);
+  ok = ok && alloc(&ctx->w, 4 * (size_t)l * n * ctx->ts);
+  ok = ok && alloc((void **)&ctx->u[0], 4 * (size_t)m * k * 8);
+  ok = ok && alloc((void **)&ctx->u[1], 4 * (size_t)m * k * 8);
+  ok = ok && alloc((void **)&ctx->small, S_COUNT * kk * 8);
+  ok = ok && alloc((void **)&ctx->work, (8 * kk + 16 * (size_t)k) * 8);
+  const int64_t maxk = l > k ? l : k;
+  ctx->partial_elems = 64 * maxk * k * 4;
+  ok = ok && alloc((void **)&ctx->partials, (size_t)ctx->partial_elems * 8);
+  ok = ok && alloc((void **)&ctx->pbuf, 4 * (size_t)l * k * 8);
+  ok = ok && alloc((void **)&ctx->p1buf, 4 * (size_t)l * k * 8);
+  ok = ok && alloc((void **)&ctx->sbuf, 4 * (size_t)l * k * 8);
+  ok = ok && alloc((void **)&ctx->err_acc, 2 * 8);
+  ok = ok && alloc((void **)&ctx->status, sizeof(SmallStatus));
+  // W split-K partials for the matrix-core path: up to 16 slices of l x maxcols x 4 floats
+  ctx->w_scratch_bytes = (int64_t)16 * l * ctx->cfg.max_block_cols * 4 * 4;
+  if (c.sketch_dtype != QSK_F64) ok = ok && alloc(&ctx->w_scratch, (size_t)ctx->w_scratch_bytes);
+  else ctx->w_scratch_bytes = 0;
+  if (!ok) {
+    free_all(ctx);
+    delete ctx;
+    return QSK_E_NOMEM;
+  }
+  hipError_t e = hipMemsetAsync(ctx->y, 0, 4 * (size_t)m * k * ctx->ts, ctx->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->w, 0, 4 * (size_t)l * n * ctx->ts, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    free_all(ctx);
+    delete ctx;
+    return QSK_E_HIP;
+  }
+  *out = ctx;
+  return QSK_OK;
+}
+
+void qsketch_destroy(qsk_ctx *ctx) {
+  if (!ctx) return;
+  if (ctx->stream || true) (void)hipStreamSynchronize(ctx->stream);
+  free_all(ctx);
+  delete ctx;
+}
+
+qsk_status qsketch_reset(qsk_ctx *ctx) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  const qsk_config &c = ctx->cfg;
+  HIPCHK(ctx, hipMemsetAsync(ctx->y, 0, 4 * (size_t)c.m * c.k * ctx->ts, ctx->stream));
+  HIPCHK(ctx, hipMemsetAsync(ctx->w, 0, 4 * (size_t)c.l * c.n * ctx->ts, ctx->stream));
+  ctx->columns_seen = 0;
+  return QSK_OK;
+}
+
+qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void *const planes[4],
+                          int64_t ld) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  const qsk_config &c = ctx->cfg;
+  if (!planes) return fail_arg(ctx, "planes is NULL");
+  if (col0 < 0 || ncols < 1 || ncols > c.max_block_cols || col0 + ncols > c.n)
+    return fail_arg(ctx, "column block out of range");
+  if (ld < c.m) return fail_arg(ctx, "ld < m");
+  for (int p = c.pure ? 1 : 0; p < 4; ++p)
+    if (!planes[p]) return fail_arg(ctx, "NULL plane");
+  qsk::SketchArgs s{};
+  s.stream = ctx->stream;
+  s.mode = ctx->mode;
+  s.in_dtype = c.input_dtype;
+  for (int p = 0; p < 4; ++p) s.planes[p] = planes[p];
+  if (c.pure) s.planes[0] = planes[1];
+  s.lda = ld;
+  s.pure = c.pure;
+  s.m = c.m; s.col0 = col0; s.ncols = ncols;
+  s.k = c.k; s.l = c.l;
+  s.y = ctx->y; s.ldy = c.m; s.psy = c.m * (int64_t)c.k;
+  s.w = ctx->w; s.ldw = c.l; s.psw = c.l * (int64_t)c.n;
+  s.rad = c.embedding == QSK_RADEMACHER;
+  s.terms = c.split_terms;
+  s.k0 = ctx->k0; s.k1 = ctx->k1;
+  s.scratch = ctx->w_scratch;
+  s.scratch_bytes = ctx->w_scratch_bytes;
+  hipError_t e = hipErrorNotSupported;
+  if (ctx->use_mfma && ctx->mode != qsk::MODE_F64) e = qsk::launch_sketch_mfma(s);
+  if (e == hipErrorNotSupported) e = qsk::launch_sketch_generic(s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "sketch update");
+  ctx->columns_seen += ncols;
+  return QSK_OK;
+}
+
+qsk_status qsketch_sketches(qsk_ctx *ctx, double *const Y[4], int64_t ldy, double *const W[4],
+                            int64_t ldw) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  const qsk_config &c = ctx->cfg;
+  const int t = ctx->mode == qsk::MODE_F64 ? 0 : 1;
+  if (Y) {
+    if (ldy < c.m) return fail_arg(ctx, "ldy < m");
+    HIPCHK(ctx, qsk::launch_widen(ctx->stream, t, ctx->y, c.m, c.m * (int64_t)c.k, c.m, c.k, Y, ldy));
+  }
+  if (W) {
+    if (ldw < c.l) return fail_arg(ctx, "ldw < l");
+    HIPCHK(ctx, qsk::launch_widen(ctx->stream, t, ctx->w, c.l, c.l * (int64_t)c.n, c.l, c.n, W, ldw));
+  }
+  return QSK_OK;
+}
+
+qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4], int64_t ldq,
+                            double *const X[4], int64_t ldx, qsk_report *report) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  const qsk_config &c = ctx->cfg;
+  if (rf != QSK_PSEUDO_QR && rf != QSK_PSEUDO_SVD) return fail_arg(ctx, "unknown rangefinder");
+  if (!Q || !X) return fail_arg(ctx, "Q/X NULL");
+  for (int p = 0; p < 4; ++p)
+    if (!Q[p] || !X[p]) return fail_arg(ctx, "NULL output plane");
+  if (ldq < c.m || ldx < c.k) return fail_arg(ctx, "leading dimension too small");
+  hipStream_t st = ctx->stream;
+  const int k = c.k, l = c.l;
+  const int64_t m = c.m, n = c.n;
+  const int ty = ctx->mode == qsk::MODE_F64 ? 0 : 1;
+  const int complex_only = rf == QSK_PSEUDO_QR;
+  const size_t kk = (size_t)k * k * 4;
+  SmallStatus hs{};
+  int flags = 0;
+
+  const void *yp[4];
+  for (int p = 0; p < 4; ++p) yp[p] = (const char *)ctx->y + (size_t)p * m * k * ctx->ts;
+
+  // ---- CholeskyQR of Y (complex QR of Y_c for pseudo-QR, quaternion QR for pseudo-SVD)
+  HIPCHK(ctx, qsk::launch_crossprod(st, ty, yp, m, ty, yp, m, m, k, k, ctx->partials,
+                                    ctx->partial_elems, slot(ctx, S_G1)));
+  HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_G1), k, complex_only, 0.0, slot(ctx, S_R),
+                                   slot(ctx, S_T), ctx->status));
+  HIPCHK(ctx, hipMemcpyAsync(&hs, ctx->status, sizeof(hs), hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  int passes = 2;
+  if (hs.fail) {
+    // shifted CholeskyQR3 (Fukaya et al., 2020): shift 11 (M N + N (N + 1)) u ||Y||^2
+    const double rows_c = complex_only ? 2.0 * m : 4.0 * m;
+    const double shift = 11.0 * (rows_c * k + (double)k * (k + 1)) * 0x1p-53 * hs.trace;
+    if (!(hs.trace > 0.0) || !std::isfinite(hs.trace)) {
+      ctx->last_error = "sketch Y is zero or non-finite";
+      return QSK_E_NUMERIC;
+    }
+    HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_G1), k, complex_only, shift, slot(ctx, S_R),
+                                     slot(ctx, S_T), ctx->status));
+    HIPCHK(ctx, hipMemcpyAsync(&hs, ctx->status, sizeof(hs), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    if (hs.fail) {
+      ctx->last_error = "Cholesky of the shifted Gram failed";
+      return QSK_E_NUMERIC;
+    }
+    passes = 3;
+    flags |= QSK_FLAG_CHOL_FALLBACK;
+  }
+  HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_RPROD), slot(ctx, S_R), kk * 8, hipMemcpyDeviceToDevice, st));
+  const void *zsrc[4] = {yp[0], yp[1], yp[2], yp[3]};
+  int tz = ty;
+  double *gz = slot(ctx, S_G1);
+  for (int pass = 1; pass < passes; ++pass) {
+    double *ub = ctx->u[(pass - 1) & 1];
+    double *up[4] = {ub, ub + (size_t)m * k, ub + 2 * (size_t)m * k, ub + 3 * (size_t)m * k};
+    HIPCHK(ctx, qsk::launch_apply(st, tz, zsrc, m, m, k, slot(ctx, S_T), k, up, m));
+    HIPCHK(ctx, qsk::launch_crossprod(st, 0, (const void *const *)up, m, 0,
+                                      (const void *const *)up, m, m, k, k, ctx->partials,
+                                      ctx->partial_elems, slot(ctx, S_GU)));
+    HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GU), k, complex_only, 0.0, slot(ctx, S_R),
+                                     slot(ctx, S_T), ctx->status));
+    HIPCHK(ctx, hipMemcpyAsync(&hs, ctx->status, sizeof(hs), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    if (hs.fail) {
+      ctx->last_error = "Cholesky failed in a later CholeskyQR pass";
+      return QSK_E_NUMERIC;
+    }
+    // Rprod <- R Rprod
+    HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_R), 0, slot(ctx, S_RPROD), 0, slot(ctx, S_RTMP)));
+    HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_RPROD), slot(ctx, S_RTMP), kk * 8, hipMemcpyDeviceToDevice, st));
+    for (int p = 0; p < 4; ++p) zsrc[p] = up[p];
+    tz = 0;
+    gz = slot(ctx, S_GU);
+  }
+  // Now H0 (pseudo-QR) or Q_Y (pseudo-SVD) = Z T with G_Z = gz.
+  HIPCHK(ctx, hipMemsetAsync(ctx->status, 0, sizeof(SmallStatus), st));
+  if (rf == QSK_PSEUDO_QR) {
+    HIPCHK(ctx, qsk::launch_small_gemm(st, k, gz, 0, slot(ctx, S_T), 0, slot(ctx, S_TMP)));
+    HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_T), 1, slot(ctx, S_TMP), 0, slot(ctx, S_G0)));
+    HIPCHK(ctx, qsk::launch_kappa(st, k, gz, slot(ctx, S_T), ctx->work, 1, ctx->status));
+    HIPCHK(ctx, qsk::launch_pqr_corrections(st, k, slot(ctx, S_G0), c.n_correction, c.n_power,
+                                            ctx->k0, ctx->k1, slot(ctx, S_C), ctx->work, ctx->status));
+  } else {
+    HIPCHK(ctx, qsk::launch_psvd_select(st, k, slot(ctx, S_RPROD), ctx->k0, ctx->k1, slot(ctx, S_C),
+                                        ctx->work, ctx->status));
+  }
+  HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_T), 0, slot(ctx, S_C), 0, slot(ctx, S_F)));
+  HIPCHK(ctx, qsk::launch_kappa(st, k, gz, slot(ctx, S_F), ctx->work, 0, ctx->status));
+  HIPCHK(ctx, qsk::launch_apply(st, tz, zsrc, m, m, k, slot(ctx, S_F), k, Q, ldq));
+
+  // ---- core solve X = (Psi Q)^dagger W (Alg. 2 through the normal form of
+  // a CholeskyQR2 factorisation of P = Psi Q)
+  double *pp[4], *p1[4], *sp[4];
+  for (int p = 0; p < 4; ++p) {
+    pp[p] = ctx->pbuf + (size_t)p * l * k;
+    p1[p] = ctx->p1buf + (size_t)p * l * k;
+    sp[p] = ctx->sbuf + (size_t)p * l * k;
+  }
+  HIPCHK(ctx, qsk::launch_psi_apply(st, ctx->mode, c.embedding == QSK_RADEMACHER, ctx->k0, ctx->k1, l,
+                                    m, Q, ldq, k, ctx->partials, ctx->partial_elems, pp, l));
+  SmallStatus hs2{};
+  HIPCHK(ctx, hipMemcpyAsync(&hs2, ctx->status, sizeof(hs2), hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  flags |= hs2.flags;
+  SmallStatus ps{};
+  SmallStatus *pst = (SmallStatus *)ctx->work;   // not used concurrently with drivers
+  (void)pst;
+  HIPCHK(ctx, qsk::launch_crossprod(st, 0, (const void *const *)pp, l, 0, (const void *const *)pp, l,
+                                    l, k, k, ctx->partials, ctx->partial_elems, slot(ctx, S_GP)));
+  HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GP), k, 0, 0.0, slot(ctx, S_RP), slot(ctx, S_TP1),
+                                   ctx->status));
+  HIPCHK(ctx, hipMemcpyAsync(&ps, ctx->status, sizeof(ps), hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  if (ps.fail) {
+    // (Psi Q)^*(Psi Q) singular: a tiny diagonal shift gives the regularised
+    // solution, which tends to the minimum-norm least-squares one.
+    flags |= QSK_FLAG_RANK_DEFICIENT;
+    const double shift = 1e-14 * (ps.trace > 0 ? ps.trace / k : 1.0);
+    HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GP), k, 0, shift, slot(ctx, S_RP),
+                                     slot(ctx, S_TP1), ctx->status));
+    HIPCHK(ctx, hipMemcpyAsync(&ps, ctx->status, sizeof(ps), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    if (ps.fail) {
+      ctx->last_error = "Psi Q is zero";
+      return QSK_E_NUMERIC;
+    }
+    HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_TPT), slot(ctx, S_TP1), kk * 8, hipMemcpyDeviceToDevice, st));
+  } else {
+    HIPCHK(ctx, qsk::launch_apply(st, 0, (const void *const *)pp, l, l, k, slot(ctx, S_TP1), k, p1, l));
+    HIPCHK(ctx, qsk::launch_crossprod(st, 0, (const void *const *)p1, l, 0, (const void *const *)p1,
+                                      l, l, k, k, ctx->partials, ctx->partial_elems, slot(ctx, S_GP)));
+    HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GP), k, 0, 0.0, slot(ctx, S_RP),
+                                     slot(ctx, S_TP2), ctx->status));
+    HIPCHK(ctx, hipMemcpyAsync(&ps, ctx->status, sizeof(ps), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    if (ps.fail) {
+      ctx->last_error = "second CholeskyQR pass on Psi Q failed";
+      return QSK_E_NUMERIC;
+    }
+    HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_TP1), 0, slot(ctx, S_TP2), 0, slot(ctx, S_TPT)));
+  }
+  // Z = R^{-1} R^{-*} with R^{-1} = TPT; S^* = P Z; X = S W = (S^*)^* W
+  HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_TPT), 0, slot(ctx, S_TPT), 1, slot(ctx, S_Z)));
+  HIPCHK(ctx, qsk::launch_apply(st, 0, (const void *const *)pp, l, l, k, slot(ctx, S_Z), k, sp, l));
+  const void *wp[4];
+  for (int p = 0; p < 4; ++p) wp[p] = (const char *)ctx->w + (size_t)p * l * n * ctx->ts;
+  HIPCHK(ctx, qsk::launch_crossprod_planar(st, sp, l, ty, wp, l, l, k, (int)n, X, ldx));
+
+  if (report) {
+    qsk_report r{};
+    r.kappa = hs2.kappa;
+    r.kappa_initial = rf == QSK_PSEUDO_QR ? hs2.kappa_initial : hs2.kappa;
+    r.n_eps = hs2.n_eps;
+    for (int i = 0; i < 8; ++i) r.eps[i] = hs2.eps[i];
+    r.t_bad = hs2.t_bad;
+    r.flags = flags;
+    r.passes = passes;
+    r.columns_seen = ctx->columns_seen;
+    r.orth_defect = rf == QSK_PSEUDO_SVD ? hs2.orth_defect : 0.0;
+    *report = r;
+  }
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  return QSK_OK;
+}
+
+qsk_status qsketch_rel_error(qsk_ctx *ctx, const void *const A[4], int64_t lda, double *const Q[4],
+                             int64_t ldq, double *const X[4], int64_t ldx, double *err) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  const qsk_config &c = ctx->cfg;
+  if (!A || !Q || !X || !err || lda < c.m) return fail_arg(ctx, "bad argument to rel_error");
+  HIPCHK(ctx, hipMemsetAsync(ctx->err_acc, 0, 16, ctx->stream));
+  HIPCHK(ctx, qsk::launch_error(ctx->stream, c.input_dtype, A, lda, c.pure, c.m, c.n, Q, ldq, X, ldx,
+                                c.k, ctx->err_acc));
+  double h[2];
+  HIPCHK(ctx, hipMemcpyAsync(h, ctx->err_acc, 16, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  *err = h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
+  return QSK_OK;
+}
+
+}  // extern "C"

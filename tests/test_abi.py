@@ -1,0 +1,52 @@
+"""The C-ABI library loads and exports every entry point include/qsketch.h
+declares; argument validation that happens before any device call works on
+the CPU.  No compute calls (there is no GPU here)."""
+import ctypes
+import os
+
+import pytest
+
+import paper_2404_14783_amd as qs
+
+
+def test_library_exports_every_header_symbol():
+    lib = qs._load()
+    names = qs.header_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in qsketch.h but not exported"
+
+
+def test_config_default_and_strerror():
+    lib = qs._load()
+    cfg = qs.QskConfig()
+    lib.qsketch_config_default(ctypes.byref(cfg))
+    assert cfg.n_correction == 3 and cfg.n_power == 3 and cfg.split_terms == 1
+    assert lib.qsketch_strerror(qs.QSK_E_ARG) == b"invalid argument"
+    assert lib.qsketch_last_error(None) == b"null context"
+    lib.qsketch_destroy(None)            # no-op
+
+
+@pytest.mark.parametrize("bad", [
+    dict(m=100, n=80, k=10, l=9),           # l < k
+    dict(m=100, n=80, k=0, l=9),            # k < 1
+    dict(m=100, n=80, k=10, l=81),          # l > n
+    dict(m=100, n=80, k=300, l=300),        # k above the supported maximum
+    dict(m=0, n=80, k=1, l=1),
+    dict(m=100, n=80, k=10, l=21, n_correction=9),
+    dict(m=100, n=80, k=10, l=21, sketch_dtype=2, split_terms=4),
+    dict(m=100, n=80, k=10, l=21, embedding=5),
+])
+def test_invalid_configs_rejected_before_device_use(bad):
+    assert qs.config_status(**bad) == qs.QSK_E_ARG
+
+
+def test_unsupported_combinations():
+    # FP64 data with a low-precision sketch is not accepted
+    assert qs.config_status(m=100, n=80, k=10, l=21, input_dtype=0, sketch_dtype=2) == qs.QSK_E_UNSUPPORTED
+
+
+def test_struct_layouts_match_header():
+    # field order/size of the ctypes mirrors (int64 m,n; int32 k,l; uint64 seed; 7 int32; int64)
+    assert ctypes.sizeof(qs.QskConfig) == 8 + 8 + 4 + 4 + 8 + 7 * 4 + 4 + 8
+    assert ctypes.sizeof(qs.QskReport) == 8 + 8 + 64 + 4 * 4 + 8 + 8

@@ -1,0 +1,149 @@
+"""GPU parity of the HIP path with the oracle, through the C ABI.
+
+Tolerances (relative Frobenius norm of the difference):
+  * FP64 sketch: 1e-12 (FP64 rounding of sums of <= 4n products);
+  * FP32 sketch: 1e-5;
+  * BF16 sketch: operands are exact (the oracle forms the same bf16 values);
+    the GPU accumulates in FP32, the oracle in FP64, so the bound is the FP32
+    accumulation error, 1e-5;
+  * test-matrix values: bit-exact for Rademacher and for BF16 rounding of the
+    Gaussian, 1e-14 for FP64, 2e-6 (a few FP32 ulp) for FP32.
+The QB-stage outputs H and X are not unique (Lemma 4.2, phases and pair
+representatives), so the product HX, kappa(H), the error ||A - HX|| and the
+orthonormality of pseudo-SVD are compared instead.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import embeddings, onepass, quaternion as qt
+from oracle.sketch import SketchConfig, sketch_matrix
+from tests.gpu_helpers import input_values, rel, run_sketch, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+
+def identity_q(n):
+    a = np.zeros((4, n, n))
+    a[0] = np.eye(n)
+    return a
+
+
+@pytest.mark.parametrize("sketch,emb", [("f64", "gaussian"), ("f64", "rademacher"),
+                                        ("f32", "gaussian"), ("bf16", "gaussian"),
+                                        ("bf16", "rademacher")])
+def test_test_matrix_values(sketch, emb):
+    """With A = I the sketches are the test matrices themselves:
+    Y = Omega[0:n, :] and W = Psi[:, 0:m]."""
+    n, k, l = 320, 16, 37
+    a = identity_q(n)
+    dt = "f64" if sketch == "f64" else "f32"
+    sk, _ = run_sketch(a, n, n, k, l, 64, dtype=dt, sketch=sketch, emb=emb, seed=12345)
+    y, w = (to_numpy(t) for t in sk.sketches())
+    rnd = {"f64": "f64", "f32": "f32", "bf16": "bf16"}[sketch]
+    om = embeddings.omega(emb, np.arange(n), k, 12345, rnd)
+    ps = embeddings.psi(emb, l, np.arange(n), 12345, rnd)
+    if sketch == "bf16" or emb == "rademacher":
+        np.testing.assert_array_equal(y, om)
+        np.testing.assert_array_equal(w, ps)
+    elif sketch == "f64":
+        np.testing.assert_allclose(y, om, rtol=1e-14, atol=1e-15)
+        np.testing.assert_allclose(w, ps, rtol=1e-14, atol=1e-15)
+    else:
+        assert np.max(np.abs(y - om) / np.maximum(np.abs(om), 1e-30)) < 2e-6
+        assert np.max(np.abs(w - ps) / np.maximum(np.abs(ps), 1e-30)) < 2e-6
+
+
+CASES = [
+    # sketch dtype, input dtype, embedding, terms, tolerance
+    ("f64", "f64", "gaussian", 1, 1e-12),
+    ("f64", "f64", "rademacher", 1, 1e-12),
+    ("f32", "f32", "gaussian", 1, 1e-5),
+    ("f32", "f32", "rademacher", 1, 1e-5),
+    ("bf16", "f32", "gaussian", 1, 1e-5),
+    ("bf16", "f32", "gaussian", 2, 1e-5),
+    ("bf16", "f32", "gaussian", 3, 1e-5),
+    ("bf16", "bf16", "rademacher", 1, 1e-5),
+]
+
+
+@pytest.mark.parametrize("sketch,dtype,emb,terms,tol", CASES)
+def test_sketch_parity_ragged(sketch, dtype, emb, terms, tol):
+    """Y and W against the oracle on a ragged shape (several tiles plus tails)
+    streamed in uneven blocks."""
+    m, n, k, l, block = 333, 257, 12, 25, 50
+    a = synth.lowrank_plus_noise(m, n, torch.tensor(0.8 ** np.arange(10)), 1e-3, 77).numpy()
+    a = input_values(a, dtype)
+    sk, _ = run_sketch(a, m, n, k, l, block, dtype=dtype, sketch=sketch, emb=emb, seed=5,
+                       terms=terms)
+    y, w = (to_numpy(t) for t in sk.sketches())
+    cfg = SketchConfig(m, n, k, l, seed=5, embedding=emb, dtype=sketch, terms=terms)
+    ref = sketch_matrix(a, cfg, block_cols=block)
+    assert rel(y, ref.Y) < tol
+    assert rel(w, ref.W) < tol
+
+
+def test_streaming_order_and_pure_input():
+    m, n, k, l, block = 200, 160, 8, 17, 32
+    a = synth.lowrank_plus_noise(m, n, torch.tensor(0.7 ** np.arange(6)), 1e-3, 78).numpy()
+    a[0] = 0.0                                      # pure quaternion
+    s1, _ = run_sketch(a, m, n, k, l, block, seed=3)
+    s2, _ = run_sketch(a, m, n, k, l, block, seed=3, order=[4, 1, 3, 0, 2], pure=True)
+    y1, w1 = (to_numpy(t) for t in s1.sketches())
+    y2, w2 = (to_numpy(t) for t in s2.sketches())
+    assert rel(y2, y1) < 1e-13 and rel(w2, w1) < 1e-13
+
+
+@pytest.fixture(scope="module")
+def config1():
+    a = synth.config1().numpy()
+    cfg = SketchConfig(1000, 800, 40, 81, seed=0)
+    ref = sketch_matrix(a, cfg, block_cols=256)
+    sk, dev = run_sketch(a, 1000, 800, 40, 81, 256, seed=0)
+    return a, ref, sk, dev
+
+
+def test_config1_sketches(config1):
+    a, ref, sk, _ = config1
+    y, w = (to_numpy(t) for t in sk.sketches())
+    assert rel(y, ref.Y) < 1e-12
+    assert rel(w, ref.W) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["pseudo_qr", "pseudo_svd"])
+def test_config1_qb_stage(config1, kind):
+    a, ref, sk, dev = config1
+    q, x, rep = sk.finalize(kind)
+    qn, xn = to_numpy(q), to_numpy(x)
+    h_o, x_o, info = onepass.qb_stage(ref, kind)
+    hx = qt.hamilton(qn, xn)
+    hx_o = qt.hamilton(h_o, x_o)
+    assert rel(hx, hx_o) < 1e-9
+    e_gpu = sk.rel_error(dev, q, x)
+    e_o = onepass.rel_error(a, h_o, x_o)
+    assert abs(e_gpu - e_o) <= 1e-6 * e_o
+    np.testing.assert_allclose(e_gpu, onepass.rel_error(a, qn, xn), rtol=1e-9)
+    kap = rep["kappa"]
+    np.testing.assert_allclose(kap, info["kappa"], rtol=1e-6)
+    # range of Q equals range of Y (Prop. 3.1 / Alg. 3)
+    proj = lambda z: qt.hamilton(z, qt.pinv(z))
+    assert qt.fro(proj(qn) - proj(ref.Y)) < 1e-6
+    if kind == "pseudo_qr":
+        assert kap < 10 and len(rep["eps"]) == 3
+        np.testing.assert_allclose(rep["eps"], info["eps"], rtol=1e-6)
+        np.testing.assert_allclose(rep["kappa_initial"], info["kappa0"], rtol=1e-4)
+    else:
+        assert rep["orth_defect"] < 1e-10
+        np.testing.assert_allclose(qt.hamilton(qt.conj_t(qn), qn), qt.eye(40), atol=1e-10)
+
+
+@pytest.mark.parametrize("kind", ["pseudo_qr", "pseudo_svd"])
+def test_exact_low_rank_recovery(kind):
+    """Exact rank r <= k with no noise is recovered to rounding (Z15 for the
+    rank-deficient pseudo-QR factor)."""
+    m, n, k, l = 300, 240, 8, 17
+    a = synth.lowrank_plus_noise(m, n, torch.tensor([1.0, 0.5, 0.3, 0.2]), 0.0, 79).numpy()
+    sk, dev = run_sketch(a, m, n, k, l, 60, seed=9)
+    q, x, rep = sk.finalize(kind)
+    assert sk.rel_error(dev, q, x) < 1e-8
