@@ -502,7 +502,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 // matrix: quaternion inner products are made real by a unit-quaternion
 // column scaling, then a real plane rotation orthogonalises the pair.
 // Round-robin pair order; stops after a sweep without rotations.
-__device__ void sm_jacobi(double *a, int rows, int cols, int lda, int max_sweeps, double tol) {
+__device__ void sm_jacobi(double *a, int rows, int cols, int lda, int max_sweeps, double tol,
+                          int rows_rot = -1) {
+  if (rows_rot < 0) rows_rot = rows;
   __shared__ int s_rot;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int n = cols + (cols & 1);
@@ -532,7 +534,7 @@ __device__ void sm_jacobi(double *a, int rows, int cols, int lda, int max_sweeps
         const double zeta = (be - al) / (2.0 * gn);
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int i = lane; i < rows; i += 64) {
+        for (int i = lane; i < rows_rot; i += 64) {
           const qd ap = gq(a, i, p, lda);
           const qd aq = qmul(gq(a, i, q, lda), mu_c);
           sq_(a, i, p, lda, qsub(qscale(ap, c), qscale(aq, s)));
@@ -578,11 +580,11 @@ __device__ void sm_sorted_columns(const double *a, int rows, int cols, int lda, 
 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void chol_inv_kernel(const double *g, int k, int complex_only,
-                                                        double shift, double *r, double *t,
-                                                        SmallStatus *status) {
+                                                        double shift, double tol, double *r,
+                                                        double *t, SmallStatus *status) {
   __shared__ int fail;
   __shared__ double minp, trace;
-  sm_chol(g, r, k, complex_only, shift, 1e-13, &fail, &minp, &trace);
+  sm_chol(g, r, k, complex_only, shift, tol, &fail, &minp, &trace);
   __syncthreads();
   if (threadIdx.x == 0) {
     status->fail = fail;
@@ -593,9 +595,9 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(const double *g, int k, 
 }
 
 hipError_t launch_chol_inv(hipStream_t st, const double *g, int k, int complex_only, double shift,
-                           double *r, double *t, SmallStatus *status) {
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), 0, st, g, k, complex_only, shift, r, t,
-                     status);
+                           double tol, double *r, double *t, SmallStatus *status) {
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), 0, st, g, k, complex_only, shift, tol, r,
+                     t, status);
   return hipGetLastError();
 }
 
@@ -800,6 +802,63 @@ __global__ __launch_bounds__(1024) void psvd_select_kernel(int k, const double *
 hipError_t launch_psvd_select(hipStream_t st, int k, const double *ry, uint32_t k0, uint32_t k1,
                               double *c, double *work, SmallStatus *status) {
   hipLaunchKernelGGL(psvd_select_kernel, dim3(1), dim3(1024), 0, st, k, ry, k0, k1, c, work, status);
+  return hipGetLastError();
+}
+
+// Minimum-norm least squares for a rank-deficient P (l x k, planar):
+// one-sided Jacobi on [P; I] (inner products over the P rows only) gives
+// P V = B with orthogonal columns and V accumulated; with sigma_i = ||b_i||,
+// P^dagger = V diag(1/sigma_i^2) B^* over sigma_i > tol sigma_max, so
+// S^* = (P^dagger)^* = B diag(w) V^*, written planar (l x k).
+__global__ __launch_bounds__(1024) void pinv_sstar_kernel(int l, int k, PlanesC<double> p,
+                                                          int64_t ldp, double tol, double *work,
+                                                          Planes<double> out, int64_t ldo) {
+  __shared__ double sig[256];
+  __shared__ double s_max;
+  const int rows = l + k;
+  double *M = work;                       // rows x k, AoS, ld = rows
+  for (int e = threadIdx.x; e < rows * k; e += blockDim.x) {
+    const int i = e % rows, j = e / rows;
+    qd v;
+    if (i < l) v = {p.p[0][i + j * ldp], p.p[1][i + j * ldp], p.p[2][i + j * ldp], p.p[3][i + j * ldp]};
+    else v = {(i - l) == j ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+    sq_(M, i, j, rows, v);
+  }
+  __syncthreads();
+  sm_jacobi(M, l, k, rows, 60, 1e-15, rows);
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < l; ++i) s += qnorm2(gq(M, i, j, rows));
+    sig[j] = sqrt(s);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mx = 0.0;
+    for (int j = 0; j < k; ++j) mx = fmax(mx, sig[j]);
+    s_max = mx;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < l * k; e += blockDim.x) {
+    const int r = e % l, c = e / l;
+    qd acc = qzero();
+    for (int i = 0; i < k; ++i) {
+      const double si = sig[i];
+      if (!(si > tol * s_max)) continue;
+      const double w = 1.0 / (si * si);
+      qfma(acc, qscale(gq(M, r, i, rows), w), qconj(gq(M, l + c, i, rows)));
+    }
+    const int64_t o = r + (int64_t)c * ldo;
+    out.p[0][o] = acc.w; out.p[1][o] = acc.x; out.p[2][o] = acc.y; out.p[3][o] = acc.z;
+  }
+}
+
+hipError_t launch_pinv_sstar(hipStream_t st, int l, int k, const double *const p[4], int64_t ldp,
+                             double tol, double *work, double *const out[4], int64_t ldo) {
+  PlanesC<double> pp;
+  Planes<double> oo;
+  for (int q = 0; q < 4; ++q) { pp.p[q] = p[q]; oo.p[q] = out[q]; }
+  hipLaunchKernelGGL(pinv_sstar_kernel, dim3(1), dim3(1024), 0, st, l, k, pp, ldp, tol, work, oo, ldo);
   return hipGetLastError();
 }
 

@@ -85,8 +85,9 @@ struct SmallStatus {
 
 // R = chol(G') with G' = G (full quaternion) or its complex part (j-part
 // zeroed) when complex_only; plus `shift` * I when shift > 0; T = R^{-1}.
+// A pivot^2 <= tol * max diagonal counts as a failure.
 hipError_t launch_chol_inv(hipStream_t st, const double *g, int k, int complex_only, double shift,
-                           double *r, double *t, SmallStatus *status);
+                           double tol, double *r, double *t, SmallStatus *status);
 // C = opA(A) * opB(B) (k x k AoS; op = 0 none, 1 conjugate transpose).
 hipError_t launch_small_gemm(hipStream_t st, int k, const double *a, int opa, const double *b,
                              int opb, double *c);
@@ -102,6 +103,10 @@ hipError_t launch_psvd_select(hipStream_t st, int k, const double *ry, uint32_t 
 // kappa of H = Z F from G_Z: G_H = F^* G_Z F, chol, Jacobi singular values.
 hipError_t launch_kappa(hipStream_t st, int k, const double *gz, const double *f, double *work,
                         int which, SmallStatus *status);
+// S^* = (P^dagger)^* (l x k planar) for a rank-deficient P by a Jacobi SVD
+// of [P; I]; work holds (l + k) k quaternions.
+hipError_t launch_pinv_sstar(hipStream_t st, int l, int k, const double *const p[4], int64_t ldp,
+                             double tol, double *work, double *const out[4], int64_t ldo);
 // identity into a k x k AoS buffer
 hipError_t launch_identity(hipStream_t st, int k, double *c);
 

@@ -44,6 +44,7 @@ struct qsk_ctx {
   int64_t partial_elems = 0;
   double *pbuf = nullptr, *p1buf = nullptr, *sbuf = nullptr;   // l x k planar each
   double *err_acc = nullptr;
+  double *pinv_work = nullptr;         // (l + k) x k quaternions
   SmallStatus *status = nullptr;
   void *w_scratch = nullptr;           // split-K partials of the matrix-core W kernel
   int64_t w_scratch_bytes = 0;
@@ -84,7 +85,7 @@ qsk_status hip_fail(qsk_ctx *c, hipError_t e, const char *where) {
 
 void free_all(qsk_ctx *c) {
   void *ptrs[] = {c->y, c->w, c->u[0], c->u[1], c->small, c->work, c->partials, c->pbuf,
-                  c->p1buf, c->sbuf, c->err_acc, c->status, c->w_scratch};
+                  c->p1buf, c->sbuf, c->err_acc, c->status, c->w_scratch, c->pinv_work};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->y = c->w = nullptr;
@@ -92,6 +93,7 @@ void free_all(qsk_ctx *c) {
   c->small = c->work = c->partials = c->pbuf = c->p1buf = c->sbuf = c->err_acc = nullptr;
   c->status = nullptr;
   c->w_scratch = nullptr;
+  c->pinv_work = nullptr;
 }
 
 bool alloc(void **p, size_t bytes) {
@@ -179,6 +181,7 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   ok = ok && alloc((void **)&ctx->p1buf, 4 * (size_t)l * k * 8);
   ok = ok && alloc((void **)&ctx->sbuf, 4 * (size_t)l * k * 8);
   ok = ok && alloc((void **)&ctx->err_acc, 2 * 8);
+  ok = ok && alloc((void **)&ctx->pinv_work, 4 * (size_t)(l + k) * k * 8);
   ok = ok && alloc((void **)&ctx->status, sizeof(SmallStatus));
   // W split-K partials for the matrix-core path: up to 16 slices of l x maxcols x 4 floats
   ctx->w_scratch_bytes = (int64_t)16 * l * ctx->cfg.max_block_cols * 4 * 4;
@@ -293,55 +296,53 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
   const void *yp[4];
   for (int p = 0; p < 4; ++p) yp[p] = (const char *)ctx->y + (size_t)p * m * k * ctx->ts;
 
-  // ---- CholeskyQR of Y (complex QR of Y_c for pseudo-QR, quaternion QR for pseudo-SVD)
-  HIPCHK(ctx, qsk::launch_crossprod(st, ty, yp, m, ty, yp, m, m, k, k, ctx->partials,
-                                    ctx->partial_elems, slot(ctx, S_G1)));
-  HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_G1), k, complex_only, 0.0, slot(ctx, S_R),
-                                   slot(ctx, S_T), ctx->status));
-  HIPCHK(ctx, hipMemcpyAsync(&hs, ctx->status, sizeof(hs), hipMemcpyDeviceToHost, st));
-  HIPCHK(ctx, hipStreamSynchronize(st));
-  int passes = 2;
-  if (hs.fail) {
-    // shifted CholeskyQR3 (Fukaya et al., 2020): shift 11 (M N + N (N + 1)) u ||Y||^2
-    const double rows_c = complex_only ? 2.0 * m : 4.0 * m;
-    const double shift = 11.0 * (rows_c * k + (double)k * (k + 1)) * 0x1p-53 * hs.trace;
-    if (!(hs.trace > 0.0) || !std::isfinite(hs.trace)) {
-      ctx->last_error = "sketch Y is zero or non-finite";
-      return QSK_E_NUMERIC;
-    }
-    HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_G1), k, complex_only, shift, slot(ctx, S_R),
-                                     slot(ctx, S_T), ctx->status));
-    HIPCHK(ctx, hipMemcpyAsync(&hs, ctx->status, sizeof(hs), hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipStreamSynchronize(st));
-    if (hs.fail) {
-      ctx->last_error = "Cholesky of the shifted Gram failed";
-      return QSK_E_NUMERIC;
-    }
-    passes = 3;
-    flags |= QSK_FLAG_CHOL_FALLBACK;
-  }
-  HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_RPROD), slot(ctx, S_R), kk * 8, hipMemcpyDeviceToDevice, st));
+  // ---- CholeskyQR of Y: complex QR of Y_c for pseudo-QR (the j-part of the
+  // quaternion Gram is dropped), quaternion QR for pseudo-SVD.  A Cholesky
+  // breakdown switches that pass to a shifted factorisation (Fukaya et al.,
+  // shifted CholeskyQR3) and asks for two more clean passes; repeated shifted
+  // passes lift an exactly rank-deficient sketch to a full orthonormal basis
+  // whose extra directions are arbitrary.
   const void *zsrc[4] = {yp[0], yp[1], yp[2], yp[3]};
   int tz = ty;
   double *gz = slot(ctx, S_G1);
-  for (int pass = 1; pass < passes; ++pass) {
-    double *ub = ctx->u[(pass - 1) & 1];
-    double *up[4] = {ub, ub + (size_t)m * k, ub + 2 * (size_t)m * k, ub + 3 * (size_t)m * k};
-    HIPCHK(ctx, qsk::launch_apply(st, tz, zsrc, m, m, k, slot(ctx, S_T), k, up, m));
-    HIPCHK(ctx, qsk::launch_crossprod(st, 0, (const void *const *)up, m, 0,
-                                      (const void *const *)up, m, m, k, k, ctx->partials,
-                                      ctx->partial_elems, slot(ctx, S_GU)));
-    HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GU), k, complex_only, 0.0, slot(ctx, S_R),
+  const double rows_c = complex_only ? 2.0 * m : 4.0 * m;
+  int passes = 0, need = 2;
+  const int max_passes = 8;
+  for (;;) {
+    HIPCHK(ctx, qsk::launch_crossprod(st, tz, zsrc, m, tz, zsrc, m, m, k, k, ctx->partials,
+                                      ctx->partial_elems, gz));
+    HIPCHK(ctx, qsk::launch_chol_inv(st, gz, k, complex_only, 0.0, 1e-13, slot(ctx, S_R),
                                      slot(ctx, S_T), ctx->status));
     HIPCHK(ctx, hipMemcpyAsync(&hs, ctx->status, sizeof(hs), hipMemcpyDeviceToHost, st));
     HIPCHK(ctx, hipStreamSynchronize(st));
+    ++passes;
     if (hs.fail) {
-      ctx->last_error = "Cholesky failed in a later CholeskyQR pass";
-      return QSK_E_NUMERIC;
+      if (!(hs.trace > 0.0) || !std::isfinite(hs.trace)) {
+        ctx->last_error = "sketch Y is zero or non-finite";
+        return QSK_E_NUMERIC;
+      }
+      const double shift = 11.0 * (rows_c * k + (double)k * (k + 1)) * 0x1p-53 * hs.trace;
+      HIPCHK(ctx, qsk::launch_chol_inv(st, gz, k, complex_only, shift, 0.0, slot(ctx, S_R),
+                                       slot(ctx, S_T), ctx->status));
+      HIPCHK(ctx, hipMemcpyAsync(&hs, ctx->status, sizeof(hs), hipMemcpyDeviceToHost, st));
+      HIPCHK(ctx, hipStreamSynchronize(st));
+      if (hs.fail) {
+        ctx->last_error = "Cholesky of the shifted Gram failed";
+        return QSK_E_NUMERIC;
+      }
+      flags |= QSK_FLAG_CHOL_FALLBACK;
+      if (need < passes + 2) need = passes + 2;
     }
-    // Rprod <- R Rprod
-    HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_R), 0, slot(ctx, S_RPROD), 0, slot(ctx, S_RTMP)));
-    HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_RPROD), slot(ctx, S_RTMP), kk * 8, hipMemcpyDeviceToDevice, st));
+    if (passes == 1) {
+      HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_RPROD), slot(ctx, S_R), kk * 8, hipMemcpyDeviceToDevice, st));
+    } else {
+      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_R), 0, slot(ctx, S_RPROD), 0, slot(ctx, S_RTMP)));
+      HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_RPROD), slot(ctx, S_RTMP), kk * 8, hipMemcpyDeviceToDevice, st));
+    }
+    if (passes >= need || passes >= max_passes) break;
+    double *ub = ctx->u[(passes - 1) & 1];
+    double *up[4] = {ub, ub + (size_t)m * k, ub + 2 * (size_t)m * k, ub + 3 * (size_t)m * k};
+    HIPCHK(ctx, qsk::launch_apply(st, tz, zsrc, m, m, k, slot(ctx, S_T), k, up, m));
     for (int p = 0; p < 4; ++p) zsrc[p] = up[p];
     tz = 0;
     gz = slot(ctx, S_GU);
@@ -381,41 +382,39 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
   (void)pst;
   HIPCHK(ctx, qsk::launch_crossprod(st, 0, (const void *const *)pp, l, 0, (const void *const *)pp, l,
                                     l, k, k, ctx->partials, ctx->partial_elems, slot(ctx, S_GP)));
-  HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GP), k, 0, 0.0, slot(ctx, S_RP), slot(ctx, S_TP1),
-                                   ctx->status));
+  HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GP), k, 0, 0.0, 1e-13, slot(ctx, S_RP),
+                                   slot(ctx, S_TP1), ctx->status));
   HIPCHK(ctx, hipMemcpyAsync(&ps, ctx->status, sizeof(ps), hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipStreamSynchronize(st));
+  bool have_sstar = false;
   if (ps.fail) {
-    // (Psi Q)^*(Psi Q) singular: a tiny diagonal shift gives the regularised
-    // solution, which tends to the minimum-norm least-squares one.
+    // (Psi Q)^*(Psi Q) singular: minimum-norm least squares through a Jacobi
+    // SVD of Psi Q (the reading of Alg. 2's backslash for a rank-deficient
+    // system).
     flags |= QSK_FLAG_RANK_DEFICIENT;
-    const double shift = 1e-14 * (ps.trace > 0 ? ps.trace / k : 1.0);
-    HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GP), k, 0, shift, slot(ctx, S_RP),
-                                     slot(ctx, S_TP1), ctx->status));
-    HIPCHK(ctx, hipMemcpyAsync(&ps, ctx->status, sizeof(ps), hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipStreamSynchronize(st));
-    if (ps.fail) {
-      ctx->last_error = "Psi Q is zero";
-      return QSK_E_NUMERIC;
-    }
-    HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_TPT), slot(ctx, S_TP1), kk * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(ctx, qsk::launch_pinv_sstar(st, l, k, pp, l, 1e-13, ctx->pinv_work, sp, l));
+    have_sstar = true;
   } else {
     HIPCHK(ctx, qsk::launch_apply(st, 0, (const void *const *)pp, l, l, k, slot(ctx, S_TP1), k, p1, l));
     HIPCHK(ctx, qsk::launch_crossprod(st, 0, (const void *const *)p1, l, 0, (const void *const *)p1,
                                       l, l, k, k, ctx->partials, ctx->partial_elems, slot(ctx, S_GP)));
-    HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GP), k, 0, 0.0, slot(ctx, S_RP),
+    HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GP), k, 0, 0.0, 1e-13, slot(ctx, S_RP),
                                      slot(ctx, S_TP2), ctx->status));
     HIPCHK(ctx, hipMemcpyAsync(&ps, ctx->status, sizeof(ps), hipMemcpyDeviceToHost, st));
     HIPCHK(ctx, hipStreamSynchronize(st));
     if (ps.fail) {
-      ctx->last_error = "second CholeskyQR pass on Psi Q failed";
-      return QSK_E_NUMERIC;
+      flags |= QSK_FLAG_RANK_DEFICIENT;
+      HIPCHK(ctx, qsk::launch_pinv_sstar(st, l, k, pp, l, 1e-13, ctx->pinv_work, sp, l));
+      have_sstar = true;
+    } else {
+      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_TP1), 0, slot(ctx, S_TP2), 0, slot(ctx, S_TPT)));
     }
-    HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_TP1), 0, slot(ctx, S_TP2), 0, slot(ctx, S_TPT)));
   }
   // Z = R^{-1} R^{-*} with R^{-1} = TPT; S^* = P Z; X = S W = (S^*)^* W
-  HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_TPT), 0, slot(ctx, S_TPT), 1, slot(ctx, S_Z)));
-  HIPCHK(ctx, qsk::launch_apply(st, 0, (const void *const *)pp, l, l, k, slot(ctx, S_Z), k, sp, l));
+  if (!have_sstar) {
+    HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_TPT), 0, slot(ctx, S_TPT), 1, slot(ctx, S_Z)));
+    HIPCHK(ctx, qsk::launch_apply(st, 0, (const void *const *)pp, l, l, k, slot(ctx, S_Z), k, sp, l));
+  }
   const void *wp[4];
   for (int p = 0; p < 4; ++p) wp[p] = (const char *)ctx->w + (size_t)p * l * n * ctx->ts;
   HIPCHK(ctx, qsk::launch_crossprod_planar(st, sp, l, ty, wp, l, l, k, (int)n, X, ldx));

@@ -7,7 +7,8 @@ Tolerances (relative Frobenius norm of the difference):
     the GPU accumulates in FP32, the oracle in FP64, so the bound is the FP32
     accumulation error, 1e-5;
   * test-matrix values: bit-exact for Rademacher and for BF16 rounding of the
-    Gaussian, 1e-14 for FP64, 2e-6 (a few FP32 ulp) for FP32.
+    Gaussian, 1e-14 relative or absolute for FP64, 2e-6 (a few FP32 ulp) for
+    FP32.
 The QB-stage outputs H and X are not unique (Lemma 4.2, phases and pair
 representatives), so the product HX, kappa(H), the error ||A - HX|| and the
 orthonormality of pseudo-SVD are compared instead.
@@ -48,8 +49,10 @@ def test_test_matrix_values(sketch, emb):
         np.testing.assert_array_equal(y, om)
         np.testing.assert_array_equal(w, ps)
     elif sketch == "f64":
-        np.testing.assert_allclose(y, om, rtol=1e-14, atol=1e-15)
-        np.testing.assert_allclose(w, ps, rtol=1e-14, atol=1e-15)
+        # the oracle rounds 2 pi u before its cosine, the device evaluates
+        # cos(pi * 2u): both are within a few ulp of |theta| in absolute terms
+        np.testing.assert_allclose(y, om, rtol=1e-14, atol=1e-14)
+        np.testing.assert_allclose(w, ps, rtol=1e-14, atol=1e-14)
     else:
         assert np.max(np.abs(y - om) / np.maximum(np.abs(om), 1e-30)) < 2e-6
         assert np.max(np.abs(w - ps) / np.maximum(np.abs(ps), 1e-30)) < 2e-6
@@ -111,6 +114,26 @@ def test_config1_sketches(config1):
     assert rel(w, ref.W) < 1e-12
 
 
+def oracle_sensitivity(ref, kind, rel_pert=1e-15, seed=0):
+    """Relative change of the oracle's kappa / eps when Y is perturbed by a
+    random relative 1e-15: the scale below which GPU and oracle cannot be
+    expected to agree (these diagnostics depend on the non-unique H)."""
+    from oracle.rangefinders import pseudo_qr, pseudo_svd
+    rng = np.random.default_rng(seed)
+    y2 = ref.Y * (1.0 + rel_pert * rng.standard_normal(ref.Y.shape))
+    proj = lambda z: qt.hamilton(z, qt.pinv(z))
+    if kind == "pseudo_qr":
+        ha, a = pseudo_qr(ref.Y, seed=ref.cfg.seed)
+        hb, b = pseudo_qr(y2, seed=ref.cfg.seed)
+        ek = abs(a["kappa"] - b["kappa"]) / a["kappa"]
+        ee = max(abs(x - y) / x for x, y in zip(a["eps"], b["eps"]))
+        e0 = abs(a["kappa0"] - b["kappa0"]) / a["kappa0"]
+        return ek, ee, e0, qt.fro(proj(ha) - proj(hb))
+    ha, a = pseudo_svd(ref.Y, seed=ref.cfg.seed)
+    hb, b = pseudo_svd(y2, seed=ref.cfg.seed)
+    return abs(a["kappa"] - b["kappa"]) / a["kappa"], 0.0, 0.0, qt.fro(proj(ha) - proj(hb))
+
+
 @pytest.mark.parametrize("kind", ["pseudo_qr", "pseudo_svd"])
 def test_config1_qb_stage(config1, kind):
     a, ref, sk, dev = config1
@@ -119,20 +142,25 @@ def test_config1_qb_stage(config1, kind):
     h_o, x_o, info = onepass.qb_stage(ref, kind)
     hx = qt.hamilton(qn, xn)
     hx_o = qt.hamilton(h_o, x_o)
-    assert rel(hx, hx_o) < 1e-9
+    assert rel(hx, hx_o) < 1e-9                        # HX is unique (Lemma 4.2)
     e_gpu = sk.rel_error(dev, q, x)
     e_o = onepass.rel_error(a, h_o, x_o)
     assert abs(e_gpu - e_o) <= 1e-6 * e_o
     np.testing.assert_allclose(e_gpu, onepass.rel_error(a, qn, xn), rtol=1e-9)
-    kap = rep["kappa"]
-    np.testing.assert_allclose(kap, info["kappa"], rtol=1e-6)
-    # range of Q equals range of Y (Prop. 3.1 / Alg. 3)
+    # same range as the oracle's factor, up to the oracle's own sensitivity
+    # (the paper notes pseudo-QR's weaker range precision, Section 3.3)
+    sk_, se_, s0_, sr_ = oracle_sensitivity(ref, kind)
     proj = lambda z: qt.hamilton(z, qt.pinv(z))
-    assert qt.fro(proj(qn) - proj(ref.Y)) < 1e-6
+    assert qt.fro(proj(qn) - proj(h_o)) < max(1e-8, 10 * sr_)
+    kap = rep["kappa"]
+    np.testing.assert_allclose(kap, info["kappa"], rtol=max(1e-9, 100 * sk_))
     if kind == "pseudo_qr":
         assert kap < 10 and len(rep["eps"]) == 3
-        np.testing.assert_allclose(rep["eps"], info["eps"], rtol=1e-6)
-        np.testing.assert_allclose(rep["kappa_initial"], info["kappa0"], rtol=1e-4)
+        np.testing.assert_allclose(rep["eps"], info["eps"], rtol=max(1e-9, 100 * se_))
+        # the device estimates kappa(H0) from the Gram of H0, whose relative
+        # accuracy for the smallest singular value is ~ kappa0^2 u
+        k0 = info["kappa0"]
+        np.testing.assert_allclose(rep["kappa_initial"], k0, rtol=max(1e-6, 100 * s0_, 10 * k0 * k0 * 2.0 ** -53))
     else:
         assert rep["orth_defect"] < 1e-10
         np.testing.assert_allclose(qt.hamilton(qt.conj_t(qn), qn), qt.eye(40), atol=1e-10)
