@@ -156,6 +156,17 @@ qsk_status qsketch_rel_error(qsk_ctx *ctx, const void *const A[4], int64_t lda,
                              double *const Q[4], int64_t ldq,
                              double *const X[4], int64_t ldx, double *err);
 
+/* Per-kernel timing of qsketch_update: with enable != 0, every later update
+   brackets each of its kernel launches with HIP events on the context
+   stream.  qsketch_get_timing synchronises the stream and returns, for
+   `kernel` = 0 (test-matrix staging), 1 (Y product), 2 (W product) or
+   3 (W split-K reduction), the summed duration in milliseconds and the
+   number of launches since timing was enabled (or last reset by enabling
+   again).  For measurement only: the events add a few microseconds per
+   update. */
+qsk_status qsketch_set_timing(qsk_ctx *ctx, int enable);
+qsk_status qsketch_get_timing(qsk_ctx *ctx, int kernel, double *total_ms, int64_t *launches);
+
 /* Stream (hipStream_t) of the context. */
 void *qsketch_stream(const qsk_ctx *ctx);
 

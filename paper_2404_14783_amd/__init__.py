@@ -86,6 +86,10 @@ def _load():
     lib.qsketch_reset.restype = i32
     lib.qsketch_rel_error.argtypes = [vp, _P4, i64, _P4, i64, _P4, i64, ctypes.POINTER(ctypes.c_double)]
     lib.qsketch_rel_error.restype = i32
+    lib.qsketch_set_timing.argtypes = [vp, i32]
+    lib.qsketch_set_timing.restype = i32
+    lib.qsketch_get_timing.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.qsketch_get_timing.restype = i32
     lib.qsketch_stream.argtypes = [vp]
     lib.qsketch_stream.restype = vp
     lib.qsketch_destroy.argtypes = [vp]
@@ -217,6 +221,19 @@ class Sketcher:
         out = ctypes.c_double()
         self._check(self._lib.qsketch_rel_error(self._ctx, ap, lda, qp, ldq, xp, ldx, ctypes.byref(out)))
         return out.value
+
+    def set_timing(self, enable=True):
+        self._check(self._lib.qsketch_set_timing(self._ctx, 1 if enable else 0))
+
+    def timing(self):
+        """{kernel: (total_ms, launches)} for stage / y / w / w_reduce."""
+        out = {}
+        for i, name in enumerate(("stage", "y", "w", "w_reduce")):
+            ms = ctypes.c_double()
+            n = ctypes.c_int64()
+            self._check(self._lib.qsketch_get_timing(self._ctx, i, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
 
     def close(self):
         if self._ctx:

@@ -204,7 +204,9 @@ hipError_t launch_apply(hipStream_t st, int tz, const void *const z[4], int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// P = Psi H, Psi (l x m) regenerated as the sketch of `mode` used it.
+// P = Psi H, Psi (l x m) regenerated as the sketch of `mode` used it.  A
+// block owns 16 rows of Psi and every column of H (up to 16 tiles of 16), so
+// each entry of Psi is regenerated once per chunk of rows of H.
 __global__ __launch_bounds__(256) void psi_apply_k(int mode, int rad, uint32_t k0, uint32_t k1,
                                                    int l, int64_t m, PlanesC<double> h,
                                                    int64_t ldh, int k, int64_t chunk,
@@ -213,10 +215,13 @@ __global__ __launch_bounds__(256) void psi_apply_k(int mode, int rad, uint32_t k
   __shared__ qd sh[32][17];
   const int tid = threadIdx.x;
   const int rr = tid & 15, bb = tid >> 4;
-  const int r0 = blockIdx.x * 16, b0 = blockIdx.y * 16;
-  const int64_t is = (int64_t)blockIdx.z * chunk;
+  const int r0 = blockIdx.x * 16;
+  const int nbt = (k + 15) / 16;
+  const int64_t is = (int64_t)blockIdx.y * chunk;
   const int64_t ie = min(m, is + chunk);
-  qd acc = qzero();
+  qd acc[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) acc[t] = qzero();
   for (int64_t i0 = is; i0 < ie; i0 += 32) {
     for (int e = tid; e < 512; e += 256) {
       const int ii = e & 31, q = e >> 5;
@@ -225,17 +230,34 @@ __global__ __launch_bounds__(256) void psi_apply_k(int mode, int rad, uint32_t k
       if (gi < ie && r0 + q < l)
         embed_entry_as_used(mode, rad, (uint32_t)gi, (uint32_t)(r0 + q), STREAM_PSI, k0, k1, v);
       sp[q][ii] = {v[0], v[1], v[2], v[3]};
-      sh[ii][q] = (gi < ie && b0 + q < k) ? load_q(h, gi + (int64_t)(b0 + q) * ldh) : qzero();
+    }
+#pragma unroll
+    for (int bt = 0; bt < 16; ++bt) {
+      if (bt < nbt) {
+        __syncthreads();
+        for (int e = tid; e < 512; e += 256) {
+          const int ii = e & 31, q = e >> 5;
+          const int64_t gi = i0 + ii;
+          const int b = bt * 16 + q;
+          sh[ii][q] = (gi < ie && b < k) ? load_q(h, gi + (int64_t)b * ldh) : qzero();
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int ii = 0; ii < 32; ++ii) qfma(acc[bt], sp[rr][ii], sh[ii][bb]);
+      }
     }
     __syncthreads();
-#pragma unroll 8
-    for (int ii = 0; ii < 32; ++ii) qfma(acc, sp[rr][ii], sh[ii][bb]);
-    __syncthreads();
   }
-  const int gr = r0 + rr, gb = b0 + bb;
-  if (gr < l && gb < k) {
-    double *q = partial + 4 * (((int64_t)blockIdx.z * k + gb) * l + gr);
-    q[0] = acc.w; q[1] = acc.x; q[2] = acc.y; q[3] = acc.z;
+  const int gr = r0 + rr;
+  if (gr < l) {
+#pragma unroll
+    for (int bt = 0; bt < 16; ++bt) {
+      const int gb = bt * 16 + bb;
+      if (bt < nbt && gb < k) {
+        double *q = partial + 4 * (((int64_t)blockIdx.y * k + gb) * l + gr);
+        q[0] = acc[bt].w; q[1] = acc[bt].x; q[2] = acc[bt].y; q[3] = acc[bt].z;
+      }
+    }
   }
 }
 
@@ -243,7 +265,8 @@ hipError_t launch_psi_apply(hipStream_t st, int mode, int rad, uint32_t k0, uint
                             int64_t m, const double *const h[4], int64_t ldh, int k,
                             double *partials, int64_t partial_elems, double *const p[4],
                             int64_t ldp) {
-  const int tiles = ((l + 15) / 16) * ((k + 15) / 16);
+  if (k > 256) return hipErrorInvalidValue;
+  const int tiles = (l + 15) / 16;
   const int64_t per = (int64_t)l * k * 4;
   const int64_t max_chunks = partial_elems / per;
   if (max_chunks < 1) return hipErrorInvalidValue;
@@ -252,7 +275,7 @@ hipError_t launch_psi_apply(hipStream_t st, int mode, int rad, uint32_t k0, uint
   if (nch > max_chunks) return hipErrorInvalidValue;
   PlanesC<double> hh;
   for (int q = 0; q < 4; ++q) hh.p[q] = h[q];
-  dim3 g((l + 15) / 16, (k + 15) / 16, (unsigned)nch);
+  dim3 g(tiles, (unsigned)nch);
   hipLaunchKernelGGL(psi_apply_k, g, dim3(256), 0, st, mode, rad, k0, k1, l, m, hh, ldh, k, chunk,
                      partials);
   hipError_t e = hipGetLastError();
@@ -421,13 +444,16 @@ __device__ void sm_gemm(int k, const double *a, int opa, const double *b, int op
   __syncthreads();
 }
 
-// Upper Cholesky G' = R^* R; returns in shared `fail` whether a pivot fell
-// below tol * max diagonal.
+// Upper Cholesky G' = R^* R (right-looking, blocked by CB pivot rows held in
+// LDS); returns in shared `fail` whether a pivot fell below tol * max
+// diagonal.  k <= 256.
 __device__ void sm_chol(const double *g, double *r, int k, int complex_only, double shift,
                         double tol, int *fail, double *minp, double *trace) {
-  __shared__ double s_piv;
+  constexpr int CB = 8;
+  __shared__ qd panel[CB][257];
   __shared__ double s_maxd;
-  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < k * k; e += nt) {
     const int i = e % k, j = e / k;
     qd v = qzero();
     if (i <= j) {
@@ -438,7 +464,7 @@ __device__ void sm_chol(const double *g, double *r, int k, int complex_only, dou
     sq_(r, i, j, k, v);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     double md = 0.0, tr = 0.0;
     for (int i = 0; i < k; ++i) { const double d = r[4 * (i + (int64_t)i * k)]; md = fmax(md, d); tr += d; }
     s_maxd = md;
@@ -447,29 +473,45 @@ __device__ void sm_chol(const double *g, double *r, int k, int complex_only, dou
     *minp = 1.0;
   }
   __syncthreads();
-  for (int j = 0; j < k; ++j) {
-    if (threadIdx.x == 0) {
-      const double d = r[4 * (j + (int64_t)j * k)];
-      const double rel = s_maxd > 0.0 ? d / s_maxd : 0.0;
-      if (rel < *minp) *minp = rel;
-      if (!(rel > tol)) *fail = 1;
-      s_piv = sqrt(fmax(d, 0.0));
-      r[4 * (j + (int64_t)j * k)] = s_piv;
+  for (int j0 = 0; j0 < k; j0 += CB) {
+    const int jb = min(CB, k - j0), w = k - j0;
+    for (int e = tid; e < jb * w; e += nt) {
+      const int rr = e / w, cc = e % w;
+      panel[rr][cc] = cc >= rr ? gq(r, j0 + rr, j0 + cc, k) : qzero();
     }
     __syncthreads();
-    if (*fail) return;
-    const double inv = 1.0 / s_piv;
-    for (int c = j + 1 + threadIdx.x; c < k; c += blockDim.x) sq_(r, j, c, k, qscale(gq(r, j, c, k), inv));
-    __syncthreads();
-    const int nrem = k - j - 1;
-    for (int e = threadIdx.x; e < nrem * nrem; e += blockDim.x) {
-      const int aa = e % nrem, cc = e / nrem;
+    for (int rr = 0; rr < jb; ++rr) {
+      if (tid == 0) {
+        const double d = panel[rr][rr].w;
+        const double rel = s_maxd > 0.0 ? d / s_maxd : 0.0;
+        if (rel < *minp) *minp = rel;
+        if (!(rel > tol)) *fail = 1;
+        panel[rr][rr] = {sqrt(fmax(d, 0.0)), 0.0, 0.0, 0.0};
+      }
+      __syncthreads();
+      if (*fail) return;
+      const double inv = 1.0 / panel[rr][rr].w;
+      for (int cc = rr + 1 + tid; cc < w; cc += nt) panel[rr][cc] = qscale(panel[rr][cc], inv);
+      __syncthreads();
+      const int rows = jb - rr - 1;
+      for (int e = tid; e < rows * w; e += nt) {
+        const int r2 = rr + 1 + e / w, cc = e % w;
+        if (cc >= r2) panel[r2][cc] = qsub(panel[r2][cc], qmul(qconj(panel[rr][r2]), panel[rr][cc]));
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < jb * w; e += nt) {
+      const int rr = e / w, cc = e % w;
+      if (cc >= rr) sq_(r, j0 + rr, j0 + cc, k, panel[rr][cc]);
+    }
+    const int nr = k - j0 - jb;
+    for (int e = tid; e < nr * nr; e += nt) {
+      const int aa = e % nr, cc = e / nr;
       if (aa <= cc) {
-        const int ga = j + 1 + aa, gc = j + 1 + cc;
+        const int ga = j0 + jb + aa, gc = j0 + jb + cc;
         qd v = gq(r, ga, gc, k);
-        const qd ra = qconj(gq(r, j, ga, k)), rc = gq(r, j, gc, k);
-        const qd prod = qmul(ra, rc);
-        v = qsub(v, prod);
+        for (int rr = 0; rr < jb; ++rr)
+          v = qsub(v, qmul(qconj(panel[rr][ga - j0]), panel[rr][gc - j0]));
         sq_(r, ga, gc, k, v);
       }
     }
@@ -477,7 +519,8 @@ __device__ void sm_chol(const double *g, double *r, int k, int complex_only, dou
   }
 }
 
-// T = R^{-1} for upper triangular R with real positive diagonal.
+// T = R^{-1} for upper triangular R with real positive diagonal (single
+// workgroup version, used inside drivers).
 __device__ void sm_triinv(const double *r, double *t, int k) {
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
     for (int a = k - 1; a > c; --a) sq_(t, a, c, k, qzero());
@@ -509,6 +552,9 @@ __device__ void sm_jacobi(double *a, int rows, int cols, int lda, int max_sweeps
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int n = cols + (cols & 1);
   if (n < 2) return;
+  // below ~rows * u the inner products are rounding noise: rotating on them
+  // never terminates
+  tol = fmax(tol, 4.0 * rows * 0x1p-53);
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) s_rot = 0;
     __syncthreads();
@@ -579,9 +625,9 @@ __device__ void sm_sorted_columns(const double *a, int rows, int cols, int lda, 
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void chol_inv_kernel(const double *g, int k, int complex_only,
-                                                        double shift, double tol, double *r,
-                                                        double *t, SmallStatus *status) {
+__global__ __launch_bounds__(1024) void chol_kernel(const double *g, int k, int complex_only,
+                                                    double shift, double tol, double *r,
+                                                    SmallStatus *status) {
   __shared__ int fail;
   __shared__ double minp, trace;
   sm_chol(g, r, k, complex_only, shift, tol, &fail, &minp, &trace);
@@ -591,24 +637,140 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(const double *g, int k, 
     status->min_pivot2 = minp;
     status->trace = trace;
   }
-  if (!fail) sm_triinv(r, t, k);
+}
+
+// T = R^{-1}, one workgroup per column c: T[a, c] = -(1/R[a,a]) sum_{b>a} R[a,b] T[b,c]
+// bottom-up, the column held in LDS.  Skipped when the Cholesky failed.
+__global__ __launch_bounds__(256) void triinv_kernel(const double *r, double *t, int k,
+                                                     const SmallStatus *status) {
+  __shared__ qd col[256];
+  __shared__ qd red[4];
+  if (status && status->fail) return;
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int a = tid; a < k; a += 256) col[a] = qzero();
+  __syncthreads();
+  if (tid == 0) col[c] = {1.0 / r[4 * (c + (int64_t)c * k)], 0.0, 0.0, 0.0};
+  __syncthreads();
+  for (int a = c - 1; a >= 0; --a) {
+    qd s = qzero();
+    for (int b = a + 1 + tid; b <= c; b += 256) qfma(s, gq(r, a, b, k), col[b]);
+    s.w = wave_sum(s.w); s.x = wave_sum(s.x); s.y = wave_sum(s.y); s.z = wave_sum(s.z);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    if (tid == 0) {
+      const qd tot = qadd(qadd(red[0], red[1]), qadd(red[2], red[3]));
+      col[a] = qscale(tot, -1.0 / r[4 * (a + (int64_t)a * k)]);
+    }
+    __syncthreads();
+  }
+  for (int a = tid; a < k; a += 256) sq_(t, a, c, k, col[a]);
 }
 
 hipError_t launch_chol_inv(hipStream_t st, const double *g, int k, int complex_only, double shift,
                            double tol, double *r, double *t, SmallStatus *status) {
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), 0, st, g, k, complex_only, shift, tol, r,
-                     t, status);
+  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(1024), 0, st, g, k, complex_only, shift, tol, r,
+                     status);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(triinv_kernel, dim3(k), dim3(256), 0, st, (const double *)r, t, k,
+                     (const SmallStatus *)status);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(1024) void small_gemm_kernel(int k, const double *a, int opa,
+// C = opA(A) opB(B) for k x k AoS matrices: 16 x 16 output tiles per block,
+// 16-wide slabs of A and B staged in LDS.
+__global__ __launch_bounds__(256) void qgemm_small_kernel(int k, const double *a, int opa,
                                                           const double *b, int opb, double *c) {
-  sm_gemm(k, a, opa, b, opb, c);
+  __shared__ qd sa[16][17];
+  __shared__ qd sb[16][17];
+  const int tid = threadIdx.x, ti = tid & 15, tj = tid >> 4;
+  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+  qd acc = qzero();
+  for (int t0 = 0; t0 < k; t0 += 16) {
+    {
+      const int gi = i0 + ti, gt = t0 + tj;
+      qd v = qzero();
+      if (gi < k && gt < k) v = opa ? qconj(gq(a, gt, gi, k)) : gq(a, gi, gt, k);
+      sa[ti][tj] = v;
+      const int gt2 = t0 + ti, gj = j0 + tj;
+      qd u = qzero();
+      if (gt2 < k && gj < k) u = opb ? qconj(gq(b, gj, gt2, k)) : gq(b, gt2, gj, k);
+      sb[ti][tj] = u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tt = 0; tt < 16; ++tt) qfma(acc, sa[ti][tt], sb[tt][tj]);
+    __syncthreads();
+  }
+  if (i0 + ti < k && j0 + tj < k) sq_(c, i0 + ti, j0 + tj, k, acc);
 }
 
 hipError_t launch_small_gemm(hipStream_t st, int k, const double *a, int opa, const double *b,
                              int opb, double *c) {
-  hipLaunchKernelGGL(small_gemm_kernel, dim3(1), dim3(1024), 0, st, k, a, opa, b, opb, c);
+  dim3 g((k + 15) / 16, (k + 15) / 16);
+  hipLaunchKernelGGL(qgemm_small_kernel, g, dim3(256), 0, st, k, a, opa, b, opb, c);
+  return hipGetLastError();
+}
+
+// One correction step's eps and M (eq. CondNumReductionIter in the k x k
+// space): n_power normalised power iterates v <- G^{-1} v from the Philox
+// stream-2 start vector of step `step`, eps = (v^* G^{-1} v)^{-1/2}, and
+// M = (1 - eps) I + eps G^{-1}.
+__global__ __launch_bounds__(1024) void power_m_kernel(int k, const double *gi, int step, int n_power,
+                                                       uint32_t k0, uint32_t k1, double *m_out,
+                                                       SmallStatus *status) {
+  __shared__ double v[4 * 256], w[4 * 256];
+  __shared__ double s_nrm, s_eps;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < k; i += blockDim.x) {
+    double e[4];
+    gauss_entry_f64((uint32_t)i, (uint32_t)step, STREAM_POWER, k0, k1, e);
+    v[4 * i] = e[0]; v[4 * i + 1] = e[1]; v[4 * i + 2] = e[2]; v[4 * i + 3] = e[3];
+  }
+  __syncthreads();
+  for (int it = 0; it <= n_power; ++it) {
+    if (tid == 0) {
+      double s = 0.0;
+      for (int i = 0; i < 4 * k; ++i) s += v[i] * v[i];
+      s_nrm = sqrt(s);
+    }
+    __syncthreads();
+    for (int i = tid; i < 4 * k; i += blockDim.x) v[i] /= s_nrm;
+    __syncthreads();
+    for (int i = tid; i < k; i += blockDim.x) {
+      qd s = qzero();
+      for (int t2 = 0; t2 < k; ++t2)
+        qfma(s, gq(gi, i, t2, k), {v[4 * t2], v[4 * t2 + 1], v[4 * t2 + 2], v[4 * t2 + 3]});
+      w[4 * i] = s.w; w[4 * i + 1] = s.x; w[4 * i + 2] = s.y; w[4 * i + 3] = s.z;
+    }
+    __syncthreads();
+    if (it == n_power) {
+      if (tid == 0) {
+        double rho = 0.0;
+        for (int i = 0; i < 4 * k; ++i) rho += v[i] * w[i];      // Re(v^* w)
+        s_eps = 1.0 / sqrt(rho);
+        status->eps[status->n_eps] = s_eps;
+        status->n_eps += 1;
+      }
+      __syncthreads();
+    } else {
+      for (int i = tid; i < 4 * k; i += blockDim.x) v[i] = w[i];
+      __syncthreads();
+    }
+  }
+  const double eps = s_eps;
+  for (int e = tid; e < k * k; e += blockDim.x) {
+    const int i = e % k, j = e / k;
+    qd gv = qscale(gq(gi, i, j, k), eps);
+    if (i == j) gv.w += 1.0 - eps;
+    sq_(m_out, i, j, k, gv);
+  }
+}
+
+hipError_t launch_power_m(hipStream_t st, int k, const double *gi, int step, int n_power,
+                          uint32_t k0, uint32_t k1, double *m_out, SmallStatus *status) {
+  hipLaunchKernelGGL(power_m_kernel, dim3(1), dim3(1024), 0, st, k, gi, step, n_power, k0, k1, m_out,
+                     status);
   return hipGetLastError();
 }
 
@@ -619,128 +781,40 @@ hipError_t launch_identity(hipStream_t st, int k, double *c) {
   return hipGetLastError();
 }
 
-// pseudo-QR correction steps in the k x k space.  With H_j = H0 C_j and
-// G_j = H_j^* H_j, one step (eq. CondNumReductionIter) is
-//   H_{j+1} = (1 - eps) H_j + eps (H_j^dagger)^* = H_j M_j,
-//   M_j = (1 - eps) I + eps G_j^{-1}    ((H^dagger)^* = H G^{-1}),
-// so C_{j+1} = C_j M_j and G_{j+1} = M_j^* G_j M_j.  eps comes from n_power
-// normalised power iterates v <- G_j^{-1} v started from Philox stream 2,
-// eps = (v^* G_j^{-1} v)^{-1/2}.
-__global__ __launch_bounds__(1024) void pqr_corrections_kernel(int k, const double *g0, int n_corr,
-                                                               int n_power, uint32_t k0,
-                                                               uint32_t k1, double *c,
-                                                               double *work, SmallStatus *status) {
-  __shared__ int fail;
-  __shared__ double minp, trace, s_eps, s_nrm;
-  const int64_t kk = (int64_t)k * k * 4;
-  double *G = work, *R = work + kk, *T = work + 2 * kk, *Gi = work + 3 * kk, *M = work + 4 * kk,
-         *tmp = work + 5 * kk, *v = work + 6 * kk, *w = v + 4 * k;
-  sm_copy(G, g0, (int)kk);
-  sm_identity(c, k);
-  if (threadIdx.x == 0) { status->n_eps = 0; status->flags = 0; }
-  for (int j = 0; j < n_corr; ++j) {
-    sm_chol(G, R, k, 0, 0.0, 1e-13, &fail, &minp, &trace);
-    __syncthreads();
-    if (fail) {
-      if (threadIdx.x == 0) status->flags |= 2;        // QSK_FLAG_RANK_DEFICIENT
-      break;
-    }
-    sm_triinv(R, T, k);
-    sm_gemm(k, T, 0, T, 1, Gi);                        // G^{-1} = T T^*
-    // start vector
-    for (int i = threadIdx.x; i < k; i += blockDim.x) {
-      double e[4];
-      gauss_entry_f64((uint32_t)i, (uint32_t)j, STREAM_POWER, k0, k1, e);
-      v[4 * i] = e[0]; v[4 * i + 1] = e[1]; v[4 * i + 2] = e[2]; v[4 * i + 3] = e[3];
-    }
-    __syncthreads();
-    for (int it = 0; it <= n_power; ++it) {
-      // normalise v
-      if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < 4 * k; ++i) s += v[i] * v[i];
-        s_nrm = sqrt(s);
-      }
-      __syncthreads();
-      for (int i = threadIdx.x; i < 4 * k; i += blockDim.x) v[i] /= s_nrm;
-      __syncthreads();
-      // w = G^{-1} v
-      for (int i = threadIdx.x; i < k; i += blockDim.x) {
-        qd s = qzero();
-        for (int t2 = 0; t2 < k; ++t2) qfma(s, gq(Gi, i, t2, k), {v[4 * t2], v[4 * t2 + 1], v[4 * t2 + 2], v[4 * t2 + 3]});
-        w[4 * i] = s.w; w[4 * i + 1] = s.x; w[4 * i + 2] = s.y; w[4 * i + 3] = s.z;
-      }
-      __syncthreads();
-      if (it == n_power) {
-        if (threadIdx.x == 0) {
-          double rho = 0.0;
-          for (int i = 0; i < 4 * k; ++i) rho += v[i] * w[i];     // Re(v^* w)
-          s_eps = 1.0 / sqrt(rho);
-        }
-        __syncthreads();
-      } else {
-        for (int i = threadIdx.x; i < 4 * k; i += blockDim.x) v[i] = w[i];
-        __syncthreads();
-      }
-    }
-    const double eps = s_eps;
-    for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
-      const int i = e % k, jj = e / k;
-      qd gv = qscale(gq(Gi, i, jj, k), eps);
-      if (i == jj) gv.w += 1.0 - eps;
-      sq_(M, i, jj, k, gv);
-    }
-    __syncthreads();
-    sm_gemm(k, c, 0, M, 0, tmp);                       // C <- C M
-    sm_copy(c, tmp, (int)kk);
-    sm_gemm(k, G, 0, M, 0, tmp);                       // G <- M^* (G M)
-    sm_gemm(k, M, 1, tmp, 0, G);
-    if (threadIdx.x == 0) {
-      status->eps[status->n_eps] = eps;
-      status->n_eps += 1;
-    }
-    __syncthreads();
-  }
-}
+__device__ void sm_heev(double *g, int k, double *lam, double *U, double *work);
 
-hipError_t launch_pqr_corrections(hipStream_t st, int k, const double *g0, int n_corr, int n_power,
-                                  uint32_t k0, uint32_t k1, double *c, double *work,
-                                  SmallStatus *status) {
-  hipLaunchKernelGGL(pqr_corrections_kernel, dim3(1), dim3(1024), 0, st, k, g0, n_corr, n_power, k0,
-                     k1, c, work, status);
-  return hipGetLastError();
-}
-
-// pseudo-SVD (Alg. 3) on R_Y, with Y = Q_Y R_Y and Q_Y orthonormal: the
-// complex SVD of chi_Y is chi_{Q_Y} times the SVD of chi_{R_Y}, which the
-// quaternion one-sided Jacobi returns with every singular value paired.
-// Pair rule: pair i is good iff sigma_i > TAU_S sigma_0 and it is separated
-// from its neighbours by more than tau_p sigma_0 (tau_p = 64 * 2k * 2^-53).
-// Bad part: B = [u_b..., -u_b j ...] (the two members of each bad pair),
-// B diag(f) with f from Philox stream 3, Jacobi SVD, one column per pair of
-// the leading 2t.  Output C (k x k): H = Q_Y C = [H_g, H_b~].
-__global__ __launch_bounds__(1024) void psvd_select_kernel(int k, const double *ry, uint32_t k0,
+// pseudo-SVD (Alg. 3) with Y = Q_Y R_Y, Q_Y orthonormal: the complex SVD of
+// chi_Y is chi_{Q_Y} times that of chi_{R_Y}, whose left singular vectors
+// are the eigenvectors of G_L = R_Y R_Y^* (computed by the structure-
+// preserving quaternion eigensolver above, so every singular value comes
+// paired).  Pair rule: pair i is good iff sigma_i > TAU_S sigma_0 and it is
+// separated from its neighbours by more than tau_p sigma_0 (tau_p = 64 * 2k *
+// 2^-53).  Bad part: B = [u_b..., -u_b j ...] (the two members of each bad
+// pair), B diag(f) with f from Philox stream 3, Jacobi SVD, one column per
+// pair of the leading 2t.  Output C (k x k): H = Q_Y C = [H_g, H_b~].
+__global__ __launch_bounds__(1024) void psvd_select_kernel(int k, double *gl, uint32_t k0,
                                                            uint32_t k1, double *c, double *work,
                                                            SmallStatus *status) {
   __shared__ int order[512];
   __shared__ double sig[512];
+  __shared__ double lam[256];
   __shared__ int good[256];
   __shared__ int n_good, n_bad;
   const int64_t kk = (int64_t)k * k * 4;
-  double *A = work, *U = work + kk, *B = work + 2 * kk, *UB = work + 2 * kk + 2 * kk;
-  sm_copy(A, ry, (int)kk);
-  sm_jacobi(A, k, k, k, 60, 1e-15);
+  double *U = work, *B = work + kk, *UB = work + 3 * kk, *EW = work + 5 * kk;
+  sm_heev(gl, k, lam, U, EW);
+  // descending order of sigma = sqrt(max(lambda, 0))
+  for (int i = threadIdx.x; i < k; i += blockDim.x) sig[i] = sqrt(fmax(lam[k - 1 - i], 0.0));
   __syncthreads();
-  sm_sorted_columns(A, k, k, k, sig, order, U, k);
   if (threadIdx.x == 0) {
-    const double s0 = sig[order[0]];
+    const double s0 = sig[0];
     const double tau_p = 64.0 * 2.0 * k * 0x1p-53;
     int ng = 0;
     for (int i = 0; i < k; ++i) {
-      const double si = sig[order[i]];
+      const double si = sig[i];
       bool ok = si > 1e-13 * s0;
-      if (ok && i > 0) ok = (sig[order[i - 1]] - si) > tau_p * s0;
-      if (ok && i < k - 1) ok = (si - sig[order[i + 1]]) > tau_p * s0;
+      if (ok && i > 0) ok = (sig[i - 1] - si) > tau_p * s0;
+      if (ok && i < k - 1) ok = (si - sig[i + 1]) > tau_p * s0;
       good[i] = ok ? 1 : 0;
       ng += ok ? 1 : 0;
     }
@@ -749,38 +823,28 @@ __global__ __launch_bounds__(1024) void psvd_select_kernel(int k, const double *
     status->t_bad = k - ng;
     status->good_count = ng;
     if (k - ng > 0) status->flags |= 8;
-  }
-  __syncthreads();
-  // good columns first
-  if (threadIdx.x == 0) {
     int g = 0, b = 0;
-    for (int i = 0; i < k; ++i) {
-      if (good[i]) order[i] = g++;
-      else order[i] = -(1 + b++);
-    }
+    for (int i = 0; i < k; ++i) order[i] = good[i] ? g++ : -(1 + b++);
   }
   __syncthreads();
   const int t = n_bad;
   for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
-    const int i = e % k, j = e / k;
+    const int i = e % k, j = e / k;            // j: descending singular value index
     const int dst = order[j];
-    const qd uv = gq(U, i, j, k);
+    const qd uv = gq(U, i, k - 1 - j, k);
     if (dst >= 0) {
       sq_(c, i, dst, k, uv);
     } else {
       const int bi = -dst - 1;
-      double f1[4], f2[4];
-      (void)f2;
       // f_j = 1 + u_j, u_j = (x0 + 1/2) 2^-32 from counter (j, 0, 3, 0)
       const u32x4 xa = philox((uint32_t)bi, 0u, STREAM_DIAGF, 0u, k0, k1);
       const u32x4 xb = philox((uint32_t)(t + bi), 0u, STREAM_DIAGF, 0u, k0, k1);
-      f1[0] = 1.0 + ((double)xa.x0 + 0.5) * 0x1p-32;
-      f2[0] = 1.0 + ((double)xb.x0 + 0.5) * 0x1p-32;
-      // first member u, second member -u j (the partner of u's compact
-      // representation, J conj(u_c), is the compact representation of -u j)
-      sq_(B, i, bi, k, qscale(uv, f1[0]));
-      const qd uj = qmul(uv, {0.0, 0.0, 1.0, 0.0});
-      sq_(B, i, t + bi, k, qscale(uj, -f2[0]));
+      const double fa = 1.0 + ((double)xa.x0 + 0.5) * 0x1p-32;
+      const double fb = 1.0 + ((double)xb.x0 + 0.5) * 0x1p-32;
+      // first member u, second member -u j (J conj(u_c) is the compact
+      // representation of -u j)
+      sq_(B, i, bi, k, qscale(uv, fa));
+      sq_(B, i, t + bi, k, qscale(qmul(uv, {0.0, 0.0, 1.0, 0.0}), -fb));
     }
   }
   __syncthreads();
@@ -799,9 +863,9 @@ __global__ __launch_bounds__(1024) void psvd_select_kernel(int k, const double *
   }
 }
 
-hipError_t launch_psvd_select(hipStream_t st, int k, const double *ry, uint32_t k0, uint32_t k1,
+hipError_t launch_psvd_select(hipStream_t st, int k, double *gl, uint32_t k0, uint32_t k1,
                               double *c, double *work, SmallStatus *status) {
-  hipLaunchKernelGGL(psvd_select_kernel, dim3(1), dim3(1024), 0, st, k, ry, k0, k1, c, work, status);
+  hipLaunchKernelGGL(psvd_select_kernel, dim3(1), dim3(1024), 0, st, k, gl, k0, k1, c, work, status);
   return hipGetLastError();
 }
 
@@ -862,49 +926,313 @@ hipError_t launch_pinv_sstar(hipStream_t st, int l, int k, const double *const p
   return hipGetLastError();
 }
 
-// kappa of H = Z F from G_Z = Z^* Z: G_H = F^* G_Z F; R = chol(G_H);
-// singular values of R (Jacobi) are those of H.  which: 0 -> status->kappa,
-// 1 -> status->kappa_initial.  Also the orthonormality defect max|G_H - I|.
-__global__ __launch_bounds__(1024) void kappa_kernel(int k, const double *gz, const double *f,
-                                                     double *work, int which, SmallStatus *status) {
-  __shared__ int fail;
-  __shared__ double minp, trace;
-  __shared__ int order[512];
-  __shared__ double sig[512];
+// Householder reduction of a k x k quaternion Hermitian matrix (in place, in
+// global memory) to a real symmetric tridiagonal with the same eigenvalues:
+// for column j, x = G[j+1:, j], alpha = -(x_0 / |x_0|) ||x||, v = x - alpha e_1,
+// beta = 2 / ||v||^2 (the reflector I - beta v v^* is unitary and Hermitian over
+// the quaternions), p = beta G' v, w = p - (beta / 2) Re(v^* p) v,
+// G' <- G' - v w^* - w v^*.  Diagonal d_j = Re G[j, j], off-diagonal
+// magnitudes e_j = |alpha_j| (a diagonal unitary scaling makes them real).
+__device__ void sm_tridiag(double *g, int k, double *d, double *e, double *hv = nullptr,
+                           double *hbeta = nullptr, double *halpha = nullptr) {
+  __shared__ qd v[256], pv[256];
+  __shared__ qd part[4][256];
+  __shared__ double s_red[16];
+  __shared__ double s_beta, s_k;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  for (int j = 0; j + 1 < k; ++j) {
+    const int n = k - j - 1, o = j + 1;
+    // ||x||^2
+    double loc = 0.0;
+    for (int a = tid; a < n; a += blockDim.x) loc += qnorm2(gq(g, o + a, j, k));
+    loc = wave_sum(loc);
+    if (lane == 0) s_red[wave] = loc;
+    __syncthreads();
+    if (tid == 0) {
+      double xn2 = 0.0;
+      for (int q = 0; q < nw; ++q) xn2 += s_red[q];
+      const double xn = sqrt(xn2);
+      const qd x0 = gq(g, o, j, k);
+      const double ax0 = sqrt(qnorm2(x0));
+      e[j] = xn;
+      if (xn == 0.0) {
+        s_beta = 0.0;
+        if (halpha) { halpha[4 * j] = 0.0; halpha[4 * j + 1] = 0.0; halpha[4 * j + 2] = 0.0; halpha[4 * j + 3] = 0.0; }
+      } else {
+        const qd u = ax0 > 0.0 ? qscale(x0, 1.0 / ax0) : qd{1.0, 0.0, 0.0, 0.0};
+        const qd alpha = qscale(u, -xn);
+        v[0] = qsub(x0, alpha);
+        s_beta = 1.0 / (xn2 + xn * ax0);               // 2 / ||v||^2
+        if (halpha) { halpha[4 * j] = alpha.w; halpha[4 * j + 1] = alpha.x; halpha[4 * j + 2] = alpha.y; halpha[4 * j + 3] = alpha.z; }
+      }
+      if (hbeta) hbeta[j] = s_beta;
+    }
+    __syncthreads();
+    const double beta = s_beta;
+    if (beta != 0.0) {
+      for (int a = 1 + tid; a < n; a += blockDim.x) v[a] = gq(g, o + a, j, k);
+      __syncthreads();
+      if (hv)
+        for (int a = tid; a < n; a += blockDim.x) sq_(hv, a, j, k, v[a]);
+      // p = beta G' v: four column groups, summed in LDS
+      const int grp = tid >> 8, a = tid & 255;
+      if (a < n) {
+        qd s = qzero();
+        for (int c = grp; c < n; c += 4) qfma(s, gq(g, o + a, o + c, k), v[c]);
+        part[grp][a] = s;
+      }
+      __syncthreads();
+      double kl = 0.0;
+      for (int aa = tid; aa < n; aa += blockDim.x) {
+        const qd pa = qscale(qadd(qadd(part[0][aa], part[1][aa]), qadd(part[2][aa], part[3][aa])), beta);
+        pv[aa] = pa;
+        kl += v[aa].w * pa.w + v[aa].x * pa.x + v[aa].y * pa.y + v[aa].z * pa.z;   // Re(conj(v) p)
+      }
+      kl = wave_sum(kl);
+      if (lane == 0) s_red[wave] = kl;
+      __syncthreads();
+      if (tid == 0) {
+        double t = 0.0;
+        for (int q = 0; q < nw; ++q) t += s_red[q];
+        s_k = 0.5 * beta * t;
+      }
+      __syncthreads();
+      for (int aa = tid; aa < n; aa += blockDim.x) pv[aa] = qsub(pv[aa], qscale(v[aa], s_k));   // w
+      __syncthreads();
+      for (int q = tid; q < n * n; q += blockDim.x) {
+        const int aa = q % n, cc = q / n;
+        qd gv = gq(g, o + aa, o + cc, k);
+        gv = qsub(gv, qmul(v[aa], qconj(pv[cc])));
+        gv = qsub(gv, qmul(pv[aa], qconj(v[cc])));
+        sq_(g, o + aa, o + cc, k, gv);
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < k; i += blockDim.x) d[i] = gq(g, i, i, k).w;
+  __syncthreads();
+}
+
+// Number of eigenvalues of the real symmetric tridiagonal (d, e) below x
+// (Sturm count through the LDL^T pivots of T - x I).
+__device__ int sturm_count(const double *d, const double *e, int k, double x) {
+  int c = 0;
+  double q = d[0] - x;
+  if (q < 0.0) ++c;
+  for (int i = 1; i < k; ++i) {
+    if (q == 0.0) q = 1e-300;
+    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    if (q < 0.0) ++c;
+  }
+  return c;
+}
+
+// All eigenvalues (ascending) by bisection, one thread per eigenvalue.
+__device__ void sm_bisect_all(const double *d, const double *e, int k, double *lam) {
+  __shared__ double s_lo, s_hi;
+  if (threadIdx.x == 0) {
+    double lo = d[0], hi = d[0];
+    for (int i = 0; i < k; ++i) {
+      const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < k ? fabs(e[i]) : 0.0);
+      lo = fmin(lo, d[i] - r);
+      hi = fmax(hi, d[i] + r);
+    }
+    const double pad = 1e-14 * fmax(fabs(lo), fabs(hi)) + 1e-300;
+    s_lo = lo - pad;
+    s_hi = hi + pad;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    double lo = s_lo, hi = s_hi;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (sturm_count(d, e, k, mid) > i) hi = mid;
+      else lo = mid;
+    }
+    lam[i] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+}
+
+// Eigenvector of the real symmetric tridiagonal (d, e) for eigenvalue lam by
+// inverse iteration (two solves with the partial-pivoting LU of T - lam I);
+// x and the five LU arrays are private global slices of length k.
+__device__ void inverse_iteration(const double *d, const double *e, int k, double lam, double tnorm,
+                                  double *x, double *dl, double *dd, double *du, double *du2,
+                                  double *pv) {
+  const double tiny = 0x1p-52 * tnorm + 1e-300;
+  for (int j = 0; j < k; ++j) x[j] = 1.0 + 0.001 * j;      // deterministic start
+  for (int j = 0; j < k; ++j) {
+    dd[j] = d[j] - lam;
+    if (j + 1 < k) { dl[j] = e[j]; du[j] = e[j]; }
+    du2[j] = 0.0;
+    pv[j] = 0.0;
+  }
+  for (int j = 0; j + 1 < k; ++j) {
+    if (fabs(dd[j]) >= fabs(dl[j])) {
+      if (dd[j] == 0.0) dd[j] = tiny;
+      const double f = dl[j] / dd[j];
+      dl[j] = f;
+      dd[j + 1] -= f * du[j];
+    } else {
+      const double f = dd[j] / dl[j];
+      dd[j] = dl[j];
+      dl[j] = f;
+      const double t = du[j];
+      du[j] = dd[j + 1];
+      dd[j + 1] = t - f * dd[j + 1];
+      if (j + 2 < k) {
+        du2[j] = du[j + 1];
+        du[j + 1] = -f * du[j + 1];
+      }
+      pv[j] = 1.0;
+    }
+  }
+  if (dd[k - 1] == 0.0) dd[k - 1] = tiny;
+  for (int it = 0; it < 3; ++it) {
+    for (int j = 0; j + 1 < k; ++j) {
+      if (pv[j] != 0.0) { const double t = x[j]; x[j] = x[j + 1]; x[j + 1] = t; }
+      x[j + 1] -= dl[j] * x[j];
+    }
+    x[k - 1] /= dd[k - 1];
+    if (k > 1) x[k - 2] = (x[k - 2] - du[k - 2] * x[k - 1]) / dd[k - 2];
+    for (int j = k - 3; j >= 0; --j) x[j] = (x[j] - du[j] * x[j + 1] - du2[j] * x[j + 2]) / dd[j];
+    double nrm = 0.0;
+    for (int j = 0; j < k; ++j) nrm += x[j] * x[j];
+    nrm = sqrt(nrm);
+    if (!(nrm > 0.0) || !isfinite(nrm)) { for (int j = 0; j < k; ++j) x[j] = (j == 0); nrm = 1.0; }
+    for (int j = 0; j < k; ++j) x[j] /= nrm;
+  }
+}
+
+// Full eigendecomposition of a k x k quaternion Hermitian matrix (destroyed):
+// tridiagonalisation, bisection, inverse iteration with classical Gram-Schmidt
+// (twice) inside clusters of eigenvalues closer than 1e-3 ||T||, and the
+// back-transformation through the diagonal unitary scaling and the
+// Householder reflectors.  Eigenvectors into U (k x k AoS), eigenvalues
+// ascending into lam.  work holds >= 12 k^2 + 8 k doubles.
+__device__ void sm_heev(double *g, int k, double *lam, double *U, double *work) {
+  __shared__ double dd[256], ee[256], hb[256];
+  __shared__ double s_tn;
+  __shared__ double coef[256];
+  const int tid = threadIdx.x;
+  const int64_t kk = (int64_t)k * k;
+  double *HV = work;                 // 4 kk
+  double *X = work + 4 * kk;         // kk (real eigenvectors of T)
+  double *LU = work + 5 * kk;        // 5 kk
+  double *HA = work + 10 * kk;       // 4 k (alpha_j)
+  sm_tridiag(g, k, dd, ee, HV, hb, HA);
+  sm_bisect_all(dd, ee, k, lam);
+  if (tid == 0) {
+    double tn = 0.0;
+    for (int i = 0; i < k; ++i) tn = fmax(tn, fabs(dd[i]) + (i > 0 ? ee[i - 1] : 0.0) + (i + 1 < k ? ee[i] : 0.0));
+    s_tn = tn;
+  }
+  __syncthreads();
+  for (int i = tid; i < k; i += blockDim.x) {
+    double *b = LU + (int64_t)i * 5 * k;
+    inverse_iteration(dd, ee, k, lam[i], s_tn, X + (int64_t)i * k, b, b + k, b + 2 * k, b + 3 * k, b + 4 * k);
+  }
+  __syncthreads();
+  // re-orthogonalise within clusters (ascending order)
+  int c0 = 0;
+  for (int i = 1; i < k; ++i) {
+    if (lam[i] - lam[i - 1] > 1e-3 * s_tn) { c0 = i; continue; }
+    double *xi = X + (int64_t)i * k;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = c0 + tid; j < i; j += blockDim.x) {
+        const double *xj = X + (int64_t)j * k;
+        double s = 0.0;
+        for (int r = 0; r < k; ++r) s += xj[r] * xi[r];
+        coef[j - c0] = s;
+      }
+      __syncthreads();
+      for (int r = tid; r < k; r += blockDim.x) {
+        double s = xi[r];
+        for (int j = c0; j < i; ++j) s -= coef[j - c0] * X[(int64_t)j * k + r];
+        xi[r] = s;
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      double nrm = 0.0;
+      for (int r = 0; r < k; ++r) nrm += xi[r] * xi[r];
+      coef[255] = 1.0 / sqrt(nrm);
+    }
+    __syncthreads();
+    for (int r = tid; r < k; r += blockDim.x) xi[r] *= coef[255];
+    __syncthreads();
+  }
+  // back-transform: y = D x (delta_0 = 1, delta_{j+1} = alpha_j delta_j / |alpha_j|),
+  // then u = H_0 H_1 ... H_{k-2} y
+  for (int i = tid; i < k; i += blockDim.x) {
+    const double *x = X + (int64_t)i * k;
+    qd delta = {1.0, 0.0, 0.0, 0.0};
+    sq_(U, 0, i, k, qscale(delta, x[0]));
+    for (int j = 0; j + 1 < k; ++j) {
+      const qd al = {HA[4 * j], HA[4 * j + 1], HA[4 * j + 2], HA[4 * j + 3]};
+      const double aa = sqrt(qnorm2(al));
+      if (aa > 0.0) delta = qmul(qscale(al, 1.0 / aa), delta);
+      sq_(U, j + 1, i, k, qscale(delta, x[j + 1]));
+    }
+    for (int j = k - 2; j >= 0; --j) {
+      const double beta = hb[j];
+      if (beta == 0.0) continue;
+      const int n = k - j - 1;
+      qd s = qzero();
+      for (int a = 0; a < n; ++a) qfma_cj(s, gq(HV, a, j, k), gq(U, j + 1 + a, i, k));   // v^* y
+      s = qscale(s, beta);
+      for (int a = 0; a < n; ++a)
+        sq_(U, j + 1 + a, i, k, qsub(gq(U, j + 1 + a, i, k), qmul(gq(HV, a, j, k), s)));
+    }
+  }
+  __syncthreads();
+}
+
+// kappa of H from its Gram G_H = H^* H: the eigenvalues of G_H are the
+// squared singular values of H, so kappa(H) = sqrt(lambda_max / lambda_min)
+// (Section 3.1, after Remark 3.1).  which: 0 -> status->kappa (and the
+// orthonormality defect max|G_H - I|), 1 -> status->kappa_initial.
+__global__ __launch_bounds__(1024) void kappa_kernel(int k, const double *gh, double *work, int which,
+                                                     SmallStatus *status) {
+  __shared__ double dd[256], ee[256], lam[256];
   __shared__ double s_def;
   const int64_t kk = (int64_t)k * k * 4;
-  double *tmp = work, *GH = work + kk, *R = work + 2 * kk, *U = work + 3 * kk;
-  sm_gemm(k, gz, 0, f, 0, tmp);
-  sm_gemm(k, f, 1, tmp, 0, GH);
-  if (threadIdx.x == 0) {
-    double d = 0.0;
-    for (int e = 0; e < k * k; ++e) {
-      const int i = e % k, j = e / k;
-      qd v = gq(GH, i, j, k);
+  double *G = work;
+  {
+    __shared__ double s_w[16];
+    double dft = 0.0;
+    for (int q = threadIdx.x; q < k * k; q += blockDim.x) {
+      const int i = q % k, j = q / k;
+      qd v = gq(gh, i, j, k);
       if (i == j) v.w -= 1.0;
-      d = fmax(d, sqrt(qnorm2(v)));
+      dft = fmax(dft, sqrt(qnorm2(v)));
     }
-    s_def = d;
-  }
-  sm_chol(GH, R, k, 0, 0.0, 1e-300, &fail, &minp, &trace);
-  __syncthreads();
-  double kap = INFINITY;
-  if (!fail) {
-    sm_jacobi(R, k, k, k, 60, 1e-15);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dft = fmax(dft, __shfl_xor(dft, off, 64));
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = dft;
     __syncthreads();
-    sm_sorted_columns(R, k, k, k, sig, order, U, k);
-    const double smax = sig[order[0]], smin = sig[order[k - 1]];
-    kap = smin > 0.0 ? smax / smin : INFINITY;
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t = fmax(t, s_w[q]);
+      s_def = t;
+    }
   }
+  sm_copy(G, gh, (int)kk);
+  sm_tridiag(G, k, dd, ee);
+  sm_bisect_all(dd, ee, k, lam);
   if (threadIdx.x == 0) {
+    const double lmin = lam[0], lmax = lam[k - 1];
+    const double kap = lmin > 0.0 ? sqrt(lmax / lmin) : INFINITY;
     if (which == 0) { status->kappa = kap; status->orth_defect = s_def; }
     else status->kappa_initial = kap;
   }
 }
 
-hipError_t launch_kappa(hipStream_t st, int k, const double *gz, const double *f, double *work,
-                        int which, SmallStatus *status) {
-  hipLaunchKernelGGL(kappa_kernel, dim3(1), dim3(1024), 0, st, k, gz, f, work, which, status);
+hipError_t launch_kappa(hipStream_t st, int k, const double *gh, double *work, int which,
+                        SmallStatus *status) {
+  hipLaunchKernelGGL(kappa_kernel, dim3(1), dim3(1024), 0, st, k, gh, work, which, status);
   return hipGetLastError();
 }
 

@@ -30,11 +30,25 @@ struct SketchArgs {
   uint32_t k0, k1;       // Philox key
   void *scratch;         // split-K partial buffer for W (matrix-core path)
   int64_t scratch_bytes;
+  // optional timing: events[2 * kernel] before, [2 * kernel + 1] after (may be null)
+  hipEvent_t *events;
 };
 
 hipError_t launch_sketch_generic(const SketchArgs &s);
+
+// Transient staging buffers of the matrix-core path: this update's Omega_J
+// ([4][KP][NP]) and Psi ([4][LP][MP]) in the operand format, regenerated from
+// the Philox stream on every update.
+struct MfmaStage {
+  void *omega;
+  void *psi;
+  int LP, KP;
+  int64_t MP, NP;
+};
+void stage_geometry(int64_t m, int l, int k, int64_t maxcols, int *LP, int64_t *MP, int *KP,
+                    int64_t *NP);
 // Matrix-core path; returns hipErrorNotSupported for shapes it does not take.
-hipError_t launch_sketch_mfma(const SketchArgs &s);
+hipError_t launch_sketch_mfma(const SketchArgs &s, const MfmaStage &g);
 
 // ---------------------------------------------------------------------------
 // FP64 finalize building blocks (finalize.hip).  Small k x k quaternion
@@ -91,18 +105,18 @@ hipError_t launch_chol_inv(hipStream_t st, const double *g, int k, int complex_o
 // C = opA(A) * opB(B) (k x k AoS; op = 0 none, 1 conjugate transpose).
 hipError_t launch_small_gemm(hipStream_t st, int k, const double *a, int opa, const double *b,
                              int opb, double *c);
-// pseudo-QR corrections in the small space: given G0 = H0* H0, compute
-// C = M_0 ... M_{n-1} and the report entries.
-hipError_t launch_pqr_corrections(hipStream_t st, int k, const double *g0, int n_corr, int n_power,
-                                  uint32_t k0, uint32_t k1, double *c, double *work,
-                                  SmallStatus *status);
-// pseudo-SVD selection on R_Y (k x k): Jacobi SVD, pair rule, bad-part
-// repair; writes the k x k combination C (H = Q_Y C).
-hipError_t launch_psvd_select(hipStream_t st, int k, const double *ry, uint32_t k0, uint32_t k1,
+// One pseudo-QR correction step's eps (power iteration on G^{-1}, recorded
+// in status->eps) and M = (1 - eps) I + eps G^{-1}, given gi = G^{-1}.
+hipError_t launch_power_m(hipStream_t st, int k, const double *gi, int step, int n_power,
+                          uint32_t k0, uint32_t k1, double *m_out, SmallStatus *status);
+// pseudo-SVD selection from G_L = R_Y R_Y^* (k x k, destroyed): quaternion
+// eigensolver, pair rule, bad-part repair; writes the k x k combination C
+// (H = Q_Y C).  work: >= 17 k^2 + 8 k quaternion-sized doubles.
+hipError_t launch_psvd_select(hipStream_t st, int k, double *gl, uint32_t k0, uint32_t k1,
                               double *c, double *work, SmallStatus *status);
-// kappa of H = Z F from G_Z: G_H = F^* G_Z F, chol, Jacobi singular values.
-hipError_t launch_kappa(hipStream_t st, int k, const double *gz, const double *f, double *work,
-                        int which, SmallStatus *status);
+// kappa of H from G_H = H^* H: chol, Jacobi singular values.
+hipError_t launch_kappa(hipStream_t st, int k, const double *gh, double *work, int which,
+                        SmallStatus *status);
 // S^* = (P^dagger)^* (l x k planar) for a rank-deficient P by a Jacobi SVD
 // of [P; I]; work holds (l + k) k quaternions.
 hipError_t launch_pinv_sstar(hipStream_t st, int l, int k, const double *const p[4], int64_t ldp,

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/qsketch.h"
 #include "qsk_kernels.hpp"
@@ -48,6 +49,13 @@ struct qsk_ctx {
   SmallStatus *status = nullptr;
   void *w_scratch = nullptr;           // split-K partials of the matrix-core W kernel
   int64_t w_scratch_bytes = 0;
+  qsk::MfmaStage stage{};              // transient test-matrix slices (matrix-core path)
+  // optional per-kernel timing of updates
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;     // 8 events per recorded update
+  size_t ev_used = 0;
+  double t_ms[4] = {0, 0, 0, 0};
+  int64_t t_count[4] = {0, 0, 0, 0};
   int use_mfma = 1;
 };
 
@@ -83,9 +91,32 @@ qsk_status hip_fail(qsk_ctx *c, hipError_t e, const char *where) {
     if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr); \
   } while (0)
 
+void resolve_timing(qsk_ctx *c) {
+  for (size_t u = 0; u + 8 <= c->ev_used; u += 8) {
+    for (int kk = 0; kk < 4; ++kk) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev_pool[u + 2 * kk], c->ev_pool[u + 2 * kk + 1]) == hipSuccess) {
+        c->t_ms[kk] += ms;
+        c->t_count[kk] += 1;
+      } else {
+        (void)hipGetLastError();
+      }
+    }
+  }
+  c->ev_used = 0;
+}
+
+void free_events(qsk_ctx *c) {
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  c->ev_pool.clear();
+  c->ev_used = 0;
+}
+
 void free_all(qsk_ctx *c) {
+  free_events(c);
   void *ptrs[] = {c->y, c->w, c->u[0], c->u[1], c->small, c->work, c->partials, c->pbuf,
-                  c->p1buf, c->sbuf, c->err_acc, c->status, c->w_scratch, c->pinv_work};
+                  c->p1buf, c->sbuf, c->err_acc, c->status, c->w_scratch, c->pinv_work,
+                  c->stage.omega, c->stage.psi};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->y = c->w = nullptr;
@@ -94,6 +125,7 @@ void free_all(qsk_ctx *c) {
   c->status = nullptr;
   c->w_scratch = nullptr;
   c->pinv_work = nullptr;
+  c->stage.omega = c->stage.psi = nullptr;
 }
 
 bool alloc(void **p, size_t bytes) {
@@ -108,7 +140,7 @@ bool alloc(void **p, size_t bytes) {
 
 // Offsets of the k x k matrices inside ctx->small.
 enum SmallSlot { S_G1 = 0, S_GU, S_R, S_T, S_RPROD, S_RTMP, S_G0, S_TMP, S_C, S_F, S_GP, S_RP,
-                 S_TP1, S_TP2, S_TPT, S_Z, S_COUNT };
+                 S_TP1, S_TP2, S_TPT, S_Z, S_CR, S_CT, S_GI, S_M, S_TMP2, S_GH, S_COUNT };
 
 double *slot(qsk_ctx *c, int s) { return c->small + (size_t)s * c->cfg.k * c->cfg.k * 4; }
 
@@ -135,6 +167,26 @@ const char *qsketch_last_error(const qsk_ctx *ctx) {
 }
 
 void *qsketch_stream(const qsk_ctx *ctx) { return ctx ? (void *)ctx->stream : nullptr; }
+
+qsk_status qsketch_set_timing(qsk_ctx *ctx, int enable) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->ev_used = 0;
+  for (int i = 0; i < 4; ++i) { ctx->t_ms[i] = 0.0; ctx->t_count[i] = 0; }
+  ctx->timing = enable != 0;
+  return QSK_OK;
+}
+
+qsk_status qsketch_get_timing(qsk_ctx *ctx, int kernel, double *total_ms, int64_t *launches) {
+  if (!ctx || kernel < 0 || kernel > 3 || !total_ms || !launches) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  resolve_timing(ctx);
+  *total_ms = ctx->t_ms[kernel];
+  *launches = ctx->t_count[kernel];
+  return QSK_OK;
+}
 
 qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) {
   if (!cfg || !out) return QSK_E_ARG;
@@ -173,7 +225,7 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   ok = ok && alloc((void **)&ctx->u[0], 4 * (size_t)m * k * 8);
   ok = ok && alloc((void **)&ctx->u[1], 4 * (size_t)m * k * 8);
   ok = ok && alloc((void **)&ctx->small, S_COUNT * kk * 8);
-  ok = ok && alloc((void **)&ctx->work, (8 * kk + 16 * (size_t)k) * 8);
+  ok = ok && alloc((void **)&ctx->work, (12 * kk + 64 * (size_t)k) * 8);
   const int64_t maxk = l > k ? l : k;
   ctx->partial_elems = 64 * maxk * k * 4;
   ok = ok && alloc((void **)&ctx->partials, (size_t)ctx->partial_elems * 8);
@@ -183,10 +235,16 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   ok = ok && alloc((void **)&ctx->err_acc, 2 * 8);
   ok = ok && alloc((void **)&ctx->pinv_work, 4 * (size_t)(l + k) * k * 8);
   ok = ok && alloc((void **)&ctx->status, sizeof(SmallStatus));
-  // W split-K partials for the matrix-core path: up to 16 slices of l x maxcols x 4 floats
-  ctx->w_scratch_bytes = (int64_t)16 * l * ctx->cfg.max_block_cols * 4 * 4;
-  if (c.sketch_dtype != QSK_F64) ok = ok && alloc(&ctx->w_scratch, (size_t)ctx->w_scratch_bytes);
-  else ctx->w_scratch_bytes = 0;
+  // matrix-core path: staging of Omega_J / Psi and the W split-K partials
+  if (c.sketch_dtype == QSK_BF16 || c.sketch_dtype == QSK_F32) {
+    qsk::MfmaStage &g = ctx->stage;
+    qsk::stage_geometry(m, (int)l, (int)k, ctx->cfg.max_block_cols, &g.LP, &g.MP, &g.KP, &g.NP);
+    const size_t es = c.sketch_dtype == QSK_BF16 ? 2 : 4;
+    ok = ok && alloc(&g.omega, 4 * (size_t)g.KP * g.NP * es);
+    ok = ok && alloc(&g.psi, 4 * (size_t)g.LP * g.MP * es);
+    ctx->w_scratch_bytes = (int64_t)16 * 4 * ctx->cfg.max_block_cols * g.LP * 4;
+    ok = ok && alloc(&ctx->w_scratch, (size_t)ctx->w_scratch_bytes);
+  }
   if (!ok) {
     free_all(ctx);
     delete ctx;
@@ -249,8 +307,20 @@ qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void 
   s.k0 = ctx->k0; s.k1 = ctx->k1;
   s.scratch = ctx->w_scratch;
   s.scratch_bytes = ctx->w_scratch_bytes;
+  s.events = nullptr;
+  if (ctx->timing && ctx->use_mfma && ctx->mode != qsk::MODE_F64) {
+    if (ctx->ev_used + 8 > ctx->ev_pool.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t ev;
+        HIPCHK(ctx, hipEventCreate(&ev));
+        ctx->ev_pool.push_back(ev);
+      }
+    }
+    s.events = &ctx->ev_pool[ctx->ev_used];
+    ctx->ev_used += 8;
+  }
   hipError_t e = hipErrorNotSupported;
-  if (ctx->use_mfma && ctx->mode != qsk::MODE_F64) e = qsk::launch_sketch_mfma(s);
+  if (ctx->use_mfma && ctx->mode != qsk::MODE_F64) e = qsk::launch_sketch_mfma(s, ctx->stage);
   if (e == hipErrorNotSupported) e = qsk::launch_sketch_generic(s);
   if (e != hipSuccess) return hip_fail(ctx, e, "sketch update");
   ctx->columns_seen += ncols;
@@ -350,17 +420,44 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
   // Now H0 (pseudo-QR) or Q_Y (pseudo-SVD) = Z T with G_Z = gz.
   HIPCHK(ctx, hipMemsetAsync(ctx->status, 0, sizeof(SmallStatus), st));
   if (rf == QSK_PSEUDO_QR) {
+    // G0 = H0^* H0 = T^* G_Z T; kappa of the raw factor
     HIPCHK(ctx, qsk::launch_small_gemm(st, k, gz, 0, slot(ctx, S_T), 0, slot(ctx, S_TMP)));
     HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_T), 1, slot(ctx, S_TMP), 0, slot(ctx, S_G0)));
-    HIPCHK(ctx, qsk::launch_kappa(st, k, gz, slot(ctx, S_T), ctx->work, 1, ctx->status));
-    HIPCHK(ctx, qsk::launch_pqr_corrections(st, k, slot(ctx, S_G0), c.n_correction, c.n_power,
-                                            ctx->k0, ctx->k1, slot(ctx, S_C), ctx->work, ctx->status));
+    HIPCHK(ctx, qsk::launch_kappa(st, k, slot(ctx, S_G0), ctx->work, 1, ctx->status));
+    // correction steps (eq. CondNumReductionIter) in the k x k space: with
+    // H_j = H0 C_j and G_j = H_j^* H_j, H_{j+1} = (1 - eps) H_j + eps (H_j^dagger)^*
+    // = H_j M_j with M_j = (1 - eps) I + eps G_j^{-1}  ((H^dagger)^* = H G^{-1});
+    // C_{j+1} = C_j M_j, G_{j+1} = M_j^* G_j M_j.
+    HIPCHK(ctx, qsk::launch_identity(st, k, slot(ctx, S_C)));
+    for (int j = 0; j < c.n_correction; ++j) {
+      HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_G0), k, 0, 0.0, 1e-13, slot(ctx, S_CR),
+                                       slot(ctx, S_CT), ctx->status));
+      int fail = 0;
+      HIPCHK(ctx, hipMemcpyAsync(&fail, &ctx->status->fail, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(ctx, hipStreamSynchronize(st));
+      if (fail) {
+        flags |= QSK_FLAG_RANK_DEFICIENT;      // G_j singular: no further correction
+        break;
+      }
+      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_CT), 0, slot(ctx, S_CT), 1, slot(ctx, S_GI)));
+      HIPCHK(ctx, qsk::launch_power_m(st, k, slot(ctx, S_GI), j, c.n_power, ctx->k0, ctx->k1,
+                                      slot(ctx, S_M), ctx->status));
+      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_C), 0, slot(ctx, S_M), 0, slot(ctx, S_TMP)));
+      HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_C), slot(ctx, S_TMP), kk * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_G0), 0, slot(ctx, S_M), 0, slot(ctx, S_TMP)));
+      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_M), 1, slot(ctx, S_TMP), 0, slot(ctx, S_G0)));
+    }
   } else {
-    HIPCHK(ctx, qsk::launch_psvd_select(st, k, slot(ctx, S_RPROD), ctx->k0, ctx->k1, slot(ctx, S_C),
+    // G_L = R_Y R_Y^*
+    HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_RPROD), 0, slot(ctx, S_RPROD), 1, slot(ctx, S_TMP)));
+    HIPCHK(ctx, qsk::launch_psvd_select(st, k, slot(ctx, S_TMP), ctx->k0, ctx->k1, slot(ctx, S_C),
                                         ctx->work, ctx->status));
   }
   HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_T), 0, slot(ctx, S_C), 0, slot(ctx, S_F)));
-  HIPCHK(ctx, qsk::launch_kappa(st, k, gz, slot(ctx, S_F), ctx->work, 0, ctx->status));
+  // kappa(Q) from G_Q = F^* G_Z F
+  HIPCHK(ctx, qsk::launch_small_gemm(st, k, gz, 0, slot(ctx, S_F), 0, slot(ctx, S_TMP2)));
+  HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_F), 1, slot(ctx, S_TMP2), 0, slot(ctx, S_GH)));
+  HIPCHK(ctx, qsk::launch_kappa(st, k, slot(ctx, S_GH), ctx->work, 0, ctx->status));
   HIPCHK(ctx, qsk::launch_apply(st, tz, zsrc, m, m, k, slot(ctx, S_F), k, Q, ldq));
 
   // ---- core solve X = (Psi Q)^dagger W (Alg. 2 through the normal form of

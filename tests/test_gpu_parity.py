@@ -87,6 +87,33 @@ def test_sketch_parity_ragged(sketch, dtype, emb, terms, tol):
     assert rel(w, ref.W) < tol
 
 
+MFMA_CASES = [
+    ("f32", "f32", "gaussian", 1, False),
+    ("bf16", "f32", "gaussian", 3, False),
+    ("bf16", "f32", "rademacher", 2, True),
+    ("bf16", "bf16", "rademacher", 1, True),
+]
+
+
+@pytest.mark.parametrize("sketch,dtype,emb,terms,pure", MFMA_CASES)
+def test_matrix_core_sketch_multitile(sketch, dtype, emb, terms, pure):
+    """Shapes that exercise the matrix-core kernels' tiling: 7 column tiles
+    of Y, two row groups of W, several row chunks of A (split K) and ragged
+    edges everywhere.  FP32 accumulation bound 1e-5."""
+    m, n, k, l, block = 1500, 300, 100, 201, 130
+    a = synth.lowrank_plus_noise(m, n, torch.tensor(0.85 ** np.arange(30)), 1e-3, 88).numpy()
+    if pure:
+        a[0] = 0.0
+    a = input_values(a, dtype)
+    sk, _ = run_sketch(a, m, n, k, l, block, dtype=dtype, sketch=sketch, emb=emb, seed=21,
+                       terms=terms, pure=pure)
+    y, w = (to_numpy(t) for t in sk.sketches())
+    cfg = SketchConfig(m, n, k, l, seed=21, embedding=emb, dtype=sketch, terms=terms)
+    ref = sketch_matrix(a, cfg, block_cols=block)
+    assert rel(y, ref.Y) < 1e-5
+    assert rel(w, ref.W) < 1e-5
+
+
 def test_streaming_order_and_pure_input():
     m, n, k, l, block = 200, 160, 8, 17, 32
     a = synth.lowrank_plus_noise(m, n, torch.tensor(0.7 ** np.arange(6)), 1e-3, 78).numpy()
@@ -164,6 +191,17 @@ def test_config1_qb_stage(config1, kind):
     else:
         assert rep["orth_defect"] < 1e-10
         np.testing.assert_allclose(qt.hamilton(qt.conj_t(qn), qn), qt.eye(40), atol=1e-10)
+        # Thm 3.1: the columns are left singular vectors of Y, so Q^* Y Y^* Q is
+        # diagonal, holding sigma_i^2 in descending order
+        y = to_numpy(sk.sketches()[0])
+        g = qt.hamilton(qt.hamilton(qt.conj_t(qn), y), qt.hamilton(qt.conj_t(y), qn))
+        sig2 = qt.singular_values(ref.Y) ** 2
+        dg = g[0].diagonal()
+        top = sig2 > 1e-6 * sig2[0]                    # well-resolved singular values
+        np.testing.assert_allclose(dg[top], sig2[top], rtol=1e-9)
+        off = g.copy()
+        off[0] -= np.diag(dg)
+        assert np.abs(off).max() < 1e-10 * sig2[0]
 
 
 @pytest.mark.parametrize("kind", ["pseudo_qr", "pseudo_svd"])
