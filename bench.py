@@ -18,6 +18,9 @@ Prints one JSON line.  `value` = algorithmic sketch TFLOP/s of the bf16 path
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import platform
@@ -36,6 +39,9 @@ import synth  # noqa: E402
 PEAK_BF16 = 2.5e15     # dense bf16 MFMA, MI355X
 PEAK_F32 = 157.3e12    # fp32 MFMA
 PEAK_HBM = 8e12
+CALIB_BYTES = 256 << 20                    # the plain copy used to scale the HBM counters
+KERNEL_SRC = os.path.join(ROOT, "paper_2404_14783_amd", "csrc", "sketch_mfma.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "w_mfma_c2_bf16x2_traffic.md")
 
 
 def log(*a):
@@ -87,6 +93,90 @@ def cpu_baseline(a_dev, m, n, k, l, block, seconds=20.0):
                       f"(m={m}, k={k}, l={l}, Gaussian, Psi generation included), {dt:.1f} s"}
 
 
+def source_digest():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _pmc_rows(directory):
+    files = glob.glob(os.path.join(directory, "**", "*counter_collection*.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection csv under {directory}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def _per_dispatch(rows, counter):
+    """{dispatch id: (kernel name, value)} for one counter (values summed over
+    the rows of a dispatch)."""
+    out = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter:
+            continue
+        d = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        name, val = out.get(d, (r.get("Kernel_Name", ""), 0.0))
+        out[d] = (name, val + float(r["Counter_Value"]))
+    return out
+
+
+def summarize_traffic(fetch_dir, write_dir, cmd_fetch, cmd_write):
+    """Per-launch HBM traffic of the W kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+    same counter reads for the plain copy of CALIB_BYTES."""
+    fetch = _per_dispatch(_pmc_rows(fetch_dir), "FETCH_SIZE")
+    write = _per_dispatch(_pmc_rows(write_dir), "WRITE_SIZE")
+
+    def pick(tab, key):
+        return [v for (n, v) in tab.values() if key in n]
+    cf = max(pick(fetch, "copyBuffer")) * 1024.0
+    cw = max(pick(write, "copyBuffer")) * 1024.0
+    ff, fw = CALIB_BYTES / cf, CALIB_BYTES / cw
+    wf = pick(fetch, "w_mfma_kernel")
+    ww = pick(write, "w_mfma_kernel")
+    f_avg = float(np.mean(wf)) * 1024.0 * ff
+    w_avg = float(np.mean(ww)) * 1024.0 * fw
+    lines = [
+        "# HBM traffic of w_mfma_kernel: 20000x15000 FP32 quaternion, BF16 2-term sketch, k=100, l=201",
+        "",
+        "Two counter passes over the same program (from the repository root, on one MI355X):",
+        "",
+        f"    {cmd_fetch}",
+        f"    {cmd_write}",
+        "",
+        f"Calibration: a plain copy of {CALIB_BYTES} bytes reads FETCH_SIZE = {cf / 1024:.0f} KiB and "
+        f"WRITE_SIZE = {cw / 1024:.0f} KiB (scale factors {ff:.4f}, {fw:.4f}).",
+        "",
+        "| quantity | value |",
+        "|---|---:|",
+        f"| W-kernel dispatches | {len(wf)} |",
+        f"| FETCH_SIZE per launch (KiB, raw) | {np.mean(wf):.0f} |",
+        f"| WRITE_SIZE per launch (KiB, raw) | {np.mean(ww):.0f} |",
+        f"| fetched bytes per launch (scaled) | {f_avg:.4e} |",
+        f"| written bytes per launch (scaled) | {w_avg:.4e} |",
+        "",
+        f"traffic_bytes_per_launch: {f_avg + w_avg:.6e}",
+        f"kernel_source_sha256_16: {source_digest()}",
+        "",
+    ]
+    with open(TRAFFIC_FILE, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+def committed_traffic():
+    """Per-launch HBM bytes of the W kernel from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines()
+                if line.startswith(("traffic_bytes_per_launch:", "kernel_source_sha256_16:")))
+    if vals.get("kernel_source_sha256_16", "").strip() != source_digest():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,13 +187,18 @@ def main():
     ap.add_argument("--k", type=int, default=100)
     ap.add_argument("--l", type=int, default=201)
     ap.add_argument("--block", type=int, default=2048)
-    ap.add_argument("--terms", type=int, default=3)
+    ap.add_argument("--terms", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-only", action="store_true",
                     help="one bf16 pass only (for rocprofv3 runs)")
+    ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CMD_FETCH", "CMD_WRITE"),
+                    help="write the W-kernel traffic summary from two rocprofv3 --pmc runs")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -120,6 +215,13 @@ def main():
                            sketch_dtype=sketch, split_terms=terms, max_block_cols=block)
 
     if args.profile_only:
+        # a plain copy of known size (one read and one write of CALIB_BYTES)
+        # scales the HBM counters of the profiled kernels
+        src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
         sk = make("bf16", args.terms)
         for _ in range(max(1, args.steps)):
             up, tot, _ = run_pass(sk, a, block)
@@ -178,11 +280,12 @@ def main():
     w_flops_total = 2.0 * 16 * m * n * l * args.steps
     y_flops_total = 2.0 * 16 * m * n * k * args.steps
     w_avg_ms = w_ms / max(w_n, 1)
+    traffic = committed_traffic() if args.terms == 2 and (m, n, k, l, block) == (20000, 15000, 100, 201, 2048) else None
     w_ach = w_flops_total / (w_ms * 1e-3) if w_ms > 0 else 0.0
     y_ach = y_flops_total / (y_ms * 1e-3) if y_ms > 0 else 0.0
     roofline = {"bound": "mfma", "kernel": "w_mfma_kernel (bf16, %d terms)" % args.terms,
                 "achieved": w_ach / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
-                "frac": w_ach / PEAK_BF16, "traffic": None,
+                "frac": w_ach / PEAK_BF16, "traffic": traffic,
                 "avg_launch_ms": w_avg_ms, "launches": w_n,
                 "executed_frac": w_ach * args.terms / PEAK_BF16,
                 "y_kernel_achieved": y_ach / 1e12}

@@ -781,7 +781,9 @@ hipError_t launch_identity(hipStream_t st, int k, double *c) {
   return hipGetLastError();
 }
 
-__device__ void sm_heev(double *g, int k, double *lam, double *U, double *work);
+// LDS pool (doubles) of the tridiagonalisation and of the eigenvector clean-up.
+constexpr int TRI_POOL = 16384;
+__device__ __forceinline__ void sm_heev(double *g, int k, double *lam, double *U, double *work, double *pool);
 
 // pseudo-SVD (Alg. 3) with Y = Q_Y R_Y, Q_Y orthonormal: the complex SVD of
 // chi_Y is chi_{Q_Y} times that of chi_{R_Y}, whose left singular vectors
@@ -800,9 +802,10 @@ __global__ __launch_bounds__(1024) void psvd_select_kernel(int k, double *gl, ui
   __shared__ double lam[256];
   __shared__ int good[256];
   __shared__ int n_good, n_bad;
+  __shared__ double pool[TRI_POOL];
   const int64_t kk = (int64_t)k * k * 4;
   double *U = work, *B = work + kk, *UB = work + 3 * kk, *EW = work + 5 * kk;
-  sm_heev(gl, k, lam, U, EW);
+  sm_heev(gl, k, lam, U, EW, pool);
   // descending order of sigma = sqrt(max(lambda, 0))
   for (int i = threadIdx.x; i < k; i += blockDim.x) sig[i] = sqrt(fmax(lam[k - 1 - i], 0.0));
   __syncthreads();
@@ -926,33 +929,61 @@ hipError_t launch_pinv_sstar(hipStream_t st, int l, int k, const double *const p
   return hipGetLastError();
 }
 
-// Householder reduction of a k x k quaternion Hermitian matrix (in place, in
-// global memory) to a real symmetric tridiagonal with the same eigenvalues:
-// for column j, x = G[j+1:, j], alpha = -(x_0 / |x_0|) ||x||, v = x - alpha e_1,
-// beta = 2 / ||v||^2 (the reflector I - beta v v^* is unitary and Hermitian over
-// the quaternions), p = beta G' v, w = p - (beta / 2) Re(v^* p) v,
+// Householder reduction of a k x k quaternion Hermitian matrix to a real
+// symmetric tridiagonal with the same eigenvalues: for column j,
+// x = G[j+1:, j], alpha = -(x_0 / |x_0|) ||x||, v = x - alpha e_1,
+// beta = 2 / ||v||^2 (the reflector I - beta v v^* is unitary and Hermitian
+// over the quaternions), p = beta G' v, w = p - (beta / 2) Re(v^* p) v,
 // G' <- G' - v w^* - w v^*.  Diagonal d_j = Re G[j, j], off-diagonal
 // magnitudes e_j = |alpha_j| (a diagonal unitary scaling makes them real).
-__device__ void sm_tridiag(double *g, int k, double *d, double *e, double *hv = nullptr,
-                           double *hbeta = nullptr, double *halpha = nullptr) {
-  __shared__ qd v[256], pv[256];
-  __shared__ qd part[4][256];
+//
+// The first steps work on G in global memory (G is destroyed); once the
+// trailing matrix fits, its lower triangle moves to LDS (packed by columns)
+// and the remaining steps run there.  pool: TRI_POOL doubles of LDS.
+
+// packed lower storage of an n0 x n0 block: column s holds rows s..n0-1
+__device__ __forceinline__ int pk(int r, int s, int n0) { return s * n0 - ((s * (s - 1)) >> 1) + (r - s); }
+
+__device__ __forceinline__ void sm_tridiag(double *g, int k, double *d, double *e, double *pool,
+                           double *hv = nullptr, double *hbeta = nullptr, double *halpha = nullptr) {
   __shared__ double s_red[16];
   __shared__ double s_beta, s_k;
+  qd *v = (qd *)pool;                 // up to 256
+  qd *pv = v + 256;                   // up to 256
+  qd *part = pv + 256;                // 4 x 256 (global phase)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  int n0 = 0, o0 = 0;                 // LDS block: rows/cols o0 .. o0 + n0 - 1
+  qd *P = nullptr;
+  #pragma unroll 1
   for (int j = 0; j + 1 < k; ++j) {
     const int n = k - j - 1, o = j + 1;
-    // ||x||^2
+    if (!P && 2 * (n + 1) + (n + 1) * (n + 2) / 2 <= TRI_POOL / 4) {
+      // move the lower triangle of G[j:, j:] to LDS (v, pv then sit at its front)
+      n0 = n + 1;
+      o0 = j;
+      v = (qd *)pool;
+      pv = v + n0;
+      P = pv + n0;
+      #pragma unroll 1
+      for (int s = wave; s < n0; s += nw)
+        #pragma unroll 1
+        for (int r = s + lane; r < n0; r += 64) P[pk(r, s, n0)] = gq(g, o0 + r, o0 + s, k);
+      __syncthreads();
+    }
+    // column j below the diagonal and its norm; d_j
+    if (tid == 0) d[j] = P ? P[pk(j - o0, j - o0, n0)].w : gq(g, j, j, k).w;
     double loc = 0.0;
-    for (int a = tid; a < n; a += blockDim.x) loc += qnorm2(gq(g, o + a, j, k));
+    #pragma unroll 1
+    for (int a = tid; a < n; a += blockDim.x) loc += qnorm2(P ? P[pk(o + a - o0, j - o0, n0)] : gq(g, o + a, j, k));
     loc = wave_sum(loc);
     if (lane == 0) s_red[wave] = loc;
     __syncthreads();
     if (tid == 0) {
       double xn2 = 0.0;
+      #pragma unroll 1
       for (int q = 0; q < nw; ++q) xn2 += s_red[q];
       const double xn = sqrt(xn2);
-      const qd x0 = gq(g, o, j, k);
+      const qd x0 = P ? P[pk(o - o0, j - o0, n0)] : gq(g, o, j, k);
       const double ax0 = sqrt(qnorm2(x0));
       e[j] = xn;
       if (xn == 0.0) {
@@ -969,36 +1000,68 @@ __device__ void sm_tridiag(double *g, int k, double *d, double *e, double *hv = 
     }
     __syncthreads();
     const double beta = s_beta;
-    if (beta != 0.0) {
-      for (int a = 1 + tid; a < n; a += blockDim.x) v[a] = gq(g, o + a, j, k);
-      __syncthreads();
-      if (hv)
-        for (int a = tid; a < n; a += blockDim.x) sq_(hv, a, j, k, v[a]);
-      // p = beta G' v: four column groups, summed in LDS
+    if (beta == 0.0) continue;
+    #pragma unroll 1
+    for (int a = 1 + tid; a < n; a += blockDim.x) v[a] = P ? P[pk(o + a - o0, j - o0, n0)] : gq(g, o + a, j, k);
+    __syncthreads();
+    if (hv)
+      #pragma unroll 1
+      for (int a = tid; a < n; a += blockDim.x) sq_(hv, a, j, k, v[a]);
+    // p = beta G' v
+    if (!P) {
       const int grp = tid >> 8, a = tid & 255;
       if (a < n) {
         qd s = qzero();
+        #pragma unroll 1
         for (int c = grp; c < n; c += 4) qfma(s, gq(g, o + a, o + c, k), v[c]);
-        part[grp][a] = s;
+        part[grp * 256 + a] = s;
       }
       __syncthreads();
-      double kl = 0.0;
-      for (int aa = tid; aa < n; aa += blockDim.x) {
-        const qd pa = qscale(qadd(qadd(part[0][aa], part[1][aa]), qadd(part[2][aa], part[3][aa])), beta);
-        pv[aa] = pa;
-        kl += v[aa].w * pa.w + v[aa].x * pa.x + v[aa].y * pa.y + v[aa].z * pa.z;   // Re(conj(v) p)
+      #pragma unroll 1
+      for (int aa = tid; aa < n; aa += blockDim.x)
+        pv[aa] = qscale(qadd(qadd(part[aa], part[256 + aa]), qadd(part[512 + aa], part[768 + aa])), beta);
+    } else {
+      // row a = tid / 4, four lanes per row (c congruent to sub mod 4);
+      // lower entries L[a, c] (c <= a) and conj(L[c, a]) above
+      const int a = tid >> 2, sub = tid & 3;
+      qd s = qzero();
+      if (a < n) {
+        const int ra = o + a - o0;
+#pragma unroll 1
+        for (int c = sub; c < n; c += 4) {
+          const int rc = o + c - o0;
+          const qd gac = c <= a ? P[pk(ra, rc, n0)] : qconj(P[pk(rc, ra, n0)]);
+          qfma(s, gac, v[c]);
+        }
       }
-      kl = wave_sum(kl);
-      if (lane == 0) s_red[wave] = kl;
+      s.w += __shfl_xor(s.w, 1, 64); s.x += __shfl_xor(s.x, 1, 64);
+      s.y += __shfl_xor(s.y, 1, 64); s.z += __shfl_xor(s.z, 1, 64);
+      s.w += __shfl_xor(s.w, 2, 64); s.x += __shfl_xor(s.x, 2, 64);
+      s.y += __shfl_xor(s.y, 2, 64); s.z += __shfl_xor(s.z, 2, 64);
+      if (a < n && sub == 0) pv[a] = qscale(s, beta);
       __syncthreads();
-      if (tid == 0) {
-        double t = 0.0;
-        for (int q = 0; q < nw; ++q) t += s_red[q];
-        s_k = 0.5 * beta * t;
-      }
-      __syncthreads();
-      for (int aa = tid; aa < n; aa += blockDim.x) pv[aa] = qsub(pv[aa], qscale(v[aa], s_k));   // w
-      __syncthreads();
+    }
+    double kl = 0.0;
+    #pragma unroll 1
+    for (int aa = tid; aa < n; aa += blockDim.x) {
+      const qd pa = pv[aa];
+      kl += v[aa].w * pa.w + v[aa].x * pa.x + v[aa].y * pa.y + v[aa].z * pa.z;   // Re(conj(v) p)
+    }
+    kl = wave_sum(kl);
+    if (lane == 0) s_red[wave] = kl;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      #pragma unroll 1
+      for (int q = 0; q < nw; ++q) t += s_red[q];
+      s_k = 0.5 * beta * t;
+    }
+    __syncthreads();
+    #pragma unroll 1
+    for (int aa = tid; aa < n; aa += blockDim.x) pv[aa] = qsub(pv[aa], qscale(v[aa], s_k));   // w
+    __syncthreads();
+    if (!P) {
+      #pragma unroll 1
       for (int q = tid; q < n * n; q += blockDim.x) {
         const int aa = q % n, cc = q / n;
         qd gv = gq(g, o + aa, o + cc, k);
@@ -1006,10 +1069,23 @@ __device__ void sm_tridiag(double *g, int k, double *d, double *e, double *hv = 
         gv = qsub(gv, qmul(pv[aa], qconj(v[cc])));
         sq_(g, o + aa, o + cc, k, gv);
       }
-      __syncthreads();
+    } else {
+      // lower triangle only: one wave per column
+      #pragma unroll 1
+      for (int cc = wave; cc < n; cc += nw) {
+        const int rc = o + cc - o0;
+        const qd vc = qconj(v[cc]), wc = qconj(pv[cc]);
+#pragma unroll 1
+        for (int aa = cc + lane; aa < n; aa += 64) {
+          qd &gv = P[pk(o + aa - o0, rc, n0)];
+          gv = qsub(gv, qmul(v[aa], wc));
+          gv = qsub(gv, qmul(pv[aa], vc));
+        }
+      }
     }
+    __syncthreads();
   }
-  for (int i = tid; i < k; i += blockDim.x) d[i] = gq(g, i, i, k).w;
+  if (tid == 0) d[k - 1] = P ? P[pk(k - 1 - o0, k - 1 - o0, n0)].w : gq(g, k - 1, k - 1, k).w;
   __syncthreads();
 }
 
@@ -1027,8 +1103,16 @@ __device__ int sturm_count(const double *d, const double *e, int k, double x) {
   return c;
 }
 
-// All eigenvalues (ascending) by bisection, one thread per eigenvalue.
-__device__ void sm_bisect_all(const double *d, const double *e, int k, double *lam) {
+// Selected eigenvalues of the real symmetric tridiagonal (d, e) by
+// multisection: the eigenvalue of ascending index idx[g] (idx == nullptr:
+// index g) for g < cnt goes to lam[g].  A group of P threads (P a power of
+// two <= 64, so a group never spans two waves) evaluates P Sturm counts per
+// round on an even grid of the bracket and keeps the sub-interval where the
+// count passes the index; P + 1 times narrower per round.  Stops at full
+// precision (bracket within a few ulps of its end points) or below
+// u^2 ||T||.
+__device__ __forceinline__ void sm_bisect_sel(const double *d, const double *e, int k, const int *idx, int cnt,
+                              double *lam) {
   __shared__ double s_lo, s_hi;
   if (threadIdx.x == 0) {
     double lo = d[0], hi = d[0];
@@ -1042,27 +1126,64 @@ __device__ void sm_bisect_all(const double *d, const double *e, int k, double *l
     s_hi = hi + pad;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < k; i += blockDim.x) {
-    double lo = s_lo, hi = s_hi;
-    for (int it = 0; it < 200; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (mid <= lo || mid >= hi) break;
-      if (sturm_count(d, e, k, mid) > i) hi = mid;
-      else lo = mid;
+  int P = 64;
+  while (P > 1 && P * cnt > (int)blockDim.x) P >>= 1;
+  const int ngroups = blockDim.x / P;
+  const int grp = threadIdx.x / P, sub = threadIdx.x % P;
+  const int lane_base = (threadIdx.x & 63) & ~(P - 1);
+  const uint64_t gmask = P == 64 ? ~0ull : ((1ull << P) - 1ull);
+  const double floor_w = 0x1p-106 * fmax(fabs(s_lo), fabs(s_hi));
+  // every lane of a wave runs the same number of rounds (the ballot needs the
+  // whole wave): groups past cnt work on a dummy index and store nothing
+  const int rounds_groups = (cnt + ngroups - 1) / ngroups;
+  for (int rg = 0; rg < rounds_groups; ++rg) {
+    const int g = grp + rg * ngroups;
+    const bool active = g < cnt;
+    const int i = active ? (idx ? idx[g] : g) : 0;
+    double lo = s_lo, hi = active ? s_hi : s_lo;     // inactive groups start done
+    for (int it = 0; it < 120; ++it) {
+      const double w = hi - lo;
+      const bool done = w <= 4.0 * 0x1p-53 * fmax(fabs(lo), fabs(hi)) || w <= floor_w;
+      // the wave keeps iterating until all its groups are done
+      if (__ballot(!done) == 0ull) break;
+      const double h = w / (double)(P + 1);
+      const double x = lo + (double)(sub + 1) * h;
+      const bool above = sturm_count(d, e, k, x) > i;    // lambda_i < x
+      const uint64_t bits = (__ballot(above) >> lane_base) & gmask;
+      if (!done) {
+        if (bits == 0ull) {
+          lo = lo + (double)P * h;
+        } else {
+          const int s = __builtin_ctzll(bits);
+          const double nhi = lo + (double)(s + 1) * h;
+          const double nlo = s > 0 ? lo + (double)s * h : lo;
+          lo = nlo;
+          hi = nhi;
+        }
+      }
     }
-    lam[i] = 0.5 * (lo + hi);
+    if (active && sub == 0) lam[g] = 0.5 * (lo + hi);
   }
   __syncthreads();
 }
 
+__device__ void sm_bisect_all(const double *d, const double *e, int k, double *lam) {
+  sm_bisect_sel(d, e, k, nullptr, k, lam);
+}
+
 // Eigenvector of the real symmetric tridiagonal (d, e) for eigenvalue lam by
-// inverse iteration (two solves with the partial-pivoting LU of T - lam I);
-// x and the five LU arrays are private global slices of length k.
+// inverse iteration (three solves with the partial-pivoting LU of T - lam I)
+// from a pseudo-random start (Philox, fixed key, counter (seq, j)) so that
+// equal or nearly equal eigenvalues still give independent vectors; x and the
+// five LU arrays are private global slices of length k.
 __device__ void inverse_iteration(const double *d, const double *e, int k, double lam, double tnorm,
-                                  double *x, double *dl, double *dd, double *du, double *du2,
-                                  double *pv) {
+                                  uint32_t seq, double *x, double *dl, double *dd, double *du,
+                                  double *du2, double *pv) {
   const double tiny = 0x1p-52 * tnorm + 1e-300;
-  for (int j = 0; j < k; ++j) x[j] = 1.0 + 0.001 * j;      // deterministic start
+  for (int j = 0; j < k; ++j) {
+    const u32x4 r = philox(seq, (uint32_t)j, 0x51u, 0u, 0x2545F491u, 0x9E3779B9u);
+    x[j] = ((double)r.x0 + 0.5) * 0x1p-31 - 1.0;
+  }
   for (int j = 0; j < k; ++j) {
     dd[j] = d[j] - lam;
     if (j + 1 < k) { dl[j] = e[j]; du[j] = e[j]; }
@@ -1106,15 +1227,52 @@ __device__ void inverse_iteration(const double *d, const double *e, int k, doubl
   }
 }
 
+// Classical Gram-Schmidt, twice, over the c vectors xs[0..c) (length k,
+// stride k; LDS or global), in order: each vector loses its components along
+// the earlier ones and is normalised.
+__device__ __forceinline__ void cgs2_block(double *xs, int k, int c, double *coef, double *s_nrm) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  for (int i = 1; i < c; ++i) {
+    double *xi = xs + (int64_t)i * k;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = wave; j < i; j += nw) {
+        const double *xj = xs + (int64_t)j * k;
+        double s = 0.0;
+        for (int r = lane; r < k; r += 64) s += xj[r] * xi[r];
+        s = wave_sum(s);
+        if (lane == 0) coef[j] = s;
+      }
+      __syncthreads();
+      for (int r = tid; r < k; r += blockDim.x) {
+        double s = xi[r];
+        for (int j = 0; j < i; ++j) s -= coef[j] * xs[(int64_t)j * k + r];
+        xi[r] = s;
+      }
+      __syncthreads();
+    }
+    if (wave == 0) {
+      double s = 0.0;
+      for (int r = lane; r < k; r += 64) s += xi[r] * xi[r];
+      s = wave_sum(s);
+      if (lane == 0) *s_nrm = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    }
+    __syncthreads();
+    const double sc = *s_nrm;
+    for (int r = tid; r < k; r += blockDim.x) xi[r] *= sc;
+    __syncthreads();
+  }
+}
+
 // Full eigendecomposition of a k x k quaternion Hermitian matrix (destroyed):
 // tridiagonalisation, bisection, inverse iteration with classical Gram-Schmidt
 // (twice) inside clusters of eigenvalues closer than 1e-3 ||T||, and the
 // back-transformation through the diagonal unitary scaling and the
 // Householder reflectors.  Eigenvectors into U (k x k AoS), eigenvalues
-// ascending into lam.  work holds >= 12 k^2 + 8 k doubles.
-__device__ void sm_heev(double *g, int k, double *lam, double *U, double *work) {
+// ascending into lam.  work holds >= 12 k^2 + 8 k doubles; pool is TRI_POOL
+// doubles of LDS.
+__device__ __forceinline__ void sm_heev(double *g, int k, double *lam, double *U, double *work, double *pool) {
   __shared__ double dd[256], ee[256], hb[256];
-  __shared__ double s_tn;
+  __shared__ double s_tn, s_nrm;
   __shared__ double coef[256];
   const int tid = threadIdx.x;
   const int64_t kk = (int64_t)k * k;
@@ -1122,7 +1280,7 @@ __device__ void sm_heev(double *g, int k, double *lam, double *U, double *work) 
   double *X = work + 4 * kk;         // kk (real eigenvectors of T)
   double *LU = work + 5 * kk;        // 5 kk
   double *HA = work + 10 * kk;       // 4 k (alpha_j)
-  sm_tridiag(g, k, dd, ee, HV, hb, HA);
+  sm_tridiag(g, k, dd, ee, pool, HV, hb, HA);
   sm_bisect_all(dd, ee, k, lam);
   if (tid == 0) {
     double tn = 0.0;
@@ -1132,59 +1290,72 @@ __device__ void sm_heev(double *g, int k, double *lam, double *U, double *work) 
   __syncthreads();
   for (int i = tid; i < k; i += blockDim.x) {
     double *b = LU + (int64_t)i * 5 * k;
-    inverse_iteration(dd, ee, k, lam[i], s_tn, X + (int64_t)i * k, b, b + k, b + 2 * k, b + 3 * k, b + 4 * k);
+    inverse_iteration(dd, ee, k, lam[i], s_tn, (uint32_t)i, X + (int64_t)i * k, b, b + k, b + 2 * k,
+                      b + 3 * k, b + 4 * k);
   }
   __syncthreads();
-  // re-orthogonalise within clusters (ascending order)
-  int c0 = 0;
-  for (int i = 1; i < k; ++i) {
-    if (lam[i] - lam[i - 1] > 1e-3 * s_tn) { c0 = i; continue; }
-    double *xi = X + (int64_t)i * k;
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int j = c0 + tid; j < i; j += blockDim.x) {
-        const double *xj = X + (int64_t)j * k;
-        double s = 0.0;
-        for (int r = 0; r < k; ++r) s += xj[r] * xi[r];
-        coef[j - c0] = s;
+  // re-orthogonalise within clusters (ascending order), in LDS when they fit
+  for (int c0 = 0; c0 < k;) {
+    int c1 = c0 + 1;
+    while (c1 < k && lam[c1] - lam[c1 - 1] <= 1e-3 * s_tn) ++c1;
+    const int c = c1 - c0;
+    if (c > 1) {
+      double *xg = X + (int64_t)c0 * k;
+      const bool in_lds = (int64_t)c * k <= TRI_POOL;
+      double *xs = in_lds ? pool : xg;
+      if (in_lds) {
+        for (int q = tid; q < c * k; q += blockDim.x) pool[q] = xg[q];
+        __syncthreads();
       }
-      __syncthreads();
-      for (int r = tid; r < k; r += blockDim.x) {
-        double s = xi[r];
-        for (int j = c0; j < i; ++j) s -= coef[j - c0] * X[(int64_t)j * k + r];
-        xi[r] = s;
+      cgs2_block(xs, k, c, coef, &s_nrm);
+      if (in_lds) {
+        for (int q = tid; q < c * k; q += blockDim.x) xg[q] = pool[q];
+        __syncthreads();
       }
-      __syncthreads();
     }
-    if (tid == 0) {
-      double nrm = 0.0;
-      for (int r = 0; r < k; ++r) nrm += xi[r] * xi[r];
-      coef[255] = 1.0 / sqrt(nrm);
-    }
-    __syncthreads();
-    for (int r = tid; r < k; r += blockDim.x) xi[r] *= coef[255];
-    __syncthreads();
+    c0 = c1;
   }
+  qd *coefq = (qd *)pool;            // k diagonal scalings (pool is free again)
   // back-transform: y = D x (delta_0 = 1, delta_{j+1} = alpha_j delta_j / |alpha_j|),
-  // then u = H_0 H_1 ... H_{k-2} y
-  for (int i = tid; i < k; i += blockDim.x) {
-    const double *x = X + (int64_t)i * k;
+  // then u = H_0 H_1 ... H_{k-2} y.  The reflectors go to all k columns at
+  // once: a group of G lanes (one wave) owns column i, lane r owns the rows
+  // congruent to r mod G, so a column's rows never change hands and only the
+  // inner product v^* y crosses lanes (shuffles).
+  if (tid == 0) {
     qd delta = {1.0, 0.0, 0.0, 0.0};
-    sq_(U, 0, i, k, qscale(delta, x[0]));
+    coefq[0] = delta;
     for (int j = 0; j + 1 < k; ++j) {
       const qd al = {HA[4 * j], HA[4 * j + 1], HA[4 * j + 2], HA[4 * j + 3]};
       const double aa = sqrt(qnorm2(al));
       if (aa > 0.0) delta = qmul(qscale(al, 1.0 / aa), delta);
-      sq_(U, j + 1, i, k, qscale(delta, x[j + 1]));
+      coefq[j + 1] = delta;
     }
+  }
+  __syncthreads();
+  for (int q = tid; q < k * k; q += blockDim.x) {
+    const int r = q % k, i = q / k;
+    sq_(U, r, i, k, qscale(coefq[r], X[(int64_t)i * k + r]));
+  }
+  __syncthreads();
+  int G = 64;
+  while (G > 1 && G * k > (int)blockDim.x) G >>= 1;
+  const int col = tid / G, sub = tid % G;
+  if (col < k) {
     for (int j = k - 2; j >= 0; --j) {
       const double beta = hb[j];
-      if (beta == 0.0) continue;
-      const int n = k - j - 1;
+      if (beta == 0.0) continue;                 // wave-uniform
       qd s = qzero();
-      for (int a = 0; a < n; ++a) qfma_cj(s, gq(HV, a, j, k), gq(U, j + 1 + a, i, k));   // v^* y
+      for (int r = j + 1 + ((sub - (j + 1)) % G + G) % G; r < k; r += G)
+        qfma_cj(s, gq(HV, r - j - 1, j, k), gq(U, r, col, k));
+      for (int off = 1; off < G; off <<= 1) {
+        s.w += __shfl_xor(s.w, off, 64);
+        s.x += __shfl_xor(s.x, off, 64);
+        s.y += __shfl_xor(s.y, off, 64);
+        s.z += __shfl_xor(s.z, off, 64);
+      }
       s = qscale(s, beta);
-      for (int a = 0; a < n; ++a)
-        sq_(U, j + 1 + a, i, k, qsub(gq(U, j + 1 + a, i, k), qmul(gq(HV, a, j, k), s)));
+      for (int r = j + 1 + ((sub - (j + 1)) % G + G) % G; r < k; r += G)
+        sq_(U, r, col, k, qsub(gq(U, r, col, k), qmul(gq(HV, r - j - 1, j, k), s)));
     }
   }
   __syncthreads();
@@ -1219,11 +1390,15 @@ __global__ __launch_bounds__(1024) void kappa_kernel(int k, const double *gh, do
       s_def = t;
     }
   }
+  __shared__ int ends[2];
+  __shared__ double pool[TRI_POOL];
   sm_copy(G, gh, (int)kk);
-  sm_tridiag(G, k, dd, ee);
-  sm_bisect_all(dd, ee, k, lam);
+  sm_tridiag(G, k, dd, ee, pool);
+  if (threadIdx.x == 0) { ends[0] = 0; ends[1] = k - 1; }
+  __syncthreads();
+  sm_bisect_sel(dd, ee, k, ends, 2, lam);
   if (threadIdx.x == 0) {
-    const double lmin = lam[0], lmax = lam[k - 1];
+    const double lmin = lam[0], lmax = lam[1];
     const double kap = lmin > 0.0 ? sqrt(lmax / lmin) : INFINITY;
     if (which == 0) { status->kappa = kap; status->orth_defect = s_def; }
     else status->kappa_initial = kap;

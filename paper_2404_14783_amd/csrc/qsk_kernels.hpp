@@ -24,6 +24,8 @@ struct SketchArgs {
   int64_t m, col0, ncols;
   int k, l;
   void *y; int64_t ldy, psy;   // Y planes: y + p * psy, element (i, j) at i + j * ldy
+  int64_t pss;           // stride between the split-K copies of Y (matrix-core path)
+  int y_copies;          // number of Y copies the matrix-core path may add into
   void *w; int64_t ldw, psw;
   int rad;               // 1 = Rademacher, 0 = Gaussian
   int terms;
@@ -45,8 +47,12 @@ struct MfmaStage {
   int LP, KP;
   int64_t MP, NP;
 };
-void stage_geometry(int64_t m, int l, int k, int64_t maxcols, int *LP, int64_t *MP, int *KP,
-                    int64_t *NP);
+void stage_geometry(int64_t m, int l, int k, int64_t maxcols, int op_bf16, int *LP, int64_t *MP,
+                    int *KP, int64_t *NP);
+// Copies of Y the matrix-core Y kernel splits its columns over; Y is their sum.
+constexpr int Y_COPIES = 4;
+// copy 0 += copies 1 .. S-1 (each n_per_copy floats), which are cleared.
+hipError_t launch_y_fold(hipStream_t st, float *y, int64_t n_per_copy, int S);
 // Matrix-core path; returns hipErrorNotSupported for shapes it does not take.
 hipError_t launch_sketch_mfma(const SketchArgs &s, const MfmaStage &g);
 

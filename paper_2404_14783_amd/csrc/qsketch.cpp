@@ -35,8 +35,10 @@ struct qsk_ctx {
   int64_t maxcols = 0;
   int64_t columns_seen = 0;
   uint32_t k0 = 0, k1 = 0;
-  // sketches
+  // sketches; the matrix-core path keeps y_copies partial copies of Y whose
+  // sum is Y (folded into copy 0 before Y is read)
   void *y = nullptr, *w = nullptr;
+  int y_copies = 1;
   // finalize workspace (FP64)
   double *u[2] = {nullptr, nullptr};   // m x k planar, two alternating buffers
   double *small = nullptr;             // k x k AoS matrices
@@ -47,6 +49,12 @@ struct qsk_ctx {
   double *err_acc = nullptr;
   double *pinv_work = nullptr;         // (l + k) x k quaternions
   SmallStatus *status = nullptr;
+  // kappa estimates only feed the report, so they run on a side stream that
+  // forks from and joins back into the context stream within each finalize
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  double *kwork = nullptr;             // workspace of the side-stream kappa kernels
+  SmallStatus *kstatus = nullptr;
   void *w_scratch = nullptr;           // split-K partials of the matrix-core W kernel
   int64_t w_scratch_bytes = 0;
   qsk::MfmaStage stage{};              // transient test-matrix slices (matrix-core path)
@@ -114,9 +122,15 @@ void free_events(qsk_ctx *c) {
 
 void free_all(qsk_ctx *c) {
   free_events(c);
+  if (c->side) (void)hipStreamSynchronize(c->side);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->side) (void)hipStreamDestroy(c->side);
+  c->ev_fork = c->ev_join = nullptr;
+  c->side = nullptr;
   void *ptrs[] = {c->y, c->w, c->u[0], c->u[1], c->small, c->work, c->partials, c->pbuf,
                   c->p1buf, c->sbuf, c->err_acc, c->status, c->w_scratch, c->pinv_work,
-                  c->stage.omega, c->stage.psi};
+                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->y = c->w = nullptr;
@@ -126,6 +140,8 @@ void free_all(qsk_ctx *c) {
   c->w_scratch = nullptr;
   c->pinv_work = nullptr;
   c->stage.omega = c->stage.psi = nullptr;
+  c->kwork = nullptr;
+  c->kstatus = nullptr;
 }
 
 bool alloc(void **p, size_t bytes) {
@@ -140,9 +156,15 @@ bool alloc(void **p, size_t bytes) {
 
 // Offsets of the k x k matrices inside ctx->small.
 enum SmallSlot { S_G1 = 0, S_GU, S_R, S_T, S_RPROD, S_RTMP, S_G0, S_TMP, S_C, S_F, S_GP, S_RP,
-                 S_TP1, S_TP2, S_TPT, S_Z, S_CR, S_CT, S_GI, S_M, S_TMP2, S_GH, S_COUNT };
+                 S_TP1, S_TP2, S_TPT, S_Z, S_CR, S_CT, S_GI, S_M, S_TMP2, S_GH, S_GK0, S_COUNT };
 
 double *slot(qsk_ctx *c, int s) { return c->small + (size_t)s * c->cfg.k * c->cfg.k * 4; }
+
+// Sum the split-K copies of Y into copy 0 (stream-ordered).
+hipError_t fold_y(qsk_ctx *c) {
+  if (c->y_copies <= 1) return hipSuccess;
+  return qsk::launch_y_fold(c->stream, (float *)c->y, 4 * c->cfg.m * (int64_t)c->cfg.k, c->y_copies);
+}
 
 }  // namespace
 
@@ -220,7 +242,9 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   const int64_t m = c.m, n = c.n, k = c.k, l = c.l;
   const size_t kk = (size_t)k * k * 4;
   bool ok = true;
-  ok = ok && alloc(&ctx->y, 4 * (size_t)m * k * ctx->ts);
+  const bool mfma_mode = c.sketch_dtype == QSK_BF16 || c.sketch_dtype == QSK_F32;
+  ctx->y_copies = mfma_mode ? qsk::Y_COPIES : 1;
+  ok = ok && alloc(&ctx->y, (size_t)ctx->y_copies * 4 * m * k * ctx->ts);
   ok = ok && alloc(&ctx->w, 4 * (size_t)l * n * ctx->ts);
   ok = ok && alloc((void **)&ctx->u[0], 4 * (size_t)m * k * 8);
   ok = ok && alloc((void **)&ctx->u[1], 4 * (size_t)m * k * 8);
@@ -235,10 +259,16 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   ok = ok && alloc((void **)&ctx->err_acc, 2 * 8);
   ok = ok && alloc((void **)&ctx->pinv_work, 4 * (size_t)(l + k) * k * 8);
   ok = ok && alloc((void **)&ctx->status, sizeof(SmallStatus));
+  ok = ok && alloc((void **)&ctx->kstatus, sizeof(SmallStatus));
+  ok = ok && alloc((void **)&ctx->kwork, kk * 8);
+  ok = ok && hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) == hipSuccess;
   // matrix-core path: staging of Omega_J / Psi and the W split-K partials
   if (c.sketch_dtype == QSK_BF16 || c.sketch_dtype == QSK_F32) {
     qsk::MfmaStage &g = ctx->stage;
-    qsk::stage_geometry(m, (int)l, (int)k, ctx->cfg.max_block_cols, &g.LP, &g.MP, &g.KP, &g.NP);
+    qsk::stage_geometry(m, (int)l, (int)k, ctx->cfg.max_block_cols, c.sketch_dtype == QSK_BF16,
+                        &g.LP, &g.MP, &g.KP, &g.NP);
     const size_t es = c.sketch_dtype == QSK_BF16 ? 2 : 4;
     ok = ok && alloc(&g.omega, 4 * (size_t)g.KP * g.NP * es);
     ok = ok && alloc(&g.psi, 4 * (size_t)g.LP * g.MP * es);
@@ -250,7 +280,7 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
     delete ctx;
     return QSK_E_NOMEM;
   }
-  hipError_t e = hipMemsetAsync(ctx->y, 0, 4 * (size_t)m * k * ctx->ts, ctx->stream);
+  hipError_t e = hipMemsetAsync(ctx->y, 0, (size_t)ctx->y_copies * 4 * m * k * ctx->ts, ctx->stream);
   if (e == hipSuccess) e = hipMemsetAsync(ctx->w, 0, 4 * (size_t)l * n * ctx->ts, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
@@ -273,7 +303,7 @@ qsk_status qsketch_reset(qsk_ctx *ctx) {
   if (!ctx) return QSK_E_ARG;
   if (ctx->poisoned) return QSK_E_STATE;
   const qsk_config &c = ctx->cfg;
-  HIPCHK(ctx, hipMemsetAsync(ctx->y, 0, 4 * (size_t)c.m * c.k * ctx->ts, ctx->stream));
+  HIPCHK(ctx, hipMemsetAsync(ctx->y, 0, (size_t)ctx->y_copies * 4 * c.m * c.k * ctx->ts, ctx->stream));
   HIPCHK(ctx, hipMemsetAsync(ctx->w, 0, 4 * (size_t)c.l * c.n * ctx->ts, ctx->stream));
   ctx->columns_seen = 0;
   return QSK_OK;
@@ -301,6 +331,8 @@ qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void 
   s.m = c.m; s.col0 = col0; s.ncols = ncols;
   s.k = c.k; s.l = c.l;
   s.y = ctx->y; s.ldy = c.m; s.psy = c.m * (int64_t)c.k;
+  s.pss = 4 * c.m * (int64_t)c.k;
+  s.y_copies = ctx->y_copies;
   s.w = ctx->w; s.ldw = c.l; s.psw = c.l * (int64_t)c.n;
   s.rad = c.embedding == QSK_RADEMACHER;
   s.terms = c.split_terms;
@@ -335,6 +367,7 @@ qsk_status qsketch_sketches(qsk_ctx *ctx, double *const Y[4], int64_t ldy, doubl
   const int t = ctx->mode == qsk::MODE_F64 ? 0 : 1;
   if (Y) {
     if (ldy < c.m) return fail_arg(ctx, "ldy < m");
+    HIPCHK(ctx, fold_y(ctx));
     HIPCHK(ctx, qsk::launch_widen(ctx->stream, t, ctx->y, c.m, c.m * (int64_t)c.k, c.m, c.k, Y, ldy));
   }
   if (W) {
@@ -363,6 +396,7 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
   SmallStatus hs{};
   int flags = 0;
 
+  HIPCHK(ctx, fold_y(ctx));
   const void *yp[4];
   for (int p = 0; p < 4; ++p) yp[p] = (const char *)ctx->y + (size_t)p * m * k * ctx->ts;
 
@@ -419,11 +453,15 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
   }
   // Now H0 (pseudo-QR) or Q_Y (pseudo-SVD) = Z T with G_Z = gz.
   HIPCHK(ctx, hipMemsetAsync(ctx->status, 0, sizeof(SmallStatus), st));
+  HIPCHK(ctx, hipMemsetAsync(ctx->kstatus, 0, sizeof(SmallStatus), st));
   if (rf == QSK_PSEUDO_QR) {
     // G0 = H0^* H0 = T^* G_Z T; kappa of the raw factor
     HIPCHK(ctx, qsk::launch_small_gemm(st, k, gz, 0, slot(ctx, S_T), 0, slot(ctx, S_TMP)));
     HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_T), 1, slot(ctx, S_TMP), 0, slot(ctx, S_G0)));
-    HIPCHK(ctx, qsk::launch_kappa(st, k, slot(ctx, S_G0), ctx->work, 1, ctx->status));
+    HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_GK0), slot(ctx, S_G0), kk * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(ctx, hipEventRecord(ctx->ev_fork, st));
+    HIPCHK(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+    HIPCHK(ctx, qsk::launch_kappa(ctx->side, k, slot(ctx, S_GK0), ctx->kwork, 1, ctx->kstatus));
     // correction steps (eq. CondNumReductionIter) in the k x k space: with
     // H_j = H0 C_j and G_j = H_j^* H_j, H_{j+1} = (1 - eps) H_j + eps (H_j^dagger)^*
     // = H_j M_j with M_j = (1 - eps) I + eps G_j^{-1}  ((H^dagger)^* = H G^{-1});
@@ -457,7 +495,10 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
   // kappa(Q) from G_Q = F^* G_Z F
   HIPCHK(ctx, qsk::launch_small_gemm(st, k, gz, 0, slot(ctx, S_F), 0, slot(ctx, S_TMP2)));
   HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_F), 1, slot(ctx, S_TMP2), 0, slot(ctx, S_GH)));
-  HIPCHK(ctx, qsk::launch_kappa(st, k, slot(ctx, S_GH), ctx->work, 0, ctx->status));
+  HIPCHK(ctx, hipEventRecord(ctx->ev_fork, st));
+  HIPCHK(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+  HIPCHK(ctx, qsk::launch_kappa(ctx->side, k, slot(ctx, S_GH), ctx->kwork, 0, ctx->kstatus));
+  HIPCHK(ctx, hipEventRecord(ctx->ev_join, ctx->side));
   HIPCHK(ctx, qsk::launch_apply(st, tz, zsrc, m, m, k, slot(ctx, S_F), k, Q, ldq));
 
   // ---- core solve X = (Psi Q)^dagger W (Alg. 2 through the normal form of
@@ -516,17 +557,22 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
   for (int p = 0; p < 4; ++p) wp[p] = (const char *)ctx->w + (size_t)p * l * n * ctx->ts;
   HIPCHK(ctx, qsk::launch_crossprod_planar(st, sp, l, ty, wp, l, l, k, (int)n, X, ldx));
 
+  // join the side stream (kappa estimates) before reading its results
+  HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_join, 0));
+  SmallStatus ks{};
+  HIPCHK(ctx, hipMemcpyAsync(&ks, ctx->kstatus, sizeof(ks), hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
   if (report) {
     qsk_report r{};
-    r.kappa = hs2.kappa;
-    r.kappa_initial = rf == QSK_PSEUDO_QR ? hs2.kappa_initial : hs2.kappa;
+    r.kappa = ks.kappa;
+    r.kappa_initial = rf == QSK_PSEUDO_QR ? ks.kappa_initial : ks.kappa;
     r.n_eps = hs2.n_eps;
     for (int i = 0; i < 8; ++i) r.eps[i] = hs2.eps[i];
     r.t_bad = hs2.t_bad;
     r.flags = flags;
     r.passes = passes;
     r.columns_seen = ctx->columns_seen;
-    r.orth_defect = rf == QSK_PSEUDO_SVD ? hs2.orth_defect : 0.0;
+    r.orth_defect = rf == QSK_PSEUDO_SVD ? ks.orth_defect : 0.0;
     *report = r;
   }
   HIPCHK(ctx, hipStreamSynchronize(st));

@@ -29,6 +29,9 @@ namespace qsk {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
 typedef __attribute__((ext_vector_type(4))) float floatx4;
+// native 16-byte vector for the register-staged tiles (HIP's uint4 is a
+// struct that keeps arrays of it out of registers)
+typedef __attribute__((ext_vector_type(4))) unsigned int u32v4;
 
 enum : int { OP_BF16 = 0, OP_F32 = 1 };
 
@@ -127,18 +130,86 @@ __device__ constexpr int ssel(int p, int q) {      // S(Psi)[p][q]
 }
 
 // ---------------------------------------------------------------------------
-// W kernel.  Block = 4 waves; blockIdx.x -> 64 columns of the update block
-// (16 per wave), blockIdx.y -> NMT row tiles of W (16 rows each), blockIdx.z
-// -> a chunk of the rows of A (split K).  Psi's tile is staged in LDS; each
-// wave reads its own A fragments straight from HBM (8 contiguous rows per
-// lane).
+// Block-to-tile mapping.  Workgroups are dispatched to the eight XCDs in
+// turn (block b runs on XCD b mod 8), so the linear tile index is taken as
+// (b mod 8) * (total / 8) + b / 8: consecutive tiles, which share a slice of
+// the staged test matrix, then run on one XCD and hit its L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t total) {
+  if ((total & 7) != 0) return b;
+  return (b & 7) * (total >> 3) + (b >> 3);
+}
+
+// Loads of 8 consecutive input values (rows i .. i+7 of one column) for the
+// operand conversion; vector loads when the column segment is aligned.
+template <typename TIN>
+__device__ __forceinline__ void load8(const TIN *p, int64_t idx, int64_t navail, bool vec, float (&x)[8]);
+template <>
+__device__ __forceinline__ void load8<float>(const float *p, int64_t idx, int64_t navail, bool vec,
+                                             float (&x)[8]) {
+  if (vec && navail >= 8) {
+    const float4 u0 = *(const float4 *)(p + idx), u1 = *(const float4 *)(p + idx + 4);
+    x[0] = u0.x; x[1] = u0.y; x[2] = u0.z; x[3] = u0.w;
+    x[4] = u1.x; x[5] = u1.y; x[6] = u1.z; x[7] = u1.w;
+  } else {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) x[s] = s < navail ? p[idx + s] : 0.f;
+  }
+}
+template <>
+__device__ __forceinline__ void load8<uint16_t>(const uint16_t *p, int64_t idx, int64_t navail,
+                                                bool vec, float (&x)[8]) {
+  if (vec && navail >= 8) {
+    const uint4 u = *(const uint4 *)(p + idx);
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      x[2 * s] = __uint_as_float(w[s] << 16);
+      x[2 * s + 1] = __uint_as_float(w[s] & 0xFFFF0000u);
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) x[s] = s < navail ? __uint_as_float(((uint32_t)p[idx + s]) << 16) : 0.f;
+  }
+}
+
+template <typename Frag, typename OPT>
+__device__ __forceinline__ void lds_frag(const OPT *src, Frag &f);
+template <>
+__device__ __forceinline__ void lds_frag<FragB, uint16_t>(const uint16_t *src, FragB &f) {
+  const uint4 u = *(const uint4 *)src;
+  f.v[0] = u.x; f.v[1] = u.y; f.v[2] = u.z; f.v[3] = u.w;
+}
+template <>
+__device__ __forceinline__ void lds_frag<FragF, float>(const float *src, FragF &f) {
+  const float4 u0 = *(const float4 *)src, u1 = *(const float4 *)(src + 4);
+  f.v[0] = u0.x; f.v[1] = u0.y; f.v[2] = u0.z; f.v[3] = u0.w;
+  f.v[4] = u1.x; f.v[5] = u1.y; f.v[6] = u1.z; f.v[7] = u1.w;
+}
+
+// The data operand of one lane: 8 values per plane -> TERMS fragments.
+template <int OP, int TERMS>
+__device__ __forceinline__ void to_frags(const float (&x)[8], FragB (&out)[3]) { split_terms<TERMS>(x, out); }
+template <int OP, int TERMS>
+__device__ __forceinline__ void to_frags(const float (&x)[8], FragF (&out)[3]) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s) out[0].v[s] = x[s];
+}
+
+// ---------------------------------------------------------------------------
+// W kernel.  Tiles: 64 columns of the update block x NMT row tiles of W
+// (16 rows each) x one chunk of the rows of A (split K over S chunks).
+// Block = 4 waves; wave w owns columns 16 w .. 16 w + 15 of the tile, all NMT
+// row tiles and all four planes.  Per 32-row step the Psi tile (4 planes x
+// 16 NMT rows x 32) goes through LDS; each lane's A values (8 consecutive
+// rows of its column, four planes) go straight from HBM into registers.  Both
+// are fetched one step ahead (software pipelining).
 struct WArgs {
   const void *a[4];
   int64_t lda, m, ncols, col0;
   const void *psi;            // staged [4][LP][MP]
   int LP;
   int64_t MP;
-  int l, terms, pure, S;
+  int l, pure, S, ctiles, rgroups, vec;
   int64_t kchunk;
   float *w;
   int64_t ldw, psw;
@@ -146,21 +217,32 @@ struct WArgs {
 };
 
 template <int OP, typename TIN, int NMT, int TERMS>
-__global__ __launch_bounds__(256) void w_mfma_kernel(WArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void w_mfma_kernel(WArgs a) {
   using OPT = typename std::conditional<OP == OP_BF16, uint16_t, float>::type;
   using Frag = typename std::conditional<OP == OP_BF16, FragB, FragF>::type;
   constexpr int LDK = 32 + (OP == OP_BF16 ? 8 : 4);        // padded K stride in LDS
+  constexpr int EPV = 16 / sizeof(OPT);                    // elements per 16-byte vector
+  constexpr int VPR = 32 / EPV;                            // vectors per tile row
+  constexpr int NV = 4 * NMT * 16 * VPR;                   // vectors per Psi tile
+  constexpr int VPT = NV / 256;
+  static_assert(NV % 256 == 0, "Psi tile must split evenly over the block");
   __shared__ OPT s_psi[4][NMT * 16][LDK];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int c16 = lane & 15, g = lane >> 4;
-  const int64_t j = (int64_t)blockIdx.x * 64 + wave * 16 + c16;
-  const int rbase = blockIdx.y * NMT * 16;
-  const int64_t ib = (int64_t)blockIdx.z * a.kchunk;
+  const int64_t total = (int64_t)a.ctiles * a.rgroups * a.S;
+  const int64_t t = xcd_tile(blockIdx.x, total);
+  const int bx = (int)(t % a.ctiles);
+  const int by = (int)((t / a.ctiles) % a.rgroups);
+  const int bz = (int)(t / ((int64_t)a.ctiles * a.rgroups));
+  const int64_t j = (int64_t)bx * 64 + wave * 16 + c16;
+  const int rbase = by * NMT * 16;
+  const int64_t ib = (int64_t)bz * a.kchunk;
   const int64_t ie = min(a.m, ib + a.kchunk);
   const OPT *psi = (const OPT *)a.psi;
   const int64_t pps = (int64_t)a.LP * a.MP;
   const TIN *ap[4] = {(const TIN *)a.a[0], (const TIN *)a.a[1], (const TIN *)a.a[2], (const TIN *)a.a[3]};
   const bool jok = j < a.ncols;
+  const bool vec = a.vec != 0;
 
   floatx4 acc[NMT][4];
 #pragma unroll
@@ -168,61 +250,53 @@ __global__ __launch_bounds__(256) void w_mfma_kernel(WArgs a) {
 #pragma unroll
     for (int p = 0; p < 4; ++p) acc[r][p] = {0.f, 0.f, 0.f, 0.f};
 
+  float xa[4][8];
+  u32v4 pr[VPT];
+#define QSK_W_FETCH(I0)                                                                         \
+  do {                                                                                          \
+    const int64_t i_ = (I0) + 8 * g;                                                            \
+    const int64_t nav_ = jok ? min((int64_t)8, ie - i_) : 0;                                    \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                             \
+      if (q == 0 && a.pure) {                                                                   \
+        _Pragma("unroll") for (int s = 0; s < 8; ++s) xa[q][s] = 0.f;                           \
+      } else {                                                                                  \
+        load8<TIN>(ap[q], i_ + j * a.lda, nav_, vec, xa[q]);                                    \
+      }                                                                                         \
+    }                                                                                           \
+    _Pragma("unroll") for (int u = 0; u < VPT; ++u) {                                           \
+      const int e = tid + u * 256;                                                              \
+      const int v = e % VPR, rr = (e / VPR) % (NMT * 16), pl = e / (VPR * NMT * 16);            \
+      pr[u] = *(const u32v4 *)(psi + pl * pps + (int64_t)(rbase + rr) * a.MP + (I0) + v * EPV);   \
+    }                                                                                           \
+  } while (0)
+
+  QSK_W_FETCH(ib);
   for (int64_t i0 = ib; i0 < ie; i0 += 32) {
-    // stage Psi[rbase .. rbase + 16 NMT, i0 .. i0 + 32) for the four planes
-    constexpr int EPV = 16 / sizeof(OPT);                  // elements per 16-byte vector
-    constexpr int VPR = 32 / EPV;                          // vectors per row
-    for (int e = tid; e < 4 * NMT * 16 * VPR; e += 256) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int e = tid + u * 256;
       const int v = e % VPR, rr = (e / VPR) % (NMT * 16), pl = e / (VPR * NMT * 16);
-      const uint4 val = *(const uint4 *)(psi + pl * pps + (int64_t)(rbase + rr) * a.MP + i0 + v * EPV);
-      *(uint4 *)&s_psi[pl][rr][v * EPV] = val;
+      *(u32v4 *)&s_psi[pl][rr][v * EPV] = pr[u];
     }
-    // this wave's A fragments: rows i0 + 8g .. +7 of column j, four planes
-    float x[4][8];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int64_t i = i0 + 8 * g + s;
-        x[q][s] = (jok && i < ie && !(q == 0 && a.pure)) ? ldin<TIN>(ap[q], i + j * a.lda) : 0.f;
-      }
-    }
-    __syncthreads();
     Frag af[4][3];
-    if constexpr (OP == OP_BF16) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) split_terms<TERMS>(x[q], af[q]);
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int s = 0; s < 8; ++s) af[q][0].v[s] = x[q][s];
-    }
+    for (int q = 0; q < 4; ++q) to_frags<OP, TERMS>(xa[q], af[q]);
+    __syncthreads();
+    if (i0 + 32 < ie) QSK_W_FETCH(i0 + 32);
 #pragma unroll
     for (int rt = 0; rt < NMT; ++rt) {
       Frag pf[7];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const OPT *src = &s_psi[s][rt * 16 + c16][8 * g];
-        if constexpr (OP == OP_BF16) {
-          const uint4 u = *(const uint4 *)src;
-          pf[s].v[0] = u.x; pf[s].v[1] = u.y; pf[s].v[2] = u.z; pf[s].v[3] = u.w;
-        } else {
-#pragma unroll
-          for (int t = 0; t < 8; ++t) pf[s].v[t] = src[t];
-        }
-      }
+      for (int s = 0; s < 4; ++s) lds_frag<Frag, OPT>(&s_psi[s][rt * 16 + c16][8 * g], pf[s]);
       if constexpr (OP == OP_BF16) { pf[4] = negB(pf[1]); pf[5] = negB(pf[2]); pf[6] = negB(pf[3]); }
       else { pf[4] = negF(pf[1]); pf[5] = negF(pf[2]); pf[6] = negF(pf[3]); }
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
+      for (int q = 0; q < 4; ++q) {
+        if (q == 0 && a.pure) continue;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (q == 0 && a.pure) continue;
-          const Frag &ps = pf[ssel(p, q)];
+        for (int tm = 0; tm < TERMS; ++tm)
 #pragma unroll
-          for (int tm = 0; tm < TERMS; ++tm) acc[rt][p] = mma(ps, af[q][tm], acc[rt][p]);
-        }
+          for (int p = 0; p < 4; ++p) acc[rt][p] = mma(pf[ssel(p, q)], af[q][tm], acc[rt][p]);
       }
     }
     __syncthreads();
@@ -237,10 +311,10 @@ __global__ __launch_bounds__(256) void w_mfma_kernel(WArgs a) {
       if (a.S == 1) {
         float *dst = a.w + p * a.psw + (a.col0 + j) * a.ldw;
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-          if (r0 + t < a.l) dst[r0 + t] += acc[rt][p][t];
+        for (int tt = 0; tt < 4; ++tt)
+          if (r0 + tt < a.l) dst[r0 + tt] += acc[rt][p][tt];
       } else {
-        float *dst = a.part + (((int64_t)blockIdx.z * 4 + p) * a.ncols + j) * a.LP + r0;
+        float *dst = a.part + (((int64_t)bz * 4 + p) * a.ncols + j) * a.LP + r0;
         *(floatx4 *)dst = acc[rt][p];
       }
     }
@@ -263,143 +337,200 @@ __global__ void w_reduce_kernel(const float *part, int S, int LP, int64_t ncols,
 }
 
 // ---------------------------------------------------------------------------
-// Y kernel.  Block = WAVES waves covering 16 WAVES rows of A; wave w owns row
-// tile w and NJ column tiles of Y (16 columns each) for all four planes;
-// blockIdx.y selects the group of NJ column tiles.  The A tile is staged in
-// LDS in the operand format (transposed so each lane reads 8 consecutive
-// columns of A); Omega fragments come from the staging buffer.
+// Y kernel.  Tiles: 64 rows of A x NJ column tiles of Y (16 columns each) x
+// one chunk of the update's columns (split K over S chunks; chunk s adds into
+// its own copy s of Y, and the copies are summed when the sketch is read).
+// Block = 4 waves; wave w owns rows 16 w .. 16 w + 15 of the tile, all NJ
+// column tiles and all four planes.  Per 32-column step the A tile is staged
+// in LDS in the operand format (transposed so that each lane reads 8
+// consecutive columns of A) and the Omega tile is copied to LDS; both are
+// fetched into registers one step ahead.
 struct YArgs {
   const void *a[4];
   int64_t lda, m, ncols;
   const void *om;             // staged [4][KP][NP]
   int KP;
   int64_t NP;
-  int k, terms, pure;
+  int k, pure, S, rblocks, cgroups;
+  int64_t tchunk;
   float *y;
-  int64_t ldy, psy;
+  int64_t ldy, psy, pss;      // copy s of plane p: y + s * pss + p * psy
 };
 
-template <int OP, typename TIN, int NJ, int WAVES, int TERMS>
-__global__ __launch_bounds__(64 * WAVES) void y_mfma_kernel(YArgs a) {
+template <int OP, typename TIN, int NJ, int TERMS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void y_mfma_kernel(YArgs a) {
   using OPT = typename std::conditional<OP == OP_BF16, uint16_t, float>::type;
   using Frag = typename std::conditional<OP == OP_BF16, FragB, FragF>::type;
   constexpr int NT = TERMS;
-  constexpr int ROWS = 16 * WAVES;
+  constexpr int ROWS = 64;
   constexpr int LDK = 32 + (OP == OP_BF16 ? 8 : 4);
+  constexpr int EPV = 16 / sizeof(OPT);
+  constexpr int VPR = 32 / EPV;
+  constexpr int NV = 4 * NJ * 16 * VPR;                     // vectors per Omega tile
+  constexpr int VPT = NV / 256;
+  static_assert(NV % 256 == 0, "Omega tile must split evenly over the block");
   __shared__ OPT s_a[NT][4][ROWS][LDK];
+  __shared__ OPT s_om[4][NJ * 16][LDK];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int c16 = lane & 15, g = lane >> 4;
-  const int64_t rb = (int64_t)blockIdx.x * ROWS;
-  const int jt0 = blockIdx.y * NJ;
+  const int64_t total = (int64_t)a.rblocks * a.cgroups * a.S;
+  const int64_t t = xcd_tile(blockIdx.x, total);
+  const int64_t bx = t % a.rblocks;
+  const int by = (int)((t / a.rblocks) % a.cgroups);
+  const int bz = (int)(t / ((int64_t)a.rblocks * a.cgroups));
+  const int64_t rb = bx * ROWS;
+  const int jt0 = by * NJ;
+  const int64_t tb = (int64_t)bz * a.tchunk;
+  const int64_t te = min(a.ncols, tb + a.tchunk);
   const OPT *om = (const OPT *)a.om;
   const int64_t ops = (int64_t)a.KP * a.NP;
   const TIN *ap[4] = {(const TIN *)a.a[0], (const TIN *)a.a[1], (const TIN *)a.a[2], (const TIN *)a.a[3]};
   // loader role: row lr of the tile, column group lg (8 columns)
   const int lr = tid % ROWS, lg = tid / ROWS;                // lg in 0..3
   const int64_t grow = rb + lr;
+  const bool rok = grow < a.m;
 
   floatx4 acc[NJ][4];
 #pragma unroll
-  for (int t = 0; t < NJ; ++t)
+  for (int u = 0; u < NJ; ++u)
 #pragma unroll
-    for (int p = 0; p < 4; ++p) acc[t][p] = {0.f, 0.f, 0.f, 0.f};
+    for (int p = 0; p < 4; ++p) acc[u][p] = {0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t t0 = 0; t0 < a.ncols; t0 += 32) {
-    {
-      float x[8];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const int64_t t = t0 + 8 * lg + s;
-          x[s] = (grow < a.m && t < a.ncols && !(q == 0 && a.pure)) ? ldin<TIN>(ap[q], grow + t * a.lda) : 0.f;
-        }
-        if constexpr (OP == OP_BF16) {
-          FragB f[3];
-          split_terms<TERMS>(x, f);
-#pragma unroll
-          for (int tm = 0; tm < TERMS; ++tm)
-            *(uint4 *)&s_a[tm][q][lr][8 * lg] = make_uint4(f[tm].v[0], f[tm].v[1], f[tm].v[2], f[tm].v[3]);
-        } else {
-#pragma unroll
-          for (int s = 0; s < 8; ++s) s_a[0][q][lr][8 * lg + s] = x[s];
-        }
-      }
-    }
-    __syncthreads();
-    Frag af[4][NT];
+  float xa[4][8];
+  u32v4 orr[VPT];
+#define QSK_Y_FETCH(T0)                                                                         \
+  do {                                                                                          \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                             \
+      _Pragma("unroll") for (int s = 0; s < 8; ++s) {                                           \
+        const int64_t tt = (T0) + 8 * lg + s;                                                   \
+        xa[q][s] = (rok && tt < te && !(q == 0 && a.pure)) ? ldin<TIN>(ap[q], grow + tt * a.lda) : 0.f; \
+      }                                                                                         \
+    }                                                                                           \
+    _Pragma("unroll") for (int u = 0; u < VPT; ++u) {                                           \
+      const int e = tid + u * 256;                                                              \
+      const int v = e % VPR, oo = (e / VPR) % (NJ * 16), pl = e / (VPR * NJ * 16);              \
+      orr[u] = *(const u32v4 *)(om + pl * ops + (int64_t)(jt0 * 16 + oo) * a.NP + (T0) + v * EPV); \
+    }                                                                                           \
+  } while (0)
+
+  QSK_Y_FETCH(tb);
+  for (int64_t t0 = tb; t0 < te; t0 += 32) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
+      if constexpr (OP == OP_BF16) {
+        FragB f[3];
+        split_terms<TERMS>(xa[q], f);
 #pragma unroll
-      for (int tm = 0; tm < NT; ++tm) {
-        {
-          const OPT *src = &s_a[tm][q][wave * 16 + c16][8 * g];
-          if constexpr (OP == OP_BF16) {
-            const uint4 u = *(const uint4 *)src;
-            af[q][tm].v[0] = u.x; af[q][tm].v[1] = u.y; af[q][tm].v[2] = u.z; af[q][tm].v[3] = u.w;
-          } else {
-#pragma unroll
-            for (int s = 0; s < 8; ++s) af[q][tm].v[s] = src[s];
-          }
-        }
+        for (int tm = 0; tm < TERMS; ++tm)
+          *(uint4 *)&s_a[tm][q][lr][8 * lg] = make_uint4(f[tm].v[0], f[tm].v[1], f[tm].v[2], f[tm].v[3]);
+      } else {
+        *(float4 *)&s_a[0][q][lr][8 * lg] = make_float4(xa[q][0], xa[q][1], xa[q][2], xa[q][3]);
+        *(float4 *)&s_a[0][q][lr][8 * lg + 4] = make_float4(xa[q][4], xa[q][5], xa[q][6], xa[q][7]);
       }
     }
 #pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int e = tid + u * 256;
+      const int v = e % VPR, oo = (e / VPR) % (NJ * 16), pl = e / (VPR * NJ * 16);
+      *(u32v4 *)&s_om[pl][oo][v * EPV] = orr[u];
+    }
+    __syncthreads();
+    if (t0 + 32 < te) QSK_Y_FETCH(t0 + 32);
+    Frag af[4][NT];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int tm = 0; tm < NT; ++tm) lds_frag<Frag, OPT>(&s_a[tm][q][wave * 16 + c16][8 * g], af[q][tm]);
+#pragma unroll
     for (int jt = 0; jt < NJ; ++jt) {
-      const int jj = (jt0 + jt) * 16 + c16;                 // column of Y this lane reads Omega for
       Frag of[7];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const OPT *src = om + s * ops + (int64_t)jj * a.NP + t0 + 8 * g;
-        if constexpr (OP == OP_BF16) {
-          const uint4 u = *(const uint4 *)src;
-          of[s].v[0] = u.x; of[s].v[1] = u.y; of[s].v[2] = u.z; of[s].v[3] = u.w;
-        } else {
-          const float4 u0 = *(const float4 *)src, u1 = *(const float4 *)(src + 4);
-          of[s].v[0] = u0.x; of[s].v[1] = u0.y; of[s].v[2] = u0.z; of[s].v[3] = u0.w;
-          of[s].v[4] = u1.x; of[s].v[5] = u1.y; of[s].v[6] = u1.z; of[s].v[7] = u1.w;
-        }
-      }
+      for (int s = 0; s < 4; ++s) lds_frag<Frag, OPT>(&s_om[s][jt * 16 + c16][8 * g], of[s]);
       if constexpr (OP == OP_BF16) { of[4] = negB(of[1]); of[5] = negB(of[2]); of[6] = negB(of[3]); }
       else { of[4] = negF(of[1]); of[5] = negF(of[2]); of[6] = negF(of[3]); }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (q == 0 && a.pure) continue;
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          const Frag &os = of[rsel(q, p)];
+        for (int tm = 0; tm < TERMS; ++tm)
 #pragma unroll
-          for (int tm = 0; tm < TERMS; ++tm) acc[jt][p] = mma(af[q][tm], os, acc[jt][p]);
-        }
+          for (int p = 0; p < 4; ++p) acc[jt][p] = mma(af[q][tm], of[rsel(q, p)], acc[jt][p]);
       }
     }
     __syncthreads();
   }
   // epilogue: lane holds column (jt0 + jt) * 16 + c16 of Y, rows rb + 16 wave + 4g + (0..3)
   const int64_t r0 = rb + wave * 16 + 4 * g;
+  float *ys = a.y + bz * a.pss;
 #pragma unroll
   for (int jt = 0; jt < NJ; ++jt) {
     const int jj = (jt0 + jt) * 16 + c16;
     if (jj >= a.k) continue;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      float *dst = a.y + p * a.psy + (int64_t)jj * a.ldy;
+      float *dst = ys + p * a.psy + (int64_t)jj * a.ldy;
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (r0 + t < a.m) dst[r0 + t] += acc[jt][p][t];
+      for (int tt = 0; tt < 4; ++tt)
+        if (r0 + tt < a.m) dst[r0 + tt] += acc[jt][p][tt];
     }
   }
+}
+
+#undef QSK_W_FETCH
+#undef QSK_Y_FETCH
+
+// Y = sum of its split-K copies: copy 0 += copies 1 .. S-1, which are cleared.
+__global__ void y_fold_kernel(float *y, int64_t n_per_copy, int S) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_per_copy;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    float s = y[e];
+    for (int c = 1; c < S; ++c) {
+      s += y[c * n_per_copy + e];
+      y[c * n_per_copy + e] = 0.f;
+    }
+    y[e] = s;
+  }
+}
+
+hipError_t launch_y_fold(hipStream_t st, float *y, int64_t n_per_copy, int S) {
+  if (S <= 1) return hipSuccess;
+  int64_t blocks = (n_per_copy + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(y_fold_kernel, dim3((unsigned)blocks), dim3(256), 0, st, y, n_per_copy, S);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 static inline int64_t rup(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
+// Tile choices: NMT row tiles of W per block (from {4, 7, 13}; 13 only for
+// bf16 operands, whose Psi tile is half the size) and NJ column tiles of Y
+// per block (from {4, 7}), each minimising the padded tile count (ties go to
+// the larger tile).
+static int pick_tiles(int tiles, const int *cand, int nc) {
+  int best = cand[0], best_pad = 1 << 30;
+  for (int i = 0; i < nc; ++i) {
+    const int c = cand[i];
+    const int pad = (tiles + c - 1) / c * c;
+    if (pad < best_pad || (pad == best_pad && c > best)) { best = c; best_pad = pad; }
+  }
+  return best;
+}
+static int w_nmt(int l, int op_bf16) {
+  static const int cb[3] = {4, 7, 13}, cf[2] = {4, 7};
+  return op_bf16 ? pick_tiles((l + 15) / 16, cb, 3) : pick_tiles((l + 15) / 16, cf, 2);
+}
+static int y_nj(int k) {
+  static const int c[2] = {4, 7};
+  return pick_tiles((k + 15) / 16, c, 2);
+}
+
 // Staging geometry shared with the host's allocation.
-void stage_geometry(int64_t m, int l, int k, int64_t maxcols, int *LP, int64_t *MP, int *KP,
-                    int64_t *NP) {
-  *LP = (int)rup(l, 112);
+void stage_geometry(int64_t m, int l, int k, int64_t maxcols, int op_bf16, int *LP, int64_t *MP,
+                    int *KP, int64_t *NP) {
+  *LP = (int)rup(l, 16 * w_nmt(l, op_bf16));
   *MP = rup(m, 32);
-  *KP = (int)rup(k, 16 * 7);
+  *KP = (int)rup(k, 16 * y_nj(k));
   *NP = rup(maxcols, 32);
 }
 
@@ -418,6 +549,17 @@ static inline void mark(const SketchArgs &s, int idx) {
   if (s.events) (void)hipEventRecord(s.events[idx], s.stream);
 }
 
+template <int OP, typename TIN, int TERMS, int NMT>
+static void launch_w(const WArgs &w, int64_t blocks, hipStream_t st) {
+  hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS>), dim3((unsigned)blocks), dim3(256), 0, st, w);
+}
+template <int OP, typename TIN, int TERMS, int NJ>
+static void launch_y(const YArgs &y, int64_t blocks, hipStream_t st) {
+  hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS>), dim3((unsigned)blocks), dim3(256), 0, st, y);
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
 template <int OP, typename TIN, int TERMS>
 static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
   using OPT = typename std::conditional<OP == OP_BF16, uint16_t, float>::type;
@@ -430,19 +572,18 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
   if (s.mode == MODE_BF16) {
     e = gen_stage<MODE_BF16, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
-    {
-      e = gen_stage<MODE_BF16, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
-      if (e != hipSuccess) return e;
-    }
+    e = gen_stage<MODE_BF16, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
+    if (e != hipSuccess) return e;
   } else {
     e = gen_stage<MODE_F32, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
-    {
-      e = gen_stage<MODE_F32, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
-      if (e != hipSuccess) return e;
-    }
+    e = gen_stage<MODE_F32, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
+    if (e != hipSuccess) return e;
   }
   mark(s, 1);
+  // vector loads of the input need 16-byte aligned column segments
+  bool vec = (s.lda % (16 / (int64_t)sizeof(TIN))) == 0;
+  for (int p = s.pure ? 1 : 0; p < 4; ++p) vec = vec && aligned16(s.planes[p]);
   // ---- Y
   {
     mark(s, 2);
@@ -450,12 +591,23 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     for (int p = 0; p < 4; ++p) y.a[p] = s.planes[p];
     y.lda = s.lda; y.m = s.m; y.ncols = s.ncols;
     y.om = om; y.KP = g.KP; y.NP = NPu;
-    y.k = s.k; y.terms = s.terms; y.pure = s.pure;
-    y.y = (float *)s.y; y.ldy = s.ldy; y.psy = s.psy;
-    constexpr int WAVES = 4, NJ = 7;
+    y.k = s.k; y.pure = s.pure;
+    y.y = (float *)s.y; y.ldy = s.ldy; y.psy = s.psy; y.pss = s.pss;
+    const int nj = y_nj(s.k);
     const int ntiles = (s.k + 15) / 16;
-    dim3 grid((unsigned)((s.m + 16 * WAVES - 1) / (16 * WAVES)), (unsigned)((ntiles + NJ - 1) / NJ));
-    hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, WAVES, TERMS>), grid, dim3(64 * WAVES), 0, s.stream, y);
+    y.rblocks = (int)((s.m + 63) / 64);
+    y.cgroups = (ntiles + nj - 1) / nj;
+    // split the update's columns over the Y copies so that the grid holds
+    // about four blocks per CU
+    int64_t S = (1024 + (int64_t)y.rblocks * y.cgroups - 1) / ((int64_t)y.rblocks * y.cgroups);
+    if (S > s.y_copies) S = s.y_copies;
+    if (S < 1) S = 1;
+    int64_t tchunk = rup((s.ncols + S - 1) / S, 32);
+    S = (s.ncols + tchunk - 1) / tchunk;
+    y.S = (int)S; y.tchunk = tchunk;
+    const int64_t blocks = (int64_t)y.rblocks * y.cgroups * S;
+    if (nj == 7) launch_y<OP, TIN, TERMS, 7>(y, blocks, s.stream);
+    else launch_y<OP, TIN, TERMS, 4>(y, blocks, s.stream);
     e = hipGetLastError();
     mark(s, 3);
     if (e != hipSuccess) return e;
@@ -466,13 +618,14 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     for (int p = 0; p < 4; ++p) w.a[p] = s.planes[p];
     w.lda = s.lda; w.m = s.m; w.ncols = s.ncols; w.col0 = s.col0;
     w.psi = ps; w.LP = g.LP; w.MP = g.MP;
-    w.l = s.l; w.terms = s.terms; w.pure = s.pure;
+    w.l = s.l; w.pure = s.pure; w.vec = vec ? 1 : 0;
     w.w = (float *)s.w; w.ldw = s.ldw; w.psw = s.psw;
-    constexpr int NMT = 7;
-    const int mgroups = (s.l + 16 * NMT - 1) / (16 * NMT);
-    const int64_t ctiles = (s.ncols + 63) / 64;
+    const int nmt = w_nmt(s.l, OP == OP_BF16);
+    w.rgroups = (int)(g.LP / (16 * nmt));
+    w.ctiles = (int)((s.ncols + 63) / 64);
     // split the rows of A so that there are >= ~2 blocks per CU
-    int64_t S = (512 + ctiles * mgroups - 1) / (ctiles * mgroups);
+    const int64_t base = (int64_t)w.ctiles * w.rgroups;
+    int64_t S = (512 + base - 1) / base;
     if (S > 16) S = 16;
     int64_t kchunk = rup((s.m + S - 1) / S, 32);
     if (kchunk < 256) kchunk = 256;
@@ -480,18 +633,20 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     const int64_t need = S * 4 * s.ncols * (int64_t)g.LP * 4;
     if (S > 1 && need > s.scratch_bytes) { S = 1; kchunk = rup(s.m, 32); }
     w.S = (int)S; w.kchunk = kchunk; w.part = (float *)s.scratch;
-    dim3 grid((unsigned)ctiles, (unsigned)mgroups, (unsigned)S);
+    const int64_t blocks = base * S;
     mark(s, 4);
-    hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS>), grid, dim3(256), 0, s.stream, w);
+    if (nmt == 13) launch_w<OP, TIN, TERMS, (OP == OP_BF16 ? 13 : 7)>(w, blocks, s.stream);
+    else if (nmt == 7) launch_w<OP, TIN, TERMS, 7>(w, blocks, s.stream);
+    else launch_w<OP, TIN, TERMS, 4>(w, blocks, s.stream);
     e = hipGetLastError();
     mark(s, 5);
     if (e != hipSuccess) return e;
     mark(s, 6);
     if (S > 1) {
       const int64_t total = 4 * s.ncols * (int64_t)s.l;
-      int64_t blocks = (total + 255) / 256;
-      if (blocks > 65536) blocks = 65536;
-      hipLaunchKernelGGL(w_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s.stream,
+      int64_t rblocks = (total + 255) / 256;
+      if (rblocks > 65536) rblocks = 65536;
+      hipLaunchKernelGGL(w_reduce_kernel, dim3((unsigned)rblocks), dim3(256), 0, s.stream,
                          (const float *)s.scratch, (int)S, g.LP, s.ncols, s.l, s.col0, (float *)s.w,
                          s.ldw, s.psw);
       e = hipGetLastError();
