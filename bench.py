@@ -163,6 +163,35 @@ def summarize_traffic(fetch_dir, write_dir, cmd_fetch, cmd_write):
     print("\n".join(lines))
 
 
+def summarize_stats(directory, cmd, out_path):
+    """Short kernel-time table from a rocprofv3 --kernel-trace --stats run."""
+    files = glob.glob(os.path.join(directory, "**", "*kernel_stats.csv"), recursive=True)
+    rows = list(csv.DictReader(open(files[0])))
+    lines = [
+        "# Kernel time summary: 20000x15000 FP32 quaternion, BF16 (2-term) sketch, both rangefinders",
+        "",
+        "Command (from the repository root, on one MI355X):",
+        "",
+        f"    {cmd}",
+        "",
+        "Two whole one-pass approximations (8 column-block updates of 2048 columns each, then the QB stage",
+        "with pseudo-QR and with pseudo-SVD), after a 256 MiB calibration copy; input generation kernels",
+        "(torch, rocBLAS) are listed too.",
+        "",
+        "| total ms | calls | avg us | kernel |",
+        "|---:|---:|---:|---|",
+    ]
+    for r in rows:
+        name = r["Name"].replace("|", "/")
+        if len(name) > 110:
+            name = name[:110]
+        lines.append(f"| {float(r['TotalDurationNs']) / 1e6:.3f} | {r['Calls']} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | `{name}` |")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines[:30]))
+
+
 def committed_traffic():
     """Per-launch HBM bytes of the W kernel from the committed counter
     summary, or None when the kernel source changed since it was taken."""
@@ -195,7 +224,12 @@ def main():
                     help="one bf16 pass only (for rocprofv3 runs)")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CMD_FETCH", "CMD_WRITE"),
                     help="write the W-kernel traffic summary from two rocprofv3 --pmc runs")
+    ap.add_argument("--summarize-stats", nargs=3, metavar=("DIR", "CMD", "OUT"),
+                    help="write a kernel-time summary from a rocprofv3 --stats run")
     args = ap.parse_args()
+    if args.summarize_stats:
+        summarize_stats(*args.summarize_stats)
+        return
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic)
         return
