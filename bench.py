@@ -206,6 +206,68 @@ def committed_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
+def bench_batch(args):
+    """64 independent problems (m in [512, 8192], n in [256, 4096] log-uniform,
+    rank 8..64 with geometric decay, k = 2r, l = 2k + 1, FP32 data, 1e-4
+    noise) through the batched path: one run = both sketches of every
+    problem and the QB stage with one rangefinder, all problems together."""
+    specs = synth.batch_specs(64)
+    mats = [qs.to_colmajor(synth.batch_matrix(sp, i, device="cuda")) for i, sp in enumerate(specs)]
+    shapes = [(sp["m"], sp["n"], sp["k"], sp["l"], i) for i, sp in enumerate(specs)]
+    torch.cuda.synchronize()
+    flops = sum(sketch_flops(m, n, k, l) for (m, n, k, l, _) in shapes)
+    out = {}
+    errs = {}
+    for name, sketch, terms in (("fp32", "f32", 1), ("bf16", "bf16", args.terms)):
+        b = qs.Batch(shapes, input_dtype="f32", sketch_dtype=sketch, split_terms=terms)
+        outs = b.outputs()
+        st = torch.cuda.current_stream()
+        for kind in ("pseudo_qr", "pseudo_svd"):
+            for _ in range(args.warmup):
+                b.run(mats, kind, outputs=outs)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(st)
+            for _ in range(args.steps):
+                b.run(mats, kind, outputs=outs)
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            errs[(name, kind)] = b.rel_error(mats, *outs)
+            out[f"{name}_{kind}_ms"] = ms
+            log(f"[bench] batch {name} {kind}: {ms:.2f} ms per run")
+        b.close()
+    # FP64 single-problem references for the first problems
+    nref = min(16, len(shapes))
+    worst = 0.0
+    for i in range(nref):
+        m, n, k, l, seed = shapes[i]
+        sk = qs.Sketcher(m, n, k, l, seed=seed, input_dtype="f32", sketch_dtype="f64", max_block_cols=n)
+        sk.update(0, mats[i])
+        for kind in ("pseudo_qr", "pseudo_svd"):
+            q, x, _ = sk.finalize(kind)
+            ref = sk.rel_error(mats[i], q, x)
+            worst = max(worst, abs(errs[("bf16", kind)][i] - ref) / ref)
+        sk.close()
+    step_ms = out["bf16_pseudo_qr_ms"] + out["bf16_pseudo_svd_ms"]
+    fp32_ms = out["fp32_pseudo_qr_ms"] + out["fp32_pseudo_svd_ms"]
+    line = {
+        "metric": "one-pass qLRA wall time + sketch TFLOP/s at equal rel. error, BF16/FP8 vs FP32",
+        "value": 2 * flops / (step_ms * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "batch of 64 FP32 quaternion problems, m 512-8192, n 256-4096, "
+                               "k = 2r (r 8-64), l = 2k + 1, Gaussian; step = one batched run with "
+                               "pseudo-QR plus one with pseudo-SVD (sketches recomputed in each)",
+                   "problems": len(shapes), "sketch_flops_per_run": flops, "bf16_terms": args.terms},
+        "paths": out, "speedup_vs_fp32_wall": fp32_ms / step_ms,
+        "equal_error": {"max_rel_diff_bf16_vs_fp64": worst, "problems_checked": nref},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +286,8 @@ def main():
                     help="one bf16 pass only (for rocprofv3 runs)")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CMD_FETCH", "CMD_WRITE"),
                     help="write the W-kernel traffic summary from two rocprofv3 --pmc runs")
+    ap.add_argument("--workload", default="c2", choices=["c2", "batch64"],
+                    help="c2: the 20000 x 15000 streamed matrix (default); batch64: 64 problems batched")
     ap.add_argument("--summarize-stats", nargs=3, metavar=("DIR", "CMD", "OUT"),
                     help="write a kernel-time summary from a rocprofv3 --stats run")
     args = ap.parse_args()
@@ -237,6 +301,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.workload == "batch64":
+        bench_batch(args)
+        return
     m, n, k, l, block = args.m, args.n, args.k, args.l, args.block
 
     log(f"[bench] generating input {m}x{n} (4 FP32 planes) on the GPU")

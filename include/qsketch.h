@@ -170,6 +170,51 @@ qsk_status qsketch_get_timing(qsk_ctx *ctx, int kernel, double *total_ms, int64_
 /* Stream (hipStream_t) of the context. */
 void *qsketch_stream(const qsk_ctx *ctx);
 
+/* ---------------------------------------------------------------------------
+   Batches of independent problems.  Each problem i is a whole matrix A_i
+   (cfgs[i].m x cfgs[i].n) whose one-pass approximation A_i ~ Q_i X_i
+   (Alg. 4: both sketches of all columns, the rangefinder, the core solve) is
+   computed for all problems together: the two sketch products of every
+   problem run in one grouped launch each, and every step of the QB stage is
+   one launch over all problems (one workgroup per problem for the small
+   k x k algebra).  Randomness, rangefinders and results per problem are
+   those of a single context with the same configuration.
+
+   All configurations must share embedding, input_dtype, sketch_dtype (QSK_BF16
+   or QSK_F32: the matrix-core path), pure, split_terms, n_correction and
+   n_power; m, n, k, l and seed may differ.  max_block_cols is ignored.  Test
+   matrices are drawn and staged once, at init. */
+typedef struct qsk_batch qsk_batch;
+
+/* Validate the configurations and allocate every problem's workspace on the
+   current device (count >= 1).  Synchronous.  QSK_E_ARG for an invalid or
+   inconsistent set, QSK_E_UNSUPPORTED for a sketch_dtype other than BF16 or
+   F32, QSK_E_NOMEM if device memory is short. */
+qsk_status qsketch_batch_init(int32_t count, const qsk_config *cfgs, void *hip_stream,
+                              qsk_batch **out);
+
+/* One-pass approximation of every problem with rangefinder rf.  Problem i
+   reads A_i from planes[4 i + p] (input_dtype, column-major, leading
+   dimension ld[i] >= m_i; planes[4 i] may be NULL when pure) and writes
+   Q_i (m_i x k_i, FP64 planes Q[4 i + p], leading dimension ldq[i]) and
+   X_i (k_i x n_i, FP64 planes X[4 i + p], leading dimension ldx[i]).  All
+   arrays are host arrays of device pointers.  reports (count entries) may
+   be NULL.  Allocates nothing; synchronises the stream before returning.
+   QSK_E_NUMERIC if some problem's sketch is zero or non-finite (the other
+   problems' outputs are still written). */
+qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const *planes,
+                             const int64_t *ld, double *const *Q, const int64_t *ldq,
+                             double *const *X, const int64_t *ldx, qsk_report *reports);
+
+/* ||A_i - Q_i X_i||_F / ||A_i||_F for every problem into err[i] (a second
+   pass over the inputs, for measurement).  Synchronous. */
+qsk_status qsketch_batch_rel_error(qsk_batch *b, const void *const *planes, const int64_t *ld,
+                                   double *const *Q, const int64_t *ldq, double *const *X,
+                                   const int64_t *ldx, double *err);
+
+void qsketch_batch_destroy(qsk_batch *b);
+const char *qsketch_batch_last_error(const qsk_batch *b);
+
 /* Free everything.  Always valid, also on a poisoned context; NULL is a no-op. */
 void qsketch_destroy(qsk_ctx *ctx);
 

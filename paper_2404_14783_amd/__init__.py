@@ -98,6 +98,17 @@ def _load():
     lib.qsketch_strerror.restype = ctypes.c_char_p
     lib.qsketch_last_error.argtypes = [vp]
     lib.qsketch_last_error.restype = ctypes.c_char_p
+    pp, pi64 = ctypes.POINTER(vp), ctypes.POINTER(i64)
+    lib.qsketch_batch_init.argtypes = [i32, ctypes.POINTER(QskConfig), vp, ctypes.POINTER(vp)]
+    lib.qsketch_batch_init.restype = i32
+    lib.qsketch_batch_run.argtypes = [vp, i32, pp, pi64, pp, pi64, pp, pi64, ctypes.POINTER(QskReport)]
+    lib.qsketch_batch_run.restype = i32
+    lib.qsketch_batch_rel_error.argtypes = [vp, pp, pi64, pp, pi64, pp, pi64, ctypes.POINTER(ctypes.c_double)]
+    lib.qsketch_batch_rel_error.restype = i32
+    lib.qsketch_batch_destroy.argtypes = [vp]
+    lib.qsketch_batch_destroy.restype = None
+    lib.qsketch_batch_last_error.argtypes = [vp]
+    lib.qsketch_batch_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -239,6 +250,106 @@ class Sketcher:
         if self._ctx:
             self._lib.qsketch_destroy(self._ctx)
             self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _config(m, n, k, l, seed=0, embedding="gaussian", input_dtype="f32", sketch_dtype="bf16",
+            pure=False, split_terms=1, n_correction=3, n_power=3, max_block_cols=0):
+    lib = _load()
+    cfg = QskConfig()
+    lib.qsketch_config_default(ctypes.byref(cfg))
+    cfg.m, cfg.n, cfg.k, cfg.l = int(m), int(n), int(k), int(l)
+    cfg.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    cfg.embedding = EMBEDDINGS[embedding]
+    cfg.input_dtype = DTYPES[input_dtype]
+    cfg.sketch_dtype = DTYPES[sketch_dtype]
+    cfg.pure = 1 if pure else 0
+    cfg.split_terms = int(split_terms)
+    cfg.n_correction = int(n_correction)
+    cfg.n_power = int(n_power)
+    cfg.max_block_cols = int(max_block_cols)
+    return cfg
+
+
+class Batch:
+    """Independent problems run together (qsketch_batch_*): ``shapes`` is a list
+    of (m, n, k, l, seed); the remaining settings are common."""
+
+    def __init__(self, shapes, embedding="gaussian", input_dtype="f32", sketch_dtype="bf16",
+                 pure=False, split_terms=1, n_correction=3, n_power=3, stream=None):
+        lib = _load()
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        cfgs = (QskConfig * len(self.shapes))()
+        for i, (m, n, k, l, seed) in enumerate(self.shapes):
+            cfgs[i] = _config(m, n, k, l, seed, embedding, input_dtype, sketch_dtype, pure,
+                              split_terms, n_correction, n_power)
+        self.count = len(self.shapes)
+        self.pure = bool(pure)
+        self.input_dtype = input_dtype
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._b = ctypes.c_void_p()
+        st = lib.qsketch_batch_init(self.count, cfgs, ctypes.c_void_p(self.stream.cuda_stream),
+                                    ctypes.byref(self._b))
+        if st != QSK_OK:
+            raise QSketchError(st, lib.qsketch_strerror(st).decode())
+        self._lib = lib
+
+    def _check(self, st):
+        if st != QSK_OK:
+            msg = self._lib.qsketch_batch_last_error(self._b).decode() or self._lib.qsketch_strerror(st).decode()
+            raise QSketchError(st, msg)
+
+    def _ptr_tables(self, mats):
+        n = self.count
+        ptrs = (ctypes.c_void_p * (4 * n))()
+        lds = (ctypes.c_int64 * n)()
+        for i, t in enumerate(mats):
+            p4, ld = _plane_ptrs(t, self.pure and t.shape[0] == 3)
+            for q in range(4):
+                ptrs[4 * i + q] = p4[q]
+            lds[i] = ld
+        return ptrs, lds
+
+    def outputs(self):
+        qs_ = [qempty(4, m, k, torch.float64, self.device) for (m, n, k, l, s) in self.shapes]
+        xs_ = [qempty(4, k, n, torch.float64, self.device) for (m, n, k, l, s) in self.shapes]
+        return qs_, xs_
+
+    def run(self, mats, rangefinder="pseudo_qr", outputs=None):
+        """One-pass approximation of every matrix in ``mats`` (list of (4 or 3,
+        m, n) column-major device tensors); returns (Qs, Xs, reports)."""
+        if len(mats) != self.count:
+            raise ValueError("one matrix per problem")
+        for t in mats:
+            if t.dtype != TORCH_DTYPE[self.input_dtype]:
+                raise TypeError(f"dtype {t.dtype} != input dtype {self.input_dtype}")
+        qs_, xs_ = outputs if outputs is not None else self.outputs()
+        ap, ald = self._ptr_tables(mats)
+        qp, qld = self._ptr_tables(qs_)
+        xp, xld = self._ptr_tables(xs_)
+        reps = (QskReport * self.count)()
+        self._check(self._lib.qsketch_batch_run(self._b, RANGEFINDERS[rangefinder], ap, ald, qp, qld,
+                                                xp, xld, reps))
+        return qs_, xs_, [r.as_dict() for r in reps]
+
+    def rel_error(self, mats, qs_, xs_):
+        ap, ald = self._ptr_tables(mats)
+        qp, qld = self._ptr_tables(qs_)
+        xp, xld = self._ptr_tables(xs_)
+        out = (ctypes.c_double * self.count)()
+        self._check(self._lib.qsketch_batch_rel_error(self._b, ap, ald, qp, qld, xp, xld, out))
+        return list(out)
+
+    def close(self):
+        if self._b:
+            self._lib.qsketch_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
 
     def __del__(self):
         try:

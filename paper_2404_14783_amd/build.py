@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libqsketch.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["qsketch.cpp", "sketch_generic.hip", "sketch_mfma.hip", "finalize.hip"]
+SOURCES = ["qsketch.cpp", "batch.cpp", "sketch_generic.hip", "sketch_mfma.hip", "finalize.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -42,7 +42,7 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(5, len(SOURCES))) as ex:
         results = list(ex.map(_compile, SOURCES))
     objs = [o for o, _ in results]
     if verbose:

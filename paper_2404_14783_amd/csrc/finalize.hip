@@ -17,19 +17,52 @@ __device__ __forceinline__ qd load_q(const PlanesC<T> &z, int64_t idx) {
   return {ldv(z.p[0], idx), ldv(z.p[1], idx), ldv(z.p[2], idx), ldv(z.p[3], idx)};
 }
 
+template <typename T, typename P>
+__device__ __forceinline__ PlanesC<T> mkc_d(const P (&z)[4]) {
+  PlanesC<T> r;
+  for (int q = 0; q < 4; ++q) r.p[q] = (const T *)z[q];
+  return r;
+}
+
+// The problem and block indices of this block (see GroupRef).
+template <typename A>
+__device__ __forceinline__ bool group_select(const A &a0, const GroupRef &g, A &a, int &bx, int &by,
+                                             int &bz) {
+  if (!g.tab) {
+    a = a0;
+    bx = blockIdx.x; by = blockIdx.y; bz = blockIdx.z;
+    return true;
+  }
+  int p;
+  int64_t local;
+  group_find(g, &p, &local);
+  a = ((const A *)g.tab)[p];
+  bx = (int)(local % a.gx);
+  by = (int)((local / a.gx) % a.gy);
+  bz = (int)(local / ((int64_t)a.gx * a.gy));
+  return true;
+}
+
 // ---------------------------------------------------------------------------
 // C = Z1^* Z2 (k1 x k2) over a chunk of rows per block.z.
 template <typename T1, typename T2>
-__global__ __launch_bounds__(256) void crossprod_k(PlanesC<T1> z1, int64_t ld1, PlanesC<T2> z2,
-                                                   int64_t ld2, int64_t rows, int64_t chunk, int k1,
-                                                   int k2, double *partial, Planes<double> outp,
-                                                   int64_t ldo, int planar) {
+__global__ __launch_bounds__(256) void crossprod_k(CrossArgs args, GroupRef grp) {
+  CrossArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const PlanesC<T1> z1 = mkc_d<T1>(A.z1);
+  const PlanesC<T2> z2 = mkc_d<T2>(A.z2);
+  const int64_t ld1 = A.ld1, ld2 = A.ld2, rows = A.rows, chunk = A.chunk, ldo = A.ldo;
+  const int k1 = A.k1, k2 = A.k2, planar = A.planar;
+  double *partial = A.partial;
+  Planes<double> outp;
+  for (int q = 0; q < 4; ++q) outp.p[q] = A.out[q];
   __shared__ qd s1[32][17];
   __shared__ qd s2[32][17];
   const int tid = threadIdx.x;
   const int a = tid & 15, b = tid >> 4;
-  const int a0 = blockIdx.x * 16, b0 = blockIdx.y * 16;
-  const int64_t rs = (int64_t)blockIdx.z * chunk;
+  const int a0 = bx * 16, b0 = by * 16;
+  const int64_t rs = (int64_t)bz * chunk;
   const int64_t re = min(rows, rs + chunk);
   qd acc = qzero();
   for (int64_t r0 = rs; r0 < re; r0 += 32) {
@@ -51,14 +84,21 @@ __global__ __launch_bounds__(256) void crossprod_k(PlanesC<T1> z1, int64_t ld1, 
       const int64_t o = ga + (int64_t)gb * ldo;
       outp.p[0][o] = acc.w; outp.p[1][o] = acc.x; outp.p[2][o] = acc.y; outp.p[3][o] = acc.z;
     } else {
-      double *q = partial + 4 * (((int64_t)blockIdx.z * k2 + gb) * k1 + ga);
+      double *q = partial + 4 * (((int64_t)bz * k2 + gb) * k1 + ga);
       q[0] = acc.w; q[1] = acc.x; q[2] = acc.y; q[3] = acc.z;
     }
   }
 }
 
-__global__ void reduce_chunks_k(const double *partial, int nchunks, int64_t elems, double *out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void reduce_chunks_k(ReduceArgs args, GroupRef grp) {
+  ReduceArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const double *partial = A.partial;
+  const int nchunks = A.nchunks;
+  const int64_t elems = A.elems;
+  double *out = A.out;
+  const int64_t e = (int64_t)bx * blockDim.x + threadIdx.x;
   if (e >= elems) return;
   double s = 0.0;
   for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * elems + e];
@@ -66,9 +106,16 @@ __global__ void reduce_chunks_k(const double *partial, int nchunks, int64_t elem
 }
 
 // AoS (r x c, ld = r) partial sums -> planar output.
-__global__ void reduce_chunks_planar_k(const double *partial, int nchunks, int r, int c,
-                                       Planes<double> out, int64_t ldo) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void reduce_chunks_planar_k(ReducePlanarArgs args, GroupRef grp) {
+  ReducePlanarArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const double *partial = A.partial;
+  const int nchunks = A.nchunks, r = A.r, c = A.c;
+  Planes<double> out;
+  for (int q = 0; q < 4; ++q) out.p[q] = A.out[q];
+  const int64_t ldo = A.ldo;
+  const int64_t e = (int64_t)bx * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)r * c;
   if (e >= n) return;
   const int i = (int)(e % r), j = (int)(e / r);
@@ -95,63 +142,103 @@ static int64_t chunk_rows(int64_t rows, int tiles, int64_t max_chunks) {
   return chunk;
 }
 
+static void set_planes(const void *dst[4], const void *const src[4]) {
+  for (int q = 0; q < 4; ++q) dst[q] = src[q];
+}
+static void set_planes(double *dst[4], double *const src[4]) {
+  for (int q = 0; q < 4; ++q) dst[q] = src[q];
+}
+static void set_planes(const double *dst[4], const double *const src[4]) {
+  for (int q = 0; q < 4; ++q) dst[q] = src[q];
+}
+
+// Plan of a crossprod: chunking of the rows and the partial-sum size.
+bool plan_crossprod(int64_t rows, int k1, int k2, int64_t partial_elems, int64_t *chunk,
+                    int64_t *nch) {
+  const int tiles = ((k1 + 15) / 16) * ((k2 + 15) / 16);
+  const int64_t per = (int64_t)k1 * k2 * 4;
+  const int64_t max_chunks = partial_elems / per;
+  if (max_chunks < 1) return false;
+  *chunk = chunk_rows(rows, tiles, max_chunks);
+  *nch = (rows + *chunk - 1) / *chunk;
+  return *nch <= max_chunks;
+}
+
+hipError_t launch_crossprod_k(hipStream_t st, int t1, int t2, const CrossArgs &a, GroupRef g,
+                              int64_t blocks) {
+  dim3 grid = g.tab ? dim3((unsigned)blocks) : dim3(a.gx, a.gy, (unsigned)blocks);
+  if (t1 == 0 && t2 == 0)
+    hipLaunchKernelGGL((crossprod_k<double, double>), grid, dim3(256), 0, st, a, g);
+  else if (t1 == 1 && t2 == 1)
+    hipLaunchKernelGGL((crossprod_k<float, float>), grid, dim3(256), 0, st, a, g);
+  else if (t1 == 0 && t2 == 1)
+    hipLaunchKernelGGL((crossprod_k<double, float>), grid, dim3(256), 0, st, a, g);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_k(hipStream_t st, const ReduceArgs &a, GroupRef g, int64_t blocks) {
+  hipLaunchKernelGGL(reduce_chunks_k, dim3((unsigned)(g.tab ? blocks : a.gx)), dim3(256), 0, st, a, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_planar_k(hipStream_t st, const ReducePlanarArgs &a, GroupRef g,
+                                  int64_t blocks) {
+  hipLaunchKernelGGL(reduce_chunks_planar_k, dim3((unsigned)(g.tab ? blocks : a.gx)), dim3(256), 0,
+                     st, a, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_crossprod(hipStream_t st, int t1, const void *const z1[4], int64_t ld1, int t2,
                             const void *const z2[4], int64_t ld2, int64_t rows, int k1, int k2,
                             double *partials, int64_t partial_elems, double *out_aos) {
-  const int tiles = ((k1 + 15) / 16) * ((k2 + 15) / 16);
-  const int64_t per = (int64_t)k1 * k2 * 4;
-  int64_t max_chunks = partial_elems / per;
-  if (max_chunks < 1) return hipErrorInvalidValue;
-  const int64_t chunk = chunk_rows(rows, tiles, max_chunks);
-  const int64_t nch = (rows + chunk - 1) / chunk;
-  if (nch > max_chunks) return hipErrorInvalidValue;
-  dim3 g((k1 + 15) / 16, (k2 + 15) / 16, (unsigned)nch);
-  Planes<double> none{};
-  if (t1 == 0 && t2 == 0)
-    hipLaunchKernelGGL((crossprod_k<double, double>), g, dim3(256), 0, st, mkc<double>(z1), ld1,
-                       mkc<double>(z2), ld2, rows, chunk, k1, k2, partials, none, 0, 0);
-  else if (t1 == 1 && t2 == 1)
-    hipLaunchKernelGGL((crossprod_k<float, float>), g, dim3(256), 0, st, mkc<float>(z1), ld1,
-                       mkc<float>(z2), ld2, rows, chunk, k1, k2, partials, none, 0, 0);
-  else if (t1 == 0 && t2 == 1)
-    hipLaunchKernelGGL((crossprod_k<double, float>), g, dim3(256), 0, st, mkc<double>(z1), ld1,
-                       mkc<float>(z2), ld2, rows, chunk, k1, k2, partials, none, 0, 0);
-  else
-    return hipErrorInvalidValue;
-  hipError_t e = hipGetLastError();
+  int64_t chunk, nch;
+  if (!plan_crossprod(rows, k1, k2, partial_elems, &chunk, &nch)) return hipErrorInvalidValue;
+  CrossArgs a{};
+  set_planes(a.z1, z1);
+  set_planes(a.z2, z2);
+  a.ld1 = ld1; a.ld2 = ld2; a.rows = rows; a.chunk = chunk; a.k1 = k1; a.k2 = k2;
+  a.partial = partials; a.planar = 0;
+  a.gx = (k1 + 15) / 16; a.gy = (k2 + 15) / 16;
+  hipError_t e = launch_crossprod_k(st, t1, t2, a, GroupRef{}, nch);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(reduce_chunks_k, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, st,
-                     partials, (int)nch, per, out_aos);
-  return hipGetLastError();
+  ReduceArgs r{};
+  r.partial = partials; r.nchunks = (int)nch; r.elems = (int64_t)k1 * k2 * 4; r.out = out_aos;
+  r.gx = (int)((r.elems + 255) / 256); r.gy = 1;
+  return launch_reduce_k(st, r, GroupRef{}, r.gx);
 }
 
 hipError_t launch_crossprod_planar(hipStream_t st, const double *const z1[4], int64_t ld1, int t2,
                                    const void *const z2[4], int64_t ld2, int64_t rows, int k1,
                                    int k2, double *const out[4], int64_t ldo) {
-  dim3 g((k1 + 15) / 16, (k2 + 15) / 16, 1);
-  Planes<double> o;
-  for (int p = 0; p < 4; ++p) o.p[p] = out[p];
-  const void *zz1[4] = {z1[0], z1[1], z1[2], z1[3]};
-  if (t2 == 1)
-    hipLaunchKernelGGL((crossprod_k<double, float>), g, dim3(256), 0, st, mkc<double>(zz1), ld1,
-                       mkc<float>(z2), ld2, rows, rows, k1, k2, (double *)nullptr, o, ldo, 1);
-  else
-    hipLaunchKernelGGL((crossprod_k<double, double>), g, dim3(256), 0, st, mkc<double>(zz1), ld1,
-                       mkc<double>(z2), ld2, rows, rows, k1, k2, (double *)nullptr, o, ldo, 1);
-  return hipGetLastError();
+  CrossArgs a{};
+  for (int q = 0; q < 4; ++q) a.z1[q] = z1[q];
+  set_planes(a.z2, z2);
+  a.ld1 = ld1; a.ld2 = ld2; a.rows = rows; a.chunk = rows; a.k1 = k1; a.k2 = k2;
+  a.partial = nullptr; set_planes(a.out, out); a.ldo = ldo; a.planar = 1;
+  a.gx = (k1 + 15) / 16; a.gy = (k2 + 15) / 16;
+  return launch_crossprod_k(st, 0, t2, a, GroupRef{}, 1);
 }
 
 // ---------------------------------------------------------------------------
 // Out = Z C: one row per thread, 16 output columns per block.y, C staged in
 // LDS 64 rows at a time.
 template <typename TZ>
-__global__ __launch_bounds__(256) void apply_k(PlanesC<TZ> z, int64_t ldz, int64_t rows, int k,
-                                               const double *__restrict__ c, int kc,
-                                               Planes<double> out, int64_t ldo) {
+__global__ __launch_bounds__(256) void apply_k(ApplyArgs args, GroupRef grp) {
+  ApplyArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const PlanesC<TZ> z = mkc_d<TZ>(A.z);
+  const int64_t ldz = A.ldz, rows = A.rows, ldo = A.ldo;
+  const int k = A.k, kc = A.kc;
+  const double *__restrict__ c = A.c;
+  Planes<double> out;
+  for (int q = 0; q < 4; ++q) out.p[q] = A.out[q];
   __shared__ qd sc[64][16];
   const int tid = threadIdx.x;
-  const int b0 = blockIdx.y * 16;
-  const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+  const int b0 = by * 16;
+  const int64_t i = (int64_t)bx * 256 + tid;
   qd acc[16];
 #pragma unroll
   for (int b = 0; b < 16; ++b) acc[b] = qzero();
@@ -189,35 +276,43 @@ __global__ __launch_bounds__(256) void apply_k(PlanesC<TZ> z, int64_t ldz, int64
   }
 }
 
+hipError_t launch_apply_k(hipStream_t st, int tz, const ApplyArgs &a, GroupRef g, int64_t blocks) {
+  dim3 grid = g.tab ? dim3((unsigned)blocks) : dim3(a.gx, a.gy);
+  if (tz == 0) hipLaunchKernelGGL((apply_k<double>), grid, dim3(256), 0, st, a, g);
+  else hipLaunchKernelGGL((apply_k<float>), grid, dim3(256), 0, st, a, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_apply(hipStream_t st, int tz, const void *const z[4], int64_t ldz, int64_t rows,
                         int k, const double *c_aos, int kc, double *const out[4], int64_t ldo) {
-  dim3 g((unsigned)((rows + 255) / 256), (kc + 15) / 16);
-  Planes<double> o;
-  for (int p = 0; p < 4; ++p) o.p[p] = out[p];
-  if (tz == 0)
-    hipLaunchKernelGGL((apply_k<double>), g, dim3(256), 0, st, mkc<double>(z), ldz, rows, k, c_aos,
-                       kc, o, ldo);
-  else
-    hipLaunchKernelGGL((apply_k<float>), g, dim3(256), 0, st, mkc<float>(z), ldz, rows, k, c_aos,
-                       kc, o, ldo);
-  return hipGetLastError();
+  ApplyArgs a{};
+  set_planes(a.z, z);
+  a.ldz = ldz; a.rows = rows; a.k = k; a.c = c_aos; a.kc = kc;
+  set_planes(a.out, out); a.ldo = ldo;
+  a.gx = (int)((rows + 255) / 256); a.gy = (kc + 15) / 16;
+  return launch_apply_k(st, tz, a, GroupRef{}, 0);
 }
 
 // ---------------------------------------------------------------------------
 // P = Psi H, Psi (l x m) regenerated as the sketch of `mode` used it.  A
 // block owns 16 rows of Psi and every column of H (up to 16 tiles of 16), so
 // each entry of Psi is regenerated once per chunk of rows of H.
-__global__ __launch_bounds__(256) void psi_apply_k(int mode, int rad, uint32_t k0, uint32_t k1,
-                                                   int l, int64_t m, PlanesC<double> h,
-                                                   int64_t ldh, int k, int64_t chunk,
-                                                   double *partial) {
+__global__ __launch_bounds__(256) void psi_apply_k(PsiApplyArgs args, GroupRef grp) {
+  PsiApplyArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const int mode = A.mode, rad = A.rad, l = A.l, k = A.k;
+  const uint32_t k0 = A.k0, k1 = A.k1;
+  const int64_t m = A.m, ldh = A.ldh, chunk = A.chunk;
+  const PlanesC<double> h = mkc_d<double>(A.h);
+  double *partial = A.partial;
   __shared__ qd sp[16][33];
   __shared__ qd sh[32][17];
   const int tid = threadIdx.x;
   const int rr = tid & 15, bb = tid >> 4;
-  const int r0 = blockIdx.x * 16;
+  const int r0 = bx * 16;
   const int nbt = (k + 15) / 16;
-  const int64_t is = (int64_t)blockIdx.y * chunk;
+  const int64_t is = (int64_t)by * chunk;
   const int64_t ie = min(m, is + chunk);
   qd acc[16];
 #pragma unroll
@@ -254,38 +349,48 @@ __global__ __launch_bounds__(256) void psi_apply_k(int mode, int rad, uint32_t k
     for (int bt = 0; bt < 16; ++bt) {
       const int gb = bt * 16 + bb;
       if (bt < nbt && gb < k) {
-        double *q = partial + 4 * (((int64_t)blockIdx.y * k + gb) * l + gr);
+        double *q = partial + 4 * (((int64_t)by * k + gb) * l + gr);
         q[0] = acc[bt].w; q[1] = acc[bt].x; q[2] = acc[bt].y; q[3] = acc[bt].z;
       }
     }
   }
 }
 
+bool plan_psi_apply(int l, int64_t m, int k, int64_t partial_elems, int64_t *chunk, int64_t *nch) {
+  if (k > 256) return false;
+  const int tiles = (l + 15) / 16;
+  const int64_t per = (int64_t)l * k * 4;
+  const int64_t max_chunks = partial_elems / per;
+  if (max_chunks < 1) return false;
+  *chunk = chunk_rows(m, tiles, max_chunks);
+  *nch = (m + *chunk - 1) / *chunk;
+  return *nch <= max_chunks;
+}
+
+hipError_t launch_psi_apply_k(hipStream_t st, const PsiApplyArgs &a, GroupRef g, int64_t blocks) {
+  dim3 grid = g.tab ? dim3((unsigned)blocks) : dim3(a.gx, a.gy);
+  hipLaunchKernelGGL(psi_apply_k, grid, dim3(256), 0, st, a, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_psi_apply(hipStream_t st, int mode, int rad, uint32_t k0, uint32_t k1, int l,
                             int64_t m, const double *const h[4], int64_t ldh, int k,
                             double *partials, int64_t partial_elems, double *const p[4],
                             int64_t ldp) {
-  if (k > 256) return hipErrorInvalidValue;
-  const int tiles = (l + 15) / 16;
-  const int64_t per = (int64_t)l * k * 4;
-  const int64_t max_chunks = partial_elems / per;
-  if (max_chunks < 1) return hipErrorInvalidValue;
-  const int64_t chunk = chunk_rows(m, tiles, max_chunks);
-  const int64_t nch = (m + chunk - 1) / chunk;
-  if (nch > max_chunks) return hipErrorInvalidValue;
-  PlanesC<double> hh;
-  for (int q = 0; q < 4; ++q) hh.p[q] = h[q];
-  dim3 g(tiles, (unsigned)nch);
-  hipLaunchKernelGGL(psi_apply_k, g, dim3(256), 0, st, mode, rad, k0, k1, l, m, hh, ldh, k, chunk,
-                     partials);
-  hipError_t e = hipGetLastError();
+  int64_t chunk, nch;
+  if (!plan_psi_apply(l, m, k, partial_elems, &chunk, &nch)) return hipErrorInvalidValue;
+  PsiApplyArgs a{};
+  a.mode = mode; a.rad = rad; a.k0 = k0; a.k1 = k1; a.l = l; a.m = m;
+  set_planes(a.h, h);
+  a.ldh = ldh; a.k = k; a.chunk = chunk; a.partial = partials;
+  a.gx = (l + 15) / 16; a.gy = (int)nch;
+  hipError_t e = launch_psi_apply_k(st, a, GroupRef{}, 0);
   if (e != hipSuccess) return e;
-  Planes<double> o;
-  for (int q = 0; q < 4; ++q) o.p[q] = p[q];
-  const int64_t n = (int64_t)l * k;
-  hipLaunchKernelGGL(reduce_chunks_planar_k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                     partials, (int)nch, l, k, o, ldp);
-  return hipGetLastError();
+  ReducePlanarArgs r{};
+  r.partial = partials; r.nchunks = (int)nch; r.r = l; r.c = k;
+  set_planes(r.out, p); r.ldo = ldp;
+  r.gx = (int)(((int64_t)l * k + 255) / 256); r.gy = 1;
+  return launch_reduce_planar_k(st, r, GroupRef{}, r.gx);
 }
 
 // ---------------------------------------------------------------------------
@@ -322,15 +427,21 @@ template <> __device__ __forceinline__ double lda_val<uint16_t>(const uint16_t *
 }
 
 template <typename TIN>
-__global__ __launch_bounds__(256) void error_k(PlanesC<TIN> a, int64_t lda, int pure, int64_t m,
-                                               int64_t n, PlanesC<double> q, int64_t ldq,
-                                               PlanesC<double> x, int64_t ldx, int k, double *acc) {
+__global__ __launch_bounds__(256) void error_k(ErrorArgs args, GroupRef grp) {
+  ErrorArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const PlanesC<TIN> a = mkc_d<TIN>(A.a);
+  const PlanesC<double> q = mkc_d<double>(A.q), x = mkc_d<double>(A.x);
+  const int64_t lda = A.lda, m = A.m, n = A.n, ldq = A.ldq, ldx = A.ldx;
+  const int pure = A.pure, k = A.k;
+  double *acc = A.acc;
   __shared__ qd sq[64][9];
   __shared__ qd sx[8][65];
   __shared__ double red[2][256];
   const int tid = threadIdx.x;
   const int tr = tid & 15, tc = tid >> 4;      // 4 x 4 outputs per thread
-  const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
+  const int64_t i0 = (int64_t)bx * 64, j0 = (int64_t)by * 64;
   qd c[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
@@ -383,23 +494,26 @@ __global__ __launch_bounds__(256) void error_k(PlanesC<TIN> a, int64_t lda, int 
   if (tid == 0) { atomicAdd(&acc[0], red[0][0]); atomicAdd(&acc[1], red[1][0]); }
 }
 
+hipError_t launch_error_k(hipStream_t st, int tin, const ErrorArgs &a, GroupRef g, int64_t blocks) {
+  dim3 grid = g.tab ? dim3((unsigned)blocks) : dim3(a.gx, a.gy);
+  if (tin == DT_F64) hipLaunchKernelGGL((error_k<double>), grid, dim3(256), 0, st, a, g);
+  else if (tin == DT_F32) hipLaunchKernelGGL((error_k<float>), grid, dim3(256), 0, st, a, g);
+  else hipLaunchKernelGGL((error_k<uint16_t>), grid, dim3(256), 0, st, a, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_error(hipStream_t st, int tin, const void *const a[4], int64_t lda, int pure,
                         int64_t m, int64_t n, const double *const q[4], int64_t ldq,
                         const double *const x[4], int64_t ldx, int k, double *acc) {
-  PlanesC<double> qq, xx;
-  for (int p = 0; p < 4; ++p) { qq.p[p] = q[p]; xx.p[p] = x[p]; }
-  const void *aa[4] = {a[0] ? a[0] : a[1], a[1], a[2], a[3]};
-  dim3 g((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64));
-  if (tin == DT_F64)
-    hipLaunchKernelGGL((error_k<double>), g, dim3(256), 0, st, mkc<double>(aa), lda, pure, m, n, qq,
-                       ldq, xx, ldx, k, acc);
-  else if (tin == DT_F32)
-    hipLaunchKernelGGL((error_k<float>), g, dim3(256), 0, st, mkc<float>(aa), lda, pure, m, n, qq,
-                       ldq, xx, ldx, k, acc);
-  else
-    hipLaunchKernelGGL((error_k<uint16_t>), g, dim3(256), 0, st, mkc<uint16_t>(aa), lda, pure, m,
-                       n, qq, ldq, xx, ldx, k, acc);
-  return hipGetLastError();
+  ErrorArgs e{};
+  e.a[0] = a[0] ? a[0] : a[1];
+  for (int p = 1; p < 4; ++p) e.a[p] = a[p];
+  e.lda = lda; e.pure = pure; e.m = m; e.n = n;
+  set_planes(e.q, q); e.ldq = ldq;
+  set_planes(e.x, x); e.ldx = ldx;
+  e.k = k; e.acc = acc;
+  e.gx = (int)((m + 63) / 64); e.gy = (int)((n + 63) / 64);
+  return launch_error_k(st, tin, e, GroupRef{}, 0);
 }
 
 // ===========================================================================
@@ -625,9 +739,16 @@ __device__ void sm_sorted_columns(const double *a, int rows, int cols, int lda, 
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void chol_kernel(const double *g, int k, int complex_only,
-                                                    double shift, double tol, double *r,
-                                                    SmallStatus *status) {
+__global__ __launch_bounds__(1024) void chol_kernel(CholArgs args, GroupRef grp) {
+  CholArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const double *g = A.g;
+  const int k = A.k, complex_only = A.complex_only;
+  const double shift = A.shift, tol = A.tol;
+  double *r = A.r;
+  SmallStatus *status = A.status;
+  if (A.only_failed && !status->fail) return;
   __shared__ int fail;
   __shared__ double minp, trace;
   sm_chol(g, r, k, complex_only, shift, tol, &fail, &minp, &trace);
@@ -641,12 +762,19 @@ __global__ __launch_bounds__(1024) void chol_kernel(const double *g, int k, int 
 
 // T = R^{-1}, one workgroup per column c: T[a, c] = -(1/R[a,a]) sum_{b>a} R[a,b] T[b,c]
 // bottom-up, the column held in LDS.  Skipped when the Cholesky failed.
-__global__ __launch_bounds__(256) void triinv_kernel(const double *r, double *t, int k,
-                                                     const SmallStatus *status) {
+__global__ __launch_bounds__(256) void triinv_kernel(CholArgs args, GroupRef grp) {
+  CholArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const double *r = A.r;
+  double *t = A.t;
+  const int k = A.k;
+  const SmallStatus *status = A.status;
   __shared__ qd col[256];
   __shared__ qd red[4];
   if (status && status->fail) return;
-  const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (bx >= k) return;
+  const int c = bx, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int a = tid; a < k; a += 256) col[a] = qzero();
   __syncthreads();
   if (tid == 0) col[c] = {1.0 / r[4 * (c + (int64_t)c * k)], 0.0, 0.0, 0.0};
@@ -666,25 +794,40 @@ __global__ __launch_bounds__(256) void triinv_kernel(const double *r, double *t,
   for (int a = tid; a < k; a += 256) sq_(t, a, c, k, col[a]);
 }
 
+hipError_t launch_chol_k(hipStream_t st, const CholArgs &a, GroupRef g, int count) {
+  hipLaunchKernelGGL(chol_kernel, dim3(g.tab ? count : 1), dim3(1024), 0, st, a, g);
+  return hipGetLastError();
+}
+hipError_t launch_triinv_k(hipStream_t st, const CholArgs &a, GroupRef g, int64_t blocks) {
+  hipLaunchKernelGGL(triinv_kernel, dim3((unsigned)(g.tab ? blocks : a.k)), dim3(256), 0, st, a, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_chol_inv(hipStream_t st, const double *g, int k, int complex_only, double shift,
                            double tol, double *r, double *t, SmallStatus *status) {
-  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(1024), 0, st, g, k, complex_only, shift, tol, r,
-                     status);
-  hipError_t e = hipGetLastError();
+  CholArgs a{};
+  a.g = g; a.k = k; a.complex_only = complex_only; a.shift = shift; a.tol = tol;
+  a.r = r; a.t = t; a.status = status; a.only_failed = 0;
+  a.gx = k; a.gy = 1;
+  hipError_t e = launch_chol_k(st, a, GroupRef{}, 1);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(triinv_kernel, dim3(k), dim3(256), 0, st, (const double *)r, t, k,
-                     (const SmallStatus *)status);
-  return hipGetLastError();
+  return launch_triinv_k(st, a, GroupRef{}, 0);
 }
 
 // C = opA(A) opB(B) for k x k AoS matrices: 16 x 16 output tiles per block,
 // 16-wide slabs of A and B staged in LDS.
-__global__ __launch_bounds__(256) void qgemm_small_kernel(int k, const double *a, int opa,
-                                                          const double *b, int opb, double *c) {
+__global__ __launch_bounds__(256) void qgemm_small_kernel(GemmArgs args, GroupRef grp) {
+  GemmArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const int k = A.k, opa = A.opa, opb = A.opb;
+  const double *a = A.a, *b = A.b;
+  double *c = A.c;
   __shared__ qd sa[16][17];
   __shared__ qd sb[16][17];
   const int tid = threadIdx.x, ti = tid & 15, tj = tid >> 4;
-  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+  const int i0 = bx * 16, j0 = by * 16;
+  if (i0 >= k || j0 >= k) return;
   qd acc = qzero();
   for (int t0 = 0; t0 < k; t0 += 16) {
     {
@@ -705,20 +848,33 @@ __global__ __launch_bounds__(256) void qgemm_small_kernel(int k, const double *a
   if (i0 + ti < k && j0 + tj < k) sq_(c, i0 + ti, j0 + tj, k, acc);
 }
 
+hipError_t launch_gemm_k(hipStream_t st, const GemmArgs &a, GroupRef g, int64_t blocks) {
+  dim3 grid = g.tab ? dim3((unsigned)blocks) : dim3(a.gx, a.gy);
+  hipLaunchKernelGGL(qgemm_small_kernel, grid, dim3(256), 0, st, a, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_small_gemm(hipStream_t st, int k, const double *a, int opa, const double *b,
                              int opb, double *c) {
-  dim3 g((k + 15) / 16, (k + 15) / 16);
-  hipLaunchKernelGGL(qgemm_small_kernel, g, dim3(256), 0, st, k, a, opa, b, opb, c);
-  return hipGetLastError();
+  GemmArgs x{};
+  x.k = k; x.a = a; x.opa = opa; x.b = b; x.opb = opb; x.c = c;
+  x.gx = (k + 15) / 16; x.gy = (k + 15) / 16;
+  return launch_gemm_k(st, x, GroupRef{}, 0);
 }
 
 // One correction step's eps and M (eq. CondNumReductionIter in the k x k
 // space): n_power normalised power iterates v <- G^{-1} v from the Philox
 // stream-2 start vector of step `step`, eps = (v^* G^{-1} v)^{-1/2}, and
 // M = (1 - eps) I + eps G^{-1}.
-__global__ __launch_bounds__(1024) void power_m_kernel(int k, const double *gi, int step, int n_power,
-                                                       uint32_t k0, uint32_t k1, double *m_out,
-                                                       SmallStatus *status) {
+__global__ __launch_bounds__(1024) void power_m_kernel(PowerArgs args, GroupRef grp) {
+  PowerArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const int k = A.k, step = A.step, n_power = A.n_power;
+  const double *gi = A.gi;
+  const uint32_t k0 = A.k0, k1 = A.k1;
+  double *m_out = A.m_out;
+  SmallStatus *status = A.status;
   __shared__ double v[4 * 256], w[4 * 256];
   __shared__ double s_nrm, s_eps;
   const int tid = threadIdx.x;
@@ -767,18 +923,48 @@ __global__ __launch_bounds__(1024) void power_m_kernel(int k, const double *gi, 
   }
 }
 
-hipError_t launch_power_m(hipStream_t st, int k, const double *gi, int step, int n_power,
-                          uint32_t k0, uint32_t k1, double *m_out, SmallStatus *status) {
-  hipLaunchKernelGGL(power_m_kernel, dim3(1), dim3(1024), 0, st, k, gi, step, n_power, k0, k1, m_out,
-                     status);
+hipError_t launch_power_k(hipStream_t st, const PowerArgs &a, GroupRef g, int count) {
+  hipLaunchKernelGGL(power_m_kernel, dim3(g.tab ? count : 1), dim3(1024), 0, st, a, g);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(1024) void identity_kernel(int k, double *c) { sm_identity(c, k); }
+hipError_t launch_power_m(hipStream_t st, int k, const double *gi, int step, int n_power,
+                          uint32_t k0, uint32_t k1, double *m_out, SmallStatus *status) {
+  PowerArgs a{};
+  a.k = k; a.gi = gi; a.step = step; a.n_power = n_power; a.k0 = k0; a.k1 = k1;
+  a.m_out = m_out; a.status = status; a.gx = 1; a.gy = 1;
+  return launch_power_k(st, a, GroupRef{}, 1);
+}
+
+__global__ __launch_bounds__(1024) void identity_kernel(GemmArgs args, GroupRef grp) {
+  GemmArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  sm_identity(A.c, A.k);
+}
+
+// C = A (k x k AoS copy)
+__global__ __launch_bounds__(1024) void copy_small_kernel(GemmArgs args, GroupRef grp) {
+  GemmArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const int64_t n = 4 * (int64_t)A.k * A.k;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) A.c[e] = A.a[e];
+}
+
+hipError_t launch_identity_k(hipStream_t st, const GemmArgs &a, GroupRef g, int count) {
+  hipLaunchKernelGGL(identity_kernel, dim3(g.tab ? count : 1), dim3(1024), 0, st, a, g);
+  return hipGetLastError();
+}
+hipError_t launch_copy_small_k(hipStream_t st, const GemmArgs &a, GroupRef g, int count) {
+  hipLaunchKernelGGL(copy_small_kernel, dim3(g.tab ? count : 1), dim3(1024), 0, st, a, g);
+  return hipGetLastError();
+}
 
 hipError_t launch_identity(hipStream_t st, int k, double *c) {
-  hipLaunchKernelGGL(identity_kernel, dim3(1), dim3(1024), 0, st, k, c);
-  return hipGetLastError();
+  GemmArgs a{};
+  a.k = k; a.c = c; a.gx = 1; a.gy = 1;
+  return launch_identity_k(st, a, GroupRef{}, 1);
 }
 
 // LDS pool (doubles) of the tridiagonalisation and of the eigenvector clean-up.
@@ -794,9 +980,14 @@ __device__ __forceinline__ void sm_heev(double *g, int k, double *lam, double *U
 // 2^-53).  Bad part: B = [u_b..., -u_b j ...] (the two members of each bad
 // pair), B diag(f) with f from Philox stream 3, Jacobi SVD, one column per
 // pair of the leading 2t.  Output C (k x k): H = Q_Y C = [H_g, H_b~].
-__global__ __launch_bounds__(1024) void psvd_select_kernel(int k, double *gl, uint32_t k0,
-                                                           uint32_t k1, double *c, double *work,
-                                                           SmallStatus *status) {
+__global__ __launch_bounds__(1024) void psvd_select_kernel(PsvdArgs args, GroupRef grp) {
+  PsvdArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const int k = A.k;
+  double *gl = A.gl, *c = A.c, *work = A.work;
+  const uint32_t k0 = A.k0, k1 = A.k1;
+  SmallStatus *status = A.status;
   __shared__ int order[512];
   __shared__ double sig[512];
   __shared__ double lam[256];
@@ -866,10 +1057,17 @@ __global__ __launch_bounds__(1024) void psvd_select_kernel(int k, double *gl, ui
   }
 }
 
+hipError_t launch_psvd_k(hipStream_t st, const PsvdArgs &a, GroupRef g, int count) {
+  hipLaunchKernelGGL(psvd_select_kernel, dim3(g.tab ? count : 1), dim3(1024), 0, st, a, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_psvd_select(hipStream_t st, int k, double *gl, uint32_t k0, uint32_t k1,
                               double *c, double *work, SmallStatus *status) {
-  hipLaunchKernelGGL(psvd_select_kernel, dim3(1), dim3(1024), 0, st, k, gl, k0, k1, c, work, status);
-  return hipGetLastError();
+  PsvdArgs a{};
+  a.k = k; a.gl = gl; a.k0 = k0; a.k1 = k1; a.c = c; a.work = work; a.status = status;
+  a.gx = 1; a.gy = 1;
+  return launch_psvd_k(st, a, GroupRef{}, 1);
 }
 
 // Minimum-norm least squares for a rank-deficient P (l x k, planar):
@@ -877,9 +1075,17 @@ hipError_t launch_psvd_select(hipStream_t st, int k, double *gl, uint32_t k0, ui
 // P V = B with orthogonal columns and V accumulated; with sigma_i = ||b_i||,
 // P^dagger = V diag(1/sigma_i^2) B^* over sigma_i > tol sigma_max, so
 // S^* = (P^dagger)^* = B diag(w) V^*, written planar (l x k).
-__global__ __launch_bounds__(1024) void pinv_sstar_kernel(int l, int k, PlanesC<double> p,
-                                                          int64_t ldp, double tol, double *work,
-                                                          Planes<double> out, int64_t ldo) {
+__global__ __launch_bounds__(1024) void pinv_sstar_kernel(PinvArgs args, GroupRef grp) {
+  PinvArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const int l = A.l, k = A.k;
+  const PlanesC<double> p = mkc_d<double>(A.p);
+  const int64_t ldp = A.ldp, ldo = A.ldo;
+  const double tol = A.tol;
+  double *work = A.work;
+  Planes<double> out;
+  for (int q = 0; q < 4; ++q) out.p[q] = A.out[q];
   __shared__ double sig[256];
   __shared__ double s_max;
   const int rows = l + k;
@@ -920,13 +1126,17 @@ __global__ __launch_bounds__(1024) void pinv_sstar_kernel(int l, int k, PlanesC<
   }
 }
 
+hipError_t launch_pinv_k(hipStream_t st, const PinvArgs &a, GroupRef g, int count) {
+  hipLaunchKernelGGL(pinv_sstar_kernel, dim3(g.tab ? count : 1), dim3(1024), 0, st, a, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_pinv_sstar(hipStream_t st, int l, int k, const double *const p[4], int64_t ldp,
                              double tol, double *work, double *const out[4], int64_t ldo) {
-  PlanesC<double> pp;
-  Planes<double> oo;
-  for (int q = 0; q < 4; ++q) { pp.p[q] = p[q]; oo.p[q] = out[q]; }
-  hipLaunchKernelGGL(pinv_sstar_kernel, dim3(1), dim3(1024), 0, st, l, k, pp, ldp, tol, work, oo, ldo);
-  return hipGetLastError();
+  PinvArgs a{};
+  a.l = l; a.k = k; set_planes(a.p, p); a.ldp = ldp; a.tol = tol; a.work = work;
+  set_planes(a.out, out); a.ldo = ldo; a.gx = 1; a.gy = 1;
+  return launch_pinv_k(st, a, GroupRef{}, 1);
 }
 
 // Householder reduction of a k x k quaternion Hermitian matrix to a real
@@ -1365,8 +1575,14 @@ __device__ __forceinline__ void sm_heev(double *g, int k, double *lam, double *U
 // squared singular values of H, so kappa(H) = sqrt(lambda_max / lambda_min)
 // (Section 3.1, after Remark 3.1).  which: 0 -> status->kappa (and the
 // orthonormality defect max|G_H - I|), 1 -> status->kappa_initial.
-__global__ __launch_bounds__(1024) void kappa_kernel(int k, const double *gh, double *work, int which,
-                                                     SmallStatus *status) {
+__global__ __launch_bounds__(1024) void kappa_kernel(KappaArgs args, GroupRef grp) {
+  KappaArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const int k = A.k, which = A.which;
+  const double *gh = A.gh;
+  double *work = A.work;
+  SmallStatus *status = A.status;
   __shared__ double dd[256], ee[256], lam[256];
   __shared__ double s_def;
   const int64_t kk = (int64_t)k * k * 4;
@@ -1405,10 +1621,16 @@ __global__ __launch_bounds__(1024) void kappa_kernel(int k, const double *gh, do
   }
 }
 
+hipError_t launch_kappa_k(hipStream_t st, const KappaArgs &a, GroupRef g, int count) {
+  hipLaunchKernelGGL(kappa_kernel, dim3(g.tab ? count : 1), dim3(1024), 0, st, a, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_kappa(hipStream_t st, int k, const double *gh, double *work, int which,
                         SmallStatus *status) {
-  hipLaunchKernelGGL(kappa_kernel, dim3(1), dim3(1024), 0, st, k, gh, work, which, status);
-  return hipGetLastError();
+  KappaArgs a{};
+  a.k = k; a.gh = gh; a.work = work; a.which = which; a.status = status; a.gx = 1; a.gy = 1;
+  return launch_kappa_k(st, a, GroupRef{}, 1);
 }
 
 }  // namespace qsk

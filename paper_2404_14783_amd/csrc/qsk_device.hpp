@@ -218,6 +218,21 @@ __device__ __forceinline__ void embed_entry_as_used(int mode, int rademacher, ui
 }
 
 // ---------------------------------------------------------------------------
+// Grouped launches (see GroupRef): the problem p of this block and the
+// block's linear index within that problem.
+__device__ __forceinline__ void group_find(const GroupRef &g, int *p, int64_t *local) {
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = g.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g.prefix[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  *p = lo;
+  *local = b - g.prefix[lo];
+}
+
+// ---------------------------------------------------------------------------
 // FP64 quaternion arithmetic (Hamilton product, Section 2).
 struct qd { double w, x, y, z; };
 

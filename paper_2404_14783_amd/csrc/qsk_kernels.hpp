@@ -49,6 +49,28 @@ struct MfmaStage {
 };
 void stage_geometry(int64_t m, int l, int k, int64_t maxcols, int op_bf16, int *LP, int64_t *MP,
                     int *KP, int64_t *NP);
+// Device copies of small argument tables (grouped launches).  `host` is
+// pinned; push copies `bytes` to the next free slot and enqueues its upload
+// on `st`, returning the device address (nullptr when full).  Reset `used`
+// only after the stream has passed every launch that reads the tables.
+struct ArgArena {
+  char *host;
+  char *dev;
+  size_t cap, used;
+};
+void *arena_push(ArgArena &a, hipStream_t st, const void *src, size_t bytes);
+
+// Batches of problems on the matrix-core path (see batch.cpp).
+void batch_tiles(const int *l, const int *k, int count, int op_bf16, int *nmt, int *nj);
+void stage_geometry_tiles(int64_t m, int l, int k, int64_t maxcols, int nmt, int nj, int *LP,
+                          int64_t *MP, int *KP, int64_t *NP);
+// Omega (all s.ncols columns) and Psi of one problem into its staging buffers.
+hipError_t stage_test_matrices(const SketchArgs &s, const MfmaStage &g);
+// Y = A Omega and W = Psi A of `count` problems (s[i].col0 = 0, s[i].ncols = n)
+// in one grouped launch per product.
+hipError_t launch_sketch_mfma_batch(const SketchArgs *s, const MfmaStage *g, int count, int nmt,
+                                    int nj, ArgArena &ar);
+
 // Copies of Y the matrix-core Y kernel splits its columns over; Y is their sum.
 constexpr int Y_COPIES = 4;
 // copy 0 += copies 1 .. S-1 (each n_per_copy floats), which are cleared.
@@ -103,6 +125,84 @@ struct SmallStatus {
   int pad;
 };
 
+// ---------------------------------------------------------------------------
+// Argument structs of the FP64 finalize kernels.  Every kernel takes its
+// struct by value plus a GroupRef: with tab == nullptr it is a plain launch
+// for one problem (block indices from the grid); otherwise tab points to
+// `count` structs in device memory, prefix[p] is the first linear block of
+// problem p (prefix[count] = total blocks), and each block finds its problem
+// and its (bx, by, bz) within that problem's gx x gy x gz grid.
+struct GroupRef {
+  const void *tab;
+  const int64_t *prefix;
+  int count;
+};
+
+struct CrossArgs {          // C = Z1^* Z2 over row chunks (bz), 16 x 16 tiles (bx, by)
+  const void *z1[4]; int64_t ld1;
+  const void *z2[4]; int64_t ld2;
+  int64_t rows, chunk;
+  int k1, k2;
+  double *partial;          // [chunk][k2][k1] AoS when !planar
+  double *out[4]; int64_t ldo;
+  int planar;
+  int gx, gy;
+};
+struct ReduceArgs { const double *partial; int nchunks; int64_t elems; double *out; int gx, gy; };
+struct ReducePlanarArgs {
+  const double *partial; int nchunks, r, c;
+  double *out[4]; int64_t ldo;
+  int gx, gy;
+};
+struct ApplyArgs {          // Out = Z C
+  const void *z[4]; int64_t ldz, rows;
+  int k;
+  const double *c; int kc;
+  double *out[4]; int64_t ldo;
+  int gx, gy;
+};
+struct PsiApplyArgs {       // partial sums of Psi H
+  int mode, rad;
+  uint32_t k0, k1;
+  int l;
+  int64_t m;
+  const double *h[4]; int64_t ldh;
+  int k;
+  int64_t chunk;
+  double *partial;
+  int gx, gy;
+};
+struct ErrorArgs {
+  const void *a[4]; int64_t lda;
+  int pure;
+  int64_t m, n;
+  const double *q[4]; int64_t ldq;
+  const double *x[4]; int64_t ldx;
+  int k;
+  double *acc;
+  int gx, gy;
+};
+struct CholArgs {           // R = chol(G'), T = R^{-1}
+  const double *g;
+  int k, complex_only;
+  double shift, tol;
+  double *r, *t;
+  SmallStatus *status;
+  int only_failed;          // factor only where status->fail is set (the shifted retry)
+  int gx, gy;
+};
+struct GemmArgs { int k; const double *a; int opa; const double *b; int opb; double *c; int gx, gy; };
+struct PowerArgs {
+  int k; const double *gi; int step, n_power; uint32_t k0, k1; double *m_out; SmallStatus *status;
+  int gx, gy;
+};
+struct PsvdArgs { int k; double *gl; uint32_t k0, k1; double *c, *work; SmallStatus *status; int gx, gy; };
+struct PinvArgs {
+  int l, k; const double *p[4]; int64_t ldp; double tol; double *work; double *out[4]; int64_t ldo;
+  int gx, gy;
+};
+struct KappaArgs { int k; const double *gh; double *work; int which; SmallStatus *status; int gx, gy; };
+
 // R = chol(G') with G' = G (full quaternion) or its complex part (j-part
 // zeroed) when complex_only; plus `shift` * I when shift > 0; T = R^{-1}.
 // A pivot^2 <= tol * max diagonal counts as a failure.
@@ -129,5 +229,25 @@ hipError_t launch_pinv_sstar(hipStream_t st, int l, int k, const double *const p
                              double tol, double *work, double *const out[4], int64_t ldo);
 // identity into a k x k AoS buffer
 hipError_t launch_identity(hipStream_t st, int k, double *c);
+
+// Kernel launches taking an argument struct and a GroupRef (batched form:
+// `blocks` / `count` = total linear blocks / problems of the table).
+bool plan_crossprod(int64_t rows, int k1, int k2, int64_t partial_elems, int64_t *chunk, int64_t *nch);
+bool plan_psi_apply(int l, int64_t m, int k, int64_t partial_elems, int64_t *chunk, int64_t *nch);
+hipError_t launch_crossprod_k(hipStream_t st, int t1, int t2, const CrossArgs &a, GroupRef g, int64_t blocks);
+hipError_t launch_reduce_k(hipStream_t st, const ReduceArgs &a, GroupRef g, int64_t blocks);
+hipError_t launch_reduce_planar_k(hipStream_t st, const ReducePlanarArgs &a, GroupRef g, int64_t blocks);
+hipError_t launch_apply_k(hipStream_t st, int tz, const ApplyArgs &a, GroupRef g, int64_t blocks);
+hipError_t launch_psi_apply_k(hipStream_t st, const PsiApplyArgs &a, GroupRef g, int64_t blocks);
+hipError_t launch_error_k(hipStream_t st, int tin, const ErrorArgs &a, GroupRef g, int64_t blocks);
+hipError_t launch_chol_k(hipStream_t st, const CholArgs &a, GroupRef g, int count);
+hipError_t launch_triinv_k(hipStream_t st, const CholArgs &a, GroupRef g, int64_t blocks);
+hipError_t launch_gemm_k(hipStream_t st, const GemmArgs &a, GroupRef g, int64_t blocks);
+hipError_t launch_power_k(hipStream_t st, const PowerArgs &a, GroupRef g, int count);
+hipError_t launch_identity_k(hipStream_t st, const GemmArgs &a, GroupRef g, int count);
+hipError_t launch_copy_small_k(hipStream_t st, const GemmArgs &a, GroupRef g, int count);
+hipError_t launch_psvd_k(hipStream_t st, const PsvdArgs &a, GroupRef g, int count);
+hipError_t launch_pinv_k(hipStream_t st, const PinvArgs &a, GroupRef g, int count);
+hipError_t launch_kappa_k(hipStream_t st, const KappaArgs &a, GroupRef g, int count);
 
 }  // namespace qsk

@@ -21,6 +21,7 @@
 // from the Philox stream into a transient staging buffer by gen_stage_kernel,
 // already rounded to the operand format, then read by the GEMMs.
 #include <type_traits>
+#include <vector>
 
 #include "qsk_device.hpp"
 #include "qsk_kernels.hpp"
@@ -217,7 +218,17 @@ struct WArgs {
 };
 
 template <int OP, typename TIN, int NMT, int TERMS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void w_mfma_kernel(WArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void w_mfma_kernel(WArgs a0, GroupRef grp) {
+  WArgs a;
+  int64_t t;
+  if (grp.tab) {
+    int p;
+    group_find(grp, &p, &t);
+    a = ((const WArgs *)grp.tab)[p];
+  } else {
+    a = a0;
+    t = xcd_tile(blockIdx.x, (int64_t)a.ctiles * a.rgroups * a.S);
+  }
   using OPT = typename std::conditional<OP == OP_BF16, uint16_t, float>::type;
   using Frag = typename std::conditional<OP == OP_BF16, FragB, FragF>::type;
   constexpr int LDK = 32 + (OP == OP_BF16 ? 8 : 4);        // padded K stride in LDS
@@ -229,8 +240,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   __shared__ OPT s_psi[4][NMT * 16][LDK];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int c16 = lane & 15, g = lane >> 4;
-  const int64_t total = (int64_t)a.ctiles * a.rgroups * a.S;
-  const int64_t t = xcd_tile(blockIdx.x, total);
   const int bx = (int)(t % a.ctiles);
   const int by = (int)((t / a.ctiles) % a.rgroups);
   const int bz = (int)(t / ((int64_t)a.ctiles * a.rgroups));
@@ -358,7 +367,17 @@ struct YArgs {
 };
 
 template <int OP, typename TIN, int NJ, int TERMS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void y_mfma_kernel(YArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void y_mfma_kernel(YArgs a0, GroupRef grp) {
+  YArgs a;
+  int64_t t;
+  if (grp.tab) {
+    int p;
+    group_find(grp, &p, &t);
+    a = ((const YArgs *)grp.tab)[p];
+  } else {
+    a = a0;
+    t = xcd_tile(blockIdx.x, (int64_t)a.rblocks * a.cgroups * a.S);
+  }
   using OPT = typename std::conditional<OP == OP_BF16, uint16_t, float>::type;
   using Frag = typename std::conditional<OP == OP_BF16, FragB, FragF>::type;
   constexpr int NT = TERMS;
@@ -373,8 +392,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   __shared__ OPT s_om[4][NJ * 16][LDK];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int c16 = lane & 15, g = lane >> 4;
-  const int64_t total = (int64_t)a.rblocks * a.cgroups * a.S;
-  const int64_t t = xcd_tile(blockIdx.x, total);
   const int64_t bx = t % a.rblocks;
   const int by = (int)((t / a.rblocks) % a.cgroups);
   const int bz = (int)(t / ((int64_t)a.rblocks * a.cgroups));
@@ -550,12 +567,12 @@ static inline void mark(const SketchArgs &s, int idx) {
 }
 
 template <int OP, typename TIN, int TERMS, int NMT>
-static void launch_w(const WArgs &w, int64_t blocks, hipStream_t st) {
-  hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS>), dim3((unsigned)blocks), dim3(256), 0, st, w);
+static void launch_w(const WArgs &w, int64_t blocks, hipStream_t st, GroupRef g = GroupRef{}) {
+  hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS>), dim3((unsigned)blocks), dim3(256), 0, st, w, g);
 }
 template <int OP, typename TIN, int TERMS, int NJ>
-static void launch_y(const YArgs &y, int64_t blocks, hipStream_t st) {
-  hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS>), dim3((unsigned)blocks), dim3(256), 0, st, y);
+static void launch_y(const YArgs &y, int64_t blocks, hipStream_t st, GroupRef g = GroupRef{}) {
+  hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS>), dim3((unsigned)blocks), dim3(256), 0, st, y, g);
 }
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
@@ -654,6 +671,126 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     mark(s, 7);
   }
   return e;
+}
+
+// ---------------------------------------------------------------------------
+// Batches: one tile choice for all problems, the test matrices staged once
+// (all n columns of Omega), and the Y and W products of every problem in one
+// grouped launch each (no split K: each problem's tiles write its own Y and
+// W directly).
+void batch_tiles(const int *l, const int *k, int count, int op_bf16, int *nmt, int *nj) {
+  static const int cb[3] = {4, 7, 13}, cf[2] = {4, 7}, cy[2] = {4, 7};
+  const int *cw = op_bf16 ? cb : cf;
+  const int ncw = op_bf16 ? 3 : 2;
+  int64_t best = -1;
+  for (int i = 0; i < ncw; ++i) {
+    int64_t pad = 0;
+    for (int p = 0; p < count; ++p) {
+      const int t = (l[p] + 15) / 16;
+      pad += (t + cw[i] - 1) / cw[i] * cw[i];
+    }
+    if (best < 0 || pad < best || (pad == best && cw[i] > *nmt)) { best = pad; *nmt = cw[i]; }
+  }
+  best = -1;
+  for (int i = 0; i < 2; ++i) {
+    int64_t pad = 0;
+    for (int p = 0; p < count; ++p) {
+      const int t = (k[p] + 15) / 16;
+      pad += (t + cy[i] - 1) / cy[i] * cy[i];
+    }
+    if (best < 0 || pad < best || (pad == best && cy[i] > *nj)) { best = pad; *nj = cy[i]; }
+  }
+}
+
+void stage_geometry_tiles(int64_t m, int l, int k, int64_t maxcols, int nmt, int nj, int *LP,
+                          int64_t *MP, int *KP, int64_t *NP) {
+  *LP = (int)rup(l, 16 * nmt);
+  *MP = rup(m, 32);
+  *KP = (int)rup(k, 16 * nj);
+  *NP = rup(maxcols, 32);
+}
+
+hipError_t stage_test_matrices(const SketchArgs &s, const MfmaStage &g) {
+  if (s.mode == MODE_BF16) {
+    hipError_t e = gen_stage<MODE_BF16, uint16_t>(s.stream, (uint16_t *)g.omega, s.k, g.KP, 0, s.ncols,
+                                                  g.NP, STREAM_OMEGA, s.rad, s.k0, s.k1);
+    if (e != hipSuccess) return e;
+    return gen_stage<MODE_BF16, uint16_t>(s.stream, (uint16_t *)g.psi, s.l, g.LP, 0, s.m, g.MP,
+                                          STREAM_PSI, s.rad, s.k0, s.k1);
+  }
+  if (s.mode == MODE_F32) {
+    hipError_t e = gen_stage<MODE_F32, float>(s.stream, (float *)g.omega, s.k, g.KP, 0, s.ncols, g.NP,
+                                              STREAM_OMEGA, s.rad, s.k0, s.k1);
+    if (e != hipSuccess) return e;
+    return gen_stage<MODE_F32, float>(s.stream, (float *)g.psi, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI,
+                                      s.rad, s.k0, s.k1);
+  }
+  return hipErrorNotSupported;
+}
+
+template <int OP, typename TIN, int TERMS>
+static hipError_t launch_batch_t(const SketchArgs *s, const MfmaStage *g, int count, int nmt, int nj,
+                                 ArgArena &ar) {
+  std::vector<YArgs> ys(count);
+  std::vector<WArgs> ws(count);
+  std::vector<int64_t> py(count + 1, 0), pw(count + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    const SketchArgs &q = s[i];
+    bool vec = (q.lda % (16 / (int64_t)sizeof(TIN))) == 0;
+    for (int p = q.pure ? 1 : 0; p < 4; ++p) vec = vec && aligned16(q.planes[p]);
+    YArgs &y = ys[i];
+    for (int p = 0; p < 4; ++p) y.a[p] = q.planes[p];
+    y.lda = q.lda; y.m = q.m; y.ncols = q.ncols;
+    y.om = g[i].omega; y.KP = g[i].KP; y.NP = g[i].NP;
+    y.k = q.k; y.pure = q.pure;
+    y.y = (float *)q.y; y.ldy = q.ldy; y.psy = q.psy; y.pss = 0;
+    y.rblocks = (int)((q.m + 63) / 64);
+    y.cgroups = g[i].KP / (16 * nj);
+    y.S = 1; y.tchunk = rup(q.ncols, 32);
+    py[i + 1] = py[i] + (int64_t)y.rblocks * y.cgroups;
+    WArgs &w = ws[i];
+    for (int p = 0; p < 4; ++p) w.a[p] = q.planes[p];
+    w.lda = q.lda; w.m = q.m; w.ncols = q.ncols; w.col0 = 0;
+    w.psi = g[i].psi; w.LP = g[i].LP; w.MP = g[i].MP;
+    w.l = q.l; w.pure = q.pure; w.vec = vec ? 1 : 0;
+    w.w = (float *)q.w; w.ldw = q.ldw; w.psw = q.psw;
+    w.rgroups = g[i].LP / (16 * nmt);
+    w.ctiles = (int)((q.ncols + 63) / 64);
+    w.S = 1; w.kchunk = rup(q.m, 32); w.part = nullptr;
+    pw[i + 1] = pw[i] + (int64_t)w.ctiles * w.rgroups;
+  }
+  hipStream_t st = s[0].stream;
+  GroupRef gy{arena_push(ar, st, ys.data(), ys.size() * sizeof(YArgs)),
+              (const int64_t *)arena_push(ar, st, py.data(), py.size() * sizeof(int64_t)), count};
+  GroupRef gw{arena_push(ar, st, ws.data(), ws.size() * sizeof(WArgs)),
+              (const int64_t *)arena_push(ar, st, pw.data(), pw.size() * sizeof(int64_t)), count};
+  if (!gy.tab || !gy.prefix || !gw.tab || !gw.prefix) return hipErrorOutOfMemory;
+  if (nj == 7) launch_y<OP, TIN, TERMS, 7>(ys[0], py[count], st, gy);
+  else launch_y<OP, TIN, TERMS, 4>(ys[0], py[count], st, gy);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (nmt == 13) launch_w<OP, TIN, TERMS, (OP == OP_BF16 ? 13 : 7)>(ws[0], pw[count], st, gw);
+  else if (nmt == 7) launch_w<OP, TIN, TERMS, 7>(ws[0], pw[count], st, gw);
+  else launch_w<OP, TIN, TERMS, 4>(ws[0], pw[count], st, gw);
+  return hipGetLastError();
+}
+
+hipError_t launch_sketch_mfma_batch(const SketchArgs *s, const MfmaStage *g, int count, int nmt,
+                                    int nj, ArgArena &ar) {
+  if (count < 1) return hipSuccess;
+  const SketchArgs &a = s[0];
+  if (a.mode == MODE_BF16) {
+    if (a.in_dtype == DT_F32) {
+      if (a.terms == 1) return launch_batch_t<OP_BF16, float, 1>(s, g, count, nmt, nj, ar);
+      if (a.terms == 2) return launch_batch_t<OP_BF16, float, 2>(s, g, count, nmt, nj, ar);
+      return launch_batch_t<OP_BF16, float, 3>(s, g, count, nmt, nj, ar);
+    }
+    if (a.in_dtype == DT_BF16) return launch_batch_t<OP_BF16, uint16_t, 1>(s, g, count, nmt, nj, ar);
+  } else if (a.mode == MODE_F32) {
+    if (a.in_dtype == DT_F32) return launch_batch_t<OP_F32, float, 1>(s, g, count, nmt, nj, ar);
+    if (a.in_dtype == DT_BF16) return launch_batch_t<OP_F32, uint16_t, 1>(s, g, count, nmt, nj, ar);
+  }
+  return hipErrorNotSupported;
 }
 
 hipError_t launch_sketch_mfma(const SketchArgs &s, const MfmaStage &g) {

@@ -1,0 +1,105 @@
+"""The batched path (qsketch_batch_*): independent problems of different
+shapes, sketched and finalised together through grouped launches, give
+problem by problem the oracle's one-pass result on the same operands
+(Alg. 4; HX is unique, Lemma 4.2) and the result of a single-problem
+context.  One batch includes an exactly low-rank problem, which takes the
+rank-deficient branches (shifted CholeskyQR, skipped corrections, minimum-norm
+core solve) while its neighbours do not.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2404_14783_amd as qs
+import synth
+from oracle import onepass, quaternion as qt
+from oracle.sketch import SketchConfig, sketch_matrix
+from tests.gpu_helpers import input_values, rel, to_device, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [  # m, n, k, l, seed
+    (333, 257, 12, 25, 11),
+    (700, 300, 20, 41, 12),
+    (512, 640, 16, 33, 13),
+    (1200, 250, 40, 81, 14),
+    (257, 511, 8, 17, 15),
+]
+
+
+def inputs(shapes, dtype, exact_rank=None):
+    mats = []
+    for i, (m, n, k, l, seed) in enumerate(shapes):
+        if exact_rank is not None and i == 0:
+            sig, noise = torch.tensor([1.0, 0.5, 0.3, 0.2][:exact_rank]), 0.0
+        else:
+            sig, noise = torch.tensor(0.8 ** np.arange(max(2, k // 2))), 1e-3
+        a = synth.lowrank_plus_noise(m, n, sig, noise, 300 + i).numpy()
+        mats.append(input_values(a, dtype))
+    return mats
+
+
+@pytest.mark.parametrize("sketch,terms", [("bf16", 2), ("f32", 1)])
+@pytest.mark.parametrize("kind", ["pseudo_qr", "pseudo_svd"])
+def test_batch_matches_oracle_and_single(sketch, terms, kind):
+    mats = inputs(SHAPES, "f32")
+    devs = [to_device(a, "f32") for a in mats]
+    b = qs.Batch(SHAPES, input_dtype="f32", sketch_dtype=sketch, split_terms=terms)
+    qb, xb, reps = b.run(devs, kind)
+    errs = b.rel_error(devs, qb, xb)
+    for i, (m, n, k, l, seed) in enumerate(SHAPES):
+        a = mats[i]
+        # oracle on the same operands (bf16 split / fp32 values, rounded test matrices)
+        cfg = SketchConfig(m, n, k, l, seed=seed, dtype=sketch, terms=terms)
+        ref = sketch_matrix(a, cfg)
+        h_o, x_o, info = onepass.qb_stage(ref, kind)
+        hx_o = qt.hamilton(h_o, x_o)
+        hx_b = qt.hamilton(to_numpy(qb[i]), to_numpy(xb[i]))
+        e_o = onepass.rel_error(a, h_o, x_o)
+        assert rel(hx_b, hx_o) < 1e-4, (i, rel(hx_b, hx_o))
+        assert abs(errs[i] - e_o) <= 1e-4 * e_o, (i, errs[i], e_o)
+        # a single-problem context on the same data
+        sk = qs.Sketcher(m, n, k, l, seed=seed, input_dtype="f32", sketch_dtype=sketch,
+                         split_terms=terms, max_block_cols=n)
+        sk.update(0, devs[i])
+        q1, x1, rep1 = sk.finalize(kind)
+        hx_1 = qt.hamilton(to_numpy(q1), to_numpy(x1))
+        assert rel(hx_b, hx_1) < 1e-5, (i, rel(hx_b, hx_1))
+        np.testing.assert_allclose(reps[i]["kappa"], rep1["kappa"], rtol=1e-4)
+        if kind == "pseudo_qr":
+            assert reps[i]["kappa"] < 10 and len(reps[i]["eps"]) == 3
+        else:
+            assert reps[i]["orth_defect"] < 1e-10
+        sk.close()
+    b.close()
+
+
+@pytest.mark.parametrize("kind", ["pseudo_qr", "pseudo_svd"])
+def test_batch_with_exact_low_rank_problem(kind):
+    shapes = [(300, 240, 8, 17, 9)] + SHAPES[:3]
+    mats = inputs(shapes, "f32", exact_rank=4)
+    devs = [to_device(a, "f32") for a in mats]
+    b = qs.Batch(shapes, input_dtype="f32", sketch_dtype="f32")
+    qb, xb, reps = b.run(devs, kind)
+    errs = b.rel_error(devs, qb, xb)
+    assert errs[0] < 1e-5, errs[0]
+    for i in range(1, len(shapes)):
+        m, n, k, l, seed = shapes[i]
+        cfg = SketchConfig(m, n, k, l, seed=seed, dtype="f32")
+        h_o, x_o, _ = onepass.qb_stage(sketch_matrix(mats[i], cfg), kind)
+        e_o = onepass.rel_error(mats[i], h_o, x_o)
+        assert abs(errs[i] - e_o) <= 1e-4 * e_o, (i, errs[i], e_o)
+    b.close()
+
+
+def test_batch_rerun_is_repeatable():
+    """A second run on the same batch context (and its argument tables)
+    reproduces the first bit for bit."""
+    mats = inputs(SHAPES[:3], "f32")
+    devs = [to_device(a, "f32") for a in mats]
+    b = qs.Batch(SHAPES[:3], input_dtype="f32", sketch_dtype="bf16", split_terms=2)
+    q1, x1, _ = b.run(devs, "pseudo_svd")
+    q2, x2, _ = b.run(devs, "pseudo_svd")
+    for i in range(3):
+        assert torch.equal(q1[i], q2[i]) and torch.equal(x1[i], x2[i])
+    b.close()
