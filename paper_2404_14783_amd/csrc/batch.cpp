@@ -668,6 +668,9 @@ qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const
       x.l = q.l; x.m = q.m;
       for (int p = 0; p < 4; ++p) x.h[p] = Q[4 * id + p];
       x.ldh = ldq[id]; x.k = q.k; x.chunk = chunk; x.partial = q.partials;
+      // Psi exactly as staged for the sketch
+      x.psi_st = q.stage.psi; x.psi_st_type = b->mode == qsk::MODE_BF16 ? 1 : 2;
+      x.psi_ld = q.stage.MP; x.psi_ps = (int64_t)q.stage.LP * q.stage.MP;
       x.gx = (q.l + 15) / 16; x.gy = (int)nch;
       nb[i] = (int64_t)x.gx * x.gy;
       rr[i].partial = q.partials; rr[i].nchunks = (int)nch; rr[i].r = q.l; rr[i].c = q.k;

@@ -10,7 +10,7 @@
 
 namespace qsk {
 
-template <typename T> __device__ __forceinline__ double ldv(const T *p, int64_t i) { return (double)p[i]; }
+template <typename T> __device__ __forceinline__ double ldv(const T *p, int64_t i) { return (double)gp(p)[i]; }
 
 template <typename T>
 __device__ __forceinline__ qd load_q(const PlanesC<T> &z, int64_t idx) {
@@ -82,9 +82,9 @@ __global__ __launch_bounds__(256) void crossprod_k(CrossArgs args, GroupRef grp)
   if (ga < k1 && gb < k2) {
     if (planar) {
       const int64_t o = ga + (int64_t)gb * ldo;
-      outp.p[0][o] = acc.w; outp.p[1][o] = acc.x; outp.p[2][o] = acc.y; outp.p[3][o] = acc.z;
+      gpw(outp.p[0])[o] = acc.w; gpw(outp.p[1])[o] = acc.x; gpw(outp.p[2])[o] = acc.y; gpw(outp.p[3])[o] = acc.z;
     } else {
-      double *q = partial + 4 * (((int64_t)bz * k2 + gb) * k1 + ga);
+      QSK_GLOBAL double *q = gpw(partial) + 4 * (((int64_t)bz * k2 + gb) * k1 + ga);
       q[0] = acc.w; q[1] = acc.x; q[2] = acc.y; q[3] = acc.z;
     }
   }
@@ -101,8 +101,8 @@ __global__ void reduce_chunks_k(ReduceArgs args, GroupRef grp) {
   const int64_t e = (int64_t)bx * blockDim.x + threadIdx.x;
   if (e >= elems) return;
   double s = 0.0;
-  for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * elems + e];
-  out[e] = s;
+  for (int c = 0; c < nchunks; ++c) s += gp(partial)[(int64_t)c * elems + e];
+  gpw(out)[e] = s;
 }
 
 // AoS (r x c, ld = r) partial sums -> planar output.
@@ -121,8 +121,8 @@ __global__ void reduce_chunks_planar_k(ReducePlanarArgs args, GroupRef grp) {
   const int i = (int)(e % r), j = (int)(e / r);
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   for (int ch = 0; ch < nchunks; ++ch)
-    for (int p = 0; p < 4; ++p) s[p] += partial[((int64_t)ch * n + e) * 4 + p];
-  for (int p = 0; p < 4; ++p) out.p[p][i + (int64_t)j * ldo] = s[p];
+    for (int p = 0; p < 4; ++p) s[p] += gp(partial)[((int64_t)ch * n + e) * 4 + p];
+  for (int p = 0; p < 4; ++p) gpw(out.p[p])[i + (int64_t)j * ldo] = s[p];
 }
 
 template <typename T> static PlanesC<T> mkc(const void *const z[4]) {
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void apply_k(ApplyArgs args, GroupRef grp) {
       const int aa = e >> 4, bb = e & 15;
       const int ga = a0 + aa, gb = b0 + bb;
       if (ga < k && gb < kc) {
-        const double *q = c + 4 * ((int64_t)ga + (int64_t)gb * k);
+        const QSK_GLOBAL double *q = gp(c) + 4 * ((int64_t)ga + (int64_t)gb * k);
         sc[aa][bb] = {q[0], q[1], q[2], q[3]};
       } else {
         sc[aa][bb] = qzero();
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void apply_k(ApplyArgs args, GroupRef grp) {
       const int gb = b0 + b;
       if (gb < kc) {
         const int64_t o = i + (int64_t)gb * ldo;
-        out.p[0][o] = acc[b].w; out.p[1][o] = acc[b].x; out.p[2][o] = acc[b].y; out.p[3][o] = acc[b].z;
+        gpw(out.p[0])[o] = acc[b].w; gpw(out.p[1])[o] = acc[b].x; gpw(out.p[2])[o] = acc[b].y; gpw(out.p[3])[o] = acc[b].z;
       }
     }
   }
@@ -322,8 +322,19 @@ __global__ __launch_bounds__(256) void psi_apply_k(PsiApplyArgs args, GroupRef g
       const int ii = e & 31, q = e >> 5;
       const int64_t gi = i0 + ii;
       double v[4] = {0.0, 0.0, 0.0, 0.0};
-      if (gi < ie && r0 + q < l)
-        embed_entry_as_used(mode, rad, (uint32_t)gi, (uint32_t)(r0 + q), STREAM_PSI, k0, k1, v);
+      if (gi < ie && r0 + q < l) {
+        if (A.psi_st_type == 1) {          // bf16 staging of the sketch
+          const QSK_GLOBAL uint16_t *ps = gp((const uint16_t *)A.psi_st) + (int64_t)(r0 + q) * A.psi_ld + gi;
+#pragma unroll
+          for (int p = 0; p < 4; ++p) v[p] = (double)__uint_as_float(((uint32_t)ps[p * A.psi_ps]) << 16);
+        } else if (A.psi_st_type == 2) {   // fp32 staging
+          const QSK_GLOBAL float *ps = gp((const float *)A.psi_st) + (int64_t)(r0 + q) * A.psi_ld + gi;
+#pragma unroll
+          for (int p = 0; p < 4; ++p) v[p] = (double)ps[p * A.psi_ps];
+        } else {
+          embed_entry_as_used(mode, rad, (uint32_t)gi, (uint32_t)(r0 + q), STREAM_PSI, k0, k1, v);
+        }
+      }
       sp[q][ii] = {v[0], v[1], v[2], v[3]};
     }
 #pragma unroll
@@ -349,7 +360,7 @@ __global__ __launch_bounds__(256) void psi_apply_k(PsiApplyArgs args, GroupRef g
     for (int bt = 0; bt < 16; ++bt) {
       const int gb = bt * 16 + bb;
       if (bt < nbt && gb < k) {
-        double *q = partial + 4 * (((int64_t)by * k + gb) * l + gr);
+        QSK_GLOBAL double *q = gpw(partial) + 4 * (((int64_t)by * k + gb) * l + gr);
         q[0] = acc[bt].w; q[1] = acc[bt].x; q[2] = acc[bt].y; q[3] = acc[bt].z;
       }
     }
@@ -376,13 +387,15 @@ hipError_t launch_psi_apply_k(hipStream_t st, const PsiApplyArgs &a, GroupRef g,
 hipError_t launch_psi_apply(hipStream_t st, int mode, int rad, uint32_t k0, uint32_t k1, int l,
                             int64_t m, const double *const h[4], int64_t ldh, int k,
                             double *partials, int64_t partial_elems, double *const p[4],
-                            int64_t ldp) {
+                            int64_t ldp, const void *psi_st, int psi_st_type, int64_t psi_ld,
+                            int64_t psi_ps) {
   int64_t chunk, nch;
   if (!plan_psi_apply(l, m, k, partial_elems, &chunk, &nch)) return hipErrorInvalidValue;
   PsiApplyArgs a{};
   a.mode = mode; a.rad = rad; a.k0 = k0; a.k1 = k1; a.l = l; a.m = m;
   set_planes(a.h, h);
   a.ldh = ldh; a.k = k; a.chunk = chunk; a.partial = partials;
+  a.psi_st = psi_st; a.psi_st_type = psi_st_type; a.psi_ld = psi_ld; a.psi_ps = psi_ps;
   a.gx = (l + 15) / 16; a.gy = (int)nch;
   hipError_t e = launch_psi_apply_k(st, a, GroupRef{}, 0);
   if (e != hipSuccess) return e;
@@ -420,10 +433,10 @@ hipError_t launch_widen(hipStream_t st, int tsrc, const void *src, int64_t lds, 
 // ---------------------------------------------------------------------------
 // Error pass: 64 x 64 tiles of H X, accumulated against A in FP64.
 template <typename T> __device__ __forceinline__ double lda_val(const T *p, int64_t i);
-template <> __device__ __forceinline__ double lda_val<double>(const double *p, int64_t i) { return p[i]; }
-template <> __device__ __forceinline__ double lda_val<float>(const float *p, int64_t i) { return p[i]; }
+template <> __device__ __forceinline__ double lda_val<double>(const double *p, int64_t i) { return gp(p)[i]; }
+template <> __device__ __forceinline__ double lda_val<float>(const float *p, int64_t i) { return gp(p)[i]; }
 template <> __device__ __forceinline__ double lda_val<uint16_t>(const uint16_t *p, int64_t i) {
-  return (double)__uint_as_float(((uint32_t)p[i]) << 16);
+  return (double)__uint_as_float(((uint32_t)gp(p)[i]) << 16);
 }
 
 template <typename TIN>
@@ -522,11 +535,11 @@ hipError_t launch_error(hipStream_t st, int tin, const void *const a[4], int64_t
 // __syncthreads() makes a block's global writes visible to the block).
 
 __device__ __forceinline__ qd gq(const double *a, int i, int j, int ld) {
-  const double *p = a + 4 * ((int64_t)i + (int64_t)j * ld);
+  const QSK_GLOBAL double *p = gp(a) + 4 * ((int64_t)i + (int64_t)j * ld);
   return {p[0], p[1], p[2], p[3]};
 }
 __device__ __forceinline__ void sq_(double *a, int i, int j, int ld, qd v) {
-  double *p = a + 4 * ((int64_t)i + (int64_t)j * ld);
+  QSK_GLOBAL double *p = gpw(a) + 4 * ((int64_t)i + (int64_t)j * ld);
   p[0] = v.w; p[1] = v.x; p[2] = v.y; p[3] = v.z;
 }
 
@@ -563,8 +576,12 @@ __device__ void sm_gemm(int k, const double *a, int opa, const double *b, int op
 // diagonal.  k <= 256.
 __device__ void sm_chol(const double *g, double *r, int k, int complex_only, double shift,
                         double tol, int *fail, double *minp, double *trace) {
+  // Panels of CB pivot rows live in LDS twice: `panel` holds the rows as
+  // updated so far (read by the elimination), `done` the finished, scaled
+  // rows (read by the trailing update), so each pivot costs one barrier.
   constexpr int CB = 8;
   __shared__ qd panel[CB][257];
+  __shared__ qd done[CB][257];
   __shared__ double s_maxd;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < k * k; e += nt) {
@@ -595,28 +612,30 @@ __device__ void sm_chol(const double *g, double *r, int k, int complex_only, dou
     }
     __syncthreads();
     for (int rr = 0; rr < jb; ++rr) {
+      // every thread reads the pivot; a pivot below tol * max diagonal marks
+      // failure (the factor is then discarded by the caller)
+      const double d = panel[rr][rr].w;
+      const double rel = s_maxd > 0.0 ? d / s_maxd : 0.0;
       if (tid == 0) {
-        const double d = panel[rr][rr].w;
-        const double rel = s_maxd > 0.0 ? d / s_maxd : 0.0;
         if (rel < *minp) *minp = rel;
         if (!(rel > tol)) *fail = 1;
-        panel[rr][rr] = {sqrt(fmax(d, 0.0)), 0.0, 0.0, 0.0};
       }
-      __syncthreads();
-      if (*fail) return;
-      const double inv = 1.0 / panel[rr][rr].w;
-      for (int cc = rr + 1 + tid; cc < w; cc += nt) panel[rr][cc] = qscale(panel[rr][cc], inv);
-      __syncthreads();
+      const double sd = sqrt(fmax(d, 0.0));
+      const double inv_d = d > 0.0 ? 1.0 / d : 0.0, inv_s = sd > 0.0 ? 1.0 / sd : 0.0;
       const int rows = jb - rr - 1;
       for (int e = tid; e < rows * w; e += nt) {
         const int r2 = rr + 1 + e / w, cc = e % w;
-        if (cc >= r2) panel[r2][cc] = qsub(panel[r2][cc], qmul(qconj(panel[rr][r2]), panel[rr][cc]));
+        if (cc >= r2)
+          panel[r2][cc] = qsub(panel[r2][cc], qscale(qmul(qconj(panel[rr][r2]), panel[rr][cc]), inv_d));
       }
+      for (int cc = tid; cc < w; cc += nt)
+        done[rr][cc] = cc < rr ? qzero() : (cc == rr ? qd{sd, 0.0, 0.0, 0.0} : qscale(panel[rr][cc], inv_s));
       __syncthreads();
     }
+    if (*fail) return;
     for (int e = tid; e < jb * w; e += nt) {
       const int rr = e / w, cc = e % w;
-      if (cc >= rr) sq_(r, j0 + rr, j0 + cc, k, panel[rr][cc]);
+      if (cc >= rr) sq_(r, j0 + rr, j0 + cc, k, done[rr][cc]);
     }
     const int nr = k - j0 - jb;
     for (int e = tid; e < nr * nr; e += nt) {
@@ -625,7 +644,7 @@ __device__ void sm_chol(const double *g, double *r, int k, int complex_only, dou
         const int ga = j0 + jb + aa, gc = j0 + jb + cc;
         qd v = gq(r, ga, gc, k);
         for (int rr = 0; rr < jb; ++rr)
-          v = qsub(v, qmul(qconj(panel[rr][ga - j0]), panel[rr][gc - j0]));
+          v = qsub(v, qmul(qconj(done[rr][ga - j0]), done[rr][gc - j0]));
         sq_(r, ga, gc, k, v);
       }
     }
@@ -760,8 +779,10 @@ __global__ __launch_bounds__(1024) void chol_kernel(CholArgs args, GroupRef grp)
   }
 }
 
-// T = R^{-1}, one workgroup per column c: T[a, c] = -(1/R[a,a]) sum_{b>a} R[a,b] T[b,c]
-// bottom-up, the column held in LDS.  Skipped when the Cholesky failed.
+// T = R^{-1}, one workgroup per column c, by a column sweep of R T = I:
+// for b = c, c-1, ..., 0: T[b, c] = (delta_bc - s_b) / R[b, b], then
+// s_a += R[a, b] T[b, c] for a < b (no reductions, one barrier per b).
+// Skipped when the Cholesky failed.
 __global__ __launch_bounds__(256) void triinv_kernel(CholArgs args, GroupRef grp) {
   CholArgs A;
   int bx, by, bz;
@@ -770,25 +791,18 @@ __global__ __launch_bounds__(256) void triinv_kernel(CholArgs args, GroupRef grp
   double *t = A.t;
   const int k = A.k;
   const SmallStatus *status = A.status;
+  __shared__ qd acc[256];
   __shared__ qd col[256];
-  __shared__ qd red[4];
   if (status && status->fail) return;
   if (bx >= k) return;
-  const int c = bx, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int a = tid; a < k; a += 256) col[a] = qzero();
+  const int c = bx, tid = threadIdx.x;
+  for (int a = tid; a < k; a += 256) { acc[a] = qzero(); col[a] = qzero(); }
   __syncthreads();
-  if (tid == 0) col[c] = {1.0 / r[4 * (c + (int64_t)c * k)], 0.0, 0.0, 0.0};
-  __syncthreads();
-  for (int a = c - 1; a >= 0; --a) {
-    qd s = qzero();
-    for (int b = a + 1 + tid; b <= c; b += 256) qfma(s, gq(r, a, b, k), col[b]);
-    s.w = wave_sum(s.w); s.x = wave_sum(s.x); s.y = wave_sum(s.y); s.z = wave_sum(s.z);
-    if (lane == 0) red[wave] = s;
-    __syncthreads();
-    if (tid == 0) {
-      const qd tot = qadd(qadd(red[0], red[1]), qadd(red[2], red[3]));
-      col[a] = qscale(tot, -1.0 / r[4 * (a + (int64_t)a * k)]);
-    }
+  for (int b = c; b >= 0; --b) {
+    qd tb = qsub(b == c ? qd{1.0, 0.0, 0.0, 0.0} : qzero(), acc[b]);
+    tb = qscale(tb, 1.0 / gp(r)[4 * (b + (int64_t)b * k)]);
+    if (tid == 0) col[b] = tb;
+    for (int a = tid; a < b; a += 256) qfma(acc[a], gq(r, a, b, k), tb);
     __syncthreads();
   }
   for (int a = tid; a < k; a += 256) sq_(t, a, c, k, col[a]);
@@ -1387,8 +1401,10 @@ __device__ void sm_bisect_all(const double *d, const double *e, int k, double *l
 // equal or nearly equal eigenvalues still give independent vectors; x and the
 // five LU arrays are private global slices of length k.
 __device__ void inverse_iteration(const double *d, const double *e, int k, double lam, double tnorm,
-                                  uint32_t seq, double *x, double *dl, double *dd, double *du,
-                                  double *du2, double *pv) {
+                                  uint32_t seq, double *x_, double *dl_, double *dd_, double *du_,
+                                  double *du2_, double *pv_) {
+  QSK_GLOBAL double *x = gpw(x_), *dl = gpw(dl_), *dd = gpw(dd_), *du = gpw(du_), *du2 = gpw(du2_),
+                    *pv = gpw(pv_);
   const double tiny = 0x1p-52 * tnorm + 1e-300;
   for (int j = 0; j < k; ++j) {
     const u32x4 r = philox(seq, (uint32_t)j, 0x51u, 0u, 0x2545F491u, 0x9E3779B9u);
@@ -1440,13 +1456,14 @@ __device__ void inverse_iteration(const double *d, const double *e, int k, doubl
 // Classical Gram-Schmidt, twice, over the c vectors xs[0..c) (length k,
 // stride k; LDS or global), in order: each vector loses its components along
 // the earlier ones and is normalised.
-__device__ __forceinline__ void cgs2_block(double *xs, int k, int c, double *coef, double *s_nrm) {
+template <typename P>
+__device__ __forceinline__ void cgs2_block(P xs, int k, int c, double *coef, double *s_nrm) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   for (int i = 1; i < c; ++i) {
-    double *xi = xs + (int64_t)i * k;
+    P xi = xs + (int64_t)i * k;
     for (int pass = 0; pass < 2; ++pass) {
       for (int j = wave; j < i; j += nw) {
-        const double *xj = xs + (int64_t)j * k;
+        P xj = xs + (int64_t)j * k;
         double s = 0.0;
         for (int r = lane; r < k; r += 64) s += xj[r] * xi[r];
         s = wave_sum(s);
@@ -1510,17 +1527,16 @@ __device__ __forceinline__ void sm_heev(double *g, int k, double *lam, double *U
     while (c1 < k && lam[c1] - lam[c1 - 1] <= 1e-3 * s_tn) ++c1;
     const int c = c1 - c0;
     if (c > 1) {
-      double *xg = X + (int64_t)c0 * k;
-      const bool in_lds = (int64_t)c * k <= TRI_POOL;
-      double *xs = in_lds ? pool : xg;
-      if (in_lds) {
-        for (int q = tid; q < c * k; q += blockDim.x) pool[q] = xg[q];
+      QSK_GLOBAL double *xg = gpw(X) + (int64_t)c0 * k;
+      if ((int64_t)c * k <= TRI_POOL) {
+        QSK_LDS double *xs = (QSK_LDS double *)pool;
+        for (int q = tid; q < c * k; q += blockDim.x) xs[q] = xg[q];
         __syncthreads();
-      }
-      cgs2_block(xs, k, c, coef, &s_nrm);
-      if (in_lds) {
-        for (int q = tid; q < c * k; q += blockDim.x) xg[q] = pool[q];
+        cgs2_block(xs, k, c, coef, &s_nrm);
+        for (int q = tid; q < c * k; q += blockDim.x) xg[q] = xs[q];
         __syncthreads();
+      } else {
+        cgs2_block(xg, k, c, coef, &s_nrm);
       }
     }
     c0 = c1;
@@ -1544,7 +1560,7 @@ __device__ __forceinline__ void sm_heev(double *g, int k, double *lam, double *U
   __syncthreads();
   for (int q = tid; q < k * k; q += blockDim.x) {
     const int r = q % k, i = q / k;
-    sq_(U, r, i, k, qscale(coefq[r], X[(int64_t)i * k + r]));
+    sq_(U, r, i, k, qscale(coefq[r], gp(X)[(int64_t)i * k + r]));
   }
   __syncthreads();
   int G = 64;

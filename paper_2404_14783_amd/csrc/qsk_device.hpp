@@ -8,6 +8,16 @@
 
 #include "qsk_kernels.hpp"
 
+// Global-memory views of generic pointers: loads and stores through them are
+// global_* instructions (counted by vmcnt only), so waits for LDS results do
+// not also wait for global loads in flight, as they must for flat_* ones.
+#define QSK_GLOBAL __attribute__((address_space(1)))
+#define QSK_LDS __attribute__((address_space(3)))
+template <typename T>
+__device__ __forceinline__ const QSK_GLOBAL T *gp(const T *p) { return (const QSK_GLOBAL T *)p; }
+template <typename T>
+__device__ __forceinline__ QSK_GLOBAL T *gpw(T *p) { return (QSK_GLOBAL T *)p; }
+
 namespace qsk {
 
 enum : int { STREAM_OMEGA = 0, STREAM_PSI = 1, STREAM_POWER = 2, STREAM_DIAGF = 3 };

@@ -100,7 +100,8 @@ hipError_t launch_apply(hipStream_t st, int tz, const void *const z[4], int64_t 
 hipError_t launch_psi_apply(hipStream_t st, int mode, int rad, uint32_t k0, uint32_t k1, int l,
                             int64_t m, const double *const h[4], int64_t ldh, int k,
                             double *partials, int64_t partial_elems, double *const p[4],
-                            int64_t ldp);
+                            int64_t ldp, const void *psi_st = nullptr, int psi_st_type = 0,
+                            int64_t psi_ld = 0, int64_t psi_ps = 0);
 // Convert sketch planes (float or double) to FP64 planes.
 hipError_t launch_widen(hipStream_t st, int tsrc, const void *src, int64_t lds, int64_t pss,
                         int64_t rows, int64_t cols, double *const dst[4], int64_t ldd);
@@ -170,6 +171,11 @@ struct PsiApplyArgs {       // partial sums of Psi H
   int k;
   int64_t chunk;
   double *partial;
+  // optional: Psi as the sketch staged it (0 none: regenerate; 1 bf16;
+  // 2 fp32), element (row o, column t) of plane p at o * psi_ld + t + p * psi_ps
+  const void *psi_st;
+  int psi_st_type;
+  int64_t psi_ld, psi_ps;
   int gx, gy;
 };
 struct ErrorArgs {

@@ -65,6 +65,7 @@ struct qsk_ctx {
   double t_ms[4] = {0, 0, 0, 0};
   int64_t t_count[4] = {0, 0, 0, 0};
   int use_mfma = 1;
+  bool psi_staged = false;             // stage.psi holds Psi as the sketch used it
 };
 
 namespace {
@@ -352,7 +353,10 @@ qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void 
     ctx->ev_used += 8;
   }
   hipError_t e = hipErrorNotSupported;
-  if (ctx->use_mfma && ctx->mode != qsk::MODE_F64) e = qsk::launch_sketch_mfma(s, ctx->stage);
+  if (ctx->use_mfma && ctx->mode != qsk::MODE_F64) {
+    e = qsk::launch_sketch_mfma(s, ctx->stage);
+    if (e == hipSuccess) ctx->psi_staged = true;
+  }
   if (e == hipErrorNotSupported) e = qsk::launch_sketch_generic(s);
   if (e != hipSuccess) return hip_fail(ctx, e, "sketch update");
   ctx->columns_seen += ncols;
@@ -509,8 +513,13 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
     p1[p] = ctx->p1buf + (size_t)p * l * k;
     sp[p] = ctx->sbuf + (size_t)p * l * k;
   }
+  // Psi as the sketch used it: the matrix-core path's staging holds exactly
+  // those values (rounded to the operand format); otherwise regenerate
+  const int psi_st_type = !ctx->psi_staged ? 0 : (ctx->mode == qsk::MODE_BF16 ? 1 : 2);
   HIPCHK(ctx, qsk::launch_psi_apply(st, ctx->mode, c.embedding == QSK_RADEMACHER, ctx->k0, ctx->k1, l,
-                                    m, Q, ldq, k, ctx->partials, ctx->partial_elems, pp, l));
+                                    m, Q, ldq, k, ctx->partials, ctx->partial_elems, pp, l,
+                                    ctx->stage.psi, psi_st_type, ctx->stage.MP,
+                                    (int64_t)ctx->stage.LP * ctx->stage.MP));
   SmallStatus hs2{};
   HIPCHK(ctx, hipMemcpyAsync(&hs2, ctx->status, sizeof(hs2), hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipStreamSynchronize(st));

@@ -92,7 +92,10 @@ __device__ __forceinline__ floatx4 mma(const FragF &a, const FragF &b, floatx4 c
   return c;
 }
 
-// Split 8 fp32 data values into TERMS bf16 fragments (hi, mid, lo).
+// Split 8 fp32 data values into TERMS bf16 fragments (hi, mid, lo): each
+// term is the round-to-nearest-even bf16 value of what the previous terms
+// left (the hardware conversion v_cvt_pk_bf16_f32 rounds to nearest even).
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2_t;
 template <int TERMS>
 __device__ __forceinline__ void split_terms(const float (&x)[8], FragB (&out)[3]) {
   float r[8];
@@ -103,19 +106,23 @@ __device__ __forceinline__ void split_terms(const float (&x)[8], FragB (&out)[3]
     if (tm < TERMS) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float a0 = bf16_rne(r[2 * i]), a1 = bf16_rne(r[2 * i + 1]);
-        out[tm].v[i] = (__float_as_uint(a0) >> 16) | (__float_as_uint(a1) & 0xFFFF0000u);
-        r[2 * i] -= a0;
-        r[2 * i + 1] -= a1;
+        const bf16x2_t h = {(__bf16)r[2 * i], (__bf16)r[2 * i + 1]};
+        uint32_t u;
+        __builtin_memcpy(&u, &h, 4);
+        out[tm].v[i] = u;
+        if (tm + 1 < TERMS) {
+          r[2 * i] -= __uint_as_float(u << 16);
+          r[2 * i + 1] -= __uint_as_float(u & 0xFFFF0000u);
+        }
       }
     }
   }
 }
 
 template <typename TIN> __device__ __forceinline__ float ldin(const TIN *p, int64_t i);
-template <> __device__ __forceinline__ float ldin<float>(const float *p, int64_t i) { return p[i]; }
+template <> __device__ __forceinline__ float ldin<float>(const float *p, int64_t i) { return gp(p)[i]; }
 template <> __device__ __forceinline__ float ldin<uint16_t>(const uint16_t *p, int64_t i) {
-  return __uint_as_float(((uint32_t)p[i]) << 16);
+  return __uint_as_float(((uint32_t)gp(p)[i]) << 16);
 }
 
 // Signed plane selection of R(Omega) (Y) and S(Psi) (W): index into
@@ -148,19 +155,20 @@ template <>
 __device__ __forceinline__ void load8<float>(const float *p, int64_t idx, int64_t navail, bool vec,
                                              float (&x)[8]) {
   if (vec && navail >= 8) {
-    const float4 u0 = *(const float4 *)(p + idx), u1 = *(const float4 *)(p + idx + 4);
+    const QSK_GLOBAL floatx4 *v = (const QSK_GLOBAL floatx4 *)(p + idx);
+    const floatx4 u0 = v[0], u1 = v[1];
     x[0] = u0.x; x[1] = u0.y; x[2] = u0.z; x[3] = u0.w;
     x[4] = u1.x; x[5] = u1.y; x[6] = u1.z; x[7] = u1.w;
   } else {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) x[s] = s < navail ? p[idx + s] : 0.f;
+    for (int s = 0; s < 8; ++s) x[s] = s < navail ? gp(p)[idx + s] : 0.f;
   }
 }
 template <>
 __device__ __forceinline__ void load8<uint16_t>(const uint16_t *p, int64_t idx, int64_t navail,
                                                 bool vec, float (&x)[8]) {
   if (vec && navail >= 8) {
-    const uint4 u = *(const uint4 *)(p + idx);
+    const u32v4 u = *(const QSK_GLOBAL u32v4 *)(p + idx);
     const uint32_t w[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -169,9 +177,22 @@ __device__ __forceinline__ void load8<uint16_t>(const uint16_t *p, int64_t idx, 
     }
   } else {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) x[s] = s < navail ? __uint_as_float(((uint32_t)p[idx + s]) << 16) : 0.f;
+    for (int s = 0; s < 8; ++s) x[s] = s < navail ? __uint_as_float(((uint32_t)gp(p)[idx + s]) << 16) : 0.f;
   }
 }
+
+// One input element at a byte address (global).
+template <typename TIN> __device__ __forceinline__ float ld_elem(const QSK_GLOBAL char *p);
+template <> __device__ __forceinline__ float ld_elem<float>(const QSK_GLOBAL char *p) {
+  return *(const QSK_GLOBAL float *)p;
+}
+template <> __device__ __forceinline__ float ld_elem<uint16_t>(const QSK_GLOBAL char *p) {
+  return __uint_as_float(((uint32_t)*(const QSK_GLOBAL uint16_t *)p) << 16);
+}
+
+// The negated copies of planes x, y, z of a test-matrix fragment set.
+__device__ __forceinline__ void neg3(FragB (&f)[7]) { f[4] = negB(f[1]); f[5] = negB(f[2]); f[6] = negB(f[3]); }
+__device__ __forceinline__ void neg3(FragF (&f)[7]) { f[4] = negF(f[1]); f[5] = negF(f[2]); f[6] = negF(f[3]); }
 
 template <typename Frag, typename OPT>
 __device__ __forceinline__ void lds_frag(const OPT *src, Frag &f);
@@ -217,7 +238,7 @@ struct WArgs {
   float *part;                // [S][4][ncols][LP]
 };
 
-template <int OP, typename TIN, int NMT, int TERMS>
+template <int OP, typename TIN, int NMT, int TERMS, bool PURE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void w_mfma_kernel(WArgs a0, GroupRef grp) {
   WArgs a;
   int64_t t;
@@ -237,7 +258,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   constexpr int NV = 4 * NMT * 16 * VPR;                   // vectors per Psi tile
   constexpr int VPT = NV / 256;
   static_assert(NV % 256 == 0, "Psi tile must split evenly over the block");
-  __shared__ OPT s_psi[4][NMT * 16][LDK];
+  __shared__ OPT s_psi[2][4][NMT * 16][LDK];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int bx = (int)(t % a.ctiles);
@@ -266,7 +287,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const int64_t i_ = (I0) + 8 * g;                                                            \
     const int64_t nav_ = jok ? min((int64_t)8, ie - i_) : 0;                                    \
     _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                             \
-      if (q == 0 && a.pure) {                                                                   \
+      if (q == 0 && PURE) {                                                                   \
         _Pragma("unroll") for (int s = 0; s < 8; ++s) xa[q][s] = 0.f;                           \
       } else {                                                                                  \
         load8<TIN>(ap[q], i_ + j * a.lda, nav_, vec, xa[q]);                                    \
@@ -275,40 +296,57 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     _Pragma("unroll") for (int u = 0; u < VPT; ++u) {                                           \
       const int e = tid + u * 256;                                                              \
       const int v = e % VPR, rr = (e / VPR) % (NMT * 16), pl = e / (VPR * NMT * 16);            \
-      pr[u] = *(const u32v4 *)(psi + pl * pps + (int64_t)(rbase + rr) * a.MP + (I0) + v * EPV);   \
+      pr[u] = *(const QSK_GLOBAL u32v4 *)(psi + pl * pps + (int64_t)(rbase + rr) * a.MP + (I0) + v * EPV);   \
+    }                                                                                           \
+  } while (0)
+
+#define QSK_W_STORE_PSI(BUF)                                                                    \
+  do {                                                                                          \
+    _Pragma("unroll") for (int u = 0; u < VPT; ++u) {                                           \
+      const int e = tid + u * 256;                                                              \
+      const int v = e % VPR, rr = (e / VPR) % (NMT * 16), pl = e / (VPR * NMT * 16);            \
+      *(u32v4 *)&s_psi[BUF][pl][rr][v * EPV] = pr[u];                                           \
     }                                                                                           \
   } while (0)
 
   QSK_W_FETCH(ib);
+  QSK_W_STORE_PSI(0);
+  __syncthreads();
+  int buf = 0;
   for (int64_t i0 = ib; i0 < ie; i0 += 32) {
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) {
-      const int e = tid + u * 256;
-      const int v = e % VPR, rr = (e / VPR) % (NMT * 16), pl = e / (VPR * NMT * 16);
-      *(u32v4 *)&s_psi[pl][rr][v * EPV] = pr[u];
-    }
     Frag af[4][3];
 #pragma unroll
     for (int q = 0; q < 4; ++q) to_frags<OP, TERMS>(xa[q], af[q]);
-    __syncthreads();
-    if (i0 + 32 < ie) QSK_W_FETCH(i0 + 32);
+    const bool more = i0 + 32 < ie;
+    if (more) QSK_W_FETCH(i0 + 32);
+    // Psi fragments of row tile rt + 1 are read from LDS while the matrix
+    // cores work on row tile rt
+    Frag pnext[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) lds_frag<Frag, OPT>(&s_psi[buf][s][c16][8 * g], pnext[s]);
 #pragma unroll
     for (int rt = 0; rt < NMT; ++rt) {
       Frag pf[7];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) lds_frag<Frag, OPT>(&s_psi[s][rt * 16 + c16][8 * g], pf[s]);
+      for (int s = 0; s < 4; ++s) pf[s] = pnext[s];
+      if (rt + 1 < NMT) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) lds_frag<Frag, OPT>(&s_psi[buf][s][(rt + 1) * 16 + c16][8 * g], pnext[s]);
+      }
       if constexpr (OP == OP_BF16) { pf[4] = negB(pf[1]); pf[5] = negB(pf[2]); pf[6] = negB(pf[3]); }
       else { pf[4] = negF(pf[1]); pf[5] = negF(pf[2]); pf[6] = negF(pf[3]); }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (q == 0 && a.pure) continue;
+        if (q == 0 && PURE) continue;
 #pragma unroll
         for (int tm = 0; tm < TERMS; ++tm)
 #pragma unroll
           for (int p = 0; p < 4; ++p) acc[rt][p] = mma(pf[ssel(p, q)], af[q][tm], acc[rt][p]);
       }
     }
+    if (more) QSK_W_STORE_PSI(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
   // epilogue: lane holds column j, rows rbase + rt*16 + 4g + (0..3)
   if (!jok) return;
@@ -318,13 +356,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       if (a.S == 1) {
-        float *dst = a.w + p * a.psw + (a.col0 + j) * a.ldw;
+        QSK_GLOBAL float *dst = gpw(a.w + p * a.psw + (a.col0 + j) * a.ldw);
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt)
           if (r0 + tt < a.l) dst[r0 + tt] += acc[rt][p][tt];
       } else {
         float *dst = a.part + (((int64_t)bz * 4 + p) * a.ncols + j) * a.LP + r0;
-        *(floatx4 *)dst = acc[rt][p];
+        *(QSK_GLOBAL floatx4 *)dst = acc[rt][p];
       }
     }
   }
@@ -340,8 +378,8 @@ __global__ void w_reduce_kernel(const float *part, int S, int LP, int64_t ncols,
     const int64_t j = jp % ncols;
     const int p = (int)(jp / ncols);
     float s = 0.f;
-    for (int z = 0; z < S; ++z) s += part[(((int64_t)z * 4 + p) * ncols + j) * LP + r];
-    w[p * psw + (col0 + j) * ldw + r] += s;
+    for (int z = 0; z < S; ++z) s += gp(part)[(((int64_t)z * 4 + p) * ncols + j) * LP + r];
+    gpw(w)[p * psw + (col0 + j) * ldw + r] += s;
   }
 }
 
@@ -350,10 +388,11 @@ __global__ void w_reduce_kernel(const float *part, int S, int LP, int64_t ncols,
 // one chunk of the update's columns (split K over S chunks; chunk s adds into
 // its own copy s of Y, and the copies are summed when the sketch is read).
 // Block = 4 waves; wave w owns rows 16 w .. 16 w + 15 of the tile, all NJ
-// column tiles and all four planes.  Per 32-column step the A tile is staged
-// in LDS in the operand format (transposed so that each lane reads 8
-// consecutive columns of A) and the Omega tile is copied to LDS; both are
-// fetched into registers one step ahead.
+// column tiles and all four planes.  No other wave needs a wave's rows of A,
+// so each lane loads its own operand values (row c16, columns 8 g .. 8 g + 7
+// of the step) straight from HBM; only the Omega tile, which all four waves
+// share, goes through LDS (two buffers, one barrier per step).  Both are
+// fetched one step ahead.
 struct YArgs {
   const void *a[4];
   int64_t lda, m, ncols;
@@ -366,7 +405,7 @@ struct YArgs {
   int64_t ldy, psy, pss;      // copy s of plane p: y + s * pss + p * psy
 };
 
-template <int OP, typename TIN, int NJ, int TERMS>
+template <int OP, typename TIN, int NJ, int TERMS, bool PURE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void y_mfma_kernel(YArgs a0, GroupRef grp) {
   YArgs a;
   int64_t t;
@@ -380,32 +419,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   }
   using OPT = typename std::conditional<OP == OP_BF16, uint16_t, float>::type;
   using Frag = typename std::conditional<OP == OP_BF16, FragB, FragF>::type;
-  constexpr int NT = TERMS;
-  constexpr int ROWS = 64;
   constexpr int LDK = 32 + (OP == OP_BF16 ? 8 : 4);
   constexpr int EPV = 16 / sizeof(OPT);
   constexpr int VPR = 32 / EPV;
   constexpr int NV = 4 * NJ * 16 * VPR;                     // vectors per Omega tile
   constexpr int VPT = NV / 256;
   static_assert(NV % 256 == 0, "Omega tile must split evenly over the block");
-  __shared__ OPT s_a[NT][4][ROWS][LDK];
-  __shared__ OPT s_om[4][NJ * 16][LDK];
+  __shared__ OPT s_om[2][4][NJ * 16][LDK];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int64_t bx = t % a.rblocks;
   const int by = (int)((t / a.rblocks) % a.cgroups);
   const int bz = (int)(t / ((int64_t)a.rblocks * a.cgroups));
-  const int64_t rb = bx * ROWS;
+  const int64_t rb = bx * 64;
   const int jt0 = by * NJ;
   const int64_t tb = (int64_t)bz * a.tchunk;
   const int64_t te = min(a.ncols, tb + a.tchunk);
   const OPT *om = (const OPT *)a.om;
   const int64_t ops = (int64_t)a.KP * a.NP;
-  const TIN *ap[4] = {(const TIN *)a.a[0], (const TIN *)a.a[1], (const TIN *)a.a[2], (const TIN *)a.a[3]};
-  // loader role: row lr of the tile, column group lg (8 columns)
-  const int lr = tid % ROWS, lg = tid / ROWS;                // lg in 0..3
-  const int64_t grow = rb + lr;
-  const bool rok = grow < a.m;
+  // plane bases (uniform) and this lane's byte offsets into them: the update
+  // block of every plane spans < 4 GiB (checked on the host), so a 32-bit
+  // offset from a scalar base addresses it
+  const QSK_GLOBAL char *ab[4] = {(const QSK_GLOBAL char *)a.a[0], (const QSK_GLOBAL char *)a.a[1],
+                                  (const QSK_GLOBAL char *)a.a[2], (const QSK_GLOBAL char *)a.a[3]};
+  const int64_t row = rb + wave * 16 + c16;                 // this lane's row of A
+  const bool rok = row < a.m;
+  const int64_t rowc = rok ? row : a.m - 1;
 
   floatx4 acc[NJ][4];
 #pragma unroll
@@ -413,68 +452,80 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
     for (int p = 0; p < 4; ++p) acc[u][p] = {0.f, 0.f, 0.f, 0.f};
 
-  float xa[4][8];
+  // A values of two steps in flight: X[q][s] = A_q[row, T + 8 g + s]
+  float xa0[4][8], xa1[4][8];
   u32v4 orr[VPT];
-#define QSK_Y_FETCH(T0)                                                                         \
+#define QSK_Y_FETCH_A(T0, X)                                                                    \
   do {                                                                                          \
-    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                             \
-      _Pragma("unroll") for (int s = 0; s < 8; ++s) {                                           \
-        const int64_t tt = (T0) + 8 * lg + s;                                                   \
-        xa[q][s] = (rok && tt < te && !(q == 0 && a.pure)) ? ldin<TIN>(ap[q], grow + tt * a.lda) : 0.f; \
+    /* out-of-range elements load a valid address and are zeroed (no branches) */              \
+    _Pragma("unroll") for (int s = 0; s < 8; ++s) {                                             \
+      const int64_t tt = (T0) + 8 * g + s;                                                      \
+      const bool ok_ = rok && tt < te;                                                          \
+      const uint32_t off_ = (uint32_t)((rowc + (ok_ ? tt : tb) * a.lda) * (int64_t)sizeof(TIN)); \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                           \
+        if (q == 0 && PURE) { X[q][s] = 0.f; continue; }                                        \
+        const float v_ = ld_elem<TIN>(ab[q] + off_);                                            \
+        X[q][s] = ok_ ? v_ : 0.f;                                                               \
       }                                                                                         \
     }                                                                                           \
+  } while (0)
+#define QSK_Y_FETCH_OM(T0)                                                                      \
+  do {                                                                                          \
     _Pragma("unroll") for (int u = 0; u < VPT; ++u) {                                           \
       const int e = tid + u * 256;                                                              \
       const int v = e % VPR, oo = (e / VPR) % (NJ * 16), pl = e / (VPR * NJ * 16);              \
-      orr[u] = *(const u32v4 *)(om + pl * ops + (int64_t)(jt0 * 16 + oo) * a.NP + (T0) + v * EPV); \
+      orr[u] = *(const QSK_GLOBAL u32v4 *)(om + pl * ops + (int64_t)(jt0 * 16 + oo) * a.NP + (T0) + v * EPV); \
     }                                                                                           \
   } while (0)
+#define QSK_Y_STORE_OM(BUF)                                                                     \
+  do {                                                                                          \
+    _Pragma("unroll") for (int u = 0; u < VPT; ++u) {                                           \
+      const int e = tid + u * 256;                                                              \
+      const int v = e % VPR, oo = (e / VPR) % (NJ * 16), pl = e / (VPR * NJ * 16);              \
+      *(u32v4 *)&s_om[BUF][pl][oo][v * EPV] = orr[u];                                           \
+    }                                                                                           \
+  } while (0)
+  // one 32-column step from the A values in X: convert, refetch X two steps
+  // ahead, fetch the next Omega tile, run the matrix cores, stage Omega
+#define QSK_Y_STEP(T0, X)                                                                       \
+  do {                                                                                          \
+    Frag af[4][3];                                                                              \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) to_frags<OP, TERMS>(X[q], af[q]);             \
+    if ((T0) + 64 < te) QSK_Y_FETCH_A((T0) + 64, X);                                            \
+    const bool more_ = (T0) + 32 < te;                                                          \
+    if (more_) QSK_Y_FETCH_OM((T0) + 32);                                                       \
+    Frag onext[4];                                                                              \
+    _Pragma("unroll") for (int s = 0; s < 4; ++s)                                               \
+      lds_frag<Frag, OPT>(&s_om[buf][s][c16][8 * g], onext[s]);                                 \
+    _Pragma("unroll") for (int jt = 0; jt < NJ; ++jt) {                                         \
+      Frag of[7];                                                                               \
+      _Pragma("unroll") for (int s = 0; s < 4; ++s) of[s] = onext[s];                           \
+      if (jt + 1 < NJ) {                                                                        \
+        _Pragma("unroll") for (int s = 0; s < 4; ++s)                                           \
+          lds_frag<Frag, OPT>(&s_om[buf][s][(jt + 1) * 16 + c16][8 * g], onext[s]);             \
+      }                                                                                         \
+      neg3(of);                                                                                 \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                           \
+        if (q == 0 && PURE) continue;                                                         \
+        _Pragma("unroll") for (int tm = 0; tm < TERMS; ++tm)                                    \
+          _Pragma("unroll") for (int p = 0; p < 4; ++p)                                         \
+            acc[jt][p] = mma(af[q][tm], of[rsel(q, p)], acc[jt][p]);                            \
+      }                                                                                         \
+    }                                                                                           \
+    if (more_) QSK_Y_STORE_OM(buf ^ 1);                                                         \
+    __syncthreads();                                                                            \
+    buf ^= 1;                                                                                   \
+  } while (0)
 
-  QSK_Y_FETCH(tb);
-  for (int64_t t0 = tb; t0 < te; t0 += 32) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if constexpr (OP == OP_BF16) {
-        FragB f[3];
-        split_terms<TERMS>(xa[q], f);
-#pragma unroll
-        for (int tm = 0; tm < TERMS; ++tm)
-          *(uint4 *)&s_a[tm][q][lr][8 * lg] = make_uint4(f[tm].v[0], f[tm].v[1], f[tm].v[2], f[tm].v[3]);
-      } else {
-        *(float4 *)&s_a[0][q][lr][8 * lg] = make_float4(xa[q][0], xa[q][1], xa[q][2], xa[q][3]);
-        *(float4 *)&s_a[0][q][lr][8 * lg + 4] = make_float4(xa[q][4], xa[q][5], xa[q][6], xa[q][7]);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) {
-      const int e = tid + u * 256;
-      const int v = e % VPR, oo = (e / VPR) % (NJ * 16), pl = e / (VPR * NJ * 16);
-      *(u32v4 *)&s_om[pl][oo][v * EPV] = orr[u];
-    }
-    __syncthreads();
-    if (t0 + 32 < te) QSK_Y_FETCH(t0 + 32);
-    Frag af[4][NT];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int tm = 0; tm < NT; ++tm) lds_frag<Frag, OPT>(&s_a[tm][q][wave * 16 + c16][8 * g], af[q][tm]);
-#pragma unroll
-    for (int jt = 0; jt < NJ; ++jt) {
-      Frag of[7];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) lds_frag<Frag, OPT>(&s_om[s][jt * 16 + c16][8 * g], of[s]);
-      if constexpr (OP == OP_BF16) { of[4] = negB(of[1]); of[5] = negB(of[2]); of[6] = negB(of[3]); }
-      else { of[4] = negF(of[1]); of[5] = negF(of[2]); of[6] = negF(of[3]); }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (q == 0 && a.pure) continue;
-#pragma unroll
-        for (int tm = 0; tm < TERMS; ++tm)
-#pragma unroll
-          for (int p = 0; p < 4; ++p) acc[jt][p] = mma(af[q][tm], of[rsel(q, p)], acc[jt][p]);
-      }
-    }
-    __syncthreads();
+  QSK_Y_FETCH_A(tb, xa0);
+  if (tb + 32 < te) QSK_Y_FETCH_A(tb + 32, xa1);
+  QSK_Y_FETCH_OM(tb);
+  QSK_Y_STORE_OM(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t t0 = tb; t0 < te; t0 += 64) {
+    QSK_Y_STEP(t0, xa0);
+    if (t0 + 32 < te) QSK_Y_STEP(t0 + 32, xa1);
   }
   // epilogue: lane holds column (jt0 + jt) * 16 + c16 of Y, rows rb + 16 wave + 4g + (0..3)
   const int64_t r0 = rb + wave * 16 + 4 * g;
@@ -485,7 +536,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     if (jj >= a.k) continue;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      float *dst = ys + p * a.psy + (int64_t)jj * a.ldy;
+      QSK_GLOBAL float *dst = gpw(ys + p * a.psy + (int64_t)jj * a.ldy);
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt)
         if (r0 + tt < a.m) dst[r0 + tt] += acc[jt][p][tt];
@@ -494,7 +545,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 }
 
 #undef QSK_W_FETCH
-#undef QSK_Y_FETCH
+#undef QSK_W_STORE_PSI
+#undef QSK_Y_FETCH_A
+#undef QSK_Y_FETCH_OM
+#undef QSK_Y_STORE_OM
+#undef QSK_Y_STEP
 
 // Y = sum of its split-K copies: copy 0 += copies 1 .. S-1, which are cleared.
 __global__ void y_fold_kernel(float *y, int64_t n_per_copy, int S) {
@@ -566,13 +621,21 @@ static inline void mark(const SketchArgs &s, int idx) {
   if (s.events) (void)hipEventRecord(s.events[idx], s.stream);
 }
 
+// `pure` (no real plane) is a template parameter so that the product
+// sequences have no branches
 template <int OP, typename TIN, int TERMS, int NMT>
 static void launch_w(const WArgs &w, int64_t blocks, hipStream_t st, GroupRef g = GroupRef{}) {
-  hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS>), dim3((unsigned)blocks), dim3(256), 0, st, w, g);
+  if (w.pure)
+    hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS, true>), dim3((unsigned)blocks), dim3(256), 0, st, w, g);
+  else
+    hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS, false>), dim3((unsigned)blocks), dim3(256), 0, st, w, g);
 }
 template <int OP, typename TIN, int TERMS, int NJ>
 static void launch_y(const YArgs &y, int64_t blocks, hipStream_t st, GroupRef g = GroupRef{}) {
-  hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS>), dim3((unsigned)blocks), dim3(256), 0, st, y, g);
+  if (y.pure)
+    hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS, true>), dim3((unsigned)blocks), dim3(256), 0, st, y, g);
+  else
+    hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS, false>), dim3((unsigned)blocks), dim3(256), 0, st, y, g);
 }
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
@@ -580,6 +643,8 @@ static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 template <int OP, typename TIN, int TERMS>
 static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
   using OPT = typename std::conditional<OP == OP_BF16, uint16_t, float>::type;
+  // the Y kernel addresses each plane's update block with 32-bit byte offsets
+  if ((uint64_t)((s.m - 1) + (s.ncols - 1) * s.lda) * sizeof(TIN) >= (1ull << 32)) return hipErrorNotSupported;
   hipError_t e;
   mark(s, 0);
   // regenerate Omega_J and Psi in the operand format
@@ -736,6 +801,7 @@ static hipError_t launch_batch_t(const SketchArgs *s, const MfmaStage *g, int co
   std::vector<int64_t> py(count + 1, 0), pw(count + 1, 0);
   for (int i = 0; i < count; ++i) {
     const SketchArgs &q = s[i];
+    if ((uint64_t)((q.m - 1) + (q.ncols - 1) * q.lda) * sizeof(TIN) >= (1ull << 32)) return hipErrorNotSupported;
     bool vec = (q.lda % (16 / (int64_t)sizeof(TIN))) == 0;
     for (int p = q.pure ? 1 : 0; p < 4; ++p) vec = vec && aligned16(q.planes[p]);
     YArgs &y = ys[i];
