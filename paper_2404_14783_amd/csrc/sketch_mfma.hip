@@ -119,12 +119,6 @@ __device__ __forceinline__ void split_terms(const float (&x)[8], FragB (&out)[3]
   }
 }
 
-template <typename TIN> __device__ __forceinline__ float ldin(const TIN *p, int64_t i);
-template <> __device__ __forceinline__ float ldin<float>(const float *p, int64_t i) { return gp(p)[i]; }
-template <> __device__ __forceinline__ float ldin<uint16_t>(const uint16_t *p, int64_t i) {
-  return __uint_as_float(((uint32_t)gp(p)[i]) << 16);
-}
-
 // Signed plane selection of R(Omega) (Y) and S(Psi) (W): index into
 // {+w, +x, +y, +z, -x, -y, -z} = {0, 1, 2, 3, 4, 5, 6}.  Used inside fully
 // unrolled loops so that every index is a compile-time constant.
@@ -147,66 +141,9 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t total) {
   return (b & 7) * (total >> 3) + (b >> 3);
 }
 
-// Loads of 8 consecutive input values (rows i .. i+7 of one column) for the
-// operand conversion; vector loads when the column segment is aligned.
-template <typename TIN>
-__device__ __forceinline__ void load8(const TIN *p, int64_t idx, int64_t navail, bool vec, float (&x)[8]);
-template <>
-__device__ __forceinline__ void load8<float>(const float *p, int64_t idx, int64_t navail, bool vec,
-                                             float (&x)[8]) {
-  if (vec && navail >= 8) {
-    const QSK_GLOBAL floatx4 *v = (const QSK_GLOBAL floatx4 *)(p + idx);
-    const floatx4 u0 = v[0], u1 = v[1];
-    x[0] = u0.x; x[1] = u0.y; x[2] = u0.z; x[3] = u0.w;
-    x[4] = u1.x; x[5] = u1.y; x[6] = u1.z; x[7] = u1.w;
-  } else {
-#pragma unroll
-    for (int s = 0; s < 8; ++s) x[s] = s < navail ? gp(p)[idx + s] : 0.f;
-  }
-}
-template <>
-__device__ __forceinline__ void load8<uint16_t>(const uint16_t *p, int64_t idx, int64_t navail,
-                                                bool vec, float (&x)[8]) {
-  if (vec && navail >= 8) {
-    const u32v4 u = *(const QSK_GLOBAL u32v4 *)(p + idx);
-    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      x[2 * s] = __uint_as_float(w[s] << 16);
-      x[2 * s + 1] = __uint_as_float(w[s] & 0xFFFF0000u);
-    }
-  } else {
-#pragma unroll
-    for (int s = 0; s < 8; ++s) x[s] = s < navail ? __uint_as_float(((uint32_t)gp(p)[idx + s]) << 16) : 0.f;
-  }
-}
-
-// One input element at a byte address (global).
-template <typename TIN> __device__ __forceinline__ float ld_elem(const QSK_GLOBAL char *p);
-template <> __device__ __forceinline__ float ld_elem<float>(const QSK_GLOBAL char *p) {
-  return *(const QSK_GLOBAL float *)p;
-}
-template <> __device__ __forceinline__ float ld_elem<uint16_t>(const QSK_GLOBAL char *p) {
-  return __uint_as_float(((uint32_t)*(const QSK_GLOBAL uint16_t *)p) << 16);
-}
-
 // The negated copies of planes x, y, z of a test-matrix fragment set.
 __device__ __forceinline__ void neg3(FragB (&f)[7]) { f[4] = negB(f[1]); f[5] = negB(f[2]); f[6] = negB(f[3]); }
 __device__ __forceinline__ void neg3(FragF (&f)[7]) { f[4] = negF(f[1]); f[5] = negF(f[2]); f[6] = negF(f[3]); }
-
-template <typename Frag, typename OPT>
-__device__ __forceinline__ void lds_frag(const OPT *src, Frag &f);
-template <>
-__device__ __forceinline__ void lds_frag<FragB, uint16_t>(const uint16_t *src, FragB &f) {
-  const uint4 u = *(const uint4 *)src;
-  f.v[0] = u.x; f.v[1] = u.y; f.v[2] = u.z; f.v[3] = u.w;
-}
-template <>
-__device__ __forceinline__ void lds_frag<FragF, float>(const float *src, FragF &f) {
-  const float4 u0 = *(const float4 *)src, u1 = *(const float4 *)(src + 4);
-  f.v[0] = u0.x; f.v[1] = u0.y; f.v[2] = u0.z; f.v[3] = u0.w;
-  f.v[4] = u1.x; f.v[5] = u1.y; f.v[6] = u1.z; f.v[7] = u1.w;
-}
 
 // The data operand of one lane: 8 values per plane -> TERMS fragments.
 template <int OP, int TERMS>
@@ -218,28 +155,92 @@ __device__ __forceinline__ void to_frags(const float (&x)[8], FragF (&out)[3]) {
 }
 
 // ---------------------------------------------------------------------------
+// Operand access shared by both kernels.
+//
+// The data planes are read through buffer resources that span one plane of
+// the update block, [0, ((ncols - 1) lda + m) elements): a load at an offset
+// past the end returns zero instead of faulting, so the loads need no
+// predicates and never split the instruction stream into branches.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+// 8 consecutive values of one column (W's data operand); byte offset voff
+template <typename TIN> __device__ __forceinline__ void bload8(rsrc_t r, uint32_t voff, float (&x)[8]);
+template <> __device__ __forceinline__ void bload8<float>(rsrc_t r, uint32_t voff, float (&x)[8]) {
+  const u32v4 u0 = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
+  const u32v4 u1 = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16, 0, 0);
+  x[0] = __uint_as_float(u0.x); x[1] = __uint_as_float(u0.y); x[2] = __uint_as_float(u0.z); x[3] = __uint_as_float(u0.w);
+  x[4] = __uint_as_float(u1.x); x[5] = __uint_as_float(u1.y); x[6] = __uint_as_float(u1.z); x[7] = __uint_as_float(u1.w);
+}
+template <> __device__ __forceinline__ void bload8<uint16_t>(rsrc_t r, uint32_t voff, float (&x)[8]) {
+  const u32v4 u = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    x[2 * s] = __uint_as_float(w[s] << 16);
+    x[2 * s + 1] = __uint_as_float(w[s] & 0xFFFF0000u);
+  }
+}
+// one value (Y's data operand); the column stride goes in the scalar offset
+template <typename TIN> __device__ __forceinline__ float bload1(rsrc_t r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ float bload1<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ float bload1<uint16_t>(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __uint_as_float(((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)) << 16);
+}
+
+// The staged test-matrix tiles go from HBM straight into LDS (no register
+// staging): one instruction moves 16 bytes per lane into 1 KB of LDS, lane L
+// writing bytes 16 L .. 16 L + 15 of the block.  A (plane, 16-row tile) block
+// of a 32-wide step is laid out in the order the fragment reads want it:
+// lane L = 16 g + c holds row c, contraction indices 8 g .. 8 g + 7 (bf16:
+// one block; fp32: two blocks, indices 8g..8g+3 and 8g+4..8g+7), so a
+// fragment read is one contiguous, conflict-free 1 KB wave access per block.
+__device__ __forceinline__ void dma16(const void *src, void *lds_block) {
+  __builtin_amdgcn_global_load_lds((const QSK_GLOBAL void *)src, (QSK_LDS void *)lds_block, 16, 0, 0);
+}
+// wait until this wave's loads (direct-to-LDS ones included) have landed
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+template <typename Frag> __device__ __forceinline__ void dma_frag(const char *blk, int lane, Frag &f);
+template <> __device__ __forceinline__ void dma_frag<FragB>(const char *blk, int lane, FragB &f) {
+  const u32v4 u = *(const QSK_LDS u32v4 *)(blk + lane * 16);
+  f.v[0] = u.x; f.v[1] = u.y; f.v[2] = u.z; f.v[3] = u.w;
+}
+template <> __device__ __forceinline__ void dma_frag<FragF>(const char *blk, int lane, FragF &f) {
+  const floatx4 u0 = *(const QSK_LDS floatx4 *)(blk + lane * 16);
+  const floatx4 u1 = *(const QSK_LDS floatx4 *)(blk + 1024 + lane * 16);
+  f.v[0] = u0.x; f.v[1] = u0.y; f.v[2] = u0.z; f.v[3] = u0.w;
+  f.v[4] = u1.x; f.v[5] = u1.y; f.v[6] = u1.z; f.v[7] = u1.w;
+}
+
+// ---------------------------------------------------------------------------
 // W kernel.  Tiles: 64 columns of the update block x NMT row tiles of W
 // (16 rows each) x one chunk of the rows of A (split K over S chunks).
-// Block = 4 waves; wave w owns columns 16 w .. 16 w + 15 of the tile, all NMT
-// row tiles and all four planes.  Per 32-row step the Psi tile (4 planes x
-// 16 NMT rows x 32) goes through LDS; each lane's A values (8 consecutive
-// rows of its column, four planes) go straight from HBM into registers.  Both
-// are fetched one step ahead (software pipelining).
+// Block = 4H waves, H per SIMD: wave w owns columns 16 (w mod 4) .. + 15 of
+// the tile and the w / 4-th of H slices of the NMT row tiles, all four
+// planes.  With H = 2 one wave's loads, conversions and barrier waits overlap
+// the other's matrix-core work.  Per 32-row step the Psi tile (4 planes x 16
+// NMT rows x 32) goes HBM -> LDS directly (two buffers, one barrier per
+// step); each lane's A values (8 consecutive rows of its column, four planes)
+// come from HBM into registers.  Both are fetched one step ahead.
 struct WArgs {
   const void *a[4];
   int64_t lda, m, ncols, col0;
   const void *psi;            // staged [4][LP][MP]
   int LP;
   int64_t MP;
-  int l, pure, S, ctiles, rgroups, vec;
+  int l, pure, S, ctiles, rgroups;
   int64_t kchunk;
   float *w;
   int64_t ldw, psw;
   float *part;                // [S][4][ncols][LP]
 };
 
-template <int OP, typename TIN, int NMT, int TERMS, bool PURE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void w_mfma_kernel(WArgs a0, GroupRef grp) {
+template <int OP, typename TIN, int NMT, int TERMS, bool PURE, int H>
+__global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H))) void w_mfma_kernel(WArgs a0, GroupRef grp) {
   WArgs a;
   int64_t t;
   if (grp.tab) {
@@ -252,106 +253,127 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   }
   using OPT = typename std::conditional<OP == OP_BF16, uint16_t, float>::type;
   using Frag = typename std::conditional<OP == OP_BF16, FragB, FragF>::type;
-  constexpr int LDK = 32 + (OP == OP_BF16 ? 8 : 4);        // padded K stride in LDS
-  constexpr int EPV = 16 / sizeof(OPT);                    // elements per 16-byte vector
-  constexpr int VPR = 32 / EPV;                            // vectors per tile row
-  constexpr int NV = 4 * NMT * 16 * VPR;                   // vectors per Psi tile
-  constexpr int VPT = NV / 256;
-  static_assert(NV % 256 == 0, "Psi tile must split evenly over the block");
-  __shared__ OPT s_psi[2][4][NMT * 16][LDK];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  constexpr int NH = (NMT + H - 1) / H;                    // row tiles per wave
+  constexpr int SUB = OP == OP_BF16 ? 1 : 2;               // 1 KB blocks per (plane, row tile)
+  constexpr int NBLK = 4 * NMT * SUB;                      // 1 KB blocks per step
+  constexpr int NW = 4 * H;                                // waves per block
+  __shared__ __attribute__((aligned(1024))) char s_psi[2][NBLK][1024];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c16 = lane & 15, g = lane >> 4;
+  const int cg = wave & 3, hf = wave >> 2;
   const int bx = (int)(t % a.ctiles);
   const int by = (int)((t / a.ctiles) % a.rgroups);
   const int bz = (int)(t / ((int64_t)a.ctiles * a.rgroups));
-  const int64_t j = (int64_t)bx * 64 + wave * 16 + c16;
+  const int64_t j = (int64_t)bx * 64 + cg * 16 + c16;
   const int rbase = by * NMT * 16;
+  const int rt0 = hf * NH;                                 // first row tile of this wave
   const int64_t ib = (int64_t)bz * a.kchunk;
   const int64_t ie = min(a.m, ib + a.kchunk);
   const OPT *psi = (const OPT *)a.psi;
   const int64_t pps = (int64_t)a.LP * a.MP;
-  const TIN *ap[4] = {(const TIN *)a.a[0], (const TIN *)a.a[1], (const TIN *)a.a[2], (const TIN *)a.a[3]};
-  const bool jok = j < a.ncols;
-  const bool vec = a.vec != 0;
-
-  floatx4 acc[NMT][4];
+  const uint32_t abytes = (uint32_t)(((a.ncols - 1) * a.lda + a.m) * (int64_t)sizeof(TIN));
+  rsrc_t ar[4];
 #pragma unroll
-  for (int r = 0; r < NMT; ++r)
+  for (int q = 0; q < 4; ++q) ar[q] = make_rsrc(a.a[q], abytes);
+  // byte offset of rows ib + 8g .. of column j (the host keeps every offset
+  // of the block below 2^32; columns j >= ncols read zeros or other
+  // columns' values and are never stored)
+  uint32_t voff = (uint32_t)((ib + 8 * g + j * a.lda) * (int64_t)sizeof(TIN));
+  const uint32_t vstep = 32u * (uint32_t)sizeof(TIN);
+  // this lane's DMA source: row c16 of a 16-row tile, indices 8g (+4 sb)
+  const OPT *psrc = psi + (int64_t)(rbase + c16) * a.MP + 8 * g;
+  const int64_t tile_st = 16 * a.MP;                       // next row tile
+
+  floatx4 acc[NH][4];
+#pragma unroll
+  for (int r = 0; r < NH; ++r)
 #pragma unroll
     for (int p = 0; p < 4; ++p) acc[r][p] = {0.f, 0.f, 0.f, 0.f};
 
+  // The range check of a 16-byte load works per dword: with bf16 data the
+  // dword that holds the block's last element, A[m-1, ncols-1], may reach
+  // past the end of the buffer and read as zero.  That element is loaded on
+  // its own once and put back where it belongs.
+  float last[4] = {0.f, 0.f, 0.f, 0.f};
+  const bool fix_last = sizeof(TIN) == 2 && j == a.ncols - 1 && ie == a.m;
+  if constexpr (sizeof(TIN) == 2) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (!(q == 0 && PURE)) last[q] = bload1<TIN>(ar[q], abytes - 2, 0);
+  }
+
   float xa[4][8];
-  u32v4 pr[VPT];
-#define QSK_W_FETCH(I0)                                                                         \
+#define QSK_W_FETCH_A()                                                                         \
   do {                                                                                          \
-    const int64_t i_ = (I0) + 8 * g;                                                            \
-    const int64_t nav_ = jok ? min((int64_t)8, ie - i_) : 0;                                    \
     _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                             \
-      if (q == 0 && PURE) {                                                                   \
+      if (q == 0 && PURE) {                                                                     \
         _Pragma("unroll") for (int s = 0; s < 8; ++s) xa[q][s] = 0.f;                           \
       } else {                                                                                  \
-        load8<TIN>(ap[q], i_ + j * a.lda, nav_, vec, xa[q]);                                    \
+        bload8<TIN>(ar[q], voff, xa[q]);                                                        \
       }                                                                                         \
     }                                                                                           \
-    _Pragma("unroll") for (int u = 0; u < VPT; ++u) {                                           \
-      const int e = tid + u * 256;                                                              \
-      const int v = e % VPR, rr = (e / VPR) % (NMT * 16), pl = e / (VPR * NMT * 16);            \
-      pr[u] = *(const QSK_GLOBAL u32v4 *)(psi + pl * pps + (int64_t)(rbase + rr) * a.MP + (I0) + v * EPV);   \
-    }                                                                                           \
   } while (0)
-
-#define QSK_W_STORE_PSI(BUF)                                                                    \
+#define QSK_W_DMA(I0, B)                                                                        \
   do {                                                                                          \
-    _Pragma("unroll") for (int u = 0; u < VPT; ++u) {                                           \
-      const int e = tid + u * 256;                                                              \
-      const int v = e % VPR, rr = (e / VPR) % (NMT * 16), pl = e / (VPR * NMT * 16);            \
-      *(u32v4 *)&s_psi[BUF][pl][rr][v * EPV] = pr[u];                                           \
+    _Pragma("unroll") for (int k_ = 0; k_ < (NBLK + NW - 1) / NW; ++k_) {                       \
+      const int u_ = wave + k_ * NW;                                                            \
+      if (u_ < NBLK) {                                                                          \
+        const int sb_ = u_ % SUB, rt_ = (u_ / SUB) % NMT, pl_ = u_ / (SUB * NMT);               \
+        dma16(psrc + pl_ * pps + rt_ * tile_st + (I0) + 4 * sb_, &s_psi[B][u_][0]);             \
+      }                                                                                         \
     }                                                                                           \
   } while (0)
 
-  QSK_W_FETCH(ib);
-  QSK_W_STORE_PSI(0);
+  QSK_W_FETCH_A();
+  QSK_W_DMA(ib, 0);
+  wait_vm();
   __syncthreads();
   int buf = 0;
   for (int64_t i0 = ib; i0 < ie; i0 += 32) {
+    // rows past the end hold other columns' values (or zeros): drop them
+    const int64_t rem = ie - (i0 + 8 * g);
     Frag af[4][3];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) to_frags<OP, TERMS>(xa[q], af[q]);
-    const bool more = i0 + 32 < ie;
-    if (more) QSK_W_FETCH(i0 + 32);
-    // Psi fragments of row tile rt + 1 are read from LDS while the matrix
-    // cores work on row tile rt
-    Frag pnext[4];
+    for (int q = 0; q < 4; ++q) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) lds_frag<Frag, OPT>(&s_psi[buf][s][c16][8 * g], pnext[s]);
-#pragma unroll
-    for (int rt = 0; rt < NMT; ++rt) {
-      Frag pf[7];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) pf[s] = pnext[s];
-      if (rt + 1 < NMT) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) lds_frag<Frag, OPT>(&s_psi[buf][s][(rt + 1) * 16 + c16][8 * g], pnext[s]);
+      for (int s = 0; s < 8; ++s) {
+        xa[q][s] = s < rem ? xa[q][s] : 0.f;
+        if constexpr (sizeof(TIN) == 2) xa[q][s] = (fix_last && s == rem - 1) ? last[q] : xa[q][s];
       }
-      if constexpr (OP == OP_BF16) { pf[4] = negB(pf[1]); pf[5] = negB(pf[2]); pf[6] = negB(pf[3]); }
-      else { pf[4] = negF(pf[1]); pf[5] = negF(pf[2]); pf[6] = negF(pf[3]); }
+      to_frags<OP, TERMS>(xa[q], af[q]);
+    }
+    voff += vstep;
+    QSK_W_FETCH_A();                                       // next step (past the end: unused)
+    if (i0 + 32 < ie) QSK_W_DMA(i0 + 32, buf ^ 1);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (q == 0 && PURE) continue;
+    for (int i = 0; i < NH; ++i) {
+      const int rt = rt0 + i;
+      if (rt < NMT) {
+        Frag pf[7];
 #pragma unroll
-        for (int tm = 0; tm < TERMS; ++tm)
+        for (int s = 0; s < 4; ++s) dma_frag<Frag>(&s_psi[buf][(s * NMT + rt) * SUB][0], lane, pf[s]);
+        neg3(pf);
 #pragma unroll
-          for (int p = 0; p < 4; ++p) acc[rt][p] = mma(pf[ssel(p, q)], af[q][tm], acc[rt][p]);
+        for (int q = 0; q < 4; ++q) {
+          if (q == 0 && PURE) continue;
+#pragma unroll
+          for (int tm = 0; tm < TERMS; ++tm)
+#pragma unroll
+            for (int p = 0; p < 4; ++p) acc[i][p] = mma(pf[ssel(p, q)], af[q][tm], acc[i][p]);
+        }
       }
     }
-    if (more) QSK_W_STORE_PSI(buf ^ 1);
+    wait_vm();
     __syncthreads();
     buf ^= 1;
   }
   // epilogue: lane holds column j, rows rbase + rt*16 + 4g + (0..3)
-  if (!jok) return;
+  if (j >= a.ncols) return;
 #pragma unroll
-  for (int rt = 0; rt < NMT; ++rt) {
+  for (int i = 0; i < NH; ++i) {
+    const int rt = rt0 + i;
+    if (rt >= NMT) continue;
     const int r0 = rbase + rt * 16 + 4 * g;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
@@ -359,10 +381,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         QSK_GLOBAL float *dst = gpw(a.w + p * a.psw + (a.col0 + j) * a.ldw);
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt)
-          if (r0 + tt < a.l) dst[r0 + tt] += acc[rt][p][tt];
+          if (r0 + tt < a.l) dst[r0 + tt] += acc[i][p][tt];
       } else {
         float *dst = a.part + (((int64_t)bz * 4 + p) * a.ncols + j) * a.LP + r0;
-        *(QSK_GLOBAL floatx4 *)dst = acc[rt][p];
+        *(QSK_GLOBAL floatx4 *)dst = acc[i][p];
       }
     }
   }
@@ -384,15 +406,14 @@ __global__ void w_reduce_kernel(const float *part, int S, int LP, int64_t ncols,
 }
 
 // ---------------------------------------------------------------------------
-// Y kernel.  Tiles: 64 rows of A x NJ column tiles of Y (16 columns each) x
-// one chunk of the update's columns (split K over S chunks; chunk s adds into
-// its own copy s of Y, and the copies are summed when the sketch is read).
-// Block = 4 waves; wave w owns rows 16 w .. 16 w + 15 of the tile, all NJ
-// column tiles and all four planes.  No other wave needs a wave's rows of A,
-// so each lane loads its own operand values (row c16, columns 8 g .. 8 g + 7
-// of the step) straight from HBM; only the Omega tile, which all four waves
-// share, goes through LDS (two buffers, one barrier per step).  Both are
-// fetched one step ahead.
+// Y kernel.  Tiles: 64 H rows of A x NJ column tiles of Y (16 columns each)
+// x one chunk of the update's columns (split K over S chunks; chunk s adds
+// into its own copy s of Y, and the copies are summed when the sketch is
+// read).  Block = 4H waves, H per SIMD: wave w owns rows 16 w .. 16 w + 15 of
+// the tile and all NJ column tiles, all four planes.  Each lane loads its
+// own operand values (row c16, columns 8 g .. 8 g + 7 of the step) from HBM;
+// the Omega tile, which all waves share, goes HBM -> LDS directly (two
+// buffers, one barrier per step).  Both are fetched one step ahead.
 struct YArgs {
   const void *a[4];
   int64_t lda, m, ncols;
@@ -405,8 +426,8 @@ struct YArgs {
   int64_t ldy, psy, pss;      // copy s of plane p: y + s * pss + p * psy
 };
 
-template <int OP, typename TIN, int NJ, int TERMS, bool PURE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void y_mfma_kernel(YArgs a0, GroupRef grp) {
+template <int OP, typename TIN, int NJ, int TERMS, bool PURE, int H>
+__global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H))) void y_mfma_kernel(YArgs a0, GroupRef grp) {
   YArgs a;
   int64_t t;
   if (grp.tab) {
@@ -419,32 +440,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   }
   using OPT = typename std::conditional<OP == OP_BF16, uint16_t, float>::type;
   using Frag = typename std::conditional<OP == OP_BF16, FragB, FragF>::type;
-  constexpr int LDK = 32 + (OP == OP_BF16 ? 8 : 4);
-  constexpr int EPV = 16 / sizeof(OPT);
-  constexpr int VPR = 32 / EPV;
-  constexpr int NV = 4 * NJ * 16 * VPR;                     // vectors per Omega tile
-  constexpr int VPT = NV / 256;
-  static_assert(NV % 256 == 0, "Omega tile must split evenly over the block");
-  __shared__ OPT s_om[2][4][NJ * 16][LDK];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  constexpr int SUB = OP == OP_BF16 ? 1 : 2;
+  constexpr int NBLK = 4 * NJ * SUB;
+  constexpr int NW = 4 * H;
+  __shared__ __attribute__((aligned(1024))) char s_om[2][NBLK][1024];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c16 = lane & 15, g = lane >> 4;
   const int64_t bx = t % a.rblocks;
   const int by = (int)((t / a.rblocks) % a.cgroups);
   const int bz = (int)(t / ((int64_t)a.rblocks * a.cgroups));
-  const int64_t rb = bx * 64;
-  const int jt0 = by * NJ;
+  const int64_t rb = bx * 64 * H;
+  const int jt0 = by * NJ;                                  // first column tile of the block
   const int64_t tb = (int64_t)bz * a.tchunk;
   const int64_t te = min(a.ncols, tb + a.tchunk);
   const OPT *om = (const OPT *)a.om;
   const int64_t ops = (int64_t)a.KP * a.NP;
-  // plane bases (uniform) and this lane's byte offsets into them: the update
-  // block of every plane spans < 4 GiB (checked on the host), so a 32-bit
-  // offset from a scalar base addresses it
-  const QSK_GLOBAL char *ab[4] = {(const QSK_GLOBAL char *)a.a[0], (const QSK_GLOBAL char *)a.a[1],
-                                  (const QSK_GLOBAL char *)a.a[2], (const QSK_GLOBAL char *)a.a[3]};
-  const int64_t row = rb + wave * 16 + c16;                 // this lane's row of A
-  const bool rok = row < a.m;
-  const int64_t rowc = rok ? row : a.m - 1;
+  const uint32_t abytes = (uint32_t)(((a.ncols - 1) * a.lda + a.m) * (int64_t)sizeof(TIN));
+  rsrc_t ar[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) ar[q] = make_rsrc(a.a[q], abytes);
+  // this lane's row; rows >= m read other columns' values (or zeros) and
+  // only feed rows of Y that are never stored; columns >= ncols lie past the
+  // end of the buffer and read zeros (the host keeps every offset < 2^32)
+  const int64_t row = rb + wave * 16 + c16;
+  const uint32_t col_bytes = (uint32_t)(a.lda * (int64_t)sizeof(TIN));
+  uint32_t voff = (uint32_t)((row + (tb + 8 * g) * a.lda) * (int64_t)sizeof(TIN));
+  const uint32_t vstep = 32u * col_bytes;
+  const OPT *osrc = om + (int64_t)(jt0 * 16 + c16) * a.NP + 8 * g;
+  const int64_t tile_st = 16 * a.NP;
 
   floatx4 acc[NJ][4];
 #pragma unroll
@@ -452,104 +476,110 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
     for (int p = 0; p < 4; ++p) acc[u][p] = {0.f, 0.f, 0.f, 0.f};
 
-  // A values of two steps in flight: X[q][s] = A_q[row, T + 8 g + s]
-  float xa0[4][8], xa1[4][8];
-  u32v4 orr[VPT];
-#define QSK_Y_FETCH_A(T0, X)                                                                    \
+  // A values of the next step: xa[q][s] = A_q[row, T + 8 g + s]
+  float xa[4][8];
+#define QSK_Y_FETCH_A()                                                                         \
   do {                                                                                          \
-    /* out-of-range elements load a valid address and are zeroed (no branches) */              \
-    _Pragma("unroll") for (int s = 0; s < 8; ++s) {                                             \
-      const int64_t tt = (T0) + 8 * g + s;                                                      \
-      const bool ok_ = rok && tt < te;                                                          \
-      const uint32_t off_ = (uint32_t)((rowc + (ok_ ? tt : tb) * a.lda) * (int64_t)sizeof(TIN)); \
-      _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                           \
-        if (q == 0 && PURE) { X[q][s] = 0.f; continue; }                                        \
-        const float v_ = ld_elem<TIN>(ab[q] + off_);                                            \
-        X[q][s] = ok_ ? v_ : 0.f;                                                               \
-      }                                                                                         \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                             \
+      _Pragma("unroll") for (int s = 0; s < 8; ++s)                                             \
+        xa[q][s] = (q == 0 && PURE) ? 0.f : bload1<TIN>(ar[q], voff, (uint32_t)s * col_bytes);  \
     }                                                                                           \
   } while (0)
-#define QSK_Y_FETCH_OM(T0)                                                                      \
+#define QSK_Y_DMA(T0, B)                                                                        \
   do {                                                                                          \
-    _Pragma("unroll") for (int u = 0; u < VPT; ++u) {                                           \
-      const int e = tid + u * 256;                                                              \
-      const int v = e % VPR, oo = (e / VPR) % (NJ * 16), pl = e / (VPR * NJ * 16);              \
-      orr[u] = *(const QSK_GLOBAL u32v4 *)(om + pl * ops + (int64_t)(jt0 * 16 + oo) * a.NP + (T0) + v * EPV); \
-    }                                                                                           \
-  } while (0)
-#define QSK_Y_STORE_OM(BUF)                                                                     \
-  do {                                                                                          \
-    _Pragma("unroll") for (int u = 0; u < VPT; ++u) {                                           \
-      const int e = tid + u * 256;                                                              \
-      const int v = e % VPR, oo = (e / VPR) % (NJ * 16), pl = e / (VPR * NJ * 16);              \
-      *(u32v4 *)&s_om[BUF][pl][oo][v * EPV] = orr[u];                                           \
-    }                                                                                           \
-  } while (0)
-  // one 32-column step from the A values in X: convert, refetch X two steps
-  // ahead, fetch the next Omega tile, run the matrix cores, stage Omega
-#define QSK_Y_STEP(T0, X)                                                                       \
-  do {                                                                                          \
-    Frag af[4][3];                                                                              \
-    _Pragma("unroll") for (int q = 0; q < 4; ++q) to_frags<OP, TERMS>(X[q], af[q]);             \
-    if ((T0) + 64 < te) QSK_Y_FETCH_A((T0) + 64, X);                                            \
-    const bool more_ = (T0) + 32 < te;                                                          \
-    if (more_) QSK_Y_FETCH_OM((T0) + 32);                                                       \
-    Frag onext[4];                                                                              \
-    _Pragma("unroll") for (int s = 0; s < 4; ++s)                                               \
-      lds_frag<Frag, OPT>(&s_om[buf][s][c16][8 * g], onext[s]);                                 \
-    _Pragma("unroll") for (int jt = 0; jt < NJ; ++jt) {                                         \
-      Frag of[7];                                                                               \
-      _Pragma("unroll") for (int s = 0; s < 4; ++s) of[s] = onext[s];                           \
-      if (jt + 1 < NJ) {                                                                        \
-        _Pragma("unroll") for (int s = 0; s < 4; ++s)                                           \
-          lds_frag<Frag, OPT>(&s_om[buf][s][(jt + 1) * 16 + c16][8 * g], onext[s]);             \
-      }                                                                                         \
-      neg3(of);                                                                                 \
-      _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                           \
-        if (q == 0 && PURE) continue;                                                         \
-        _Pragma("unroll") for (int tm = 0; tm < TERMS; ++tm)                                    \
-          _Pragma("unroll") for (int p = 0; p < 4; ++p)                                         \
-            acc[jt][p] = mma(af[q][tm], of[rsel(q, p)], acc[jt][p]);                            \
+    _Pragma("unroll") for (int k_ = 0; k_ < (NBLK + NW - 1) / NW; ++k_) {                       \
+      const int u_ = wave + k_ * NW;                                                            \
+      if (u_ < NBLK) {                                                                          \
+        const int sb_ = u_ % SUB, jt_ = (u_ / SUB) % NJ, pl_ = u_ / (SUB * NJ);                 \
+        dma16(osrc + pl_ * ops + jt_ * tile_st + (T0) + 4 * sb_, &s_om[B][u_][0]);              \
       }                                                                                         \
     }                                                                                           \
-    if (more_) QSK_Y_STORE_OM(buf ^ 1);                                                         \
-    __syncthreads();                                                                            \
-    buf ^= 1;                                                                                   \
   } while (0)
 
-  QSK_Y_FETCH_A(tb, xa0);
-  if (tb + 32 < te) QSK_Y_FETCH_A(tb + 32, xa1);
-  QSK_Y_FETCH_OM(tb);
-  QSK_Y_STORE_OM(0);
+  QSK_Y_FETCH_A();
+  QSK_Y_DMA(tb, 0);
+  wait_vm();
   __syncthreads();
   int buf = 0;
-  for (int64_t t0 = tb; t0 < te; t0 += 64) {
-    QSK_Y_STEP(t0, xa0);
-    if (t0 + 32 < te) QSK_Y_STEP(t0 + 32, xa1);
+  for (int64_t t0 = tb; t0 < te; t0 += 32) {
+    Frag af[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) to_frags<OP, TERMS>(xa[q], af[q]);
+    voff += vstep;
+    QSK_Y_FETCH_A();                                        // next step (past the end: unused)
+    if (t0 + 32 < te) QSK_Y_DMA(t0 + 32, buf ^ 1);
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+      Frag of[7];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) dma_frag<Frag>(&s_om[buf][(s * NJ + i) * SUB][0], lane, of[s]);
+      neg3(of);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q == 0 && PURE) continue;
+#pragma unroll
+        for (int tm = 0; tm < TERMS; ++tm)
+#pragma unroll
+          for (int p = 0; p < 4; ++p) acc[i][p] = mma(af[q][tm], of[rsel(q, p)], acc[i][p]);
+      }
+    }
+    wait_vm();
+    __syncthreads();
+    buf ^= 1;
   }
-  // epilogue: lane holds column (jt0 + jt) * 16 + c16 of Y, rows rb + 16 wave + 4g + (0..3)
+  // epilogue: lane holds column (jt0 + i) * 16 + c16 of Y, rows rb + 16 wave + 4g + (0..3)
   const int64_t r0 = rb + wave * 16 + 4 * g;
   float *ys = a.y + bz * a.pss;
+  const bool full = rb + 64 * H <= a.m && ((a.ldy | a.psy | a.pss) & 3) == 0;
+  if (full) {
+    // whole tile inside Y: 16-byte read-modify-writes through one buffer per
+    // plane; columns past k get an offset past the end, so their loads read
+    // zeros and their stores are dropped (no branches)
+    rsrc_t yr[4];
 #pragma unroll
-  for (int jt = 0; jt < NJ; ++jt) {
-    const int jj = (jt0 + jt) * 16 + c16;
+    for (int p = 0; p < 4; ++p) yr[p] = make_rsrc(ys + p * a.psy, (uint32_t)(a.psy * 4));
+    floatx4 old[NJ][4];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+      const int jj = (jt0 + i) * 16 + c16;
+      const uint32_t o = jj < a.k ? (uint32_t)((jj * a.ldy + r0) * 4) : 0xFFFFFFF0u;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const u32v4 u = __builtin_amdgcn_raw_buffer_load_b128(yr[p], o, 0, 0);
+        old[i][p] = {__uint_as_float(u.x), __uint_as_float(u.y), __uint_as_float(u.z), __uint_as_float(u.w)};
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+      const int jj = (jt0 + i) * 16 + c16;
+      const uint32_t o = jj < a.k ? (uint32_t)((jj * a.ldy + r0) * 4) : 0xFFFFFFF0u;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const floatx4 v = old[i][p] + acc[i][p];
+        const u32v4 u = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z), __float_as_uint(v.w)};
+        __builtin_amdgcn_raw_buffer_store_b128(u, yr[p], o, 0, 0);
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    const int jj = (jt0 + i) * 16 + c16;
     if (jj >= a.k) continue;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       QSK_GLOBAL float *dst = gpw(ys + p * a.psy + (int64_t)jj * a.ldy);
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt)
-        if (r0 + tt < a.m) dst[r0 + tt] += acc[jt][p][tt];
+        if (r0 + tt < a.m) dst[r0 + tt] += acc[i][p][tt];
     }
   }
 }
 
-#undef QSK_W_FETCH
-#undef QSK_W_STORE_PSI
+#undef QSK_W_FETCH_A
+#undef QSK_W_DMA
 #undef QSK_Y_FETCH_A
-#undef QSK_Y_FETCH_OM
-#undef QSK_Y_STORE_OM
-#undef QSK_Y_STEP
+#undef QSK_Y_DMA
 
 // Y = sum of its split-K copies: copy 0 += copies 1 .. S-1, which are cleared.
 __global__ void y_fold_kernel(float *y, int64_t n_per_copy, int S) {
@@ -621,30 +651,52 @@ static inline void mark(const SketchArgs &s, int idx) {
   if (s.events) (void)hipEventRecord(s.events[idx], s.stream);
 }
 
+// Waves per SIMD of the two kernels (the block has 4 H waves).
+#ifndef QSK_W_WAVES
+#define QSK_W_WAVES 2
+#endif
+#ifndef QSK_Y_WAVES
+#define QSK_Y_WAVES 2
+#endif
+template <int OP> constexpr int w_waves() { return OP == OP_BF16 ? QSK_W_WAVES : 1; }
+template <int OP> constexpr int y_waves() { return OP == OP_BF16 ? QSK_Y_WAVES : 1; }
+
 // `pure` (no real plane) is a template parameter so that the product
 // sequences have no branches
 template <int OP, typename TIN, int TERMS, int NMT>
 static void launch_w(const WArgs &w, int64_t blocks, hipStream_t st, GroupRef g = GroupRef{}) {
+  constexpr int H = w_waves<OP>();
   if (w.pure)
-    hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS, true>), dim3((unsigned)blocks), dim3(256), 0, st, w, g);
+    hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS, true, H>), dim3((unsigned)blocks), dim3(256 * H), 0, st, w, g);
   else
-    hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS, false>), dim3((unsigned)blocks), dim3(256), 0, st, w, g);
+    hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS, false, H>), dim3((unsigned)blocks), dim3(256 * H), 0, st, w, g);
 }
 template <int OP, typename TIN, int TERMS, int NJ>
 static void launch_y(const YArgs &y, int64_t blocks, hipStream_t st, GroupRef g = GroupRef{}) {
+  constexpr int H = y_waves<OP>();
   if (y.pure)
-    hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS, true>), dim3((unsigned)blocks), dim3(256), 0, st, y, g);
+    hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS, true, H>), dim3((unsigned)blocks), dim3(256 * H), 0, st, y, g);
   else
-    hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS, false>), dim3((unsigned)blocks), dim3(256), 0, st, y, g);
+    hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS, false, H>), dim3((unsigned)blocks), dim3(256 * H), 0, st, y, g);
 }
+// Rows of A per Y block.
+template <int OP> constexpr int y_rows() { return 64 * y_waves<OP>(); }
 
-static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+// The Y epilogue addresses a plane of Y (m x k fp32) with 32-bit offsets.
+static bool y_plane_fits(int64_t m, int64_t k) { return (uint64_t)m * k * 4 < 0xFFFFFFF0ull; }
+
+// Both kernels address a plane of the update block with 32-bit byte offsets,
+// including the rows and columns that whole tiles and steps run past the
+// end (which read zeros or values that are never used).
+template <typename TIN>
+static bool offsets_fit(int64_t m, int64_t ncols, int64_t lda) {
+  return (uint64_t)((ncols + 64) * lda + rup(m, 128) + 64) * sizeof(TIN) < (1ull << 32);
+}
 
 template <int OP, typename TIN, int TERMS>
 static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
   using OPT = typename std::conditional<OP == OP_BF16, uint16_t, float>::type;
-  // the Y kernel addresses each plane's update block with 32-bit byte offsets
-  if ((uint64_t)((s.m - 1) + (s.ncols - 1) * s.lda) * sizeof(TIN) >= (1ull << 32)) return hipErrorNotSupported;
+  if (!offsets_fit<TIN>(s.m, s.ncols, s.lda) || !y_plane_fits(s.m, s.k)) return hipErrorNotSupported;
   hipError_t e;
   mark(s, 0);
   // regenerate Omega_J and Psi in the operand format
@@ -663,9 +715,6 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     if (e != hipSuccess) return e;
   }
   mark(s, 1);
-  // vector loads of the input need 16-byte aligned column segments
-  bool vec = (s.lda % (16 / (int64_t)sizeof(TIN))) == 0;
-  for (int p = s.pure ? 1 : 0; p < 4; ++p) vec = vec && aligned16(s.planes[p]);
   // ---- Y
   {
     mark(s, 2);
@@ -677,7 +726,7 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     y.y = (float *)s.y; y.ldy = s.ldy; y.psy = s.psy; y.pss = s.pss;
     const int nj = y_nj(s.k);
     const int ntiles = (s.k + 15) / 16;
-    y.rblocks = (int)((s.m + 63) / 64);
+    y.rblocks = (int)((s.m + y_rows<OP>() - 1) / y_rows<OP>());
     y.cgroups = (ntiles + nj - 1) / nj;
     // split the update's columns over the Y copies so that the grid holds
     // about four blocks per CU
@@ -700,7 +749,7 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     for (int p = 0; p < 4; ++p) w.a[p] = s.planes[p];
     w.lda = s.lda; w.m = s.m; w.ncols = s.ncols; w.col0 = s.col0;
     w.psi = ps; w.LP = g.LP; w.MP = g.MP;
-    w.l = s.l; w.pure = s.pure; w.vec = vec ? 1 : 0;
+    w.l = s.l; w.pure = s.pure;
     w.w = (float *)s.w; w.ldw = s.ldw; w.psw = s.psw;
     const int nmt = w_nmt(s.l, OP == OP_BF16);
     w.rgroups = (int)(g.LP / (16 * nmt));
@@ -801,16 +850,14 @@ static hipError_t launch_batch_t(const SketchArgs *s, const MfmaStage *g, int co
   std::vector<int64_t> py(count + 1, 0), pw(count + 1, 0);
   for (int i = 0; i < count; ++i) {
     const SketchArgs &q = s[i];
-    if ((uint64_t)((q.m - 1) + (q.ncols - 1) * q.lda) * sizeof(TIN) >= (1ull << 32)) return hipErrorNotSupported;
-    bool vec = (q.lda % (16 / (int64_t)sizeof(TIN))) == 0;
-    for (int p = q.pure ? 1 : 0; p < 4; ++p) vec = vec && aligned16(q.planes[p]);
+    if (!offsets_fit<TIN>(q.m, q.ncols, q.lda) || !y_plane_fits(q.m, q.k)) return hipErrorNotSupported;
     YArgs &y = ys[i];
     for (int p = 0; p < 4; ++p) y.a[p] = q.planes[p];
     y.lda = q.lda; y.m = q.m; y.ncols = q.ncols;
     y.om = g[i].omega; y.KP = g[i].KP; y.NP = g[i].NP;
     y.k = q.k; y.pure = q.pure;
     y.y = (float *)q.y; y.ldy = q.ldy; y.psy = q.psy; y.pss = 0;
-    y.rblocks = (int)((q.m + 63) / 64);
+    y.rblocks = (int)((q.m + y_rows<OP>() - 1) / y_rows<OP>());
     y.cgroups = g[i].KP / (16 * nj);
     y.S = 1; y.tchunk = rup(q.ncols, 32);
     py[i + 1] = py[i] + (int64_t)y.rblocks * y.cgroups;
@@ -818,7 +865,7 @@ static hipError_t launch_batch_t(const SketchArgs *s, const MfmaStage *g, int co
     for (int p = 0; p < 4; ++p) w.a[p] = q.planes[p];
     w.lda = q.lda; w.m = q.m; w.ncols = q.ncols; w.col0 = 0;
     w.psi = g[i].psi; w.LP = g[i].LP; w.MP = g[i].MP;
-    w.l = q.l; w.pure = q.pure; w.vec = vec ? 1 : 0;
+    w.l = q.l; w.pure = q.pure;
     w.w = (float *)q.w; w.ldw = q.ldw; w.psw = q.psw;
     w.rgroups = g[i].LP / (16 * nmt);
     w.ctiles = (int)((q.ncols + 63) / 64);
