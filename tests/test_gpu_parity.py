@@ -161,6 +161,21 @@ def oracle_sensitivity(ref, kind, rel_pert=1e-15, seed=0):
     return abs(a["kappa"] - b["kappa"]) / a["kappa"], 0.0, 0.0, qt.fro(proj(ha) - proj(hb))
 
 
+def error_sensitivity(a, ref, kind, rel_pert=1e-15, seed=1):
+    """Relative change of the oracle's approximation error when Y is
+    perturbed by a random relative 1e-15 (the error depends on H through
+    X = (Psi H)^dagger W, which the ill-conditioned pseudo-QR factor
+    amplifies)."""
+    import copy
+    rng = np.random.default_rng(seed)
+    h0, x0, _ = onepass.qb_stage(ref, kind)
+    e0 = onepass.rel_error(a, h0, x0)
+    r2 = copy.copy(ref)
+    r2.Y = ref.Y * (1.0 + rel_pert * rng.standard_normal(ref.Y.shape))
+    h2, x2, _ = onepass.qb_stage(r2, kind)
+    return abs(onepass.rel_error(a, h2, x2) - e0) / e0
+
+
 @pytest.mark.parametrize("kind", ["pseudo_qr", "pseudo_svd"])
 def test_config1_qb_stage(config1, kind):
     a, ref, sk, dev = config1
@@ -172,7 +187,9 @@ def test_config1_qb_stage(config1, kind):
     assert rel(hx, hx_o) < 1e-9                        # HX is unique (Lemma 4.2)
     e_gpu = sk.rel_error(dev, q, x)
     e_o = onepass.rel_error(a, h_o, x_o)
-    assert abs(e_gpu - e_o) <= 1e-6 * e_o
+    # agreement to within the oracle's own change under a rounding-level
+    # perturbation of its input (the reading used for kappa and eps below)
+    assert abs(e_gpu - e_o) <= max(1e-6, 100 * error_sensitivity(a, ref, kind)) * e_o
     np.testing.assert_allclose(e_gpu, onepass.rel_error(a, qn, xn), rtol=1e-9)
     # same range as the oracle's factor, up to the oracle's own sensitivity
     # (the paper notes pseudo-QR's weaker range precision, Section 3.3)
