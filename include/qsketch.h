@@ -60,10 +60,16 @@ typedef enum {
      QSK_BF16 data split into split_terms bf16 terms (hi, mid, lo: each term
               rounds what the previous ones left), test matrices rounded to
               bf16 once from their FP64 value, FP32 accumulation, FP32 Y/W;
-     QSK_FP8_E4M3 data quantised to OCP fp8 e4m3 with a power-of-two scale per
-              32 x 32 tile of each plane, optionally plus the exact FP32
-              residual as a second term (split_terms = 2), test matrices
-              rounded to e4m3 once from their FP64 value, FP32 accumulation. */
+     QSK_FP8_E4M3 data quantised to OCP fp8 e4m3 (round to nearest even)
+              with the smallest power-of-two scale per 32 x 32 tile of each
+              plane of the update block that keeps |x / scale| <= 448;
+              split_terms = 2 adds the exact FP32 residual x - q * scale as a
+              correction term (carried as two bf16 terms, i.e. to 2^-16 of the
+              residual); test matrices rounded to e4m3 once from their FP64
+              value; FP32 accumulation, FP32 Y/W.  The dequantised fp8 values
+              are exact in bf16 and all terms run on the bf16 matrix-core
+              product.  Update blocks whose planes need byte offsets of 2^32
+              or more return QSK_E_UNSUPPORTED in this format. */
 typedef enum { QSK_F64 = 0, QSK_F32 = 1, QSK_BF16 = 2, QSK_FP8_E4M3 = 3 } qsk_dtype;
 
 /* Test-matrix distributions: quaternion standard Gaussian, all four

@@ -32,6 +32,8 @@ struct SketchArgs {
   uint32_t k0, k1;       // Philox key
   void *scratch;         // split-K partial buffer for W (matrix-core path)
   int64_t scratch_bytes;
+  float *fp8_scales;     // fp8 tile scales of the block, [4][ceil(m/32)][ceil(ncols/32)]
+  int64_t fp8_scale_elems;
   // optional timing: events[2 * kernel] before, [2 * kernel + 1] after (may be null)
   hipEvent_t *events;
 };

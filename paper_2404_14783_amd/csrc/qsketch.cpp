@@ -57,6 +57,8 @@ struct qsk_ctx {
   SmallStatus *kstatus = nullptr;
   void *w_scratch = nullptr;           // split-K partials of the matrix-core W kernel
   int64_t w_scratch_bytes = 0;
+  float *fp8_scales = nullptr;         // fp8 tile scales of the current block
+  int64_t fp8_scale_elems = 0;
   qsk::MfmaStage stage{};              // transient test-matrix slices (matrix-core path)
   // optional per-kernel timing of updates
   bool timing = false;
@@ -131,7 +133,7 @@ void free_all(qsk_ctx *c) {
   c->side = nullptr;
   void *ptrs[] = {c->y, c->w, c->u[0], c->u[1], c->small, c->work, c->partials, c->pbuf,
                   c->p1buf, c->sbuf, c->err_acc, c->status, c->w_scratch, c->pinv_work,
-                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus};
+                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus, c->fp8_scales};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->y = c->w = nullptr;
@@ -142,6 +144,7 @@ void free_all(qsk_ctx *c) {
   c->pinv_work = nullptr;
   c->stage.omega = c->stage.psi = nullptr;
   c->kwork = nullptr;
+  c->fp8_scales = nullptr;
   c->kstatus = nullptr;
 }
 
@@ -223,14 +226,14 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   if (c.n_correction < 0 || c.n_correction > 8 || c.n_power < 1 || c.n_power > 64) return QSK_E_ARG;
   if (c.max_block_cols < 0) return QSK_E_ARG;
   if (c.sketch_dtype == QSK_BF16 && (c.split_terms < 1 || c.split_terms > 3)) return QSK_E_ARG;
-  if (c.sketch_dtype == QSK_FP8_E4M3) return QSK_E_UNSUPPORTED;
+  if (c.sketch_dtype == QSK_FP8_E4M3 && (c.split_terms < 1 || c.split_terms > 2)) return QSK_E_ARG;
   if (c.sketch_dtype != QSK_F64 && c.input_dtype == QSK_F64) return QSK_E_UNSUPPORTED;
 
   qsk_ctx *ctx = new (std::nothrow) qsk_ctx;
   if (!ctx) return QSK_E_NOMEM;
   ctx->cfg = c;
   if (ctx->cfg.max_block_cols == 0 || ctx->cfg.max_block_cols > c.n) ctx->cfg.max_block_cols = c.n;
-  if (ctx->cfg.sketch_dtype != QSK_BF16) ctx->cfg.split_terms = 1;
+  if (ctx->cfg.sketch_dtype != QSK_BF16 && ctx->cfg.sketch_dtype != QSK_FP8_E4M3) ctx->cfg.split_terms = 1;
   ctx->stream = (hipStream_t)hip_stream;
   ctx->mode = c.sketch_dtype;     // MODE_* and QSK dtypes share the numbering
   ctx->ts = c.sketch_dtype == QSK_F64 ? 8 : 4;
@@ -243,7 +246,8 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   const int64_t m = c.m, n = c.n, k = c.k, l = c.l;
   const size_t kk = (size_t)k * k * 4;
   bool ok = true;
-  const bool mfma_mode = c.sketch_dtype == QSK_BF16 || c.sketch_dtype == QSK_F32;
+  const bool mfma_mode = c.sketch_dtype == QSK_BF16 || c.sketch_dtype == QSK_F32 ||
+                         c.sketch_dtype == QSK_FP8_E4M3;
   ctx->y_copies = mfma_mode ? qsk::Y_COPIES : 1;
   ok = ok && alloc(&ctx->y, (size_t)ctx->y_copies * 4 * m * k * ctx->ts);
   ok = ok && alloc(&ctx->w, 4 * (size_t)l * n * ctx->ts);
@@ -266,11 +270,15 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   ok = ok && hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) == hipSuccess;
   // matrix-core path: staging of Omega_J / Psi and the W split-K partials
-  if (c.sketch_dtype == QSK_BF16 || c.sketch_dtype == QSK_F32) {
+  if (mfma_mode) {
     qsk::MfmaStage &g = ctx->stage;
-    qsk::stage_geometry(m, (int)l, (int)k, ctx->cfg.max_block_cols, c.sketch_dtype == QSK_BF16,
-                        &g.LP, &g.MP, &g.KP, &g.NP);
-    const size_t es = c.sketch_dtype == QSK_BF16 ? 2 : 4;
+    const bool op16 = c.sketch_dtype != QSK_F32;     // bf16 operands (BF16, FP8 data)
+    qsk::stage_geometry(m, (int)l, (int)k, ctx->cfg.max_block_cols, op16, &g.LP, &g.MP, &g.KP, &g.NP);
+    const size_t es = op16 ? 2 : 4;
+    if (c.sketch_dtype == QSK_FP8_E4M3) {
+      ctx->fp8_scale_elems = 4 * ((m + 31) / 32) * ((ctx->cfg.max_block_cols + 31) / 32);
+      ok = ok && alloc((void **)&ctx->fp8_scales, (size_t)ctx->fp8_scale_elems * 4);
+    }
     ok = ok && alloc(&g.omega, 4 * (size_t)g.KP * g.NP * es);
     ok = ok && alloc(&g.psi, 4 * (size_t)g.LP * g.MP * es);
     ctx->w_scratch_bytes = (int64_t)16 * 4 * ctx->cfg.max_block_cols * g.LP * 4;
@@ -340,6 +348,8 @@ qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void 
   s.k0 = ctx->k0; s.k1 = ctx->k1;
   s.scratch = ctx->w_scratch;
   s.scratch_bytes = ctx->w_scratch_bytes;
+  s.fp8_scales = ctx->fp8_scales;
+  s.fp8_scale_elems = ctx->fp8_scale_elems;
   s.events = nullptr;
   if (ctx->timing && ctx->use_mfma && ctx->mode != qsk::MODE_F64) {
     if (ctx->ev_used + 8 > ctx->ev_pool.size()) {
@@ -356,6 +366,11 @@ qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void 
   if (ctx->use_mfma && ctx->mode != qsk::MODE_F64) {
     e = qsk::launch_sketch_mfma(s, ctx->stage);
     if (e == hipSuccess) ctx->psi_staged = true;
+  }
+  if (e == hipErrorNotSupported && ctx->mode == qsk::MODE_FP8) {
+    ctx->last_error = "fp8 sketch: block too large for the matrix-core path (32-bit offsets) or "
+                      "matrix-core path disabled";
+    return QSK_E_UNSUPPORTED;
   }
   if (e == hipErrorNotSupported) e = qsk::launch_sketch_generic(s);
   if (e != hipSuccess) return hip_fail(ctx, e, "sketch update");
@@ -515,7 +530,7 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
   }
   // Psi as the sketch used it: the matrix-core path's staging holds exactly
   // those values (rounded to the operand format); otherwise regenerate
-  const int psi_st_type = !ctx->psi_staged ? 0 : (ctx->mode == qsk::MODE_BF16 ? 1 : 2);
+  const int psi_st_type = !ctx->psi_staged ? 0 : (ctx->mode == qsk::MODE_F32 ? 2 : 1);
   HIPCHK(ctx, qsk::launch_psi_apply(st, ctx->mode, c.embedding == QSK_RADEMACHER, ctx->k0, ctx->k1, l,
                                     m, Q, ldq, k, ctx->partials, ctx->partial_elems, pp, l,
                                     ctx->stage.psi, psi_st_type, ctx->stage.MP,

@@ -34,7 +34,12 @@ typedef __attribute__((ext_vector_type(4))) float floatx4;
 // struct that keeps arrays of it out of registers)
 typedef __attribute__((ext_vector_type(4))) unsigned int u32v4;
 
-enum : int { OP_BF16 = 0, OP_F32 = 1 };
+// Operand formats of the products: bf16 (data split into bf16 terms), fp32,
+// and fp8-quantised data: e4m3 with a power-of-two scale per 32 x 32 tile,
+// whose dequantised values are exact in bf16, plus the exact residual as
+// further bf16 terms (all three run on the bf16 matrix-core instruction).
+enum : int { OP_BF16 = 0, OP_F32 = 1, OP_FP8 = 2 };
+constexpr bool op_f32(int op) { return op == OP_F32; }
 
 // ---------------------------------------------------------------------------
 // Staging of the test matrices.  Layout [plane][o][t] with t (the contraction
@@ -145,13 +150,86 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t total) {
 __device__ __forceinline__ void neg3(FragB (&f)[7]) { f[4] = negB(f[1]); f[5] = negB(f[2]); f[6] = negB(f[3]); }
 __device__ __forceinline__ void neg3(FragF (&f)[7]) { f[4] = negF(f[1]); f[5] = negF(f[2]); f[6] = negF(f[3]); }
 
+// fp8 operand split of 8 data values sharing the tile scale sc (a power of
+// two): term 0 is q * sc with q = e4m3(x / sc) (round to nearest even, as
+// the tile scale keeps |x / sc| <= 448 no saturation occurs), exact in bf16;
+// the residual x - q * sc is exact in fp32 and follows as TERMS - 1 bf16
+// terms.
+template <int TERMS>
+__device__ __forceinline__ void split_fp8(const float (&x)[8], float sc, FragB (&out)[3]) {
+  const float inv = 1.0f / sc;                       // exact: sc is a power of two
+  float r[8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float d0 = e4m3_rne(x[2 * i] * inv) * sc, d1 = e4m3_rne(x[2 * i + 1] * inv) * sc;
+    out[0].v[i] = (__float_as_uint(d0) >> 16) | (__float_as_uint(d1) & 0xFFFF0000u);
+    r[2 * i] = x[2 * i] - d0;
+    r[2 * i + 1] = x[2 * i + 1] - d1;
+  }
+  if constexpr (TERMS > 1) {
+    FragB rest[3];
+    split_terms<TERMS - 1>(r, rest);
+#pragma unroll
+    for (int tm = 1; tm < TERMS; ++tm) out[tm] = rest[tm - 1];
+  }
+}
+
 // The data operand of one lane: 8 values per plane -> TERMS fragments.
 template <int OP, int TERMS>
-__device__ __forceinline__ void to_frags(const float (&x)[8], FragB (&out)[3]) { split_terms<TERMS>(x, out); }
+__device__ __forceinline__ void to_frags(const float (&x)[8], float sc, FragB (&out)[3]) {
+  if constexpr (OP == OP_FP8) split_fp8<TERMS>(x, sc, out);
+  else split_terms<TERMS>(x, out);
+}
 template <int OP, int TERMS>
-__device__ __forceinline__ void to_frags(const float (&x)[8], FragF (&out)[3]) {
+__device__ __forceinline__ void to_frags(const float (&x)[8], float sc, FragF (&out)[3]) {
 #pragma unroll
   for (int s = 0; s < 8; ++s) out[0].v[s] = x[s];
+}
+
+// ---------------------------------------------------------------------------
+// fp8 tile scales of one update block: for plane p and the 32 x 32 tile
+// (rt, ct) of the block (rows from 0, columns from the block's first), the
+// smallest power of two sc with amax / sc <= 448, 1 for an all-zero tile;
+// sc[(p * RT + rt) * CT + ct].  One wave per tile: lane c < 32 reads rows
+// 0..15 of column c, lane c + 32 rows 16..31.
+template <typename TIN>
+__global__ __launch_bounds__(256) void fp8_scale_kernel(const void *a0, const void *a1, const void *a2,
+                                                        const void *a3, int64_t lda, int64_t m,
+                                                        int64_t ncols, int pure, int RT, int CT,
+                                                        float *sc) {
+  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t ntiles = 4 * (int64_t)RT * CT;
+  if (tile >= ntiles) return;
+  const int p = (int)(tile / ((int64_t)RT * CT));
+  const int rt = (int)((tile / CT) % RT), ct = (int)(tile % CT);
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)ct * 32 + (lane & 31), r0 = (int64_t)rt * 32 + (lane >> 5) * 16;
+  const TIN *a = (const TIN *)(p == 0 ? a0 : p == 1 ? a1 : p == 2 ? a2 : a3);
+  float mx = 0.f;
+  if (!(p == 0 && pure) && c < ncols) {
+    for (int i = 0; i < 16; ++i) {
+      const int64_t r = r0 + i;
+      if (r < m) {
+        float v;
+        if constexpr (sizeof(TIN) == 4) v = gp((const float *)a)[r + c * lda];
+        else v = __uint_as_float(((uint32_t)gp((const uint16_t *)a)[r + c * lda]) << 16);
+        mx = fmaxf(mx, fabsf(v));
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+  if (lane == 0) {
+    float s = 1.f;
+    if (mx > 0.f) {
+      // mx = f 2^E with 0.5 <= f < 1, and 448 = 0.875 2^9: the smallest e with
+      // mx <= 448 2^e is E - 9, or E - 8 when f > 0.875
+      int E;
+      const float f = frexpf(mx, &E);
+      s = ldexpf(1.f, E - 9 + (f > 0.875f ? 1 : 0));
+    }
+    sc[tile] = s;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -237,6 +315,8 @@ struct WArgs {
   float *w;
   int64_t ldw, psw;
   float *part;                // [S][4][ncols][LP]
+  const float *fsc;           // fp8 tile scales [4][RT][CT] (OP_FP8)
+  int RT, CT;
 };
 
 template <int OP, typename TIN, int NMT, int TERMS, bool PURE, int H>
@@ -251,10 +331,10 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
     a = a0;
     t = xcd_tile(blockIdx.x, (int64_t)a.ctiles * a.rgroups * a.S);
   }
-  using OPT = typename std::conditional<OP == OP_BF16, uint16_t, float>::type;
-  using Frag = typename std::conditional<OP == OP_BF16, FragB, FragF>::type;
+  using OPT = typename std::conditional<!op_f32(OP), uint16_t, float>::type;
+  using Frag = typename std::conditional<!op_f32(OP), FragB, FragF>::type;
   constexpr int NH = (NMT + H - 1) / H;                    // row tiles per wave
-  constexpr int SUB = OP == OP_BF16 ? 1 : 2;               // 1 KB blocks per (plane, row tile)
+  constexpr int SUB = !op_f32(OP) ? 1 : 2;               // 1 KB blocks per (plane, row tile)
   constexpr int NBLK = 4 * NMT * SUB;                      // 1 KB blocks per step
   constexpr int NW = 4 * H;                                // waves per block
   __shared__ __attribute__((aligned(1024))) char s_psi[2][NBLK][1024];
@@ -304,13 +384,18 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
   }
 
   float xa[4][8];
-#define QSK_W_FETCH_A()                                                                         \
+  // fp8: the scales of this lane's tiles (rows of the step, column j)
+  float scn[4] = {1.f, 1.f, 1.f, 1.f};
+  const int sct = OP == OP_FP8 ? (int)min(j >> 5, (int64_t)a.CT - 1) : 0;
+#define QSK_W_FETCH_A(I0)                                                                       \
   do {                                                                                          \
     _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                             \
       if (q == 0 && PURE) {                                                                     \
         _Pragma("unroll") for (int s = 0; s < 8; ++s) xa[q][s] = 0.f;                           \
       } else {                                                                                  \
         bload8<TIN>(ar[q], voff, xa[q]);                                                        \
+        if constexpr (OP == OP_FP8)                                                             \
+          scn[q] = gp(a.fsc)[((int64_t)q * a.RT + min((int64_t)(I0) >> 5, (int64_t)a.RT - 1)) * a.CT + sct]; \
       }                                                                                         \
     }                                                                                           \
   } while (0)
@@ -325,7 +410,7 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
     }                                                                                           \
   } while (0)
 
-  QSK_W_FETCH_A();
+  QSK_W_FETCH_A(ib);
   QSK_W_DMA(ib, 0);
   wait_vm();
   __syncthreads();
@@ -341,10 +426,10 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
         xa[q][s] = s < rem ? xa[q][s] : 0.f;
         if constexpr (sizeof(TIN) == 2) xa[q][s] = (fix_last && s == rem - 1) ? last[q] : xa[q][s];
       }
-      to_frags<OP, TERMS>(xa[q], af[q]);
+      to_frags<OP, TERMS>(xa[q], scn[q], af[q]);
     }
     voff += vstep;
-    QSK_W_FETCH_A();                                       // next step (past the end: unused)
+    QSK_W_FETCH_A(i0 + 32);                                // next step (past the end: unused)
     if (i0 + 32 < ie) QSK_W_DMA(i0 + 32, buf ^ 1);
 #pragma unroll
     for (int i = 0; i < NH; ++i) {
@@ -424,6 +509,8 @@ struct YArgs {
   int64_t tchunk;
   float *y;
   int64_t ldy, psy, pss;      // copy s of plane p: y + s * pss + p * psy
+  const float *fsc;           // fp8 tile scales [4][RT][CT] (OP_FP8)
+  int RT, CT;
 };
 
 template <int OP, typename TIN, int NJ, int TERMS, bool PURE, int H>
@@ -438,9 +525,9 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
     a = a0;
     t = xcd_tile(blockIdx.x, (int64_t)a.rblocks * a.cgroups * a.S);
   }
-  using OPT = typename std::conditional<OP == OP_BF16, uint16_t, float>::type;
-  using Frag = typename std::conditional<OP == OP_BF16, FragB, FragF>::type;
-  constexpr int SUB = OP == OP_BF16 ? 1 : 2;
+  using OPT = typename std::conditional<!op_f32(OP), uint16_t, float>::type;
+  using Frag = typename std::conditional<!op_f32(OP), FragB, FragF>::type;
+  constexpr int SUB = !op_f32(OP) ? 1 : 2;
   constexpr int NBLK = 4 * NJ * SUB;
   constexpr int NW = 4 * H;
   __shared__ __attribute__((aligned(1024))) char s_om[2][NBLK][1024];
@@ -478,11 +565,17 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
 
   // A values of the next step: xa[q][s] = A_q[row, T + 8 g + s]
   float xa[4][8];
-#define QSK_Y_FETCH_A()                                                                         \
+  // fp8: the scales of this lane's tiles (its row, columns of the step)
+  float scn[4] = {1.f, 1.f, 1.f, 1.f};
+  const int64_t srt = OP == OP_FP8 ? min(row >> 5, (int64_t)a.RT - 1) : 0;
+#define QSK_Y_FETCH_A(T0)                                                                       \
   do {                                                                                          \
     _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                             \
       _Pragma("unroll") for (int s = 0; s < 8; ++s)                                             \
         xa[q][s] = (q == 0 && PURE) ? 0.f : bload1<TIN>(ar[q], voff, (uint32_t)s * col_bytes);  \
+      if constexpr (OP == OP_FP8)                                                               \
+        if (!(q == 0 && PURE))                                                                  \
+          scn[q] = gp(a.fsc)[((int64_t)q * a.RT + srt) * a.CT + min((int64_t)(T0) >> 5, (int64_t)a.CT - 1)]; \
     }                                                                                           \
   } while (0)
 #define QSK_Y_DMA(T0, B)                                                                        \
@@ -496,7 +589,7 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
     }                                                                                           \
   } while (0)
 
-  QSK_Y_FETCH_A();
+  QSK_Y_FETCH_A(tb);
   QSK_Y_DMA(tb, 0);
   wait_vm();
   __syncthreads();
@@ -504,9 +597,9 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
   for (int64_t t0 = tb; t0 < te; t0 += 32) {
     Frag af[4][3];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) to_frags<OP, TERMS>(xa[q], af[q]);
+    for (int q = 0; q < 4; ++q) to_frags<OP, TERMS>(xa[q], scn[q], af[q]);
     voff += vstep;
-    QSK_Y_FETCH_A();                                        // next step (past the end: unused)
+    QSK_Y_FETCH_A(t0 + 32);                                 // next step (past the end: unused)
     if (t0 + 32 < te) QSK_Y_DMA(t0 + 32, buf ^ 1);
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
@@ -658,8 +751,8 @@ static inline void mark(const SketchArgs &s, int idx) {
 #ifndef QSK_Y_WAVES
 #define QSK_Y_WAVES 2
 #endif
-template <int OP> constexpr int w_waves() { return OP == OP_BF16 ? QSK_W_WAVES : 1; }
-template <int OP> constexpr int y_waves() { return OP == OP_BF16 ? QSK_Y_WAVES : 1; }
+template <int OP> constexpr int w_waves() { return !op_f32(OP) ? QSK_W_WAVES : 1; }
+template <int OP> constexpr int y_waves() { return !op_f32(OP) ? QSK_Y_WAVES : 1; }
 
 // `pure` (no real plane) is a template parameter so that the product
 // sequences have no branches
@@ -695,7 +788,7 @@ static bool offsets_fit(int64_t m, int64_t ncols, int64_t lda) {
 
 template <int OP, typename TIN, int TERMS>
 static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
-  using OPT = typename std::conditional<OP == OP_BF16, uint16_t, float>::type;
+  using OPT = typename std::conditional<!op_f32(OP), uint16_t, float>::type;
   if (!offsets_fit<TIN>(s.m, s.ncols, s.lda) || !y_plane_fits(s.m, s.k)) return hipErrorNotSupported;
   hipError_t e;
   mark(s, 0);
@@ -708,10 +801,27 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     if (e != hipSuccess) return e;
     e = gen_stage<MODE_BF16, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
+  } else if (s.mode == MODE_FP8) {
+    // e4m3 test-matrix values, staged as (exact) bf16
+    e = gen_stage<MODE_FP8, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
+    if (e != hipSuccess) return e;
+    e = gen_stage<MODE_FP8, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
+    if (e != hipSuccess) return e;
   } else {
     e = gen_stage<MODE_F32, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
     e = gen_stage<MODE_F32, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
+    if (e != hipSuccess) return e;
+  }
+  // fp8: the tile scales of this block
+  const int RT = (int)((s.m + 31) / 32), CT = (int)((s.ncols + 31) / 32);
+  if constexpr (OP == OP_FP8) {
+    if (!s.fp8_scales || 4 * (int64_t)RT * CT > s.fp8_scale_elems) return hipErrorInvalidValue;
+    const int64_t tiles = 4 * (int64_t)RT * CT;
+    hipLaunchKernelGGL(fp8_scale_kernel<TIN>, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s.stream,
+                       s.planes[0], s.planes[1], s.planes[2], s.planes[3], s.lda, s.m, s.ncols, s.pure,
+                       RT, CT, s.fp8_scales);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   mark(s, 1);
@@ -719,6 +829,7 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
   {
     mark(s, 2);
     YArgs y{};
+    y.fsc = s.fp8_scales; y.RT = RT; y.CT = CT;
     for (int p = 0; p < 4; ++p) y.a[p] = s.planes[p];
     y.lda = s.lda; y.m = s.m; y.ncols = s.ncols;
     y.om = om; y.KP = g.KP; y.NP = NPu;
@@ -746,12 +857,13 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
   // ---- W
   {
     WArgs w{};
+    w.fsc = s.fp8_scales; w.RT = RT; w.CT = CT;
     for (int p = 0; p < 4; ++p) w.a[p] = s.planes[p];
     w.lda = s.lda; w.m = s.m; w.ncols = s.ncols; w.col0 = s.col0;
     w.psi = ps; w.LP = g.LP; w.MP = g.MP;
     w.l = s.l; w.pure = s.pure;
     w.w = (float *)s.w; w.ldw = s.ldw; w.psw = s.psw;
-    const int nmt = w_nmt(s.l, OP == OP_BF16);
+    const int nmt = w_nmt(s.l, !op_f32(OP));
     w.rgroups = (int)(g.LP / (16 * nmt));
     w.ctiles = (int)((s.ncols + 63) / 64);
     // split the rows of A so that there are >= ~2 blocks per CU
@@ -766,7 +878,7 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     w.S = (int)S; w.kchunk = kchunk; w.part = (float *)s.scratch;
     const int64_t blocks = base * S;
     mark(s, 4);
-    if (nmt == 13) launch_w<OP, TIN, TERMS, (OP == OP_BF16 ? 13 : 7)>(w, blocks, s.stream);
+    if (nmt == 13) launch_w<OP, TIN, TERMS, (!op_f32(OP) ? 13 : 7)>(w, blocks, s.stream);
     else if (nmt == 7) launch_w<OP, TIN, TERMS, 7>(w, blocks, s.stream);
     else launch_w<OP, TIN, TERMS, 4>(w, blocks, s.stream);
     e = hipGetLastError();
@@ -882,7 +994,7 @@ static hipError_t launch_batch_t(const SketchArgs *s, const MfmaStage *g, int co
   else launch_y<OP, TIN, TERMS, 4>(ys[0], py[count], st, gy);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (nmt == 13) launch_w<OP, TIN, TERMS, (OP == OP_BF16 ? 13 : 7)>(ws[0], pw[count], st, gw);
+  if (nmt == 13) launch_w<OP, TIN, TERMS, (!op_f32(OP) ? 13 : 7)>(ws[0], pw[count], st, gw);
   else if (nmt == 7) launch_w<OP, TIN, TERMS, 7>(ws[0], pw[count], st, gw);
   else launch_w<OP, TIN, TERMS, 4>(ws[0], pw[count], st, gw);
   return hipGetLastError();
@@ -907,8 +1019,16 @@ hipError_t launch_sketch_mfma_batch(const SketchArgs *s, const MfmaStage *g, int
 }
 
 hipError_t launch_sketch_mfma(const SketchArgs &s, const MfmaStage &g) {
-  if (s.mode != MODE_BF16 && s.mode != MODE_F32) return hipErrorNotSupported;
+  if (s.mode != MODE_BF16 && s.mode != MODE_F32 && s.mode != MODE_FP8) return hipErrorNotSupported;
   if (!g.omega || !g.psi) return hipErrorNotSupported;
+  if (s.mode == MODE_FP8) {
+    // split_terms 1: the e4m3 term alone; 2: plus the residual (two bf16 terms)
+    if (s.in_dtype == DT_F32)
+      return s.terms == 1 ? launch_t<OP_FP8, float, 1>(s, g) : launch_t<OP_FP8, float, 3>(s, g);
+    if (s.in_dtype == DT_BF16)
+      return s.terms == 1 ? launch_t<OP_FP8, uint16_t, 1>(s, g) : launch_t<OP_FP8, uint16_t, 3>(s, g);
+    return hipErrorNotSupported;
+  }
   if (s.mode == MODE_BF16) {
     if (s.in_dtype == DT_F32) {
       if (s.terms == 1) return launch_t<OP_BF16, float, 1>(s, g);

@@ -122,6 +122,18 @@ def test_fp8_block_quantisation():
         for bj in range(2):
             blk = a[bi * 32:(bi + 1) * 32, bj * 32:(bj + 1) * 32]
             assert np.max(np.abs(blk)) / sc[bi, bj] <= 448
+    # and the smallest such power of two: half the scale would overflow 448
+    for bi in range(3):
+        for bj in range(2):
+            amax = np.max(np.abs(a[bi * 32:(bi + 1) * 32, bj * 32:(bj + 1) * 32]))
+            assert amax / (sc[bi, bj] / 2) > 448
+    # edge values: exact 448 * 2^e keeps scale 2^e, one ulp above doubles it,
+    # an all-zero block has scale 1
+    for e in (-20, -1, 0, 3, 40):
+        v = 448.0 * 2.0 ** e
+        assert lowprec.pow2_scale(np.array(v)) == 2.0 ** e
+        assert lowprec.pow2_scale(np.array(np.nextafter(np.float32(v), np.float32(np.inf)), dtype=np.float64)) == 2.0 ** (e + 1)
+    assert lowprec.pow2_scale(np.array(0.0)) == 1.0
     res = a - deq
     np.testing.assert_array_equal(res.astype(np.float32).astype(np.float64), res)  # exact in FP32
     big = np.abs(a) > 1e-2 * np.max(np.abs(a))
