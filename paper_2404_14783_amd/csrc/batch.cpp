@@ -625,17 +625,21 @@ qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const
   } else {
     if ((r = gemm_all(b, st, ok_ids, SC(B_RPROD), 0, SC(B_RPROD), 1, S(B_TMP))) != QSK_OK) return r;
     if (!ok_ids.empty()) {
-      std::vector<qsk::PsvdArgs> a(ok_ids.size());
-      std::vector<int64_t> one(ok_ids.size(), 1);
-      for (size_t i = 0; i < ok_ids.size(); ++i) {
-        const Prob &q = b->p[ok_ids[i]];
-        a[i].k = q.k; a[i].gl = q.slot(B_TMP); a[i].k0 = q.k0; a[i].k1 = q.k1; a[i].c = q.slot(B_C);
-        a[i].work = q.work; a[i].status = b->status + ok_ids[i]; a[i].gx = 1; a[i].gy = 1;
+      for (int stage = 0; stage < 5; ++stage) {
+        std::vector<qsk::PsvdArgs> a(ok_ids.size());
+        std::vector<int64_t> nb(ok_ids.size());
+        for (size_t i = 0; i < ok_ids.size(); ++i) {
+          const Prob &q = b->p[ok_ids[i]];
+          a[i].k = q.k; a[i].gl = q.slot(B_TMP); a[i].k0 = q.k0; a[i].k1 = q.k1; a[i].c = q.slot(B_C);
+          a[i].work = q.work; a[i].status = b->status + ok_ids[i];
+          a[i].gx = qsk::psvd_blocks(q.k, stage); a[i].gy = 1;
+          nb[i] = a[i].gx;
+        }
+        GroupRef g;
+        int64_t tot;
+        if (!push_group(b, a, nb, &g, &tot)) return arena_full(b);
+        BCHK(b, qsk::launch_psvd_stage(st, stage, a[0], g, tot));
       }
-      GroupRef g;
-      int64_t tot;
-      if (!push_group(b, a, one, &g, &tot)) return arena_full(b);
-      BCHK(b, qsk::launch_psvd_k(st, a[0], g, (int)ok_ids.size()));
     }
   }
   if ((r = gemm_all(b, st, ok_ids, SC(B_T), 0, SC(B_C), 0, S(B_F))) != QSK_OK) return r;

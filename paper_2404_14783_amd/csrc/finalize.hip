@@ -774,6 +774,7 @@ __global__ __launch_bounds__(1024) void chol_kernel(CholArgs args, GroupRef grp)
   __syncthreads();
   if (threadIdx.x == 0) {
     status->fail = fail;
+    if (fail) status->fail_any = 1;
     status->min_pivot2 = minp;
     status->trace = trace;
   }
@@ -900,6 +901,7 @@ __global__ __launch_bounds__(1024) void cholinv_reg_kernel(CholArgs args, GroupR
     double m = maxd;
     for (int q = 0; q < 16; ++q) m = fmin(m, s_red[2][q]);
     status->fail = fail;
+    if (fail) status->fail_any = 1;
     status->min_pivot2 = maxd > 0.0 ? fmin(1.0, m / maxd) : 0.0;
     status->trace = trace;
   }
@@ -965,6 +967,18 @@ __global__ __launch_bounds__(256) void triinv_kernel(CholArgs args, GroupRef grp
     __syncthreads();
   }
   for (int a = tid; a < k; a += 256) sq_(t, a, c, k, col[a]);
+}
+
+__global__ void status_reset_kernel(SmallStatus *s, int keep_fail_any) {
+  if (threadIdx.x == 0) {
+    const int fa = keep_fail_any ? s->fail_any : 0;
+    *s = SmallStatus{};
+    s->fail_any = fa;
+  }
+}
+hipError_t launch_status_reset(hipStream_t st, SmallStatus *s, int keep_fail_any) {
+  hipLaunchKernelGGL(status_reset_kernel, dim3(1), dim3(64), 0, st, s, keep_fail_any);
+  return hipGetLastError();
 }
 
 hipError_t launch_chol_k(hipStream_t st, const CholArgs &a, GroupRef g, int count) {
@@ -1152,7 +1166,28 @@ hipError_t launch_identity(hipStream_t st, int k, double *c) {
 
 // LDS pool (doubles) of the tridiagonalisation and of the eigenvector clean-up.
 constexpr int TRI_POOL = 16384;
-__device__ __forceinline__ void sm_heev(double *g, int k, double *lam, double *U, double *work, double *pool);
+
+// Work layout of the pseudo-SVD pipeline (doubles; kq = k * k):
+//   U  [0, 4kq)           eigenvectors of G_L (AoS k x k), then the bad-pair
+//   B  [4kq, 12kq)        matrices of the repair (B, UB as in the kernel);
+//   E = work + 20 kq:     the eigensolver's state between its kernels:
+//     HV [0, 4kq)         Householder vectors (column j: rows j+1..k-1)
+//     X  [4kq, 5kq)       eigenvectors of the tridiagonal T (column i at i k)
+//     HA [5kq, 5kq + 4k)  alpha_j of the reflectors
+//     DD, EE, LAM, HB     4 arrays of k: diagonal, off-diagonal, eigenvalues
+//                         (ascending), reflector betas
+//     CQ [.., + 4k)       diagonal unitary scaling delta_r (quaternions)
+//     TN                  ||T|| (max row sum)
+struct PsvdLayout {
+  double *U, *B, *UB, *HV, *X, *HA, *DD, *EE, *LAM, *HB, *CQ, *TN;
+  __host__ __device__ PsvdLayout(double *work, int k) {
+    const int64_t kq = (int64_t)k * k;
+    U = work; B = work + 4 * kq; UB = work + 12 * kq;
+    double *e = work + 20 * kq;
+    HV = e; X = e + 4 * kq; HA = e + 5 * kq;
+    DD = HA + 4 * k; EE = DD + k; LAM = EE + k; HB = LAM + k; CQ = HB + k; TN = CQ + 4 * k;
+  }
+};
 
 // pseudo-SVD (Alg. 3) with Y = Q_Y R_Y, Q_Y orthonormal: the complex SVD of
 // chi_Y is chi_{Q_Y} times that of chi_{R_Y}, whose left singular vectors
@@ -1163,12 +1198,14 @@ __device__ __forceinline__ void sm_heev(double *g, int k, double *lam, double *U
 // 2^-53).  Bad part: B = [u_b..., -u_b j ...] (the two members of each bad
 // pair), B diag(f) with f from Philox stream 3, Jacobi SVD, one column per
 // pair of the leading 2t.  Output C (k x k): H = Q_Y C = [H_g, H_b~].
-__global__ __launch_bounds__(1024) void psvd_select_kernel(PsvdArgs args, GroupRef grp) {
+// (Last kernel of the pipeline: the eigenvectors are in U, the eigenvalues
+// in LAM.)
+__global__ __launch_bounds__(1024) void psvd_finish_kernel(PsvdArgs args, GroupRef grp) {
   PsvdArgs A;
   int bx, by, bz;
   if (!group_select(args, grp, A, bx, by, bz)) return;
   const int k = A.k;
-  double *gl = A.gl, *c = A.c, *work = A.work;
+  double *c = A.c, *work = A.work;
   const uint32_t k0 = A.k0, k1 = A.k1;
   SmallStatus *status = A.status;
   __shared__ int order[512];
@@ -1176,10 +1213,10 @@ __global__ __launch_bounds__(1024) void psvd_select_kernel(PsvdArgs args, GroupR
   __shared__ double lam[256];
   __shared__ int good[256];
   __shared__ int n_good, n_bad;
-  __shared__ double pool[TRI_POOL];
-  const int64_t kk = (int64_t)k * k * 4;
-  double *U = work, *B = work + kk, *UB = work + 3 * kk, *EW = work + 5 * kk;
-  sm_heev(gl, k, lam, U, EW, pool);
+  const PsvdLayout L(work, k);
+  double *U = L.U, *B = L.B, *UB = L.UB;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) lam[i] = gp(L.LAM)[i];
+  __syncthreads();
   // descending order of sigma = sqrt(max(lambda, 0))
   for (int i = threadIdx.x; i < k; i += blockDim.x) sig[i] = sqrt(fmax(lam[k - 1 - i], 0.0));
   __syncthreads();
@@ -1240,18 +1277,6 @@ __global__ __launch_bounds__(1024) void psvd_select_kernel(PsvdArgs args, GroupR
   }
 }
 
-hipError_t launch_psvd_k(hipStream_t st, const PsvdArgs &a, GroupRef g, int count) {
-  hipLaunchKernelGGL(psvd_select_kernel, dim3(g.tab ? count : 1), dim3(1024), 0, st, a, g);
-  return hipGetLastError();
-}
-
-hipError_t launch_psvd_select(hipStream_t st, int k, double *gl, uint32_t k0, uint32_t k1,
-                              double *c, double *work, SmallStatus *status) {
-  PsvdArgs a{};
-  a.k = k; a.gl = gl; a.k0 = k0; a.k1 = k1; a.c = c; a.work = work; a.status = status;
-  a.gx = 1; a.gy = 1;
-  return launch_psvd_k(st, a, GroupRef{}, 1);
-}
 
 // Minimum-norm least squares for a rank-deficient P (l x k, planar):
 // one-sided Jacobi on [P; I] (inner products over the P rows only) gives
@@ -1564,64 +1589,6 @@ __device__ void sm_bisect_all(const double *d, const double *e, int k, double *l
   sm_bisect_sel(d, e, k, nullptr, k, lam);
 }
 
-// Eigenvector of the real symmetric tridiagonal (d, e) for eigenvalue lam by
-// inverse iteration (three solves with the partial-pivoting LU of T - lam I)
-// from a pseudo-random start (Philox, fixed key, counter (seq, j)) so that
-// equal or nearly equal eigenvalues still give independent vectors; x and the
-// five LU arrays are private global slices of length k.
-__device__ void inverse_iteration(const double *d, const double *e, int k, double lam, double tnorm,
-                                  uint32_t seq, double *x_, double *dl_, double *dd_, double *du_,
-                                  double *du2_, double *pv_) {
-  QSK_GLOBAL double *x = gpw(x_), *dl = gpw(dl_), *dd = gpw(dd_), *du = gpw(du_), *du2 = gpw(du2_),
-                    *pv = gpw(pv_);
-  const double tiny = 0x1p-52 * tnorm + 1e-300;
-  for (int j = 0; j < k; ++j) {
-    const u32x4 r = philox(seq, (uint32_t)j, 0x51u, 0u, 0x2545F491u, 0x9E3779B9u);
-    x[j] = ((double)r.x0 + 0.5) * 0x1p-31 - 1.0;
-  }
-  for (int j = 0; j < k; ++j) {
-    dd[j] = d[j] - lam;
-    if (j + 1 < k) { dl[j] = e[j]; du[j] = e[j]; }
-    du2[j] = 0.0;
-    pv[j] = 0.0;
-  }
-  for (int j = 0; j + 1 < k; ++j) {
-    if (fabs(dd[j]) >= fabs(dl[j])) {
-      if (dd[j] == 0.0) dd[j] = tiny;
-      const double f = dl[j] / dd[j];
-      dl[j] = f;
-      dd[j + 1] -= f * du[j];
-    } else {
-      const double f = dd[j] / dl[j];
-      dd[j] = dl[j];
-      dl[j] = f;
-      const double t = du[j];
-      du[j] = dd[j + 1];
-      dd[j + 1] = t - f * dd[j + 1];
-      if (j + 2 < k) {
-        du2[j] = du[j + 1];
-        du[j + 1] = -f * du[j + 1];
-      }
-      pv[j] = 1.0;
-    }
-  }
-  if (dd[k - 1] == 0.0) dd[k - 1] = tiny;
-  for (int it = 0; it < 3; ++it) {
-    for (int j = 0; j + 1 < k; ++j) {
-      if (pv[j] != 0.0) { const double t = x[j]; x[j] = x[j + 1]; x[j + 1] = t; }
-      x[j + 1] -= dl[j] * x[j];
-    }
-    x[k - 1] /= dd[k - 1];
-    if (k > 1) x[k - 2] = (x[k - 2] - du[k - 2] * x[k - 1]) / dd[k - 2];
-    for (int j = k - 3; j >= 0; --j) x[j] = (x[j] - du[j] * x[j + 1] - du2[j] * x[j + 2]) / dd[j];
-    double nrm = 0.0;
-    for (int j = 0; j < k; ++j) nrm += x[j] * x[j];
-    nrm = sqrt(nrm);
-    if (!(nrm > 0.0) || !isfinite(nrm)) { for (int j = 0; j < k; ++j) x[j] = (j == 0); nrm = 1.0; }
-    for (int j = 0; j < k; ++j) x[j] /= nrm;
-  }
-}
-
 // Classical Gram-Schmidt, twice, over the c vectors xs[0..c) (length k,
 // stride k; LDS or global), in order: each vector loses its components along
 // the earlier ones and is normalised.
@@ -1659,44 +1626,159 @@ __device__ __forceinline__ void cgs2_block(P xs, int k, int c, double *coef, dou
   }
 }
 
-// Full eigendecomposition of a k x k quaternion Hermitian matrix (destroyed):
-// tridiagonalisation, bisection, inverse iteration with classical Gram-Schmidt
-// (twice) inside clusters of eigenvalues closer than 1e-3 ||T||, and the
-// back-transformation through the diagonal unitary scaling and the
-// Householder reflectors.  Eigenvectors into U (k x k AoS), eigenvalues
-// ascending into lam.  work holds >= 12 k^2 + 8 k doubles; pool is TRI_POOL
-// doubles of LDS.
-__device__ __forceinline__ void sm_heev(double *g, int k, double *lam, double *U, double *work, double *pool) {
-  __shared__ double dd[256], ee[256], hb[256];
-  __shared__ double s_tn, s_nrm;
-  __shared__ double coef[256];
-  const int tid = threadIdx.x;
-  const int64_t kk = (int64_t)k * k;
-  double *HV = work;                 // 4 kk
-  double *X = work + 4 * kk;         // kk (real eigenvectors of T)
-  double *LU = work + 5 * kk;        // 5 kk
-  double *HA = work + 10 * kk;       // 4 k (alpha_j)
-  sm_tridiag(g, k, dd, ee, pool, HV, hb, HA);
+// Full eigendecomposition of the k x k quaternion Hermitian G_L for the
+// pseudo-SVD, as a pipeline of kernels (state in the PsvdLayout arrays):
+//   psvd_eig_kernel      tridiagonalisation and all eigenvalues (bisection),
+//                        one workgroup;
+//   psvd_invit_kernel    eigenvectors of T by inverse iteration, eight per
+//                        workgroup, each lane with its LU factors in LDS;
+//   psvd_orth_kernel     Gram-Schmidt twice inside clusters of eigenvalues
+//                        closer than 1e-3 ||T|| and the diagonal unitary
+//                        scaling, one workgroup;
+//   psvd_bt_kernel       back-transformation through the Householder
+//                        reflectors, one wave per column, four columns per
+//                        workgroup;
+//   psvd_finish_kernel   pair rule and bad-pair repair (above).
+__global__ __launch_bounds__(1024) void psvd_eig_kernel(PsvdArgs args, GroupRef grp) {
+  PsvdArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const int k = A.k;
+  const PsvdLayout L(A.work, k);
+  __shared__ double dd[256], ee[256], hb[256], lam[256];
+  __shared__ double pool[TRI_POOL];
+  sm_tridiag(A.gl, k, dd, ee, pool, L.HV, hb, L.HA);
   sm_bisect_all(dd, ee, k, lam);
+  const int tid = threadIdx.x;
   if (tid == 0) {
     double tn = 0.0;
     for (int i = 0; i < k; ++i) tn = fmax(tn, fabs(dd[i]) + (i > 0 ? ee[i - 1] : 0.0) + (i + 1 < k ? ee[i] : 0.0));
-    s_tn = tn;
+    gpw(L.TN)[0] = tn;
   }
-  __syncthreads();
   for (int i = tid; i < k; i += blockDim.x) {
-    double *b = LU + (int64_t)i * 5 * k;
-    inverse_iteration(dd, ee, k, lam[i], s_tn, (uint32_t)i, X + (int64_t)i * k, b, b + k, b + 2 * k,
-                      b + 3 * k, b + 4 * k);
+    gpw(L.DD)[i] = dd[i];
+    gpw(L.EE)[i] = ee[i];
+    gpw(L.LAM)[i] = lam[i];
+    gpw(L.HB)[i] = hb[i];
   }
+}
+
+// Eigenvector of the real symmetric tridiagonal (d, e) for eigenvalue lam:
+// three solves with the partial-pivoting LU of T - lam I from a
+// pseudo-random start (Philox, fixed key, counter (seq, j)), so that equal or
+// nearly equal eigenvalues still give independent vectors.  The LU factors
+// and x are private LDS arrays of length k; the pivots' reciprocals are
+// formed once.
+__device__ void invit_lds(const QSK_LDS double *d, const QSK_LDS double *e, int k, double lam, double tnorm,
+                          uint32_t seq, QSK_LDS double *x, QSK_LDS double *dl, QSK_LDS double *dd,
+                          QSK_LDS double *du, QSK_LDS double *du2, QSK_LDS double *pv) {
+  const double tiny = 0x1p-52 * tnorm + 1e-300;
+  for (int j = 0; j < k; ++j) {
+    const u32x4 r = philox(seq, (uint32_t)j, 0x51u, 0u, 0x2545F491u, 0x9E3779B9u);
+    x[j] = ((double)r.x0 + 0.5) * 0x1p-31 - 1.0;
+  }
+  for (int j = 0; j < k; ++j) {
+    dd[j] = d[j] - lam;
+    if (j + 1 < k) { dl[j] = e[j]; du[j] = e[j]; }
+    du2[j] = 0.0;
+    pv[j] = 0.0;
+  }
+  double dj = dd[0];
+  for (int j = 0; j + 1 < k; ++j) {
+    const double lj = dl[j], uj = du[j], dn = dd[j + 1];
+    if (fabs(dj) >= fabs(lj)) {
+      if (dj == 0.0) dj = tiny;
+      const double f = lj / dj;
+      dd[j] = dj;
+      dl[j] = f;
+      dj = dn - f * uj;
+    } else {
+      const double f = dj / lj;
+      dd[j] = lj;
+      dl[j] = f;
+      du[j] = dn;
+      dj = uj - f * dn;
+      if (j + 2 < k) {
+        const double u1 = du[j + 1];
+        du2[j] = u1;
+        du[j + 1] = -f * u1;
+      }
+      pv[j] = 1.0;
+    }
+  }
+  if (dj == 0.0) dj = tiny;
+  dd[k - 1] = dj;
+  for (int j = 0; j < k; ++j) dd[j] = 1.0 / dd[j];        // reciprocals of the pivots
+  for (int it = 0; it < 3; ++it) {
+    double xj = x[0];
+    for (int j = 0; j + 1 < k; ++j) {
+      double xn = x[j + 1];
+      if (pv[j] != 0.0) { const double t = xj; xj = xn; xn = t; }
+      x[j] = xj;
+      xj = xn - dl[j] * xj;
+    }
+    x[k - 1] = xj;
+    double x2 = xj * dd[k - 1];
+    x[k - 1] = x2;
+    double x1 = 0.0;
+    if (k > 1) { x1 = (x[k - 2] - du[k - 2] * x2) * dd[k - 2]; x[k - 2] = x1; }
+    for (int j = k - 3; j >= 0; --j) {
+      const double xv = (x[j] - du[j] * x1 - du2[j] * x2) * dd[j];
+      x[j] = xv;
+      x2 = x1;
+      x1 = xv;
+    }
+    double nrm = 0.0;
+    for (int j = 0; j < k; ++j) nrm += x[j] * x[j];
+    nrm = sqrt(nrm);
+    if (!(nrm > 0.0) || !isfinite(nrm)) { for (int j = 0; j < k; ++j) x[j] = (j == 0); nrm = 1.0; }
+    const double inv = 1.0 / nrm;
+    for (int j = 0; j < k; ++j) x[j] *= inv;
+  }
+}
+
+constexpr int INVIT_EPB = 8;          // eigenvectors per workgroup
+__global__ __launch_bounds__(64) void psvd_invit_kernel(PsvdArgs args, GroupRef grp) {
+  PsvdArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const int k = A.k;
+  const PsvdLayout L(A.work, k);
+  __shared__ double sd[256], se[256];
+  __shared__ double lu[INVIT_EPB][6][258];     // padded: lanes hit different banks
+  const int lane = threadIdx.x;
+  for (int j = lane; j < k; j += 64) { sd[j] = gp(L.DD)[j]; se[j] = gp(L.EE)[j]; }
   __syncthreads();
+  const int i = bx * INVIT_EPB + lane;
+  if (lane < INVIT_EPB && i < k) {
+    QSK_LDS double(*b)[258] = (QSK_LDS double(*)[258])lu[lane];
+    invit_lds((const QSK_LDS double *)sd, (const QSK_LDS double *)se, k, gp(L.LAM)[i], gp(L.TN)[0],
+              (uint32_t)i, b[0], b[1], b[2], b[3], b[4], b[5]);
+    QSK_GLOBAL double *xo = gpw(L.X) + (int64_t)i * k;
+    for (int j = 0; j < k; ++j) xo[j] = b[0][j];
+  }
+}
+
+__global__ __launch_bounds__(1024) void psvd_orth_kernel(PsvdArgs args, GroupRef grp) {
+  PsvdArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const int k = A.k;
+  const PsvdLayout L(A.work, k);
+  __shared__ double lam[256], coef[256];
+  __shared__ double s_nrm;
+  __shared__ double pool[TRI_POOL];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < k; i += blockDim.x) lam[i] = gp(L.LAM)[i];
+  __syncthreads();
+  const double tn = gp(L.TN)[0];
   // re-orthogonalise within clusters (ascending order), in LDS when they fit
   for (int c0 = 0; c0 < k;) {
     int c1 = c0 + 1;
-    while (c1 < k && lam[c1] - lam[c1 - 1] <= 1e-3 * s_tn) ++c1;
+    while (c1 < k && lam[c1] - lam[c1 - 1] <= 1e-3 * tn) ++c1;
     const int c = c1 - c0;
     if (c > 1) {
-      QSK_GLOBAL double *xg = gpw(X) + (int64_t)c0 * k;
+      QSK_GLOBAL double *xg = gpw(L.X) + (int64_t)c0 * k;
       if ((int64_t)c * k <= TRI_POOL) {
         QSK_LDS double *xs = (QSK_LDS double *)pool;
         for (int q = tid; q < c * k; q += blockDim.x) xs[q] = xg[q];
@@ -1710,50 +1792,112 @@ __device__ __forceinline__ void sm_heev(double *g, int k, double *lam, double *U
     }
     c0 = c1;
   }
-  qd *coefq = (qd *)pool;            // k diagonal scalings (pool is free again)
-  // back-transform: y = D x (delta_0 = 1, delta_{j+1} = alpha_j delta_j / |alpha_j|),
-  // then u = H_0 H_1 ... H_{k-2} y.  The reflectors go to all k columns at
-  // once: a group of G lanes (one wave) owns column i, lane r owns the rows
-  // congruent to r mod G, so a column's rows never change hands and only the
-  // inner product v^* y crosses lanes (shuffles).
+  // diagonal unitary scaling: delta_0 = 1, delta_{j+1} = alpha_j delta_j / |alpha_j|
   if (tid == 0) {
     qd delta = {1.0, 0.0, 0.0, 0.0};
-    coefq[0] = delta;
+    QSK_GLOBAL double *cq = gpw(L.CQ);
+    cq[0] = 1.0; cq[1] = 0.0; cq[2] = 0.0; cq[3] = 0.0;
     for (int j = 0; j + 1 < k; ++j) {
-      const qd al = {HA[4 * j], HA[4 * j + 1], HA[4 * j + 2], HA[4 * j + 3]};
+      const qd al = {gp(L.HA)[4 * j], gp(L.HA)[4 * j + 1], gp(L.HA)[4 * j + 2], gp(L.HA)[4 * j + 3]};
       const double aa = sqrt(qnorm2(al));
       if (aa > 0.0) delta = qmul(qscale(al, 1.0 / aa), delta);
-      coefq[j + 1] = delta;
+      cq[4 * (j + 1)] = delta.w; cq[4 * (j + 1) + 1] = delta.x;
+      cq[4 * (j + 1) + 2] = delta.y; cq[4 * (j + 1) + 3] = delta.z;
     }
   }
-  __syncthreads();
-  for (int q = tid; q < k * k; q += blockDim.x) {
-    const int r = q % k, i = q / k;
-    sq_(U, r, i, k, qscale(coefq[r], gp(X)[(int64_t)i * k + r]));
-  }
-  __syncthreads();
-  int G = 64;
-  while (G > 1 && G * k > (int)blockDim.x) G >>= 1;
-  const int col = tid / G, sub = tid % G;
-  if (col < k) {
-    for (int j = k - 2; j >= 0; --j) {
-      const double beta = hb[j];
-      if (beta == 0.0) continue;                 // wave-uniform
-      qd s = qzero();
-      for (int r = j + 1 + ((sub - (j + 1)) % G + G) % G; r < k; r += G)
-        qfma_cj(s, gq(HV, r - j - 1, j, k), gq(U, r, col, k));
-      for (int off = 1; off < G; off <<= 1) {
-        s.w += __shfl_xor(s.w, off, 64);
-        s.x += __shfl_xor(s.x, off, 64);
-        s.y += __shfl_xor(s.y, off, 64);
-        s.z += __shfl_xor(s.z, off, 64);
-      }
-      s = qscale(s, beta);
-      for (int r = j + 1 + ((sub - (j + 1)) % G + G) % G; r < k; r += G)
-        sq_(U, r, col, k, qsub(gq(U, r, col, k), qmul(gq(HV, r - j - 1, j, k), s)));
+}
+
+// u = H_0 H_1 ... H_{k-2} D x for each column: lane r of the column's wave
+// owns rows r, r + 64, ... (in registers); only the inner products v^* u
+// cross lanes.  The reflector of the next step is loaded while this one is
+// applied.
+constexpr int BT_COLS = 4;             // columns (waves) per workgroup
+__global__ __launch_bounds__(64 * BT_COLS) void psvd_bt_kernel(PsvdArgs args, GroupRef grp) {
+  PsvdArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const int k = A.k;
+  const PsvdLayout L(A.work, k);
+  const int lane = threadIdx.x & 63;
+  const int col = bx * BT_COLS + (threadIdx.x >> 6);
+  if (col >= k) return;                         // whole wave
+  constexpr int R = 4;                          // rows per lane (k <= 256)
+  qd u[R];
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int r = lane + 64 * t;
+    u[t] = qzero();
+    if (r < k) {
+      const QSK_GLOBAL double *cq = gp(L.CQ) + 4 * r;
+      u[t] = qscale(qd{cq[0], cq[1], cq[2], cq[3]}, gp(L.X)[(int64_t)col * k + r]);
     }
   }
-  __syncthreads();
+  qd vn[R];
+  double bn = 0.0;
+#define QSK_BT_LOAD(J)                                                               \
+  do {                                                                               \
+    bn = (J) >= 0 ? gp(L.HB)[(J)] : 0.0;                                             \
+    _Pragma("unroll") for (int t = 0; t < R; ++t) {                                  \
+      const int r = lane + 64 * t;                                                   \
+      vn[t] = ((J) >= 0 && r > (J) && r < k) ? gq(L.HV, r - (J) - 1, (J), k) : qzero(); \
+    }                                                                                \
+  } while (0)
+  QSK_BT_LOAD(k - 2);
+  for (int j = k - 2; j >= 0; --j) {
+    qd v[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) v[t] = vn[t];
+    const double beta = bn;
+    QSK_BT_LOAD(j - 1);
+    if (beta == 0.0) continue;                  // uniform
+    qd s = qzero();
+#pragma unroll
+    for (int t = 0; t < R; ++t) qfma_cj(s, v[t], u[t]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s.w += __shfl_xor(s.w, off, 64);
+      s.x += __shfl_xor(s.x, off, 64);
+      s.y += __shfl_xor(s.y, off, 64);
+      s.z += __shfl_xor(s.z, off, 64);
+    }
+    s = qscale(s, beta);
+#pragma unroll
+    for (int t = 0; t < R; ++t) u[t] = qsub(u[t], qmul(v[t], s));
+  }
+#undef QSK_BT_LOAD
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int r = lane + 64 * t;
+    if (r < k) sq_(L.U, r, col, k, u[t]);
+  }
+}
+
+static int psvd_invit_blocks(int k) { return (k + INVIT_EPB - 1) / INVIT_EPB; }
+static int psvd_bt_blocks(int k) { return (k + BT_COLS - 1) / BT_COLS; }
+int psvd_blocks(int k, int stage) { return stage == 1 ? psvd_invit_blocks(k) : stage == 3 ? psvd_bt_blocks(k) : 1; }
+
+hipError_t launch_psvd_stage(hipStream_t st, int stage, const PsvdArgs &a, GroupRef g, int64_t blocks) {
+  const dim3 grid((unsigned)(g.tab ? blocks : psvd_blocks(a.k, stage)));
+  switch (stage) {
+    case 0: hipLaunchKernelGGL(psvd_eig_kernel, grid, dim3(1024), 0, st, a, g); break;
+    case 1: hipLaunchKernelGGL(psvd_invit_kernel, grid, dim3(64), 0, st, a, g); break;
+    case 2: hipLaunchKernelGGL(psvd_orth_kernel, grid, dim3(1024), 0, st, a, g); break;
+    case 3: hipLaunchKernelGGL(psvd_bt_kernel, grid, dim3(64 * BT_COLS), 0, st, a, g); break;
+    default: hipLaunchKernelGGL(psvd_finish_kernel, grid, dim3(1024), 0, st, a, g); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_psvd_select(hipStream_t st, int k, double *gl, uint32_t k0, uint32_t k1,
+                              double *c, double *work, SmallStatus *status) {
+  for (int stage = 0; stage < 5; ++stage) {
+    PsvdArgs a{};
+    a.k = k; a.gl = gl; a.k0 = k0; a.k1 = k1; a.c = c; a.work = work; a.status = status;
+    a.gx = psvd_blocks(k, stage); a.gy = 1;
+    const hipError_t e = launch_psvd_stage(st, stage, a, GroupRef{}, 0);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // kappa of H from its Gram G_H = H^* H: the eigenvalues of G_H are the

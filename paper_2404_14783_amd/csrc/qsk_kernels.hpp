@@ -125,7 +125,7 @@ struct SmallStatus {
   double kappa_initial;
   double orth_defect;
   int good_count;
-  int pad;
+  int fail_any;        // sticky: some Cholesky since the last full reset failed
 };
 
 // ---------------------------------------------------------------------------
@@ -253,13 +253,19 @@ hipError_t launch_error_k(hipStream_t st, int tin, const ErrorArgs &a, GroupRef 
 // by launch_triinv_k.
 hipError_t launch_cholinv_reg_k(hipStream_t st, const CholArgs &a, GroupRef g, int count, int kmax);
 int cholinv_reg_max_k();
+// Zero a status; keep_fail_any = 1 leaves the sticky fail_any as it is.
+hipError_t launch_status_reset(hipStream_t st, SmallStatus *s, int keep_fail_any);
 hipError_t launch_chol_k(hipStream_t st, const CholArgs &a, GroupRef g, int count);
 hipError_t launch_triinv_k(hipStream_t st, const CholArgs &a, GroupRef g, int64_t blocks);
 hipError_t launch_gemm_k(hipStream_t st, const GemmArgs &a, GroupRef g, int64_t blocks);
 hipError_t launch_power_k(hipStream_t st, const PowerArgs &a, GroupRef g, int count);
 hipError_t launch_identity_k(hipStream_t st, const GemmArgs &a, GroupRef g, int count);
 hipError_t launch_copy_small_k(hipStream_t st, const GemmArgs &a, GroupRef g, int count);
-hipError_t launch_psvd_k(hipStream_t st, const PsvdArgs &a, GroupRef g, int count);
+// The pseudo-SVD pipeline: stage 0 eigenvalues, 1 inverse iteration, 2
+// re-orthogonalisation, 3 back-transformation, 4 selection; stage s uses
+// psvd_blocks(k, s) workgroups per problem (the args' gx).
+int psvd_blocks(int k, int stage);
+hipError_t launch_psvd_stage(hipStream_t st, int stage, const PsvdArgs &a, GroupRef g, int64_t blocks);
 hipError_t launch_pinv_k(hipStream_t st, const PinvArgs &a, GroupRef g, int count);
 hipError_t launch_kappa_k(hipStream_t st, const KappaArgs &a, GroupRef g, int count);
 

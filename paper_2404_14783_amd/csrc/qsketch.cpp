@@ -396,8 +396,14 @@ qsk_status qsketch_sketches(qsk_ctx *ctx, double *const Y[4], int64_t ldy, doubl
   return QSK_OK;
 }
 
-qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4], int64_t ldq,
-                            double *const X[4], int64_t ldx, qsk_report *report) {
+// One QB stage.  optimistic: no host synchronisation after the Cholesky
+// factorisations (every one is assumed to succeed); a failure anywhere is
+// recorded in the status's sticky fail_any and the call returns
+// QSK_RETRY_CAREFUL, after which the caller runs the careful version, which
+// checks each factorisation and takes the fallbacks.
+static const qsk_status QSK_RETRY_CAREFUL = static_cast<qsk_status>(-1);
+static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4], int64_t ldq,
+                                double *const X[4], int64_t ldx, qsk_report *report, bool opt) {
   if (!ctx) return QSK_E_ARG;
   if (ctx->poisoned) return QSK_E_STATE;
   const qsk_config &c = ctx->cfg;
@@ -416,6 +422,7 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
   int flags = 0;
 
   HIPCHK(ctx, fold_y(ctx));
+  if (opt) HIPCHK(ctx, qsk::launch_status_reset(st, ctx->status, 0));
   const void *yp[4];
   for (int p = 0; p < 4; ++p) yp[p] = (const char *)ctx->y + (size_t)p * m * k * ctx->ts;
 
@@ -436,8 +443,10 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
                                       ctx->partial_elems, gz));
     HIPCHK(ctx, qsk::launch_chol_inv(st, gz, k, complex_only, 0.0, 1e-13, slot(ctx, S_R),
                                      slot(ctx, S_T), ctx->status));
-    HIPCHK(ctx, hipMemcpyAsync(&hs, ctx->status, sizeof(hs), hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipStreamSynchronize(st));
+    if (!opt) {
+      HIPCHK(ctx, hipMemcpyAsync(&hs, ctx->status, sizeof(hs), hipMemcpyDeviceToHost, st));
+      HIPCHK(ctx, hipStreamSynchronize(st));
+    }
     ++passes;
     if (hs.fail) {
       if (!(hs.trace > 0.0) || !std::isfinite(hs.trace)) {
@@ -470,8 +479,13 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
     tz = 0;
     gz = slot(ctx, S_GU);
   }
-  // Now H0 (pseudo-QR) or Q_Y (pseudo-SVD) = Z T with G_Z = gz.
-  HIPCHK(ctx, hipMemsetAsync(ctx->status, 0, sizeof(SmallStatus), st));
+  // Now H0 (pseudo-QR) or Q_Y (pseudo-SVD) = Z T with G_Z = gz.  (The
+  // optimistic run keeps the sticky failure flag of the passes above.)
+  if (opt) {
+    HIPCHK(ctx, qsk::launch_status_reset(st, ctx->status, 1));
+  } else {
+    HIPCHK(ctx, hipMemsetAsync(ctx->status, 0, sizeof(SmallStatus), st));
+  }
   HIPCHK(ctx, hipMemsetAsync(ctx->kstatus, 0, sizeof(SmallStatus), st));
   if (rf == QSK_PSEUDO_QR) {
     // G0 = H0^* H0 = T^* G_Z T; kappa of the raw factor
@@ -490,8 +504,10 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
       HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_G0), k, 0, 0.0, 1e-13, slot(ctx, S_CR),
                                        slot(ctx, S_CT), ctx->status));
       int fail = 0;
-      HIPCHK(ctx, hipMemcpyAsync(&fail, &ctx->status->fail, sizeof(int), hipMemcpyDeviceToHost, st));
-      HIPCHK(ctx, hipStreamSynchronize(st));
+      if (!opt) {
+        HIPCHK(ctx, hipMemcpyAsync(&fail, &ctx->status->fail, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+      }
       if (fail) {
         flags |= QSK_FLAG_RANK_DEFICIENT;      // G_j singular: no further correction
         break;
@@ -535,10 +551,6 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
                                     m, Q, ldq, k, ctx->partials, ctx->partial_elems, pp, l,
                                     ctx->stage.psi, psi_st_type, ctx->stage.MP,
                                     (int64_t)ctx->stage.LP * ctx->stage.MP));
-  SmallStatus hs2{};
-  HIPCHK(ctx, hipMemcpyAsync(&hs2, ctx->status, sizeof(hs2), hipMemcpyDeviceToHost, st));
-  HIPCHK(ctx, hipStreamSynchronize(st));
-  flags |= hs2.flags;
   SmallStatus ps{};
   SmallStatus *pst = (SmallStatus *)ctx->work;   // not used concurrently with drivers
   (void)pst;
@@ -546,8 +558,10 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
                                     l, k, k, ctx->partials, ctx->partial_elems, slot(ctx, S_GP)));
   HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GP), k, 0, 0.0, 1e-13, slot(ctx, S_RP),
                                    slot(ctx, S_TP1), ctx->status));
-  HIPCHK(ctx, hipMemcpyAsync(&ps, ctx->status, sizeof(ps), hipMemcpyDeviceToHost, st));
-  HIPCHK(ctx, hipStreamSynchronize(st));
+  if (!opt) {
+    HIPCHK(ctx, hipMemcpyAsync(&ps, ctx->status, sizeof(ps), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+  }
   bool have_sstar = false;
   if (ps.fail) {
     // (Psi Q)^*(Psi Q) singular: minimum-norm least squares through a Jacobi
@@ -562,8 +576,10 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
                                       l, l, k, k, ctx->partials, ctx->partial_elems, slot(ctx, S_GP)));
     HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GP), k, 0, 0.0, 1e-13, slot(ctx, S_RP),
                                      slot(ctx, S_TP2), ctx->status));
-    HIPCHK(ctx, hipMemcpyAsync(&ps, ctx->status, sizeof(ps), hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipStreamSynchronize(st));
+    if (!opt) {
+      HIPCHK(ctx, hipMemcpyAsync(&ps, ctx->status, sizeof(ps), hipMemcpyDeviceToHost, st));
+      HIPCHK(ctx, hipStreamSynchronize(st));
+    }
     if (ps.fail) {
       flags |= QSK_FLAG_RANK_DEFICIENT;
       HIPCHK(ctx, qsk::launch_pinv_sstar(st, l, k, pp, l, 1e-13, ctx->pinv_work, sp, l));
@@ -583,9 +599,12 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
 
   // join the side stream (kappa estimates) before reading its results
   HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_join, 0));
-  SmallStatus ks{};
+  SmallStatus ks{}, hs2{};
   HIPCHK(ctx, hipMemcpyAsync(&ks, ctx->kstatus, sizeof(ks), hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipMemcpyAsync(&hs2, ctx->status, sizeof(hs2), hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipStreamSynchronize(st));
+  if (opt && hs2.fail_any) return QSK_RETRY_CAREFUL;
+  flags |= hs2.flags;
   if (report) {
     qsk_report r{};
     r.kappa = ks.kappa;
@@ -601,6 +620,13 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
   }
   HIPCHK(ctx, hipStreamSynchronize(st));
   return QSK_OK;
+}
+
+qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4], int64_t ldq,
+                            double *const X[4], int64_t ldx, qsk_report *report) {
+  const qsk_status r = finalize_impl(ctx, rf, Q, ldq, X, ldx, report, true);
+  if (r != QSK_RETRY_CAREFUL) return r;
+  return finalize_impl(ctx, rf, Q, ldq, X, ldx, report, false);
 }
 
 qsk_status qsketch_rel_error(qsk_ctx *ctx, const void *const A[4], int64_t lda, double *const Q[4],
