@@ -161,15 +161,8 @@ qsk_status chol_all(qsk_batch *b, const std::vector<int> &ids, FG fg, int comple
     a[i].only_failed = only_failed; a[i].gx = q.k; a[i].gy = 1;
     kb[i] = q.k;
   }
-  int64_t kmax = 0;
-  for (int64_t kk : kb) kmax = std::max(kmax, kk);
   GroupRef g1, g2;
   int64_t t1, t2;
-  if (kmax <= qsk::cholinv_reg_max_k()) {
-    if (!push_group(b, a, one, &g1, &t1)) return arena_full(b);
-    BCHK(b, qsk::launch_cholinv_reg_k(b->stream, a[0], g1, (int)ids.size(), (int)kmax));
-    return QSK_OK;
-  }
   if (!push_group(b, a, one, &g1, &t1) || !push_group(b, a, kb, &g2, &t2)) return arena_full(b);
   BCHK(b, qsk::launch_chol_k(b->stream, a[0], g1, (int)ids.size()));
   BCHK(b, qsk::launch_triinv_k(b->stream, a[0], g2, t2));

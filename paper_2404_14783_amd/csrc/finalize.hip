@@ -780,166 +780,6 @@ __global__ __launch_bounds__(1024) void chol_kernel(CholArgs args, GroupRef grp)
   }
 }
 
-// Cholesky G' = R^* R and T = R^{-1} with the matrix in registers, for k <=
-// CHOL_REG_K.  The 1024 threads own the upper-triangle positions (i, j),
-// i <= j, taken row by row from the last row up (row k-1, then row k-2
-// left to right, ...), position e to thread e mod 1024 (at most E each), so
-// the rows still being updated are always a prefix: whole waves drop out as
-// the factorisation proceeds.  Every step is one barrier.
-//   Cholesky, pivot p: the owners of row p publish G[p][j] (unscaled); the
-//   owner of G[p][p] publishes sqrt(d), 1/sqrt(d), 1/d; then
-//   G[i][j] -= conj(G[p][i]) G[p][j] / d for p < i <= j, and row p becomes
-//   R[p][j] = G[p][j] / sqrt(d), R[p][p] = sqrt(d).
-//   Inverse, a = k-1 .. 0 (rows of R T = I from the bottom): the owners of
-//   row a finish T[a][c] = (delta_ac - acc[a][c]) / R[a][a] and publish it,
-//   the owners of column a publish R[b][a] (b < a), whose register then
-//   starts the accumulator acc[b][a]; then acc[b][c] += R[b][a] T[a][c] for
-//   b < a <= c.
-// G' is G with the j-parts dropped when complex_only, and the diagonal
-// made real and shifted.  A pivot d <= tol * max diag sets fail; the
-// factorisation stops there (R is then partial and T is not written).
-constexpr int CHOL_REG_K = 128;
-// positions per thread: 5 covers k <= 100 without spills, 9 covers k <= 128
-template <int E> constexpr int chol_reg_k() { return E == 5 ? 100 : CHOL_REG_K; }
-
-template <int E>
-__global__ __launch_bounds__(1024) void cholinv_reg_kernel(CholArgs args, GroupRef grp) {
-  CholArgs A;
-  int bx, by, bz;
-  if (!group_select(args, grp, A, bx, by, bz)) return;
-  const double *g = A.g;
-  const int k = A.k, complex_only = A.complex_only;
-  const double shift = A.shift, tol = A.tol;
-  double *r = A.r, *t = A.t;
-  SmallStatus *status = A.status;
-  if (A.only_failed && !status->fail) return;
-  __shared__ qd row[2][CHOL_REG_K];
-  __shared__ qd col[2][CHOL_REG_K];
-  __shared__ double s_sc[2][4];            // sqrt(d), 1/sqrt(d), 1/d, fail
-  __shared__ double s_ri[CHOL_REG_K];      // 1 / R[i][i]
-  __shared__ double s_red[3][16];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int npos = k * (k + 1) / 2;
-  int ij[E];                               // i | j << 16, or -1
-  qd v[E];
-#define QSK_I(u) (ij[u] & 0xFFFF)
-#define QSK_J(u) (ij[u] >> 16)
-  double dmax = 0.0, dsum = 0.0;
-#pragma unroll
-  for (int u = 0; u < E; ++u) {
-    const int e = tid + 1024 * u;
-    ij[u] = -1;
-    v[u] = qzero();
-    if (e < npos) {
-      // rows k-1 .. i hold (k - i)(k - i + 1) / 2 positions
-      int h = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);   // full rows before e: rows k-1 .. k-h
-      while (h * (h + 1) / 2 > e) --h;
-      while ((h + 1) * (h + 2) / 2 <= e) ++h;
-      const int i = k - 1 - h, j = i + (e - h * (h + 1) / 2);
-      ij[u] = i | (j << 16);
-      qd x = gq(g, i, j, k);
-      if (complex_only) { x.y = 0.0; x.z = 0.0; }
-      if (i == j) { x = {x.w + shift, 0.0, 0.0, 0.0}; dmax = fmax(dmax, x.w); dsum += x.w; }
-      v[u] = x;
-    }
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
-    dsum += __shfl_xor(dsum, off, 64);
-  }
-  if (lane == 0) { s_red[0][wave] = dmax; s_red[1][wave] = dsum; }
-  __syncthreads();
-  double maxd = 0.0, trace = 0.0;
-  for (int q = 0; q < 16; ++q) { maxd = fmax(maxd, s_red[0][q]); trace += s_red[1][q]; }
-  const double dtol = tol * maxd;
-  double dmin = maxd;
-  int fail = 0;
-  for (int pv = 0; pv < k; ++pv) {
-    const int b = pv & 1;
-#pragma unroll
-    for (int u = 0; u < E; ++u) {
-      if (QSK_I(u) == pv) {
-        if (QSK_J(u) == pv) {
-          const double d = v[u].w;
-          const double sd = sqrt(d), is = 1.0 / sd;
-          s_sc[b][0] = sd; s_sc[b][1] = is; s_sc[b][2] = is * is;
-          s_sc[b][3] = (maxd > 0.0 && d > dtol) ? 0.0 : 1.0;
-          dmin = fmin(dmin, d);
-        } else {
-          row[b][QSK_J(u)] = v[u];
-        }
-      }
-    }
-    __syncthreads();
-    if (s_sc[b][3] != 0.0) { fail = 1; break; }          // uniform: every thread read the same flag
-    const double sd = s_sc[b][0], inv_s = s_sc[b][1], inv_d = s_sc[b][2];
-#pragma unroll
-    for (int u = 0; u < E; ++u) {
-      if (QSK_I(u) == pv) {
-        v[u] = QSK_J(u) == pv ? qd{sd, 0.0, 0.0, 0.0} : qscale(v[u], inv_s);
-      } else if (QSK_I(u) > pv) {
-        v[u] = qsub(v[u], qscale(qmul(qconj(row[b][QSK_I(u)]), row[b][QSK_J(u)]), inv_d));
-      }
-    }
-  }
-  // R (lower part zero)
-#pragma unroll
-  for (int u = 0; u < E; ++u)
-    if (ij[u] >= 0) sq_(r, QSK_I(u), QSK_J(u), k, v[u]);
-  for (int e = tid; e < k * k; e += 1024) {
-    const int i = e % k, j = e / k;
-    if (i > j) sq_(r, i, j, k, qzero());
-  }
-  // the smallest pivot (the diagonal owners saw them all)
-  double dm = dmin;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) dm = fmin(dm, __shfl_xor(dm, off, 64));
-  if (lane == 0) s_red[2][wave] = dm;
-  __syncthreads();
-  if (tid == 0) {
-    double m = maxd;
-    for (int q = 0; q < 16; ++q) m = fmin(m, s_red[2][q]);
-    status->fail = fail;
-    if (fail) status->fail_any = 1;
-    status->min_pivot2 = maxd > 0.0 ? fmin(1.0, m / maxd) : 0.0;
-    status->trace = trace;
-  }
-  if (fail) return;
-#pragma unroll
-  for (int u = 0; u < E; ++u)
-    if (ij[u] >= 0 && QSK_I(u) == QSK_J(u)) s_ri[QSK_I(u)] = 1.0 / v[u].w;
-  __syncthreads();
-  for (int a = k - 1; a >= 0; --a) {
-    const int b = a & 1;
-    const double inv_r = s_ri[a];
-#pragma unroll
-    for (int u = 0; u < E; ++u) {
-      if (QSK_J(u) == a && QSK_I(u) < a) {
-        col[b][QSK_I(u)] = v[u];                        // R[i][a]; its register now accumulates
-        v[u] = qzero();
-      } else if (QSK_I(u) == a) {
-        v[u] = QSK_J(u) == a ? qd{inv_r, 0.0, 0.0, 0.0} : qscale(v[u], -inv_r);
-        row[b][QSK_J(u)] = v[u];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < E; ++u)
-      if (ij[u] >= 0 && QSK_I(u) < a && QSK_J(u) >= a) qfma(v[u], col[b][QSK_I(u)], row[b][QSK_J(u)]);
-  }
-#pragma unroll
-  for (int u = 0; u < E; ++u)
-    if (ij[u] >= 0) sq_(t, QSK_I(u), QSK_J(u), k, v[u]);
-  for (int e = tid; e < k * k; e += 1024) {
-    const int i = e % k, j = e / k;
-    if (i > j) sq_(t, i, j, k, qzero());
-  }
-}
-
-#undef QSK_I
-#undef QSK_J
-
 // T = R^{-1}, one workgroup per column c, by a column sweep of R T = I:
 // for b = c, c-1, ..., 0: T[b, c] = (delta_bc - s_b) / R[b, b], then
 // s_a += R[a, b] T[b, c] for a < b (no reductions, one barrier per b).
@@ -990,14 +830,6 @@ hipError_t launch_triinv_k(hipStream_t st, const CholArgs &a, GroupRef g, int64_
   return hipGetLastError();
 }
 
-hipError_t launch_cholinv_reg_k(hipStream_t st, const CholArgs &a, GroupRef g, int count, int kmax) {
-  if (kmax <= chol_reg_k<5>())
-    hipLaunchKernelGGL(cholinv_reg_kernel<5>, dim3(g.tab ? count : 1), dim3(1024), 0, st, a, g);
-  else
-    hipLaunchKernelGGL(cholinv_reg_kernel<9>, dim3(g.tab ? count : 1), dim3(1024), 0, st, a, g);
-  return hipGetLastError();
-}
-int cholinv_reg_max_k() { return CHOL_REG_K; }
 
 hipError_t launch_chol_inv(hipStream_t st, const double *g, int k, int complex_only, double shift,
                            double tol, double *r, double *t, SmallStatus *status) {
@@ -1005,7 +837,6 @@ hipError_t launch_chol_inv(hipStream_t st, const double *g, int k, int complex_o
   a.g = g; a.k = k; a.complex_only = complex_only; a.shift = shift; a.tol = tol;
   a.r = r; a.t = t; a.status = status; a.only_failed = 0;
   a.gx = k; a.gy = 1;
-  if (k <= CHOL_REG_K) return launch_cholinv_reg_k(st, a, GroupRef{}, 1, k);
   hipError_t e = launch_chol_k(st, a, GroupRef{}, 1);
   if (e != hipSuccess) return e;
   return launch_triinv_k(st, a, GroupRef{}, 0);
@@ -1509,13 +1340,21 @@ __device__ __forceinline__ void sm_tridiag(double *g, int k, double *d, double *
 
 // Number of eigenvalues of the real symmetric tridiagonal (d, e) below x
 // (Sturm count through the LDL^T pivots of T - x I).
+// The pivot recurrence needs 1/q only to full working precision, not
+// correctly rounded: the hardware reciprocal estimate plus one Newton step
+// (error ~ the square of the estimate's) replaces the division, and a pivot
+// of magnitude below 1e-300 is replaced by +-1e-300 (keeping its sign), so
+// that no reciprocal overflows.
 __device__ int sturm_count(const double *d, const double *e, int k, double x) {
   int c = 0;
   double q = d[0] - x;
   if (q < 0.0) ++c;
   for (int i = 1; i < k; ++i) {
-    if (q == 0.0) q = 1e-300;
-    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    if (fabs(q) < 1e-300) q = q < 0.0 ? -1e-300 : 1e-300;
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(r, fma(-q, r, 1.0), r);
+    const double ei = e[i - 1];
+    q = (d[i] - x) - ei * ei * r;
     if (q < 0.0) ++c;
   }
   return c;

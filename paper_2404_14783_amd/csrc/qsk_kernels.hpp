@@ -248,11 +248,6 @@ hipError_t launch_reduce_planar_k(hipStream_t st, const ReducePlanarArgs &a, Gro
 hipError_t launch_apply_k(hipStream_t st, int tz, const ApplyArgs &a, GroupRef g, int64_t blocks);
 hipError_t launch_psi_apply_k(hipStream_t st, const PsiApplyArgs &a, GroupRef g, int64_t blocks);
 hipError_t launch_error_k(hipStream_t st, int tin, const ErrorArgs &a, GroupRef g, int64_t blocks);
-// Cholesky and inverse in one kernel with the matrix in registers (k up to
-// cholinv_reg_max_k()); same arguments and results as launch_chol_k followed
-// by launch_triinv_k.
-hipError_t launch_cholinv_reg_k(hipStream_t st, const CholArgs &a, GroupRef g, int count, int kmax);
-int cholinv_reg_max_k();
 // Zero a status; keep_fail_any = 1 leaves the sticky fail_any as it is.
 hipError_t launch_status_reset(hipStream_t st, SmallStatus *s, int keep_fail_any);
 hipError_t launch_chol_k(hipStream_t st, const CholArgs &a, GroupRef g, int count);
