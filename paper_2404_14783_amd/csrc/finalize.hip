@@ -90,6 +90,119 @@ __global__ __launch_bounds__(256) void crossprod_k(CrossArgs args, GroupRef grp)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Quaternion FP64 products on the matrix cores: C = opA(A) B with
+// opA(A)(i, t) = A(i, t) or its conjugate, as 16 real products per 16 x 16
+// output tile (v_mfma_f64_16x16x4_f64, K = 4 per instruction).  Element
+// (i, t) of plane p of A is a[p][i * sa_i + t * sa_t] (types double, float
+// or bf16 bits), element (t, j) of B is b[p][t * sb_t + j * sb_j]; so the
+// same kernel serves Z1^* Z2 (Gram matrices), Z T, Psi Q and S^* W.  One
+// wave per output tile, four tiles per workgroup, one chunk of K per
+// blockIdx.y; the operands of the next K step are loaded while the matrix
+// cores work on this one.  Lane l supplies A(i0 + l mod 16, t0 + l / 16) and
+// B(t0 + l / 16, j0 + l mod 16) and holds C(i0 + l / 16 + 4 u, j0 + l mod 16),
+// u = 0..3.  Output: planar (out, ldo; accumulate adds) or, for a split K,
+// AoS partial sums partial[((chunk * N + j) * M + i) * 4 + p].
+typedef __attribute__((ext_vector_type(4))) double v4d;
+template <typename T> __device__ __forceinline__ double ld64(const void *p, int64_t i);
+template <> __device__ __forceinline__ double ld64<double>(const void *p, int64_t i) { return gp((const double *)p)[i]; }
+template <> __device__ __forceinline__ double ld64<float>(const void *p, int64_t i) { return gp((const float *)p)[i]; }
+template <> __device__ __forceinline__ double ld64<uint16_t>(const void *p, int64_t i) {
+  return __uint_as_float(((uint32_t)gp((const uint16_t *)p)[i]) << 16);
+}
+
+// Hamilton product a b: plane p of the result takes sign * a_q * b_{qsel(p, q)}
+__device__ constexpr int hp_b(int p, int q) {
+  constexpr int t[4][4] = {{0, 1, 2, 3}, {1, 0, 3, 2}, {2, 3, 0, 1}, {3, 2, 1, 0}};
+  return t[p][q];
+}
+__device__ constexpr int hp_s(int p, int q) {   // +1 / -1
+  constexpr int t[4][4] = {{1, -1, -1, -1}, {1, 1, 1, -1}, {1, -1, 1, 1}, {1, 1, -1, 1}};
+  return t[p][q];
+}
+
+template <typename TA, typename TB, bool CONJ_A>
+__global__ __launch_bounds__(256) void qgemm64_k(Gemm64Args args, GroupRef grp) {
+  Gemm64Args A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const int lane = threadIdx.x & 63;
+  const int tile = bx * 4 + (threadIdx.x >> 6);
+  if (tile >= A.mt * A.nt) return;                       // whole wave
+  const int tm = tile % A.mt, tn = tile / A.mt;
+  const int64_t i = (int64_t)tm * 16 + (lane & 15);      // A row of this lane
+  const int64_t j = (int64_t)tn * 16 + (lane & 15);      // B column of this lane
+  const int kq = lane >> 4;
+  const int64_t kb = (int64_t)by * A.kchunk, ke = min(A.K, kb + A.kchunk);
+  const bool iok = i < A.M, jok = j < A.N;
+  const int64_t ai = (iok ? i : 0) * A.sa_i, bj = (jok ? j : 0) * A.sb_j;
+  v4d acc[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) acc[p] = {0.0, 0.0, 0.0, 0.0};
+  double na[4], nb[4];
+#define QSK_G64_LOAD(T0)                                                               \
+  do {                                                                                 \
+    const int64_t t_ = (T0) + kq;                                                      \
+    const bool ta_ = iok && t_ < ke, tb_ = jok && t_ < ke;                              \
+    const int64_t tc_ = t_ < ke ? t_ : kb;                                             \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                    \
+      const double x_ = ld64<TA>(A.a[q], ai + tc_ * A.sa_t);                          \
+      const double y_ = ld64<TB>(A.b[q], tc_ * A.sb_t + bj);                           \
+      na[q] = ta_ ? x_ : 0.0;                                                          \
+      nb[q] = tb_ ? y_ : 0.0;                                                          \
+    }                                                                                  \
+  } while (0)
+  QSK_G64_LOAD(kb);
+  for (int64_t t0 = kb; t0 < ke; t0 += 4) {
+    double xa[4], xb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { xa[q] = CONJ_A && q > 0 ? -na[q] : na[q]; xb[q] = nb[q]; }
+    if (t0 + 4 < ke) QSK_G64_LOAD(t0 + 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double aq = xa[q], naq = -xa[q];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(hp_s(p, q) > 0 ? aq : naq, xb[hp_b(p, q)], acc[p], 0, 0, 0);
+    }
+  }
+#undef QSK_G64_LOAD
+  if (!jok) return;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t r = (int64_t)tm * 16 + kq + 4 * u;
+    if (r >= A.M) continue;
+    if (A.partial) {
+      QSK_GLOBAL double *q = gpw(A.partial) + 4 * (((int64_t)by * A.N + j) * A.M + r);
+      q[0] = acc[0][u]; q[1] = acc[1][u]; q[2] = acc[2][u]; q[3] = acc[3][u];
+    } else {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        QSK_GLOBAL double *o = gpw(A.out[p]) + r + j * A.ldo;
+        *o = A.accumulate ? *o + acc[p][u] : acc[p][u];
+      }
+    }
+  }
+}
+
+hipError_t launch_qgemm64_k(hipStream_t st, int ta, int tb, bool conj_a, const Gemm64Args &a, GroupRef g,
+                            int64_t blocks) {
+  const dim3 grid = g.tab ? dim3((unsigned)blocks) : dim3((unsigned)a.gx, (unsigned)a.gy);
+  // ta / tb: 0 double, 1 float, 2 bf16
+  if (conj_a) {
+    if (ta == 0 && tb == 0) hipLaunchKernelGGL((qgemm64_k<double, double, true>), grid, dim3(256), 0, st, a, g);
+    else if (ta == 0 && tb == 1) hipLaunchKernelGGL((qgemm64_k<double, float, true>), grid, dim3(256), 0, st, a, g);
+    else if (ta == 1 && tb == 1) hipLaunchKernelGGL((qgemm64_k<float, float, true>), grid, dim3(256), 0, st, a, g);
+    else return hipErrorInvalidValue;
+  } else {
+    if (ta == 0 && tb == 0) hipLaunchKernelGGL((qgemm64_k<double, double, false>), grid, dim3(256), 0, st, a, g);
+    else if (ta == 1 && tb == 0) hipLaunchKernelGGL((qgemm64_k<float, double, false>), grid, dim3(256), 0, st, a, g);
+    else if (ta == 2 && tb == 0) hipLaunchKernelGGL((qgemm64_k<uint16_t, double, false>), grid, dim3(256), 0, st, a, g);
+    else return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 __global__ void reduce_chunks_k(ReduceArgs args, GroupRef grp) {
   ReduceArgs A;
   int bx, by, bz;
@@ -190,18 +303,42 @@ hipError_t launch_reduce_planar_k(hipStream_t st, const ReducePlanarArgs &a, Gro
   return hipGetLastError();
 }
 
+// Split of K for the matrix-core products: about 2048 waves in all (eight
+// per CU), chunks a multiple of 4, at most max_chunks of them.
+static int64_t g64_chunk(int64_t K, int64_t tiles, int64_t max_chunks, int64_t *nch) {
+  int64_t want = (2048 + tiles - 1) / tiles;
+  if (want > max_chunks) want = max_chunks;
+  if (want < 1) want = 1;
+  int64_t chunk = (K + want - 1) / want;
+  chunk = (chunk + 3) / 4 * 4;
+  if (chunk < 64) chunk = 64;
+  *nch = (K + chunk - 1) / chunk;
+  return chunk;
+}
+
+static Gemm64Args g64_args(const void *const a[4], int64_t sa_i, int64_t sa_t, const void *const b[4],
+                           int64_t sb_t, int64_t sb_j, int64_t M, int64_t N, int64_t K) {
+  Gemm64Args g{};
+  for (int p = 0; p < 4; ++p) { g.a[p] = a[p]; g.b[p] = b[p]; }
+  g.sa_i = sa_i; g.sa_t = sa_t; g.sb_t = sb_t; g.sb_j = sb_j;
+  g.M = M; g.N = N; g.K = K; g.kchunk = K;
+  g.mt = (int)((M + 15) / 16); g.nt = (int)((N + 15) / 16);
+  g.gx = (g.mt * g.nt + 3) / 4; g.gy = 1;
+  return g;
+}
+
 hipError_t launch_crossprod(hipStream_t st, int t1, const void *const z1[4], int64_t ld1, int t2,
                             const void *const z2[4], int64_t ld2, int64_t rows, int k1, int k2,
                             double *partials, int64_t partial_elems, double *out_aos) {
-  int64_t chunk, nch;
-  if (!plan_crossprod(rows, k1, k2, partial_elems, &chunk, &nch)) return hipErrorInvalidValue;
-  CrossArgs a{};
-  set_planes(a.z1, z1);
-  set_planes(a.z2, z2);
-  a.ld1 = ld1; a.ld2 = ld2; a.rows = rows; a.chunk = chunk; a.k1 = k1; a.k2 = k2;
-  a.partial = partials; a.planar = 0;
-  a.gx = (k1 + 15) / 16; a.gy = (k2 + 15) / 16;
-  hipError_t e = launch_crossprod_k(st, t1, t2, a, GroupRef{}, nch);
+  // C(i, j) = sum_t conj(Z1(t, i)) Z2(t, j) on the FP64 matrix cores, K split
+  const int64_t max_chunks = partial_elems / ((int64_t)k1 * k2 * 4);
+  if (max_chunks < 1) return hipErrorInvalidValue;
+  Gemm64Args g = g64_args(z1, ld1, 1, z2, 1, ld2, k1, k2, rows);
+  int64_t nch;
+  g.kchunk = g64_chunk(rows, (int64_t)g.mt * g.nt, max_chunks, &nch);
+  g.gy = (int)nch;
+  g.partial = partials;
+  hipError_t e = launch_qgemm64_k(st, t1, t2, true, g, GroupRef{}, 0);
   if (e != hipSuccess) return e;
   ReduceArgs r{};
   r.partial = partials; r.nchunks = (int)nch; r.elems = (int64_t)k1 * k2 * 4; r.out = out_aos;
@@ -212,13 +349,11 @@ hipError_t launch_crossprod(hipStream_t st, int t1, const void *const z1[4], int
 hipError_t launch_crossprod_planar(hipStream_t st, const double *const z1[4], int64_t ld1, int t2,
                                    const void *const z2[4], int64_t ld2, int64_t rows, int k1,
                                    int k2, double *const out[4], int64_t ldo) {
-  CrossArgs a{};
-  for (int q = 0; q < 4; ++q) a.z1[q] = z1[q];
-  set_planes(a.z2, z2);
-  a.ld1 = ld1; a.ld2 = ld2; a.rows = rows; a.chunk = rows; a.k1 = k1; a.k2 = k2;
-  a.partial = nullptr; set_planes(a.out, out); a.ldo = ldo; a.planar = 1;
-  a.gx = (k1 + 15) / 16; a.gy = (k2 + 15) / 16;
-  return launch_crossprod_k(st, 0, t2, a, GroupRef{}, 1);
+  const void *zz[4] = {z1[0], z1[1], z1[2], z1[3]};
+  Gemm64Args g = g64_args(zz, ld1, 1, z2, 1, ld2, k1, k2, rows);
+  for (int p = 0; p < 4; ++p) g.out[p] = out[p];
+  g.ldo = ldo;
+  return launch_qgemm64_k(st, 0, t2, true, g, GroupRef{}, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -285,12 +420,12 @@ hipError_t launch_apply_k(hipStream_t st, int tz, const ApplyArgs &a, GroupRef g
 
 hipError_t launch_apply(hipStream_t st, int tz, const void *const z[4], int64_t ldz, int64_t rows,
                         int k, const double *c_aos, int kc, double *const out[4], int64_t ldo) {
-  ApplyArgs a{};
-  set_planes(a.z, z);
-  a.ldz = ldz; a.rows = rows; a.k = k; a.c = c_aos; a.kc = kc;
-  set_planes(a.out, out); a.ldo = ldo;
-  a.gx = (int)((rows + 255) / 256); a.gy = (kc + 15) / 16;
-  return launch_apply_k(st, tz, a, GroupRef{}, 0);
+  // Out(i, j) = sum_t Z(i, t) C(t, j), C AoS with leading dimension k
+  const void *cp[4] = {c_aos, c_aos + 1, c_aos + 2, c_aos + 3};
+  Gemm64Args g = g64_args(z, 1, ldz, cp, 4, 4 * (int64_t)k, rows, kc, k);
+  for (int p = 0; p < 4; ++p) g.out[p] = out[p];
+  g.ldo = ldo;
+  return launch_qgemm64_k(st, tz, 0, false, g, GroupRef{}, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -390,6 +525,26 @@ hipError_t launch_psi_apply(hipStream_t st, int mode, int rad, uint32_t k0, uint
                             int64_t ldp, const void *psi_st, int psi_st_type, int64_t psi_ld,
                             int64_t psi_ps) {
   int64_t chunk, nch;
+  if (psi_st && (psi_st_type == 1 || psi_st_type == 2)) {
+    // staged Psi: P(i, j) = sum_t Psi(i, t) H(t, j) on the FP64 matrix cores
+    const int64_t max_chunks = partial_elems / ((int64_t)l * k * 4);
+    if (max_chunks < 1) return hipErrorInvalidValue;
+    const size_t es = psi_st_type == 1 ? 2 : 4;
+    const void *pp[4];
+    for (int q = 0; q < 4; ++q) pp[q] = (const char *)psi_st + (size_t)q * psi_ps * es;
+    const void *hh[4] = {h[0], h[1], h[2], h[3]};
+    Gemm64Args g = g64_args(pp, psi_ld, 1, hh, 1, ldh, l, k, m);
+    g.kchunk = g64_chunk(m, (int64_t)g.mt * g.nt, max_chunks, &nch);
+    g.gy = (int)nch;
+    g.partial = partials;
+    hipError_t e = launch_qgemm64_k(st, psi_st_type == 1 ? 2 : 1, 0, false, g, GroupRef{}, 0);
+    if (e != hipSuccess) return e;
+    ReducePlanarArgs r{};
+    r.partial = partials; r.nchunks = (int)nch; r.r = l; r.c = k;
+    set_planes(r.out, p); r.ldo = ldp;
+    r.gx = (int)(((int64_t)l * k + 255) / 256); r.gy = 1;
+    return launch_reduce_planar_k(st, r, GroupRef{}, r.gx);
+  }
   if (!plan_psi_apply(l, m, k, partial_elems, &chunk, &nch)) return hipErrorInvalidValue;
   PsiApplyArgs a{};
   a.mode = mode; a.rad = rad; a.k0 = k0; a.k1 = k1; a.l = l; a.m = m;

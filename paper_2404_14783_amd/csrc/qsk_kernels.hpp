@@ -141,6 +141,15 @@ struct GroupRef {
   int count;
 };
 
+struct Gemm64Args {         // C = opA(A) B, quaternion, FP64 matrix cores (16 x 16 tiles)
+  const void *a[4]; int64_t sa_i, sa_t;   // A(i, t) of plane p: a[p][i * sa_i + t * sa_t]
+  const void *b[4]; int64_t sb_t, sb_j;   // B(t, j): b[p][t * sb_t + j * sb_j]
+  int64_t M, N, K, kchunk;                // K split in chunks of kchunk (blockIdx.y)
+  int mt, nt;                             // 16-wide tiles in M and N
+  double *out[4]; int64_t ldo; int accumulate;
+  double *partial;                        // split K: [chunk][N][M] AoS partial sums
+  int gx, gy;
+};
 struct CrossArgs {          // C = Z1^* Z2 over row chunks (bz), 16 x 16 tiles (bx, by)
   const void *z1[4]; int64_t ld1;
   const void *z2[4]; int64_t ld2;
@@ -242,6 +251,9 @@ hipError_t launch_identity(hipStream_t st, int k, double *c);
 // `blocks` / `count` = total linear blocks / problems of the table).
 bool plan_crossprod(int64_t rows, int k1, int k2, int64_t partial_elems, int64_t *chunk, int64_t *nch);
 bool plan_psi_apply(int l, int64_t m, int k, int64_t partial_elems, int64_t *chunk, int64_t *nch);
+// ta / tb: 0 double, 1 float, 2 bf16 bits; conj_a conjugates A's entries.
+hipError_t launch_qgemm64_k(hipStream_t st, int ta, int tb, bool conj_a, const Gemm64Args &a, GroupRef g,
+                            int64_t blocks);
 hipError_t launch_crossprod_k(hipStream_t st, int t1, int t2, const CrossArgs &a, GroupRef g, int64_t blocks);
 hipError_t launch_reduce_k(hipStream_t st, const ReduceArgs &a, GroupRef g, int64_t blocks);
 hipError_t launch_reduce_planar_k(hipStream_t st, const ReducePlanarArgs &a, GroupRef g, int64_t blocks);

@@ -141,10 +141,16 @@ def test_config1_sketches(config1):
     assert rel(w, ref.W) < 1e-12
 
 
-def oracle_sensitivity(ref, kind, rel_pert=1e-15, seed=0):
+def oracle_sensitivity(ref, kind, rel_pert=1e-15, draws=4):
     """Relative change of the oracle's kappa / eps when Y is perturbed by a
-    random relative 1e-15: the scale below which GPU and oracle cannot be
+    random relative 1e-15, the largest over a few draws (a single draw
+    varies by several times): the scale below which GPU and oracle cannot be
     expected to agree (these diagnostics depend on the non-unique H)."""
+    out = [_sensitivity_draw(ref, kind, rel_pert, sd) for sd in range(draws)]
+    return tuple(max(o[i] for o in out) for i in range(4))
+
+
+def _sensitivity_draw(ref, kind, rel_pert, seed):
     from oracle.rangefinders import pseudo_qr, pseudo_svd
     rng = np.random.default_rng(seed)
     y2 = ref.Y * (1.0 + rel_pert * rng.standard_normal(ref.Y.shape))
