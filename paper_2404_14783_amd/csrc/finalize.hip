@@ -121,8 +121,114 @@ __device__ constexpr int hp_s(int p, int q) {   // +1 / -1
   return t[p][q];
 }
 
-template <typename TA, typename TB, bool CONJ_A>
+// Loads of 4 operand values at t, t + 1, t + 2, t + 3: one vector load when
+// t is the contiguous index (CONT), else four strided loads.
+template <typename T, bool CONT>
+__device__ __forceinline__ void ld64x4(const void *p, int64_t base, int64_t st, double (&v)[4]) {
+  if constexpr (CONT && sizeof(T) == 8) {
+    typedef double d2 __attribute__((ext_vector_type(2), aligned(8)));   // element alignment only
+    const QSK_GLOBAL d2 *q = (const QSK_GLOBAL d2 *)((const double *)p + base);
+    const d2 x = q[0], y = q[1];
+    v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+  } else if constexpr (CONT && sizeof(T) == 4) {
+    typedef float f4 __attribute__((ext_vector_type(4), aligned(4)));
+    const f4 x = *(const QSK_GLOBAL f4 *)((const float *)p + base);
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+  } else if constexpr (CONT && sizeof(T) == 2) {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2), aligned(2)));
+    const u2 x = *(const QSK_GLOBAL u2 *)((const uint16_t *)p + base);
+    v[0] = __uint_as_float(x.x << 16); v[1] = __uint_as_float(x.x & 0xFFFF0000u);
+    v[2] = __uint_as_float(x.y << 16); v[3] = __uint_as_float(x.y & 0xFFFF0000u);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = ld64<T>(p, base + s * st);
+  }
+}
+
+template <typename TA, typename TB, bool CONJ_A, bool ACONT, bool BCONT>
 __global__ __launch_bounds__(256) void qgemm64_k(Gemm64Args args, GroupRef grp) {
+  Gemm64Args A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  const int lane = threadIdx.x & 63;
+  const int tile = bx * 4 + (threadIdx.x >> 6);
+  if (tile >= A.mt * A.nt) return;                       // whole wave
+  const int tm = tile % A.mt, tn = tile / A.mt;
+  const int64_t i = (int64_t)tm * 16 + (lane & 15);      // A row of this lane
+  const int64_t j = (int64_t)tn * 16 + (lane & 15);      // B column of this lane
+  const int kq = lane >> 4;
+  const int64_t kb = (int64_t)by * A.kchunk, ke = min(A.K, kb + A.kchunk);
+  const bool iok = i < A.M, jok = j < A.N;
+  const int64_t ai = (iok ? i : 0) * A.sa_i, bj = (jok ? j : 0) * A.sb_j;
+  v4d acc[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) acc[p] = {0.0, 0.0, 0.0, 0.0};
+  // super-steps of 16 values of t: K slot kq of the s-th instruction is
+  // t = t0 + 4 kq + s, so each lane reads 4 consecutive t per operand
+  double na[4][4], nb[4][4];
+#define QSK_G64_LOAD(T0)                                                               \
+  do {                                                                                 \
+    const int64_t t_ = (T0) + 4 * kq;                                                  \
+    if ((T0) + 16 <= ke) {                                                             \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                  \
+        ld64x4<TA, ACONT>(A.a[q], ai + t_ * A.sa_t, A.sa_t, na[q]);                    \
+        ld64x4<TB, BCONT>(A.b[q], t_ * A.sb_t + bj, A.sb_t, nb[q]);                    \
+      }                                                                                \
+    } else {                                                                           \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q)                                    \
+        _Pragma("unroll") for (int s = 0; s < 4; ++s) {                                \
+          const bool in_ = t_ + s < ke;                                                \
+          const int64_t tc_ = in_ ? t_ + s : kb;                                       \
+          const double x_ = ld64<TA>(A.a[q], ai + tc_ * A.sa_t);                       \
+          const double y_ = ld64<TB>(A.b[q], tc_ * A.sb_t + bj);                       \
+          na[q][s] = in_ ? x_ : 0.0;                                                   \
+          nb[q][s] = in_ ? y_ : 0.0;                                                   \
+        }                                                                              \
+    }                                                                                  \
+    if (!iok) _Pragma("unroll") for (int q = 0; q < 4; ++q) _Pragma("unroll") for (int s = 0; s < 4; ++s) na[q][s] = 0.0; \
+    if (!jok) _Pragma("unroll") for (int q = 0; q < 4; ++q) _Pragma("unroll") for (int s = 0; s < 4; ++s) nb[q][s] = 0.0; \
+  } while (0)
+  QSK_G64_LOAD(kb);
+  for (int64_t t0 = kb; t0 < ke; t0 += 16) {
+    double xa[4][4], xb[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) { xa[q][s] = CONJ_A && q > 0 ? -na[q][s] : na[q][s]; xb[q][s] = nb[q][s]; }
+    if (t0 + 16 < ke) QSK_G64_LOAD(t0 + 16);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double aq = xa[q][s], naq = -xa[q][s];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(hp_s(p, q) > 0 ? aq : naq, xb[hp_b(p, q)][s], acc[p], 0, 0, 0);
+      }
+  }
+#undef QSK_G64_LOAD
+  if (!jok) return;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t r = (int64_t)tm * 16 + kq + 4 * u;
+    if (r >= A.M) continue;
+    if (A.partial) {
+      QSK_GLOBAL double *q = gpw(A.partial) + 4 * (((int64_t)by * A.N + j) * A.M + r);
+      q[0] = acc[0][u]; q[1] = acc[1][u]; q[2] = acc[2][u]; q[3] = acc[3][u];
+    } else {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        QSK_GLOBAL double *o = gpw(A.out[p]) + r + j * A.ldo;
+        *o = A.accumulate ? *o + acc[p][u] : acc[p][u];
+      }
+    }
+  }
+}
+
+// Strided operands (t not contiguous): one K step of 4 per iteration, one
+// value per lane and plane.
+template <typename TA, typename TB, bool CONJ_A>
+__global__ __launch_bounds__(256) void qgemm64s_k(Gemm64Args args, GroupRef grp) {
   Gemm64Args A;
   int bx, by, bz;
   if (!group_select(args, grp, A, bx, by, bz)) return;
@@ -188,18 +294,25 @@ __global__ __launch_bounds__(256) void qgemm64_k(Gemm64Args args, GroupRef grp) 
 hipError_t launch_qgemm64_k(hipStream_t st, int ta, int tb, bool conj_a, const Gemm64Args &a, GroupRef g,
                             int64_t blocks) {
   const dim3 grid = g.tab ? dim3((unsigned)blocks) : dim3((unsigned)a.gx, (unsigned)a.gy);
-  // ta / tb: 0 double, 1 float, 2 bf16
+  // ta / tb: 0 double, 1 float, 2 bf16; vector loads where t is contiguous
+  const bool ac = a.sa_t == 1, bc = a.sb_t == 1;
+#define QSK_G64(TA, TB, CJ)                                                                       \
+  do {                                                                                             \
+    if (ac && bc) hipLaunchKernelGGL((qgemm64_k<TA, TB, CJ, true, true>), grid, dim3(256), 0, st, a, g);   \
+    else hipLaunchKernelGGL((qgemm64s_k<TA, TB, CJ>), grid, dim3(256), 0, st, a, g);                      \
+  } while (0)
   if (conj_a) {
-    if (ta == 0 && tb == 0) hipLaunchKernelGGL((qgemm64_k<double, double, true>), grid, dim3(256), 0, st, a, g);
-    else if (ta == 0 && tb == 1) hipLaunchKernelGGL((qgemm64_k<double, float, true>), grid, dim3(256), 0, st, a, g);
-    else if (ta == 1 && tb == 1) hipLaunchKernelGGL((qgemm64_k<float, float, true>), grid, dim3(256), 0, st, a, g);
+    if (ta == 0 && tb == 0) QSK_G64(double, double, true);
+    else if (ta == 0 && tb == 1) QSK_G64(double, float, true);
+    else if (ta == 1 && tb == 1) QSK_G64(float, float, true);
     else return hipErrorInvalidValue;
   } else {
-    if (ta == 0 && tb == 0) hipLaunchKernelGGL((qgemm64_k<double, double, false>), grid, dim3(256), 0, st, a, g);
-    else if (ta == 1 && tb == 0) hipLaunchKernelGGL((qgemm64_k<float, double, false>), grid, dim3(256), 0, st, a, g);
-    else if (ta == 2 && tb == 0) hipLaunchKernelGGL((qgemm64_k<uint16_t, double, false>), grid, dim3(256), 0, st, a, g);
+    if (ta == 0 && tb == 0) QSK_G64(double, double, false);
+    else if (ta == 1 && tb == 0) QSK_G64(float, double, false);
+    else if (ta == 2 && tb == 0) QSK_G64(uint16_t, double, false);
     else return hipErrorInvalidValue;
   }
+#undef QSK_G64
   return hipGetLastError();
 }
 
@@ -304,13 +417,13 @@ hipError_t launch_reduce_planar_k(hipStream_t st, const ReducePlanarArgs &a, Gro
 }
 
 // Split of K for the matrix-core products: about 2048 waves in all (eight
-// per CU), chunks a multiple of 4, at most max_chunks of them.
+// per CU), chunks a multiple of 16, at most max_chunks of them.
 static int64_t g64_chunk(int64_t K, int64_t tiles, int64_t max_chunks, int64_t *nch) {
   int64_t want = (2048 + tiles - 1) / tiles;
   if (want > max_chunks) want = max_chunks;
   if (want < 1) want = 1;
   int64_t chunk = (K + want - 1) / want;
-  chunk = (chunk + 3) / 4 * 4;
+  chunk = (chunk + 15) / 16 * 16;
   if (chunk < 64) chunk = 64;
   *nch = (K + chunk - 1) / chunk;
   return chunk;
