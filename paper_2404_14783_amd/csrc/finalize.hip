@@ -1264,7 +1264,7 @@ hipError_t launch_identity(hipStream_t st, int k, double *c) {
 }
 
 // LDS pool (doubles) of the tridiagonalisation and of the eigenvector clean-up.
-constexpr int TRI_POOL = 16384;
+constexpr int TRI_POOL = 19200;
 
 // Work layout of the pseudo-SVD pipeline (doubles; kq = k * k):
 //   U  [0, 4kq)           eigenvectors of G_L (AoS k x k), then the bad-pair
@@ -1461,19 +1461,136 @@ hipError_t launch_pinv_sstar(hipStream_t st, int l, int k, const double *const p
 // packed lower storage of an n0 x n0 block: column s holds rows s..n0-1
 __device__ __forceinline__ int pk(int r, int s, int n0) { return s * n0 - ((s * (s - 1)) >> 1) + (r - s); }
 
+// Element (r, c), r >= c, of the lower triangle: packed in LDS (L) or in the
+// full matrix in global memory.
+template <bool L>
+__device__ __forceinline__ qd tri_get(const qd *P, const double *g, int r, int c, int o0, int n0, int k) {
+  if constexpr (L) return P[pk(r - o0, c - o0, n0)];
+  else return gq(g, r, c, k);
+}
+template <bool L>
+__device__ __forceinline__ void tri_set(qd *P, double *g, int r, int c, int o0, int n0, int k, qd x) {
+  if constexpr (L) P[pk(r - o0, c - o0, n0)] = x;
+  else sq_(g, r, c, k, x);
+}
+
+// One Householder step j of sm_tridiag; the storage (LDS or global) is a
+// template parameter so that no access pays for the other's branch or waits.
+template <bool L>
+__device__ __forceinline__ void tri_step(int j, int k, double *g, qd *P, int o0, int n0, qd *v, qd *pv,
+                                         double *d, double *e, double *hv, double *hbeta, double *halpha,
+                                         double *s_beta) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int n = k - j - 1, o = j + 1;
+  // (A) one wave forms the reflector of column j: x = G[o.., j], alpha =
+  // -|x| x0 / |x0|, v = x - alpha e_0, beta = 2 / |v|^2
+  if (wave == 0) {
+    qd x[4];
+    double loc = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int aa = lane + 64 * t;
+      x[t] = aa < n ? tri_get<L>(P, g, o + aa, j, o0, n0, k) : qzero();
+      loc += qnorm2(x[t]);
+    }
+    const double xn2 = wave_sum(loc), xn = sqrt(xn2);
+    const qd x0 = {__shfl(x[0].w, 0, 64), __shfl(x[0].x, 0, 64), __shfl(x[0].y, 0, 64), __shfl(x[0].z, 0, 64)};
+    const double ax0 = sqrt(qnorm2(x0));
+    double beta = 0.0;
+    qd alpha = qzero();
+    if (xn != 0.0) {
+      const qd u = ax0 > 0.0 ? qscale(x0, 1.0 / ax0) : qd{1.0, 0.0, 0.0, 0.0};
+      alpha = qscale(u, -xn);
+      beta = 1.0 / (xn2 + xn * ax0);
+    }
+    if (lane == 0) {
+      d[j] = tri_get<L>(P, g, j, j, o0, n0, k).w;
+      e[j] = xn;
+      s_beta[j & 1] = beta;
+      if (halpha) { halpha[4 * j] = alpha.w; halpha[4 * j + 1] = alpha.x; halpha[4 * j + 2] = alpha.y; halpha[4 * j + 3] = alpha.z; }
+      if (hbeta) hbeta[j] = beta;
+    }
+    if (beta != 0.0) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int aa = lane + 64 * t;
+        if (aa < n) v[aa] = aa == 0 ? qsub(x0, alpha) : x[t];
+      }
+    }
+  }
+  __syncthreads();
+  const double beta = s_beta[j & 1];
+  if (beta == 0.0) return;                         // uniform; G unchanged
+  if (hv)
+    for (int aa = tid; aa < n; aa += blockDim.x) sq_(hv, aa, j, k, v[aa]);
+  // (B) p = beta G' v: lpr lanes per row a (c congruent to sub mod lpr);
+  // lower entries G[a, c] (c <= a) and conj(G[c, a]) above, without branches
+  {
+    const int lpr = n <= 128 ? 8 : 4;
+    const int aa = tid / lpr, sub = tid % lpr;
+    qd sacc = qzero();
+    if (aa < n) {
+#pragma unroll 4
+      for (int c = sub; c < n; c += lpr) {
+        const bool lo = c <= aa;
+        qd x = tri_get<L>(P, g, o + (lo ? aa : c), o + (lo ? c : aa), o0, n0, k);
+        const double sg = lo ? 1.0 : -1.0;
+        x.x *= sg; x.y *= sg; x.z *= sg;
+        qfma(sacc, x, v[c]);
+      }
+    }
+    for (int off = 1; off < lpr; off <<= 1) {
+      sacc.w += __shfl_xor(sacc.w, off, 64); sacc.x += __shfl_xor(sacc.x, off, 64);
+      sacc.y += __shfl_xor(sacc.y, off, 64); sacc.z += __shfl_xor(sacc.z, off, 64);
+    }
+    if (aa < n && sub == 0) pv[aa] = qscale(sacc, beta);
+  }
+  __syncthreads();
+  // (C) every wave forms s_k = beta/2 Re(v^* p) itself (same order, same
+  // value), then the rank-2 update of the lower triangle with w = p - s_k v:
+  // G'[a, c] -= v_a conj(w_c) + w_a conj(v_c); thread (cs, a) takes row a,
+  // columns cs, cs + nc, ... <= a
+  {
+    double kl = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int aa = lane + 64 * t;
+      if (aa < n) {
+        const qd pa = pv[aa], va = v[aa];
+        kl += va.w * pa.w + va.x * pa.x + va.y * pa.y + va.z * pa.z;
+      }
+    }
+    const double sk = 0.5 * beta * wave_sum(kl);
+    const int nc = (int)blockDim.x / n;
+    const int cs = tid / n, aa = tid % n;
+    if (cs < nc) {
+      const qd va = v[aa];
+      const qd wa = qsub(pv[aa], qscale(va, sk));
+#pragma unroll 4
+      for (int cc = cs; cc <= aa; cc += nc) {
+        const qd vc = v[cc];
+        const qd wc = qsub(pv[cc], qscale(vc, sk));
+        qd gv = tri_get<L>(P, g, o + aa, o + cc, o0, n0, k);
+        gv = qsub(gv, qmul(va, qconj(wc)));
+        gv = qsub(gv, qmul(wa, qconj(vc)));
+        tri_set<L>(P, g, o + aa, o + cc, o0, n0, k, gv);
+      }
+    }
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void sm_tridiag(double *g, int k, double *d, double *e, double *pool,
                            double *hv = nullptr, double *hbeta = nullptr, double *halpha = nullptr) {
-  __shared__ double s_red[16];
-  __shared__ double s_beta, s_k;
+  __shared__ double s_beta[2];        // by parity of j: a step that skips has no closing barrier
   qd *v = (qd *)pool;                 // up to 256
   qd *pv = v + 256;                   // up to 256
-  qd *part = pv + 256;                // 4 x 256 (global phase)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   int n0 = 0, o0 = 0;                 // LDS block: rows/cols o0 .. o0 + n0 - 1
   qd *P = nullptr;
   #pragma unroll 1
   for (int j = 0; j + 1 < k; ++j) {
-    const int n = k - j - 1, o = j + 1;
+    const int n = k - j - 1;
     if (!P && 2 * (n + 1) + (n + 1) * (n + 2) / 2 <= TRI_POOL / 4) {
       // move the lower triangle of G[j:, j:] to LDS (v, pv then sit at its front)
       n0 = n + 1;
@@ -1487,120 +1604,8 @@ __device__ __forceinline__ void sm_tridiag(double *g, int k, double *d, double *
         for (int r = s + lane; r < n0; r += 64) P[pk(r, s, n0)] = gq(g, o0 + r, o0 + s, k);
       __syncthreads();
     }
-    // column j below the diagonal and its norm; d_j
-    if (tid == 0) d[j] = P ? P[pk(j - o0, j - o0, n0)].w : gq(g, j, j, k).w;
-    double loc = 0.0;
-    #pragma unroll 1
-    for (int a = tid; a < n; a += blockDim.x) loc += qnorm2(P ? P[pk(o + a - o0, j - o0, n0)] : gq(g, o + a, j, k));
-    loc = wave_sum(loc);
-    if (lane == 0) s_red[wave] = loc;
-    __syncthreads();
-    if (tid == 0) {
-      double xn2 = 0.0;
-      #pragma unroll 1
-      for (int q = 0; q < nw; ++q) xn2 += s_red[q];
-      const double xn = sqrt(xn2);
-      const qd x0 = P ? P[pk(o - o0, j - o0, n0)] : gq(g, o, j, k);
-      const double ax0 = sqrt(qnorm2(x0));
-      e[j] = xn;
-      if (xn == 0.0) {
-        s_beta = 0.0;
-        if (halpha) { halpha[4 * j] = 0.0; halpha[4 * j + 1] = 0.0; halpha[4 * j + 2] = 0.0; halpha[4 * j + 3] = 0.0; }
-      } else {
-        const qd u = ax0 > 0.0 ? qscale(x0, 1.0 / ax0) : qd{1.0, 0.0, 0.0, 0.0};
-        const qd alpha = qscale(u, -xn);
-        v[0] = qsub(x0, alpha);
-        s_beta = 1.0 / (xn2 + xn * ax0);               // 2 / ||v||^2
-        if (halpha) { halpha[4 * j] = alpha.w; halpha[4 * j + 1] = alpha.x; halpha[4 * j + 2] = alpha.y; halpha[4 * j + 3] = alpha.z; }
-      }
-      if (hbeta) hbeta[j] = s_beta;
-    }
-    __syncthreads();
-    const double beta = s_beta;
-    if (beta == 0.0) continue;
-    #pragma unroll 1
-    for (int a = 1 + tid; a < n; a += blockDim.x) v[a] = P ? P[pk(o + a - o0, j - o0, n0)] : gq(g, o + a, j, k);
-    __syncthreads();
-    if (hv)
-      #pragma unroll 1
-      for (int a = tid; a < n; a += blockDim.x) sq_(hv, a, j, k, v[a]);
-    // p = beta G' v
-    if (!P) {
-      const int grp = tid >> 8, a = tid & 255;
-      if (a < n) {
-        qd s = qzero();
-        #pragma unroll 1
-        for (int c = grp; c < n; c += 4) qfma(s, gq(g, o + a, o + c, k), v[c]);
-        part[grp * 256 + a] = s;
-      }
-      __syncthreads();
-      #pragma unroll 1
-      for (int aa = tid; aa < n; aa += blockDim.x)
-        pv[aa] = qscale(qadd(qadd(part[aa], part[256 + aa]), qadd(part[512 + aa], part[768 + aa])), beta);
-    } else {
-      // row a = tid / 4, four lanes per row (c congruent to sub mod 4);
-      // lower entries L[a, c] (c <= a) and conj(L[c, a]) above
-      const int a = tid >> 2, sub = tid & 3;
-      qd s = qzero();
-      if (a < n) {
-        const int ra = o + a - o0;
-#pragma unroll 1
-        for (int c = sub; c < n; c += 4) {
-          const int rc = o + c - o0;
-          const qd gac = c <= a ? P[pk(ra, rc, n0)] : qconj(P[pk(rc, ra, n0)]);
-          qfma(s, gac, v[c]);
-        }
-      }
-      s.w += __shfl_xor(s.w, 1, 64); s.x += __shfl_xor(s.x, 1, 64);
-      s.y += __shfl_xor(s.y, 1, 64); s.z += __shfl_xor(s.z, 1, 64);
-      s.w += __shfl_xor(s.w, 2, 64); s.x += __shfl_xor(s.x, 2, 64);
-      s.y += __shfl_xor(s.y, 2, 64); s.z += __shfl_xor(s.z, 2, 64);
-      if (a < n && sub == 0) pv[a] = qscale(s, beta);
-      __syncthreads();
-    }
-    double kl = 0.0;
-    #pragma unroll 1
-    for (int aa = tid; aa < n; aa += blockDim.x) {
-      const qd pa = pv[aa];
-      kl += v[aa].w * pa.w + v[aa].x * pa.x + v[aa].y * pa.y + v[aa].z * pa.z;   // Re(conj(v) p)
-    }
-    kl = wave_sum(kl);
-    if (lane == 0) s_red[wave] = kl;
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      #pragma unroll 1
-      for (int q = 0; q < nw; ++q) t += s_red[q];
-      s_k = 0.5 * beta * t;
-    }
-    __syncthreads();
-    #pragma unroll 1
-    for (int aa = tid; aa < n; aa += blockDim.x) pv[aa] = qsub(pv[aa], qscale(v[aa], s_k));   // w
-    __syncthreads();
-    if (!P) {
-      #pragma unroll 1
-      for (int q = tid; q < n * n; q += blockDim.x) {
-        const int aa = q % n, cc = q / n;
-        qd gv = gq(g, o + aa, o + cc, k);
-        gv = qsub(gv, qmul(v[aa], qconj(pv[cc])));
-        gv = qsub(gv, qmul(pv[aa], qconj(v[cc])));
-        sq_(g, o + aa, o + cc, k, gv);
-      }
-    } else {
-      // lower triangle only: one wave per column
-      #pragma unroll 1
-      for (int cc = wave; cc < n; cc += nw) {
-        const int rc = o + cc - o0;
-        const qd vc = qconj(v[cc]), wc = qconj(pv[cc]);
-#pragma unroll 1
-        for (int aa = cc + lane; aa < n; aa += 64) {
-          qd &gv = P[pk(o + aa - o0, rc, n0)];
-          gv = qsub(gv, qmul(v[aa], wc));
-          gv = qsub(gv, qmul(pv[aa], vc));
-        }
-      }
-    }
-    __syncthreads();
+    if (P) tri_step<true>(j, k, g, P, o0, n0, v, pv, d, e, hv, hbeta, halpha, s_beta);
+    else tri_step<false>(j, k, g, P, o0, n0, v, pv, d, e, hv, hbeta, halpha, s_beta);
   }
   if (tid == 0) d[k - 1] = P ? P[pk(k - 1 - o0, k - 1 - o0, n0)].w : gq(g, k - 1, k - 1, k).w;
   __syncthreads();
