@@ -346,7 +346,8 @@ def main():
         sk64.close()
         del res
 
-    paths = [("fp32", "f32", 1), ("bf16", "bf16", args.terms)]
+    # fp8: e4m3 data with per-tile scales plus a two-term residual correction
+    paths = [("fp32", "f32", 1), ("bf16", "bf16", args.terms), ("fp8", "fp8", 2)]
     timing = {}
     for name, sketch, terms in paths:
         sk = make(sketch, terms)
@@ -394,11 +395,11 @@ def main():
     eq = {}
     for kind in ("pseudo_qr", "pseudo_svd"):
         ref = errors.get(("fp64", kind))
-        e16 = errors.get(("bf16", kind))
-        e32 = errors.get(("fp32", kind))
-        eq[kind] = {"e_fp64": ref, "e_fp32": e32, "e_bf16": e16,
-                    "rel_diff_bf16": (abs(e16 - ref) / ref) if ref else None,
-                    "rel_diff_fp32": (abs(e32 - ref) / ref) if ref else None}
+        eq[kind] = {"e_fp64": ref}
+        for name, _, _ in paths:
+            e = errors.get((name, kind))
+            eq[kind]["e_" + name] = e
+            eq[kind]["rel_diff_" + name] = (abs(e - ref) / ref) if ref else None
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
@@ -414,6 +415,7 @@ def main():
                    "m": m, "n": n, "k": k, "l": l, "block": block, "bf16_terms": args.terms},
         "paths": out_paths, "equal_error": eq,
         "speedup_vs_fp32_wall": speedup,
+        "speedup_vs_fp32_wall_fp8": out_paths["fp32"]["total_ms"] / out_paths["fp8"]["total_ms"],
         "roofline": roofline, "cpu_baseline": cpu,
         "host": {"cpu": platform.processor() or platform.machine(), "cores": os.cpu_count()},
     }
