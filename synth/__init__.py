@@ -114,7 +114,7 @@ def flow_snapshots(grid=128, steps=300, modes=40, seed=1005, device="cpu", noise
     gen = _gen(seed, device)
     ks = []
     while len(ks) < modes:
-        kv = torch.randint(-kmax, kmax + 1, (3,), generator=gen, device="cpu")
+        kv = torch.randint(-kmax, kmax + 1, (3,), generator=gen, device=device).cpu()
         nrm = float(torch.linalg.vector_norm(kv.double()))
         if 0 < nrm <= kmax:
             ks.append(kv.double())
