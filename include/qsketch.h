@@ -207,7 +207,17 @@ qsk_status qsketch_batch_init(int32_t count, const qsk_config *cfgs, void *hip_s
    arrays are host arrays of device pointers.  reports (count entries) may
    be NULL.  Allocates nothing; synchronises the stream before returning.
    QSK_E_NUMERIC if some problem's sketch is zero or non-finite (the other
-   problems' outputs are still written). */
+   problems' outputs are still written).
+
+   By default (execution mode 2, see qsketch_batch_set_exec) the run is
+   first tried optimistically, every Cholesky factorisation assumed to
+   succeed: the whole sequence of launches is captured once per rangefinder
+   into a HIP graph on an internal stream (ordered after the caller's stream
+   and before its later work) and replayed on later calls with the same
+   pointer and leading-dimension arrays; a changed array recaptures.  If any
+   factorisation failed, the run is repeated with a host check after every
+   factorisation and the fallbacks of the single-problem driver.  Concurrent
+   runs on one batch handle race. */
 qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const *planes,
                              const int64_t *ld, double *const *Q, const int64_t *ldq,
                              double *const *X, const int64_t *ldx, qsk_report *reports);
@@ -217,6 +227,12 @@ qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const
 qsk_status qsketch_batch_rel_error(qsk_batch *b, const void *const *planes, const int64_t *ld,
                                    double *const *Q, const int64_t *ldq, double *const *X,
                                    const int64_t *ldx, double *err);
+
+/* Execution mode of qsketch_batch_run: 0 careful only (a host check after
+   every factorisation), 1 optimistic stream-ordered launches, 2 optimistic
+   as a replayed HIP graph (the default).  Modes give the same results when
+   no factorisation fails.  QSK_E_ARG for another value. */
+qsk_status qsketch_batch_set_exec(qsk_batch *b, int32_t mode);
 
 void qsketch_batch_destroy(qsk_batch *b);
 const char *qsketch_batch_last_error(const qsk_batch *b);

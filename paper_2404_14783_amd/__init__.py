@@ -105,6 +105,8 @@ def _load():
     lib.qsketch_batch_run.restype = i32
     lib.qsketch_batch_rel_error.argtypes = [vp, pp, pi64, pp, pi64, pp, pi64, ctypes.POINTER(ctypes.c_double)]
     lib.qsketch_batch_rel_error.restype = i32
+    lib.qsketch_batch_set_exec.argtypes = [vp, i32]
+    lib.qsketch_batch_set_exec.restype = i32
     lib.qsketch_batch_destroy.argtypes = [vp]
     lib.qsketch_batch_destroy.restype = None
     lib.qsketch_batch_last_error.argtypes = [vp]
@@ -337,6 +339,13 @@ class Batch:
         self._check(self._lib.qsketch_batch_run(self._b, RANGEFINDERS[rangefinder], ap, ald, qp, qld,
                                                 xp, xld, reps))
         return qs_, xs_, [r.as_dict() for r in reps]
+
+    EXEC_MODES = {"careful": 0, "stream": 1, "graph": 2}
+
+    def set_exec(self, mode):
+        """Execution of run(): 'careful', 'stream' (optimistic launches) or
+        'graph' (optimistic, captured once and replayed; the default)."""
+        self._check(self._lib.qsketch_batch_set_exec(self._b, self.EXEC_MODES[mode]))
 
     def rel_error(self, mats, qs_, xs_):
         ap, ald = self._ptr_tables(mats)

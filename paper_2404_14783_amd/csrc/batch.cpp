@@ -21,7 +21,7 @@ void *arena_push(ArgArena &a, hipStream_t st, const void *src, size_t bytes) {
   const size_t off = (a.used + 255) & ~(size_t)255;
   if (off + bytes > a.cap) return nullptr;
   std::memcpy(a.host + off, src, bytes);
-  if (hipMemcpyAsync(a.dev + off, a.host + off, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+  if (!a.defer && hipMemcpyAsync(a.dev + off, a.host + off, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
     return nullptr;
   a.used = off + bytes;
   return a.dev + off;
@@ -70,7 +70,17 @@ struct qsk_batch {
   double *err_acc = nullptr;
   qsk::ArgArena arena{};
   bool poisoned = false;
+  bool numeric_fail = false;
   std::string last_error;
+  // execution: 0 careful (a host check after every factorisation), 1
+  // optimistic stream-ordered, 2 optimistic as one captured graph per
+  // rangefinder (replayed while the caller's pointers stay the same)
+  int exec_mode = 2;
+  hipStream_t gstream = nullptr;       // the graphs' stream (the caller's may be the null stream)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  qsk::ArgArena garena[2] = {};        // argument tables of each graph, written once per capture
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  std::vector<uintptr_t> gkey[2];
 };
 
 namespace {
@@ -239,181 +249,45 @@ void planes_of(double *base, int64_t rows, int k, double *out[4]) {
 
 }  // namespace
 
-extern "C" {
-
-qsk_status qsketch_batch_init(int32_t count, const qsk_config *cfgs, void *hip_stream,
-                              qsk_batch **out) {
-  if (!out || !cfgs || count < 1) return QSK_E_ARG;
-  *out = nullptr;
-  const qsk_config &c0 = cfgs[0];
-  for (int i = 0; i < count; ++i) {
-    const qsk_config &c = cfgs[i];
-    if (c.m < 1 || c.n < 1 || c.m >= (1ll << 31) || c.n >= (1ll << 31)) return QSK_E_ARG;
-    if (c.k < 1 || c.l < c.k || c.l > c.m || c.l > c.n || c.k > 256 || c.l > 1024) return QSK_E_ARG;
-    if (c.embedding != QSK_GAUSSIAN && c.embedding != QSK_RADEMACHER) return QSK_E_ARG;
-    if (c.input_dtype < QSK_F64 || c.input_dtype > QSK_BF16) return QSK_E_ARG;
-    if (c.sketch_dtype < QSK_F64 || c.sketch_dtype > QSK_FP8_E4M3) return QSK_E_ARG;
-    if (c.n_correction < 0 || c.n_correction > 8 || c.n_power < 1 || c.n_power > 64) return QSK_E_ARG;
-    if (c.sketch_dtype == QSK_BF16 && (c.split_terms < 1 || c.split_terms > 3)) return QSK_E_ARG;
-    if (c.embedding != c0.embedding || c.input_dtype != c0.input_dtype ||
-        c.sketch_dtype != c0.sketch_dtype || c.pure != c0.pure ||
-        (c.sketch_dtype == QSK_BF16 && c.split_terms != c0.split_terms) ||
-        c.n_correction != c0.n_correction || c.n_power != c0.n_power)
-      return QSK_E_ARG;
-  }
-  if (c0.sketch_dtype != QSK_BF16 && c0.sketch_dtype != QSK_F32) return QSK_E_UNSUPPORTED;
-  if (c0.input_dtype == QSK_F64) return QSK_E_UNSUPPORTED;
-
-  qsk_batch *b = new (std::nothrow) qsk_batch;
-  if (!b) return QSK_E_NOMEM;
-  b->count = count;
-  b->stream = (hipStream_t)hip_stream;
-  b->mode = c0.sketch_dtype;
-  b->p.resize(count);
-  std::vector<int> ls(count), ks(count);
-  for (int i = 0; i < count; ++i) { ls[i] = cfgs[i].l; ks[i] = cfgs[i].k; }
-  qsk::batch_tiles(ls.data(), ks.data(), count, c0.sketch_dtype == QSK_BF16, &b->nmt, &b->nj);
-
-  // carve every problem's workspace out of one allocation
-  const size_t es = c0.sketch_dtype == QSK_BF16 ? 2 : 4;
-  size_t total = 0;
-  std::vector<std::vector<size_t>> off(count);
-  for (int i = 0; i < count; ++i) {
-    Prob &q = b->p[i];
-    q.cfg = cfgs[i];
-    if (c0.sketch_dtype != QSK_BF16) q.cfg.split_terms = 1;
-    q.m = cfgs[i].m; q.n = cfgs[i].n; q.k = cfgs[i].k; q.l = cfgs[i].l;
-    q.k0 = (uint32_t)(cfgs[i].seed & 0xFFFFFFFFull);
-    q.k1 = (uint32_t)(cfgs[i].seed >> 32);
-    qsk::stage_geometry_tiles(q.m, q.l, q.k, q.n, b->nmt, b->nj, &q.stage.LP, &q.stage.MP, &q.stage.KP,
-                              &q.stage.NP);
-    const size_t kk = (size_t)q.k * q.k * 4;
-    const int64_t maxk = q.l > q.k ? q.l : q.k;
-    q.partial_elems = 16 * maxk * q.k * 4;
-    const size_t sizes[] = {
-        4 * (size_t)q.m * q.k * 4,                 // y
-        4 * (size_t)q.l * q.n * 4,                 // w
-        4 * (size_t)q.m * q.k * 8,                 // u0
-        4 * (size_t)q.m * q.k * 8,                 // u1
-        (size_t)B_COUNT * kk * 8,                  // small
-        (12 * kk + 64 * (size_t)q.k) * 8,          // work
-        kk * 8,                                    // kwork
-        (size_t)q.partial_elems * 8,               // partials
-        4 * (size_t)q.l * q.k * 8,                 // pbuf
-        4 * (size_t)q.l * q.k * 8,                 // p1buf
-        4 * (size_t)q.l * q.k * 8,                 // sbuf
-        4 * (size_t)(q.l + q.k) * q.k * 8,         // pinv_work
-        4 * (size_t)q.stage.KP * q.stage.NP * es,  // omega staging
-        4 * (size_t)q.stage.LP * q.stage.MP * es,  // psi staging
-    };
-    for (size_t s : sizes) {
-      off[i].push_back(total);
-      total += al(s);
-    }
-  }
-  const size_t st_off = total;
-  total += al(sizeof(SmallStatus) * count) * 2 + al(16 * (size_t)count);
-  bool ok = hipMalloc(&b->pool, total) == hipSuccess;
-  const size_t arena_cap = 8u << 20;
-  ok = ok && hipHostMalloc((void **)&b->arena.host, arena_cap, hipHostMallocDefault) == hipSuccess;
-  ok = ok && hipMalloc((void **)&b->arena.dev, arena_cap) == hipSuccess;
-  b->arena.cap = arena_cap;
-  ok = ok && hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) == hipSuccess;
-  ok = ok && hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess;
-  ok = ok && hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) == hipSuccess;
-  if (!ok) {
-    (void)hipGetLastError();
-    qsketch_batch_destroy(b);
-    return QSK_E_NOMEM;
-  }
-  char *base = (char *)b->pool;
-  for (int i = 0; i < count; ++i) {
-    Prob &q = b->p[i];
-    const std::vector<size_t> &o = off[i];
-    q.y = (float *)(base + o[0]);
-    q.w = (float *)(base + o[1]);
-    q.u[0] = (double *)(base + o[2]);
-    q.u[1] = (double *)(base + o[3]);
-    q.small = (double *)(base + o[4]);
-    q.work = (double *)(base + o[5]);
-    q.kwork = (double *)(base + o[6]);
-    q.partials = (double *)(base + o[7]);
-    q.pbuf = (double *)(base + o[8]);
-    q.p1buf = (double *)(base + o[9]);
-    q.sbuf = (double *)(base + o[10]);
-    q.pinv_work = (double *)(base + o[11]);
-    q.stage.omega = base + o[12];
-    q.stage.psi = base + o[13];
-  }
-  b->status = (SmallStatus *)(base + st_off);
-  b->kstatus = (SmallStatus *)(base + st_off + al(sizeof(SmallStatus) * count));
-  b->err_acc = (double *)(base + st_off + 2 * al(sizeof(SmallStatus) * count));
-  // the test matrices are fixed per problem: stage them once
-  for (int i = 0; i < count; ++i) {
-    Prob &q = b->p[i];
-    qsk::SketchArgs s{};
-    s.stream = b->stream; s.mode = b->mode; s.m = q.m; s.col0 = 0; s.ncols = q.n; s.k = q.k; s.l = q.l;
-    s.rad = q.cfg.embedding == QSK_RADEMACHER; s.k0 = q.k0; s.k1 = q.k1;
-    hipError_t e = qsk::stage_test_matrices(s, q.stage);
-    if (e != hipSuccess) {
-      qsketch_batch_destroy(b);
-      return QSK_E_HIP;
-    }
-  }
-  if (hipStreamSynchronize(b->stream) != hipSuccess) {
-    qsketch_batch_destroy(b);
-    return QSK_E_HIP;
-  }
-  *out = b;
-  return QSK_OK;
-}
-
-void qsketch_batch_destroy(qsk_batch *b) {
-  if (!b) return;
-  if (b->stream || true) (void)hipStreamSynchronize(b->stream);
-  if (b->side) (void)hipStreamSynchronize(b->side);
-  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
-  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
-  if (b->side) (void)hipStreamDestroy(b->side);
-  if (b->pool) (void)hipFree(b->pool);
-  if (b->arena.dev) (void)hipFree(b->arena.dev);
-  if (b->arena.host) (void)hipHostFree(b->arena.host);
-  delete b;
-}
-
-const char *qsketch_batch_last_error(const qsk_batch *b) {
-  if (!b) return "null batch";
-  return b->last_error.c_str();
-}
-
-qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const *planes,
+// Every step of one batched run, stream-ordered on b->stream.  opt: no host
+// synchronisation (every factorisation assumed to succeed, failures only
+// recorded in the sticky status flag); the caller prepares the arena.
+static qsk_status batch_body(qsk_batch *b, qsk_rangefinder rf, const void *const *planes,
                              const int64_t *ld, double *const *Q, const int64_t *ldq,
-                             double *const *X, const int64_t *ldx, qsk_report *reports) {
-  if (!b) return QSK_E_ARG;
-  if (b->poisoned) return QSK_E_STATE;
-  if (rf != QSK_PSEUDO_QR && rf != QSK_PSEUDO_SVD) return QSK_E_ARG;
-  if (!planes || !ld || !Q || !ldq || !X || !ldx) return QSK_E_ARG;
-  const int n_all = b->count;
-  for (int i = 0; i < n_all; ++i) {
-    const Prob &q = b->p[i];
-    if (ld[i] < q.m || ldq[i] < q.m || ldx[i] < q.k) return QSK_E_ARG;
-    for (int p = q.cfg.pure ? 1 : 0; p < 4; ++p)
-      if (!planes[4 * i + p]) return QSK_E_ARG;
-    for (int p = 0; p < 4; ++p)
-      if (!Q[4 * i + p] || !X[4 * i + p]) return QSK_E_ARG;
-  }
+                             double *const *X, const int64_t *ldx, bool opt) {
   hipStream_t st = b->stream;
-  BCHK(b, hipStreamSynchronize(st));        // previous users of the arena are done
-  b->arena.used = 0;
+  if (!opt) {
+    BCHK(b, hipStreamSynchronize(st));      // previous users of the arena are done
+    b->arena.used = 0;
+  }
+  const int n_all = b->count;
   std::vector<int> all(n_all);
   for (int i = 0; i < n_all; ++i) all[i] = i;
 
   // ---- sketches (Section 4.1): Y = A Omega, W = Psi A of every problem
-  for (int i = 0; i < n_all; ++i) {
-    Prob &q = b->p[i];
-    BCHK(b, hipMemsetAsync(q.y, 0, 4 * (size_t)q.m * q.k * 4, st));
-    BCHK(b, hipMemsetAsync(q.w, 0, 4 * (size_t)q.l * q.n * 4, st));
-    q.passes = 0; q.need = 2; q.flags = 0; q.z_is_u = false;
+  b->numeric_fail = false;
+  {
+    // Y, W and the statuses start at zero (by kernel: no memset nodes in a graph)
+    std::vector<qsk::ZeroArgs> za(2 * n_all + 1);
+    std::vector<int64_t> zb(2 * n_all + 1);
+    for (int i = 0; i < n_all; ++i) {
+      Prob &q = b->p[i];
+      q.passes = 0; q.need = 2; q.flags = 0; q.z_is_u = false;
+      za[2 * i].p = q.y; za[2 * i].n16 = (int64_t)q.m * q.k;          // 4 planes x 4 bytes
+      za[2 * i + 1].p = q.w; za[2 * i + 1].n16 = (int64_t)q.l * q.n;
+    }
+    // status and kstatus are adjacent, each padded to 256 bytes
+    za[2 * n_all].p = b->status;
+    za[2 * n_all].n16 = (int64_t)(((char *)b->kstatus - (char *)b->status) + sizeof(SmallStatus) * n_all) / 16;
+    for (size_t i = 0; i < za.size(); ++i) {
+      za[i].gx = (int)((za[i].n16 + qsk::ZERO_UNITS_PER_BLOCK - 1) / qsk::ZERO_UNITS_PER_BLOCK);
+      za[i].gy = 1;
+      zb[i] = za[i].gx;
+    }
+    GroupRef g;
+    int64_t tot;
+    if (!push_group(b, za, zb, &g, &tot)) return arena_full(b);
+    BCHK(b, qsk::launch_zero_k(st, za[0], g, tot));
   }
   {
     std::vector<qsk::SketchArgs> sa(n_all);
@@ -440,7 +314,7 @@ qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const
     for (int p = 0; p < 4; ++p) q.zsrc[p] = nullptr;
     q.gz = q.slot(B_G1);
   }
-  std::vector<SmallStatus> hs;
+  std::vector<SmallStatus> hs(n_all);     // all-successful unless read (careful mode)
   std::vector<int> active = all;
   bool numeric_fail = false;
   const int max_passes = 8;
@@ -464,7 +338,7 @@ qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const
                  [](int) { return 0.0; }, 1e-13, [](const Prob &q) { return q.slot(B_R); },
                  [](const Prob &q) { return q.slot(B_T); }, 0);
     if (r != QSK_OK) return r;
-    if ((r = read_status(b, hs)) != QSK_OK) return r;
+    if (!opt && (r = read_status(b, hs)) != QSK_OK) return r;
     std::vector<int> failed;
     std::vector<double> shifts(n_all, 0.0);
     for (int i : active) {
@@ -484,7 +358,7 @@ qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const
                    [&](int i) { return shifts[i]; }, 0.0, [](const Prob &q) { return q.slot(B_R); },
                    [](const Prob &q) { return q.slot(B_T); }, 1);
       if (r != QSK_OK) return r;
-      if ((r = read_status(b, hs)) != QSK_OK) return r;
+      if (!opt && (r = read_status(b, hs)) != QSK_OK) return r;
       for (int i : failed) {
         Prob &q = b->p[i];
         if (hs[i].fail) { numeric_fail = true; q.need = -1; continue; }
@@ -542,8 +416,9 @@ qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const
   for (int i : all)
     if (b->p[i].need >= 0) ok_ids.push_back(i);
 
-  BCHK(b, hipMemsetAsync(b->status, 0, sizeof(SmallStatus) * n_all, st));
-  BCHK(b, hipMemsetAsync(b->kstatus, 0, sizeof(SmallStatus) * n_all, st));
+  // the optimistic run keeps the sticky failure flag of the passes above
+  BCHK(b, qsk::launch_status_reset_n(st, b->status, n_all, opt ? 1 : 0));
+  BCHK(b, qsk::launch_status_reset_n(st, b->kstatus, n_all, 0));
   qsk_status r = QSK_OK;
   auto S = [](int s) { return [s](const Prob &q) { return q.slot(s); }; };
   auto SC = [](int s) { return [s](const Prob &q) { return (const double *)q.slot(s); }; };
@@ -587,7 +462,7 @@ qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const
     for (int j = 0; j < b->p[0].cfg.n_correction && !corr.empty(); ++j) {
       if ((r = chol_all(b, corr, SC(B_G0), 0, [](int) { return 0.0; }, 1e-13, S(B_CR), S(B_CT), 0)) != QSK_OK)
         return r;
-      if ((r = read_status(b, hs)) != QSK_OK) return r;
+      if (!opt && (r = read_status(b, hs)) != QSK_OK) return r;
       std::vector<int> go;
       for (int i : corr) {
         if (hs[i].fail) b->p[i].flags |= QSK_FLAG_RANK_DEFICIENT;
@@ -722,7 +597,7 @@ qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const
   if ((r = crossprod_all(b, ok_ids, 0, 0, PZ(&Prob::pbuf), PZ(&Prob::pbuf), S(B_GP), true)) != QSK_OK) return r;
   if ((r = chol_all(b, ok_ids, SC(B_GP), 0, [](int) { return 0.0; }, 1e-13, S(B_RP), S(B_TP1), 0)) != QSK_OK)
     return r;
-  if ((r = read_status(b, hs)) != QSK_OK) return r;
+  if (!opt && (r = read_status(b, hs)) != QSK_OK) return r;
   std::vector<int> p_ok, p_bad;
   for (int i : ok_ids) (hs[i].fail ? p_bad : p_ok).push_back(i);
   if ((r = pinv_all(p_bad)) != QSK_OK) return r;
@@ -730,7 +605,7 @@ qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const
   if ((r = crossprod_all(b, p_ok, 0, 0, PZ(&Prob::p1buf), PZ(&Prob::p1buf), S(B_GP), true)) != QSK_OK) return r;
   if ((r = chol_all(b, p_ok, SC(B_GP), 0, [](int) { return 0.0; }, 1e-13, S(B_RP), S(B_TP2), 0)) != QSK_OK)
     return r;
-  if ((r = read_status(b, hs)) != QSK_OK) return r;
+  if (!opt && (r = read_status(b, hs)) != QSK_OK) return r;
   std::vector<int> p_ok2, p_bad2;
   for (int i : p_ok) (hs[i].fail ? p_bad2 : p_ok2).push_back(i);
   if ((r = pinv_all(p_bad2)) != QSK_OK) return r;
@@ -760,13 +635,29 @@ qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const
     if (!push_group(b, a, nb, &g, &tot)) return arena_full(b);
     BCHK(b, qsk::launch_crossprod_k(st, 0, 1, a[0], g, tot));
   }
-  // join the kappa side stream and collect the reports
+  // join the kappa side stream
   BCHK(b, hipStreamWaitEvent(st, b->ev_join, 0));
-  std::vector<SmallStatus> ks(n_all);
-  hs.resize(n_all);
+  b->numeric_fail = numeric_fail;
+  return QSK_OK;
+}
+
+// Read the statuses of the run just issued (one synchronisation) and fill
+// the reports.  After an optimistic run *retry says whether any
+// factorisation failed, in which case nothing is reported.
+static qsk_status batch_collect(qsk_batch *b, qsk_rangefinder rf, qsk_report *reports, bool opt,
+                                bool *retry) {
+  const int n_all = b->count;
+  hipStream_t st = b->stream;
+  *retry = false;
+  std::vector<SmallStatus> hs(n_all), ks(n_all);
   BCHK(b, hipMemcpyAsync(hs.data(), b->status, sizeof(SmallStatus) * n_all, hipMemcpyDeviceToHost, st));
   BCHK(b, hipMemcpyAsync(ks.data(), b->kstatus, sizeof(SmallStatus) * n_all, hipMemcpyDeviceToHost, st));
   BCHK(b, hipStreamSynchronize(st));
+  if (opt) {
+    for (int i = 0; i < n_all; ++i)
+      if (hs[i].fail_any) *retry = true;
+    if (*retry) return QSK_OK;
+  }
   if (reports) {
     for (int i = 0; i < n_all; ++i) {
       const Prob &q = b->p[i];
@@ -776,17 +667,283 @@ qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const
       rep.n_eps = hs[i].n_eps;
       for (int e = 0; e < 8; ++e) rep.eps[e] = hs[i].eps[e];
       rep.t_bad = hs[i].t_bad;
-      rep.flags = q.flags | hs[i].flags | (q.need < 0 ? QSK_FLAG_NONFINITE : 0);
-      rep.passes = q.passes;
+      rep.flags = opt ? hs[i].flags : (q.flags | hs[i].flags | (q.need < 0 ? QSK_FLAG_NONFINITE : 0));
+      rep.passes = opt ? 2 : q.passes;
       rep.columns_seen = q.n;
       rep.orth_defect = rf == QSK_PSEUDO_SVD ? ks[i].orth_defect : 0.0;
       reports[i] = rep;
     }
   }
-  if (numeric_fail) {
+  if (!opt && b->numeric_fail) {
     b->last_error = "a problem's sketch Y is zero or non-finite";
     return QSK_E_NUMERIC;
   }
+  return QSK_OK;
+}
+
+// The optimistic run as a graph on b->gstream: captured on first use (and
+// again when the caller's pointers change), then replayed.  The argument
+// tables go to the graph's own arena once, after the capture, so the graph
+// holds kernel nodes only.
+static qsk_status batch_graph(qsk_batch *b, qsk_rangefinder rf, const void *const *planes,
+                              const int64_t *ld, double *const *Q, const int64_t *ldq,
+                              double *const *X, const int64_t *ldx) {
+  const int n_all = b->count;
+  const int gi = rf == QSK_PSEUDO_SVD ? 1 : 0;
+  std::vector<uintptr_t> key;
+  key.reserve(16 * (size_t)n_all);
+  for (int i = 0; i < n_all; ++i) {
+    for (int p = 0; p < 4; ++p) {
+      key.push_back((uintptr_t)planes[4 * i + p]);
+      key.push_back((uintptr_t)Q[4 * i + p]);
+      key.push_back((uintptr_t)X[4 * i + p]);
+    }
+    key.push_back((uintptr_t)ld[i]);
+    key.push_back((uintptr_t)ldq[i]);
+    key.push_back((uintptr_t)ldx[i]);
+  }
+  hipStream_t user = b->stream;
+  BCHK(b, hipEventRecord(b->ev_in, user));
+  BCHK(b, hipStreamWaitEvent(b->gstream, b->ev_in, 0));
+  if (!b->gexec[gi] || key != b->gkey[gi]) {
+    if (b->gexec[gi]) {
+      BCHK(b, hipStreamSynchronize(b->gstream));
+      (void)hipGraphExecDestroy(b->gexec[gi]);
+      b->gexec[gi] = nullptr;
+    }
+    std::swap(b->arena, b->garena[gi]);
+    b->arena.used = 0;
+    b->arena.defer = true;
+    b->stream = b->gstream;
+    hipError_t e = hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal);
+    qsk_status r = e == hipSuccess ? batch_body(b, rf, planes, ld, Q, ldq, X, ldx, true) : QSK_E_HIP;
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(b->gstream, &graph) : e;
+    b->stream = user;
+    b->arena.defer = false;
+    std::swap(b->arena, b->garena[gi]);
+    if (r != QSK_OK || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      if (r != QSK_OK) return r;
+      return bfail(b, e2, "graph capture");
+    }
+    const hipError_t e3 = hipGraphInstantiate(&b->gexec[gi], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) {
+      b->gexec[gi] = nullptr;
+      return bfail(b, e3, "hipGraphInstantiate");
+    }
+    BCHK(b, hipMemcpyAsync(b->garena[gi].dev, b->garena[gi].host, b->garena[gi].used,
+                           hipMemcpyHostToDevice, b->gstream));
+    b->gkey[gi] = key;
+  }
+  BCHK(b, hipGraphLaunch(b->gexec[gi], b->gstream));
+  BCHK(b, hipEventRecord(b->ev_out, b->gstream));
+  BCHK(b, hipStreamWaitEvent(user, b->ev_out, 0));
+  return QSK_OK;
+}
+
+extern "C" {
+
+qsk_status qsketch_batch_init(int32_t count, const qsk_config *cfgs, void *hip_stream,
+                              qsk_batch **out) {
+  if (!out || !cfgs || count < 1) return QSK_E_ARG;
+  *out = nullptr;
+  const qsk_config &c0 = cfgs[0];
+  for (int i = 0; i < count; ++i) {
+    const qsk_config &c = cfgs[i];
+    if (c.m < 1 || c.n < 1 || c.m >= (1ll << 31) || c.n >= (1ll << 31)) return QSK_E_ARG;
+    if (c.k < 1 || c.l < c.k || c.l > c.m || c.l > c.n || c.k > 256 || c.l > 1024) return QSK_E_ARG;
+    if (c.embedding != QSK_GAUSSIAN && c.embedding != QSK_RADEMACHER) return QSK_E_ARG;
+    if (c.input_dtype < QSK_F64 || c.input_dtype > QSK_BF16) return QSK_E_ARG;
+    if (c.sketch_dtype < QSK_F64 || c.sketch_dtype > QSK_FP8_E4M3) return QSK_E_ARG;
+    if (c.n_correction < 0 || c.n_correction > 8 || c.n_power < 1 || c.n_power > 64) return QSK_E_ARG;
+    if (c.sketch_dtype == QSK_BF16 && (c.split_terms < 1 || c.split_terms > 3)) return QSK_E_ARG;
+    if (c.embedding != c0.embedding || c.input_dtype != c0.input_dtype ||
+        c.sketch_dtype != c0.sketch_dtype || c.pure != c0.pure ||
+        (c.sketch_dtype == QSK_BF16 && c.split_terms != c0.split_terms) ||
+        c.n_correction != c0.n_correction || c.n_power != c0.n_power)
+      return QSK_E_ARG;
+  }
+  if (c0.sketch_dtype != QSK_BF16 && c0.sketch_dtype != QSK_F32) return QSK_E_UNSUPPORTED;
+  if (c0.input_dtype == QSK_F64) return QSK_E_UNSUPPORTED;
+
+  qsk_batch *b = new (std::nothrow) qsk_batch;
+  if (!b) return QSK_E_NOMEM;
+  b->count = count;
+  b->stream = (hipStream_t)hip_stream;
+  b->mode = c0.sketch_dtype;
+  b->p.resize(count);
+  std::vector<int> ls(count), ks(count);
+  for (int i = 0; i < count; ++i) { ls[i] = cfgs[i].l; ks[i] = cfgs[i].k; }
+  qsk::batch_tiles(ls.data(), ks.data(), count, c0.sketch_dtype == QSK_BF16, &b->nmt, &b->nj);
+
+  // carve every problem's workspace out of one allocation
+  const size_t es = c0.sketch_dtype == QSK_BF16 ? 2 : 4;
+  size_t total = 0;
+  std::vector<std::vector<size_t>> off(count);
+  for (int i = 0; i < count; ++i) {
+    Prob &q = b->p[i];
+    q.cfg = cfgs[i];
+    if (c0.sketch_dtype != QSK_BF16) q.cfg.split_terms = 1;
+    q.m = cfgs[i].m; q.n = cfgs[i].n; q.k = cfgs[i].k; q.l = cfgs[i].l;
+    q.k0 = (uint32_t)(cfgs[i].seed & 0xFFFFFFFFull);
+    q.k1 = (uint32_t)(cfgs[i].seed >> 32);
+    qsk::stage_geometry_tiles(q.m, q.l, q.k, q.n, b->nmt, b->nj, &q.stage.LP, &q.stage.MP, &q.stage.KP,
+                              &q.stage.NP);
+    const size_t kk = (size_t)q.k * q.k * 4;
+    const int64_t maxk = q.l > q.k ? q.l : q.k;
+    q.partial_elems = 16 * maxk * q.k * 4;
+    const size_t sizes[] = {
+        4 * (size_t)q.m * q.k * 4,                 // y
+        4 * (size_t)q.l * q.n * 4,                 // w
+        4 * (size_t)q.m * q.k * 8,                 // u0
+        4 * (size_t)q.m * q.k * 8,                 // u1
+        (size_t)B_COUNT * kk * 8,                  // small
+        (12 * kk + 64 * (size_t)q.k) * 8,          // work
+        kk * 8,                                    // kwork
+        (size_t)q.partial_elems * 8,               // partials
+        4 * (size_t)q.l * q.k * 8,                 // pbuf
+        4 * (size_t)q.l * q.k * 8,                 // p1buf
+        4 * (size_t)q.l * q.k * 8,                 // sbuf
+        4 * (size_t)(q.l + q.k) * q.k * 8,         // pinv_work
+        4 * (size_t)q.stage.KP * q.stage.NP * es,  // omega staging
+        4 * (size_t)q.stage.LP * q.stage.MP * es,  // psi staging
+    };
+    for (size_t s : sizes) {
+      off[i].push_back(total);
+      total += al(s);
+    }
+  }
+  const size_t st_off = total;
+  total += al(sizeof(SmallStatus) * count) * 2 + al(16 * (size_t)count);
+  bool ok = hipMalloc(&b->pool, total) == hipSuccess;
+  const size_t arena_cap = 8u << 20;
+  ok = ok && hipHostMalloc((void **)&b->arena.host, arena_cap, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipMalloc((void **)&b->arena.dev, arena_cap) == hipSuccess;
+  b->arena.cap = arena_cap;
+  ok = ok && hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess;
+  for (int r = 0; r < 2; ++r) {
+    ok = ok && hipHostMalloc((void **)&b->garena[r].host, arena_cap, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b->garena[r].dev, arena_cap) == hipSuccess;
+    b->garena[r].cap = arena_cap;
+  }
+  if (!ok) {
+    (void)hipGetLastError();
+    qsketch_batch_destroy(b);
+    return QSK_E_NOMEM;
+  }
+  char *base = (char *)b->pool;
+  for (int i = 0; i < count; ++i) {
+    Prob &q = b->p[i];
+    const std::vector<size_t> &o = off[i];
+    q.y = (float *)(base + o[0]);
+    q.w = (float *)(base + o[1]);
+    q.u[0] = (double *)(base + o[2]);
+    q.u[1] = (double *)(base + o[3]);
+    q.small = (double *)(base + o[4]);
+    q.work = (double *)(base + o[5]);
+    q.kwork = (double *)(base + o[6]);
+    q.partials = (double *)(base + o[7]);
+    q.pbuf = (double *)(base + o[8]);
+    q.p1buf = (double *)(base + o[9]);
+    q.sbuf = (double *)(base + o[10]);
+    q.pinv_work = (double *)(base + o[11]);
+    q.stage.omega = base + o[12];
+    q.stage.psi = base + o[13];
+  }
+  b->status = (SmallStatus *)(base + st_off);
+  b->kstatus = (SmallStatus *)(base + st_off + al(sizeof(SmallStatus) * count));
+  b->err_acc = (double *)(base + st_off + 2 * al(sizeof(SmallStatus) * count));
+  // the test matrices are fixed per problem: stage them once
+  for (int i = 0; i < count; ++i) {
+    Prob &q = b->p[i];
+    qsk::SketchArgs s{};
+    s.stream = b->stream; s.mode = b->mode; s.m = q.m; s.col0 = 0; s.ncols = q.n; s.k = q.k; s.l = q.l;
+    s.rad = q.cfg.embedding == QSK_RADEMACHER; s.k0 = q.k0; s.k1 = q.k1;
+    hipError_t e = qsk::stage_test_matrices(s, q.stage);
+    if (e != hipSuccess) {
+      qsketch_batch_destroy(b);
+      return QSK_E_HIP;
+    }
+  }
+  if (hipStreamSynchronize(b->stream) != hipSuccess) {
+    qsketch_batch_destroy(b);
+    return QSK_E_HIP;
+  }
+  *out = b;
+  return QSK_OK;
+}
+
+void qsketch_batch_destroy(qsk_batch *b) {
+  if (!b) return;
+  if (b->stream || true) (void)hipStreamSynchronize(b->stream);
+  if (b->side) (void)hipStreamSynchronize(b->side);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  if (b->gstream) (void)hipStreamSynchronize(b->gstream);
+  for (int r = 0; r < 2; ++r) {
+    if (b->gexec[r]) (void)hipGraphExecDestroy(b->gexec[r]);
+    if (b->garena[r].dev) (void)hipFree(b->garena[r].dev);
+    if (b->garena[r].host) (void)hipHostFree(b->garena[r].host);
+  }
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->gstream) (void)hipStreamDestroy(b->gstream);
+  if (b->side) (void)hipStreamDestroy(b->side);
+  if (b->pool) (void)hipFree(b->pool);
+  if (b->arena.dev) (void)hipFree(b->arena.dev);
+  if (b->arena.host) (void)hipHostFree(b->arena.host);
+  delete b;
+}
+
+const char *qsketch_batch_last_error(const qsk_batch *b) {
+  if (!b) return "null batch";
+  return b->last_error.c_str();
+}
+
+qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const *planes,
+                             const int64_t *ld, double *const *Q, const int64_t *ldq,
+                             double *const *X, const int64_t *ldx, qsk_report *reports) {
+  if (!b) return QSK_E_ARG;
+  if (b->poisoned) return QSK_E_STATE;
+  if (rf != QSK_PSEUDO_QR && rf != QSK_PSEUDO_SVD) return QSK_E_ARG;
+  if (!planes || !ld || !Q || !ldq || !X || !ldx) return QSK_E_ARG;
+  const int n_all = b->count;
+  for (int i = 0; i < n_all; ++i) {
+    const Prob &q = b->p[i];
+    if (ld[i] < q.m || ldq[i] < q.m || ldx[i] < q.k) return QSK_E_ARG;
+    for (int p = q.cfg.pure ? 1 : 0; p < 4; ++p)
+      if (!planes[4 * i + p]) return QSK_E_ARG;
+    for (int p = 0; p < 4; ++p)
+      if (!Q[4 * i + p] || !X[4 * i + p]) return QSK_E_ARG;
+  }
+  qsk_status r;
+  bool retry = false;
+  if (b->exec_mode == 2) {
+    if ((r = batch_graph(b, rf, planes, ld, Q, ldq, X, ldx)) != QSK_OK) return r;
+    if ((r = batch_collect(b, rf, reports, true, &retry)) != QSK_OK) return r;
+    if (!retry) return QSK_OK;
+  } else if (b->exec_mode == 1) {
+    BCHK(b, hipStreamSynchronize(b->stream));
+    b->arena.used = 0;
+    if ((r = batch_body(b, rf, planes, ld, Q, ldq, X, ldx, true)) != QSK_OK) return r;
+    if ((r = batch_collect(b, rf, reports, true, &retry)) != QSK_OK) return r;
+    if (!retry) return QSK_OK;
+  }
+  if ((r = batch_body(b, rf, planes, ld, Q, ldq, X, ldx, false)) != QSK_OK) return r;
+  return batch_collect(b, rf, reports, false, &retry);
+}
+
+qsk_status qsketch_batch_set_exec(qsk_batch *b, int32_t mode) {
+  if (!b || mode < 0 || mode > 2) return QSK_E_ARG;
+  if (b->poisoned) return QSK_E_STATE;
+  b->exec_mode = mode;
   return QSK_OK;
 }
 

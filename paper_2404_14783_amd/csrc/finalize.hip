@@ -1089,6 +1089,34 @@ hipError_t launch_status_reset(hipStream_t st, SmallStatus *s, int keep_fail_any
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void status_reset_n_kernel(SmallStatus *s, int count, int keep_fail_any) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    const int fa = keep_fail_any ? s[i].fail_any : 0;
+    s[i] = SmallStatus{};
+    s[i].fail_any = fa;
+  }
+}
+hipError_t launch_status_reset_n(hipStream_t st, SmallStatus *s, int count, int keep_fail_any) {
+  hipLaunchKernelGGL(status_reset_n_kernel, dim3(1), dim3(256), 0, st, s, count, keep_fail_any);
+  return hipGetLastError();
+}
+
+// Zeroing by a kernel instead of a memset command, so that a captured graph
+// holds kernel nodes only.
+__global__ __launch_bounds__(256) void zero_kernel(ZeroArgs args, GroupRef grp) {
+  ZeroArgs A;
+  int bx, by, bz;
+  if (!group_select(args, grp, A, bx, by, bz)) return;
+  uint4 *p = (uint4 *)A.p;
+  const int64_t base = (int64_t)bx * ZERO_UNITS_PER_BLOCK;
+  for (int j = threadIdx.x; j < ZERO_UNITS_PER_BLOCK; j += 256)
+    if (base + j < A.n16) p[base + j] = make_uint4(0u, 0u, 0u, 0u);
+}
+hipError_t launch_zero_k(hipStream_t st, const ZeroArgs &a, GroupRef g, int64_t blocks) {
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)(g.tab ? blocks : a.gx)), dim3(256), 0, st, a, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_chol_k(hipStream_t st, const CholArgs &a, GroupRef g, int count) {
   hipLaunchKernelGGL(chol_kernel, dim3(g.tab ? count : 1), dim3(1024), 0, st, a, g);
   return hipGetLastError();

@@ -59,6 +59,7 @@ struct ArgArena {
   char *host;
   char *dev;
   size_t cap, used;
+  bool defer;          // tables only written to host; the caller copies [0, used) later
 };
 void *arena_push(ArgArena &a, hipStream_t st, const void *src, size_t bytes);
 
@@ -262,6 +263,12 @@ hipError_t launch_psi_apply_k(hipStream_t st, const PsiApplyArgs &a, GroupRef g,
 hipError_t launch_error_k(hipStream_t st, int tin, const ErrorArgs &a, GroupRef g, int64_t blocks);
 // Zero a status; keep_fail_any = 1 leaves the sticky fail_any as it is.
 hipError_t launch_status_reset(hipStream_t st, SmallStatus *s, int keep_fail_any);
+// count consecutive statuses, the same way
+hipError_t launch_status_reset_n(hipStream_t st, SmallStatus *s, int count, int keep_fail_any);
+// Zero a buffer of n16 16-byte units (grouped: one entry per buffer).
+struct ZeroArgs { void *p; int64_t n16; int gx, gy; };
+constexpr int ZERO_UNITS_PER_BLOCK = 1024;
+hipError_t launch_zero_k(hipStream_t st, const ZeroArgs &a, GroupRef g, int64_t blocks);
 hipError_t launch_chol_k(hipStream_t st, const CholArgs &a, GroupRef g, int count);
 hipError_t launch_triinv_k(hipStream_t st, const CholArgs &a, GroupRef g, int64_t blocks);
 hipError_t launch_gemm_k(hipStream_t st, const GemmArgs &a, GroupRef g, int64_t blocks);

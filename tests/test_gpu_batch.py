@@ -103,3 +103,38 @@ def test_batch_rerun_is_repeatable():
     for i in range(3):
         assert torch.equal(q1[i], q2[i]) and torch.equal(x1[i], x2[i])
     b.close()
+
+
+@pytest.mark.parametrize("kind", ["pseudo_qr", "pseudo_svd"])
+def test_batch_graph_replays_match_careful_run(kind):
+    """The optimistic run, issued as stream-ordered launches and as a
+    captured graph, gives the careful run's outputs bit for bit.  The graph
+    is replayed several times with other work in between (a careful run of
+    the other rangefinder, an error pass), and recaptured when the output
+    buffers change; every replay is checked."""
+    other = "pseudo_svd" if kind == "pseudo_qr" else "pseudo_qr"
+    mats = inputs(SHAPES, "f32")
+    devs = [to_device(a, "f32") for a in mats]
+    b = qs.Batch(SHAPES, input_dtype="f32", sketch_dtype="bf16", split_terms=2)
+    b.set_exec("careful")
+    q0, x0, r0 = b.run(devs, kind)
+    b.set_exec("stream")
+    q1, x1, r1 = b.run(devs, kind)
+    for i in range(len(SHAPES)):
+        assert torch.equal(q0[i], q1[i]) and torch.equal(x0[i], x1[i]), i
+        assert r0[i]["kappa"] == r1[i]["kappa"] and r0[i]["passes"] == r1[i]["passes"], i
+    outs = b.outputs()
+    for rep in range(4):
+        b.set_exec("graph")
+        if rep == 2:
+            outs = b.outputs()                     # new pointers: a new capture
+        q2, x2, r2 = b.run(devs, kind, outputs=outs)
+        torch.cuda.synchronize()
+        for i in range(len(SHAPES)):
+            assert torch.equal(q0[i], q2[i]) and torch.equal(x0[i], x2[i]), (rep, i)
+            assert r0[i]["kappa"] == r2[i]["kappa"], (rep, i)
+        # other work between the replays
+        b.set_exec("careful")
+        b.run(devs, other)
+        b.rel_error(devs, q2, x2)
+    b.close()
