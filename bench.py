@@ -216,10 +216,23 @@ def bench_batch(args):
     shapes = [(sp["m"], sp["n"], sp["k"], sp["l"], i) for i, sp in enumerate(specs)]
     torch.cuda.synchronize()
     flops = sum(sketch_flops(m, n, k, l) for (m, n, k, l, _) in shapes)
+    if args.profile_only:
+        b = qs.Batch(shapes, input_dtype="f32", sketch_dtype="bf16", split_terms=args.terms)
+        b.autotune(mats)
+        outs = b.outputs()
+        for kind in ("pseudo_qr", "pseudo_svd"):
+            for _ in range(max(1, args.steps)):
+                b.run(mats, kind, outputs=outs)
+        torch.cuda.synchronize()
+        b.close()
+        print(json.dumps({"profile_only": True, "workload": "batch64"}))
+        return
     out = {}
     errs = {}
+    tiles = {}
     for name, sketch, terms in (("fp32", "f32", 1), ("bf16", "bf16", args.terms)):
         b = qs.Batch(shapes, input_dtype="f32", sketch_dtype=sketch, split_terms=terms)
+        tiles[name] = b.autotune(mats)
         outs = b.outputs()
         st = torch.cuda.current_stream()
         for kind in ("pseudo_qr", "pseudo_svd"):
@@ -262,6 +275,7 @@ def bench_batch(args):
                                "pseudo-QR plus one with pseudo-SVD (sketches recomputed in each)",
                    "problems": len(shapes), "sketch_flops_per_run": flops, "bf16_terms": args.terms},
         "paths": out, "speedup_vs_fp32_wall": fp32_ms / step_ms,
+        "autotuned_tiles": {k: {"w_row_tiles": v[0], "y_col_tiles": v[1]} for k, v in tiles.items()},
         "equal_error": {"max_rel_diff_bf16_vs_fp64": worst, "problems_checked": nref},
         "roofline": None, "cpu_baseline": None,
     }

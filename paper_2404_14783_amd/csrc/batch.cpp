@@ -6,8 +6,11 @@
 // finds its problem from the prefix sums of the block counts.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -64,7 +67,7 @@ struct qsk_batch {
   hipStream_t stream = nullptr, side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<Prob> p;
-  int mode = 0, nmt = 4, nj = 4;
+  int mode = 0, nmt = 4, nj = 4;       // tile shapes of the grouped sketch launches
   void *pool = nullptr;
   SmallStatus *status = nullptr, *kstatus = nullptr;
   double *err_acc = nullptr;
@@ -86,6 +89,17 @@ struct qsk_batch {
 namespace {
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+int64_t rup_i(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+// Tile shapes of the grouped sketch launches: row tiles of W per block
+// (13 only with bf16 operands) and column tiles of Y per block.
+const int kNmt[3] = {4, 7, 13}, kNj[2] = {4, 7};
+// the largest of rup(x, 16 t) over the first n tile counts t
+int64_t max_pad(int64_t x, const int *t, int n) {
+  int64_t r = 0;
+  for (int i = 0; i < n; ++i) r = std::max(r, rup_i(x, 16 * (int64_t)t[i]));
+  return r;
+}
 
 qsk_status bfail(qsk_batch *b, hipError_t e, const char *where) {
   b->poisoned = true;
@@ -179,60 +193,76 @@ qsk_status chol_all(qsk_batch *b, const std::vector<int> &ids, FG fg, int comple
   return QSK_OK;
 }
 
-// C_i = Z1_i^* Z2_i (AoS k1 x k2) through row-chunk partial sums.
+// Rows per K chunk of a grouped split-K product: one length for all
+// problems, so that the waves (one 16 x 16 tile each) get equal work and
+// about 4096 of them run in all.
+int64_t group_chunk(const std::vector<int64_t> &rows, const std::vector<int64_t> &tiles) {
+  double work = 0.0;
+  for (size_t i = 0; i < rows.size(); ++i) work += (double)rows[i] * (double)tiles[i];
+  int64_t c = (int64_t)(work / 4096.0);
+  c = (c + 15) / 16 * 16;
+  return c < 64 ? 64 : c;
+}
+
+// C_i = Z1_i^* Z2_i (AoS k x k) on the FP64 matrix cores through row-chunk
+// partial sums.
 template <typename FZ1, typename FZ2, typename FO>
 qsk_status crossprod_all(qsk_batch *b, const std::vector<int> &ids, int t1, int t2, FZ1 fz1, FZ2 fz2,
                          FO fo, bool tall_l) {
   if (ids.empty()) return QSK_OK;
-  std::vector<qsk::CrossArgs> a(ids.size());
+  std::vector<qsk::Gemm64Args> a(ids.size());
   std::vector<qsk::ReduceArgs> r(ids.size());
-  std::vector<int64_t> nb(ids.size()), rb(ids.size());
+  std::vector<int64_t> nb(ids.size()), rb(ids.size()), rows_v, tiles_v;
+  for (int id : ids) {
+    const Prob &q = b->p[id];
+    rows_v.push_back(tall_l ? q.l : q.m);
+    tiles_v.push_back((int64_t)((q.k + 15) / 16) * ((q.k + 15) / 16));
+  }
+  const int64_t budget = group_chunk(rows_v, tiles_v);
   for (size_t i = 0; i < ids.size(); ++i) {
     const Prob &q = b->p[ids[i]];
     const int64_t rows = tall_l ? q.l : q.m;
-    int64_t chunk, nch;
-    if (!qsk::plan_crossprod(rows, q.k, q.k, q.partial_elems, &chunk, &nch)) {
+    const void *z1[4], *z2[4];
+    int64_t ld1, ld2;
+    fz1(q, z1, &ld1);
+    fz2(q, z2, &ld2);
+    if (!qsk::g64_plan_crossprod(z1, ld1, z2, ld2, rows, q.k, q.k, q.partials, q.partial_elems, budget,
+                                 fo(q), &a[i], &r[i])) {
       b->last_error = "crossprod partial buffer too small";
       return QSK_E_HIP;
     }
-    qsk::CrossArgs &c = a[i];
-    fz1(q, c.z1, &c.ld1);
-    fz2(q, c.z2, &c.ld2);
-    c.rows = rows; c.chunk = chunk; c.k1 = q.k; c.k2 = q.k; c.partial = q.partials; c.planar = 0;
-    c.gx = (q.k + 15) / 16; c.gy = c.gx;
-    nb[i] = (int64_t)c.gx * c.gy * nch;
-    r[i].partial = q.partials; r[i].nchunks = (int)nch; r[i].elems = (int64_t)q.k * q.k * 4;
-    r[i].out = fo(q); r[i].gx = (int)((r[i].elems + 255) / 256); r[i].gy = 1;
+    nb[i] = (int64_t)a[i].gx * a[i].gy;
     rb[i] = r[i].gx;
   }
   GroupRef g1, g2;
   int64_t n1, n2;
   if (!push_group(b, a, nb, &g1, &n1) || !push_group(b, r, rb, &g2, &n2)) return arena_full(b);
-  BCHK(b, qsk::launch_crossprod_k(b->stream, t1, t2, a[0], g1, n1));
+  BCHK(b, qsk::launch_qgemm64_k(b->stream, t1, t2, true, a[0], g1, n1));
   BCHK(b, qsk::launch_reduce_k(b->stream, r[0], g2, n2));
   return QSK_OK;
 }
 
-// Out_i = Z_i C_i (planar FP64).
+// Out_i = Z_i C_i (planar FP64) on the FP64 matrix cores.
 template <typename FZ, typename FC, typename FO>
 qsk_status apply_all(qsk_batch *b, const std::vector<int> &ids, int tz, FZ fz, FC fc, FO fo,
                      bool tall_l) {
   if (ids.empty()) return QSK_OK;
-  std::vector<qsk::ApplyArgs> a(ids.size());
+  std::vector<qsk::Gemm64Args> a(ids.size());
   std::vector<int64_t> nb(ids.size());
   for (size_t i = 0; i < ids.size(); ++i) {
     const Prob &q = b->p[ids[i]];
-    qsk::ApplyArgs &x = a[i];
-    fz(q, x.z, &x.ldz);
-    x.rows = tall_l ? q.l : q.m; x.k = q.k; x.c = fc(q); x.kc = q.k;
-    fo(q, x.out, &x.ldo);
-    x.gx = (int)((x.rows + 255) / 256); x.gy = (q.k + 15) / 16;
-    nb[i] = (int64_t)x.gx * x.gy;
+    const void *z[4];
+    int64_t ldz, ldo;
+    double *o[4];
+    fz(q, z, &ldz);
+    fo(q, o, &ldo);
+    a[i] = qsk::g64_plan_apply(z, ldz, tall_l ? q.l : q.m, q.k, fc(q), q.k, o, ldo);
+    nb[i] = (int64_t)a[i].gx * a[i].gy;
   }
   GroupRef g;
   int64_t tot;
   if (!push_group(b, a, nb, &g, &tot)) return arena_full(b);
-  BCHK(b, qsk::launch_apply_k(b->stream, tz, a[0], g, tot));
+  BCHK(b, qsk::launch_qgemm64_k(b->stream, tz, 0, false, a[0], g, tot));
   return QSK_OK;
 }
 
@@ -248,6 +278,29 @@ void planes_of(double *base, int64_t rows, int k, double *out[4]) {
 }
 
 }  // namespace
+
+// Y = A Omega and W = Psi A of every problem (accumulated into Y and W) in
+// one grouped launch each, with the batch's current tile shapes.
+static qsk_status launch_sketches(qsk_batch *b, const void *const *planes, const int64_t *ld) {
+  const int n_all = b->count;
+  hipStream_t st = b->stream;
+  std::vector<qsk::SketchArgs> sa(n_all);
+  std::vector<qsk::MfmaStage> sg(n_all);
+  for (int i = 0; i < n_all; ++i) {
+    Prob &q = b->p[i];
+    qsk::SketchArgs &s = sa[i];
+    s.stream = st; s.mode = b->mode; s.in_dtype = q.cfg.input_dtype;
+    for (int p = 0; p < 4; ++p) s.planes[p] = planes[4 * i + p];
+    if (q.cfg.pure) s.planes[0] = planes[4 * i + 1];
+    s.lda = ld[i]; s.pure = q.cfg.pure; s.m = q.m; s.col0 = 0; s.ncols = q.n; s.k = q.k; s.l = q.l;
+    s.y = q.y; s.ldy = q.m; s.psy = q.m * (int64_t)q.k; s.pss = 0; s.y_copies = 1;
+    s.w = q.w; s.ldw = q.l; s.psw = q.l * (int64_t)q.n;
+    s.rad = q.cfg.embedding == QSK_RADEMACHER; s.terms = q.cfg.split_terms; s.k0 = q.k0; s.k1 = q.k1;
+    sg[i] = q.stage;
+  }
+  BCHK(b, qsk::launch_sketch_mfma_batch(sa.data(), sg.data(), n_all, b->nmt, b->nj, b->arena));
+  return QSK_OK;
+}
 
 // Every step of one batched run, stream-ordered on b->stream.  opt: no host
 // synchronisation (every factorisation assumed to succeed, failures only
@@ -290,21 +343,8 @@ static qsk_status batch_body(qsk_batch *b, qsk_rangefinder rf, const void *const
     BCHK(b, qsk::launch_zero_k(st, za[0], g, tot));
   }
   {
-    std::vector<qsk::SketchArgs> sa(n_all);
-    std::vector<qsk::MfmaStage> sg(n_all);
-    for (int i = 0; i < n_all; ++i) {
-      Prob &q = b->p[i];
-      qsk::SketchArgs &s = sa[i];
-      s.stream = st; s.mode = b->mode; s.in_dtype = q.cfg.input_dtype;
-      for (int p = 0; p < 4; ++p) s.planes[p] = planes[4 * i + p];
-      if (q.cfg.pure) s.planes[0] = planes[4 * i + 1];
-      s.lda = ld[i]; s.pure = q.cfg.pure; s.m = q.m; s.col0 = 0; s.ncols = q.n; s.k = q.k; s.l = q.l;
-      s.y = q.y; s.ldy = q.m; s.psy = q.m * (int64_t)q.k; s.pss = 0; s.y_copies = 1;
-      s.w = q.w; s.ldw = q.l; s.psw = q.l * (int64_t)q.n;
-      s.rad = q.cfg.embedding == QSK_RADEMACHER; s.terms = q.cfg.split_terms; s.k0 = q.k0; s.k1 = q.k1;
-      sg[i] = q.stage;
-    }
-    BCHK(b, qsk::launch_sketch_mfma_batch(sa.data(), sg.data(), n_all, b->nmt, b->nj, b->arena));
+    qsk_status r = launch_sketches(b, planes, ld);
+    if (r != QSK_OK) return r;
   }
 
   // ---- CholeskyQR of Y (as in the single-problem driver)
@@ -531,36 +571,36 @@ static qsk_status batch_body(qsk_batch *b, qsk_rangefinder rf, const void *const
     return r;
   // ---- core solve: P = Psi Q, X = (P^dagger) W through CholeskyQR2 of P
   if (!ok_ids.empty()) {
-    std::vector<qsk::PsiApplyArgs> a(ok_ids.size());
+    // P = Psi Q from the staged Psi (exactly the values that formed W)
+    std::vector<qsk::Gemm64Args> a(ok_ids.size());
     std::vector<qsk::ReducePlanarArgs> rr(ok_ids.size());
-    std::vector<int64_t> nb(ok_ids.size()), rb(ok_ids.size());
+    std::vector<int64_t> nb(ok_ids.size()), rb(ok_ids.size()), rows_v, tiles_v;
+    for (int id : ok_ids) {
+      const Prob &q = b->p[id];
+      rows_v.push_back(q.m);
+      tiles_v.push_back((int64_t)((q.l + 15) / 16) * ((q.k + 15) / 16));
+    }
+    const int64_t budget = group_chunk(rows_v, tiles_v);
+    const int es = b->mode == qsk::MODE_BF16 ? 2 : 4;
     for (size_t i = 0; i < ok_ids.size(); ++i) {
       const int id = ok_ids[i];
       const Prob &q = b->p[id];
-      int64_t chunk, nch;
-      if (!qsk::plan_psi_apply(q.l, q.m, q.k, q.partial_elems, &chunk, &nch)) {
-        b->last_error = "psi_apply partial buffer too small";
+      const double *h[4] = {Q[4 * id], Q[4 * id + 1], Q[4 * id + 2], Q[4 * id + 3]};
+      double *pout[4];
+      planes_of(q.pbuf, q.l, q.k, pout);
+      if (!qsk::g64_plan_psi(q.stage.psi, es, q.stage.MP, (int64_t)q.stage.LP * q.stage.MP, h, ldq[id],
+                             q.l, q.m, q.k, q.partials, q.partial_elems, budget, pout, q.l, &a[i],
+                             &rr[i])) {
+        b->last_error = "psi product partial buffer too small";
         return QSK_E_HIP;
       }
-      qsk::PsiApplyArgs &x = a[i];
-      x.mode = b->mode; x.rad = q.cfg.embedding == QSK_RADEMACHER; x.k0 = q.k0; x.k1 = q.k1;
-      x.l = q.l; x.m = q.m;
-      for (int p = 0; p < 4; ++p) x.h[p] = Q[4 * id + p];
-      x.ldh = ldq[id]; x.k = q.k; x.chunk = chunk; x.partial = q.partials;
-      // Psi exactly as staged for the sketch
-      x.psi_st = q.stage.psi; x.psi_st_type = b->mode == qsk::MODE_BF16 ? 1 : 2;
-      x.psi_ld = q.stage.MP; x.psi_ps = (int64_t)q.stage.LP * q.stage.MP;
-      x.gx = (q.l + 15) / 16; x.gy = (int)nch;
-      nb[i] = (int64_t)x.gx * x.gy;
-      rr[i].partial = q.partials; rr[i].nchunks = (int)nch; rr[i].r = q.l; rr[i].c = q.k;
-      planes_of(q.pbuf, q.l, q.k, rr[i].out);
-      rr[i].ldo = q.l; rr[i].gx = (int)(((int64_t)q.l * q.k + 255) / 256); rr[i].gy = 1;
+      nb[i] = (int64_t)a[i].gx * a[i].gy;
       rb[i] = rr[i].gx;
     }
     GroupRef g1, g2;
     int64_t n1, n2;
     if (!push_group(b, a, nb, &g1, &n1) || !push_group(b, rr, rb, &g2, &n2)) return arena_full(b);
-    BCHK(b, qsk::launch_psi_apply_k(st, a[0], g1, n1));
+    BCHK(b, qsk::launch_qgemm64_k(st, es == 2 ? 2 : 1, 0, false, a[0], g1, n1));
     BCHK(b, qsk::launch_reduce_planar_k(st, rr[0], g2, n2));
   }
   auto PZ = [](double *Prob::*buf) {
@@ -614,26 +654,25 @@ static qsk_status batch_body(qsk_batch *b, qsk_rangefinder rf, const void *const
   if ((r = apply_all(b, p_ok2, 0, PZ(&Prob::pbuf), SC(B_Z), PO(&Prob::sbuf), true)) != QSK_OK) return r;
   // X = (S^*)^* W
   if (!ok_ids.empty()) {
-    std::vector<qsk::CrossArgs> a(ok_ids.size());
+    std::vector<qsk::Gemm64Args> a(ok_ids.size());
     std::vector<int64_t> nb(ok_ids.size());
     for (size_t i = 0; i < ok_ids.size(); ++i) {
       const int id = ok_ids[i];
       const Prob &q = b->p[id];
-      qsk::CrossArgs &c = a[i];
+      const void *z1[4], *z2[4];
+      double *o[4];
       for (int p = 0; p < 4; ++p) {
-        c.z1[p] = q.sbuf + (size_t)p * q.l * q.k;
-        c.z2[p] = q.w + (size_t)p * q.l * q.n;
-        c.out[p] = X[4 * id + p];
+        z1[p] = q.sbuf + (size_t)p * q.l * q.k;
+        z2[p] = q.w + (size_t)p * q.l * q.n;
+        o[p] = X[4 * id + p];
       }
-      c.ld1 = q.l; c.ld2 = q.l; c.rows = q.l; c.chunk = q.l; c.k1 = q.k; c.k2 = (int)q.n;
-      c.partial = nullptr; c.ldo = ldx[id]; c.planar = 1;
-      c.gx = (q.k + 15) / 16; c.gy = (int)((q.n + 15) / 16);
-      nb[i] = (int64_t)c.gx * c.gy;
+      a[i] = qsk::g64_plan_crossprod_planar(z1, q.l, z2, q.l, q.l, q.k, (int)q.n, o, ldx[id]);
+      nb[i] = (int64_t)a[i].gx * a[i].gy;
     }
     GroupRef g;
     int64_t tot;
     if (!push_group(b, a, nb, &g, &tot)) return arena_full(b);
-    BCHK(b, qsk::launch_crossprod_k(st, 0, 1, a[0], g, tot));
+    BCHK(b, qsk::launch_qgemm64_k(st, 0, 1, true, a[0], g, tot));
   }
   // join the kappa side stream
   BCHK(b, hipStreamWaitEvent(st, b->ev_join, 0));
@@ -743,6 +782,42 @@ static qsk_status batch_graph(qsk_batch *b, qsk_rangefinder rf, const void *cons
   return QSK_OK;
 }
 
+// Lay the staged test matrices out for tile shapes (nmt, nj) and regenerate
+// them; the captured graphs hold the old layout and are dropped.
+static qsk_status restage(qsk_batch *b, int nmt, int nj) {
+  for (int i = 0; i < b->count; ++i) {
+    Prob &q = b->p[i];
+    qsk::stage_geometry_tiles(q.m, q.l, q.k, q.n, nmt, nj, &q.stage.LP, &q.stage.MP, &q.stage.KP,
+                              &q.stage.NP);
+    qsk::SketchArgs s{};
+    s.stream = b->stream; s.mode = b->mode; s.m = q.m; s.col0 = 0; s.ncols = q.n; s.k = q.k; s.l = q.l;
+    s.rad = q.cfg.embedding == QSK_RADEMACHER; s.k0 = q.k0; s.k1 = q.k1;
+    BCHK(b, qsk::stage_test_matrices(s, q.stage));
+  }
+  b->nmt = nmt;
+  b->nj = nj;
+  BCHK(b, hipStreamSynchronize(b->stream));
+  for (int r = 0; r < 2; ++r) {
+    if (b->gexec[r]) (void)hipGraphExecDestroy(b->gexec[r]);
+    b->gexec[r] = nullptr;
+    b->gkey[r].clear();
+  }
+  return QSK_OK;
+}
+
+// Tuned tile shapes by batch signature (operand format and every problem's
+// m, n, k, l), shared by the batches of this process.
+static std::mutex g_tune_mu;
+static std::map<std::vector<int64_t>, std::pair<int, int>> g_tuned;
+
+static std::vector<int64_t> tune_key(const qsk_batch *b) {
+  std::vector<int64_t> key = {b->mode, b->p[0].cfg.split_terms, b->p[0].cfg.input_dtype, b->p[0].cfg.pure};
+  for (const Prob &q : b->p) {
+    key.push_back(q.m); key.push_back(q.n); key.push_back(q.k); key.push_back(q.l);
+  }
+  return key;
+}
+
 extern "C" {
 
 qsk_status qsketch_batch_init(int32_t count, const qsk_config *cfgs, void *hip_stream,
@@ -807,8 +882,10 @@ qsk_status qsketch_batch_init(int32_t count, const qsk_config *cfgs, void *hip_s
         4 * (size_t)q.l * q.k * 8,                 // p1buf
         4 * (size_t)q.l * q.k * 8,                 // sbuf
         4 * (size_t)(q.l + q.k) * q.k * 8,         // pinv_work
-        4 * (size_t)q.stage.KP * q.stage.NP * es,  // omega staging
-        4 * (size_t)q.stage.LP * q.stage.MP * es,  // psi staging
+        // staging sized for the largest padding of any tile shape the
+        // autotuner may pick
+        4 * (size_t)max_pad(q.k, kNj, 2) * q.stage.NP * es,                            // omega staging
+        4 * (size_t)max_pad(q.l, kNmt, c0.sketch_dtype == QSK_BF16 ? 3 : 2) * q.stage.MP * es,  // psi
     };
     for (size_t s : sizes) {
       off[i].push_back(total);
@@ -938,6 +1015,63 @@ qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const
   }
   if ((r = batch_body(b, rf, planes, ld, Q, ldq, X, ldx, false)) != QSK_OK) return r;
   return batch_collect(b, rf, reports, false, &retry);
+}
+
+qsk_status qsketch_batch_autotune(qsk_batch *b, const void *const *planes, const int64_t *ld,
+                                  int32_t reps, int32_t *nmt_out, int32_t *nj_out) {
+  if (!b || !planes || !ld || reps < 0 || reps > 100) return QSK_E_ARG;
+  if (b->poisoned) return QSK_E_STATE;
+  for (int i = 0; i < b->count; ++i) {
+    const Prob &q = b->p[i];
+    if (ld[i] < q.m) return QSK_E_ARG;
+    for (int p = q.cfg.pure ? 1 : 0; p < 4; ++p)
+      if (!planes[4 * i + p]) return QSK_E_ARG;
+  }
+  const std::vector<int64_t> key = tune_key(b);
+  int best_nmt = -1, best_nj = -1;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) { best_nmt = it->second.first; best_nj = it->second.second; }
+  }
+  if (best_nmt < 0 && reps > 0) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BCHK(b, hipEventCreate(&e0));
+    BCHK(b, hipEventCreate(&e1));
+    float best = -1.0f;
+    qsk_status r = QSK_OK;
+    const int n_nmt = b->mode == qsk::MODE_BF16 ? 3 : 2;
+    for (int a = 0; a < n_nmt && r == QSK_OK; ++a) {
+      for (int c = 0; c < 2 && r == QSK_OK; ++c) {
+        if ((r = restage(b, kNmt[a], kNj[c])) != QSK_OK) break;
+        b->arena.used = 0;
+        // one untimed launch, then reps timed ones; Y and W only accumulate
+        if ((r = launch_sketches(b, planes, ld)) != QSK_OK) break;
+        if (hipEventRecord(e0, b->stream) != hipSuccess) { r = QSK_E_HIP; break; }
+        for (int t = 0; t < reps && r == QSK_OK; ++t) r = launch_sketches(b, planes, ld);
+        if (r != QSK_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          r = QSK_E_HIP;
+          break;
+        }
+        if (best < 0.0f || ms < best) { best = ms; best_nmt = kNmt[a]; best_nj = kNj[c]; }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r != QSK_OK) return r;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = {best_nmt, best_nj};
+  }
+  if (best_nmt > 0) {
+    qsk_status r = restage(b, best_nmt, best_nj);
+    if (r != QSK_OK) return r;
+  }
+  if (nmt_out) *nmt_out = b->nmt;
+  if (nj_out) *nj_out = b->nj;
+  return QSK_OK;
 }
 
 qsk_status qsketch_batch_set_exec(qsk_batch *b, int32_t mode) {

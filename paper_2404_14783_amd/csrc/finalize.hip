@@ -469,6 +469,72 @@ hipError_t launch_crossprod_planar(hipStream_t st, const double *const z1[4], in
   return launch_qgemm64_k(st, 0, t2, true, g, GroupRef{}, 0);
 }
 
+// Split of K for one problem of a grouped launch: chunks of chunk_hint rows
+// (the same for every problem, so that all waves get about the same work),
+// fewer and longer where the partial-sum buffer holds fewer.
+static int64_t g64_group_chunk(int64_t K, int64_t chunk_hint, int64_t max_chunks, int64_t *nch) {
+  int64_t chunk = chunk_hint < 16 ? 16 : (chunk_hint + 15) / 16 * 16;
+  const int64_t least = ((K + max_chunks - 1) / max_chunks + 15) / 16 * 16;
+  if (chunk < least) chunk = least;
+  *nch = (K + chunk - 1) / chunk;
+  return chunk;
+}
+
+bool g64_plan_crossprod(const void *const z1[4], int64_t ld1, const void *const z2[4], int64_t ld2,
+                        int64_t rows, int k1, int k2, double *partials, int64_t partial_elems,
+                        int64_t chunk_hint, double *out_aos, Gemm64Args *g, ReduceArgs *r) {
+  const int64_t max_chunks = partial_elems / ((int64_t)k1 * k2 * 4);
+  if (max_chunks < 1) return false;
+  *g = g64_args(z1, ld1, 1, z2, 1, ld2, k1, k2, rows);
+  int64_t nch;
+  g->kchunk = g64_group_chunk(rows, chunk_hint, max_chunks, &nch);
+  g->gy = (int)nch;
+  g->partial = partials;
+  *r = ReduceArgs{};
+  r->partial = partials; r->nchunks = (int)nch; r->elems = (int64_t)k1 * k2 * 4; r->out = out_aos;
+  r->gx = (int)((r->elems + 255) / 256); r->gy = 1;
+  return true;
+}
+
+Gemm64Args g64_plan_crossprod_planar(const void *const z1[4], int64_t ld1, const void *const z2[4],
+                                     int64_t ld2, int64_t rows, int k1, int k2, double *const out[4],
+                                     int64_t ldo) {
+  Gemm64Args g = g64_args(z1, ld1, 1, z2, 1, ld2, k1, k2, rows);
+  for (int p = 0; p < 4; ++p) g.out[p] = out[p];
+  g.ldo = ldo;
+  return g;
+}
+
+Gemm64Args g64_plan_apply(const void *const z[4], int64_t ldz, int64_t rows, int k, const double *c_aos,
+                          int kc, double *const out[4], int64_t ldo) {
+  const void *cp[4] = {c_aos, c_aos + 1, c_aos + 2, c_aos + 3};
+  Gemm64Args g = g64_args(z, 1, ldz, cp, 4, 4 * (int64_t)k, rows, kc, k);
+  for (int p = 0; p < 4; ++p) g.out[p] = out[p];
+  g.ldo = ldo;
+  return g;
+}
+
+bool g64_plan_psi(const void *psi_st, int es, int64_t psi_ld, int64_t psi_ps, const double *const h[4],
+                  int64_t ldh, int l, int64_t m, int k, double *partials, int64_t partial_elems,
+                  int64_t chunk_hint, double *const p[4], int64_t ldp, Gemm64Args *g,
+                  ReducePlanarArgs *r) {
+  const int64_t max_chunks = partial_elems / ((int64_t)l * k * 4);
+  if (max_chunks < 1) return false;
+  const void *pp[4];
+  for (int q = 0; q < 4; ++q) pp[q] = (const char *)psi_st + (size_t)q * psi_ps * es;
+  const void *hh[4] = {h[0], h[1], h[2], h[3]};
+  *g = g64_args(pp, psi_ld, 1, hh, 1, ldh, l, k, m);
+  int64_t nch;
+  g->kchunk = g64_group_chunk(m, chunk_hint, max_chunks, &nch);
+  g->gy = (int)nch;
+  g->partial = partials;
+  *r = ReducePlanarArgs{};
+  r->partial = partials; r->nchunks = (int)nch; r->r = l; r->c = k;
+  set_planes(r->out, p); r->ldo = ldp;
+  r->gx = (int)(((int64_t)l * k + 255) / 256); r->gy = 1;
+  return true;
+}
+
 // ---------------------------------------------------------------------------
 // Out = Z C: one row per thread, 16 output columns per block.y, C staged in
 // LDS 64 rows at a time.

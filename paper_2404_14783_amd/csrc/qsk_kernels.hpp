@@ -256,6 +256,26 @@ bool plan_psi_apply(int l, int64_t m, int k, int64_t partial_elems, int64_t *chu
 hipError_t launch_qgemm64_k(hipStream_t st, int ta, int tb, bool conj_a, const Gemm64Args &a, GroupRef g,
                             int64_t blocks);
 hipError_t launch_crossprod_k(hipStream_t st, int t1, int t2, const CrossArgs &a, GroupRef g, int64_t blocks);
+// Arguments of the FP64 matrix-core products for one problem of a grouped
+// launch; K is split in chunks of chunk_hint rows (longer where the
+// partial-sum buffer is short).
+//   C (AoS k1 x k2) = Z1^* Z2 through split-K partials and *r;
+bool g64_plan_crossprod(const void *const z1[4], int64_t ld1, const void *const z2[4], int64_t ld2,
+                        int64_t rows, int k1, int k2, double *partials, int64_t partial_elems,
+                        int64_t chunk_hint, double *out_aos, Gemm64Args *g, ReduceArgs *r);
+//   Out (planar) = Z1^* Z2 without a split;
+Gemm64Args g64_plan_crossprod_planar(const void *const z1[4], int64_t ld1, const void *const z2[4],
+                                     int64_t ld2, int64_t rows, int k1, int k2, double *const out[4],
+                                     int64_t ldo);
+//   Out (planar) = Z C with C AoS k x kc;
+Gemm64Args g64_plan_apply(const void *const z[4], int64_t ldz, int64_t rows, int k, const double *c_aos,
+                          int kc, double *const out[4], int64_t ldo);
+//   P (planar l x k) = Psi H from the staged Psi (element size es) through
+//   split-K partials and *r.
+bool g64_plan_psi(const void *psi_st, int es, int64_t psi_ld, int64_t psi_ps, const double *const h[4],
+                  int64_t ldh, int l, int64_t m, int k, double *partials, int64_t partial_elems,
+                  int64_t chunk_hint, double *const p[4], int64_t ldp, Gemm64Args *g,
+                  ReducePlanarArgs *r);
 hipError_t launch_reduce_k(hipStream_t st, const ReduceArgs &a, GroupRef g, int64_t blocks);
 hipError_t launch_reduce_planar_k(hipStream_t st, const ReducePlanarArgs &a, GroupRef g, int64_t blocks);
 hipError_t launch_apply_k(hipStream_t st, int tz, const ApplyArgs &a, GroupRef g, int64_t blocks);

@@ -138,3 +138,26 @@ def test_batch_graph_replays_match_careful_run(kind):
         b.run(devs, other)
         b.rel_error(devs, q2, x2)
     b.close()
+
+
+@pytest.mark.parametrize("sketch,terms", [("bf16", 2), ("f32", 1)])
+def test_batch_autotune(sketch, terms):
+    """The autotuner picks one of the candidate tile shapes (13 row tiles of
+    W only with bf16 operands), runs after it give the same approximation,
+    and a second batch with the same shapes takes the remembered choice
+    without timing."""
+    mats = inputs(SHAPES, "f32")
+    devs = [to_device(a, "f32") for a in mats]
+    b = qs.Batch(SHAPES, input_dtype="f32", sketch_dtype=sketch, split_terms=terms)
+    q0, x0, _ = b.run(devs, "pseudo_qr")
+    nmt, nj = b.autotune(devs, reps=2)
+    assert nmt in ((4, 7, 13) if sketch == "bf16" else (4, 7)) and nj in (4, 7)
+    q1, x1, _ = b.run(devs, "pseudo_qr")
+    for i in range(len(SHAPES)):
+        hx0 = qt.hamilton(to_numpy(q0[i]), to_numpy(x0[i]))
+        hx1 = qt.hamilton(to_numpy(q1[i]), to_numpy(x1[i]))
+        assert rel(hx1, hx0) < 1e-12, (i, rel(hx1, hx0))
+    b2 = qs.Batch(SHAPES, input_dtype="f32", sketch_dtype=sketch, split_terms=terms)
+    assert b2.autotune(devs, reps=0) == (nmt, nj)
+    b2.close()
+    b.close()
