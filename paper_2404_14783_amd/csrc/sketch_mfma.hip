@@ -20,6 +20,7 @@
 // The test-matrix slices this update needs (Omega_J, Psi) are regenerated
 // from the Philox stream into a transient staging buffer by gen_stage_kernel,
 // already rounded to the operand format, then read by the GEMMs.
+#include <algorithm>
 #include <type_traits>
 #include <vector>
 
@@ -984,6 +985,23 @@ static hipError_t launch_batch_t(const SketchArgs *s, const MfmaStage *g, int co
     w.S = 1; w.kchunk = rup(q.m, 32); w.part = nullptr;
     pw[i + 1] = pw[i] + (int64_t)w.ctiles * w.rgroups;
   }
+  // Blocks are dispatched in table order; the problems whose blocks run
+  // longest (most columns for Y, most rows for W) go first so that they do
+  // not form the tail of the launch.
+  std::vector<int> oy(count), ow(count);
+  for (int i = 0; i < count; ++i) oy[i] = ow[i] = i;
+  std::stable_sort(oy.begin(), oy.end(), [&](int a, int b) { return ys[a].ncols > ys[b].ncols; });
+  std::stable_sort(ow.begin(), ow.end(), [&](int a, int b) { return ws[a].m > ws[b].m; });
+  std::vector<YArgs> ys2(count);
+  std::vector<WArgs> ws2(count);
+  for (int i = 0; i < count; ++i) {
+    ys2[i] = ys[oy[i]];
+    ws2[i] = ws[ow[i]];
+    py[i + 1] = py[i] + (int64_t)ys2[i].rblocks * ys2[i].cgroups;
+    pw[i + 1] = pw[i] + (int64_t)ws2[i].ctiles * ws2[i].rgroups;
+  }
+  ys.swap(ys2);
+  ws.swap(ws2);
   hipStream_t st = s[0].stream;
   GroupRef gy{arena_push(ar, st, ys.data(), ys.size() * sizeof(YArgs)),
               (const int64_t *)arena_push(ar, st, py.data(), py.size() * sizeof(int64_t)), count};
