@@ -1266,34 +1266,52 @@ __global__ __launch_bounds__(1024) void power_m_kernel(PowerArgs args, GroupRef 
   double *m_out = A.m_out;
   SmallStatus *status = A.status;
   __shared__ double v[4 * 256], w[4 * 256];
-  __shared__ double s_nrm, s_eps;
-  const int tid = threadIdx.x;
+  __shared__ qd part[4][256];
+  __shared__ double s_red[16];
+  __shared__ double s_eps;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // sum of one value per thread over the block
+  auto block_sum = [&](double x) -> double {
+    x = wave_sum(x);
+    if (lane == 0) s_red[wave] = x;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < 16; ++i) t += s_red[i];
+    __syncthreads();
+    return t;
+  };
   for (int i = tid; i < k; i += blockDim.x) {
     double e[4];
     gauss_entry_f64((uint32_t)i, (uint32_t)step, STREAM_POWER, k0, k1, e);
     v[4 * i] = e[0]; v[4 * i + 1] = e[1]; v[4 * i + 2] = e[2]; v[4 * i + 3] = e[3];
   }
   __syncthreads();
+  // w = G^{-1} v: row i = tid mod 256, the columns split over 4 parts
+  const int row = tid & 255, prt = tid >> 8;
   for (int it = 0; it <= n_power; ++it) {
-    if (tid == 0) {
-      double s = 0.0;
-      for (int i = 0; i < 4 * k; ++i) s += v[i] * v[i];
-      s_nrm = sqrt(s);
+    double sq = 0.0;
+    for (int i = tid; i < 4 * k; i += blockDim.x) sq += v[i] * v[i];
+    const double inv_nrm = 1.0 / sqrt(block_sum(sq));
+    for (int i = tid; i < 4 * k; i += blockDim.x) v[i] *= inv_nrm;
+    __syncthreads();
+    if (row < k) {
+      qd acc = qzero();
+      for (int t2 = prt; t2 < k; t2 += 4)
+        qfma(acc, gq(gi, row, t2, k), {v[4 * t2], v[4 * t2 + 1], v[4 * t2 + 2], v[4 * t2 + 3]});
+      part[prt][row] = acc;
     }
     __syncthreads();
-    for (int i = tid; i < 4 * k; i += blockDim.x) v[i] /= s_nrm;
-    __syncthreads();
     for (int i = tid; i < k; i += blockDim.x) {
-      qd s = qzero();
-      for (int t2 = 0; t2 < k; ++t2)
-        qfma(s, gq(gi, i, t2, k), {v[4 * t2], v[4 * t2 + 1], v[4 * t2 + 2], v[4 * t2 + 3]});
-      w[4 * i] = s.w; w[4 * i + 1] = s.x; w[4 * i + 2] = s.y; w[4 * i + 3] = s.z;
+      qd s2 = part[0][i];
+      for (int p = 1; p < 4; ++p) s2 = qadd(s2, part[p][i]);
+      w[4 * i] = s2.w; w[4 * i + 1] = s2.x; w[4 * i + 2] = s2.y; w[4 * i + 3] = s2.z;
     }
     __syncthreads();
     if (it == n_power) {
+      double rl = 0.0;
+      for (int i = tid; i < 4 * k; i += blockDim.x) rl += v[i] * w[i];      // Re(v^* w)
+      const double rho = block_sum(rl);
       if (tid == 0) {
-        double rho = 0.0;
-        for (int i = 0; i < 4 * k; ++i) rho += v[i] * w[i];      // Re(v^* w)
         s_eps = 1.0 / sqrt(rho);
         status->eps[status->n_eps] = s_eps;
         status->n_eps += 1;
