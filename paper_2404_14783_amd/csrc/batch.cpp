@@ -245,7 +245,7 @@ qsk_status crossprod_all(qsk_batch *b, const std::vector<int> &ids, int t1, int 
 // Out_i = Z_i C_i (planar FP64) on the FP64 matrix cores.
 template <typename FZ, typename FC, typename FO>
 qsk_status apply_all(qsk_batch *b, const std::vector<int> &ids, int tz, FZ fz, FC fc, FO fo,
-                     bool tall_l) {
+                     bool tall_l, bool c_upper = false) {
   if (ids.empty()) return QSK_OK;
   std::vector<qsk::Gemm64Args> a(ids.size());
   std::vector<int64_t> nb(ids.size());
@@ -256,7 +256,7 @@ qsk_status apply_all(qsk_batch *b, const std::vector<int> &ids, int tz, FZ fz, F
     double *o[4];
     fz(q, z, &ldz);
     fo(q, o, &ldo);
-    a[i] = qsk::g64_plan_apply(z, ldz, tall_l ? q.l : q.m, q.k, fc(q), q.k, o, ldo);
+    a[i] = qsk::g64_plan_apply(z, ldz, tall_l ? q.l : q.m, q.k, fc(q), q.k, o, ldo, c_upper ? 1 : 0);
     nb[i] = (int64_t)a[i].gx * a[i].gy;
   }
   GroupRef g;
@@ -442,7 +442,7 @@ static qsk_status batch_body(qsk_batch *b, qsk_rangefinder rf, const void *const
         [](const Prob &q, double *o[4], int64_t *ldo) {
           planes_of(q.u[(q.passes - 1) & 1], q.m, q.k, o);
           *ldo = q.m;
-        }, false);
+        }, false, true);
     if (r != QSK_OK) return r;
     for (int i : next) {
       Prob &q = b->p[i];
@@ -641,7 +641,8 @@ static qsk_status batch_body(qsk_batch *b, qsk_rangefinder rf, const void *const
   std::vector<int> p_ok, p_bad;
   for (int i : ok_ids) (hs[i].fail ? p_bad : p_ok).push_back(i);
   if ((r = pinv_all(p_bad)) != QSK_OK) return r;
-  if ((r = apply_all(b, p_ok, 0, PZ(&Prob::pbuf), SC(B_TP1), PO(&Prob::p1buf), true)) != QSK_OK) return r;
+  if ((r = apply_all(b, p_ok, 0, PZ(&Prob::pbuf), SC(B_TP1), PO(&Prob::p1buf), true, true)) != QSK_OK)
+    return r;
   if ((r = crossprod_all(b, p_ok, 0, 0, PZ(&Prob::p1buf), PZ(&Prob::p1buf), S(B_GP), true)) != QSK_OK) return r;
   if ((r = chol_all(b, p_ok, SC(B_GP), 0, [](int) { return 0.0; }, 1e-13, S(B_RP), S(B_TP2), 0)) != QSK_OK)
     return r;

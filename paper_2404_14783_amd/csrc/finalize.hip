@@ -145,6 +145,25 @@ __device__ __forceinline__ void ld64x4(const void *p, int64_t base, int64_t st, 
   }
 }
 
+// Output tile of a wave: column-major over the mt x nt tiles, or over the
+// tiles on and above the diagonal (tm <= tn, column by column) for a
+// Hermitian product.
+__device__ __forceinline__ bool g64_tile(const Gemm64Args &A, int tile, int *tm, int *tn) {
+  if (A.herm) {
+    if (tile >= A.mt * (A.mt + 1) / 2) return false;
+    int c = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+    while ((c + 1) * (c + 2) / 2 <= tile) ++c;
+    while (c * (c + 1) / 2 > tile) --c;
+    *tn = c;
+    *tm = tile - c * (c + 1) / 2;
+    return true;
+  }
+  if (tile >= A.mt * A.nt) return false;
+  *tm = tile % A.mt;
+  *tn = tile / A.mt;
+  return true;
+}
+
 template <typename TA, typename TB, bool CONJ_A, bool ACONT, bool BCONT>
 __global__ __launch_bounds__(256) void qgemm64_k(Gemm64Args args, GroupRef grp) {
   Gemm64Args A;
@@ -152,12 +171,13 @@ __global__ __launch_bounds__(256) void qgemm64_k(Gemm64Args args, GroupRef grp) 
   if (!group_select(args, grp, A, bx, by, bz)) return;
   const int lane = threadIdx.x & 63;
   const int tile = bx * 4 + (threadIdx.x >> 6);
-  if (tile >= A.mt * A.nt) return;                       // whole wave
-  const int tm = tile % A.mt, tn = tile / A.mt;
+  int tm, tn;
+  if (!g64_tile(A, tile, &tm, &tn)) return;              // whole wave
   const int64_t i = (int64_t)tm * 16 + (lane & 15);      // A row of this lane
   const int64_t j = (int64_t)tn * 16 + (lane & 15);      // B column of this lane
   const int kq = lane >> 4;
-  const int64_t kb = (int64_t)by * A.kchunk, ke = min(A.K, kb + A.kchunk);
+  const int64_t kb = (int64_t)by * A.kchunk;
+  const int64_t ke = min(A.b_upper ? min(A.K, (int64_t)tn * 16 + 16) : A.K, kb + A.kchunk);
   const bool iok = i < A.M, jok = j < A.N;
   const int64_t ai = (iok ? i : 0) * A.sa_i, bj = (jok ? j : 0) * A.sb_j;
   v4d acc[4];
@@ -234,12 +254,13 @@ __global__ __launch_bounds__(256) void qgemm64s_k(Gemm64Args args, GroupRef grp)
   if (!group_select(args, grp, A, bx, by, bz)) return;
   const int lane = threadIdx.x & 63;
   const int tile = bx * 4 + (threadIdx.x >> 6);
-  if (tile >= A.mt * A.nt) return;                       // whole wave
-  const int tm = tile % A.mt, tn = tile / A.mt;
+  int tm, tn;
+  if (!g64_tile(A, tile, &tm, &tn)) return;              // whole wave
   const int64_t i = (int64_t)tm * 16 + (lane & 15);      // A row of this lane
   const int64_t j = (int64_t)tn * 16 + (lane & 15);      // B column of this lane
   const int kq = lane >> 4;
-  const int64_t kb = (int64_t)by * A.kchunk, ke = min(A.K, kb + A.kchunk);
+  const int64_t kb = (int64_t)by * A.kchunk;
+  const int64_t ke = min(A.b_upper ? min(A.K, (int64_t)tn * 16 + 16) : A.K, kb + A.kchunk);
   const bool iok = i < A.M, jok = j < A.N;
   const int64_t ai = (iok ? i : 0) * A.sa_i, bj = (jok ? j : 0) * A.sb_j;
   v4d acc[4];
@@ -326,9 +347,21 @@ __global__ void reduce_chunks_k(ReduceArgs args, GroupRef grp) {
   double *out = A.out;
   const int64_t e = (int64_t)bx * blockDim.x + threadIdx.x;
   if (e >= elems) return;
+  int64_t src = e;
+  double sg = 1.0;
+  if (A.herm) {
+    // element (i, j), plane p of an m x m AoS matrix; tiles below the
+    // diagonal were not computed: C(i, j) = conj(C(j, i))
+    const int p = (int)(e & 3);
+    const int64_t ij = e >> 2, i = ij % A.m, j = ij / A.m;
+    if (i / 16 > j / 16) {
+      src = 4 * (i * A.m + j) + p;
+      if (p > 0) sg = -1.0;
+    }
+  }
   double s = 0.0;
-  for (int c = 0; c < nchunks; ++c) s += gp(partial)[(int64_t)c * elems + e];
-  gpw(out)[e] = s;
+  for (int c = 0; c < nchunks; ++c) s += gp(partial)[(int64_t)c * elems + src];
+  gpw(out)[e] = sg * s;
 }
 
 // AoS (r x c, ld = r) partial sums -> planar output.
@@ -429,6 +462,18 @@ static int64_t g64_chunk(int64_t K, int64_t tiles, int64_t max_chunks, int64_t *
   return chunk;
 }
 
+static bool same_planes(const void *const a[4], const void *const b[4]) {
+  return a[0] == b[0] && a[1] == b[1] && a[2] == b[2] && a[3] == b[3];
+}
+static int64_t g64_tiles(const Gemm64Args &g) {
+  return g.herm ? (int64_t)g.mt * (g.mt + 1) / 2 : (int64_t)g.mt * g.nt;
+}
+// Hermitian product: only the tiles on and above the diagonal
+static void g64_set_herm(Gemm64Args &g, bool herm) {
+  g.herm = herm ? 1 : 0;
+  g.gx = (int)((g64_tiles(g) + 3) / 4);
+}
+
 static Gemm64Args g64_args(const void *const a[4], int64_t sa_i, int64_t sa_t, const void *const b[4],
                            int64_t sb_t, int64_t sb_j, int64_t M, int64_t N, int64_t K) {
   Gemm64Args g{};
@@ -447,14 +492,16 @@ hipError_t launch_crossprod(hipStream_t st, int t1, const void *const z1[4], int
   const int64_t max_chunks = partial_elems / ((int64_t)k1 * k2 * 4);
   if (max_chunks < 1) return hipErrorInvalidValue;
   Gemm64Args g = g64_args(z1, ld1, 1, z2, 1, ld2, k1, k2, rows);
+  g64_set_herm(g, t1 == t2 && ld1 == ld2 && k1 == k2 && same_planes(z1, z2));
   int64_t nch;
-  g.kchunk = g64_chunk(rows, (int64_t)g.mt * g.nt, max_chunks, &nch);
+  g.kchunk = g64_chunk(rows, g64_tiles(g), max_chunks, &nch);
   g.gy = (int)nch;
   g.partial = partials;
   hipError_t e = launch_qgemm64_k(st, t1, t2, true, g, GroupRef{}, 0);
   if (e != hipSuccess) return e;
   ReduceArgs r{};
   r.partial = partials; r.nchunks = (int)nch; r.elems = (int64_t)k1 * k2 * 4; r.out = out_aos;
+  r.herm = g.herm; r.m = k1;
   r.gx = (int)((r.elems + 255) / 256); r.gy = 1;
   return launch_reduce_k(st, r, GroupRef{}, r.gx);
 }
@@ -486,12 +533,14 @@ bool g64_plan_crossprod(const void *const z1[4], int64_t ld1, const void *const 
   const int64_t max_chunks = partial_elems / ((int64_t)k1 * k2 * 4);
   if (max_chunks < 1) return false;
   *g = g64_args(z1, ld1, 1, z2, 1, ld2, k1, k2, rows);
+  g64_set_herm(*g, ld1 == ld2 && k1 == k2 && same_planes(z1, z2));
   int64_t nch;
   g->kchunk = g64_group_chunk(rows, chunk_hint, max_chunks, &nch);
   g->gy = (int)nch;
   g->partial = partials;
   *r = ReduceArgs{};
   r->partial = partials; r->nchunks = (int)nch; r->elems = (int64_t)k1 * k2 * 4; r->out = out_aos;
+  r->herm = g->herm; r->m = k1;
   r->gx = (int)((r->elems + 255) / 256); r->gy = 1;
   return true;
 }
@@ -506,9 +555,10 @@ Gemm64Args g64_plan_crossprod_planar(const void *const z1[4], int64_t ld1, const
 }
 
 Gemm64Args g64_plan_apply(const void *const z[4], int64_t ldz, int64_t rows, int k, const double *c_aos,
-                          int kc, double *const out[4], int64_t ldo) {
+                          int kc, double *const out[4], int64_t ldo, int c_upper) {
   const void *cp[4] = {c_aos, c_aos + 1, c_aos + 2, c_aos + 3};
   Gemm64Args g = g64_args(z, 1, ldz, cp, 4, 4 * (int64_t)k, rows, kc, k);
+  g.b_upper = c_upper;
   for (int p = 0; p < 4; ++p) g.out[p] = out[p];
   g.ldo = ldo;
   return g;
@@ -598,10 +648,12 @@ hipError_t launch_apply_k(hipStream_t st, int tz, const ApplyArgs &a, GroupRef g
 }
 
 hipError_t launch_apply(hipStream_t st, int tz, const void *const z[4], int64_t ldz, int64_t rows,
-                        int k, const double *c_aos, int kc, double *const out[4], int64_t ldo) {
+                        int k, const double *c_aos, int kc, double *const out[4], int64_t ldo,
+                        int c_upper) {
   // Out(i, j) = sum_t Z(i, t) C(t, j), C AoS with leading dimension k
   const void *cp[4] = {c_aos, c_aos + 1, c_aos + 2, c_aos + 3};
   Gemm64Args g = g64_args(z, 1, ldz, cp, 4, 4 * (int64_t)k, rows, kc, k);
+  g.b_upper = c_upper;
   for (int p = 0; p < 4; ++p) g.out[p] = out[p];
   g.ldo = ldo;
   return launch_qgemm64_k(st, tz, 0, false, g, GroupRef{}, 0);

@@ -98,7 +98,8 @@ hipError_t launch_crossprod_planar(hipStream_t st, const double *const z1[4], in
                                    int k1, int k2, double *const out[4], int64_t ldo);
 // Out (rows x kc, planar FP64) = Z (rows x k, planar, type tz) * C (k x kc, AoS, ldc = k).
 hipError_t launch_apply(hipStream_t st, int tz, const void *const z[4], int64_t ldz, int64_t rows,
-                        int k, const double *c_aos, int kc, double *const out[4], int64_t ldo);
+                        int k, const double *c_aos, int kc, double *const out[4], int64_t ldo,
+                        int c_upper = 0);
 // P (l x k, planar FP64) = Psi H with Psi regenerated as the sketch of `mode` used it.
 hipError_t launch_psi_apply(hipStream_t st, int mode, int rad, uint32_t k0, uint32_t k1, int l,
                             int64_t m, const double *const h[4], int64_t ldh, int k,
@@ -149,6 +150,8 @@ struct Gemm64Args {         // C = opA(A) B, quaternion, FP64 matrix cores (16 x
   int mt, nt;                             // 16-wide tiles in M and N
   double *out[4]; int64_t ldo; int accumulate;
   double *partial;                        // split K: [chunk][N][M] AoS partial sums
+  int herm;                               // C Hermitian (A = B, conj): tiles tm <= tn only
+  int b_upper;                            // B upper triangular: t < 16 (tn + 1) only
   int gx, gy;
 };
 struct CrossArgs {          // C = Z1^* Z2 over row chunks (bz), 16 x 16 tiles (bx, by)
@@ -161,7 +164,11 @@ struct CrossArgs {          // C = Z1^* Z2 over row chunks (bz), 16 x 16 tiles (
   int planar;
   int gx, gy;
 };
-struct ReduceArgs { const double *partial; int nchunks; int64_t elems; double *out; int gx, gy; };
+struct ReduceArgs {
+  const double *partial; int nchunks; int64_t elems; double *out;
+  int herm, m;              // herm: tiles below the diagonal (16 x 16, m rows) mirror the ones above
+  int gx, gy;
+};
 struct ReducePlanarArgs {
   const double *partial; int nchunks, r, c;
   double *out[4]; int64_t ldo;
@@ -269,7 +276,7 @@ Gemm64Args g64_plan_crossprod_planar(const void *const z1[4], int64_t ld1, const
                                      int64_t ldo);
 //   Out (planar) = Z C with C AoS k x kc;
 Gemm64Args g64_plan_apply(const void *const z[4], int64_t ldz, int64_t rows, int k, const double *c_aos,
-                          int kc, double *const out[4], int64_t ldo);
+                          int kc, double *const out[4], int64_t ldo, int c_upper);
 //   P (planar l x k) = Psi H from the staged Psi (element size es) through
 //   split-K partials and *r.
 bool g64_plan_psi(const void *psi_st, int es, int64_t psi_ld, int64_t psi_ps, const double *const h[4],

@@ -474,7 +474,7 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
     if (passes >= need || passes >= max_passes) break;
     double *ub = ctx->u[(passes - 1) & 1];
     double *up[4] = {ub, ub + (size_t)m * k, ub + 2 * (size_t)m * k, ub + 3 * (size_t)m * k};
-    HIPCHK(ctx, qsk::launch_apply(st, tz, zsrc, m, m, k, slot(ctx, S_T), k, up, m));
+    HIPCHK(ctx, qsk::launch_apply(st, tz, zsrc, m, m, k, slot(ctx, S_T), k, up, m, 1));
     for (int p = 0; p < 4; ++p) zsrc[p] = up[p];
     tz = 0;
     gz = slot(ctx, S_GU);
@@ -571,7 +571,7 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
     HIPCHK(ctx, qsk::launch_pinv_sstar(st, l, k, pp, l, 1e-13, ctx->pinv_work, sp, l));
     have_sstar = true;
   } else {
-    HIPCHK(ctx, qsk::launch_apply(st, 0, (const void *const *)pp, l, l, k, slot(ctx, S_TP1), k, p1, l));
+    HIPCHK(ctx, qsk::launch_apply(st, 0, (const void *const *)pp, l, l, k, slot(ctx, S_TP1), k, p1, l, 1));
     HIPCHK(ctx, qsk::launch_crossprod(st, 0, (const void *const *)p1, l, 0, (const void *const *)p1,
                                       l, l, k, k, ctx->partials, ctx->partial_elems, slot(ctx, S_GP)));
     HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GP), k, 0, 0.0, 1e-13, slot(ctx, S_RP),
