@@ -21,6 +21,7 @@
 // from the Philox stream into a transient staging buffer by gen_stage_kernel,
 // already rounded to the operand format, then read by the GEMMs.
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 #include <vector>
 
@@ -773,6 +774,42 @@ static void launch_y(const YArgs &y, int64_t blocks, hipStream_t st, GroupRef g 
   else
     hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS, false, H>), dim3((unsigned)blocks), dim3(256 * H), 0, st, y, g);
 }
+// Blocks of 4 H waves resident at once on the device: every CU holds two
+// waves per SIMD of these kernels (their register budget).
+static int64_t resident_blocks(int H) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      cus = n;
+    else
+      cus = 256;
+  }
+  return (int64_t)cus * std::max(1, 2 / H);
+}
+
+// Split count S in [1, smax] of a grid of base * S blocks: the largest
+// fraction of busy slots in the last round of `slots` resident blocks; among
+// equal fractions the fewest splits that still fill every slot once.
+static int64_t pick_split(int64_t base, int64_t smax, int64_t slots) {
+  int64_t best = 1;
+  double best_u = -1.0;
+  bool best_full = false;
+  for (int64_t S = 1; S <= smax; ++S) {
+    const int64_t b = base * S;
+    const int64_t rounds = (b + slots - 1) / slots;
+    const double u = std::floor(100.0 * (double)b / (double)(rounds * slots)) / 100.0;
+    const bool full = b >= slots;
+    if (u > best_u || (u == best_u && full && !best_full)) {
+      best = S;
+      best_u = u;
+      best_full = full;
+    }
+  }
+  return best;
+}
+
 // Rows of A per Y block.
 template <int OP> constexpr int y_rows() { return 64 * y_waves<OP>(); }
 
@@ -840,11 +877,10 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     const int ntiles = (s.k + 15) / 16;
     y.rblocks = (int)((s.m + y_rows<OP>() - 1) / y_rows<OP>());
     y.cgroups = (ntiles + nj - 1) / nj;
-    // split the update's columns over the Y copies so that the grid holds
-    // about four blocks per CU
-    int64_t S = (1024 + (int64_t)y.rblocks * y.cgroups - 1) / ((int64_t)y.rblocks * y.cgroups);
-    if (S > s.y_copies) S = s.y_copies;
-    if (S < 1) S = 1;
+    // split the update's columns over the Y copies, the grid's last round
+    // of resident blocks as full as possible
+    int64_t S = pick_split((int64_t)y.rblocks * y.cgroups, std::min<int64_t>(s.y_copies, (s.ncols + 31) / 32),
+                           resident_blocks(y_waves<OP>()));
     int64_t tchunk = rup((s.ncols + S - 1) / S, 32);
     S = (s.ncols + tchunk - 1) / tchunk;
     y.S = (int)S; y.tchunk = tchunk;
@@ -867,10 +903,13 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     const int nmt = w_nmt(s.l, !op_f32(OP));
     w.rgroups = (int)(g.LP / (16 * nmt));
     w.ctiles = (int)((s.ncols + 63) / 64);
-    // split the rows of A so that there are >= ~2 blocks per CU
+    // split the rows of A (chunks of at least 256 rows, partials within the
+    // scratch buffer), the grid's last round of resident blocks as full as
+    // possible
     const int64_t base = (int64_t)w.ctiles * w.rgroups;
-    int64_t S = (512 + base - 1) / base;
-    if (S > 16) S = 16;
+    const int64_t per_split = 4 * s.ncols * (int64_t)g.LP * 4;
+    const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(s.m / 256, s.scratch_bytes / per_split));
+    int64_t S = pick_split(base, smax, resident_blocks(w_waves<OP>()));
     int64_t kchunk = rup((s.m + S - 1) / S, 32);
     if (kchunk < 256) kchunk = 256;
     S = (s.m + kchunk - 1) / kchunk;
