@@ -34,6 +34,7 @@ struct SketchArgs {
   int64_t scratch_bytes;
   float *fp8_scales;     // fp8 tile scales of the block, [4][ceil(m/32)][ceil(ncols/32)]
   int64_t fp8_scale_elems;
+  int psi_ready;         // the staging buffer already holds Psi (it does not change)
   // optional timing: events[2 * kernel] before, [2 * kernel + 1] after (may be null)
   hipEvent_t *events;
 };

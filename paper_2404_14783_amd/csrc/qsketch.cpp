@@ -350,6 +350,7 @@ qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void 
   s.scratch_bytes = ctx->w_scratch_bytes;
   s.fp8_scales = ctx->fp8_scales;
   s.fp8_scale_elems = ctx->fp8_scale_elems;
+  s.psi_ready = ctx->psi_staged ? 1 : 0;
   s.events = nullptr;
   if (ctx->timing && ctx->use_mfma && ctx->mode != qsk::MODE_F64) {
     if (ctx->ev_used + 8 > ctx->ev_pool.size()) {

@@ -830,25 +830,26 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
   if (!offsets_fit<TIN>(s.m, s.ncols, s.lda) || !y_plane_fits(s.m, s.k)) return hipErrorNotSupported;
   hipError_t e;
   mark(s, 0);
-  // regenerate Omega_J and Psi in the operand format
+  // regenerate Omega_J in the operand format, and Psi once (it is the same
+  // for every block)
   OPT *om = (OPT *)g.omega;
   OPT *ps = (OPT *)g.psi;
   const int64_t NPu = rup(s.ncols, 32);
   if (s.mode == MODE_BF16) {
     e = gen_stage<MODE_BF16, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
-    e = gen_stage<MODE_BF16, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
+    if (!s.psi_ready) e = gen_stage<MODE_BF16, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
   } else if (s.mode == MODE_FP8) {
     // e4m3 test-matrix values, staged as (exact) bf16
     e = gen_stage<MODE_FP8, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
-    e = gen_stage<MODE_FP8, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
+    if (!s.psi_ready) e = gen_stage<MODE_FP8, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
   } else {
     e = gen_stage<MODE_F32, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
-    e = gen_stage<MODE_F32, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
+    if (!s.psi_ready) e = gen_stage<MODE_F32, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
   }
   // fp8: the tile scales of this block
