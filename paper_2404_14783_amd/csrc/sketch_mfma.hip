@@ -189,52 +189,6 @@ __device__ __forceinline__ void to_frags(const float (&x)[8], float sc, FragF (&
 }
 
 // ---------------------------------------------------------------------------
-// fp8 tile scales of one update block: for plane p and the 32 x 32 tile
-// (rt, ct) of the block (rows from 0, columns from the block's first), the
-// smallest power of two sc with amax / sc <= 448, 1 for an all-zero tile;
-// sc[(p * RT + rt) * CT + ct].  One wave per tile: lane c < 32 reads rows
-// 0..15 of column c, lane c + 32 rows 16..31.
-template <typename TIN>
-__global__ __launch_bounds__(256) void fp8_scale_kernel(const void *a0, const void *a1, const void *a2,
-                                                        const void *a3, int64_t lda, int64_t m,
-                                                        int64_t ncols, int pure, int RT, int CT,
-                                                        float *sc) {
-  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t ntiles = 4 * (int64_t)RT * CT;
-  if (tile >= ntiles) return;
-  const int p = (int)(tile / ((int64_t)RT * CT));
-  const int rt = (int)((tile / CT) % RT), ct = (int)(tile % CT);
-  const int lane = threadIdx.x & 63;
-  const int64_t c = (int64_t)ct * 32 + (lane & 31), r0 = (int64_t)rt * 32 + (lane >> 5) * 16;
-  const TIN *a = (const TIN *)(p == 0 ? a0 : p == 1 ? a1 : p == 2 ? a2 : a3);
-  float mx = 0.f;
-  if (!(p == 0 && pure) && c < ncols) {
-    for (int i = 0; i < 16; ++i) {
-      const int64_t r = r0 + i;
-      if (r < m) {
-        float v;
-        if constexpr (sizeof(TIN) == 4) v = gp((const float *)a)[r + c * lda];
-        else v = __uint_as_float(((uint32_t)gp((const uint16_t *)a)[r + c * lda]) << 16);
-        mx = fmaxf(mx, fabsf(v));
-      }
-    }
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-  if (lane == 0) {
-    float s = 1.f;
-    if (mx > 0.f) {
-      // mx = f 2^E with 0.5 <= f < 1, and 448 = 0.875 2^9: the smallest e with
-      // mx <= 448 2^e is E - 9, or E - 8 when f > 0.875
-      int E;
-      const float f = frexpf(mx, &E);
-      s = ldexpf(1.f, E - 9 + (f > 0.875f ? 1 : 0));
-    }
-    sc[tile] = s;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Operand access shared by both kernels.
 //
 // The data planes are read through buffer resources that span one plane of
@@ -269,6 +223,62 @@ template <> __device__ __forceinline__ float bload1<float>(rsrc_t r, uint32_t vo
 }
 template <> __device__ __forceinline__ float bload1<uint16_t>(rsrc_t r, uint32_t voff, uint32_t soff) {
   return __uint_as_float(((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)) << 16);
+}
+
+// ---------------------------------------------------------------------------
+// fp8 tile scales of one update block: for plane p and the 32 x 32 tile
+// (rt, ct) of the block (rows from 0, columns from the block's first), the
+// smallest power of two sc with amax / sc <= 448, 1 for an all-zero tile;
+// sc[(p * RT + rt) * CT + ct].  One wave per tile: lane L reads rows
+// 4 (L mod 8) .. + 3 of columns L / 8 + 8 j, j = 0..3, so that each load
+// instruction covers eight 128-byte column segments; reads past the block
+// return zero and rows past m are masked.
+template <typename TIN>
+__global__ __launch_bounds__(256) void fp8_scale_kernel(const void *a0, const void *a1, const void *a2,
+                                                        const void *a3, int64_t lda, int64_t m,
+                                                        int64_t ncols, int pure, int RT, int CT,
+                                                        float *sc) {
+  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t ntiles = 4 * (int64_t)RT * CT;
+  if (tile >= ntiles) return;
+  const int p = (int)(tile / ((int64_t)RT * CT));
+  const int rt = (int)((tile / CT) % RT), ct = (int)(tile % CT);
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)rt * 32 + 4 * (lane & 7);
+  const void *a = p == 0 ? a0 : p == 1 ? a1 : p == 2 ? a2 : a3;
+  float mx = 0.f;
+  if (!(p == 0 && pure)) {
+    const rsrc_t rs = make_rsrc(a, (uint32_t)(((ncols - 1) * lda + m) * (int64_t)sizeof(TIN)));
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t c = (int64_t)ct * 32 + (lane >> 3) + 8 * j;
+      const uint32_t voff = (uint32_t)((r + c * lda) * (int64_t)sizeof(TIN));
+      float x[4];
+      if constexpr (sizeof(TIN) == 4) {
+        const u32v4 u = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0, 0);
+        x[0] = __uint_as_float(u.x); x[1] = __uint_as_float(u.y);
+        x[2] = __uint_as_float(u.z); x[3] = __uint_as_float(u.w);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = bload1<uint16_t>(rs, voff + 2 * i, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) mx = fmaxf(mx, r + i < m ? fabsf(x[i]) : 0.f);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+  if (lane == 0) {
+    float s = 1.f;
+    if (mx > 0.f) {
+      // mx = f 2^E with 0.5 <= f < 1, and 448 = 0.875 2^9: the smallest e with
+      // mx <= 448 2^e is E - 9, or E - 8 when f > 0.875
+      int E;
+      const float f = frexpf(mx, &E);
+      s = ldexpf(1.f, E - 9 + (f > 0.875f ? 1 : 0));
+    }
+    sc[tile] = s;
+  }
 }
 
 // The staged test-matrix tiles go from HBM straight into LDS (no register
