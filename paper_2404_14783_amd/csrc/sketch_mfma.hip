@@ -446,7 +446,11 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
 #pragma unroll
     for (int i = 0; i < NH; ++i) {
       const int rt = rt0 + i;
-      if (rt < NMT) {
+      // with at most two waves per SIMD only a wave's last row tile can lie
+      // past NMT: the others carry no branch, so the fragment reads of the
+      // next tile can be issued during the current tile's products
+      static_assert(H <= 2, "row tiles per wave");
+      if (i < NH - 1 || rt < NMT) {
         Frag pf[7];
 #pragma unroll
         for (int s = 0; s < 4; ++s) dma_frag<Frag>(&s_psi[buf][(s * NMT + rt) * SUB][0], lane, pf[s]);
