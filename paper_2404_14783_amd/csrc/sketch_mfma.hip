@@ -293,6 +293,17 @@ __device__ __forceinline__ void dma16(const void *src, void *lds_block) {
 }
 // wait until this wave's loads (direct-to-LDS ones included) have landed
 __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// wait until at most N (< 64) of this wave's vector memory instructions are
+// outstanding: they complete in issue order, so everything issued before the
+// last N has landed
+template <int N> __device__ __forceinline__ void wait_vm_but() {
+  static_assert(N >= 0 && N < 64, "vmcnt");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+}
+// vector memory instructions of one step's operand fetch of a lane
+template <int OP, typename TIN, bool PURE> constexpr int a_fetch_loads(int per_plane) {
+  return (PURE ? 3 : 4) * (per_plane + (OP == OP_FP8 ? 1 : 0));
+}
 
 template <typename Frag> __device__ __forceinline__ void dma_frag(const char *blk, int lane, Frag &f);
 template <> __device__ __forceinline__ void dma_frag<FragB>(const char *blk, int lane, FragB &f) {
@@ -441,8 +452,12 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
       to_frags<OP, TERMS>(xa[q], scn[q], af[q]);
     }
     voff += vstep;
-    QSK_W_FETCH_A(i0 + 32);                                // next step (past the end: unused)
+    // the next step's test-matrix tile first, then its operand values, so
+    // that the wait before the barrier can leave the latter in flight
     if (i0 + 32 < ie) QSK_W_DMA(i0 + 32, buf ^ 1);
+    __builtin_amdgcn_sched_barrier(0);
+    QSK_W_FETCH_A(i0 + 32);                                // next step (past the end: unused)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int i = 0; i < NH; ++i) {
       const int rt = rt0 + i;
@@ -465,7 +480,7 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
         }
       }
     }
-    wait_vm();
+    wait_vm_but<a_fetch_loads<OP, TIN, PURE>(sizeof(TIN) == 4 ? 2 : 1)>();
     __syncthreads();
     buf ^= 1;
   }
