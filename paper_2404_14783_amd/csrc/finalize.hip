@@ -1869,23 +1869,38 @@ __device__ void sm_bisect_all(const double *d, const double *e, int k, double *l
 // stride k; LDS or global), in order: each vector loses its components along
 // the earlier ones and is normalised.
 template <typename P>
-__device__ __forceinline__ void cgs2_block(P xs, int k, int c, double *coef, double *s_nrm) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+__device__ __forceinline__ void cgs2_block(P xs, int k, int c, double *coef, double *s_nrm,
+                                           QSK_LDS double *red) {
+  // inner products: 16 lanes per pair (j, i), 64 pairs at a time; the
+  // update x_i -= sum_j coef_j x_j: rows over rb threads, the sum over j
+  // split in np partial sums (short serial chains) that meet in red
+  // (blockDim.x doubles of LDS)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nt = blockDim.x, grp = tid >> 4, sl = tid & 15, ngrp = nt >> 4;
+  const int rb = k <= 128 ? 128 : 256, np = nt / rb, row = tid % rb, part = tid / rb;
   for (int i = 1; i < c; ++i) {
     P xi = xs + (int64_t)i * k;
     for (int pass = 0; pass < 2; ++pass) {
-      for (int j = wave; j < i; j += nw) {
+      for (int j = grp; j < i; j += ngrp) {
         P xj = xs + (int64_t)j * k;
         double s = 0.0;
-        for (int r = lane; r < k; r += 64) s += xj[r] * xi[r];
-        s = wave_sum(s);
-        if (lane == 0) coef[j] = s;
+        for (int r = sl; r < k; r += 16) s += xj[r] * xi[r];
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (sl == 0) coef[j] = s;
       }
       __syncthreads();
-      for (int r = tid; r < k; r += blockDim.x) {
-        double s = xi[r];
-        for (int j = 0; j < i; ++j) s -= coef[j] * xs[(int64_t)j * k + r];
-        xi[r] = s;
+      if (part < np) {
+        double acc = 0.0;
+        if (row < k)
+          for (int j = part; j < i; j += np) acc += coef[j] * xs[(int64_t)j * k + row];
+        red[part * rb + row] = acc;
+      }
+      __syncthreads();
+      if (part == 0 && row < k) {
+        double s = 0.0;
+        for (int p = 0; p < np; ++p) s += red[p * rb + row];
+        xi[row] -= s;
       }
       __syncthreads();
     }
@@ -2055,15 +2070,15 @@ __global__ __launch_bounds__(1024) void psvd_orth_kernel(PsvdArgs args, GroupRef
     const int c = c1 - c0;
     if (c > 1) {
       QSK_GLOBAL double *xg = gpw(L.X) + (int64_t)c0 * k;
-      if ((int64_t)c * k <= TRI_POOL) {
+      if ((int64_t)c * k + 1024 <= TRI_POOL) {
         QSK_LDS double *xs = (QSK_LDS double *)pool;
         for (int q = tid; q < c * k; q += blockDim.x) xs[q] = xg[q];
         __syncthreads();
-        cgs2_block(xs, k, c, coef, &s_nrm);
+        cgs2_block(xs, k, c, coef, &s_nrm, (QSK_LDS double *)(pool + (int64_t)c * k));
         for (int q = tid; q < c * k; q += blockDim.x) xg[q] = xs[q];
         __syncthreads();
       } else {
-        cgs2_block(xg, k, c, coef, &s_nrm);
+        cgs2_block(xg, k, c, coef, &s_nrm, (QSK_LDS double *)pool);
       }
     }
     c0 = c1;
