@@ -149,6 +149,24 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t total) {
 }
 
 // The negated copies of planes x, y, z of a test-matrix fragment set.
+__device__ __forceinline__ FragB negx(const FragB &a) { return negB(a); }
+__device__ __forceinline__ FragF negx(const FragF &a) { return negF(a); }
+// The sign of a product term goes on the data operand when it has at most
+// two terms: its planes x, y, z are negated once per step (the test-matrix
+// fragments of every tile would need it once per tile), and a signed
+// selection 4..6 multiplies the plain test-matrix plane 1..3 with the
+// negated data.  With three terms the registers are short, and the
+// test-matrix fragments are negated instead.
+template <int TERMS> constexpr bool neg_on_data() { return TERMS <= 2; }
+template <typename Frag, int TERMS>
+__device__ __forceinline__ void neg_data(const Frag (&af)[4][3], Frag (&naf)[4][3]) {
+  if constexpr (neg_on_data<TERMS>()) {
+#pragma unroll
+    for (int q = 1; q < 4; ++q)
+#pragma unroll
+      for (int tm = 0; tm < TERMS; ++tm) naf[q][tm] = negx(af[q][tm]);
+  }
+}
 __device__ __forceinline__ void neg3(FragB (&f)[7]) { f[4] = negB(f[1]); f[5] = negB(f[2]); f[6] = negB(f[3]); }
 __device__ __forceinline__ void neg3(FragF (&f)[7]) { f[4] = negF(f[1]); f[5] = negF(f[2]); f[6] = negF(f[3]); }
 
@@ -451,6 +469,8 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
       }
       to_frags<OP, TERMS>(xa[q], scn[q], af[q]);
     }
+    Frag naf[4][3];
+    neg_data<Frag, TERMS>(af, naf);
     voff += vstep;
     // the next step's test-matrix tile first, then its operand values, so
     // that the wait before the barrier can leave the latter in flight
@@ -461,22 +481,25 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
 #pragma unroll
     for (int i = 0; i < NH; ++i) {
       const int rt = rt0 + i;
-      // with at most two waves per SIMD only a wave's last row tile can lie
-      // past NMT: the others carry no branch, so the fragment reads of the
-      // next tile can be issued during the current tile's products
-      static_assert(H <= 2, "row tiles per wave");
-      if (i < NH - 1 || rt < NMT) {
+      // tiles that lie below NMT in every wave carry no branch, so the
+      // fragment reads of the next tile can be issued during the current
+      // tile's products
+      if ((H - 1) * NH + i < NMT || rt < NMT) {
         Frag pf[7];
 #pragma unroll
         for (int s = 0; s < 4; ++s) dma_frag<Frag>(&s_psi[buf][(s * NMT + rt) * SUB][0], lane, pf[s]);
-        neg3(pf);
+        if constexpr (!neg_on_data<TERMS>()) neg3(pf);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (q == 0 && PURE) continue;
 #pragma unroll
           for (int tm = 0; tm < TERMS; ++tm)
 #pragma unroll
-            for (int p = 0; p < 4; ++p) acc[i][p] = mma(pf[ssel(p, q)], af[q][tm], acc[i][p]);
+            for (int p = 0; p < 4; ++p) {
+              const int sp = ssel(p, q);
+              if constexpr (!neg_on_data<TERMS>()) acc[i][p] = mma(pf[sp], af[q][tm], acc[i][p]);
+              else acc[i][p] = sp < 4 ? mma(pf[sp], af[q][tm], acc[i][p]) : mma(pf[sp - 3], naf[q][tm], acc[i][p]);
+            }
         }
       }
     }
@@ -629,6 +652,8 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
     Frag af[4][3];
 #pragma unroll
     for (int q = 0; q < 4; ++q) to_frags<OP, TERMS>(xa[q], scn[q], af[q]);
+    Frag naf[4][3];
+    neg_data<Frag, TERMS>(af, naf);
     voff += vstep;
     QSK_Y_FETCH_A(t0 + 32);                                 // next step (past the end: unused)
     if (t0 + 32 < te) QSK_Y_DMA(t0 + 32, buf ^ 1);
@@ -637,14 +662,18 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
       Frag of[7];
 #pragma unroll
       for (int s = 0; s < 4; ++s) dma_frag<Frag>(&s_om[buf][(s * NJ + i) * SUB][0], lane, of[s]);
-      neg3(of);
+      if constexpr (!neg_on_data<TERMS>()) neg3(of);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (q == 0 && PURE) continue;
 #pragma unroll
         for (int tm = 0; tm < TERMS; ++tm)
 #pragma unroll
-          for (int p = 0; p < 4; ++p) acc[i][p] = mma(af[q][tm], of[rsel(q, p)], acc[i][p]);
+          for (int p = 0; p < 4; ++p) {
+            const int rs = rsel(q, p);
+            if constexpr (!neg_on_data<TERMS>()) acc[i][p] = mma(af[q][tm], of[rs], acc[i][p]);
+            else acc[i][p] = rs < 4 ? mma(af[q][tm], of[rs], acc[i][p]) : mma(naf[q][tm], of[rs - 3], acc[i][p]);
+          }
       }
     }
     wait_vm();
