@@ -44,52 +44,6 @@ __device__ __forceinline__ bool group_select(const A &a0, const GroupRef &g, A &
 }
 
 // ---------------------------------------------------------------------------
-// C = Z1^* Z2 (k1 x k2) over a chunk of rows per block.z.
-template <typename T1, typename T2>
-__global__ __launch_bounds__(256) void crossprod_k(CrossArgs args, GroupRef grp) {
-  CrossArgs A;
-  int bx, by, bz;
-  if (!group_select(args, grp, A, bx, by, bz)) return;
-  const PlanesC<T1> z1 = mkc_d<T1>(A.z1);
-  const PlanesC<T2> z2 = mkc_d<T2>(A.z2);
-  const int64_t ld1 = A.ld1, ld2 = A.ld2, rows = A.rows, chunk = A.chunk, ldo = A.ldo;
-  const int k1 = A.k1, k2 = A.k2, planar = A.planar;
-  double *partial = A.partial;
-  Planes<double> outp;
-  for (int q = 0; q < 4; ++q) outp.p[q] = A.out[q];
-  __shared__ qd s1[32][17];
-  __shared__ qd s2[32][17];
-  const int tid = threadIdx.x;
-  const int a = tid & 15, b = tid >> 4;
-  const int a0 = bx * 16, b0 = by * 16;
-  const int64_t rs = (int64_t)bz * chunk;
-  const int64_t re = min(rows, rs + chunk);
-  qd acc = qzero();
-  for (int64_t r0 = rs; r0 < re; r0 += 32) {
-    for (int e = tid; e < 512; e += 256) {
-      const int rr = e & 31, cc = e >> 5;
-      const int64_t row = r0 + rr;
-      const int c1 = a0 + cc, c2 = b0 + cc;
-      s1[rr][cc] = (row < re && c1 < k1) ? load_q(z1, row + (int64_t)c1 * ld1) : qzero();
-      s2[rr][cc] = (row < re && c2 < k2) ? load_q(z2, row + (int64_t)c2 * ld2) : qzero();
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int rr = 0; rr < 32; ++rr) qfma_cj(acc, s1[rr][a], s2[rr][b]);
-    __syncthreads();
-  }
-  const int ga = a0 + a, gb = b0 + b;
-  if (ga < k1 && gb < k2) {
-    if (planar) {
-      const int64_t o = ga + (int64_t)gb * ldo;
-      gpw(outp.p[0])[o] = acc.w; gpw(outp.p[1])[o] = acc.x; gpw(outp.p[2])[o] = acc.y; gpw(outp.p[3])[o] = acc.z;
-    } else {
-      QSK_GLOBAL double *q = gpw(partial) + 4 * (((int64_t)bz * k2 + gb) * k1 + ga);
-      q[0] = acc.w; q[1] = acc.x; q[2] = acc.y; q[3] = acc.z;
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Quaternion FP64 products on the matrix cores: C = opA(A) B with
 // opA(A)(i, t) = A(i, t) or its conjugate, as 16 real products per 16 x 16
@@ -384,12 +338,6 @@ __global__ void reduce_chunks_planar_k(ReducePlanarArgs args, GroupRef grp) {
   for (int p = 0; p < 4; ++p) gpw(out.p[p])[i + (int64_t)j * ldo] = s[p];
 }
 
-template <typename T> static PlanesC<T> mkc(const void *const z[4]) {
-  PlanesC<T> r;
-  for (int p = 0; p < 4; ++p) r.p[p] = (const T *)z[p];
-  return r;
-}
-
 static int64_t chunk_rows(int64_t rows, int tiles, int64_t max_chunks) {
   // aim for >= ~1024 blocks; chunk a multiple of 32 rows
   int64_t want = (1024 + tiles - 1) / tiles;
@@ -401,40 +349,11 @@ static int64_t chunk_rows(int64_t rows, int tiles, int64_t max_chunks) {
   return chunk;
 }
 
-static void set_planes(const void *dst[4], const void *const src[4]) {
-  for (int q = 0; q < 4; ++q) dst[q] = src[q];
-}
 static void set_planes(double *dst[4], double *const src[4]) {
   for (int q = 0; q < 4; ++q) dst[q] = src[q];
 }
 static void set_planes(const double *dst[4], const double *const src[4]) {
   for (int q = 0; q < 4; ++q) dst[q] = src[q];
-}
-
-// Plan of a crossprod: chunking of the rows and the partial-sum size.
-bool plan_crossprod(int64_t rows, int k1, int k2, int64_t partial_elems, int64_t *chunk,
-                    int64_t *nch) {
-  const int tiles = ((k1 + 15) / 16) * ((k2 + 15) / 16);
-  const int64_t per = (int64_t)k1 * k2 * 4;
-  const int64_t max_chunks = partial_elems / per;
-  if (max_chunks < 1) return false;
-  *chunk = chunk_rows(rows, tiles, max_chunks);
-  *nch = (rows + *chunk - 1) / *chunk;
-  return *nch <= max_chunks;
-}
-
-hipError_t launch_crossprod_k(hipStream_t st, int t1, int t2, const CrossArgs &a, GroupRef g,
-                              int64_t blocks) {
-  dim3 grid = g.tab ? dim3((unsigned)blocks) : dim3(a.gx, a.gy, (unsigned)blocks);
-  if (t1 == 0 && t2 == 0)
-    hipLaunchKernelGGL((crossprod_k<double, double>), grid, dim3(256), 0, st, a, g);
-  else if (t1 == 1 && t2 == 1)
-    hipLaunchKernelGGL((crossprod_k<float, float>), grid, dim3(256), 0, st, a, g);
-  else if (t1 == 0 && t2 == 1)
-    hipLaunchKernelGGL((crossprod_k<double, float>), grid, dim3(256), 0, st, a, g);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
 }
 
 hipError_t launch_reduce_k(hipStream_t st, const ReduceArgs &a, GroupRef g, int64_t blocks) {
@@ -586,67 +505,6 @@ bool g64_plan_psi(const void *psi_st, int es, int64_t psi_ld, int64_t psi_ps, co
 }
 
 // ---------------------------------------------------------------------------
-// Out = Z C: one row per thread, 16 output columns per block.y, C staged in
-// LDS 64 rows at a time.
-template <typename TZ>
-__global__ __launch_bounds__(256) void apply_k(ApplyArgs args, GroupRef grp) {
-  ApplyArgs A;
-  int bx, by, bz;
-  if (!group_select(args, grp, A, bx, by, bz)) return;
-  const PlanesC<TZ> z = mkc_d<TZ>(A.z);
-  const int64_t ldz = A.ldz, rows = A.rows, ldo = A.ldo;
-  const int k = A.k, kc = A.kc;
-  const double *__restrict__ c = A.c;
-  Planes<double> out;
-  for (int q = 0; q < 4; ++q) out.p[q] = A.out[q];
-  __shared__ qd sc[64][16];
-  const int tid = threadIdx.x;
-  const int b0 = by * 16;
-  const int64_t i = (int64_t)bx * 256 + tid;
-  qd acc[16];
-#pragma unroll
-  for (int b = 0; b < 16; ++b) acc[b] = qzero();
-  for (int a0 = 0; a0 < k; a0 += 64) {
-    for (int e = tid; e < 64 * 16; e += 256) {
-      const int aa = e >> 4, bb = e & 15;
-      const int ga = a0 + aa, gb = b0 + bb;
-      if (ga < k && gb < kc) {
-        const QSK_GLOBAL double *q = gp(c) + 4 * ((int64_t)ga + (int64_t)gb * k);
-        sc[aa][bb] = {q[0], q[1], q[2], q[3]};
-      } else {
-        sc[aa][bb] = qzero();
-      }
-    }
-    __syncthreads();
-    if (i < rows) {
-      const int amax = min(64, k - a0);
-      for (int aa = 0; aa < amax; ++aa) {
-        const qd zi = load_q(z, i + (int64_t)(a0 + aa) * ldz);
-#pragma unroll
-        for (int b = 0; b < 16; ++b) qfma(acc[b], zi, sc[aa][b]);
-      }
-    }
-    __syncthreads();
-  }
-  if (i < rows) {
-#pragma unroll
-    for (int b = 0; b < 16; ++b) {
-      const int gb = b0 + b;
-      if (gb < kc) {
-        const int64_t o = i + (int64_t)gb * ldo;
-        gpw(out.p[0])[o] = acc[b].w; gpw(out.p[1])[o] = acc[b].x; gpw(out.p[2])[o] = acc[b].y; gpw(out.p[3])[o] = acc[b].z;
-      }
-    }
-  }
-}
-
-hipError_t launch_apply_k(hipStream_t st, int tz, const ApplyArgs &a, GroupRef g, int64_t blocks) {
-  dim3 grid = g.tab ? dim3((unsigned)blocks) : dim3(a.gx, a.gy);
-  if (tz == 0) hipLaunchKernelGGL((apply_k<double>), grid, dim3(256), 0, st, a, g);
-  else hipLaunchKernelGGL((apply_k<float>), grid, dim3(256), 0, st, a, g);
-  return hipGetLastError();
-}
-
 hipError_t launch_apply(hipStream_t st, int tz, const void *const z[4], int64_t ldz, int64_t rows,
                         int k, const double *c_aos, int kc, double *const out[4], int64_t ldo,
                         int c_upper) {

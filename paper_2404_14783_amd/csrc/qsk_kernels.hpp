@@ -155,16 +155,6 @@ struct Gemm64Args {         // C = opA(A) B, quaternion, FP64 matrix cores (16 x
   int b_upper;                            // B upper triangular: t < 16 (tn + 1) only
   int gx, gy;
 };
-struct CrossArgs {          // C = Z1^* Z2 over row chunks (bz), 16 x 16 tiles (bx, by)
-  const void *z1[4]; int64_t ld1;
-  const void *z2[4]; int64_t ld2;
-  int64_t rows, chunk;
-  int k1, k2;
-  double *partial;          // [chunk][k2][k1] AoS when !planar
-  double *out[4]; int64_t ldo;
-  int planar;
-  int gx, gy;
-};
 struct ReduceArgs {
   const double *partial; int nchunks; int64_t elems; double *out;
   int herm, m;              // herm: tiles below the diagonal (16 x 16, m rows) mirror the ones above
@@ -172,13 +162,6 @@ struct ReduceArgs {
 };
 struct ReducePlanarArgs {
   const double *partial; int nchunks, r, c;
-  double *out[4]; int64_t ldo;
-  int gx, gy;
-};
-struct ApplyArgs {          // Out = Z C
-  const void *z[4]; int64_t ldz, rows;
-  int k;
-  const double *c; int kc;
   double *out[4]; int64_t ldo;
   int gx, gy;
 };
@@ -258,12 +241,10 @@ hipError_t launch_identity(hipStream_t st, int k, double *c);
 
 // Kernel launches taking an argument struct and a GroupRef (batched form:
 // `blocks` / `count` = total linear blocks / problems of the table).
-bool plan_crossprod(int64_t rows, int k1, int k2, int64_t partial_elems, int64_t *chunk, int64_t *nch);
 bool plan_psi_apply(int l, int64_t m, int k, int64_t partial_elems, int64_t *chunk, int64_t *nch);
 // ta / tb: 0 double, 1 float, 2 bf16 bits; conj_a conjugates A's entries.
 hipError_t launch_qgemm64_k(hipStream_t st, int ta, int tb, bool conj_a, const Gemm64Args &a, GroupRef g,
                             int64_t blocks);
-hipError_t launch_crossprod_k(hipStream_t st, int t1, int t2, const CrossArgs &a, GroupRef g, int64_t blocks);
 // Arguments of the FP64 matrix-core products for one problem of a grouped
 // launch; K is split in chunks of chunk_hint rows (longer where the
 // partial-sum buffer is short).
@@ -286,7 +267,6 @@ bool g64_plan_psi(const void *psi_st, int es, int64_t psi_ld, int64_t psi_ps, co
                   ReducePlanarArgs *r);
 hipError_t launch_reduce_k(hipStream_t st, const ReduceArgs &a, GroupRef g, int64_t blocks);
 hipError_t launch_reduce_planar_k(hipStream_t st, const ReducePlanarArgs &a, GroupRef g, int64_t blocks);
-hipError_t launch_apply_k(hipStream_t st, int tz, const ApplyArgs &a, GroupRef g, int64_t blocks);
 hipError_t launch_psi_apply_k(hipStream_t st, const PsiApplyArgs &a, GroupRef g, int64_t blocks);
 hipError_t launch_error_k(hipStream_t st, int tin, const ErrorArgs &a, GroupRef g, int64_t blocks);
 // Zero a status; keep_fail_any = 1 leaves the sticky fail_any as it is.
