@@ -205,7 +205,8 @@ qsk_status qsketch_batch_init(int32_t count, const qsk_config *cfgs, void *hip_s
    Q_i (m_i x k_i, FP64 planes Q[4 i + p], leading dimension ldq[i]) and
    X_i (k_i x n_i, FP64 planes X[4 i + p], leading dimension ldx[i]).  All
    arrays are host arrays of device pointers.  reports (count entries) may
-   be NULL.  Allocates nothing; synchronises the stream before returning.
+   be NULL.  Allocates no device buffers (a graph capture, below, makes the
+   runtime instantiate the graph); synchronises the stream before returning.
    QSK_E_NUMERIC if some problem's sketch is zero or non-finite (the other
    problems' outputs are still written).
 
