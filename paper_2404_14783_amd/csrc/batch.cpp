@@ -51,6 +51,8 @@ struct Prob {
   double *small = nullptr, *work = nullptr, *kwork = nullptr, *partials = nullptr;
   int64_t partial_elems = 0;
   double *pbuf = nullptr, *p1buf = nullptr, *sbuf = nullptr, *pinv_work = nullptr;
+  float *wpart = nullptr;                 // partial sums of a split W product
+  int64_t wpart_bytes = 0;
   qsk::MfmaStage stage{};
   // per-run state
   int passes = 0, need = 2, flags = 0;
@@ -296,6 +298,7 @@ static qsk_status launch_sketches(qsk_batch *b, const void *const *planes, const
     s.y = q.y; s.ldy = q.m; s.psy = q.m * (int64_t)q.k; s.pss = 0; s.y_copies = 1;
     s.w = q.w; s.ldw = q.l; s.psw = q.l * (int64_t)q.n;
     s.rad = q.cfg.embedding == QSK_RADEMACHER; s.terms = q.cfg.split_terms; s.k0 = q.k0; s.k1 = q.k1;
+    s.scratch = q.wpart; s.scratch_bytes = q.wpart_bytes;
     sg[i] = q.stage;
   }
   BCHK(b, qsk::launch_sketch_mfma_batch(sa.data(), sg.data(), n_all, b->nmt, b->nj, b->arena));
@@ -887,6 +890,8 @@ qsk_status qsketch_batch_init(int32_t count, const qsk_config *cfgs, void *hip_s
         // autotuner may pick
         4 * (size_t)max_pad(q.k, kNj, 2) * q.stage.NP * es,                            // omega staging
         4 * (size_t)max_pad(q.l, kNmt, c0.sketch_dtype == QSK_BF16 ? 3 : 2) * q.stage.MP * es,  // psi
+        // W partial sums: up to 8 row chunks of 4 planes x n x the padded l
+        8 * 4 * (size_t)q.n * max_pad(q.l, kNmt, c0.sketch_dtype == QSK_BF16 ? 3 : 2) * 4,
     };
     for (size_t s : sizes) {
       off[i].push_back(total);
@@ -934,6 +939,8 @@ qsk_status qsketch_batch_init(int32_t count, const qsk_config *cfgs, void *hip_s
     q.pinv_work = (double *)(base + o[11]);
     q.stage.omega = base + o[12];
     q.stage.psi = base + o[13];
+    q.wpart = (float *)(base + o[14]);
+    q.wpart_bytes = (int64_t)(8 * 4 * (size_t)q.n * max_pad(q.l, kNmt, c0.sketch_dtype == QSK_BF16 ? 3 : 2) * 4);
   }
   b->status = (SmallStatus *)(base + st_off);
   b->kstatus = (SmallStatus *)(base + st_off + al(sizeof(SmallStatus) * count));

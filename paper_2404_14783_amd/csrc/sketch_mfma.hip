@@ -544,6 +544,33 @@ __global__ void w_reduce_kernel(const float *part, int S, int LP, int64_t ncols,
   }
 }
 
+// The same sum for the problems of a batch whose W product was split:
+// 256 entries of W per block.
+struct WRedArgs {
+  const float *part;
+  int S, LP;
+  int64_t ncols;
+  int l;
+  float *w;
+  int64_t ldw, psw;
+};
+__global__ __launch_bounds__(256) void w_reduce_group_kernel(WRedArgs a0, GroupRef grp) {
+  (void)a0;
+  int pi;
+  int64_t t;
+  group_find(grp, &pi, &t);
+  const WRedArgs a = ((const WRedArgs *)grp.tab)[pi];
+  const int64_t e = t * 256 + threadIdx.x;
+  if (e >= 4 * a.ncols * (int64_t)a.l) return;
+  const int r = (int)(e % a.l);
+  const int64_t jp = e / a.l;
+  const int64_t j = jp % a.ncols;
+  const int p = (int)(jp / a.ncols);
+  float s = 0.f;
+  for (int z = 0; z < a.S; ++z) s += gp(a.part)[(((int64_t)z * 4 + p) * a.ncols + j) * a.LP + r];
+  gpw(a.w)[p * a.psw + j * a.ldw + r] += s;
+}
+
 // ---------------------------------------------------------------------------
 // Y kernel.  Tiles: 64 H rows of A x NJ column tiles of Y (16 columns each)
 // x one chunk of the update's columns (split K over S chunks; chunk s adds
@@ -1081,22 +1108,53 @@ static hipError_t launch_batch_t(const SketchArgs *s, const MfmaStage *g, int co
     w.rgroups = g[i].LP / (16 * nmt);
     w.ctiles = (int)((q.ncols + 63) / 64);
     w.S = 1; w.kchunk = rup(q.m, 32); w.part = nullptr;
-    pw[i + 1] = pw[i] + (int64_t)w.ctiles * w.rgroups;
+  }
+  // W: the rows of A split so that the blocks of all problems cover about
+  // the same number of rows (about 2048 blocks in all, at least 256 rows,
+  // at most 8 splits, partial sums within the problem's scratch)
+  int64_t work = 0;
+  for (int i = 0; i < count; ++i) work += (int64_t)ws[i].ctiles * ws[i].rgroups * ws[i].m;
+  const int64_t wchunk = std::max<int64_t>(256, rup(work / 2048, 32));
+  std::vector<WRedArgs> rs;
+  std::vector<int64_t> rb;
+  for (int i = 0; i < count; ++i) {
+    WArgs &w = ws[i];
+    const SketchArgs &q = s[i];
+    const int64_t per_split = 4 * q.ncols * (int64_t)w.LP * 4;
+    int64_t S = std::min<int64_t>(8, (w.m + wchunk - 1) / wchunk);
+    if (!q.scratch) S = 1;
+    S = std::min<int64_t>(S, std::max<int64_t>(1, q.scratch_bytes / per_split));
+    if (S > 1) {
+      w.kchunk = rup((w.m + S - 1) / S, 32);
+      S = (w.m + w.kchunk - 1) / w.kchunk;
+    }
+    if (S > 1) {
+      w.S = (int)S;
+      w.part = (float *)q.scratch;
+      WRedArgs r{};
+      r.part = w.part; r.S = w.S; r.LP = w.LP; r.ncols = q.ncols; r.l = q.l;
+      r.w = (float *)q.w; r.ldw = q.ldw; r.psw = q.psw;
+      rs.push_back(r);
+      rb.push_back((4 * q.ncols * (int64_t)q.l + 255) / 256);
+    } else {
+      w.S = 1; w.kchunk = rup(w.m, 32); w.part = nullptr;
+    }
+    pw[i + 1] = pw[i] + (int64_t)w.ctiles * w.rgroups * w.S;
   }
   // Blocks are dispatched in table order; the problems whose blocks run
-  // longest (most columns for Y, most rows for W) go first so that they do
-  // not form the tail of the launch.
+  // longest (most columns for Y, the longest row chunk for W) go first so
+  // that they do not form the tail of the launch.
   std::vector<int> oy(count), ow(count);
   for (int i = 0; i < count; ++i) oy[i] = ow[i] = i;
   std::stable_sort(oy.begin(), oy.end(), [&](int a, int b) { return ys[a].ncols > ys[b].ncols; });
-  std::stable_sort(ow.begin(), ow.end(), [&](int a, int b) { return ws[a].m > ws[b].m; });
+  std::stable_sort(ow.begin(), ow.end(), [&](int a, int b) { return ws[a].kchunk > ws[b].kchunk; });
   std::vector<YArgs> ys2(count);
   std::vector<WArgs> ws2(count);
   for (int i = 0; i < count; ++i) {
     ys2[i] = ys[oy[i]];
     ws2[i] = ws[ow[i]];
     py[i + 1] = py[i] + (int64_t)ys2[i].rblocks * ys2[i].cgroups;
-    pw[i + 1] = pw[i] + (int64_t)ws2[i].ctiles * ws2[i].rgroups;
+    pw[i + 1] = pw[i] + (int64_t)ws2[i].ctiles * ws2[i].rgroups * ws2[i].S;
   }
   ys.swap(ys2);
   ws.swap(ws2);
@@ -1113,6 +1171,14 @@ static hipError_t launch_batch_t(const SketchArgs *s, const MfmaStage *g, int co
   if (nmt == 13) launch_w<OP, TIN, TERMS, (!op_f32(OP) ? 13 : 7)>(ws[0], pw[count], st, gw);
   else if (nmt == 7) launch_w<OP, TIN, TERMS, 7>(ws[0], pw[count], st, gw);
   else launch_w<OP, TIN, TERMS, 4>(ws[0], pw[count], st, gw);
+  e = hipGetLastError();
+  if (e != hipSuccess || rs.empty()) return e;
+  std::vector<int64_t> pr(rs.size() + 1, 0);
+  for (size_t i = 0; i < rs.size(); ++i) pr[i + 1] = pr[i] + rb[i];
+  GroupRef gr{arena_push(ar, st, rs.data(), rs.size() * sizeof(WRedArgs)),
+              (const int64_t *)arena_push(ar, st, pr.data(), pr.size() * sizeof(int64_t)), (int)rs.size()};
+  if (!gr.tab || !gr.prefix) return hipErrorOutOfMemory;
+  hipLaunchKernelGGL(w_reduce_group_kernel, dim3((unsigned)pr.back()), dim3(256), 0, st, rs[0], gr);
   return hipGetLastError();
 }
 
