@@ -8,6 +8,12 @@ For an update that adds H to the columns J of A (A[:, J] += H):
     W[:, J] += Psi H
 Both are plain Hamilton products (``quaternion.hamilton``) in FP64.
 
+General linear update A <- theta A + eta H (Section 5.3 streams its image
+through linear updates of the sketches in the manner of Tropp et al.; the
+sketches are linear in A, so the update carries over to them):
+    Y <- theta Y + eta H Omega[J, :],   W <- theta W,   W[:, J] += eta Psi H.
+theta = 0 stores exact zeros.
+
 Low-precision emulation: when the sketch runs on low-precision operands, the
 oracle forms the exact operand values the device uses (``lowprec``) and then
 computes the same products in FP64, so that any difference from the device
@@ -80,17 +86,31 @@ class Sketch:
         c = self.cfg
         return embeddings.omega(c.embedding, np.arange(col0, col0 + ncols), c.k, c.seed, c.dtype)
 
-    def update(self, col0, block):
-        """A[:, col0:col0+ncols] += block (a linear update), so
-        Y += block Omega[J, :] and W[:, J] += Psi block."""
+    def scale(self, theta):
+        """A <- theta A, so Y <- theta Y and W <- theta W."""
+        if theta == 0.0:
+            self.Y[...] = 0.0
+            self.W[...] = 0.0
+        else:
+            self.Y *= theta
+            self.W *= theta
+
+    def update(self, col0, block, theta=1.0, eta=1.0):
+        """A <- theta A + eta H with H = block on the columns J = col0 ..
+        col0 + ncols - 1 (defaults: A[:, J] += block), so
+        Y <- theta Y + eta block Omega[J, :] and W <- theta W,
+        W[:, J] += eta Psi block."""
         block = qt.as_planes(block)
         c = self.cfg
         ncols = block.shape[2]
         if block.shape[1] != c.m or col0 < 0 or col0 + ncols > c.n:
             raise ValueError("block out of range")
-        a = data_operand(block, c)
-        self.Y += qt.hamilton(a, self.omega_rows(col0, ncols))
-        self.W[:, :, col0:col0 + ncols] += qt.hamilton(self.psi(), a)
+        if theta != 1.0:
+            self.scale(theta)
+        if eta != 0.0:
+            a = data_operand(block, c)
+            self.Y += eta * qt.hamilton(a, self.omega_rows(col0, ncols))
+            self.W[:, :, col0:col0 + ncols] += eta * qt.hamilton(self.psi(), a)
         self.columns_seen += ncols
 
 

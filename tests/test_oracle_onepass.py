@@ -49,6 +49,44 @@ def test_streaming_equals_one_shot_and_linear_updates():
     np.testing.assert_allclose(s.W, one.W, atol=1e-12)
 
 
+def test_general_linear_update_reaches_sketch_of_final_matrix():
+    """A <- theta A + eta H over a sequence of column blocks (Section 5.3's
+    linear updates, theta = 0 included): the streamed sketches equal
+    Y = A Omega and W = Psi A of the final matrix, formed here from A through
+    the real representation (Appendix B.1)."""
+    m, n, k, l = 40, 30, 6, 13
+    cfg = SketchConfig(m, n, k, l, seed=5)
+    rng = np.random.default_rng(9)
+    s = Sketch(cfg)
+    a = np.zeros((4, m, n))
+    steps = [(1.0, 1.0, 0, 12), (0.5, 2.0, 8, 22), (-1.5, 0.25, 0, 30), (0.0, 0.75, 3, 9),
+             (2.0, -3.0, 25, 5), (1.0, 0.0, 0, 4), (0.25, 1.0, 10, 20)]
+    for theta, eta, c0, nc in steps:
+        hblk = rng.standard_normal((4, m, nc))
+        s.update(c0, hblk, theta=theta, eta=eta)
+        a = theta * a
+        a[:, :, c0:c0 + nc] += eta * hblk
+    om = embeddings.omega("gaussian", np.arange(n), k, 5)
+    ps = embeddings.psi("gaussian", l, np.arange(m), 5)
+    np.testing.assert_allclose(qt.compact_real(s.Y), qt.upsilon(a) @ qt.compact_real(om), atol=1e-11)
+    np.testing.assert_allclose(qt.compact_real(s.W), qt.upsilon(ps) @ qt.compact_real(a), atol=1e-11)
+    assert s.columns_seen == sum(st[3] for st in steps)
+
+
+def test_update_with_negated_eta_undoes_it():
+    cfg = SketchConfig(30, 20, 4, 9, seed=6, embedding="rademacher")
+    s = Sketch(cfg)
+    base = small_lowrank(30, 20, 3, 1e-3, 3)
+    s.update(0, base)
+    y0, w0 = s.Y.copy(), s.W.copy()
+    hblk = np.random.default_rng(4).standard_normal((4, 30, 7))
+    s.update(5, hblk, eta=0.3)
+    assert np.linalg.norm(s.W - w0) > 1e-3
+    s.update(5, hblk, eta=-0.3)
+    np.testing.assert_allclose(s.Y, y0, atol=1e-12)
+    np.testing.assert_allclose(s.W, w0, atol=1e-12)
+
+
 def test_hx_independent_of_rangefinder_lemma42():
     a = small_lowrank(60, 50, 6, 1e-2, 5)
     sk = sketch_matrix(a, SketchConfig(60, 50, 8, 17, seed=1))
