@@ -111,7 +111,7 @@ typedef struct {
   int32_t t_bad;           /* pseudo-SVD: number of repaired pairs */
   int32_t flags;           /* QSK_FLAG_* */
   int32_t passes;          /* CholeskyQR passes used on Y */
-  int64_t columns_seen;    /* total columns passed to qsketch_update */
+  int64_t columns_seen;    /* columns passed to the update calls (or set on restore) */
   double orth_defect;      /* ||Q*Q - I||_max (pseudo-SVD; 0 for pseudo-QR) */
 } qsk_report;
 
@@ -133,6 +133,36 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out);
    Requires 0 <= col0, 1 <= ncols <= max_block_cols, col0 + ncols <= n. */
 qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols,
                           const void *const planes[4], int64_t ld);
+
+/* General linear update A <- theta A + eta H (Section 5.3 streams the image
+   through linear sketch updates of the kind introduced by Tropp et al.; both
+   sketches are linear in A), with H zero outside the columns
+   [col0, col0 + ncols):
+       Y <- theta Y + eta H Omega[col0 : col0 + ncols, :],
+       W <- theta W,  W[:, col0 : col0 + ncols] += eta Psi H.
+   Same block arguments and limits as qsketch_update; theta and eta must be
+   finite (QSK_E_ARG otherwise, with no side effect).  theta = 0 stores exact
+   zeros (any earlier content, non-finite values included, is dropped);
+   eta = 0 skips the products.  The products are scaled in the precision the
+   sketches are stored in (FP32 for the low-precision operand formats, FP64
+   otherwise), so eta enters rounded to that precision.  Stream-ordered. */
+qsk_status qsketch_update_linear(qsk_ctx *ctx, double theta, double eta, int64_t col0,
+                                 int64_t ncols, const void *const planes[4], int64_t ld);
+
+/* A <- theta A: Y <- theta Y, W <- theta W (theta finite; 0 stores zeros).
+   Stream-ordered. */
+qsk_status qsketch_scale(qsk_ctx *ctx, double theta);
+
+/* Load sketches (checkpoint restore): Y (m x k) and W (l x n) from FP64
+   planes, rounded to the storage precision of ctx (exact for values that
+   qsketch_sketches exported from a context of the same configuration), and
+   set the column count to columns_seen.  Y or W may be NULL to keep the
+   current one.  The caller must have created ctx with the configuration
+   (sizes, seed, embedding, operand format) that formed the sketches: the
+   test matrices are regenerated from it.  The FP64 planes are device memory
+   that must stay valid until the stream passes this call.  Stream-ordered. */
+qsk_status qsketch_set_sketches(qsk_ctx *ctx, const double *const Y[4], int64_t ldy,
+                                const double *const W[4], int64_t ldw, int64_t columns_seen);
 
 /* QB stage (Alg. 4) on the current sketches, in FP64 on the device:
    Q = F(Y) with F the chosen rangefinder (Alg. 1 or Alg. 3), then

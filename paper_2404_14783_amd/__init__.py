@@ -78,6 +78,12 @@ def _load():
     lib.qsketch_init.restype = i32
     lib.qsketch_update.argtypes = [vp, i64, i64, _P4, i64]
     lib.qsketch_update.restype = i32
+    lib.qsketch_update_linear.argtypes = [vp, ctypes.c_double, ctypes.c_double, i64, i64, _P4, i64]
+    lib.qsketch_update_linear.restype = i32
+    lib.qsketch_scale.argtypes = [vp, ctypes.c_double]
+    lib.qsketch_scale.restype = i32
+    lib.qsketch_set_sketches.argtypes = [vp, vp, i64, vp, i64, i64]
+    lib.qsketch_set_sketches.restype = i32
     lib.qsketch_finalize.argtypes = [vp, i32, _P4, i64, _P4, i64, ctypes.POINTER(QskReport)]
     lib.qsketch_finalize.restype = i32
     lib.qsketch_sketches.argtypes = [vp, _P4, i64, _P4, i64]
@@ -186,6 +192,11 @@ class Sketcher:
         self.sketch_dtype = sketch_dtype
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._config = dict(m=self.m, n=self.n, k=self.k, l=self.l, seed=int(seed), embedding=embedding,
+                            input_dtype=input_dtype, sketch_dtype=sketch_dtype, pure=self.pure,
+                            split_terms=int(split_terms), n_correction=int(n_correction),
+                            n_power=int(n_power), max_block_cols=int(max_block_cols))
+        self.columns_seen = 0
         self._ctx = ctypes.c_void_p()
         st = lib.qsketch_init(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
                               ctypes.byref(self._ctx))
@@ -198,12 +209,60 @@ class Sketcher:
             msg = self._lib.qsketch_last_error(self._ctx).decode() or self._lib.qsketch_strerror(st).decode()
             raise QSketchError(st, msg)
 
-    def update(self, col0, block):
-        """A[:, col0 : col0 + ncols] += block (planes column-major, input dtype)."""
+    def update(self, col0, block, theta=1.0, eta=1.0):
+        """A <- theta A + eta H with H = block on columns col0 : col0 + ncols
+        (planes column-major, input dtype); the defaults give A[:, J] += block."""
         if block.dtype != TORCH_DTYPE[self.input_dtype]:
             raise TypeError(f"block dtype {block.dtype} != input dtype {self.input_dtype}")
         ptrs, ld = _plane_ptrs(block, self.pure)
-        self._check(self._lib.qsketch_update(self._ctx, int(col0), int(block.shape[2]), ptrs, ld))
+        if theta == 1.0 and eta == 1.0:
+            self._check(self._lib.qsketch_update(self._ctx, int(col0), int(block.shape[2]), ptrs, ld))
+        else:
+            self._check(self._lib.qsketch_update_linear(self._ctx, float(theta), float(eta), int(col0),
+                                                        int(block.shape[2]), ptrs, ld))
+        self.columns_seen += int(block.shape[2])
+
+    def scale(self, theta):
+        """A <- theta A."""
+        self._check(self._lib.qsketch_scale(self._ctx, float(theta)))
+
+    def set_sketches(self, y=None, w=None, columns_seen=0):
+        """Load Y (4, m, k) and/or W (4, l, n) FP64 device planes."""
+        def ptrs(t, rows):
+            if t is None:
+                return None, rows
+            if t.dtype != torch.float64 or tuple(t.shape[1:]) != (rows, t.shape[2]):
+                raise ValueError("sketch planes must be FP64 (4, rows, cols)")
+            p, ld = _plane_ptrs(t, False)
+            return ctypes.cast(p, ctypes.c_void_p), ld
+        if w is not None and tuple(w.shape) != (4, self.l, self.n):
+            raise ValueError("W must be (4, l, n)")
+        if y is not None and tuple(y.shape) != (4, self.m, self.k):
+            raise ValueError("Y must be (4, m, k)")
+        yp, ldy = ptrs(y, self.m)
+        wp, ldw = ptrs(w, self.l)
+        self._check(self._lib.qsketch_set_sketches(self._ctx, yp, ldy, wp, ldw, int(columns_seen)))
+        self.stream.synchronize()
+        self.columns_seen = int(columns_seen)
+
+    def config(self):
+        """The configuration a restored context must be created with."""
+        return dict(self._config)
+
+    def checkpoint(self):
+        """Host copy of the sketch state: {'config', 'Y', 'W', 'columns_seen'}
+        (Y, W as FP64 CPU tensors)."""
+        y, w = self.sketches()
+        return {"config": self.config(), "Y": y.cpu(), "W": w.cpu(), "columns_seen": self.columns_seen}
+
+    @classmethod
+    def restore(cls, state, stream=None):
+        """A new context with the checkpoint's configuration and sketches."""
+        sk = cls(**state["config"], stream=stream)
+        y = state["Y"].to(sk.device)
+        w = state["W"].to(sk.device)
+        sk.set_sketches(to_colmajor(y), to_colmajor(w), state["columns_seen"])
+        return sk
 
     def finalize(self, rangefinder="pseudo_qr", q=None, x=None):
         """QB stage: returns (Q, X, report) with Q (4, m, k) and X (4, k, n) FP64."""
@@ -228,6 +287,7 @@ class Sketcher:
 
     def reset(self):
         self._check(self._lib.qsketch_reset(self._ctx))
+        self.columns_seen = 0
 
     def rel_error(self, a, q, x):
         ap, lda = _plane_ptrs(a, self.pure)

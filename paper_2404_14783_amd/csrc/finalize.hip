@@ -5,6 +5,8 @@
 // small dense k x k quaternion algebra (Cholesky, triangular inverse,
 // products, the pseudo-QR corrections, one-sided Jacobi SVD, pseudo-SVD pair
 // selection and repair).
+#include <algorithm>
+
 #include "qsk_device.hpp"
 #include "qsk_kernels.hpp"
 
@@ -671,6 +673,47 @@ hipError_t launch_widen(hipStream_t st, int tsrc, const void *src, int64_t lds, 
   else
     hipLaunchKernelGGL((widen_k<float>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                        (const float *)src, lds, pss, rows, cols, d, ldd);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void scale_k(T *p, int64_t n, T theta) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = theta == T(0) ? T(0) : p[e] * theta;
+}
+
+hipError_t launch_scale(hipStream_t st, int tsrc, void *p, int64_t n, double theta) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 16384);
+  if (tsrc == 0)
+    hipLaunchKernelGGL((scale_k<double>), dim3((unsigned)blocks), dim3(256), 0, st, (double *)p, n, theta);
+  else
+    hipLaunchKernelGGL((scale_k<float>), dim3((unsigned)blocks), dim3(256), 0, st, (float *)p, n, (float)theta);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void narrow_k(PlanesC<double> src, int64_t lds, T *dst, int64_t ldd, int64_t pss, int64_t rows,
+                         int64_t cols) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % rows, j = e / rows;
+    for (int p = 0; p < 4; ++p) dst[p * pss + i + j * ldd] = (T)src.p[p][i + j * lds];
+  }
+}
+
+hipError_t launch_narrow(hipStream_t st, int tdst, const double *const src[4], int64_t lds,
+                         void *dst, int64_t ldd, int64_t pss, int64_t rows, int64_t cols) {
+  PlanesC<double> s;
+  for (int p = 0; p < 4; ++p) s.p[p] = src[p];
+  const int64_t blocks = std::min<int64_t>((rows * cols + 255) / 256, 16384);
+  if (blocks <= 0) return hipSuccess;
+  if (tdst == 0)
+    hipLaunchKernelGGL((narrow_k<double>), dim3((unsigned)blocks), dim3(256), 0, st, s, lds, (double *)dst, ldd,
+                       pss, rows, cols);
+  else
+    hipLaunchKernelGGL((narrow_k<float>), dim3((unsigned)blocks), dim3(256), 0, st, s, lds, (float *)dst, ldd,
+                       pss, rows, cols);
   return hipGetLastError();
 }
 

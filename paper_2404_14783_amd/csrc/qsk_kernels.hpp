@@ -35,6 +35,7 @@ struct SketchArgs {
   float *fp8_scales;     // fp8 tile scales of the block, [4][ceil(m/32)][ceil(ncols/32)]
   int64_t fp8_scale_elems;
   int psi_ready;         // the staging buffer already holds Psi (it does not change)
+  double eta = 1.0;      // scale of the products: Y += eta H Omega_J, W[:, J] += eta Psi H
   // optional timing: events[2 * kernel] before, [2 * kernel + 1] after (may be null)
   hipEvent_t *events;
 };
@@ -108,6 +109,13 @@ hipError_t launch_psi_apply(hipStream_t st, int mode, int rad, uint32_t k0, uint
                             int64_t ldp, const void *psi_st = nullptr, int psi_st_type = 0,
                             int64_t psi_ld = 0, int64_t psi_ps = 0);
 // Convert sketch planes (float or double) to FP64 planes.
+// p[0 .. n) *= theta in place (T = float when tsrc != 0, else double);
+// theta == 0 stores zeros.
+hipError_t launch_scale(hipStream_t st, int tsrc, void *p, int64_t n, double theta);
+// dst plane p (rows x cols, leading dimension ldd, planes pss apart) = the
+// FP64 planes src rounded to the destination type (float when tdst != 0).
+hipError_t launch_narrow(hipStream_t st, int tdst, const double *const src[4], int64_t lds,
+                         void *dst, int64_t ldd, int64_t pss, int64_t rows, int64_t cols);
 hipError_t launch_widen(hipStream_t st, int tsrc, const void *src, int64_t lds, int64_t pss,
                         int64_t rows, int64_t cols, double *const dst[4], int64_t ldd);
 // sum over planes/columns of ||A - Q X||^2 and ||A||^2 (into acc[0], acc[1]).

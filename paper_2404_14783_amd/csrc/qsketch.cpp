@@ -318,10 +318,8 @@ qsk_status qsketch_reset(qsk_ctx *ctx) {
   return QSK_OK;
 }
 
-qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void *const planes[4],
-                          int64_t ld) {
-  if (!ctx) return QSK_E_ARG;
-  if (ctx->poisoned) return QSK_E_STATE;
+static qsk_status check_block(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void *const planes[4],
+                              int64_t ld) {
   const qsk_config &c = ctx->cfg;
   if (!planes) return fail_arg(ctx, "planes is NULL");
   if (col0 < 0 || ncols < 1 || ncols > c.max_block_cols || col0 + ncols > c.n)
@@ -329,7 +327,15 @@ qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void 
   if (ld < c.m) return fail_arg(ctx, "ld < m");
   for (int p = c.pure ? 1 : 0; p < 4; ++p)
     if (!planes[p]) return fail_arg(ctx, "NULL plane");
+  return QSK_OK;
+}
+
+// Y += eta H Omega_J, W[:, J] += eta Psi H for a checked block.
+static qsk_status sketch_block(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void *const planes[4],
+                               int64_t ld, double eta) {
+  const qsk_config &c = ctx->cfg;
   qsk::SketchArgs s{};
+  s.eta = eta;
   s.stream = ctx->stream;
   s.mode = ctx->mode;
   s.in_dtype = c.input_dtype;
@@ -375,7 +381,75 @@ qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void 
   }
   if (e == hipErrorNotSupported) e = qsk::launch_sketch_generic(s);
   if (e != hipSuccess) return hip_fail(ctx, e, "sketch update");
-  ctx->columns_seen += ncols;
+  return QSK_OK;
+}
+
+qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void *const planes[4],
+                          int64_t ld) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  qsk_status st = check_block(ctx, col0, ncols, planes, ld);
+  if (st == QSK_OK) st = sketch_block(ctx, col0, ncols, planes, ld, 1.0);
+  if (st == QSK_OK) ctx->columns_seen += ncols;
+  return st;
+}
+
+// A <- theta A: both sketches are linear in A, so Y <- theta Y, W <- theta W
+// (every split-K copy of Y scales with the sum).
+static qsk_status scale_sketches(qsk_ctx *ctx, double theta) {
+  if (theta == 1.0) return QSK_OK;
+  const qsk_config &c = ctx->cfg;
+  const int t = ctx->mode == qsk::MODE_F64 ? 0 : 1;
+  HIPCHK(ctx, qsk::launch_scale(ctx->stream, t, ctx->y, (int64_t)ctx->y_copies * 4 * c.m * (int64_t)c.k, theta));
+  HIPCHK(ctx, qsk::launch_scale(ctx->stream, t, ctx->w, 4 * (int64_t)c.l * c.n, theta));
+  return QSK_OK;
+}
+
+qsk_status qsketch_scale(qsk_ctx *ctx, double theta) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  if (!std::isfinite(theta)) return fail_arg(ctx, "theta is not finite");
+  return scale_sketches(ctx, theta);
+}
+
+qsk_status qsketch_update_linear(qsk_ctx *ctx, double theta, double eta, int64_t col0, int64_t ncols,
+                                 const void *const planes[4], int64_t ld) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  if (!std::isfinite(theta) || !std::isfinite(eta)) return fail_arg(ctx, "theta or eta is not finite");
+  qsk_status st = check_block(ctx, col0, ncols, planes, ld);
+  if (st == QSK_OK) st = scale_sketches(ctx, theta);
+  if (st == QSK_OK && eta != 0.0) st = sketch_block(ctx, col0, ncols, planes, ld, eta);
+  if (st == QSK_OK) ctx->columns_seen += ncols;
+  return st;
+}
+
+qsk_status qsketch_set_sketches(qsk_ctx *ctx, const double *const Y[4], int64_t ldy,
+                                const double *const W[4], int64_t ldw, int64_t columns_seen) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  const qsk_config &c = ctx->cfg;
+  if (columns_seen < 0) return fail_arg(ctx, "columns_seen < 0");
+  if (Y) {
+    if (ldy < c.m) return fail_arg(ctx, "ldy < m");
+    for (int p = 0; p < 4; ++p)
+      if (!Y[p]) return fail_arg(ctx, "NULL Y plane");
+  }
+  if (W) {
+    if (ldw < c.l) return fail_arg(ctx, "ldw < l");
+    for (int p = 0; p < 4; ++p)
+      if (!W[p]) return fail_arg(ctx, "NULL W plane");
+  }
+  const int t = ctx->mode == qsk::MODE_F64 ? 0 : 1;
+  if (Y) {
+    const int64_t per_copy = 4 * c.m * (int64_t)c.k;
+    if (ctx->y_copies > 1)
+      HIPCHK(ctx, hipMemsetAsync((char *)ctx->y + per_copy * ctx->ts, 0,
+                                 (size_t)(ctx->y_copies - 1) * per_copy * ctx->ts, ctx->stream));
+    HIPCHK(ctx, qsk::launch_narrow(ctx->stream, t, Y, ldy, ctx->y, c.m, c.m * (int64_t)c.k, c.m, c.k));
+  }
+  if (W) HIPCHK(ctx, qsk::launch_narrow(ctx->stream, t, W, ldw, ctx->w, c.l, c.l * (int64_t)c.n, c.l, c.n));
+  ctx->columns_seen = columns_seen;
   return QSK_OK;
 }
 

@@ -63,7 +63,8 @@ template <int MODE, typename TIN, typename TY>
 __global__ __launch_bounds__(256) void sketch_y_generic(PlanesC<TIN> a, int64_t lda, int pure,
                                                         int64_t m, int64_t col0, int64_t ncols,
                                                         int k, TY *y, int64_t ldy, int64_t psy,
-                                                        int rad, int terms, uint32_t k0, uint32_t k1) {
+                                                        int rad, int terms, uint32_t k0, uint32_t k1,
+                                                        double eta) {
   __shared__ double om[32][8][4];
   const int r = threadIdx.x & 63, c = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + r;
@@ -100,11 +101,11 @@ __global__ __launch_bounds__(256) void sketch_y_generic(PlanesC<TIN> a, int64_t 
     const int ja = j0 + c, jb = j0 + c + 4;
     if (ja < k) {
       TY *q = y + i + ja * ldy;
-      add_out(q, acc0.w); add_out(q + psy, acc0.x); add_out(q + 2 * psy, acc0.y); add_out(q + 3 * psy, acc0.z);
+      add_out(q, eta * acc0.w); add_out(q + psy, eta * acc0.x); add_out(q + 2 * psy, eta * acc0.y); add_out(q + 3 * psy, eta * acc0.z);
     }
     if (jb < k) {
       TY *q = y + i + jb * ldy;
-      add_out(q, acc1.w); add_out(q + psy, acc1.x); add_out(q + 2 * psy, acc1.y); add_out(q + 3 * psy, acc1.z);
+      add_out(q, eta * acc1.w); add_out(q + psy, eta * acc1.x); add_out(q + 2 * psy, eta * acc1.y); add_out(q + 3 * psy, eta * acc1.z);
     }
   }
 }
@@ -114,7 +115,8 @@ template <int MODE, typename TIN, typename TW>
 __global__ __launch_bounds__(256) void sketch_w_generic(PlanesC<TIN> a, int64_t lda, int pure,
                                                         int64_t m, int64_t col0, int64_t ncols,
                                                         int l, TW *w, int64_t ldw, int64_t psw,
-                                                        int rad, int terms, uint32_t k0, uint32_t k1) {
+                                                        int rad, int terms, uint32_t k0, uint32_t k1,
+                                                        double eta) {
   __shared__ double ps[8][32][4];
   const int jc = threadIdx.x & 63, rg = threadIdx.x >> 6;
   const int64_t j = (int64_t)blockIdx.x * 64 + jc;
@@ -151,11 +153,11 @@ __global__ __launch_bounds__(256) void sketch_w_generic(PlanesC<TIN> a, int64_t 
     const int ra = r0 + rg, rb = r0 + rg + 4;
     if (ra < l) {
       TW *q = w + ra + (col0 + j) * ldw;
-      add_out(q, acc0.w); add_out(q + psw, acc0.x); add_out(q + 2 * psw, acc0.y); add_out(q + 3 * psw, acc0.z);
+      add_out(q, eta * acc0.w); add_out(q + psw, eta * acc0.x); add_out(q + 2 * psw, eta * acc0.y); add_out(q + 3 * psw, eta * acc0.z);
     }
     if (rb < l) {
       TW *q = w + rb + (col0 + j) * ldw;
-      add_out(q, acc1.w); add_out(q + psw, acc1.x); add_out(q + 2 * psw, acc1.y); add_out(q + 3 * psw, acc1.z);
+      add_out(q, eta * acc1.w); add_out(q + psw, eta * acc1.x); add_out(q + 2 * psw, eta * acc1.y); add_out(q + 3 * psw, eta * acc1.z);
     }
   }
 }
@@ -167,12 +169,12 @@ static hipError_t launch_generic_t(const SketchArgs &s) {
   if (s.pure || !a.p[0]) a.p[0] = a.p[1];
   dim3 gy((unsigned)((s.m + 63) / 64), (unsigned)((s.k + 7) / 8));
   hipLaunchKernelGGL((sketch_y_generic<MODE, TIN, TS>), gy, dim3(256), 0, s.stream, a, s.lda, s.pure,
-                     s.m, s.col0, s.ncols, s.k, (TS *)s.y, s.ldy, s.psy, s.rad, s.terms, s.k0, s.k1);
+                     s.m, s.col0, s.ncols, s.k, (TS *)s.y, s.ldy, s.psy, s.rad, s.terms, s.k0, s.k1, s.eta);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   dim3 gw((unsigned)((s.ncols + 63) / 64), (unsigned)((s.l + 7) / 8));
   hipLaunchKernelGGL((sketch_w_generic<MODE, TIN, TS>), gw, dim3(256), 0, s.stream, a, s.lda, s.pure,
-                     s.m, s.col0, s.ncols, s.l, (TS *)s.w, s.ldw, s.psw, s.rad, s.terms, s.k0, s.k1);
+                     s.m, s.col0, s.ncols, s.l, (TS *)s.w, s.ldw, s.psw, s.rad, s.terms, s.k0, s.k1, s.eta);
   return hipGetLastError();
 }
 

@@ -358,6 +358,7 @@ struct WArgs {
   float *part;                // [S][4][ncols][LP]
   const float *fsc;           // fp8 tile scales [4][RT][CT] (OP_FP8)
   int RT, CT;
+  float eta = 1.f;            // W += eta Psi H
 };
 
 template <int OP, typename TIN, int NMT, int TERMS, bool PURE, int H>
@@ -520,7 +521,7 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
         QSK_GLOBAL float *dst = gpw(a.w + p * a.psw + (a.col0 + j) * a.ldw);
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt)
-          if (r0 + tt < a.l) dst[r0 + tt] += acc[i][p][tt];
+          if (r0 + tt < a.l) dst[r0 + tt] += a.eta * acc[i][p][tt];
       } else {
         float *dst = a.part + (((int64_t)bz * 4 + p) * a.ncols + j) * a.LP + r0;
         *(QSK_GLOBAL floatx4 *)dst = acc[i][p];
@@ -530,7 +531,7 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
 }
 
 __global__ void w_reduce_kernel(const float *part, int S, int LP, int64_t ncols, int l, int64_t col0,
-                                float *w, int64_t ldw, int64_t psw) {
+                                float *w, int64_t ldw, int64_t psw, float eta) {
   const int64_t total = 4 * ncols * (int64_t)l;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -540,7 +541,7 @@ __global__ void w_reduce_kernel(const float *part, int S, int LP, int64_t ncols,
     const int p = (int)(jp / ncols);
     float s = 0.f;
     for (int z = 0; z < S; ++z) s += gp(part)[(((int64_t)z * 4 + p) * ncols + j) * LP + r];
-    gpw(w)[p * psw + (col0 + j) * ldw + r] += s;
+    gpw(w)[p * psw + (col0 + j) * ldw + r] += eta * s;
   }
 }
 
@@ -592,6 +593,7 @@ struct YArgs {
   int64_t ldy, psy, pss;      // copy s of plane p: y + s * pss + p * psy
   const float *fsc;           // fp8 tile scales [4][RT][CT] (OP_FP8)
   int RT, CT;
+  float eta = 1.f;            // Y += eta H Omega
 };
 
 template <int OP, typename TIN, int NJ, int TERMS, bool PURE, int H>
@@ -735,7 +737,7 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
       const uint32_t o = jj < a.k ? (uint32_t)((jj * a.ldy + r0) * 4) : 0xFFFFFFF0u;
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        const floatx4 v = old[i][p] + acc[i][p];
+        const floatx4 v = old[i][p] + a.eta * acc[i][p];
         const u32v4 u = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z), __float_as_uint(v.w)};
         __builtin_amdgcn_raw_buffer_store_b128(u, yr[p], o, 0, 0);
       }
@@ -751,7 +753,7 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
       QSK_GLOBAL float *dst = gpw(ys + p * a.psy + (int64_t)jj * a.ldy);
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt)
-        if (r0 + tt < a.m) dst[r0 + tt] += acc[i][p][tt];
+        if (r0 + tt < a.m) dst[r0 + tt] += a.eta * acc[i][p][tt];
     }
   }
 }
@@ -957,7 +959,7 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     for (int p = 0; p < 4; ++p) y.a[p] = s.planes[p];
     y.lda = s.lda; y.m = s.m; y.ncols = s.ncols;
     y.om = om; y.KP = g.KP; y.NP = NPu;
-    y.k = s.k; y.pure = s.pure;
+    y.k = s.k; y.pure = s.pure; y.eta = (float)s.eta;
     y.y = (float *)s.y; y.ldy = s.ldy; y.psy = s.psy; y.pss = s.pss;
     const int nj = y_nj(s.k);
     const int ntiles = (s.k + 15) / 16;
@@ -984,7 +986,7 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     for (int p = 0; p < 4; ++p) w.a[p] = s.planes[p];
     w.lda = s.lda; w.m = s.m; w.ncols = s.ncols; w.col0 = s.col0;
     w.psi = ps; w.LP = g.LP; w.MP = g.MP;
-    w.l = s.l; w.pure = s.pure;
+    w.l = s.l; w.pure = s.pure; w.eta = (float)s.eta;
     w.w = (float *)s.w; w.ldw = s.ldw; w.psw = s.psw;
     const int nmt = w_nmt(s.l, !op_f32(OP));
     w.rgroups = (int)(g.LP / (16 * nmt));
@@ -1017,7 +1019,7 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
       if (rblocks > 65536) rblocks = 65536;
       hipLaunchKernelGGL(w_reduce_kernel, dim3((unsigned)rblocks), dim3(256), 0, s.stream,
                          (const float *)s.scratch, (int)S, g.LP, s.ncols, s.l, s.col0, (float *)s.w,
-                         s.ldw, s.psw);
+                         s.ldw, s.psw, (float)s.eta);
       e = hipGetLastError();
     }
     mark(s, 7);

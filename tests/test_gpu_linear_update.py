@@ -1,0 +1,145 @@
+"""General linear updates A <- theta A + eta H (Section 5.3 streams its data
+through linear sketch updates; both sketches are linear in A) and checkpoint
+/ restore of the sketch state, through the C ABI.
+
+Tolerances as in the other parity tests (relative Frobenius norm): FP64
+sketches 1e-12; FP32 accumulation 1e-5 (the scalings by theta and eta add a
+few FP32 roundings per entry, far below that).  The oracle forms the same
+operand values (data split or quantised per update block, test matrices
+rounded) and applies theta and eta in FP64.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2404_14783_amd as qs
+import synth
+from oracle import quaternion as qt
+from oracle.sketch import Sketch, SketchConfig
+from tests.gpu_helpers import input_values, rel, to_device, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+# (theta, eta) per update; theta = 0 drops the history, eta = 0 skips the products
+STEPS = [(1.0, 1.0), (0.5, 2.0), (-1.5, 0.25), (1.0, 1.0), (0.0, 0.75), (2.0, -3.0),
+         (1.0, 0.0), (0.25, 1.0), (-0.5, -0.5)]
+
+CASES = [
+    # sketch dtype, input dtype, embedding, terms, m, tolerance
+    ("f64", "f64", "gaussian", 1, 333, 1e-12),
+    ("f32", "f32", "gaussian", 1, 333, 1e-5),
+    ("bf16", "f32", "gaussian", 2, 333, 1e-5),
+    ("bf16", "f32", "rademacher", 2, 1100, 1e-5),   # W split over row chunks + reduction
+    ("fp8", "f32", "gaussian", 2, 333, 1e-5),
+]
+
+
+def oracle_cfg(m, n, k, l, seed, emb, sketch, terms):
+    if sketch == "fp8":
+        return SketchConfig(m, n, k, l, seed=seed, embedding=emb, dtype="fp8", fp8_block=32,
+                            fp8_residual=terms == 2)
+    return SketchConfig(m, n, k, l, seed=seed, embedding=emb, dtype=sketch, terms=terms)
+
+
+@pytest.mark.parametrize("sketch,dtype,emb,terms,m,tol", CASES)
+def test_general_linear_updates(sketch, dtype, emb, terms, m, tol):
+    n, k, l, block = 257, 12, 25, 50
+    print(f"linear update: {sketch} {dtype} {emb} terms={terms} m={m}", flush=True)
+    rng = np.random.default_rng(123)
+    sk = qs.Sketcher(m, n, k, l, seed=7, embedding=emb, input_dtype=dtype, sketch_dtype=sketch,
+                     split_terms=terms, max_block_cols=block)
+    ref = Sketch(oracle_cfg(m, n, k, l, 7, emb, sketch, terms))
+    a = synth.lowrank_plus_noise(m, n, torch.tensor(0.8 ** np.arange(10)), 1e-3, 77).numpy()
+    a = input_values(a, dtype)
+    dev = to_device(a, dtype)
+    for c0 in range(0, n, block):                      # the first pass: plain updates
+        sk.update(c0, dev[:, :, c0:c0 + block])
+        ref.update(c0, a[:, :, c0:c0 + block])
+    for theta, eta in STEPS:
+        c0 = int(rng.integers(0, n - 1))
+        nc = int(min(n - c0, rng.integers(1, block + 1)))
+        h = input_values(rng.standard_normal((4, m, nc)), dtype)
+        sk.update(c0, to_device(h, dtype), theta=theta, eta=eta)
+        ref.update(c0, h, theta=theta, eta=eta)
+    y, w = (to_numpy(t) for t in sk.sketches())
+    ey, ew = rel(y, ref.Y), rel(w, ref.W)
+    print(f"  rel. diff Y {ey:.2e}, W {ew:.2e}", flush=True)
+    assert ey < tol and ew < tol
+    assert sk.columns_seen == ref.columns_seen
+    # A <- theta A alone
+    sk.scale(-0.125)
+    ref.scale(-0.125)
+    y, w = (to_numpy(t) for t in sk.sketches())
+    assert rel(y, ref.Y) < tol and rel(w, ref.W) < tol
+    sk.close()
+
+
+def test_invalid_scalars_leave_sketches_unchanged():
+    m, n, k, l = 200, 120, 8, 17
+    a = synth.lowrank_plus_noise(m, n, torch.tensor(0.7 ** np.arange(6)), 1e-3, 5).numpy()
+    sk = qs.Sketcher(m, n, k, l, seed=1, input_dtype="f32", sketch_dtype="bf16", split_terms=2,
+                     max_block_cols=64)
+    dev = to_device(input_values(a, "f32"), "f32")
+    sk.update(0, dev[:, :, :64])
+    y0, w0 = (to_numpy(t) for t in sk.sketches())
+    for theta, eta in ((float("nan"), 1.0), (1.0, float("inf"))):
+        with pytest.raises(qs.QSketchError):
+            sk.update(0, dev[:, :, :64], theta=theta, eta=eta)
+    with pytest.raises(qs.QSketchError):
+        sk.scale(float("inf"))
+    y1, w1 = (to_numpy(t) for t in sk.sketches())
+    np.testing.assert_array_equal(y1, y0)
+    np.testing.assert_array_equal(w1, w0)
+    sk.close()
+
+
+@pytest.mark.parametrize("sketch,dtype,terms", [("f64", "f64", 1), ("bf16", "f32", 2),
+                                                ("fp8", "f32", 2)])
+def test_checkpoint_restore_continues_stream(sketch, dtype, terms):
+    """Stream half the columns, checkpoint to host memory, restore into a new
+    context and stream the rest: the sketches match an uninterrupted stream
+    (W exactly: its columns are written by one block each; Y up to the order
+    of its FP32 split-K partial sums), and the QB stage on the same sketch
+    values gives the same H X."""
+    m, n, k, l, block = 700, 320, 16, 33, 64
+    cut = 192
+    print(f"checkpoint: {sketch} {dtype} terms={terms}", flush=True)
+    a = synth.lowrank_plus_noise(m, n, torch.tensor(0.8 ** np.arange(12)), 1e-4, 31).numpy()
+    a = input_values(a, dtype)
+    dev = to_device(a, dtype)
+    kw = dict(seed=11, input_dtype=dtype, sketch_dtype=sketch, split_terms=terms, max_block_cols=block)
+    full = qs.Sketcher(m, n, k, l, **kw)
+    part = qs.Sketcher(m, n, k, l, **kw)
+    for c0 in range(0, n, block):
+        full.update(c0, dev[:, :, c0:c0 + block])
+        if c0 < cut:
+            part.update(c0, dev[:, :, c0:c0 + block])
+    state = part.checkpoint()
+    part.close()
+    assert state["columns_seen"] == cut and state["Y"].device.type == "cpu"
+    res = qs.Sketcher.restore(state)
+    y_r, w_r = (to_numpy(t) for t in res.sketches())
+    np.testing.assert_array_equal(y_r, state["Y"].numpy())      # exact round trip
+    np.testing.assert_array_equal(w_r, state["W"].numpy())
+    for c0 in range(cut, n, block):
+        res.update(c0, dev[:, :, c0:c0 + block])
+    y1, w1 = full.sketches()
+    y2, w2 = res.sketches()
+    np.testing.assert_array_equal(to_numpy(w2), to_numpy(w1))
+    assert rel(to_numpy(y2), to_numpy(y1)) < (1e-15 if sketch == "f64" else 1e-6)
+    # the QB stage on identical sketch values
+    other = qs.Sketcher(m, n, k, l, **kw)
+    other.set_sketches(y1, w1, n)
+    for kind in ("pseudo_qr", "pseudo_svd"):
+        q1, x1, _ = full.finalize(kind)
+        q2, x2, _ = other.finalize(kind)
+        hx1 = qt.hamilton(to_numpy(q1), to_numpy(x1))
+        hx2 = qt.hamilton(to_numpy(q2), to_numpy(x2))
+        assert rel(hx2, hx1) < 1e-12, kind
+    # W alone: Y stays
+    other.set_sketches(None, torch.zeros_like(w1), 0)
+    y3, w3 = other.sketches()
+    np.testing.assert_array_equal(to_numpy(y3), to_numpy(y1))
+    assert float(w3.abs().max()) == 0.0
+    for s in (full, res, other):
+        s.close()
