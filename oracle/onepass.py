@@ -32,6 +32,13 @@ def qb_stage(sk, kind, n_correction=3, n_power=3):
     return h, x, info
 
 
+def project(h, a):
+    """The second pass of the two-pass variant, randomized QSVD (Section 4.1:
+    the one-pass algorithm with Psi = I and orthonormal H): X = H^* A, which
+    is H^dagger A for orthonormal H."""
+    return qt.hamilton(qt.conj_t(h), qt.as_planes(a))
+
+
 def truncate(h, x, r):
     """Alg. 5: (U, Sigma, V) = QSVD(X); keep r; H <- H U_r.  The QSVD is taken
     through chi (Prop. 2.2); the paper's own QSVD routine is unpublished."""

@@ -141,6 +141,22 @@ def test_rqsvd_special_case():
     from oracle.solve import qsolve
     x = qsolve(hq, a)                           # (I H) \ (I A)
     np.testing.assert_allclose(x, h(qt.conj_t(hq), a), atol=1e-12)
+    np.testing.assert_allclose(onepass.project(hq, a), x, atol=1e-12)
+
+
+def test_two_pass_projection_is_optimal_in_the_range():
+    """H H^* A is the best approximation of A within range(H) (H orthonormal),
+    so the two-pass error is at most the one-pass error with the same H."""
+    a = small_lowrank(60, 45, 6, 1e-2, 12)
+    cfg = SketchConfig(60, 45, 8, 17, seed=13)
+    sk = sketch_matrix(a, cfg, block_cols=10)
+    hq, x1, _ = onepass.qb_stage(sk, "pseudo_svd")
+    x2 = onepass.project(hq, a)
+    e1, e2 = onepass.rel_error(a, hq, x1), onepass.rel_error(a, hq, x2)
+    assert e2 <= e1 * (1 + 1e-12) and e2 < e1
+    # the residual of the projection is orthogonal to range(H)
+    res = a - h(hq, x2)
+    assert np.abs(h(qt.conj_t(hq), res)).max() < 1e-12 * np.abs(a).max()
 
 
 def test_truncation_bound_thm42():
