@@ -101,6 +101,9 @@ typedef struct {
   int32_t n_correction;    /* pseudo-QR correction steps, 0..8 (paper: "often 3") */
   int32_t n_power;         /* power iterates per correction step for eps (paper: 2-3) */
   int64_t max_block_cols;  /* largest ncols of one update; 0 means n */
+  int32_t y_only;          /* 1: keep Y only (the two-pass variant): W is neither stored nor
+                              updated, qsketch_finalize runs with X == NULL, and
+                              qsketch_project forms X in a second pass over A.  Not for batches. */
 } qsk_config;
 
 typedef struct {
@@ -168,13 +171,28 @@ qsk_status qsketch_set_sketches(qsk_ctx *ctx, const double *const Y[4], int64_t 
    Q = F(Y) with F the chosen rangefinder (Alg. 1 or Alg. 3), then
    X = (Psi Q)^dagger W by least squares (Alg. 2), with Psi regenerated to the
    exact values that formed W.  Q: m x k FP64 planes (ldq >= m); X: k x n FP64
-   planes (ldx >= k).  Non-destructive: may be called again (either
+   planes (ldx >= k), or X == NULL to run the rangefinder only (required in
+   a y_only context, which has no W).  Non-destructive: may be called again (either
    rangefinder) and interleaved with further updates.  Synchronises the stream
    before returning (to read the report); report may be NULL. */
 qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf,
                             double *const Q[4], int64_t ldq,
                             double *const X[4], int64_t ldx,
                             qsk_report *report);
+
+/* Second pass of the two-pass variant (randomized QSVD: the one-pass
+   algorithm with Psi = I, Section 4.1, after eq. reconstructionOfTwoSketch):
+       X[:, col0 : col0 + ncols) = Q^* A[:, col0 : col0 + ncols),
+   which is Q^dagger A when Q has orthonormal columns (the pseudo-SVD
+   rangefinder).  Q: m x k FP64 planes (ldq >= m), e.g. from
+   qsketch_finalize; planes: the block of A as in qsketch_update (input_dtype,
+   ld >= m, 1 <= ncols <= max_block_cols, col0 + ncols <= n); X: k x n FP64
+   planes (ldx >= k), only the block's columns are written.  FP64 matrix-core
+   products, no split of the m-long contraction.  Stream-ordered; works in
+   any context (y_only or not) and leaves the sketches unchanged. */
+qsk_status qsketch_project(qsk_ctx *ctx, double *const Q[4], int64_t ldq, int64_t col0,
+                           int64_t ncols, const void *const planes[4], int64_t ld,
+                           double *const X[4], int64_t ldx);
 
 /* Copy the current sketches out (Y: m x k, W: l x n) as FP64 planes, for
    tests and checkpoints.  Y or W may be NULL to skip it. */

@@ -39,6 +39,7 @@ class QskConfig(ctypes.Structure):
         ("sketch_dtype", ctypes.c_int32), ("pure", ctypes.c_int32),
         ("split_terms", ctypes.c_int32), ("n_correction", ctypes.c_int32),
         ("n_power", ctypes.c_int32), ("max_block_cols", ctypes.c_int64),
+        ("y_only", ctypes.c_int32),
     ]
 
 
@@ -84,9 +85,11 @@ def _load():
     lib.qsketch_scale.restype = i32
     lib.qsketch_set_sketches.argtypes = [vp, vp, i64, vp, i64, i64]
     lib.qsketch_set_sketches.restype = i32
-    lib.qsketch_finalize.argtypes = [vp, i32, _P4, i64, _P4, i64, ctypes.POINTER(QskReport)]
+    lib.qsketch_finalize.argtypes = [vp, i32, _P4, i64, vp, i64, ctypes.POINTER(QskReport)]
+    lib.qsketch_project.argtypes = [vp, _P4, i64, i64, i64, _P4, i64, _P4, i64]
+    lib.qsketch_project.restype = i32
     lib.qsketch_finalize.restype = i32
-    lib.qsketch_sketches.argtypes = [vp, _P4, i64, _P4, i64]
+    lib.qsketch_sketches.argtypes = [vp, _P4, i64, vp, i64]
     lib.qsketch_sketches.restype = i32
     lib.qsketch_reset.argtypes = [vp]
     lib.qsketch_reset.restype = i32
@@ -172,7 +175,7 @@ class Sketcher:
 
     def __init__(self, m, n, k, l, seed=0, embedding="gaussian", input_dtype="f64",
                  sketch_dtype="f64", pure=False, split_terms=1, n_correction=3, n_power=3,
-                 max_block_cols=0, stream=None):
+                 max_block_cols=0, y_only=False, stream=None):
         lib = _load()
         cfg = QskConfig()
         lib.qsketch_config_default(ctypes.byref(cfg))
@@ -186,6 +189,8 @@ class Sketcher:
         cfg.n_correction = int(n_correction)
         cfg.n_power = int(n_power)
         cfg.max_block_cols = int(max_block_cols)
+        cfg.y_only = 1 if y_only else 0
+        self.y_only = bool(y_only)
         self.m, self.n, self.k, self.l = cfg.m, cfg.n, cfg.k, cfg.l
         self.pure = bool(pure)
         self.input_dtype = input_dtype
@@ -195,7 +200,8 @@ class Sketcher:
         self._config = dict(m=self.m, n=self.n, k=self.k, l=self.l, seed=int(seed), embedding=embedding,
                             input_dtype=input_dtype, sketch_dtype=sketch_dtype, pure=self.pure,
                             split_terms=int(split_terms), n_correction=int(n_correction),
-                            n_power=int(n_power), max_block_cols=int(max_block_cols))
+                            n_power=int(n_power), max_block_cols=int(max_block_cols),
+                            y_only=bool(y_only))
         self.columns_seen = 0
         self._ctx = ctypes.c_void_p()
         st = lib.qsketch_init(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
@@ -253,35 +259,64 @@ class Sketcher:
         """Host copy of the sketch state: {'config', 'Y', 'W', 'columns_seen'}
         (Y, W as FP64 CPU tensors)."""
         y, w = self.sketches()
-        return {"config": self.config(), "Y": y.cpu(), "W": w.cpu(), "columns_seen": self.columns_seen}
+        return {"config": self.config(), "Y": y.cpu(), "W": None if w is None else w.cpu(),
+                "columns_seen": self.columns_seen}
 
     @classmethod
     def restore(cls, state, stream=None):
         """A new context with the checkpoint's configuration and sketches."""
         sk = cls(**state["config"], stream=stream)
-        y = state["Y"].to(sk.device)
-        w = state["W"].to(sk.device)
-        sk.set_sketches(to_colmajor(y), to_colmajor(w), state["columns_seen"])
+        y = to_colmajor(state["Y"].to(sk.device))
+        w = None if state["W"] is None else to_colmajor(state["W"].to(sk.device))
+        sk.set_sketches(y, w, state["columns_seen"])
         return sk
 
-    def finalize(self, rangefinder="pseudo_qr", q=None, x=None):
-        """QB stage: returns (Q, X, report) with Q (4, m, k) and X (4, k, n) FP64."""
+    def finalize(self, rangefinder="pseudo_qr", q=None, x=None, solve=None):
+        """QB stage: returns (Q, X, report) with Q (4, m, k) and X (4, k, n)
+        FP64; solve=False (the default in a y_only context) runs the
+        rangefinder only and returns X = None."""
+        if solve is None:
+            solve = not self.y_only
         if q is None:
             q = qempty(4, self.m, self.k, torch.float64, self.device)
-        if x is None:
-            x = qempty(4, self.k, self.n, torch.float64, self.device)
         qp, ldq = _plane_ptrs(q, False)
-        xp, ldx = _plane_ptrs(x, False)
+        xarg, ldx = None, self.k
+        if solve:
+            if x is None:
+                x = qempty(4, self.k, self.n, torch.float64, self.device)
+            xp, ldx = _plane_ptrs(x, False)
+            xarg = ctypes.cast(xp, ctypes.c_void_p)
+        else:
+            x = None
         rep = QskReport()
-        self._check(self._lib.qsketch_finalize(self._ctx, RANGEFINDERS[rangefinder], qp, ldq, xp, ldx,
+        self._check(self._lib.qsketch_finalize(self._ctx, RANGEFINDERS[rangefinder], qp, ldq, xarg, ldx,
                                                ctypes.byref(rep)))
         return q, x, rep.as_dict()
 
+    def project(self, col0, block, q, x=None):
+        """Second pass of the two-pass variant: X[:, J] = Q^* block for the
+        columns J = col0 .. col0 + ncols - 1; X (4, k, n) FP64 is created
+        (zeros) when not given.  Returns X."""
+        if block.dtype != TORCH_DTYPE[self.input_dtype]:
+            raise TypeError(f"block dtype {block.dtype} != input dtype {self.input_dtype}")
+        if x is None:
+            x = qzeros(4, self.k, self.n, torch.float64, self.device)
+        bp, ld = _plane_ptrs(block, self.pure)
+        qp, ldq = _plane_ptrs(q, False)
+        xp, ldx = _plane_ptrs(x, False)
+        self._check(self._lib.qsketch_project(self._ctx, qp, ldq, int(col0), int(block.shape[2]), bp, ld,
+                                              xp, ldx))
+        return x
+
     def sketches(self):
+        """(Y, W) as FP64 (4, m, k) and (4, l, n); W is None in a y_only context."""
         y = qempty(4, self.m, self.k, torch.float64, self.device)
-        w = qempty(4, self.l, self.n, torch.float64, self.device)
         yp, ldy = _plane_ptrs(y, False)
-        wp, ldw = _plane_ptrs(w, False)
+        w, wp, ldw = None, None, self.l
+        if not self.y_only:
+            w = qempty(4, self.l, self.n, torch.float64, self.device)
+            wp, ldw = _plane_ptrs(w, False)
+            wp = ctypes.cast(wp, ctypes.c_void_p)
         self._check(self._lib.qsketch_sketches(self._ctx, yp, ldy, wp, ldw))
         return y, w
 

@@ -281,6 +281,7 @@ hipError_t launch_qgemm64_k(hipStream_t st, int ta, int tb, bool conj_a, const G
   if (conj_a) {
     if (ta == 0 && tb == 0) QSK_G64(double, double, true);
     else if (ta == 0 && tb == 1) QSK_G64(double, float, true);
+    else if (ta == 0 && tb == 2) QSK_G64(double, uint16_t, true);
     else if (ta == 1 && tb == 1) QSK_G64(float, float, true);
     else return hipErrorInvalidValue;
   } else {
@@ -435,6 +436,13 @@ hipError_t launch_crossprod_planar(hipStream_t st, const double *const z1[4], in
   for (int p = 0; p < 4; ++p) g.out[p] = out[p];
   g.ldo = ldo;
   return launch_qgemm64_k(st, 0, t2, true, g, GroupRef{}, 0);
+}
+
+hipError_t launch_project(hipStream_t st, const double *const q[4], int64_t ldq, int tb,
+                          const void *const b[4], int64_t ldb, int64_t m, int k, int64_t ncols,
+                          double *const x[4], int64_t ldx) {
+  if ((int64_t)(int)ncols != ncols) return hipErrorInvalidValue;
+  return launch_crossprod_planar(st, q, ldq, tb, b, ldb, m, k, (int)ncols, x, ldx);
 }
 
 // Split of K for one problem of a grouped launch: chunks of chunk_hint rows

@@ -36,6 +36,7 @@ struct SketchArgs {
   int64_t fp8_scale_elems;
   int psi_ready;         // the staging buffer already holds Psi (it does not change)
   double eta = 1.0;      // scale of the products: Y += eta H Omega_J, W[:, J] += eta Psi H
+  int skip_w = 0;        // Y only: no Psi staging, no W product
   // optional timing: events[2 * kernel] before, [2 * kernel + 1] after (may be null)
   hipEvent_t *events;
 };
@@ -116,6 +117,11 @@ hipError_t launch_scale(hipStream_t st, int tsrc, void *p, int64_t n, double the
 // FP64 planes src rounded to the destination type (float when tdst != 0).
 hipError_t launch_narrow(hipStream_t st, int tdst, const double *const src[4], int64_t lds,
                          void *dst, int64_t ldd, int64_t pss, int64_t rows, int64_t cols);
+// X[:, 0 : ncols) (planar, ldx) = Q^* B with Q (m x k FP64 planes) and B
+// the m x ncols block (element type tb: 0 double, 1 float, 2 bf16 bits).
+hipError_t launch_project(hipStream_t st, const double *const q[4], int64_t ldq, int tb,
+                          const void *const b[4], int64_t ldb, int64_t m, int k, int64_t ncols,
+                          double *const x[4], int64_t ldx);
 hipError_t launch_widen(hipStream_t st, int tsrc, const void *src, int64_t lds, int64_t pss,
                         int64_t rows, int64_t cols, double *const dst[4], int64_t ldd);
 // sum over planes/columns of ||A - Q X||^2 and ||A||^2 (into acc[0], acc[1]).

@@ -68,6 +68,8 @@ struct qsk_ctx {
   int64_t t_count[4] = {0, 0, 0, 0};
   int use_mfma = 1;
   bool psi_staged = false;             // stage.psi holds Psi as the sketch used it
+  void *zero_plane = nullptr;          // zeroed real plane for qsketch_project on pure input
+  size_t zero_plane_bytes = 0;
 };
 
 namespace {
@@ -133,7 +135,7 @@ void free_all(qsk_ctx *c) {
   c->side = nullptr;
   void *ptrs[] = {c->y, c->w, c->u[0], c->u[1], c->small, c->work, c->partials, c->pbuf,
                   c->p1buf, c->sbuf, c->err_acc, c->status, c->w_scratch, c->pinv_work,
-                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus, c->fp8_scales};
+                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus, c->fp8_scales, c->zero_plane};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->y = c->w = nullptr;
@@ -225,6 +227,7 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   if (c.sketch_dtype < QSK_F64 || c.sketch_dtype > QSK_FP8_E4M3) return QSK_E_ARG;
   if (c.n_correction < 0 || c.n_correction > 8 || c.n_power < 1 || c.n_power > 64) return QSK_E_ARG;
   if (c.max_block_cols < 0) return QSK_E_ARG;
+  if (c.y_only != 0 && c.y_only != 1) return QSK_E_ARG;
   if (c.sketch_dtype == QSK_BF16 && (c.split_terms < 1 || c.split_terms > 3)) return QSK_E_ARG;
   if (c.sketch_dtype == QSK_FP8_E4M3 && (c.split_terms < 1 || c.split_terms > 2)) return QSK_E_ARG;
   if (c.sketch_dtype != QSK_F64 && c.input_dtype == QSK_F64) return QSK_E_UNSUPPORTED;
@@ -250,7 +253,7 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
                          c.sketch_dtype == QSK_FP8_E4M3;
   ctx->y_copies = mfma_mode ? qsk::Y_COPIES : 1;
   ok = ok && alloc(&ctx->y, (size_t)ctx->y_copies * 4 * m * k * ctx->ts);
-  ok = ok && alloc(&ctx->w, 4 * (size_t)l * n * ctx->ts);
+  if (!c.y_only) ok = ok && alloc(&ctx->w, 4 * (size_t)l * n * ctx->ts);
   ok = ok && alloc((void **)&ctx->u[0], 4 * (size_t)m * k * 8);
   ok = ok && alloc((void **)&ctx->u[1], 4 * (size_t)m * k * 8);
   ok = ok && alloc((void **)&ctx->small, S_COUNT * kk * 8);
@@ -290,7 +293,7 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
     return QSK_E_NOMEM;
   }
   hipError_t e = hipMemsetAsync(ctx->y, 0, (size_t)ctx->y_copies * 4 * m * k * ctx->ts, ctx->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(ctx->w, 0, 4 * (size_t)l * n * ctx->ts, ctx->stream);
+  if (e == hipSuccess && ctx->w) e = hipMemsetAsync(ctx->w, 0, 4 * (size_t)l * n * ctx->ts, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     free_all(ctx);
@@ -313,7 +316,7 @@ qsk_status qsketch_reset(qsk_ctx *ctx) {
   if (ctx->poisoned) return QSK_E_STATE;
   const qsk_config &c = ctx->cfg;
   HIPCHK(ctx, hipMemsetAsync(ctx->y, 0, (size_t)ctx->y_copies * 4 * c.m * c.k * ctx->ts, ctx->stream));
-  HIPCHK(ctx, hipMemsetAsync(ctx->w, 0, 4 * (size_t)c.l * c.n * ctx->ts, ctx->stream));
+  if (ctx->w) HIPCHK(ctx, hipMemsetAsync(ctx->w, 0, 4 * (size_t)c.l * c.n * ctx->ts, ctx->stream));
   ctx->columns_seen = 0;
   return QSK_OK;
 }
@@ -336,6 +339,7 @@ static qsk_status sketch_block(qsk_ctx *ctx, int64_t col0, int64_t ncols, const 
   const qsk_config &c = ctx->cfg;
   qsk::SketchArgs s{};
   s.eta = eta;
+  s.skip_w = c.y_only;
   s.stream = ctx->stream;
   s.mode = ctx->mode;
   s.in_dtype = c.input_dtype;
@@ -372,7 +376,7 @@ static qsk_status sketch_block(qsk_ctx *ctx, int64_t col0, int64_t ncols, const 
   hipError_t e = hipErrorNotSupported;
   if (ctx->use_mfma && ctx->mode != qsk::MODE_F64) {
     e = qsk::launch_sketch_mfma(s, ctx->stage);
-    if (e == hipSuccess) ctx->psi_staged = true;
+    if (e == hipSuccess && !c.y_only) ctx->psi_staged = true;
   }
   if (e == hipErrorNotSupported && ctx->mode == qsk::MODE_FP8) {
     ctx->last_error = "fp8 sketch: block too large for the matrix-core path (32-bit offsets) or "
@@ -401,7 +405,7 @@ static qsk_status scale_sketches(qsk_ctx *ctx, double theta) {
   const qsk_config &c = ctx->cfg;
   const int t = ctx->mode == qsk::MODE_F64 ? 0 : 1;
   HIPCHK(ctx, qsk::launch_scale(ctx->stream, t, ctx->y, (int64_t)ctx->y_copies * 4 * c.m * (int64_t)c.k, theta));
-  HIPCHK(ctx, qsk::launch_scale(ctx->stream, t, ctx->w, 4 * (int64_t)c.l * c.n, theta));
+  if (ctx->w) HIPCHK(ctx, qsk::launch_scale(ctx->stream, t, ctx->w, 4 * (int64_t)c.l * c.n, theta));
   return QSK_OK;
 }
 
@@ -436,6 +440,7 @@ qsk_status qsketch_set_sketches(qsk_ctx *ctx, const double *const Y[4], int64_t 
       if (!Y[p]) return fail_arg(ctx, "NULL Y plane");
   }
   if (W) {
+    if (!ctx->w) return fail_arg(ctx, "the context keeps no W (y_only)");
     if (ldw < c.l) return fail_arg(ctx, "ldw < l");
     for (int p = 0; p < 4; ++p)
       if (!W[p]) return fail_arg(ctx, "NULL W plane");
@@ -465,6 +470,7 @@ qsk_status qsketch_sketches(qsk_ctx *ctx, double *const Y[4], int64_t ldy, doubl
     HIPCHK(ctx, qsk::launch_widen(ctx->stream, t, ctx->y, c.m, c.m * (int64_t)c.k, c.m, c.k, Y, ldy));
   }
   if (W) {
+    if (!ctx->w) return fail_arg(ctx, "the context keeps no W (y_only)");
     if (ldw < c.l) return fail_arg(ctx, "ldw < l");
     HIPCHK(ctx, qsk::launch_widen(ctx->stream, t, ctx->w, c.l, c.l * (int64_t)c.n, c.l, c.n, W, ldw));
   }
@@ -483,10 +489,11 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
   if (ctx->poisoned) return QSK_E_STATE;
   const qsk_config &c = ctx->cfg;
   if (rf != QSK_PSEUDO_QR && rf != QSK_PSEUDO_SVD) return fail_arg(ctx, "unknown rangefinder");
-  if (!Q || !X) return fail_arg(ctx, "Q/X NULL");
+  if (!Q) return fail_arg(ctx, "Q NULL");
+  if (X && !ctx->w) return fail_arg(ctx, "the context keeps no W (y_only): call with X = NULL");
   for (int p = 0; p < 4; ++p)
-    if (!Q[p] || !X[p]) return fail_arg(ctx, "NULL output plane");
-  if (ldq < c.m || ldx < c.k) return fail_arg(ctx, "leading dimension too small");
+    if (!Q[p] || (X && !X[p])) return fail_arg(ctx, "NULL output plane");
+  if (ldq < c.m || (X && ldx < c.k)) return fail_arg(ctx, "leading dimension too small");
   hipStream_t st = ctx->stream;
   const int k = c.k, l = c.l;
   const int64_t m = c.m, n = c.n;
@@ -612,7 +619,8 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
   HIPCHK(ctx, qsk::launch_apply(st, tz, zsrc, m, m, k, slot(ctx, S_F), k, Q, ldq));
 
   // ---- core solve X = (Psi Q)^dagger W (Alg. 2 through the normal form of
-  // a CholeskyQR2 factorisation of P = Psi Q)
+  // a CholeskyQR2 factorisation of P = Psi Q); skipped when X is NULL
+  if (X) {
   double *pp[4], *p1[4], *sp[4];
   for (int p = 0; p < 4; ++p) {
     pp[p] = ctx->pbuf + (size_t)p * l * k;
@@ -671,6 +679,7 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
   const void *wp[4];
   for (int p = 0; p < 4; ++p) wp[p] = (const char *)ctx->w + (size_t)p * l * n * ctx->ts;
   HIPCHK(ctx, qsk::launch_crossprod_planar(st, sp, l, ty, wp, l, l, k, (int)n, X, ldx));
+  }
 
   // join the side stream (kappa estimates) before reading its results
   HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_join, 0));
@@ -702,6 +711,43 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4]
   const qsk_status r = finalize_impl(ctx, rf, Q, ldq, X, ldx, report, true);
   if (r != QSK_RETRY_CAREFUL) return r;
   return finalize_impl(ctx, rf, Q, ldq, X, ldx, report, false);
+}
+
+qsk_status qsketch_project(qsk_ctx *ctx, double *const Q[4], int64_t ldq, int64_t col0, int64_t ncols,
+                           const void *const planes[4], int64_t ld, double *const X[4], int64_t ldx) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  const qsk_config &c = ctx->cfg;
+  qsk_status st = check_block(ctx, col0, ncols, planes, ld);
+  if (st != QSK_OK) return st;
+  if (!Q || !X) return fail_arg(ctx, "Q/X NULL");
+  for (int p = 0; p < 4; ++p)
+    if (!Q[p] || !X[p]) return fail_arg(ctx, "NULL Q/X plane");
+  if (ldq < c.m || ldx < c.k) return fail_arg(ctx, "leading dimension too small");
+  const size_t es = c.input_dtype == QSK_F64 ? 8 : c.input_dtype == QSK_F32 ? 4 : 2;
+  const void *b[4];
+  for (int p = 0; p < 4; ++p) b[p] = planes[p];
+  if (c.pure) {
+    // the real plane of a pure quaternion block is zero: a zeroed plane of
+    // the block's shape stands in for it
+    const size_t need = ((size_t)(ncols - 1) * ld + c.m) * es;
+    if (need > ctx->zero_plane_bytes) {
+      if (ctx->zero_plane) {
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        HIPCHK(ctx, hipFree(ctx->zero_plane));
+        ctx->zero_plane = nullptr;
+        ctx->zero_plane_bytes = 0;
+      }
+      HIPCHK(ctx, hipMalloc(&ctx->zero_plane, need));
+      ctx->zero_plane_bytes = need;
+      HIPCHK(ctx, hipMemsetAsync(ctx->zero_plane, 0, need, ctx->stream));
+    }
+    b[0] = ctx->zero_plane;
+  }
+  double *xo[4];
+  for (int p = 0; p < 4; ++p) xo[p] = X[p] + col0 * ldx;
+  HIPCHK(ctx, qsk::launch_project(ctx->stream, Q, ldq, c.input_dtype, b, ld, c.m, c.k, ncols, xo, ldx));
+  return QSK_OK;
 }
 
 qsk_status qsketch_rel_error(qsk_ctx *ctx, const void *const A[4], int64_t lda, double *const Q[4],

@@ -172,6 +172,7 @@ static hipError_t launch_generic_t(const SketchArgs &s) {
                      s.m, s.col0, s.ncols, s.k, (TS *)s.y, s.ldy, s.psy, s.rad, s.terms, s.k0, s.k1, s.eta);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (s.skip_w) return hipSuccess;
   dim3 gw((unsigned)((s.ncols + 63) / 64), (unsigned)((s.l + 7) / 8));
   hipLaunchKernelGGL((sketch_w_generic<MODE, TIN, TS>), gw, dim3(256), 0, s.stream, a, s.lda, s.pure,
                      s.m, s.col0, s.ncols, s.l, (TS *)s.w, s.ldw, s.psw, s.rad, s.terms, s.k0, s.k1, s.eta);

@@ -925,18 +925,18 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
   if (s.mode == MODE_BF16) {
     e = gen_stage<MODE_BF16, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
-    if (!s.psi_ready) e = gen_stage<MODE_BF16, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
+    if (!s.psi_ready && !s.skip_w) e = gen_stage<MODE_BF16, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
   } else if (s.mode == MODE_FP8) {
     // e4m3 test-matrix values, staged as (exact) bf16
     e = gen_stage<MODE_FP8, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
-    if (!s.psi_ready) e = gen_stage<MODE_FP8, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
+    if (!s.psi_ready && !s.skip_w) e = gen_stage<MODE_FP8, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
   } else {
     e = gen_stage<MODE_F32, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
-    if (!s.psi_ready) e = gen_stage<MODE_F32, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
+    if (!s.psi_ready && !s.skip_w) e = gen_stage<MODE_F32, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
   }
   // fp8: the tile scales of this block
@@ -980,7 +980,7 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     if (e != hipSuccess) return e;
   }
   // ---- W
-  {
+  if (!s.skip_w) {
     WArgs w{};
     w.fsc = s.fp8_scales; w.RT = RT; w.CT = CT;
     for (int p = 0; p < 4; ++p) w.a[p] = s.planes[p];

@@ -36,6 +36,7 @@ def test_config_default_and_strerror():
     dict(m=100, n=80, k=10, l=21, n_correction=9),
     dict(m=100, n=80, k=10, l=21, sketch_dtype=2, split_terms=4),
     dict(m=100, n=80, k=10, l=21, embedding=5),
+    dict(m=100, n=80, k=10, l=21, y_only=2),
 ])
 def test_invalid_configs_rejected_before_device_use(bad):
     assert qs.config_status(**bad) == qs.QSK_E_ARG
@@ -47,6 +48,8 @@ def test_unsupported_combinations():
 
 
 def test_struct_layouts_match_header():
-    # field order/size of the ctypes mirrors (int64 m,n; int32 k,l; uint64 seed; 7 int32; int64)
-    assert ctypes.sizeof(qs.QskConfig) == 8 + 8 + 4 + 4 + 8 + 7 * 4 + 4 + 8
+    # field order/size of the ctypes mirrors (int64 m,n; int32 k,l; uint64 seed; 7 int32;
+    # padding; int64 max_block_cols; int32 y_only; tail padding)
+    assert ctypes.sizeof(qs.QskConfig) == 8 + 8 + 4 + 4 + 8 + 7 * 4 + 4 + 8 + 4 + 4
+    assert qs.QskConfig.max_block_cols.offset == 64 and qs.QskConfig.y_only.offset == 72
     assert ctypes.sizeof(qs.QskReport) == 8 + 8 + 64 + 4 * 4 + 8 + 8
