@@ -282,6 +282,61 @@ def bench_batch(args):
     print(json.dumps(line))
 
 
+def bench_extras(args, a, m, n, k, l, block, make):
+    """The general linear update and the two-pass variant on the same
+    workload (BF16 operands, the bench's term count): medians over the timed
+    steps."""
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    # A <- 0.999 A + 1.001 H per block: one in-place scaling of Y and W plus
+    # the products with eta folded into their epilogues
+    sk = make("bf16", args.terms)
+    lin = []
+    for it in range(args.warmup + args.steps):
+        sk.reset()
+        ev[0].record(st)
+        for c0 in range(0, n, block):
+            sk.update(c0, a[:, :, c0:c0 + block], theta=0.999, eta=1.001)
+        ev[1].record(st)
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            lin.append(ev[0].elapsed_time(ev[1]))
+    sk.close()
+    # two-pass: Y-only sketch, rangefinder only, projection pass over A
+    sk = qs.Sketcher(m, n, k, l, seed=0, embedding="gaussian", input_dtype="f32", sketch_dtype="bf16",
+                     split_terms=args.terms, max_block_cols=block, y_only=True)
+    x = qs.qzeros(4, k, n, torch.float64, a.device)
+    ys, rfs, prs = [], [], []
+    for it in range(args.warmup + args.steps):
+        sk.reset()
+        ev[0].record(st)
+        for c0 in range(0, n, block):
+            sk.update(c0, a[:, :, c0:c0 + block])
+        ev[1].record(st)
+        q, _, rep = sk.finalize("pseudo_svd")
+        ev[2].record(st)
+        for c0 in range(0, n, block):
+            sk.project(c0, a[:, :, c0:c0 + block], q, x)
+        ev[3].record(st)
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            ys.append(ev[0].elapsed_time(ev[1]))
+            rfs.append(ev[1].elapsed_time(ev[2]))
+            prs.append(ev[2].elapsed_time(ev[3]))
+    err = sk.rel_error(a, q, x)
+    sk.close()
+    pr = float(np.median(prs))
+    out = {
+        "linear_update": {"theta": 0.999, "eta": 1.001, "update_ms": float(np.median(lin))},
+        "two_pass": {"y_update_ms": float(np.median(ys)), "rangefinder_ms": float(np.median(rfs)),
+                     "project_ms": pr, "total_ms": float(np.median(ys) + np.median(rfs) + pr),
+                     "project_fp64_tflops": 2.0 * 16 * m * n * k / (pr * 1e-3) / 1e12,
+                     "rel_error_pseudo_svd": err},
+    }
+    log(f"[bench] extras: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,6 +350,8 @@ def main():
     ap.add_argument("--terms", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the general-update and two-pass measurements")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-only", action="store_true",
                     help="one bf16 pass only (for rocprofv3 runs)")
@@ -387,6 +444,8 @@ def main():
         sk.close()
         del res
 
+    extras = None if args.no_extras else bench_extras(args, a, m, n, k, l, block, make)
+
     bf = out_paths["bf16"]
     # roofline of the dominant kernel (the W product): algorithmic flops per
     # launch = 2 * 16 * m * ncols * l, averaged over the timed launches
@@ -430,7 +489,7 @@ def main():
         "paths": out_paths, "equal_error": eq,
         "speedup_vs_fp32_wall": speedup,
         "speedup_vs_fp32_wall_fp8": out_paths["fp32"]["total_ms"] / out_paths["fp8"]["total_ms"],
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "extras": extras,
         "host": {"cpu": platform.processor() or platform.machine(), "cores": os.cpu_count()},
     }
     print(json.dumps(line))

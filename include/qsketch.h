@@ -194,6 +194,22 @@ qsk_status qsketch_project(qsk_ctx *ctx, double *const Q[4], int64_t ldq, int64_
                            int64_t ncols, const void *const planes[4], int64_t ld,
                            double *const X[4], int64_t ldx);
 
+/* Truncation stage (Alg. 5): the rank-r QSVD of the approximation Q X,
+       Q X ~= (Q U_r) diag(sigma) V_r^*,
+   with (U, Sigma, V) the QSVD of X (k x n).  Computed from the eigenpairs of
+   the k x k Gram X X^* = U Sigma^2 U^* (the quaternion Hermitian eigensolver
+   of the pseudo-SVD rangefinder), V_r = X^* U_r Sigma_r^{-1}; a singular
+   value carries a relative error of about 1e-16 (sigma_1 / sigma_i)^2, and a
+   zero singular value gets a zero column of V.  Q: m x k, X: k x n FP64
+   planes as from qsketch_finalize (ldq >= m, ldx >= k); 1 <= r <= k.
+   Outputs: HU = Q U_r (m x r planes, ldh >= m), sigma (r doubles, device
+   memory, descending), V = V_r (n x r planes, ldv >= n).  The first call
+   allocates an n x k FP64 buffer for X^* that the context keeps.
+   Stream-ordered. */
+qsk_status qsketch_truncate(qsk_ctx *ctx, double *const Q[4], int64_t ldq, double *const X[4],
+                            int64_t ldx, int32_t r, double *const HU[4], int64_t ldh,
+                            double *sigma, double *const V[4], int64_t ldv);
+
 /* Copy the current sketches out (Y: m x k, W: l x n) as FP64 planes, for
    tests and checkpoints.  Y or W may be NULL to skip it. */
 qsk_status qsketch_sketches(qsk_ctx *ctx, double *const Y[4], int64_t ldy,

@@ -86,6 +86,8 @@ def _load():
     lib.qsketch_set_sketches.argtypes = [vp, vp, i64, vp, i64, i64]
     lib.qsketch_set_sketches.restype = i32
     lib.qsketch_finalize.argtypes = [vp, i32, _P4, i64, vp, i64, ctypes.POINTER(QskReport)]
+    lib.qsketch_truncate.argtypes = [vp, _P4, i64, _P4, i64, i32, _P4, i64, vp, _P4, i64]
+    lib.qsketch_truncate.restype = i32
     lib.qsketch_project.argtypes = [vp, _P4, i64, i64, i64, _P4, i64, _P4, i64]
     lib.qsketch_project.restype = i32
     lib.qsketch_finalize.restype = i32
@@ -292,6 +294,20 @@ class Sketcher:
         self._check(self._lib.qsketch_finalize(self._ctx, RANGEFINDERS[rangefinder], qp, ldq, xarg, ldx,
                                                ctypes.byref(rep)))
         return q, x, rep.as_dict()
+
+    def truncate(self, q, x, r):
+        """Truncation stage: (Q U_r (4, m, r), sigma (r,), V_r (4, n, r)) with
+        Q X ~= (Q U_r) diag(sigma) V_r^*."""
+        hu = qempty(4, self.m, r, torch.float64, self.device)
+        v = qempty(4, self.n, r, torch.float64, self.device)
+        sig = torch.empty(r, dtype=torch.float64, device=self.device)
+        qp, ldq = _plane_ptrs(q, False)
+        xp, ldx = _plane_ptrs(x, False)
+        hp, ldh = _plane_ptrs(hu, False)
+        vp_, ldv = _plane_ptrs(v, False)
+        self._check(self._lib.qsketch_truncate(self._ctx, qp, ldq, xp, ldx, int(r), hp, ldh,
+                                               ctypes.c_void_p(sig.data_ptr()), vp_, ldv))
+        return hu, sig, v
 
     def project(self, col0, block, q, x=None):
         """Second pass of the two-pass variant: X[:, J] = Q^* block for the

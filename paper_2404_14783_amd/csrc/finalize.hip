@@ -2100,6 +2100,70 @@ hipError_t launch_psvd_select(hipStream_t st, int k, double *gl, uint32_t k0, ui
   return hipSuccess;
 }
 
+// Eigen-decomposition of a k x k quaternion Hermitian matrix g (AoS, destroyed):
+// the first four stages of the pseudo-SVD pipeline (tridiagonalisation and
+// bisection, inverse iteration, re-orthogonalisation, back-transformation).
+// Eigenvalues ascending in PsvdLayout(work, k).LAM, eigenvectors in .U (AoS,
+// column i for eigenvalue i).
+hipError_t launch_herm_eig(hipStream_t st, int k, double *g, double *work, SmallStatus *status) {
+  for (int stage = 0; stage < 4; ++stage) {
+    PsvdArgs a{};
+    a.k = k; a.gl = g; a.work = work; a.status = status;
+    a.gx = psvd_blocks(k, stage); a.gy = 1;
+    const hipError_t e = launch_psvd_stage(st, stage, a, GroupRef{}, 0);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Truncation (Alg. 5) from the eigenpairs of X X^* = U Sigma^2 U^*: column c
+// of cu is the eigenvector of the c-th largest eigenvalue, cv the same
+// column over sigma_c = sqrt(max(lambda, 0)) (zero when sigma_c is zero),
+// sigma[c] = sigma_c.  cu, cv: AoS k x r.
+__global__ __launch_bounds__(256) void trunc_select_kernel(const double *work, int k, int r, double *cu,
+                                                           double *cv, double *sigma) {
+  const PsvdLayout L(const_cast<double *>(work), k);
+  for (int e = threadIdx.x; e < k * r; e += blockDim.x) {
+    const int i = e % k, c = e / k, src = k - 1 - c;
+    const double s = sqrt(fmax(gp(L.LAM)[src], 0.0));
+    const qd u = gq(L.U, i, src, k);
+    sq_(cu, i, c, k, u);
+    sq_(cv, i, c, k, s > 0.0 ? qscale(u, 1.0 / s) : qzero());
+  }
+  for (int c = threadIdx.x; c < r; c += blockDim.x) sigma[c] = sqrt(fmax(gp(L.LAM)[k - 1 - c], 0.0));
+}
+
+hipError_t launch_trunc_select(hipStream_t st, const double *work, int k, int r, double *cu, double *cv,
+                               double *sigma) {
+  hipLaunchKernelGGL(trunc_select_kernel, dim3(1), dim3(256), 0, st, work, k, r, cu, cv, sigma);
+  return hipGetLastError();
+}
+
+// Z (rows x cols planar, ldz) = X^* for X (cols x rows planar, ldx).
+__global__ void conj_transpose_k(PlanesC<double> x, int64_t ldx, int64_t rows, int64_t cols, Planes<double> z,
+                                 int64_t ldz) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = e % rows, i = e / rows;
+    const int64_t src = i + t * ldx;
+    z.p[0][t + i * ldz] = x.p[0][src];
+    z.p[1][t + i * ldz] = -x.p[1][src];
+    z.p[2][t + i * ldz] = -x.p[2][src];
+    z.p[3][t + i * ldz] = -x.p[3][src];
+  }
+}
+
+hipError_t launch_conj_transpose(hipStream_t st, const double *const x[4], int64_t ldx, int64_t rows, int64_t cols,
+                                 double *const z[4], int64_t ldz) {
+  PlanesC<double> a;
+  Planes<double> b;
+  for (int p = 0; p < 4; ++p) { a.p[p] = x[p]; b.p[p] = z[p]; }
+  const int64_t blocks = std::min<int64_t>((rows * cols + 255) / 256, 16384);
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(conj_transpose_k, dim3((unsigned)blocks), dim3(256), 0, st, a, ldx, rows, cols, b, ldz);
+  return hipGetLastError();
+}
+
 // kappa of H from its Gram G_H = H^* H: the eigenvalues of G_H are the
 // squared singular values of H, so kappa(H) = sqrt(lambda_max / lambda_min)
 // (Section 3.1, after Remark 3.1).  which: 0 -> status->kappa (and the

@@ -122,6 +122,13 @@ hipError_t launch_narrow(hipStream_t st, int tdst, const double *const src[4], i
 hipError_t launch_project(hipStream_t st, const double *const q[4], int64_t ldq, int tb,
                           const void *const b[4], int64_t ldb, int64_t m, int k, int64_t ncols,
                           double *const x[4], int64_t ldx);
+// Rank-r truncation factors from those eigenpairs of X X^*: cu, cv (AoS
+// k x r) = leading eigenvectors and the same over sigma; sigma (r).
+hipError_t launch_trunc_select(hipStream_t st, const double *work, int k, int r, double *cu, double *cv,
+                               double *sigma);
+// Z (rows x cols, ldz) = X^* for X (cols x rows, ldx), FP64 planes.
+hipError_t launch_conj_transpose(hipStream_t st, const double *const x[4], int64_t ldx, int64_t rows, int64_t cols,
+                                 double *const z[4], int64_t ldz);
 hipError_t launch_widen(hipStream_t st, int tsrc, const void *src, int64_t lds, int64_t pss,
                         int64_t rows, int64_t cols, double *const dst[4], int64_t ldd);
 // sum over planes/columns of ||A - Q X||^2 and ||A||^2 (into acc[0], acc[1]).
@@ -244,6 +251,9 @@ hipError_t launch_power_m(hipStream_t st, int k, const double *gi, int step, int
 hipError_t launch_psvd_select(hipStream_t st, int k, double *gl, uint32_t k0, uint32_t k1,
                               double *c, double *work, SmallStatus *status);
 // kappa of H from G_H = H^* H: chol, Jacobi singular values.
+// Eigenpairs of a k x k quaternion Hermitian matrix (AoS, destroyed), in
+// the pseudo-SVD work layout (eigenvalues ascending).
+hipError_t launch_herm_eig(hipStream_t st, int k, double *g, double *work, SmallStatus *status);
 hipError_t launch_kappa(hipStream_t st, int k, const double *gh, double *work, int which,
                         SmallStatus *status);
 // S^* = (P^dagger)^* (l x k planar) for a rank-deficient P by a Jacobi SVD

@@ -70,6 +70,8 @@ struct qsk_ctx {
   bool psi_staged = false;             // stage.psi holds Psi as the sketch used it
   void *zero_plane = nullptr;          // zeroed real plane for qsketch_project on pure input
   size_t zero_plane_bytes = 0;
+  double *xt = nullptr;                // X^* (n x k planes) for qsketch_truncate
+  size_t xt_bytes = 0;
 };
 
 namespace {
@@ -135,7 +137,7 @@ void free_all(qsk_ctx *c) {
   c->side = nullptr;
   void *ptrs[] = {c->y, c->w, c->u[0], c->u[1], c->small, c->work, c->partials, c->pbuf,
                   c->p1buf, c->sbuf, c->err_acc, c->status, c->w_scratch, c->pinv_work,
-                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus, c->fp8_scales, c->zero_plane};
+                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus, c->fp8_scales, c->zero_plane, c->xt};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->y = c->w = nullptr;
@@ -747,6 +749,45 @@ qsk_status qsketch_project(qsk_ctx *ctx, double *const Q[4], int64_t ldq, int64_
   double *xo[4];
   for (int p = 0; p < 4; ++p) xo[p] = X[p] + col0 * ldx;
   HIPCHK(ctx, qsk::launch_project(ctx->stream, Q, ldq, c.input_dtype, b, ld, c.m, c.k, ncols, xo, ldx));
+  return QSK_OK;
+}
+
+qsk_status qsketch_truncate(qsk_ctx *ctx, double *const Q[4], int64_t ldq, double *const X[4], int64_t ldx,
+                            int32_t r, double *const HU[4], int64_t ldh, double *sigma,
+                            double *const V[4], int64_t ldv) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  const qsk_config &c = ctx->cfg;
+  const int k = c.k;
+  const int64_t m = c.m, n = c.n;
+  if (r < 1 || r > k) return fail_arg(ctx, "need 1 <= r <= k");
+  if (!Q || !X || !HU || !V || !sigma) return fail_arg(ctx, "NULL argument");
+  for (int p = 0; p < 4; ++p)
+    if (!Q[p] || !X[p] || !HU[p] || !V[p]) return fail_arg(ctx, "NULL plane");
+  if (ldq < m || ldx < k || ldh < m || ldv < n) return fail_arg(ctx, "leading dimension too small");
+  hipStream_t st = ctx->stream;
+  // Z = X^* (n x k); the Gram Z^* Z = X X^* = U Sigma^2 U^*
+  const size_t need = 4 * (size_t)n * k * 8;
+  if (need > ctx->xt_bytes) {
+    if (ctx->xt) {
+      HIPCHK(ctx, hipStreamSynchronize(st));
+      HIPCHK(ctx, hipFree(ctx->xt));
+      ctx->xt = nullptr;
+      ctx->xt_bytes = 0;
+    }
+    HIPCHK(ctx, hipMalloc((void **)&ctx->xt, need));
+    ctx->xt_bytes = need;
+  }
+  double *z[4];
+  for (int p = 0; p < 4; ++p) z[p] = ctx->xt + (size_t)p * n * k;
+  HIPCHK(ctx, qsk::launch_conj_transpose(st, X, ldx, n, k, z, n));
+  HIPCHK(ctx, qsk::launch_crossprod(st, 0, (const void *const *)z, n, 0, (const void *const *)z, n, n, k, k,
+                                    ctx->partials, ctx->partial_elems, slot(ctx, S_TMP)));
+  HIPCHK(ctx, qsk::launch_herm_eig(st, k, slot(ctx, S_TMP), ctx->work, ctx->status));
+  HIPCHK(ctx, qsk::launch_trunc_select(st, ctx->work, k, r, slot(ctx, S_C), slot(ctx, S_F), sigma));
+  // H U_r (m x r) and V_r = X^* U_r Sigma_r^{-1} (n x r)
+  HIPCHK(ctx, qsk::launch_apply(st, 0, (const void *const *)Q, ldq, m, k, slot(ctx, S_C), r, HU, ldh));
+  HIPCHK(ctx, qsk::launch_apply(st, 0, (const void *const *)z, n, n, k, slot(ctx, S_F), r, V, ldv));
   return QSK_OK;
 }
 
