@@ -438,11 +438,38 @@ hipError_t launch_crossprod_planar(hipStream_t st, const double *const z1[4], in
   return launch_qgemm64_k(st, 0, t2, true, g, GroupRef{}, 0);
 }
 
+int64_t project_chunks(int64_t m, int k, int64_t ncols) {
+  // about 8 waves per SIMD over the output tiles and the chunks of the
+  // m-long contraction, chunks of at least 256 rows
+  const int64_t tiles = ((k + 15) / 16) * ((ncols + 15) / 16);
+  int64_t want = (8192 + tiles - 1) / tiles;
+  want = std::min<int64_t>(want, std::max<int64_t>(1, m / 256));
+  return std::max<int64_t>(1, std::min<int64_t>(want, PROJECT_MAX_CHUNKS));
+}
+
 hipError_t launch_project(hipStream_t st, const double *const q[4], int64_t ldq, int tb,
                           const void *const b[4], int64_t ldb, int64_t m, int k, int64_t ncols,
-                          double *const x[4], int64_t ldx) {
+                          double *const x[4], int64_t ldx, double *partials, int64_t partial_elems) {
   if ((int64_t)(int)ncols != ncols) return hipErrorInvalidValue;
-  return launch_crossprod_planar(st, q, ldq, tb, b, ldb, m, k, (int)ncols, x, ldx);
+  const int64_t per_chunk = (int64_t)k * ncols * 4;
+  int64_t want = project_chunks(m, k, ncols);
+  if (!partials) want = 1;
+  want = std::min<int64_t>(want, partial_elems / per_chunk);
+  if (want < 2) return launch_crossprod_planar(st, q, ldq, tb, b, ldb, m, k, (int)ncols, x, ldx);
+  const void *qq[4] = {q[0], q[1], q[2], q[3]};
+  Gemm64Args g = g64_args(qq, ldq, 1, b, 1, ldb, k, ncols, m);
+  int64_t chunk = ((m + want - 1) / want + 15) / 16 * 16;
+  const int64_t nch = (m + chunk - 1) / chunk;
+  g.kchunk = chunk;
+  g.gy = (int)nch;
+  g.partial = partials;
+  hipError_t e = launch_qgemm64_k(st, 0, tb, true, g, GroupRef{}, 0);
+  if (e != hipSuccess) return e;
+  ReducePlanarArgs r{};
+  r.partial = partials; r.nchunks = (int)nch; r.r = k; r.c = (int)ncols;
+  set_planes(r.out, x); r.ldo = ldx;
+  r.gx = (int)((per_chunk / 4 + 255) / 256); r.gy = 1;
+  return launch_reduce_planar_k(st, r, GroupRef{}, r.gx);
 }
 
 // Split of K for one problem of a grouped launch: chunks of chunk_hint rows

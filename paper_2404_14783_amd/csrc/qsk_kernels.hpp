@@ -119,9 +119,14 @@ hipError_t launch_narrow(hipStream_t st, int tdst, const double *const src[4], i
                          void *dst, int64_t ldd, int64_t pss, int64_t rows, int64_t cols);
 // X[:, 0 : ncols) (planar, ldx) = Q^* B with Q (m x k FP64 planes) and B
 // the m x ncols block (element type tb: 0 double, 1 float, 2 bf16 bits).
+// The m-long contraction is split in up to PROJECT_MAX_CHUNKS chunks whose
+// partial sums (k x ncols AoS each) go to `partials` (partial_elems doubles)
+// and are then summed; project_chunks gives the split for a shape.
+constexpr int PROJECT_MAX_CHUNKS = 12;
+int64_t project_chunks(int64_t m, int k, int64_t ncols);
 hipError_t launch_project(hipStream_t st, const double *const q[4], int64_t ldq, int tb,
                           const void *const b[4], int64_t ldb, int64_t m, int k, int64_t ncols,
-                          double *const x[4], int64_t ldx);
+                          double *const x[4], int64_t ldx, double *partials, int64_t partial_elems);
 // Rank-r truncation factors from those eigenpairs of X X^*: cu, cv (AoS
 // k x r) = leading eigenvectors and the same over sigma; sigma (r).
 hipError_t launch_trunc_select(hipStream_t st, const double *work, int k, int r, double *cu, double *cv,

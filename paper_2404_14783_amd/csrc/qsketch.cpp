@@ -72,6 +72,8 @@ struct qsk_ctx {
   size_t zero_plane_bytes = 0;
   double *xt = nullptr;                // X^* (n x k planes) for qsketch_truncate
   size_t xt_bytes = 0;
+  double *proj_part = nullptr;         // split-contraction partial sums of qsketch_project
+  size_t proj_part_bytes = 0;
 };
 
 namespace {
@@ -137,7 +139,7 @@ void free_all(qsk_ctx *c) {
   c->side = nullptr;
   void *ptrs[] = {c->y, c->w, c->u[0], c->u[1], c->small, c->work, c->partials, c->pbuf,
                   c->p1buf, c->sbuf, c->err_acc, c->status, c->w_scratch, c->pinv_work,
-                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus, c->fp8_scales, c->zero_plane, c->xt};
+                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus, c->fp8_scales, c->zero_plane, c->xt, c->proj_part};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->y = c->w = nullptr;
@@ -746,9 +748,22 @@ qsk_status qsketch_project(qsk_ctx *ctx, double *const Q[4], int64_t ldq, int64_
     }
     b[0] = ctx->zero_plane;
   }
+  const int64_t nch = qsk::project_chunks(c.m, c.k, ncols);
+  const size_t pneed = nch > 1 ? (size_t)nch * c.k * ncols * 4 * 8 : 0;
+  if (pneed > ctx->proj_part_bytes) {
+    if (ctx->proj_part) {
+      HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+      HIPCHK(ctx, hipFree(ctx->proj_part));
+      ctx->proj_part = nullptr;
+      ctx->proj_part_bytes = 0;
+    }
+    HIPCHK(ctx, hipMalloc((void **)&ctx->proj_part, pneed));
+    ctx->proj_part_bytes = pneed;
+  }
   double *xo[4];
   for (int p = 0; p < 4; ++p) xo[p] = X[p] + col0 * ldx;
-  HIPCHK(ctx, qsk::launch_project(ctx->stream, Q, ldq, c.input_dtype, b, ld, c.m, c.k, ncols, xo, ldx));
+  HIPCHK(ctx, qsk::launch_project(ctx->stream, Q, ldq, c.input_dtype, b, ld, c.m, c.k, ncols, xo, ldx,
+                                  ctx->proj_part, (int64_t)(ctx->proj_part_bytes / 8)));
   return QSK_OK;
 }
 

@@ -21,13 +21,15 @@ from tests.gpu_helpers import input_values, rel, to_device, to_numpy
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("dtype,pure", [("f64", False), ("f32", False), ("bf16", False),
-                                        ("f32", True), ("bf16", True)])
-def test_project_parity(dtype, pure):
+@pytest.mark.parametrize("dtype,pure,m", [("f64", False, 333), ("f32", False, 333), ("bf16", False, 333),
+                                          ("f32", True, 333), ("bf16", True, 333),
+                                          ("f64", False, 3001), ("bf16", True, 3001)])
+def test_project_parity(dtype, pure, m):
     """X[:, J] = Q^* A_J for a seeded Q (not from the device) over uneven
-    blocks with ragged tails (m, k and every block width off the 16 grid)."""
-    m, n, k, l = 333, 257, 21, 43
-    print(f"project: {dtype} pure={pure}", flush=True)
+    blocks with ragged tails (m, k and every block width off the 16 grid);
+    m = 3001 splits the contraction over row chunks."""
+    n, k, l = 257, 21, 43
+    print(f"project: {dtype} pure={pure} m={m}", flush=True)
     rng = np.random.default_rng(41)
     q = rng.standard_normal((4, m, k))
     a = input_values(rng.standard_normal((4, m, n)), dtype)
