@@ -188,8 +188,12 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf,
    qsketch_finalize; planes: the block of A as in qsketch_update (input_dtype,
    ld >= m, 1 <= ncols <= max_block_cols, col0 + ncols <= n); X: k x n FP64
    planes (ldx >= k), only the block's columns are written.  FP64 matrix-core
-   products, no split of the m-long contraction.  Stream-ordered; works in
-   any context (y_only or not) and leaves the sketches unchanged. */
+   products with the m-long contraction split over row chunks.  A call on a
+   block wider than any before allocates the chunk partial-sum buffer (up to
+   12 k x ncols FP64 quaternion matrices), and the first call on pure input a
+   zeroed real plane of the block's shape; the context keeps both.
+   Stream-ordered; works in any context (y_only or not) and leaves the
+   sketches unchanged. */
 qsk_status qsketch_project(qsk_ctx *ctx, double *const Q[4], int64_t ldq, int64_t col0,
                            int64_t ncols, const void *const planes[4], int64_t ld,
                            double *const X[4], int64_t ldx);
