@@ -114,6 +114,16 @@ class Sketch:
         self.columns_seen += ncols
 
 
+def update_block(sk, row0, col0, block):
+    """A[row0 : row0 + nrows, col0 : col0 + ncols] += block: the column-block
+    update of the full-height block that is zero outside those rows (the
+    sketches are linear in A; the operand formats see that full block)."""
+    block = qt.as_planes(block)
+    full = np.zeros((4, sk.cfg.m, block.shape[2]))
+    full[:, row0:row0 + block.shape[1], :] = block
+    sk.update(col0, full)
+
+
 def sketch_matrix(a, cfg, block_cols=None):
     """Sketch a whole matrix by streaming it in column blocks."""
     a = qt.as_planes(a)

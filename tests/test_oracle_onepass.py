@@ -73,6 +73,21 @@ def test_general_linear_update_reaches_sketch_of_final_matrix():
     assert s.columns_seen == sum(st[3] for st in steps)
 
 
+def test_row_and_column_block_updates_reach_the_one_shot_sketch():
+    """Sub-block updates over a ragged 2-D partition of A (rows and columns)
+    give the sketches of the whole matrix (linearity, Section 5.3)."""
+    from oracle.sketch import update_block
+    a = small_lowrank(37, 29, 4, 1e-3, 14)
+    cfg = SketchConfig(37, 29, 5, 11, seed=8)
+    one = sketch_matrix(a, cfg)
+    s = Sketch(cfg)
+    for r0, r1 in ((0, 10), (10, 11), (11, 37)):
+        for c0, c1 in ((0, 13), (13, 29)):
+            update_block(s, r0, c0, a[:, r0:r1, c0:c1])
+    np.testing.assert_allclose(s.Y, one.Y, atol=1e-12)
+    np.testing.assert_allclose(s.W, one.W, atol=1e-12)
+
+
 def test_update_with_negated_eta_undoes_it():
     cfg = SketchConfig(30, 20, 4, 9, seed=6, embedding="rademacher")
     s = Sketch(cfg)
