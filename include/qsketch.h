@@ -152,6 +152,18 @@ qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols,
 qsk_status qsketch_update_linear(qsk_ctx *ctx, double theta, double eta, int64_t col0,
                                  int64_t ncols, const void *const planes[4], int64_t ld);
 
+/* Sub-block update A[row0 : row0 + nrows, col0 : col0 + ncols) += H (row
+   blocks included), with H the nrows x ncols block in planes (input_dtype,
+   ld >= nrows): the column-block update of the full-height block that is H
+   on those rows and zero elsewhere (the sketches are linear in A), so it
+   costs a whole m-row column block.  The operand formats see that
+   full-height block (FP8 tile scales count tile rows from row 0 of A).
+   Requires 0 <= row0, 1 <= nrows, row0 + nrows <= m, and the column limits
+   of qsketch_update.  The first call allocates a 4 x m x max_block_cols
+   staging block (input_dtype) that the context keeps.  Stream-ordered. */
+qsk_status qsketch_update_block(qsk_ctx *ctx, int64_t row0, int64_t nrows, int64_t col0,
+                                int64_t ncols, const void *const planes[4], int64_t ld);
+
 /* A <- theta A: Y <- theta Y, W <- theta W (theta finite; 0 stores zeros).
    Stream-ordered. */
 qsk_status qsketch_scale(qsk_ctx *ctx, double theta);

@@ -81,6 +81,8 @@ def _load():
     lib.qsketch_update.restype = i32
     lib.qsketch_update_linear.argtypes = [vp, ctypes.c_double, ctypes.c_double, i64, i64, _P4, i64]
     lib.qsketch_update_linear.restype = i32
+    lib.qsketch_update_block.argtypes = [vp, i64, i64, i64, i64, _P4, i64]
+    lib.qsketch_update_block.restype = i32
     lib.qsketch_scale.argtypes = [vp, ctypes.c_double]
     lib.qsketch_scale.restype = i32
     lib.qsketch_set_sketches.argtypes = [vp, vp, i64, vp, i64, i64]
@@ -228,6 +230,15 @@ class Sketcher:
         else:
             self._check(self._lib.qsketch_update_linear(self._ctx, float(theta), float(eta), int(col0),
                                                         int(block.shape[2]), ptrs, ld))
+        self.columns_seen += int(block.shape[2])
+
+    def update_block(self, row0, col0, block):
+        """A[row0 : row0 + nrows, col0 : col0 + ncols] += block."""
+        if block.dtype != TORCH_DTYPE[self.input_dtype]:
+            raise TypeError(f"block dtype {block.dtype} != input dtype {self.input_dtype}")
+        ptrs, ld = _plane_ptrs(block, self.pure)
+        self._check(self._lib.qsketch_update_block(self._ctx, int(row0), int(block.shape[1]), int(col0),
+                                                   int(block.shape[2]), ptrs, ld))
         self.columns_seen += int(block.shape[2])
 
     def scale(self, theta):

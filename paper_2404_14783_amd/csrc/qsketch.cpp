@@ -74,6 +74,8 @@ struct qsk_ctx {
   size_t xt_bytes = 0;
   double *proj_part = nullptr;         // split-contraction partial sums of qsketch_project
   size_t proj_part_bytes = 0;
+  void *pad = nullptr;                 // full-height block (4 planes, m x max_block_cols) for
+  size_t pad_bytes = 0;                // qsketch_update_block
 };
 
 namespace {
@@ -139,7 +141,7 @@ void free_all(qsk_ctx *c) {
   c->side = nullptr;
   void *ptrs[] = {c->y, c->w, c->u[0], c->u[1], c->small, c->work, c->partials, c->pbuf,
                   c->p1buf, c->sbuf, c->err_acc, c->status, c->w_scratch, c->pinv_work,
-                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus, c->fp8_scales, c->zero_plane, c->xt, c->proj_part};
+                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus, c->fp8_scales, c->zero_plane, c->xt, c->proj_part, c->pad};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->y = c->w = nullptr;
@@ -398,6 +400,39 @@ qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void 
   if (ctx->poisoned) return QSK_E_STATE;
   qsk_status st = check_block(ctx, col0, ncols, planes, ld);
   if (st == QSK_OK) st = sketch_block(ctx, col0, ncols, planes, ld, 1.0);
+  if (st == QSK_OK) ctx->columns_seen += ncols;
+  return st;
+}
+
+qsk_status qsketch_update_block(qsk_ctx *ctx, int64_t row0, int64_t nrows, int64_t col0, int64_t ncols,
+                                const void *const planes[4], int64_t ld) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  const qsk_config &c = ctx->cfg;
+  if (row0 < 0 || nrows < 1 || row0 + nrows > c.m) return fail_arg(ctx, "row block out of range");
+  if (!planes) return fail_arg(ctx, "planes is NULL");
+  if (col0 < 0 || ncols < 1 || ncols > c.max_block_cols || col0 + ncols > c.n)
+    return fail_arg(ctx, "column block out of range");
+  if (ld < nrows) return fail_arg(ctx, "ld < nrows");
+  for (int p = c.pure ? 1 : 0; p < 4; ++p)
+    if (!planes[p]) return fail_arg(ctx, "NULL plane");
+  const size_t es = c.input_dtype == QSK_F64 ? 8 : c.input_dtype == QSK_F32 ? 4 : 2;
+  const size_t plane = (size_t)c.m * c.max_block_cols * es;
+  if (!ctx->pad) {
+    HIPCHK(ctx, hipMalloc(&ctx->pad, 4 * plane));
+    ctx->pad_bytes = 4 * plane;
+  }
+  // the full-height block: zero outside rows row0 .. row0 + nrows - 1
+  const void *full[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int p = c.pure ? 1 : 0; p < 4; ++p) {
+    char *dst = (char *)ctx->pad + p * plane;
+    HIPCHK(ctx, hipMemsetAsync(dst, 0, (size_t)c.m * ncols * es, ctx->stream));
+    HIPCHK(ctx, hipMemcpy2DAsync(dst + (size_t)row0 * es, (size_t)c.m * es, planes[p], (size_t)ld * es,
+                                 (size_t)nrows * es, (size_t)ncols, hipMemcpyDeviceToDevice, ctx->stream));
+    full[p] = dst;
+  }
+  if (c.pure) full[0] = full[1];
+  qsk_status st = sketch_block(ctx, col0, ncols, full, c.m, 1.0);
   if (st == QSK_OK) ctx->columns_seen += ncols;
   return st;
 }

@@ -143,3 +143,36 @@ def test_checkpoint_restore_continues_stream(sketch, dtype, terms):
     assert float(w3.abs().max()) == 0.0
     for s in (full, res, other):
         s.close()
+
+
+@pytest.mark.parametrize("sketch,dtype,emb,terms", [("f64", "f64", "gaussian", 1), ("f32", "f32", "gaussian", 1),
+                                                    ("bf16", "f32", "rademacher", 2), ("fp8", "f32", "gaussian", 2)])
+def test_row_block_updates(sketch, dtype, emb, terms):
+    """A[I, J] += H over a ragged 2-D partition of A (row blocks of 1..400
+    rows): the device against the oracle's sub-block updates, and the FP64 /
+    FP32 / BF16 paths against the one-shot sketch of A (the sub-blocks sum to
+    A; the FP8 tile scales of a sub-block differ from those of A's blocks)."""
+    from oracle.sketch import sketch_matrix, update_block
+    m, n, k, l, block = 700, 257, 12, 25, 64
+    print(f"row blocks: {sketch} {dtype} {emb} terms={terms}", flush=True)
+    a = synth.lowrank_plus_noise(m, n, torch.tensor(0.8 ** np.arange(10)), 1e-3, 79).numpy()
+    a = input_values(a, dtype)
+    dev = to_device(a, dtype)
+    sk = qs.Sketcher(m, n, k, l, seed=9, embedding=emb, input_dtype=dtype, sketch_dtype=sketch,
+                     split_terms=terms, max_block_cols=block)
+    ref = Sketch(oracle_cfg(m, n, k, l, 9, emb, sketch, terms))
+    rows = [(0, 1), (1, 300), (300, 700)]
+    for c0 in range(0, n, block):
+        c1 = min(n, c0 + block)
+        for r0, r1 in rows:
+            sk.update_block(r0, c0, dev[:, r0:r1, c0:c1])
+            update_block(ref, r0, c0, a[:, r0:r1, c0:c1])
+    y, w = (to_numpy(t) for t in sk.sketches())
+    tol = 1e-12 if sketch == "f64" else 1e-5
+    ey, ew = rel(y, ref.Y), rel(w, ref.W)
+    print(f"  rel. diff Y {ey:.2e}, W {ew:.2e}", flush=True)
+    assert ey < tol and ew < tol
+    if sketch != "fp8":
+        one = sketch_matrix(a, oracle_cfg(m, n, k, l, 9, emb, sketch, terms), block_cols=block)
+        assert rel(y, one.Y) < tol and rel(w, one.W) < tol
+    sk.close()
