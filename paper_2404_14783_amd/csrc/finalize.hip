@@ -1648,8 +1648,10 @@ __device__ __forceinline__ void tri_step(int j, int k, double *g, qd *P, int o0,
   __syncthreads();
   // (C) every wave forms s_k = beta/2 Re(v^* p) itself (same order, same
   // value), then the rank-2 update of the lower triangle with w = p - s_k v:
-  // G'[a, c] -= v_a conj(w_c) + w_a conj(v_c); thread (cs, a) takes row a,
-  // columns cs, cs + nc, ... <= a
+  // G'[a, c] -= v_a conj(w_c) + w_a conj(v_c).  The n (n + 1) / 2 entries,
+  // numbered column by column (column c holds rows c .. n - 1, starting at
+  // c n - c (c - 1) / 2), are dealt to the threads in turn, so that no thread
+  // takes more than one more entry than any other.
   {
     double kl = 0.0;
 #pragma unroll
@@ -1661,20 +1663,21 @@ __device__ __forceinline__ void tri_step(int j, int k, double *g, qd *P, int o0,
       }
     }
     const double sk = 0.5 * beta * wave_sum(kl);
-    const int nc = (int)blockDim.x / n;
-    const int cs = tid / n, aa = tid % n;
-    if (cs < nc) {
-      const qd va = v[aa];
+    const int tot = n * (n + 1) / 2;
+    const double b2 = 2.0 * n + 1.0;
+    for (int e = tid; e < tot; e += (int)blockDim.x) {
+      int cc = (int)((b2 - sqrt(b2 * b2 - 8.0 * e)) * 0.5);
+      cc = min(max(cc, 0), n - 1);
+      while (cc > 0 && cc * n - ((cc * (cc - 1)) >> 1) > e) --cc;
+      while (cc + 1 < n && (cc + 1) * n - (((cc + 1) * cc) >> 1) <= e) ++cc;
+      const int aa = cc + (e - (cc * n - ((cc * (cc - 1)) >> 1)));
+      const qd va = v[aa], vc = v[cc];
       const qd wa = qsub(pv[aa], qscale(va, sk));
-#pragma unroll 4
-      for (int cc = cs; cc <= aa; cc += nc) {
-        const qd vc = v[cc];
-        const qd wc = qsub(pv[cc], qscale(vc, sk));
-        qd gv = tri_get<L>(P, g, o + aa, o + cc, o0, n0, k);
-        gv = qsub(gv, qmul(va, qconj(wc)));
-        gv = qsub(gv, qmul(wa, qconj(vc)));
-        tri_set<L>(P, g, o + aa, o + cc, o0, n0, k, gv);
-      }
+      const qd wc = qsub(pv[cc], qscale(vc, sk));
+      qd gv = tri_get<L>(P, g, o + aa, o + cc, o0, n0, k);
+      gv = qsub(gv, qmul(va, qconj(wc)));
+      gv = qsub(gv, qmul(wa, qconj(vc)));
+      tri_set<L>(P, g, o + aa, o + cc, o0, n0, k, gv);
     }
   }
   __syncthreads();
