@@ -20,6 +20,8 @@ def rangefinder(y, kind, seed=0, n_correction=3, n_power=3):
         return pseudo_qr(y, n_correction=n_correction, n_power=n_power, seed=seed)
     if kind == "pseudo_svd":
         return pseudo_svd(y, seed=seed)
+    if kind == "pseudo_svd_gs":
+        return pseudo_svd(y, seed=seed, branch="gs")
     raise ValueError(kind)
 
 

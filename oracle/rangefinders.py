@@ -112,8 +112,24 @@ def classify_pairs(s, k):
     return np.array(good, dtype=bool)
 
 
-def pseudo_svd(y, seed=0):
-    """Alg. 3.  Returns (H, info) with info = {t_bad, sigma, kappa}."""
+# Gram-Schmidt branch of Alg. 3: a candidate column of U_b counts as
+# linearly independent of the columns taken so far (and their J-partners)
+# when its residual after two projections keeps more than GS_TOL of its norm.
+GS_TOL = 1e-8
+
+
+def _j_conj(x):
+    """J conj(x) for a 2m-vector x (the J-partner of a compact column)."""
+    m = x.shape[0] // 2
+    return np.concatenate([-np.conj(x[m:]), np.conj(x[:m])])
+
+
+def pseudo_svd(y, seed=0, branch="svd"):
+    """Alg. 3.  Returns (H, info) with info = {t_bad, sigma, kappa}.
+    branch: 'svd' repairs the bad part through H_b diag(f) and a second SVD;
+    'gs' takes the Gram-Schmidt branch: the columns of U_b in turn, each
+    orthogonalised against the columns already taken and their J-partners,
+    kept when linearly independent, until t are taken."""
     y = qt.as_planes(y)
     k = y.shape[2]
     u, s, _ = np.linalg.svd(qt.chi(y), full_matrices=False)     # step 1
@@ -124,10 +140,29 @@ def pseudo_svd(y, seed=0):
     t = len(bi)
     if t:
         ub = u[:, np.concatenate([2 * bi, 2 * bi + 1])]            # U_b, 2m x 2t
-        hb = qt.from_compact(ub)                                   # (H_b)_c = U_b
-        hb = hb * embeddings.diag_f(2 * t, seed)[None, None, :]    # H_b diag(f)
-        uh, _, _ = np.linalg.svd(qt.chi(hb), full_matrices=False)  # SVD of chi_{H_b}
-        cols.append(qt.from_compact(uh[:, 0:2 * t:2]))             # H_b~ from U_h1
+        if branch == "svd":
+            hb = qt.from_compact(ub)                               # (H_b)_c = U_b
+            hb = hb * embeddings.diag_f(2 * t, seed)[None, None, :]  # H_b diag(f)
+            uh, _, _ = np.linalg.svd(qt.chi(hb), full_matrices=False)  # SVD of chi_{H_b}
+            cols.append(qt.from_compact(uh[:, 0:2 * t:2]))         # H_b~ from U_h1
+        elif branch == "gs":
+            basis = np.zeros((ub.shape[0], 0), dtype=np.complex128)
+            taken = []
+            for c in range(ub.shape[1]):                           # U_b's columns in turn
+                x = ub[:, c].copy()
+                nx0 = np.linalg.norm(x)
+                for _ in range(2):
+                    x = x - basis @ (basis.conj().T @ x)
+                nx = np.linalg.norm(x)
+                if nx > GS_TOL * nx0:
+                    x = x / nx
+                    taken.append(x)
+                    basis = np.column_stack([basis, x, _j_conj(x)])
+                if len(taken) == t:
+                    break
+            cols.append(qt.from_compact(np.stack(taken, axis=1)))
+        else:
+            raise ValueError(branch)
     h = np.concatenate(cols, axis=2)                               # H = [H_g, H_b~]
     info = {"t_bad": int(t), "sigma": s[0::2].copy(), "kappa": condition_number(h)}
     return h, info

@@ -133,6 +133,33 @@ def test_pseudo_svd_identity_counterexample_and_repeated_values():
     assert qt.fro(projector(hs) - projector(y)) < 1e-10
 
 
+@pytest.mark.parametrize("case", ["identity", "repeated", "tiny"])
+def test_pseudo_svd_gram_schmidt_branch(case):
+    """Alg. 3's Gram-Schmidt branch for the bad part: orthonormal H with the
+    range of Y (Thm 3.1 needs the repair for Y = I_2, repeated values and
+    values below the pair rule's threshold), the same t as the SVD branch,
+    and the same good columns."""
+    if case == "identity":
+        y = qt.eye(2)
+    else:
+        u = orthonormal_q(30, 6, 4)
+        v = orthonormal_q(6, 6, 5)
+        s = (np.array([1.0, 0.5, 0.5, 0.25, 0.1, 0.05]) if case == "repeated"
+             else np.array([1.0, 0.5, 0.25, 0.1, 1e-15, 1e-16]))
+        y = h(u * s[None, None, :], qt.conj_t(v))
+    hs, info = pseudo_svd(y, branch="gs")
+    hv, info_v = pseudo_svd(y, branch="svd")
+    assert info["t_bad"] == info_v["t_bad"] >= 1
+    k = y.shape[2]
+    np.testing.assert_allclose(h(qt.conj_t(hs), hs), qt.eye(k), atol=1e-12)
+    if case != "tiny":
+        # the bad part spans a determined subspace: both branches find it
+        assert qt.fro(projector(hs) - projector(y)) < 1e-10
+        assert qt.fro(projector(hs) - projector(hv)) < 1e-10
+    ng = k - info["t_bad"]
+    np.testing.assert_array_equal(hs[:, :, :ng], hv[:, :, :ng])
+
+
 def test_pair_classification_rule():
     s = np.array([3.0, 3.0, 2.0, 2.0, 2.0, 2.0, 1e-15, 1e-15])
     np.testing.assert_array_equal(classify_pairs(s, 4), [True, False, False, False])
