@@ -78,8 +78,13 @@ typedef enum { QSK_F64 = 0, QSK_F32 = 1, QSK_BF16 = 2, QSK_FP8_E4M3 = 3 } qsk_dt
 typedef enum { QSK_GAUSSIAN = 0, QSK_RADEMACHER = 1 } qsk_embedding;
 
 /* Rangefinders (Section 3): pseudo-QR with correction steps (Alg. 1,
-   non-orthonormal, well conditioned) and pseudo-SVD (Alg. 3, orthonormal). */
-typedef enum { QSK_PSEUDO_QR = 0, QSK_PSEUDO_SVD = 1 } qsk_rangefinder;
+   non-orthonormal, well conditioned) and pseudo-SVD (Alg. 3, orthonormal),
+   whose bad part is repaired through H_b diag(f) and a second SVD
+   (QSK_PSEUDO_SVD) or through Alg. 3's Gram-Schmidt branch
+   (QSK_PSEUDO_SVD_GS: the bad columns taken in turn, each orthogonalised
+   against those already taken and their J-partners and kept when more than
+   1e-8 of its norm remains).  Batches take the first two only. */
+typedef enum { QSK_PSEUDO_QR = 0, QSK_PSEUDO_SVD = 1, QSK_PSEUDO_SVD_GS = 2 } qsk_rangefinder;
 
 /* Report flags (numeric events are flags, not errors). */
 enum {

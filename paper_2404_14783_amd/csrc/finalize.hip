@@ -1461,7 +1461,55 @@ __global__ __launch_bounds__(1024) void psvd_finish_kernel(PsvdArgs args, GroupR
     }
   }
   __syncthreads();
-  if (t > 0) {
+  if (t > 0 && A.gs) {
+    // Gram-Schmidt branch: the candidates in U_b's column order (the first
+    // members u of the bad pairs, then the second members -u j), each
+    // orthogonalised twice against the columns taken so far (a quaternion
+    // projection q (q^* x) removes a column and its J-partner at once), kept
+    // when more than 1e-8 of its norm remains, until t are taken
+    __shared__ int badj[256];
+    __shared__ qd xs[256], coef[256];
+    __shared__ double s_red[16];
+    for (int j = threadIdx.x; j < k; j += blockDim.x)
+      if (order[j] < 0) badj[-order[j] - 1] = j;
+    __syncthreads();
+    int taken = 0;
+    for (int cand = 0; cand < 2 * t && taken < t; ++cand) {
+      const int j = badj[cand % t];
+      for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        const qd uv = gq(U, i, k - 1 - j, k);
+        xs[i] = cand < t ? uv : qscale(qmul(uv, {0.0, 0.0, 1.0, 0.0}), -1.0);
+      }
+      __syncthreads();
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int s2 = threadIdx.x; s2 < taken; s2 += blockDim.x) {
+          qd a = qzero();
+          for (int i = 0; i < k; ++i) qfma_cj(a, gq(c, i, n_good + s2, k), xs[i]);
+          coef[s2] = a;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < k; i += blockDim.x) {
+          qd x = xs[i];
+          for (int s2 = 0; s2 < taken; ++s2) x = qsub(x, qmul(gq(c, i, n_good + s2, k), coef[s2]));
+          xs[i] = x;
+        }
+        __syncthreads();
+      }
+      double part = 0.0;
+      for (int i = threadIdx.x; i < k; i += blockDim.x) part += qnorm2(xs[i]);
+      part = wave_sum(part);
+      if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = part;
+      __syncthreads();
+      double nrm2 = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) nrm2 += s_red[w];
+      const double nrm = sqrt(nrm2);                      // the candidate had norm 1
+      if (nrm > 1e-8) {
+        for (int i = threadIdx.x; i < k; i += blockDim.x) sq_(c, i, n_good + taken, k, qscale(xs[i], 1.0 / nrm));
+        ++taken;
+      }
+      __syncthreads();
+    }
+  } else if (t > 0) {
     sm_jacobi(B, k, 2 * t, k, 60, 1e-15);
     __syncthreads();
     sm_sorted_columns(B, k, 2 * t, k, sig, order, UB, k);
@@ -2119,10 +2167,10 @@ hipError_t launch_psvd_stage(hipStream_t st, int stage, const PsvdArgs &a, Group
 }
 
 hipError_t launch_psvd_select(hipStream_t st, int k, double *gl, uint32_t k0, uint32_t k1,
-                              double *c, double *work, SmallStatus *status) {
+                              double *c, double *work, SmallStatus *status, int gs) {
   for (int stage = 0; stage < 5; ++stage) {
     PsvdArgs a{};
-    a.k = k; a.gl = gl; a.k0 = k0; a.k1 = k1; a.c = c; a.work = work; a.status = status;
+    a.k = k; a.gl = gl; a.k0 = k0; a.k1 = k1; a.c = c; a.work = work; a.status = status; a.gs = gs;
     a.gx = psvd_blocks(k, stage); a.gy = 1;
     const hipError_t e = launch_psvd_stage(st, stage, a, GroupRef{}, 0);
     if (e != hipSuccess) return e;

@@ -231,7 +231,10 @@ struct PowerArgs {
   int k; const double *gi; int step, n_power; uint32_t k0, k1; double *m_out; SmallStatus *status;
   int gx, gy;
 };
-struct PsvdArgs { int k; double *gl; uint32_t k0, k1; double *c, *work; SmallStatus *status; int gx, gy; };
+struct PsvdArgs {
+  int k; double *gl; uint32_t k0, k1; double *c, *work; SmallStatus *status; int gx, gy;
+  int gs;                   // bad part through Alg. 3's Gram-Schmidt branch (else the second SVD)
+};
 struct PinvArgs {
   int l, k; const double *p[4]; int64_t ldp; double tol; double *work; double *out[4]; int64_t ldo;
   int gx, gy;
@@ -254,7 +257,7 @@ hipError_t launch_power_m(hipStream_t st, int k, const double *gi, int step, int
 // eigensolver, pair rule, bad-part repair; writes the k x k combination C
 // (H = Q_Y C).  work: >= 17 k^2 + 8 k quaternion-sized doubles.
 hipError_t launch_psvd_select(hipStream_t st, int k, double *gl, uint32_t k0, uint32_t k1,
-                              double *c, double *work, SmallStatus *status);
+                              double *c, double *work, SmallStatus *status, int gs = 0);
 // kappa of H from G_H = H^* H: chol, Jacobi singular values.
 // Eigenpairs of a k x k quaternion Hermitian matrix (AoS, destroyed), in
 // the pseudo-SVD work layout (eigenvalues ascending).

@@ -527,7 +527,10 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
   if (!ctx) return QSK_E_ARG;
   if (ctx->poisoned) return QSK_E_STATE;
   const qsk_config &c = ctx->cfg;
-  if (rf != QSK_PSEUDO_QR && rf != QSK_PSEUDO_SVD) return fail_arg(ctx, "unknown rangefinder");
+  if (rf != QSK_PSEUDO_QR && rf != QSK_PSEUDO_SVD && rf != QSK_PSEUDO_SVD_GS)
+    return fail_arg(ctx, "unknown rangefinder");
+  const int gs = rf == QSK_PSEUDO_SVD_GS;
+  if (gs) rf = QSK_PSEUDO_SVD;
   if (!Q) return fail_arg(ctx, "Q NULL");
   if (X && !ctx->w) return fail_arg(ctx, "the context keeps no W (y_only): call with X = NULL");
   for (int p = 0; p < 4; ++p)
@@ -645,7 +648,7 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
     // G_L = R_Y R_Y^*
     HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_RPROD), 0, slot(ctx, S_RPROD), 1, slot(ctx, S_TMP)));
     HIPCHK(ctx, qsk::launch_psvd_select(st, k, slot(ctx, S_TMP), ctx->k0, ctx->k1, slot(ctx, S_C),
-                                        ctx->work, ctx->status));
+                                        ctx->work, ctx->status, gs));
   }
   HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_T), 0, slot(ctx, S_C), 0, slot(ctx, S_F)));
   // kappa(Q) from G_Q = F^* G_Z F

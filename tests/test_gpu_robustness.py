@@ -18,7 +18,10 @@ what the paper and the mathematics fix, for the device and the oracle alike:
     worse than 10x the oracle (or 1e-8);
   * outside that regime pseudo-QR's output is only required to be finite;
   * the number of repaired pseudo-SVD pairs matches the oracle's within one
-    (a singular value on the pair rule's threshold may fall either way).
+    (a singular value on the pair rule's threshold may fall either way);
+  * the same holds with the bad part repaired by Alg. 3's Gram-Schmidt
+    branch (pseudo_svd_gs), and where the bad part spans a determined
+    subspace (a repeated singular value) both branches return its range.
 """
 import numpy as np
 import pytest
@@ -58,15 +61,15 @@ def test_rangefinders_over_kappa(factors, kappa):
     sk = qs.Sketcher(M, K, K, K)
     sk.set_sketches(to_device(y, "f64"), None, K)
     print(f"kappa(Y) = {kappa:.0e}", flush=True)
-    for kind in ("pseudo_svd", "pseudo_qr"):
+    for kind in ("pseudo_svd", "pseudo_svd_gs", "pseudo_qr"):
         q, x, rep = sk.finalize(kind, solve=False)
         assert x is None
         h = to_numpy(q)
         assert np.isfinite(h).all()
-        if kind == "pseudo_svd":
-            h_ref, info = pseudo_svd(y)
+        if kind.startswith("pseudo_svd"):
+            h_ref, info = pseudo_svd(y, branch="gs" if kind.endswith("gs") else "svd")
             e_dev, e_ref = capture_error(h, u_lead), capture_error(h_ref, u_lead)
-            print(f"  pseudo-SVD: orth {rep['orth_defect']:.1e}, t_bad {rep['t_bad']} "
+            print(f"  {kind}: orth {rep['orth_defect']:.1e}, t_bad {rep['t_bad']} "
                   f"(oracle {info['t_bad']}), capture {e_dev:.1e} (oracle {e_ref:.1e})", flush=True)
             assert rep["orth_defect"] < 1e-10
             assert abs(rep["t_bad"] - info["t_bad"]) <= 1
@@ -81,4 +84,34 @@ def test_rangefinders_over_kappa(factors, kappa):
                 print(f"    capture {e_dev:.1e} (oracle {e_ref:.1e})", flush=True)
                 assert rep["kappa"] < 10.0 and kap_ref < 10.0
                 assert e_ref < 1e-4 and e_dev <= max(10.0 * e_ref, 1e-8)
+    sk.close()
+
+
+def projector(h):
+    return qt.hamilton(h, qt.pinv(h))
+
+
+@pytest.mark.parametrize("kind", ["pseudo_svd", "pseudo_svd_gs"])
+def test_repeated_singular_value_repair(factors, kind):
+    """A repeated singular value makes its pairs bad (the pair rule needs a
+    gap); the repaired H must still span range(Y) exactly, like the oracle's
+    branch of the same name."""
+    u, v = factors
+    sig = 0.98 ** np.arange(K)                # kappa(Y) ~ 60: range determined to rounding
+    sig[10:14] = sig[10]                      # a fourfold value
+    y = qt.hamilton(u * sig[None, None, :], qt.conj_t(v))
+    sk = qs.Sketcher(M, K, K, K)
+    sk.set_sketches(to_device(y, "f64"), None, K)
+    q, _, rep = sk.finalize(kind, solve=False)
+    h = to_numpy(q)
+    h_ref, info = pseudo_svd(y, branch="gs" if kind.endswith("gs") else "svd")
+    print(f"{kind}: t_bad {rep['t_bad']} (oracle {info['t_bad']}), orth {rep['orth_defect']:.1e}", flush=True)
+    assert rep["t_bad"] == info["t_bad"] >= 4
+    assert rep["orth_defect"] < 1e-10
+    # full rank k = 200 in a 1000-dim space: compare ranges through the
+    # projectors onto range(Y) = range(U)
+    pu = qt.hamilton(u, qt.conj_t(u))
+    e_dev, e_ref = qt.fro(projector(h) - pu), qt.fro(projector(h_ref) - pu)
+    print(f"  range: ||P_H - P_Y||_F {e_dev:.1e} (oracle {e_ref:.1e})", flush=True)
+    assert e_dev < 1e-10 and e_ref < 1e-10
     sk.close()
