@@ -895,15 +895,20 @@ __device__ void sm_gemm(int k, const double *a, int opa, const double *b, int op
 
 // Upper Cholesky G' = R^* R (right-looking, blocked by CB pivot rows held in
 // LDS); returns in shared `fail` whether a pivot fell below tol * max
-// diagonal.  k <= 256.
+// diagonal.  k <= 256.  The trailing matrix is updated in r (global memory)
+// until its upper triangle fits in the LDS pool beside the panel buffers;
+// from then on it lives there, packed by columns (column c of the block
+// holds rows 0 .. c), and only the finished rows are written to r.
+constexpr int CHOL_POOL = 4992;       // quaternions of LDS (156 KB)
+__device__ __forceinline__ int chol_pk(int a, int c) { return ((c * (c + 1)) >> 1) + a; }
 __device__ void sm_chol(const double *g, double *r, int k, int complex_only, double shift,
                         double tol, int *fail, double *minp, double *trace) {
   // Panels of CB pivot rows live in LDS twice: `panel` holds the rows as
   // updated so far (read by the elimination), `done` the finished, scaled
   // rows (read by the trailing update), so each pivot costs one barrier.
+  // Both are CB x w (row stride w = k - j0) at the front of the pool.
   constexpr int CB = 8;
-  __shared__ qd panel[CB][257];
-  __shared__ qd done[CB][257];
+  __shared__ qd pool[CHOL_POOL];
   __shared__ double s_maxd;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < k * k; e += nt) {
@@ -926,17 +931,34 @@ __device__ void sm_chol(const double *g, double *r, int k, int complex_only, dou
     *minp = 1.0;
   }
   __syncthreads();
+  qd *T = nullptr;                    // LDS trailing block, rows and columns o ..
+  int o = 0;
+#define QSK_CHOL_GET(A_, C_) (T ? T[chol_pk((A_) - o, (C_) - o)] : gq(r, (A_), (C_), k))
   for (int j0 = 0; j0 < k; j0 += CB) {
     const int jb = min(CB, k - j0), w = k - j0;
+    qd *panel = pool, *done = pool + CB * w;
+    if (!T && 2 * CB * w + ((w * (w + 1)) >> 1) <= CHOL_POOL) {
+      // move the upper triangle of rows and columns j0 .. k-1 into LDS
+      T = pool + 2 * CB * w;
+      o = j0;
+      for (int e = tid; e < ((w * (w + 1)) >> 1); e += nt) {
+        int c = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while (c > 0 && ((c * (c + 1)) >> 1) > e) --c;
+        while ((((c + 1) * (c + 2)) >> 1) <= e) ++c;
+        const int a = e - ((c * (c + 1)) >> 1);
+        T[e] = gq(r, o + a, o + c, k);
+      }
+      __syncthreads();
+    }
     for (int e = tid; e < jb * w; e += nt) {
       const int rr = e / w, cc = e % w;
-      panel[rr][cc] = cc >= rr ? gq(r, j0 + rr, j0 + cc, k) : qzero();
+      panel[rr * w + cc] = cc >= rr ? QSK_CHOL_GET(j0 + rr, j0 + cc) : qzero();
     }
     __syncthreads();
     for (int rr = 0; rr < jb; ++rr) {
       // every thread reads the pivot; a pivot below tol * max diagonal marks
       // failure (the factor is then discarded by the caller)
-      const double d = panel[rr][rr].w;
+      const double d = panel[rr * w + rr].w;
       const double rel = s_maxd > 0.0 ? d / s_maxd : 0.0;
       if (tid == 0) {
         if (rel < *minp) *minp = rel;
@@ -948,30 +970,36 @@ __device__ void sm_chol(const double *g, double *r, int k, int complex_only, dou
       for (int e = tid; e < rows * w; e += nt) {
         const int r2 = rr + 1 + e / w, cc = e % w;
         if (cc >= r2)
-          panel[r2][cc] = qsub(panel[r2][cc], qscale(qmul(qconj(panel[rr][r2]), panel[rr][cc]), inv_d));
+          panel[r2 * w + cc] = qsub(panel[r2 * w + cc],
+                                    qscale(qmul(qconj(panel[rr * w + r2]), panel[rr * w + cc]), inv_d));
       }
       for (int cc = tid; cc < w; cc += nt)
-        done[rr][cc] = cc < rr ? qzero() : (cc == rr ? qd{sd, 0.0, 0.0, 0.0} : qscale(panel[rr][cc], inv_s));
+        done[rr * w + cc] = cc < rr ? qzero() : (cc == rr ? qd{sd, 0.0, 0.0, 0.0} : qscale(panel[rr * w + cc], inv_s));
       __syncthreads();
     }
     if (*fail) return;
     for (int e = tid; e < jb * w; e += nt) {
       const int rr = e / w, cc = e % w;
-      if (cc >= rr) sq_(r, j0 + rr, j0 + cc, k, done[rr][cc]);
+      if (cc >= rr) sq_(r, j0 + rr, j0 + cc, k, done[rr * w + cc]);
     }
-    const int nr = k - j0 - jb;
-    for (int e = tid; e < nr * nr; e += nt) {
-      const int aa = e % nr, cc = e / nr;
-      if (aa <= cc) {
-        const int ga = j0 + jb + aa, gc = j0 + jb + cc;
-        qd v = gq(r, ga, gc, k);
-        for (int rr = 0; rr < jb; ++rr)
-          v = qsub(v, qmul(qconj(done[rr][ga - j0]), done[rr][gc - j0]));
-        sq_(r, ga, gc, k, v);
-      }
+    // trailing update of the upper triangle, its entries dealt to the
+    // threads in turn (packed by columns)
+    const int nr = k - j0 - jb, b0 = j0 + jb;
+    for (int e = tid; e < ((nr * (nr + 1)) >> 1); e += nt) {
+      int cc = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+      while (cc > 0 && ((cc * (cc + 1)) >> 1) > e) --cc;
+      while ((((cc + 1) * (cc + 2)) >> 1) <= e) ++cc;
+      const int aa = e - ((cc * (cc + 1)) >> 1);
+      const int ga = b0 + aa, gc = b0 + cc;
+      qd v = QSK_CHOL_GET(ga, gc);
+      for (int rr = 0; rr < jb; ++rr)
+        v = qsub(v, qmul(qconj(done[rr * w + ga - j0]), done[rr * w + gc - j0]));
+      if (T) T[chol_pk(ga - o, gc - o)] = v;
+      else sq_(r, ga, gc, k, v);
     }
     __syncthreads();
   }
+#undef QSK_CHOL_GET
 }
 
 // T = R^{-1} for upper triangular R with real positive diagonal (single
