@@ -921,10 +921,14 @@ __device__ void sm_chol(const double *g, double *r, int k, int complex_only, dou
     }
     sq_(r, i, j, k, v);
   }
+  // the diagonal goes to LDS in parallel; one thread then takes its maximum
+  // and its sum in index order
+  double *diag = (double *)pool;
+  for (int i = tid; i < k; i += nt) diag[i] = gq(g, i, i, k).w + shift;
   __syncthreads();
   if (tid == 0) {
     double md = 0.0, tr = 0.0;
-    for (int i = 0; i < k; ++i) { const double d = r[4 * (i + (int64_t)i * k)]; md = fmax(md, d); tr += d; }
+    for (int i = 0; i < k; ++i) { const double d = diag[i]; md = fmax(md, d); tr += d; }
     s_maxd = md;
     *trace = tr;
     *fail = 0;
