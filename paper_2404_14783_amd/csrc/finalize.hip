@@ -1151,13 +1151,23 @@ __global__ __launch_bounds__(256) void triinv_kernel(CholArgs args, GroupRef grp
   if (status && status->fail) return;
   if (bx >= k) return;
   const int c = bx, tid = threadIdx.x;
-  for (int a = tid; a < k; a += 256) { acc[a] = qzero(); col[a] = qzero(); }
+  // k <= 256: thread a owns row a.  The pivots' reciprocals are read once,
+  // and column b - 1 of R is loaded while step b runs.
+  __shared__ double dinv[256];
+  for (int a = tid; a < k; a += 256) {
+    acc[a] = qzero();
+    col[a] = qzero();
+    if (a <= c) dinv[a] = 1.0 / gp(r)[4 * (a + (int64_t)a * k)];
+  }
   __syncthreads();
+  qd rcur = tid < c ? gq(r, tid, c, k) : qzero();
   for (int b = c; b >= 0; --b) {
+    const qd rnext = tid + 1 < b ? gq(r, tid, b - 1, k) : qzero();
     qd tb = qsub(b == c ? qd{1.0, 0.0, 0.0, 0.0} : qzero(), acc[b]);
-    tb = qscale(tb, 1.0 / gp(r)[4 * (b + (int64_t)b * k)]);
+    tb = qscale(tb, dinv[b]);
     if (tid == 0) col[b] = tb;
-    for (int a = tid; a < b; a += 256) qfma(acc[a], gq(r, a, b, k), tb);
+    if (tid < b) qfma(acc[tid], rcur, tb);
+    rcur = rnext;
     __syncthreads();
   }
   for (int a = tid; a < k; a += 256) sq_(t, a, c, k, col[a]);
@@ -2103,17 +2113,29 @@ __global__ __launch_bounds__(1024) void psvd_orth_kernel(PsvdArgs args, GroupRef
     c0 = c1;
   }
   // diagonal unitary scaling: delta_0 = 1, delta_{j+1} = alpha_j delta_j / |alpha_j|
+  // (the alpha_j staged in LDS in parallel, the running product formed by
+  // one thread, the result copied out in parallel)
+  __syncthreads();
+  qd *als = (qd *)pool;
+  qd *dls = als + k;
+  for (int j = tid; j + 1 < k; j += blockDim.x)
+    als[j] = qd{gp(L.HA)[4 * j], gp(L.HA)[4 * j + 1], gp(L.HA)[4 * j + 2], gp(L.HA)[4 * j + 3]};
+  __syncthreads();
   if (tid == 0) {
     qd delta = {1.0, 0.0, 0.0, 0.0};
-    QSK_GLOBAL double *cq = gpw(L.CQ);
-    cq[0] = 1.0; cq[1] = 0.0; cq[2] = 0.0; cq[3] = 0.0;
+    dls[0] = delta;
     for (int j = 0; j + 1 < k; ++j) {
-      const qd al = {gp(L.HA)[4 * j], gp(L.HA)[4 * j + 1], gp(L.HA)[4 * j + 2], gp(L.HA)[4 * j + 3]};
+      const qd al = als[j];
       const double aa = sqrt(qnorm2(al));
       if (aa > 0.0) delta = qmul(qscale(al, 1.0 / aa), delta);
-      cq[4 * (j + 1)] = delta.w; cq[4 * (j + 1) + 1] = delta.x;
-      cq[4 * (j + 1) + 2] = delta.y; cq[4 * (j + 1) + 3] = delta.z;
+      dls[j + 1] = delta;
     }
+  }
+  __syncthreads();
+  QSK_GLOBAL double *cq = gpw(L.CQ);
+  for (int j = tid; j < k; j += blockDim.x) {
+    const qd dj = dls[j];
+    cq[4 * j] = dj.w; cq[4 * j + 1] = dj.x; cq[4 * j + 2] = dj.y; cq[4 * j + 3] = dj.z;
   }
 }
 
