@@ -1249,18 +1249,22 @@ __global__ __launch_bounds__(256) void qgemm_small_kernel(GemmArgs args, GroupRe
   const int i0 = bx * 16, j0 = by * 16;
   if (i0 >= k || j0 >= k) return;
   qd acc = qzero();
+  // the operands of the next 16-wide step are loaded while this one is
+  // multiplied
+  auto load_a = [&](int t0) {
+    const int gi = i0 + ti, gt = t0 + tj;
+    return (gi < k && gt < k) ? (opa ? qconj(gq(a, gt, gi, k)) : gq(a, gi, gt, k)) : qzero();
+  };
+  auto load_b = [&](int t0) {
+    const int gt2 = t0 + ti, gj = j0 + tj;
+    return (gt2 < k && gj < k) ? (opb ? qconj(gq(b, gj, gt2, k)) : gq(b, gt2, gj, k)) : qzero();
+  };
+  qd va = load_a(0), vb = load_b(0);
   for (int t0 = 0; t0 < k; t0 += 16) {
-    {
-      const int gi = i0 + ti, gt = t0 + tj;
-      qd v = qzero();
-      if (gi < k && gt < k) v = opa ? qconj(gq(a, gt, gi, k)) : gq(a, gi, gt, k);
-      sa[ti][tj] = v;
-      const int gt2 = t0 + ti, gj = j0 + tj;
-      qd u = qzero();
-      if (gt2 < k && gj < k) u = opb ? qconj(gq(b, gj, gt2, k)) : gq(b, gt2, gj, k);
-      sb[ti][tj] = u;
-    }
+    sa[ti][tj] = va;
+    sb[ti][tj] = vb;
     __syncthreads();
+    if (t0 + 16 < k) { va = load_a(t0 + 16); vb = load_b(t0 + 16); }
 #pragma unroll
     for (int tt = 0; tt < 16; ++tt) qfma(acc, sa[ti][tt], sb[tt][tj]);
     __syncthreads();
