@@ -24,7 +24,8 @@
  *    buffer alive until the stream has passed the call.
  *  - The caller owns its inputs and outputs; the context owns the sketches and
  *    all workspace, allocated in qsketch_init (update and finalize allocate
- *    nothing).
+ *    nothing; qsketch_update_block, qsketch_project and qsketch_truncate grow
+ *    work buffers of their own on first use).
  *  - On QSK_E_ARG nothing has happened.  A HIP failure returns QSK_E_HIP and
  *    poisons the context: every later call except qsketch_destroy,
  *    qsketch_last_error and qsketch_strerror returns QSK_E_STATE.
@@ -46,7 +47,9 @@ typedef enum {
   QSK_OK = 0,
   QSK_E_ARG = 1,          /* invalid argument; no side effects */
   QSK_E_STATE = 2,        /* context poisoned or destroyed */
-  QSK_E_NOMEM = 3,        /* device allocation failed in qsketch_init */
+  QSK_E_NOMEM = 3,        /* device allocation failed: in qsketch_init, or for a work
+                             buffer that qsketch_update_block, qsketch_project or
+                             qsketch_truncate grows (the context stays usable) */
   QSK_E_HIP = 4,          /* a HIP runtime call failed; context poisoned */
   QSK_E_NUMERIC = 5,      /* no Q/X could be formed (e.g. Y == 0) */
   QSK_E_UNSUPPORTED = 6   /* valid but not implemented combination */

@@ -110,6 +110,30 @@ qsk_status hip_fail(qsk_ctx *c, hipError_t e, const char *where) {
     if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr); \
   } while (0)
 
+// A buffer the context grows on demand (kept until qsketch_destroy): at
+// least `need` bytes in *p.  The stream is drained before an old buffer is
+// freed.  A shortage of device memory returns QSK_E_NOMEM and leaves the
+// context usable.
+qsk_status grow_buffer(qsk_ctx *ctx, void **p, size_t *bytes, size_t need) {
+  if (need <= *bytes) return QSK_OK;
+  if (*p) {
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipFree(*p));
+    *p = nullptr;
+    *bytes = 0;
+  }
+  const hipError_t e = hipMalloc(p, need);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    ctx->last_error = "out of device memory for a work buffer";
+    return QSK_E_NOMEM;
+  }
+  HIPCHK(ctx, e);
+  *bytes = need;
+  return QSK_OK;
+}
+
 void resolve_timing(qsk_ctx *c) {
   for (size_t u = 0; u + 8 <= c->ev_used; u += 8) {
     for (int kk = 0; kk < 4; ++kk) {
@@ -418,9 +442,9 @@ qsk_status qsketch_update_block(qsk_ctx *ctx, int64_t row0, int64_t nrows, int64
     if (!planes[p]) return fail_arg(ctx, "NULL plane");
   const size_t es = c.input_dtype == QSK_F64 ? 8 : c.input_dtype == QSK_F32 ? 4 : 2;
   const size_t plane = (size_t)c.m * c.max_block_cols * es;
-  if (!ctx->pad) {
-    HIPCHK(ctx, hipMalloc(&ctx->pad, 4 * plane));
-    ctx->pad_bytes = 4 * plane;
+  {
+    const qsk_status gs = grow_buffer(ctx, &ctx->pad, &ctx->pad_bytes, 4 * plane);
+    if (gs != QSK_OK) return gs;
   }
   // the full-height block: zero outside rows row0 .. row0 + nrows - 1
   const void *full[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -774,29 +798,17 @@ qsk_status qsketch_project(qsk_ctx *ctx, double *const Q[4], int64_t ldq, int64_
     // the block's shape stands in for it
     const size_t need = ((size_t)(ncols - 1) * ld + c.m) * es;
     if (need > ctx->zero_plane_bytes) {
-      if (ctx->zero_plane) {
-        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-        HIPCHK(ctx, hipFree(ctx->zero_plane));
-        ctx->zero_plane = nullptr;
-        ctx->zero_plane_bytes = 0;
-      }
-      HIPCHK(ctx, hipMalloc(&ctx->zero_plane, need));
-      ctx->zero_plane_bytes = need;
+      const qsk_status gs = grow_buffer(ctx, &ctx->zero_plane, &ctx->zero_plane_bytes, need);
+      if (gs != QSK_OK) return gs;
       HIPCHK(ctx, hipMemsetAsync(ctx->zero_plane, 0, need, ctx->stream));
     }
     b[0] = ctx->zero_plane;
   }
   const int64_t nch = qsk::project_chunks(c.m, c.k, ncols);
   const size_t pneed = nch > 1 ? (size_t)nch * c.k * ncols * 4 * 8 : 0;
-  if (pneed > ctx->proj_part_bytes) {
-    if (ctx->proj_part) {
-      HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-      HIPCHK(ctx, hipFree(ctx->proj_part));
-      ctx->proj_part = nullptr;
-      ctx->proj_part_bytes = 0;
-    }
-    HIPCHK(ctx, hipMalloc((void **)&ctx->proj_part, pneed));
-    ctx->proj_part_bytes = pneed;
+  {
+    const qsk_status gs = grow_buffer(ctx, (void **)&ctx->proj_part, &ctx->proj_part_bytes, pneed);
+    if (gs != QSK_OK) return gs;
   }
   double *xo[4];
   for (int p = 0; p < 4; ++p) xo[p] = X[p] + col0 * ldx;
@@ -821,15 +833,9 @@ qsk_status qsketch_truncate(qsk_ctx *ctx, double *const Q[4], int64_t ldq, doubl
   hipStream_t st = ctx->stream;
   // Z = X^* (n x k); the Gram Z^* Z = X X^* = U Sigma^2 U^*
   const size_t need = 4 * (size_t)n * k * 8;
-  if (need > ctx->xt_bytes) {
-    if (ctx->xt) {
-      HIPCHK(ctx, hipStreamSynchronize(st));
-      HIPCHK(ctx, hipFree(ctx->xt));
-      ctx->xt = nullptr;
-      ctx->xt_bytes = 0;
-    }
-    HIPCHK(ctx, hipMalloc((void **)&ctx->xt, need));
-    ctx->xt_bytes = need;
+  {
+    const qsk_status gs = grow_buffer(ctx, (void **)&ctx->xt, &ctx->xt_bytes, need);
+    if (gs != QSK_OK) return gs;
   }
   double *z[4];
   for (int p = 0; p < 4; ++p) z[p] = ctx->xt + (size_t)p * n * k;
