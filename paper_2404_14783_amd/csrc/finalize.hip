@@ -316,8 +316,17 @@ __global__ void reduce_chunks_k(ReduceArgs args, GroupRef grp) {
       if (p > 0) sg = -1.0;
     }
   }
+  // four loads in flight at a time, added in chunk order
   double s = 0.0;
-  for (int c = 0; c < nchunks; ++c) s += gp(partial)[(int64_t)c * elems + src];
+  int c = 0;
+  for (; c + 4 <= nchunks; c += 4) {
+    const double a0 = gp(partial)[(int64_t)c * elems + src];
+    const double a1 = gp(partial)[(int64_t)(c + 1) * elems + src];
+    const double a2 = gp(partial)[(int64_t)(c + 2) * elems + src];
+    const double a3 = gp(partial)[(int64_t)(c + 3) * elems + src];
+    s += a0; s += a1; s += a2; s += a3;
+  }
+  for (; c < nchunks; ++c) s += gp(partial)[(int64_t)c * elems + src];
   gpw(out)[e] = sg * s;
 }
 
@@ -336,7 +345,15 @@ __global__ void reduce_chunks_planar_k(ReducePlanarArgs args, GroupRef grp) {
   if (e >= n) return;
   const int i = (int)(e % r), j = (int)(e / r);
   double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int ch = 0; ch < nchunks; ++ch)
+  int ch = 0;
+  for (; ch + 2 <= nchunks; ch += 2) {           // two chunks' loads in flight, added in order
+    double a[2][4];
+    for (int u = 0; u < 2; ++u)
+      for (int p = 0; p < 4; ++p) a[u][p] = gp(partial)[((int64_t)(ch + u) * n + e) * 4 + p];
+    for (int u = 0; u < 2; ++u)
+      for (int p = 0; p < 4; ++p) s[p] += a[u][p];
+  }
+  for (; ch < nchunks; ++ch)
     for (int p = 0; p < 4; ++p) s[p] += gp(partial)[((int64_t)ch * n + e) * 4 + p];
   for (int p = 0; p < 4; ++p) gpw(out.p[p])[i + (int64_t)j * ldo] = s[p];
 }
