@@ -539,8 +539,17 @@ __global__ void w_reduce_kernel(const float *part, int S, int LP, int64_t ncols,
     const int64_t jp = e / l;
     const int64_t j = jp % ncols;
     const int p = (int)(jp / ncols);
+    // four partials' loads in flight at a time, added in order
     float s = 0.f;
-    for (int z = 0; z < S; ++z) s += gp(part)[(((int64_t)z * 4 + p) * ncols + j) * LP + r];
+    int z = 0;
+    for (; z + 4 <= S; z += 4) {
+      float a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = gp(part)[(((int64_t)(z + u) * 4 + p) * ncols + j) * LP + r];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s += a[u];
+    }
+    for (; z < S; ++z) s += gp(part)[(((int64_t)z * 4 + p) * ncols + j) * LP + r];
     gpw(w)[p * psw + (col0 + j) * ldw + r] += eta * s;
   }
 }
@@ -767,8 +776,17 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
 __global__ void y_fold_kernel(float *y, int64_t n_per_copy, int S) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_per_copy;
        e += (int64_t)gridDim.x * blockDim.x) {
+    // the copies are read before any is cleared, and added in order
     float s = y[e];
-    for (int c = 1; c < S; ++c) {
+    int c = 1;
+    for (; c + 2 <= S; c += 2) {
+      const float a0 = y[c * n_per_copy + e], a1 = y[(c + 1) * n_per_copy + e];
+      y[c * n_per_copy + e] = 0.f;
+      y[(c + 1) * n_per_copy + e] = 0.f;
+      s += a0;
+      s += a1;
+    }
+    for (; c < S; ++c) {
       s += y[c * n_per_copy + e];
       y[c * n_per_copy + e] = 0.f;
     }
