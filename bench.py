@@ -369,7 +369,7 @@ def main():
         summarize_traffic(*args.summarize_traffic)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     torch.cuda.set_device(0)
     if args.workload == "batch64":
