@@ -12,8 +12,23 @@ of the sketches, then the QB stage with pseudo-QR and with pseudo-SVD.  Paths:
   fp32   FP32 sketch on the matrix cores (the same-GPU FP32 plain path)
   bf16   BF16 sketch with the data split in `--terms` bf16 terms (timed: `value`)
 
+The default run also measures the other workloads, reported in the same
+JSON line under `workloads`:
+  image    31365 x 27125 pure quaternion in BF16 (5.1 GB), quaternion
+           Rademacher test matrices, k = 200, l = 401, BF16 operands (exact:
+           one term), column blocks of 2048, both rangefinders
+  batch64  64 independent FP32 problems (m 512-8192, n 256-4096 log-uniform,
+           k = 2r, l = 2k + 1), BF16 two-term operands, autotuned tiles
+  flow     2,097,152 x 300 pure quaternion FP32 snapshot matrix (7.55 GB),
+           streamed as 30 linear updates of 10 columns, e4m3 operands with
+           per-tile scales plus the residual terms, Gaussian, k = 60, l = 121
+each with its wall time, algorithmic sketch TFLOP/s, the roofline fraction of
+its dominant kernel and the relative-error difference against the same
+GPU's FP64 path.
+
 Prints one JSON line.  `value` = algorithmic sketch TFLOP/s of the bf16 path
-(2 * 16 * m * n * (k + l) flops over the time of its updates).
+on the 20000 x 15000 workload (2 * 16 * m * n * (k + l) flops over the time of
+its updates).
 """
 from __future__ import annotations
 
@@ -70,9 +85,24 @@ def run_pass(sk, a, block, kinds=("pseudo_qr", "pseudo_svd")):
     return e0.elapsed_time(e1), e0.elapsed_time(e2), res
 
 
+def cpu_threads():
+    """Threads the oracle's BLAS actually uses (threadpoolctl when present)."""
+    try:
+        from threadpoolctl import threadpool_info
+        n = [i.get("num_threads") for i in threadpool_info() if i.get("user_api") == "blas"]
+        if n:
+            return int(max(n))
+    except Exception:
+        pass
+    return os.cpu_count()
+
+
 def cpu_baseline(a_dev, m, n, k, l, block, seconds=20.0):
-    """The oracle's FP64 sketch update timed on the host cores on a bounded
-    sample: the first column blocks of the same input, until ~`seconds`."""
+    """The oracle timed on the host cores on a bounded sample of the same
+    workload: its FP64 sketch update over the first column blocks, until
+    about `seconds`, then its QB stage (both rangefinders and the core solve)
+    on that sketch, timed separately."""
+    from oracle import onepass
     from oracle.sketch import Sketch, SketchConfig
     sk = Sketch(SketchConfig(m, n, k, l, seed=0))
     t0 = time.perf_counter()
@@ -87,10 +117,18 @@ def cpu_baseline(a_dev, m, n, k, l, block, seconds=20.0):
         c0 += sample_block
     dt = time.perf_counter() - t0
     flops = sketch_flops(m, cols, k, l)
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": os.cpu_count(),
-            "kind": "oracle",
+    fin = {}
+    for kind in ("pseudo_qr", "pseudo_svd"):
+        t1 = time.perf_counter()
+        onepass.qb_stage(sk, kind)
+        fin[kind] = time.perf_counter() - t1
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cpu_threads(),
+            "kind": "oracle", "sketch_s": dt, "sketch_columns": cols,
+            "finalize_s": fin, "host_cpus": os.cpu_count(),
             "sample": f"FP64 NumPy sketch update of the first {cols} of {n} columns "
-                      f"(m={m}, k={k}, l={l}, Gaussian, Psi generation included), {dt:.1f} s"}
+                      f"(m={m}, k={k}, l={l}, Gaussian, Psi generation included), {dt:.1f} s; "
+                      f"then the QB stage on that sketch (Y {m}x{k}, W {l}x{n}): pseudo-QR "
+                      f"{fin['pseudo_qr']:.2f} s, pseudo-SVD {fin['pseudo_svd']:.2f} s"}
 
 
 def source_digest():
@@ -163,20 +201,37 @@ def summarize_traffic(fetch_dir, write_dir, cmd_fetch, cmd_write):
     print("\n".join(lines))
 
 
-def summarize_stats(directory, cmd, out_path):
+STATS_TITLES = {
+    "c2": ("20000x15000 FP32 quaternion, BF16 (2-term) sketch, both rangefinders",
+           "Whole one-pass approximations (8 column-block updates of 2048 columns each, then the QB stage "
+           "with pseudo-QR and with pseudo-SVD), after a 256 MiB calibration copy; input generation kernels "
+           "(torch, rocBLAS) are listed too."),
+    "image": ("31365x27125 pure quaternion BF16 image, Rademacher, k=200, l=401, BF16 operands, both rangefinders",
+              "Whole one-pass approximations (14 column-block updates of 2048 columns, then the QB stage with "
+              "pseudo-QR and with pseudo-SVD); input generation kernels are listed too."),
+    "flow": ("2097152x300 pure quaternion FP32 flow snapshots, 30 updates of 10 columns, fp8 + residual, "
+             "k=60, l=121, both rangefinders",
+             "Whole one-pass approximations (30 linear updates of 10 columns, then the QB stage with pseudo-QR "
+             "and with pseudo-SVD); input generation kernels are listed too."),
+    "batch64": ("64 FP32 quaternion problems, BF16 two-term operands, autotuned tiles",
+                "Batched runs (autotuning, then runs with pseudo-QR and with pseudo-SVD); input generation "
+                "kernels are listed too."),
+}
+
+
+def summarize_stats(directory, cmd, out_path, workload="c2"):
     """Short kernel-time table from a rocprofv3 --kernel-trace --stats run."""
     files = glob.glob(os.path.join(directory, "**", "*kernel_stats.csv"), recursive=True)
     rows = list(csv.DictReader(open(files[0])))
+    title, what = STATS_TITLES[workload]
     lines = [
-        "# Kernel time summary: 20000x15000 FP32 quaternion, BF16 (2-term) sketch, both rangefinders",
+        f"# Kernel time summary: {title}",
         "",
         "Command (from the repository root, on one MI355X):",
         "",
         f"    {cmd}",
         "",
-        "Two whole one-pass approximations (8 column-block updates of 2048 columns each, then the QB stage",
-        "with pseudo-QR and with pseudo-SVD), after a 256 MiB calibration copy; input generation kernels",
-        "(torch, rocBLAS) are listed too.",
+        what,
         "",
         "| total ms | calls | avg us | kernel |",
         "|---:|---:|---:|---|",
@@ -206,17 +261,21 @@ def committed_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
-def bench_batch(args):
+METRIC = "one-pass qLRA wall time + sketch TFLOP/s at equal rel. error, BF16/FP8 vs FP32"
+
+
+def bench_batch(args, profile_only=False):
     """64 independent problems (m in [512, 8192], n in [256, 4096] log-uniform,
     rank 8..64 with geometric decay, k = 2r, l = 2k + 1, FP32 data, 1e-4
     noise) through the batched path: one run = both sketches of every
-    problem and the QB stage with one rangefinder, all problems together."""
+    problem and the QB stage with one rangefinder, all problems together.
+    Returns the workload's record."""
     specs = synth.batch_specs(64)
     mats = [qs.to_colmajor(synth.batch_matrix(sp, i, device="cuda")) for i, sp in enumerate(specs)]
     shapes = [(sp["m"], sp["n"], sp["k"], sp["l"], i) for i, sp in enumerate(specs)]
     torch.cuda.synchronize()
     flops = sum(sketch_flops(m, n, k, l) for (m, n, k, l, _) in shapes)
-    if args.profile_only:
+    if profile_only:
         b = qs.Batch(shapes, input_dtype="f32", sketch_dtype="bf16", split_terms=args.terms)
         b.autotune(mats)
         outs = b.outputs()
@@ -225,8 +284,7 @@ def bench_batch(args):
                 b.run(mats, kind, outputs=outs)
         torch.cuda.synchronize()
         b.close()
-        print(json.dumps({"profile_only": True, "workload": "batch64"}))
-        return
+        return {"profile_only": True, "workload": "batch64"}
     out = {}
     errs = {}
     tiles = {}
@@ -250,10 +308,9 @@ def bench_batch(args):
             out[f"{name}_{kind}_ms"] = ms
             log(f"[bench] batch {name} {kind}: {ms:.2f} ms per run")
         b.close()
-    # FP64 single-problem references for the first problems
-    nref = min(16, len(shapes))
+    # the GPU FP64 path for every problem: the equal-error reference
     worst = 0.0
-    for i in range(nref):
+    for i in range(len(shapes)):
         m, n, k, l, seed = shapes[i]
         sk = qs.Sketcher(m, n, k, l, seed=seed, input_dtype="f32", sketch_dtype="f64", max_block_cols=n)
         sk.update(0, mats[i])
@@ -261,25 +318,179 @@ def bench_batch(args):
             q, x, _ = sk.finalize(kind)
             ref = sk.rel_error(mats[i], q, x)
             worst = max(worst, abs(errs[("bf16", kind)][i] - ref) / ref)
+            del q, x
         sk.close()
     step_ms = out["bf16_pseudo_qr_ms"] + out["bf16_pseudo_svd_ms"]
     fp32_ms = out["fp32_pseudo_qr_ms"] + out["fp32_pseudo_svd_ms"]
-    line = {
-        "metric": "one-pass qLRA wall time + sketch TFLOP/s at equal rel. error, BF16/FP8 vs FP32",
-        "value": 2 * flops / (step_ms * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
-        "data": "synthetic",
-        "config": {"workload": "batch of 64 FP32 quaternion problems, m 512-8192, n 256-4096, "
-                               "k = 2r (r 8-64), l = 2k + 1, Gaussian; step = one batched run with "
-                               "pseudo-QR plus one with pseudo-SVD (sketches recomputed in each)",
-                   "problems": len(shapes), "sketch_flops_per_run": flops, "bf16_terms": args.terms},
+    ach = 2 * flops / (step_ms * 1e-3)
+    return {
+        "workload": "batch of 64 FP32 quaternion problems, m 512-8192, n 256-4096, k = 2r (r 8-64), "
+                    "l = 2k + 1, Gaussian, BF16 two-term operands; step = one batched run with pseudo-QR "
+                    "plus one with pseudo-SVD (sketches recomputed in each)",
+        "problems": len(shapes), "sketch_flops_per_run": flops, "bf16_terms": args.terms,
+        "total_entries": int(sum(m * n for (m, n, _, _, _) in shapes)),
+        "ms_per_step": step_ms, "sketch_tflops_whole_run": ach / 1e12,
         "paths": out, "speedup_vs_fp32_wall": fp32_ms / step_ms,
         "autotuned_tiles": {k: {"w_row_tiles": v[0], "y_col_tiles": v[1]} for k, v in tiles.items()},
-        "equal_error": {"max_rel_diff_bf16_vs_fp64": worst, "problems_checked": nref},
-        "roofline": None, "cpu_baseline": None,
+        "equal_error": {"max_rel_diff_bf16_vs_fp64": worst, "problems_checked": len(shapes)},
+        "roofline": {"bound": "mfma", "kernel": "whole batched run (sketches and QB stage)",
+                     "achieved": ach / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
+                     "frac": ach / PEAK_BF16},
     }
-    print(json.dumps(line))
+
+
+def timed_passes(sk, a, block, args, kinds=("pseudo_qr", "pseudo_svd")):
+    """W untimed and K timed whole passes with per-kernel timing; returns
+    (median update ms, median pass ms, results of the last pass, timing)."""
+    for _ in range(args.warmup):
+        run_pass(sk, a, block, kinds)
+    sk.set_timing(True)
+    ups, tots = [], []
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        up, tot, res = run_pass(sk, a, block, kinds)
+        ups.append(up)
+        tots.append(tot)
+    timing = sk.timing()
+    sk.set_timing(False)
+    return float(np.median(ups)), float(np.median(tots)), res, timing
+
+
+def kernel_rooflines(timing, m, n, k, l, pure, steps, peak, y_bytes_per_update=None, updates=None):
+    """Achieved rate of the two product kernels over the timed passes: the
+    algorithmic flops of all their launches (2 P m n k for Y, 2 P m n l for W,
+    P = 12 for pure input, else 16) over the summed HIP-event durations of
+    the launches; for a streamed workload also the Y kernel's algorithmic
+    HBM bytes (A's block plus the read-modify-write of Y) per second."""
+    P = 12 if pure else 16
+    out = {}
+    for name, kk in (("w", l), ("y", k)):
+        ms, cnt = timing[name]
+        fl = 2.0 * P * m * n * kk * steps
+        ach = fl / (ms * 1e-3) if ms > 0 else 0.0
+        out[name] = {"achieved_tflops": ach / 1e12, "frac": ach / peak, "launches": cnt,
+                     "avg_launch_ms": ms / max(cnt, 1)}
+    if y_bytes_per_update is not None:
+        ms, cnt = timing["y"]
+        by = y_bytes_per_update * updates * steps
+        out["y"]["achieved_gbs"] = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        out["y"]["hbm_frac"] = by / (ms * 1e-3) / PEAK_HBM if ms > 0 else 0.0
+    return out
+
+
+def bench_stream_leg(args, label, a, m, n, k, l, block, emb, input_dtype, pure, paths, peak):
+    """One streamed workload: the GPU FP64 path (untimed, the error
+    reference), then each low-precision path timed; returns its record."""
+    res = {}
+    errors = {}
+    flops = sketch_flops(m, n, k, l, pure)
+    log(f"[bench] {label}: FP64 reference pass (untimed)")
+    sk = qs.Sketcher(m, n, k, l, seed=0, embedding=emb, input_dtype=input_dtype, sketch_dtype="f64",
+                     pure=pure, max_block_cols=block)
+    up, tot, r = run_pass(sk, a, block)
+    for kind, (q, x, rep) in r.items():
+        errors[("fp64", kind)] = sk.rel_error(a, q, x)
+    res["fp64"] = {"update_ms": up, "total_ms": tot}
+    sk.close()
+    del r
+    for name, sketch, terms in paths:
+        sk = qs.Sketcher(m, n, k, l, seed=0, embedding=emb, input_dtype=input_dtype, sketch_dtype=sketch,
+                         split_terms=terms, pure=pure, max_block_cols=block)
+        up, tot, r, timing = timed_passes(sk, a, block, args)
+        rec = {"update_ms": up, "total_ms": tot, "sketch_tflops": flops / (up * 1e-3) / 1e12,
+               "terms": terms, "kernels_ms": {kk: v[0] / args.steps for kk, v in timing.items()}}
+        for kind, (q, x, rep) in r.items():
+            errors[(name, kind)] = sk.rel_error(a, q, x)
+            rec[kind + "_kappa"] = rep["kappa"]
+        nupd = (n + block - 1) // block
+        ybytes = None
+        if block < 64:
+            # streamed in thin blocks: Y's read-modify-write dominates the traffic
+            ybytes = (3 if pure else 4) * m * (n / nupd) * (4 if input_dtype == "f32" else 2) + 2 * 4 * m * k * 4
+        rec["kernels"] = kernel_rooflines(timing, m, n, k, l, pure, args.steps, peak, ybytes, nupd)
+        res[name] = rec
+        log(f"[bench] {label} {name}: updates {up:.2f} ms, step {tot:.2f} ms, "
+            f"{rec['sketch_tflops']:.1f} TFLOP/s, kernels {rec['kernels']}")
+        sk.close()
+        del r
+    eq = {}
+    for kind in ("pseudo_qr", "pseudo_svd"):
+        ref = errors[("fp64", kind)]
+        eq[kind] = {"e_fp64": ref}
+        for name, _, _ in paths:
+            e = errors[(name, kind)]
+            eq[kind]["e_" + name] = e
+            eq[kind]["rel_diff_" + name] = abs(e - ref) / ref if ref else None
+    return {"paths": res, "equal_error": eq, "sketch_flops": flops}
+
+
+def bench_image(args, profile_only=False):
+    """The 31365 x 27125 pure-quaternion BF16 image, Rademacher, k = 200,
+    l = 401, BF16 operands (exact in one term)."""
+    m, n, k, l, block = 31365, 27125, 200, 401, 2048
+    log(f"[bench] image: generating {m}x{n} (3 BF16 planes) on the GPU")
+    a = qs.to_colmajor(synth.image_planes(m, n, device="cuda", dtype=torch.bfloat16))
+    torch.cuda.synchronize()
+    if profile_only:
+        sk = qs.Sketcher(m, n, k, l, seed=0, embedding="rademacher", input_dtype="bf16",
+                         sketch_dtype="bf16", pure=True, max_block_cols=block)
+        for _ in range(max(1, args.steps)):
+            up, tot, _ = run_pass(sk, a, block)
+            log(f"[bench] image bf16 pass: updates {up:.2f} ms, total {tot:.2f} ms")
+        sk.close()
+        return {"profile_only": True, "workload": "image", "update_ms": up, "total_ms": tot}
+    leg = bench_stream_leg(args, "image", a, m, n, k, l, block, "rademacher", "bf16", True,
+                           [("bf16", "bf16", 1)], PEAK_BF16)
+    del a
+    torch.cuda.empty_cache()
+    bf = leg["paths"]["bf16"]
+    w = bf["kernels"]["w"]
+    leg.update({
+        "workload": f"{m}x{n} pure quaternion image in BF16, column blocks of {block}, Rademacher "
+                    f"k={k} l={l}, BF16 operands (one term), both rangefinders",
+        "ms_per_step": bf["total_ms"], "sketch_tflops": bf["sketch_tflops"],
+        "roofline": {"bound": "mfma", "kernel": "w_mfma_kernel (bf16, 1 term, pure)",
+                     "achieved": w["achieved_tflops"], "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
+                     "frac": w["frac"], "avg_launch_ms": w["avg_launch_ms"],
+                     "y_kernel_frac": bf["kernels"]["y"]["frac"]},
+    })
+    return leg
+
+
+def bench_flow(args, profile_only=False):
+    """The 128^3 x 300 pure-quaternion FP32 flow snapshots, 30 linear updates
+    of 10 columns, e4m3 operands plus the residual terms, Gaussian, k = 60,
+    l = 121."""
+    grid, n, k, l, block = 128, 300, 60, 121, 10
+    m = grid ** 3
+    log(f"[bench] flow: generating {m}x{n} (3 FP32 planes) on the GPU")
+    a = qs.to_colmajor(synth.flow_snapshots(grid, n, device="cuda"))
+    torch.cuda.synchronize()
+    if profile_only:
+        sk = qs.Sketcher(m, n, k, l, seed=0, embedding="gaussian", input_dtype="f32",
+                         sketch_dtype="fp8", split_terms=2, pure=True, max_block_cols=block)
+        for _ in range(max(1, args.steps)):
+            up, tot, _ = run_pass(sk, a, block)
+            log(f"[bench] flow fp8 pass: updates {up:.2f} ms, total {tot:.2f} ms")
+        sk.close()
+        return {"profile_only": True, "workload": "flow", "update_ms": up, "total_ms": tot}
+    leg = bench_stream_leg(args, "flow", a, m, n, k, l, block, "gaussian", "f32", True,
+                           [("fp8", "fp8", 2), ("bf16", "bf16", 2)], PEAK_BF16)
+    del a
+    torch.cuda.empty_cache()
+    f8 = leg["paths"]["fp8"]
+    y = f8["kernels"]["y"]
+    leg.update({
+        "workload": f"{m}x{n} pure quaternion FP32 flow snapshots, {n // block} linear updates of {block} "
+                    f"columns, e4m3 operands with per-tile scales plus the residual terms, Gaussian "
+                    f"k={k} l={l}, both rangefinders",
+        "ms_per_step": f8["total_ms"], "sketch_tflops": f8["sketch_tflops"],
+        "roofline": {"bound": "hbm", "kernel": "y_mfma_kernel (fp8 + residual, pure)",
+                     "achieved": y.get("achieved_gbs"), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                     "frac": y.get("hbm_frac"), "avg_launch_ms": y["avg_launch_ms"],
+                     "algorithmic_bytes_per_launch": 3 * m * block * 4 + 2 * 4 * m * k * 4},
+    })
+    return leg
 
 
 def bench_extras(args, a, m, n, k, l, block, make):
@@ -357,13 +568,14 @@ def main():
                     help="one bf16 pass only (for rocprofv3 runs)")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CMD_FETCH", "CMD_WRITE"),
                     help="write the W-kernel traffic summary from two rocprofv3 --pmc runs")
-    ap.add_argument("--workload", default="c2", choices=["c2", "batch64"],
-                    help="c2: the 20000 x 15000 streamed matrix (default); batch64: 64 problems batched")
+    ap.add_argument("--workload", default="all", choices=["all", "c2", "batch64", "image", "flow"],
+                    help="all (default): the 20000 x 15000 matrix (headline) plus the image, batch "
+                         "and flow workloads in the same line; or one of them alone")
     ap.add_argument("--summarize-stats", nargs=3, metavar=("DIR", "CMD", "OUT"),
                     help="write a kernel-time summary from a rocprofv3 --stats run")
     args = ap.parse_args()
     if args.summarize_stats:
-        summarize_stats(*args.summarize_stats)
+        summarize_stats(*args.summarize_stats, workload="c2" if args.workload == "all" else args.workload)
         return
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic)
@@ -372,8 +584,19 @@ def main():
         print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     torch.cuda.set_device(0)
-    if args.workload == "batch64":
-        bench_batch(args)
+    others = {"image": bench_image, "batch64": bench_batch, "flow": bench_flow}
+    if args.workload in others:
+        rec = others[args.workload](args, profile_only=args.profile_only)
+        if args.profile_only:
+            print(json.dumps(rec))
+            return
+        line = {"metric": METRIC, "value": rec.get("sketch_tflops", rec.get("sketch_tflops_whole_run")),
+                "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                "ms_per_step": rec["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": "fp8" if args.workload == "flow" else "bf16",
+                "data": "synthetic", "config": {"workload": rec["workload"]},
+                "roofline": rec.get("roofline"), "cpu_baseline": None, "detail": rec}
+        print(json.dumps(line))
         return
     m, n, k, l, block = args.m, args.n, args.k, args.l, args.block
 
@@ -445,13 +668,26 @@ def main():
         del res
 
     extras = None if args.no_extras else bench_extras(args, a, m, n, k, l, block, make)
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(a, m, n, k, l, block, args.cpu_seconds)
+    del a
+    torch.cuda.empty_cache()
+    workloads = None
+    if args.workload == "all":
+        workloads = {}
+        for name, fn in others.items():
+            t0 = time.perf_counter()
+            workloads[name] = fn(args)
+            log(f"[bench] {name} done in {time.perf_counter() - t0:.1f} s")
+            torch.cuda.empty_cache()
 
     bf = out_paths["bf16"]
     # roofline of the dominant kernel (the W product): algorithmic flops per
     # launch = 2 * 16 * m * ncols * l, averaged over the timed launches
     w_ms, w_n = timing["bf16"]["w"]
     y_ms, y_n = timing["bf16"]["y"]
-    nblocks = (n + block - 1) // block
     w_flops_total = 2.0 * 16 * m * n * l * args.steps
     y_flops_total = 2.0 * 16 * m * n * k * args.steps
     w_avg_ms = w_ms / max(w_n, 1)
@@ -473,13 +709,9 @@ def main():
             e = errors.get((name, kind))
             eq[kind]["e_" + name] = e
             eq[kind]["rel_diff_" + name] = (abs(e - ref) / ref) if ref else None
-    cpu = None
-    if not args.no_cpu:
-        log("[bench] CPU oracle baseline")
-        cpu = cpu_baseline(a, m, n, k, l, block, args.cpu_seconds)
     speedup = out_paths["fp32"]["total_ms"] / bf["total_ms"]
     line = {
-        "metric": "one-pass qLRA wall time + sketch TFLOP/s at equal rel. error, BF16/FP8 vs FP32",
+        "metric": METRIC,
         "value": bf["sketch_tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": bf["total_ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
@@ -489,7 +721,7 @@ def main():
         "paths": out_paths, "equal_error": eq,
         "speedup_vs_fp32_wall": speedup,
         "speedup_vs_fp32_wall_fp8": out_paths["fp32"]["total_ms"] / out_paths["fp8"]["total_ms"],
-        "roofline": roofline, "cpu_baseline": cpu, "extras": extras,
+        "roofline": roofline, "cpu_baseline": cpu, "extras": extras, "workloads": workloads,
         "host": {"cpu": platform.processor() or platform.machine(), "cores": os.cpu_count()},
     }
     print(json.dumps(line))

@@ -161,3 +161,54 @@ def test_batch_autotune(sketch, terms):
     assert b2.autotune(devs, reps=0) == (nmt, nj)
     b2.close()
     b.close()
+
+
+# HX of the batch workload against the oracle: the device sketches differ
+# from the oracle's (same operands) by FP32 accumulation only
+BATCH_HX_TOL = 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_batch64_workload_every_problem_vs_oracle():
+    """The 64-problem workload of the benchmark (log-uniform m in [512, 8192]
+    and n in [256, 4096], rank 8..64 with geometric decay, k = 2r,
+    l = 2k + 1, FP32 data, BF16 two-term operands, autotuned tiles), every
+    problem against the oracle's one-pass result on the same operands
+    (Alg. 4): the relative error within 1e-3 of the oracle's (the equal-error
+    criterion) and sampled rows and columns of HX entry by entry (HX is
+    unique, Lemma 4.2)."""
+    from tests.gpu_helpers import hx_margin, sample
+    specs = synth.batch_specs(64)
+    shapes = [(sp["m"], sp["n"], sp["k"], sp["l"], i) for i, sp in enumerate(specs)]
+    mats = [qs.to_colmajor(synth.batch_matrix(sp, i, device="cuda")) for i, sp in enumerate(specs)]
+    b = qs.Batch(shapes, input_dtype="f32", sketch_dtype="bf16", split_terms=2)
+    b.autotune(mats, reps=1)
+    dev = {}
+    for kind in ("pseudo_qr", "pseudo_svd"):
+        qb, xb, reps = b.run(mats, kind)
+        errs = b.rel_error(mats, qb, xb)
+        dev[kind] = ([to_numpy(t) for t in qb], [to_numpy(t) for t in xb], reps, errs)
+        del qb, xb
+    b.close()
+    worst_e, worst_hx = 0.0, 0.0
+    for i, (m, n, k, l, seed) in enumerate(shapes):
+        a = mats[i].double().cpu().numpy()
+        ref = sketch_matrix(a, SketchConfig(m, n, k, l, seed=seed, dtype="bf16", terms=2))
+        rows = sample(m, [0, m - 1], 6, 100 + i)
+        cols = sample(n, [0, n - 1], 6, 200 + i)
+        for kind in ("pseudo_qr", "pseudo_svd"):
+            q, x, reps, errs = dev[kind]
+            h_o, x_o, _ = onepass.qb_stage(ref, kind)
+            e_o = onepass.rel_error(a, h_o, x_o)
+            de = abs(errs[i] - e_o) / e_o
+            mg = hx_margin(q[i], x[i], h_o, x_o, rows, cols)
+            worst_e, worst_hx = max(worst_e, de), max(worst_hx, mg)
+            assert de <= 1e-3, (i, kind, errs[i], e_o)
+            assert mg < BATCH_HX_TOL, (i, kind, mg)
+            if kind == "pseudo_qr":
+                assert reps[i]["kappa"] < 10 and len(reps[i]["eps"]) == 3, (i, reps[i])
+            else:
+                assert reps[i]["orth_defect"] < 1e-10, (i, reps[i])
+        del a, ref
+    print(f"batch64: worst relative error difference {worst_e:.2e} (limit 1e-3), "
+          f"worst HX margin {worst_hx:.2e} (limit {BATCH_HX_TOL:g})", flush=True)

@@ -20,7 +20,7 @@ import torch
 import paper_2404_14783_amd as qs
 import synth
 from oracle import embeddings, lowprec, quaternion as qt
-from tests.gpu_helpers import to_numpy
+from tests.gpu_helpers import assert_elementwise, w_bound, y_bound, to_numpy
 
 pytestmark = pytest.mark.gpu
 
@@ -86,6 +86,9 @@ def test_fullsize_sampled_sketches(a_dev, sketch, terms):
     ey = np.linalg.norm(y_dev - y_ref) / np.linalg.norm(y_ref)
     ew = np.linalg.norm(w_dev - w_ref) / np.linalg.norm(w_ref)
     print(f"{sketch} x{terms}: sampled rel. diff Y {ey:.2e}, W {ew:.2e}", flush=True)
+    # entry by entry: within 8 sqrt(K) u B of the oracle (B = sum of |terms|)
+    assert_elementwise(y_dev, y_ref, y_bound(a_rows, om), 4 * N * terms, f"full-size {sketch} x{terms} Y rows")
+    assert_elementwise(w_dev, w_ref, w_bound(ps, a_cols), 4 * M * terms, f"full-size {sketch} x{terms} W cols")
     assert ey < 1e-5 and ew < 1e-5
 
 

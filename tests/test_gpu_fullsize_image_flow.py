@@ -32,7 +32,7 @@ import torch
 import paper_2404_14783_amd as qs
 import synth
 from oracle import embeddings, lowprec, quaternion as qt
-from tests.gpu_helpers import to_numpy
+from tests.gpu_helpers import assert_elementwise, plane_abs_max, plane_abs_sum, w_bound, y_bound, to_numpy
 
 pytestmark = pytest.mark.gpu
 
@@ -106,12 +106,16 @@ def test_image_sampled_sketches(image_dev):
     a_rows = full_planes(image_dev[:, rows, :].double().cpu().numpy())
     om = embeddings.omega("rademacher", np.arange(IN), IK, 0, "bf16")
     y_ref = qt.hamilton(a_rows, om)
+    by = y_bound(a_rows, om)
     del om
     a_cols = full_planes(image_dev[:, :, cols].double().cpu().numpy())
     ps = embeddings.psi("rademacher", IL, np.arange(IM), 0, "bf16")
     w_ref = qt.hamilton(ps, a_cols)
+    bw = w_bound(ps, a_cols)
     ey, ew = rel(y_dev, y_ref), rel(w_dev, w_ref)
     print(f"image: sampled rel. diff Y {ey:.2e}, W {ew:.2e}", flush=True)
+    assert_elementwise(y_dev, y_ref, by, 3 * IN, "image Y rows")
+    assert_elementwise(w_dev, w_ref, bw, 3 * IM, "image W cols")
     assert ey < accum_tol(3 * IN) and ew < accum_tol(3 * IM)
 
 
@@ -159,9 +163,12 @@ def test_flow_sampled_sketches(flow_dev):
     del y, w
     # rows of Y: A[rows, :] Omega, with e4m3 test matrices
     a_rows = full_planes(flow_dev[:, rows, :].double().cpu().numpy())
-    y_ref = qt.hamilton(a_rows, embeddings.omega("gaussian", np.arange(FN), FK, 0, "fp8"))
+    om = embeddings.omega("gaussian", np.arange(FN), FK, 0, "fp8")
+    y_ref = qt.hamilton(a_rows, om)
+    by = y_bound(a_rows, om)
     # rows of W: Psi[wrows, :] A, accumulated over chunks of rows of A
     w_ref = np.zeros((4, len(wrows), FN))
+    bw = np.zeros((len(wrows), FN))
     chunk = 1 << 18
     for r0 in range(0, FM, chunk):
         r = np.arange(r0, min(FM, r0 + chunk), dtype=np.uint64)
@@ -170,9 +177,13 @@ def test_flow_sampled_sketches(flow_dev):
                                                     embeddings.STREAM_PSI, 0), "fp8")
         a_chunk = full_planes(flow_dev[:, r0:r0 + len(r), :].double().cpu().numpy())
         w_ref += qt.hamilton(ps, a_chunk)
+        bw += plane_abs_max(ps) @ plane_abs_sum(a_chunk)
         del ps, a_chunk
     ey, ew = rel(y_dev, y_ref), rel(w_dev, w_ref)
     print(f"flow: sampled rel. diff Y {ey:.2e}, W {ew:.2e}", flush=True)
+    # e4m3 data plus the residual carried as two bf16 terms: 2^-17 per operand
+    assert_elementwise(y_dev, y_ref, by, 3 * 3 * FN, "flow Y rows", op_rel=2.0 ** -17)
+    assert_elementwise(w_dev, w_ref, bw, 3 * 3 * FM, "flow W rows", op_rel=2.0 ** -17)
     assert ey < accum_tol(3 * FN) and ew < accum_tol(3 * FM)
 
 

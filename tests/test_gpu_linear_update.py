@@ -2,9 +2,11 @@
 through linear sketch updates; both sketches are linear in A) and checkpoint
 / restore of the sketch state, through the C ABI.
 
-Tolerances as in the other parity tests (relative Frobenius norm): FP64
-sketches 1e-12; FP32 accumulation 1e-5 (the scalings by theta and eta add a
-few FP32 roundings per entry, far below that).  The oracle forms the same
+Tolerances as in the other parity tests: entry by entry, within
+8 sqrt(K) u B of the oracle's value (``gpu_helpers.BoundTracker`` carries B
+through the updates; the scalings by theta and eta add one rounding each),
+and the relative Frobenius norm of the difference below 1e-12 (FP64) or
+1e-5 (FP32 accumulation).  The oracle forms the same
 operand values (data split or quantised per update block, test matrices
 rounded) and applies theta and eta in FP64.
 """
@@ -16,7 +18,7 @@ import paper_2404_14783_amd as qs
 import synth
 from oracle import quaternion as qt
 from oracle.sketch import Sketch, SketchConfig
-from tests.gpu_helpers import input_values, rel, to_device, to_numpy
+from tests.gpu_helpers import BoundTracker, input_values, rel, to_device, to_numpy
 
 pytestmark = pytest.mark.gpu
 
@@ -49,27 +51,33 @@ def test_general_linear_updates(sketch, dtype, emb, terms, m, tol):
     sk = qs.Sketcher(m, n, k, l, seed=7, embedding=emb, input_dtype=dtype, sketch_dtype=sketch,
                      split_terms=terms, max_block_cols=block)
     ref = Sketch(oracle_cfg(m, n, k, l, 7, emb, sketch, terms))
+    bt = BoundTracker(ref)
     a = synth.lowrank_plus_noise(m, n, torch.tensor(0.8 ** np.arange(10)), 1e-3, 77).numpy()
     a = input_values(a, dtype)
     dev = to_device(a, dtype)
     for c0 in range(0, n, block):                      # the first pass: plain updates
         sk.update(c0, dev[:, :, c0:c0 + block])
         ref.update(c0, a[:, :, c0:c0 + block])
+        bt.update(c0, a[:, :, c0:c0 + block])
     for theta, eta in STEPS:
         c0 = int(rng.integers(0, n - 1))
         nc = int(min(n - c0, rng.integers(1, block + 1)))
         h = input_values(rng.standard_normal((4, m, nc)), dtype)
         sk.update(c0, to_device(h, dtype), theta=theta, eta=eta)
         ref.update(c0, h, theta=theta, eta=eta)
+        bt.update(c0, h, theta=theta, eta=eta)
     y, w = (to_numpy(t) for t in sk.sketches())
     ey, ew = rel(y, ref.Y), rel(w, ref.W)
     print(f"  rel. diff Y {ey:.2e}, W {ew:.2e}", flush=True)
+    bt.check(y, w, f"linear {sketch}/{dtype}/{emb}/x{terms}")
     assert ey < tol and ew < tol
     assert sk.columns_seen == ref.columns_seen
     # A <- theta A alone
     sk.scale(-0.125)
     ref.scale(-0.125)
+    bt.scale(-0.125)
     y, w = (to_numpy(t) for t in sk.sketches())
+    bt.check(y, w, f"linear+scale {sketch}/{dtype}/{emb}/x{terms}")
     assert rel(y, ref.Y) < tol and rel(w, ref.W) < tol
     sk.close()
 
@@ -161,13 +169,18 @@ def test_row_block_updates(sketch, dtype, emb, terms):
     sk = qs.Sketcher(m, n, k, l, seed=9, embedding=emb, input_dtype=dtype, sketch_dtype=sketch,
                      split_terms=terms, max_block_cols=block)
     ref = Sketch(oracle_cfg(m, n, k, l, 9, emb, sketch, terms))
+    bt = BoundTracker(ref)
     rows = [(0, 1), (1, 300), (300, 700)]
     for c0 in range(0, n, block):
         c1 = min(n, c0 + block)
         for r0, r1 in rows:
             sk.update_block(r0, c0, dev[:, r0:r1, c0:c1])
             update_block(ref, r0, c0, a[:, r0:r1, c0:c1])
+            full = np.zeros((4, m, c1 - c0))
+            full[:, r0:r1, :] = a[:, r0:r1, c0:c1]
+            bt.update(c0, full)
     y, w = (to_numpy(t) for t in sk.sketches())
+    bt.check(y, w, f"row blocks {sketch}/{dtype}/{emb}/x{terms}")
     tol = 1e-12 if sketch == "f64" else 1e-5
     ey, ew = rel(y, ref.Y), rel(w, ref.W)
     print(f"  rel. diff Y {ey:.2e}, W {ew:.2e}", flush=True)

@@ -1,11 +1,13 @@
 """GPU parity of the HIP path with the oracle, through the C ABI.
 
-Tolerances (relative Frobenius norm of the difference):
-  * FP64 sketch: 1e-12 (FP64 rounding of sums of <= 4n products);
-  * FP32 sketch: 1e-5;
-  * BF16 sketch: operands are exact (the oracle forms the same bf16 values);
-    the GPU accumulates in FP32, the oracle in FP64, so the bound is the FP32
-    accumulation error, 1e-5;
+Tolerances:
+  * sketches, entry by entry: every entry of Y and W is a sum of K signed
+    products (K = 4n for Y, 4m for W, times the number of bf16 terms); the
+    device's value must lie within 8 sqrt(K) u B of the oracle's, with B the
+    sum of the absolute values of the terms and u the unit roundoff of the
+    accumulation (2^-53 for FP64, 2^-24 for FP32; ``gpu_helpers``).  The BF16
+    operands are exact (the oracle forms the same bf16 values), so what
+    remains is the accumulation order;
   * test-matrix values: bit-exact for Rademacher and for BF16 rounding of the
     Gaussian, 1e-14 relative or absolute for FP64, 2e-6 (a few FP32 ulp) for
     FP32.
@@ -20,7 +22,8 @@ import torch
 import synth
 from oracle import embeddings, onepass, quaternion as qt
 from oracle.sketch import SketchConfig, sketch_matrix
-from tests.gpu_helpers import input_values, rel, run_sketch, to_numpy
+from tests.gpu_helpers import (check_sketches, error_sensitivity, input_values, oracle_sensitivity, rel,
+                               run_sketch, to_numpy)
 
 pytestmark = pytest.mark.gpu
 
@@ -83,6 +86,7 @@ def test_sketch_parity_ragged(sketch, dtype, emb, terms, tol):
     y, w = (to_numpy(t) for t in sk.sketches())
     cfg = SketchConfig(m, n, k, l, seed=5, embedding=emb, dtype=sketch, terms=terms)
     ref = sketch_matrix(a, cfg, block_cols=block)
+    check_sketches(y, w, ref, a, f"ragged {sketch}/{dtype}/{emb}/x{terms}", block_cols=block)
     assert rel(y, ref.Y) < tol
     assert rel(w, ref.W) < tol
 
@@ -110,8 +114,7 @@ def test_matrix_core_sketch_multitile(sketch, dtype, emb, terms, pure):
     y, w = (to_numpy(t) for t in sk.sketches())
     cfg = SketchConfig(m, n, k, l, seed=21, embedding=emb, dtype=sketch, terms=terms)
     ref = sketch_matrix(a, cfg, block_cols=block)
-    assert rel(y, ref.Y) < 1e-5
-    assert rel(w, ref.W) < 1e-5
+    check_sketches(y, w, ref, a, f"multitile {sketch}/{dtype}/{emb}/x{terms}", block_cols=block)
 
 
 def test_streaming_order_and_pure_input():
@@ -137,49 +140,7 @@ def config1():
 def test_config1_sketches(config1):
     a, ref, sk, _ = config1
     y, w = (to_numpy(t) for t in sk.sketches())
-    assert rel(y, ref.Y) < 1e-12
-    assert rel(w, ref.W) < 1e-12
-
-
-def oracle_sensitivity(ref, kind, rel_pert=1e-15, draws=4):
-    """Relative change of the oracle's kappa / eps when Y is perturbed by a
-    random relative 1e-15, the largest over a few draws (a single draw
-    varies by several times): the scale below which GPU and oracle cannot be
-    expected to agree (these diagnostics depend on the non-unique H)."""
-    out = [_sensitivity_draw(ref, kind, rel_pert, sd) for sd in range(draws)]
-    return tuple(max(o[i] for o in out) for i in range(4))
-
-
-def _sensitivity_draw(ref, kind, rel_pert, seed):
-    from oracle.rangefinders import pseudo_qr, pseudo_svd
-    rng = np.random.default_rng(seed)
-    y2 = ref.Y * (1.0 + rel_pert * rng.standard_normal(ref.Y.shape))
-    proj = lambda z: qt.hamilton(z, qt.pinv(z))
-    if kind == "pseudo_qr":
-        ha, a = pseudo_qr(ref.Y, seed=ref.cfg.seed)
-        hb, b = pseudo_qr(y2, seed=ref.cfg.seed)
-        ek = abs(a["kappa"] - b["kappa"]) / a["kappa"]
-        ee = max(abs(x - y) / x for x, y in zip(a["eps"], b["eps"]))
-        e0 = abs(a["kappa0"] - b["kappa0"]) / a["kappa0"]
-        return ek, ee, e0, qt.fro(proj(ha) - proj(hb))
-    ha, a = pseudo_svd(ref.Y, seed=ref.cfg.seed)
-    hb, b = pseudo_svd(y2, seed=ref.cfg.seed)
-    return abs(a["kappa"] - b["kappa"]) / a["kappa"], 0.0, 0.0, qt.fro(proj(ha) - proj(hb))
-
-
-def error_sensitivity(a, ref, kind, rel_pert=1e-15, seed=1):
-    """Relative change of the oracle's approximation error when Y is
-    perturbed by a random relative 1e-15 (the error depends on H through
-    X = (Psi H)^dagger W, which the ill-conditioned pseudo-QR factor
-    amplifies)."""
-    import copy
-    rng = np.random.default_rng(seed)
-    h0, x0, _ = onepass.qb_stage(ref, kind)
-    e0 = onepass.rel_error(a, h0, x0)
-    r2 = copy.copy(ref)
-    r2.Y = ref.Y * (1.0 + rel_pert * rng.standard_normal(ref.Y.shape))
-    h2, x2, _ = onepass.qb_stage(r2, kind)
-    return abs(onepass.rel_error(a, h2, x2) - e0) / e0
+    check_sketches(y, w, ref, a, "config 1 f64", block_cols=256)
 
 
 @pytest.mark.parametrize("kind", ["pseudo_qr", "pseudo_svd"])
@@ -190,19 +151,32 @@ def test_config1_qb_stage(config1, kind):
     h_o, x_o, info = onepass.qb_stage(ref, kind)
     hx = qt.hamilton(qn, xn)
     hx_o = qt.hamilton(h_o, x_o)
-    assert rel(hx, hx_o) < 1e-9                        # HX is unique (Lemma 4.2)
+    d_hx = rel(hx, hx_o)
     e_gpu = sk.rel_error(dev, q, x)
     e_o = onepass.rel_error(a, h_o, x_o)
-    # agreement to within the oracle's own change under a rounding-level
-    # perturbation of its input (the reading used for kappa and eps below)
-    assert abs(e_gpu - e_o) <= max(1e-6, 100 * error_sensitivity(a, ref, kind)) * e_o
+    # the oracle's own change under a rounding-level perturbation of its
+    # input: the scale of agreement that can be asked of kappa, eps and the
+    # error, which depend on the non-unique H
+    es = error_sensitivity(a, ref, kind)
+    sk_, se_, s0_, sr_ = oracle_sensitivity(ref, kind)
+    kap = rep["kappa"]
+    d_e = abs(e_gpu - e_o) / e_o
+    d_k = abs(kap - info["kappa"]) / info["kappa"]
+    print(f"config 1 {kind}: |HX - HX_o|/|HX_o| {d_hx:.2e}; error diff {d_e:.2e} "
+          f"(oracle sensitivity {es:.2e}, ratio {d_e / max(es, 1e-300):.3g}); kappa diff {d_k:.2e} "
+          f"(sensitivity {sk_:.2e}, ratio {d_k / max(sk_, 1e-300):.3g})", flush=True)
+    if kind == "pseudo_qr":
+        d_eps = max(abs(u - v) / v for u, v in zip(rep["eps"], info["eps"]))
+        d_k0 = abs(rep["kappa_initial"] - info["kappa0"]) / info["kappa0"]
+        print(f"  eps diff {d_eps:.2e} (sensitivity {se_:.2e}, ratio {d_eps / max(se_, 1e-300):.3g}); "
+              f"kappa0 diff {d_k0:.2e} (sensitivity {s0_:.2e})", flush=True)
+    assert d_hx < 1e-9                                 # HX is unique (Lemma 4.2)
+    assert d_e <= max(1e-6, 100 * es)
     np.testing.assert_allclose(e_gpu, onepass.rel_error(a, qn, xn), rtol=1e-9)
     # same range as the oracle's factor, up to the oracle's own sensitivity
     # (the paper notes pseudo-QR's weaker range precision, Section 3.3)
-    sk_, se_, s0_, sr_ = oracle_sensitivity(ref, kind)
     proj = lambda z: qt.hamilton(z, qt.pinv(z))
     assert qt.fro(proj(qn) - proj(h_o)) < max(1e-8, 10 * sr_)
-    kap = rep["kappa"]
     np.testing.assert_allclose(kap, info["kappa"], rtol=max(1e-9, 100 * sk_))
     if kind == "pseudo_qr":
         assert kap < 10 and len(rep["eps"]) == 3

@@ -72,7 +72,7 @@ def test_rangefinders_over_kappa(factors, kappa):
             print(f"  {kind}: orth {rep['orth_defect']:.1e}, t_bad {rep['t_bad']} "
                   f"(oracle {info['t_bad']}), capture {e_dev:.1e} (oracle {e_ref:.1e})", flush=True)
             assert rep["orth_defect"] < 1e-10
-            assert abs(rep["t_bad"] - info["t_bad"]) <= 1
+            assert rep["t_bad"] == info["t_bad"]
             assert e_dev < 1e-8 and e_ref < 1e-8
         else:
             h_ref, info = pseudo_qr(y)

@@ -150,3 +150,28 @@ def test_planted_box_muller_error_is_caught(monkeypatch):
     monkeypatch.setattr(embeddings.np, "log", half_log)
     g = embeddings.gaussian_entries(np.arange(20000)[:, None], np.arange(1)[None, :], 0, 11)
     assert np.abs(g.reshape(4, -1).var(axis=1) - 1).max() > 0.2
+
+
+def test_diag_f_distribution():
+    """The bad-part scaling of pseudo-SVD draws f_j from Uniform(0, 1) + 1
+    (eq. sudoSVD_Hbdiagf): every value lies in (1, 2), the sample mean and
+    variance match 3/2 and 1/12, the values are distinct (the point of the
+    scaling is to avoid repeated singular values), and the sequence comes
+    from its own Philox stream (a different seed gives different values)."""
+    n = 200000
+    f = embeddings.diag_f(n, 5)
+    assert f.shape == (n,)
+    assert np.all(f > 1.0) and np.all(f < 2.0)
+    sd = np.sqrt(1.0 / 12.0 / n)
+    assert abs(f.mean() - 1.5) < 6 * sd
+    # variance of a uniform: 1/12; its sampling sd is sqrt(1/180 / n)
+    assert abs(f.var() - 1.0 / 12.0) < 6 * np.sqrt(1.0 / 180.0 / n)
+    # distinct over the sizes a repair uses (2t <= 2k columns)
+    assert np.unique(f[:4096]).size == 4096
+    # the empirical distribution of f - 1 is uniform on (0, 1): Kolmogorov
+    # distance below 1.95 / sqrt(n) (the 0.1% point)
+    u = np.sort(f - 1.0)
+    ks = np.max(np.maximum(np.arange(1, n + 1) / n - u, u - np.arange(n) / n))
+    assert ks < 1.95 / np.sqrt(n)
+    assert not np.array_equal(embeddings.diag_f(64, 5), embeddings.diag_f(64, 6))
+    np.testing.assert_array_equal(embeddings.diag_f(64, 5), f[:64])
