@@ -218,6 +218,23 @@ qsk_status qsketch_project(qsk_ctx *ctx, double *const Q[4], int64_t ldq, int64_
                            int64_t ncols, const void *const planes[4], int64_t ld,
                            double *const X[4], int64_t ldx);
 
+/* qsketch_project for callers that cannot allocate device memory (code
+   under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc): the same arguments, result and errors as qsketch_project, but
+   no call to hipMalloc, hipFree or any allocating routine.  Its work
+   memory is a static 32 MiB device array of the library, one per device,
+   held until the process ends: the zeroed real plane of a pure-quaternion
+   block (cleared on every call) and the partial sums of the split
+   contraction (the split shrinks to what the rest of the array holds, down
+   to none).  A pure-quaternion block needing more than 32 MiB for its zero
+   plane ((ncols - 1) ld + m elements of input_dtype) is rejected with
+   QSK_E_ARG.  All calls on one device share the array: calls that overlap
+   on one device (different streams or contexts without ordering between
+   them) race and give undefined results.  Stream-ordered. */
+qsk_status qsketch_project_noalloc(qsk_ctx *ctx, double *const Q[4], int64_t ldq, int64_t col0,
+                                   int64_t ncols, const void *const planes[4], int64_t ld,
+                                   double *const X[4], int64_t ldx);
+
 /* Truncation stage (Alg. 5): the rank-r QSVD of the approximation Q X,
        Q X ~= (Q U_r) diag(sigma) V_r^*,
    with (U, Sigma, V) the QSVD of X (k x n).  Computed from the eigenpairs of

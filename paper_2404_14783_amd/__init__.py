@@ -92,6 +92,8 @@ def _load():
     lib.qsketch_truncate.restype = i32
     lib.qsketch_project.argtypes = [vp, _P4, i64, i64, i64, _P4, i64, _P4, i64]
     lib.qsketch_project.restype = i32
+    lib.qsketch_project_noalloc.argtypes = [vp, _P4, i64, i64, i64, _P4, i64, _P4, i64]
+    lib.qsketch_project_noalloc.restype = i32
     lib.qsketch_finalize.restype = i32
     lib.qsketch_sketches.argtypes = [vp, _P4, i64, vp, i64]
     lib.qsketch_sketches.restype = i32
@@ -320,10 +322,11 @@ class Sketcher:
                                                ctypes.c_void_p(sig.data_ptr()), vp_, ldv))
         return hu, sig, v
 
-    def project(self, col0, block, q, x=None):
+    def project(self, col0, block, q, x=None, noalloc=False):
         """Second pass of the two-pass variant: X[:, J] = Q^* block for the
         columns J = col0 .. col0 + ncols - 1; X (4, k, n) FP64 is created
-        (zeros) when not given.  Returns X."""
+        (zeros) when not given.  Returns X.  noalloc=True calls
+        qsketch_project_noalloc (no device allocation in the library)."""
         if block.dtype != TORCH_DTYPE[self.input_dtype]:
             raise TypeError(f"block dtype {block.dtype} != input dtype {self.input_dtype}")
         if x is None:
@@ -331,8 +334,8 @@ class Sketcher:
         bp, ld = _plane_ptrs(block, self.pure)
         qp, ldq = _plane_ptrs(q, False)
         xp, ldx = _plane_ptrs(x, False)
-        self._check(self._lib.qsketch_project(self._ctx, qp, ldq, int(col0), int(block.shape[2]), bp, ld,
-                                              xp, ldx))
+        fn = self._lib.qsketch_project_noalloc if noalloc else self._lib.qsketch_project
+        self._check(fn(self._ctx, qp, ldq, int(col0), int(block.shape[2]), bp, ld, xp, ldx))
         return x
 
     def sketches(self):

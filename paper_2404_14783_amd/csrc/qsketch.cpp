@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -13,9 +14,36 @@
 #include "../../include/qsketch.h"
 #include "qsk_kernels.hpp"
 
+// Scratch of the allocation-free projection (qsketch_project_noalloc): the
+// zeroed real plane of a pure-quaternion block, then the partial sums of the
+// split contraction.  The module holds one copy per device until the process
+// ends; host code reaches it only through the address hipGetSymbolAddress
+// returns on that device (the array's name is a host-side stand-in).
+constexpr size_t QSK_NOALLOC_SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[QSK_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 using qsk::SmallStatus;
+
+// Device address of `scratch` per device, looked up once per device with
+// that device current.
+constexpr int QSK_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[QSK_MAX_DEVICES] = {};
+
+hipError_t scratch_address(int dev, void **out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= QSK_MAX_DEVICES) return hipErrorInvalidDevice;
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 struct Buf {
   void *p = nullptr;
@@ -76,6 +104,7 @@ struct qsk_ctx {
   size_t proj_part_bytes = 0;
   void *pad = nullptr;                 // full-height block (4 planes, m x max_block_cols) for
   size_t pad_bytes = 0;                // qsketch_update_block
+  void *noalloc_scratch = nullptr;     // this device's `scratch` (qsketch_project_noalloc)
 };
 
 namespace {
@@ -274,7 +303,12 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   ctx->k1 = (uint32_t)(c.seed >> 32);
   const char *env = std::getenv("QSK_NO_MFMA");
   ctx->use_mfma = (env && env[0] == '1') ? 0 : 1;
-  (void)hipGetDevice(&ctx->device);
+  if (hipGetDevice(&ctx->device) != hipSuccess ||
+      scratch_address(ctx->device, &ctx->noalloc_scratch) != hipSuccess) {
+    (void)hipGetLastError();
+    delete ctx;
+    return QSK_E_HIP;
+  }
 
   const int64_t m = c.m, n = c.n, k = c.k, l = c.l;
   const size_t kk = (size_t)k * k * 4;
@@ -814,6 +848,47 @@ qsk_status qsketch_project(qsk_ctx *ctx, double *const Q[4], int64_t ldq, int64_
   for (int p = 0; p < 4; ++p) xo[p] = X[p] + col0 * ldx;
   HIPCHK(ctx, qsk::launch_project(ctx->stream, Q, ldq, c.input_dtype, b, ld, c.m, c.k, ncols, xo, ldx,
                                   ctx->proj_part, (int64_t)(ctx->proj_part_bytes / 8)));
+  return QSK_OK;
+}
+
+qsk_status qsketch_project_noalloc(qsk_ctx *ctx, double *const Q[4], int64_t ldq, int64_t col0,
+                                   int64_t ncols, const void *const planes[4], int64_t ld,
+                                   double *const X[4], int64_t ldx) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  const qsk_config &c = ctx->cfg;
+  qsk_status st = check_block(ctx, col0, ncols, planes, ld);
+  if (st != QSK_OK) return st;
+  if (!Q || !X) return fail_arg(ctx, "Q/X NULL");
+  for (int p = 0; p < 4; ++p)
+    if (!Q[p] || !X[p]) return fail_arg(ctx, "NULL Q/X plane");
+  if (ldq < c.m || ldx < c.k) return fail_arg(ctx, "leading dimension too small");
+  const size_t es = c.input_dtype == QSK_F64 ? 8 : c.input_dtype == QSK_F32 ? 4 : 2;
+  unsigned char *base = (unsigned char *)ctx->noalloc_scratch;
+  size_t used = 0;
+  const void *b[4];
+  for (int p = 0; p < 4; ++p) b[p] = planes[p];
+  if (c.pure) {
+    // the real plane of a pure quaternion block is zero: a zeroed stretch of
+    // the scratch of the block's shape stands in for it (cleared on every
+    // call: the previous call may have left partial sums there)
+    const size_t need = ((size_t)(ncols - 1) * ld + c.m) * es;
+    const size_t rounded = (need + 255) / 256 * 256;
+    if (rounded > QSK_NOALLOC_SCRATCH_BYTES)
+      return fail_arg(ctx, "qsketch_project_noalloc: a pure-quaternion block needs a zero real plane of "
+                           "((ncols - 1) ld + m) elements, more than the 32 MiB static scratch holds");
+    HIPCHK(ctx, qsk::launch_scale(ctx->stream, 0, base, (int64_t)(rounded / 8), 0.0));
+    b[0] = base;
+    used = rounded;
+  }
+  // partial sums of the split contraction in the rest of the scratch (the
+  // split shrinks to what fits, down to none)
+  double *part = (double *)(base + used);
+  const int64_t part_elems = (int64_t)((QSK_NOALLOC_SCRATCH_BYTES - used) / 8);
+  double *xo[4];
+  for (int p = 0; p < 4; ++p) xo[p] = X[p] + col0 * ldx;
+  HIPCHK(ctx, qsk::launch_project(ctx->stream, Q, ldq, c.input_dtype, b, ld, c.m, c.k, ncols, xo, ldx, part,
+                                  part_elems));
   return QSK_OK;
 }
 
