@@ -308,11 +308,13 @@ def bench_batch(args, profile_only=False):
             out[f"{name}_{kind}_ms"] = ms
             log(f"[bench] batch {name} {kind}: {ms:.2f} ms per run")
         b.close()
-    # the GPU FP64 path for every problem: the equal-error reference
+    # the GPU FP64 path for every problem, with the bf16-rounded test
+    # matrices of the BF16 path: the equal-error reference
     worst = 0.0
     for i in range(len(shapes)):
         m, n, k, l, seed = shapes[i]
-        sk = qs.Sketcher(m, n, k, l, seed=seed, input_dtype="f32", sketch_dtype="f64", max_block_cols=n)
+        sk = qs.Sketcher(m, n, k, l, seed=seed, input_dtype="f32", sketch_dtype="f64", max_block_cols=n,
+                         embedding_round="bf16")
         sk.update(0, mats[i])
         for kind in ("pseudo_qr", "pseudo_svd"):
             q, x, _ = sk.finalize(kind)
@@ -378,33 +380,53 @@ def kernel_rooflines(timing, m, n, k, l, pure, steps, peak, y_bytes_per_update=N
     return out
 
 
-def bench_stream_leg(args, label, a, m, n, k, l, block, emb, input_dtype, pure, paths, peak):
-    """One streamed workload: the GPU FP64 path (untimed, the error
-    reference), then each low-precision path timed; returns its record."""
+EMB_ROUND = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}
+
+
+def fp64_reference(a, m, n, k, l, block, emb, input_dtype, pure, rnd):
+    """Relative errors of the GPU FP64 path (both rangefinders) with the
+    test matrices rounded to `rnd` as the low-precision path uses them: the
+    equal-error reference.  The FP64 result does not depend on the column
+    blocking (linear updates), so it streams in blocks of `block`."""
+    sk = qs.Sketcher(m, n, k, l, seed=0, embedding=emb, input_dtype=input_dtype, sketch_dtype="f64",
+                     pure=pure, max_block_cols=block, embedding_round=rnd)
+    up, tot, r = run_pass(sk, a, block)
+    errs = {kind: sk.rel_error(a, q, x) for kind, (q, x, rep) in r.items()}
+    sk.close()
+    return errs, {"update_ms": up, "total_ms": tot, "embedding_round": rnd}
+
+
+def bench_stream_leg(args, label, a, m, n, k, l, block, emb, input_dtype, pure, paths, peak,
+                     ref_block=None):
+    """One streamed workload: each low-precision path timed, and the GPU FP64
+    path (untimed) with the same rounded test matrices as the reference of
+    its equal-error comparison; returns the workload's record."""
     res = {}
     errors = {}
     flops = sketch_flops(m, n, k, l, pure)
-    log(f"[bench] {label}: FP64 reference pass (untimed)")
-    sk = qs.Sketcher(m, n, k, l, seed=0, embedding=emb, input_dtype=input_dtype, sketch_dtype="f64",
-                     pure=pure, max_block_cols=block)
-    up, tot, r = run_pass(sk, a, block)
-    for kind, (q, x, rep) in r.items():
-        errors[("fp64", kind)] = sk.rel_error(a, q, x)
-    res["fp64"] = {"update_ms": up, "total_ms": tot}
-    sk.close()
-    del r
-    for name, sketch, terms in paths:
+    refs = {}
+    for path in paths:
+        name, sketch, terms = path[:3]
+        coalesce = path[3] if len(path) > 3 else 0
+        base = name.split("_")[0]
+        rnd = "f64" if emb == "rademacher" else EMB_ROUND[base]      # +-1 is exact in every format
+        if rnd not in refs:
+            log(f"[bench] {label}: FP64 reference pass, test matrices rounded to {rnd} (untimed)")
+            refs[rnd] = fp64_reference(a, m, n, k, l, ref_block or block, emb, input_dtype, pure, rnd)
+        res["fp64_" + rnd] = refs[rnd][1]
         sk = qs.Sketcher(m, n, k, l, seed=0, embedding=emb, input_dtype=input_dtype, sketch_dtype=sketch,
-                         split_terms=terms, pure=pure, max_block_cols=block)
+                         split_terms=terms, pure=pure, max_block_cols=block, coalesce_cols=coalesce)
         up, tot, r, timing = timed_passes(sk, a, block, args)
         rec = {"update_ms": up, "total_ms": tot, "sketch_tflops": flops / (up * 1e-3) / 1e12,
-               "terms": terms, "kernels_ms": {kk: v[0] / args.steps for kk, v in timing.items()}}
+               "terms": terms, "coalesce_cols": coalesce,
+               "kernels_ms": {kk: v[0] / args.steps for kk, v in timing.items()}}
         for kind, (q, x, rep) in r.items():
             errors[(name, kind)] = sk.rel_error(a, q, x)
             rec[kind + "_kappa"] = rep["kappa"]
-        nupd = (n + block - 1) // block
+        eff = coalesce if coalesce else block          # columns per sketch product
+        nupd = (n + eff - 1) // eff
         ybytes = None
-        if block < 64:
+        if eff < 64:
             # streamed in thin blocks: Y's read-modify-write dominates the traffic
             ybytes = (3 if pure else 4) * m * (n / nupd) * (4 if input_dtype == "f32" else 2) + 2 * 4 * m * k * 4
         rec["kernels"] = kernel_rooflines(timing, m, n, k, l, pure, args.steps, peak, ybytes, nupd)
@@ -415,10 +437,13 @@ def bench_stream_leg(args, label, a, m, n, k, l, block, emb, input_dtype, pure, 
         del r
     eq = {}
     for kind in ("pseudo_qr", "pseudo_svd"):
-        ref = errors[("fp64", kind)]
-        eq[kind] = {"e_fp64": ref}
-        for name, _, _ in paths:
+        eq[kind] = {}
+        for path in paths:
+            name = path[0]
+            rnd = "f64" if emb == "rademacher" else EMB_ROUND[name.split("_")[0]]
+            ref = refs[rnd][0][kind]
             e = errors[(name, kind)]
+            eq[kind]["e_fp64_" + rnd] = ref
             eq[kind]["e_" + name] = e
             eq[kind]["rel_diff_" + name] = abs(e - ref) / ref if ref else None
     return {"paths": res, "equal_error": eq, "sketch_flops": flops}
@@ -468,27 +493,34 @@ def bench_flow(args, profile_only=False):
     torch.cuda.synchronize()
     if profile_only:
         sk = qs.Sketcher(m, n, k, l, seed=0, embedding="gaussian", input_dtype="f32",
-                         sketch_dtype="fp8", split_terms=2, pure=True, max_block_cols=block)
+                         sketch_dtype="fp8", split_terms=2, pure=True, max_block_cols=block,
+                         coalesce_cols=args.coalesce)
         for _ in range(max(1, args.steps)):
             up, tot, _ = run_pass(sk, a, block)
             log(f"[bench] flow fp8 pass: updates {up:.2f} ms, total {tot:.2f} ms")
         sk.close()
         return {"profile_only": True, "workload": "flow", "update_ms": up, "total_ms": tot}
+    # per update, and with the updates gathered into blocks of `coalesce`
+    # columns before the products (the linear updates commute)
+    co = args.coalesce
     leg = bench_stream_leg(args, "flow", a, m, n, k, l, block, "gaussian", "f32", True,
-                           [("fp8", "fp8", 2), ("bf16", "bf16", 2)], PEAK_BF16)
+                           [("fp8", "fp8", 2), ("fp8_coalesced", "fp8", 2, co),
+                            ("bf16", "bf16", 2), ("bf16_coalesced", "bf16", 2, co)],
+                           PEAK_BF16, ref_block=n)
     del a
     torch.cuda.empty_cache()
-    f8 = leg["paths"]["fp8"]
+    f8 = leg["paths"]["fp8_coalesced"]
     y = f8["kernels"]["y"]
     leg.update({
         "workload": f"{m}x{n} pure quaternion FP32 flow snapshots, {n // block} linear updates of {block} "
-                    f"columns, e4m3 operands with per-tile scales plus the residual terms, Gaussian "
-                    f"k={k} l={l}, both rangefinders",
+                    f"columns gathered into blocks of {co} before the products, e4m3 operands with "
+                    f"per-tile scales plus the residual terms, Gaussian k={k} l={l}, both rangefinders",
         "ms_per_step": f8["total_ms"], "sketch_tflops": f8["sketch_tflops"],
-        "roofline": {"bound": "hbm", "kernel": "y_mfma_kernel (fp8 + residual, pure)",
-                     "achieved": y.get("achieved_gbs"), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                     "frac": y.get("hbm_frac"), "avg_launch_ms": y["avg_launch_ms"],
-                     "algorithmic_bytes_per_launch": 3 * m * block * 4 + 2 * 4 * m * k * 4},
+        "roofline": {"bound": "mfma", "kernel": "w_mfma_kernel (fp8 + residual, pure, gathered blocks)",
+                     "achieved": f8["kernels"]["w"]["achieved_tflops"], "peak": PEAK_BF16 / 1e12,
+                     "unit": "TFLOP/s", "frac": f8["kernels"]["w"]["frac"],
+                     "avg_launch_ms": f8["kernels"]["w"]["avg_launch_ms"],
+                     "per_update_y_hbm_frac": leg["paths"]["fp8"]["kernels"]["y"].get("hbm_frac")},
     })
     return leg
 
@@ -564,6 +596,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the general-update and two-pass measurements")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--coalesce", type=int, default=150,
+                    help="flow workload: columns gathered per sketch product (coalesce_cols)")
     ap.add_argument("--profile-only", action="store_true",
                     help="one bf16 pass only (for rocprofv3 runs)")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CMD_FETCH", "CMD_WRITE"),
@@ -627,18 +661,16 @@ def main():
     errors = {}
     out_paths = {}
     if not args.no_fp64:
-        log("[bench] FP64 reference pass (untimed)")
-        sk64 = qs.Sketcher(m, n, k, l, seed=0, embedding="gaussian", input_dtype="f32",
-                           sketch_dtype="f64", max_block_cols=block)
-        t0 = time.perf_counter()
-        up, tot, res = run_pass(sk64, a, block)
-        for kind, (q, x, rep) in res.items():
-            errors[("fp64", kind)] = sk64.rel_error(a, q, x)
-        out_paths["fp64"] = {"update_ms": up, "total_ms": tot}
-        log(f"[bench] fp64: updates {up:.1f} ms, total {tot:.1f} ms, errors "
-            f"{[errors[('fp64', kd)] for kd in res]} ({time.perf_counter() - t0:.1f} s)")
-        sk64.close()
-        del res
+        # the FP64 path with the unrounded test matrices, and with the
+        # rounded ones of each low-precision path (the equal-error references)
+        for rnd in ("f64", "f32", "bf16", "fp8"):
+            t0 = time.perf_counter()
+            errs, rec = fp64_reference(a, m, n, k, l, block, "gaussian", "f32", False, rnd)
+            for kind, e in errs.items():
+                errors[("fp64_" + rnd, kind)] = e
+            out_paths["fp64_" + rnd] = rec
+            log(f"[bench] fp64 ({rnd} test matrices): updates {rec['update_ms']:.1f} ms, total "
+                f"{rec['total_ms']:.1f} ms, errors {list(errs.values())} ({time.perf_counter() - t0:.1f} s)")
 
     # fp8: e4m3 data with per-tile scales plus a two-term residual correction
     paths = [("fp32", "f32", 1), ("bf16", "bf16", args.terms), ("fp8", "fp8", 2)]
@@ -703,12 +735,17 @@ def main():
 
     eq = {}
     for kind in ("pseudo_qr", "pseudo_svd"):
-        ref = errors.get(("fp64", kind))
-        eq[kind] = {"e_fp64": ref}
+        eq[kind] = {"e_fp64": errors.get(("fp64_f64", kind))}
         for name, _, _ in paths:
+            # against the FP64 path with the same rounded test matrices
+            # (and, for context, against the unrounded ones)
+            ref = errors.get(("fp64_" + EMB_ROUND[name], kind))
+            ref0 = errors.get(("fp64_f64", kind))
             e = errors.get((name, kind))
+            eq[kind]["e_fp64_" + EMB_ROUND[name]] = ref
             eq[kind]["e_" + name] = e
             eq[kind]["rel_diff_" + name] = (abs(e - ref) / ref) if ref else None
+            eq[kind]["rel_diff_unrounded_" + name] = (abs(e - ref0) / ref0) if ref0 else None
     speedup = out_paths["fp32"]["total_ms"] / bf["total_ms"]
     line = {
         "metric": METRIC,

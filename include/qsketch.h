@@ -112,6 +112,25 @@ typedef struct {
   int32_t y_only;          /* 1: keep Y only (the two-pass variant): W is neither stored nor
                               updated, qsketch_finalize runs with X == NULL, and
                               qsketch_project forms X in a second pass over A.  Not for batches. */
+  int32_t embedding_round; /* QSK_F64 sketches only: the test matrices take the values of this
+                              format (QSK_F32, QSK_BF16 or QSK_FP8_E4M3: the FP64 draw rounded
+                              once, as a sketch of that format uses them); QSK_F64 (0, the
+                              default) keeps them unrounded.  An FP64 sketch with the test
+                              matrices of a low-precision one is the reference of the
+                              equal-error comparison (a rounded Gaussian matrix is still an
+                              entry-independent sub-Gaussian test matrix, Def. 4.2).  Must be 0
+                              for other sketch formats. */
+  int32_t coalesce_cols;   /* 0 (default): every qsketch_update runs the sketch products on its
+                              block.  c > 0: qsketch_update copies a block narrower than c that
+                              continues the pending columns (col0 = first pending column +
+                              pending count) into a context buffer of c columns and runs the
+                              products once the buffer is full, or when another call needs the
+                              sketches (finalize, sketches, scale, a general or sub-block
+                              update, a non-contiguous or wide block).  The sketches are linear
+                              in A, so the result is the same up to rounding order; the buffer
+                              (planes x m x c elements of input_dtype) trades memory for
+                              fewer read-modify-writes of Y.  In the FP8 format the per-tile
+                              scales are those of the gathered block.  Not for batches. */
 } qsk_config;
 
 typedef struct {
@@ -293,8 +312,9 @@ void *qsketch_stream(const qsk_ctx *ctx);
 
    All configurations must share embedding, input_dtype, sketch_dtype (QSK_BF16
    or QSK_F32: the matrix-core path), pure, split_terms, n_correction and
-   n_power; m, n, k, l and seed may differ.  max_block_cols is ignored.  Test
-   matrices are drawn and staged once, at init. */
+   n_power; m, n, k, l and seed may differ.  max_block_cols is ignored;
+   y_only, embedding_round and coalesce_cols must be 0.  Test matrices are drawn and staged
+   once, at init. */
 typedef struct qsk_batch qsk_batch;
 
 /* Validate the configurations and allocate every problem's workspace on the

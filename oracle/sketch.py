@@ -32,10 +32,13 @@ class SketchConfig:
     operands 'f64' | 'f32' | 'bf16' | 'fp8'; terms: number of bf16 terms of
     the residual split of the data (bf16 only); fp8_block: tile edge of the
     power-of-two fp8 scales; fp8_residual: add the exact FP32 residual of
-    the fp8 quantisation as a second term."""
+    the fp8 quantisation as a second term; embedding_dtype: the format of the
+    test-matrix values when it differs from the operand dtype (an FP64 sketch
+    with the rounded test matrices of a low-precision one: a rounded Gaussian
+    matrix is still an entry-independent sub-Gaussian test matrix, Def. 4.2)."""
 
     def __init__(self, m, n, k, l, seed=0, embedding="gaussian", dtype="f64",
-                 terms=1, fp8_block=32, fp8_residual=True):
+                 terms=1, fp8_block=32, fp8_residual=True, embedding_dtype=None):
         if not (1 <= k <= l <= min(m, n)):
             raise ValueError("need 1 <= k <= l <= min(m, n)")
         self.m, self.n, self.k, self.l = int(m), int(n), int(k), int(l)
@@ -45,6 +48,7 @@ class SketchConfig:
         self.terms = int(terms)
         self.fp8_block = int(fp8_block)
         self.fp8_residual = bool(fp8_residual)
+        self.embedding_dtype = embedding_dtype or dtype
 
 
 def data_operand(block, cfg):
@@ -79,12 +83,12 @@ class Sketch:
         """Psi (l x m) as the sketch uses it (rounded to the operand dtype)."""
         if self._psi is None:
             c = self.cfg
-            self._psi = embeddings.psi(c.embedding, c.l, np.arange(c.m), c.seed, c.dtype)
+            self._psi = embeddings.psi(c.embedding, c.l, np.arange(c.m), c.seed, c.embedding_dtype)
         return self._psi
 
     def omega_rows(self, col0, ncols):
         c = self.cfg
-        return embeddings.omega(c.embedding, np.arange(col0, col0 + ncols), c.k, c.seed, c.dtype)
+        return embeddings.omega(c.embedding, np.arange(col0, col0 + ncols), c.k, c.seed, c.embedding_dtype)
 
     def scale(self, theta):
         """A <- theta A, so Y <- theta Y and W <- theta W."""

@@ -39,7 +39,8 @@ class QskConfig(ctypes.Structure):
         ("sketch_dtype", ctypes.c_int32), ("pure", ctypes.c_int32),
         ("split_terms", ctypes.c_int32), ("n_correction", ctypes.c_int32),
         ("n_power", ctypes.c_int32), ("max_block_cols", ctypes.c_int64),
-        ("y_only", ctypes.c_int32),
+        ("y_only", ctypes.c_int32), ("embedding_round", ctypes.c_int32),
+        ("coalesce_cols", ctypes.c_int32),
     ]
 
 
@@ -181,7 +182,7 @@ class Sketcher:
 
     def __init__(self, m, n, k, l, seed=0, embedding="gaussian", input_dtype="f64",
                  sketch_dtype="f64", pure=False, split_terms=1, n_correction=3, n_power=3,
-                 max_block_cols=0, y_only=False, stream=None):
+                 max_block_cols=0, y_only=False, embedding_round="f64", coalesce_cols=0, stream=None):
         lib = _load()
         cfg = QskConfig()
         lib.qsketch_config_default(ctypes.byref(cfg))
@@ -196,6 +197,8 @@ class Sketcher:
         cfg.n_power = int(n_power)
         cfg.max_block_cols = int(max_block_cols)
         cfg.y_only = 1 if y_only else 0
+        cfg.embedding_round = DTYPES[embedding_round]
+        cfg.coalesce_cols = int(coalesce_cols)
         self.y_only = bool(y_only)
         self.m, self.n, self.k, self.l = cfg.m, cfg.n, cfg.k, cfg.l
         self.pure = bool(pure)
@@ -207,7 +210,8 @@ class Sketcher:
                             input_dtype=input_dtype, sketch_dtype=sketch_dtype, pure=self.pure,
                             split_terms=int(split_terms), n_correction=int(n_correction),
                             n_power=int(n_power), max_block_cols=int(max_block_cols),
-                            y_only=bool(y_only))
+                            y_only=bool(y_only), embedding_round=embedding_round,
+                            coalesce_cols=int(coalesce_cols))
         self.columns_seen = 0
         self._ctx = ctypes.c_void_p()
         st = lib.qsketch_init(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),

@@ -838,7 +838,7 @@ qsk_status qsketch_batch_init(int32_t count, const qsk_config *cfgs, void *hip_s
     if (c.sketch_dtype < QSK_F64 || c.sketch_dtype > QSK_FP8_E4M3) return QSK_E_ARG;
     if (c.n_correction < 0 || c.n_correction > 8 || c.n_power < 1 || c.n_power > 64) return QSK_E_ARG;
     if (c.sketch_dtype == QSK_BF16 && (c.split_terms < 1 || c.split_terms > 3)) return QSK_E_ARG;
-    if (c.y_only) return QSK_E_ARG;
+    if (c.y_only || c.embedding_round != QSK_F64 || c.coalesce_cols != 0) return QSK_E_ARG;
     if (c.embedding != c0.embedding || c.input_dtype != c0.input_dtype ||
         c.sketch_dtype != c0.sketch_dtype || c.pure != c0.pure ||
         (c.sketch_dtype == QSK_BF16 && c.split_terms != c0.split_terms) ||

@@ -37,6 +37,7 @@ struct SketchArgs {
   int psi_ready;         // the staging buffer already holds Psi (it does not change)
   double eta = 1.0;      // scale of the products: Y += eta H Omega_J, W[:, J] += eta Psi H
   int skip_w = 0;        // Y only: no Psi staging, no W product
+  int emode = -1;        // format of the test-matrix values (MODE_*); -1: that of `mode`
   // optional timing: events[2 * kernel] before, [2 * kernel + 1] after (may be null)
   hipEvent_t *events;
 };

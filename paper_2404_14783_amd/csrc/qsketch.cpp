@@ -2,6 +2,7 @@
 // stream-ordered launches of the sketch update and of the FP64 QB stage.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -59,6 +60,7 @@ struct qsk_ctx {
   bool poisoned = false;
   std::string last_error;
   int mode = 0;            // qsk::MODE_*
+  int emode = 0;           // qsk::MODE_* of the test-matrix values
   size_t ts = 8;           // bytes per Y/W element
   int64_t maxcols = 0;
   int64_t columns_seen = 0;
@@ -105,6 +107,12 @@ struct qsk_ctx {
   void *pad = nullptr;                 // full-height block (4 planes, m x max_block_cols) for
   size_t pad_bytes = 0;                // qsketch_update_block
   void *noalloc_scratch = nullptr;     // this device's `scratch` (qsketch_project_noalloc)
+  // coalescing of thin updates (cfg.coalesce_cols > 0): pending columns
+  // pend_col0 .. pend_col0 + pend_ncols - 1, one plane of m x coalesce_cols
+  // input elements after another (ld = m)
+  void *pend = nullptr;
+  int64_t pend_col0 = 0, pend_ncols = 0;
+  int64_t work_cols = 0;               // widest block the sketch products see
 };
 
 namespace {
@@ -194,7 +202,7 @@ void free_all(qsk_ctx *c) {
   c->side = nullptr;
   void *ptrs[] = {c->y, c->w, c->u[0], c->u[1], c->small, c->work, c->partials, c->pbuf,
                   c->p1buf, c->sbuf, c->err_acc, c->status, c->w_scratch, c->pinv_work,
-                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus, c->fp8_scales, c->zero_plane, c->xt, c->proj_part, c->pad};
+                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus, c->fp8_scales, c->zero_plane, c->xt, c->proj_part, c->pad, c->pend};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->y = c->w = nullptr;
@@ -287,17 +295,22 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   if (c.n_correction < 0 || c.n_correction > 8 || c.n_power < 1 || c.n_power > 64) return QSK_E_ARG;
   if (c.max_block_cols < 0) return QSK_E_ARG;
   if (c.y_only != 0 && c.y_only != 1) return QSK_E_ARG;
+  if (c.coalesce_cols < 0 || c.coalesce_cols > c.n) return QSK_E_ARG;
   if (c.sketch_dtype == QSK_BF16 && (c.split_terms < 1 || c.split_terms > 3)) return QSK_E_ARG;
   if (c.sketch_dtype == QSK_FP8_E4M3 && (c.split_terms < 1 || c.split_terms > 2)) return QSK_E_ARG;
   if (c.sketch_dtype != QSK_F64 && c.input_dtype == QSK_F64) return QSK_E_UNSUPPORTED;
+  if (c.embedding_round < QSK_F64 || c.embedding_round > QSK_FP8_E4M3) return QSK_E_ARG;
+  if (c.embedding_round != QSK_F64 && c.sketch_dtype != QSK_F64) return QSK_E_ARG;
 
   qsk_ctx *ctx = new (std::nothrow) qsk_ctx;
   if (!ctx) return QSK_E_NOMEM;
   ctx->cfg = c;
   if (ctx->cfg.max_block_cols == 0 || ctx->cfg.max_block_cols > c.n) ctx->cfg.max_block_cols = c.n;
+  ctx->work_cols = std::max<int64_t>(ctx->cfg.max_block_cols, c.coalesce_cols);
   if (ctx->cfg.sketch_dtype != QSK_BF16 && ctx->cfg.sketch_dtype != QSK_FP8_E4M3) ctx->cfg.split_terms = 1;
   ctx->stream = (hipStream_t)hip_stream;
   ctx->mode = c.sketch_dtype;     // MODE_* and QSK dtypes share the numbering
+  ctx->emode = c.sketch_dtype == QSK_F64 ? c.embedding_round : c.sketch_dtype;
   ctx->ts = c.sketch_dtype == QSK_F64 ? 8 : 4;
   ctx->k0 = (uint32_t)(c.seed & 0xFFFFFFFFull);
   ctx->k1 = (uint32_t)(c.seed >> 32);
@@ -340,16 +353,25 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   if (mfma_mode) {
     qsk::MfmaStage &g = ctx->stage;
     const bool op16 = c.sketch_dtype != QSK_F32;     // bf16 operands (BF16, FP8 data)
-    qsk::stage_geometry(m, (int)l, (int)k, ctx->cfg.max_block_cols, op16, &g.LP, &g.MP, &g.KP, &g.NP);
+    qsk::stage_geometry(m, (int)l, (int)k, ctx->work_cols, op16, &g.LP, &g.MP, &g.KP, &g.NP);
     const size_t es = op16 ? 2 : 4;
     if (c.sketch_dtype == QSK_FP8_E4M3) {
-      ctx->fp8_scale_elems = 4 * ((m + 31) / 32) * ((ctx->cfg.max_block_cols + 31) / 32);
+      ctx->fp8_scale_elems = 4 * ((m + 31) / 32) * ((ctx->work_cols + 31) / 32);
       ok = ok && alloc((void **)&ctx->fp8_scales, (size_t)ctx->fp8_scale_elems * 4);
     }
     ok = ok && alloc(&g.omega, 4 * (size_t)g.KP * g.NP * es);
     ok = ok && alloc(&g.psi, 4 * (size_t)g.LP * g.MP * es);
-    ctx->w_scratch_bytes = (int64_t)16 * 4 * ctx->cfg.max_block_cols * g.LP * 4;
+    // W split-K partials: 16 splits of the widest block, or, for thin
+    // blocks (whose few column tiles need many row chunks to fill the
+    // chip), as many splits of 256 rows as fit in 64 MiB
+    const int64_t per_split = (int64_t)4 * ctx->work_cols * g.LP * 4;
+    ctx->w_scratch_bytes = std::max<int64_t>(16 * per_split,
+                                             std::min<int64_t>((int64_t)64 << 20, (m / 256) * per_split));
     ok = ok && alloc(&ctx->w_scratch, (size_t)ctx->w_scratch_bytes);
+  }
+  if (c.coalesce_cols > 0) {
+    const size_t es = c.input_dtype == QSK_F64 ? 8 : c.input_dtype == QSK_F32 ? 4 : 2;
+    ok = ok && alloc(&ctx->pend, 4 * (size_t)m * c.coalesce_cols * es);
   }
   if (!ok) {
     free_all(ctx);
@@ -382,6 +404,7 @@ qsk_status qsketch_reset(qsk_ctx *ctx) {
   HIPCHK(ctx, hipMemsetAsync(ctx->y, 0, (size_t)ctx->y_copies * 4 * c.m * c.k * ctx->ts, ctx->stream));
   if (ctx->w) HIPCHK(ctx, hipMemsetAsync(ctx->w, 0, 4 * (size_t)c.l * c.n * ctx->ts, ctx->stream));
   ctx->columns_seen = 0;
+  ctx->pend_ncols = 0;
   return QSK_OK;
 }
 
@@ -406,6 +429,7 @@ static qsk_status sketch_block(qsk_ctx *ctx, int64_t col0, int64_t ncols, const 
   s.skip_w = c.y_only;
   s.stream = ctx->stream;
   s.mode = ctx->mode;
+  s.emode = ctx->emode;
   s.in_dtype = c.input_dtype;
   for (int p = 0; p < 4; ++p) s.planes[p] = planes[p];
   if (c.pure) s.planes[0] = planes[1];
@@ -452,12 +476,61 @@ static qsk_status sketch_block(qsk_ctx *ctx, int64_t col0, int64_t ncols, const 
   return QSK_OK;
 }
 
+// Coalescing of thin updates: the pending columns' planes in ctx->pend.
+static size_t input_size(const qsk_config &c) {
+  return c.input_dtype == QSK_F64 ? 8 : c.input_dtype == QSK_F32 ? 4 : 2;
+}
+
+static void pending_planes(qsk_ctx *ctx, const void *pl[4]) {
+  const qsk_config &c = ctx->cfg;
+  const size_t plane = (size_t)c.m * c.coalesce_cols * input_size(c);
+  for (int p = 0; p < 4; ++p) pl[p] = (const char *)ctx->pend + p * plane;
+}
+
+// Run the sketch products on the pending columns (if any).
+static qsk_status flush_pending(qsk_ctx *ctx) {
+  if (ctx->pend_ncols == 0) return QSK_OK;
+  const void *pl[4];
+  pending_planes(ctx, pl);
+  const int64_t c0 = ctx->pend_col0, nc = ctx->pend_ncols;
+  ctx->pend_ncols = 0;
+  return sketch_block(ctx, c0, nc, pl, ctx->cfg.m, 1.0);
+}
+
+// Copy a checked block behind the pending columns (stream-ordered).
+static qsk_status append_pending(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void *const planes[4],
+                                 int64_t ld) {
+  const qsk_config &c = ctx->cfg;
+  const size_t es = input_size(c);
+  const void *pl[4];
+  pending_planes(ctx, pl);
+  if (ctx->pend_ncols == 0) ctx->pend_col0 = col0;
+  for (int p = c.pure ? 1 : 0; p < 4; ++p) {
+    char *dst = (char *)pl[p] + (size_t)ctx->pend_ncols * c.m * es;
+    HIPCHK(ctx, hipMemcpy2DAsync(dst, (size_t)c.m * es, planes[p], (size_t)ld * es, (size_t)c.m * es,
+                                 (size_t)ncols, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  ctx->pend_ncols += ncols;
+  return QSK_OK;
+}
+
 qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void *const planes[4],
                           int64_t ld) {
   if (!ctx) return QSK_E_ARG;
   if (ctx->poisoned) return QSK_E_STATE;
+  const qsk_config &c = ctx->cfg;
   qsk_status st = check_block(ctx, col0, ncols, planes, ld);
-  if (st == QSK_OK) st = sketch_block(ctx, col0, ncols, planes, ld, 1.0);
+  if (st != QSK_OK) return st;
+  if (c.coalesce_cols > 0 && ncols < c.coalesce_cols) {
+    if (ctx->pend_ncols > 0 &&
+        (col0 != ctx->pend_col0 + ctx->pend_ncols || ctx->pend_ncols + ncols > c.coalesce_cols))
+      st = flush_pending(ctx);
+    if (st == QSK_OK) st = append_pending(ctx, col0, ncols, planes, ld);
+    if (st == QSK_OK && ctx->pend_ncols == c.coalesce_cols) st = flush_pending(ctx);
+  } else {
+    st = flush_pending(ctx);
+    if (st == QSK_OK) st = sketch_block(ctx, col0, ncols, planes, ld, 1.0);
+  }
   if (st == QSK_OK) ctx->columns_seen += ncols;
   return st;
 }
@@ -479,6 +552,10 @@ qsk_status qsketch_update_block(qsk_ctx *ctx, int64_t row0, int64_t nrows, int64
   {
     const qsk_status gs = grow_buffer(ctx, &ctx->pad, &ctx->pad_bytes, 4 * plane);
     if (gs != QSK_OK) return gs;
+  }
+  {
+    const qsk_status fs = flush_pending(ctx);
+    if (fs != QSK_OK) return fs;
   }
   // the full-height block: zero outside rows row0 .. row0 + nrows - 1
   const void *full[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -510,6 +587,8 @@ qsk_status qsketch_scale(qsk_ctx *ctx, double theta) {
   if (!ctx) return QSK_E_ARG;
   if (ctx->poisoned) return QSK_E_STATE;
   if (!std::isfinite(theta)) return fail_arg(ctx, "theta is not finite");
+  const qsk_status fs = flush_pending(ctx);
+  if (fs != QSK_OK) return fs;
   return scale_sketches(ctx, theta);
 }
 
@@ -519,6 +598,7 @@ qsk_status qsketch_update_linear(qsk_ctx *ctx, double theta, double eta, int64_t
   if (ctx->poisoned) return QSK_E_STATE;
   if (!std::isfinite(theta) || !std::isfinite(eta)) return fail_arg(ctx, "theta or eta is not finite");
   qsk_status st = check_block(ctx, col0, ncols, planes, ld);
+  if (st == QSK_OK) st = flush_pending(ctx);
   if (st == QSK_OK) st = scale_sketches(ctx, theta);
   if (st == QSK_OK && eta != 0.0) st = sketch_block(ctx, col0, ncols, planes, ld, eta);
   if (st == QSK_OK) ctx->columns_seen += ncols;
@@ -543,6 +623,7 @@ qsk_status qsketch_set_sketches(qsk_ctx *ctx, const double *const Y[4], int64_t 
       if (!W[p]) return fail_arg(ctx, "NULL W plane");
   }
   const int t = ctx->mode == qsk::MODE_F64 ? 0 : 1;
+  ctx->pend_ncols = 0;                   // the new state replaces pending columns too
   if (Y) {
     const int64_t per_copy = 4 * c.m * (int64_t)c.k;
     if (ctx->y_copies > 1)
@@ -561,6 +642,10 @@ qsk_status qsketch_sketches(qsk_ctx *ctx, double *const Y[4], int64_t ldy, doubl
   if (ctx->poisoned) return QSK_E_STATE;
   const qsk_config &c = ctx->cfg;
   const int t = ctx->mode == qsk::MODE_F64 ? 0 : 1;
+  {
+    const qsk_status fs = flush_pending(ctx);
+    if (fs != QSK_OK) return fs;
+  }
   if (Y) {
     if (ldy < c.m) return fail_arg(ctx, "ldy < m");
     HIPCHK(ctx, fold_y(ctx));
@@ -603,6 +688,10 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
   SmallStatus hs{};
   int flags = 0;
 
+  {
+    const qsk_status fs = flush_pending(ctx);
+    if (fs != QSK_OK) return fs;
+  }
   HIPCHK(ctx, fold_y(ctx));
   if (opt) HIPCHK(ctx, qsk::launch_status_reset(st, ctx->status, 0));
   const void *yp[4];
@@ -730,7 +819,7 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
   // Psi as the sketch used it: the matrix-core path's staging holds exactly
   // those values (rounded to the operand format); otherwise regenerate
   const int psi_st_type = !ctx->psi_staged ? 0 : (ctx->mode == qsk::MODE_F32 ? 2 : 1);
-  HIPCHK(ctx, qsk::launch_psi_apply(st, ctx->mode, c.embedding == QSK_RADEMACHER, ctx->k0, ctx->k1, l,
+  HIPCHK(ctx, qsk::launch_psi_apply(st, ctx->emode, c.embedding == QSK_RADEMACHER, ctx->k0, ctx->k1, l,
                                     m, Q, ldq, k, ctx->partials, ctx->partial_elems, pp, l,
                                     ctx->stage.psi, psi_st_type, ctx->stage.MP,
                                     (int64_t)ctx->stage.LP * ctx->stage.MP));

@@ -59,7 +59,7 @@ __device__ __forceinline__ void entry_d(int rad, uint32_t t, uint32_t o, uint32_
 template <typename TO> __device__ __forceinline__ void add_out(TO *p, double v) { *p = (TO)((double)*p + v); }
 
 // Y[i, j] += sum_t H[i, t] Omega[col0 + t, j]; 64 rows x 8 columns per block.
-template <int MODE, typename TIN, typename TY>
+template <int MODE, int EMODE, typename TIN, typename TY>
 __global__ __launch_bounds__(256) void sketch_y_generic(PlanesC<TIN> a, int64_t lda, int pure,
                                                         int64_t m, int64_t col0, int64_t ncols,
                                                         int k, TY *y, int64_t ldy, int64_t psy,
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void sketch_y_generic(PlanesC<TIN> a, int64_t 
       const int tt = threadIdx.x >> 3, jj = threadIdx.x & 7;
       double e[4] = {0.0, 0.0, 0.0, 0.0};
       if (t0 + tt < ncols && j0 + jj < k)
-        entry_d<MODE>(rad, (uint32_t)(col0 + t0 + tt), (uint32_t)(j0 + jj), STREAM_OMEGA, k0, k1, e);
+        entry_d<EMODE>(rad, (uint32_t)(col0 + t0 + tt), (uint32_t)(j0 + jj), STREAM_OMEGA, k0, k1, e);
 #pragma unroll
       for (int p = 0; p < 4; ++p) om[tt][jj][p] = e[p];
     }
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void sketch_y_generic(PlanesC<TIN> a, int64_t 
 }
 
 // W[r, col0 + j] += sum_i Psi[r, i] H[i, j]; 64 columns x 8 rows per block.
-template <int MODE, typename TIN, typename TW>
+template <int MODE, int EMODE, typename TIN, typename TW>
 __global__ __launch_bounds__(256) void sketch_w_generic(PlanesC<TIN> a, int64_t lda, int pure,
                                                         int64_t m, int64_t col0, int64_t ncols,
                                                         int l, TW *w, int64_t ldw, int64_t psw,
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void sketch_w_generic(PlanesC<TIN> a, int64_t 
       const int rr = threadIdx.x >> 5, ii = threadIdx.x & 31;
       double e[4] = {0.0, 0.0, 0.0, 0.0};
       if (i0 + ii < m && r0 + rr < l)
-        entry_d<MODE>(rad, (uint32_t)(i0 + ii), (uint32_t)(r0 + rr), STREAM_PSI, k0, k1, e);
+        entry_d<EMODE>(rad, (uint32_t)(i0 + ii), (uint32_t)(r0 + rr), STREAM_PSI, k0, k1, e);
 #pragma unroll
       for (int p = 0; p < 4; ++p) ps[rr][ii][p] = e[p];
     }
@@ -162,35 +162,54 @@ __global__ __launch_bounds__(256) void sketch_w_generic(PlanesC<TIN> a, int64_t 
   }
 }
 
-template <int MODE, typename TIN, typename TS>
+// EMODE: the format of the test-matrix values (an FP64 sketch may take the
+// rounded values of a low-precision one)
+template <int MODE, int EMODE, typename TIN, typename TS>
 static hipError_t launch_generic_t(const SketchArgs &s) {
   PlanesC<TIN> a;
   for (int p = 0; p < 4; ++p) a.p[p] = (const TIN *)s.planes[p];
   if (s.pure || !a.p[0]) a.p[0] = a.p[1];
   dim3 gy((unsigned)((s.m + 63) / 64), (unsigned)((s.k + 7) / 8));
-  hipLaunchKernelGGL((sketch_y_generic<MODE, TIN, TS>), gy, dim3(256), 0, s.stream, a, s.lda, s.pure,
+  hipLaunchKernelGGL((sketch_y_generic<MODE, EMODE, TIN, TS>), gy, dim3(256), 0, s.stream, a, s.lda, s.pure,
                      s.m, s.col0, s.ncols, s.k, (TS *)s.y, s.ldy, s.psy, s.rad, s.terms, s.k0, s.k1, s.eta);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (s.skip_w) return hipSuccess;
   dim3 gw((unsigned)((s.ncols + 63) / 64), (unsigned)((s.l + 7) / 8));
-  hipLaunchKernelGGL((sketch_w_generic<MODE, TIN, TS>), gw, dim3(256), 0, s.stream, a, s.lda, s.pure,
+  hipLaunchKernelGGL((sketch_w_generic<MODE, EMODE, TIN, TS>), gw, dim3(256), 0, s.stream, a, s.lda, s.pure,
                      s.m, s.col0, s.ncols, s.l, (TS *)s.w, s.ldw, s.psw, s.rad, s.terms, s.k0, s.k1, s.eta);
   return hipGetLastError();
+}
+
+template <int MODE, typename TIN, typename TS>
+static hipError_t launch_generic_e(const SketchArgs &s) {
+  const int em = s.emode < 0 ? MODE : s.emode;
+  if constexpr (MODE == MODE_F64) {
+    switch (em) {
+      case MODE_F64: return launch_generic_t<MODE, MODE_F64, TIN, TS>(s);
+      case MODE_F32: return launch_generic_t<MODE, MODE_F32, TIN, TS>(s);
+      case MODE_BF16: return launch_generic_t<MODE, MODE_BF16, TIN, TS>(s);
+      case MODE_FP8: return launch_generic_t<MODE, MODE_FP8, TIN, TS>(s);
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    if (em != MODE) return hipErrorInvalidValue;
+    return launch_generic_t<MODE, MODE, TIN, TS>(s);
+  }
 }
 
 hipError_t launch_sketch_generic(const SketchArgs &s) {
   switch (s.mode) {
     case MODE_F64:
-      if (s.in_dtype == DT_F64) return launch_generic_t<MODE_F64, double, double>(s);
-      if (s.in_dtype == DT_F32) return launch_generic_t<MODE_F64, float, double>(s);
-      return launch_generic_t<MODE_F64, uint16_t, double>(s);
+      if (s.in_dtype == DT_F64) return launch_generic_e<MODE_F64, double, double>(s);
+      if (s.in_dtype == DT_F32) return launch_generic_e<MODE_F64, float, double>(s);
+      return launch_generic_e<MODE_F64, uint16_t, double>(s);
     case MODE_F32:
-      if (s.in_dtype == DT_F32) return launch_generic_t<MODE_F32, float, float>(s);
-      return launch_generic_t<MODE_F32, uint16_t, float>(s);
+      if (s.in_dtype == DT_F32) return launch_generic_e<MODE_F32, float, float>(s);
+      return launch_generic_e<MODE_F32, uint16_t, float>(s);
     case MODE_BF16:
-      if (s.in_dtype == DT_F32) return launch_generic_t<MODE_BF16, float, float>(s);
-      return launch_generic_t<MODE_BF16, uint16_t, float>(s);
+      if (s.in_dtype == DT_F32) return launch_generic_e<MODE_BF16, float, float>(s);
+      return launch_generic_e<MODE_BF16, uint16_t, float>(s);
     default:
       return hipErrorInvalidValue;
   }

@@ -188,9 +188,10 @@ class BoundTracker:
         self.ky += 1
         self.kw += 1
 
-    def check(self, y, w, label):
+    def check(self, y, w, label, u=None):
         c = self.ref.cfg
-        u = U64 if c.dtype == "f64" else U32
+        if u is None:
+            u = U64 if c.dtype == "f64" else U32
         orel = operand_rel(c)
         assert_elementwise(y, self.ref.Y, self.by, self.ky, label + " Y", u=u, op_rel=orel)
         if w is not None:

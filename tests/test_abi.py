@@ -37,6 +37,10 @@ def test_config_default_and_strerror():
     dict(m=100, n=80, k=10, l=21, sketch_dtype=2, split_terms=4),
     dict(m=100, n=80, k=10, l=21, embedding=5),
     dict(m=100, n=80, k=10, l=21, y_only=2),
+    dict(m=100, n=80, k=10, l=21, embedding_round=4),
+    dict(m=100, n=80, k=10, l=21, input_dtype=1, sketch_dtype=2, embedding_round=2),  # only FP64 sketches
+    dict(m=100, n=80, k=10, l=21, coalesce_cols=81),
+    dict(m=100, n=80, k=10, l=21, coalesce_cols=-1),
 ])
 def test_invalid_configs_rejected_before_device_use(bad):
     assert qs.config_status(**bad) == qs.QSK_E_ARG
@@ -49,7 +53,9 @@ def test_unsupported_combinations():
 
 def test_struct_layouts_match_header():
     # field order/size of the ctypes mirrors (int64 m,n; int32 k,l; uint64 seed; 7 int32;
-    # padding; int64 max_block_cols; int32 y_only; tail padding)
-    assert ctypes.sizeof(qs.QskConfig) == 8 + 8 + 4 + 4 + 8 + 7 * 4 + 4 + 8 + 4 + 4
+    # padding; int64 max_block_cols; int32 y_only; int32 embedding_round; int32
+    # coalesce_cols; tail padding)
+    assert ctypes.sizeof(qs.QskConfig) == 8 + 8 + 4 + 4 + 8 + 7 * 4 + 4 + 8 + 4 + 4 + 4 + 4
     assert qs.QskConfig.max_block_cols.offset == 64 and qs.QskConfig.y_only.offset == 72
+    assert qs.QskConfig.embedding_round.offset == 76 and qs.QskConfig.coalesce_cols.offset == 80
     assert ctypes.sizeof(qs.QskReport) == 8 + 8 + 64 + 4 * 4 + 8 + 8

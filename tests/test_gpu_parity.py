@@ -210,3 +210,39 @@ def test_exact_low_rank_recovery(kind):
     sk, dev = run_sketch(a, m, n, k, l, 60, seed=9)
     q, x, rep = sk.finalize(kind)
     assert sk.rel_error(dev, q, x) < 1e-8
+
+
+@pytest.mark.parametrize("emb,rnd", [("gaussian", "bf16"), ("gaussian", "fp8"), ("rademacher", "bf16")])
+def test_fp64_sketch_with_rounded_test_matrices(emb, rnd):
+    """An FP64 context with embedding_round takes the test matrices of a
+    low-precision sketch (the reference of the equal-error comparison): with
+    A = I its sketches are exactly those rounded values; on data, Y, W and
+    the QB stage (which regenerates Psi for Psi Q) match the oracle's FP64
+    sketch with the same rounded test matrices."""
+    import paper_2404_14783_amd as qs
+    n, k, l = 320, 16, 37
+    dev = qs.to_colmajor(torch.from_numpy(identity_q(n)).cuda())
+    sk = qs.Sketcher(n, n, k, l, seed=12345, embedding=emb, max_block_cols=64, embedding_round=rnd)
+    for c0 in range(0, n, 64):
+        sk.update(c0, dev[:, :, c0:c0 + 64])
+    y, w = (to_numpy(t) for t in sk.sketches())
+    sk.close()
+    np.testing.assert_array_equal(y, embeddings.omega(emb, np.arange(n), k, 12345, rnd))
+    np.testing.assert_array_equal(w, embeddings.psi(emb, l, np.arange(n), 12345, rnd))
+    m, n, k, l, block = 333, 257, 12, 25, 50
+    a = synth.lowrank_plus_noise(m, n, torch.tensor(0.8 ** np.arange(10)), 1e-4, 77).numpy()
+    cfg = SketchConfig(m, n, k, l, seed=5, embedding=emb, dtype="f64", embedding_dtype=rnd)
+    ref = sketch_matrix(a, cfg, block_cols=block)
+    sk = qs.Sketcher(m, n, k, l, seed=5, embedding=emb, max_block_cols=block, embedding_round=rnd)
+    dev = qs.to_colmajor(torch.from_numpy(a).cuda())
+    for c0 in range(0, n, block):
+        sk.update(c0, dev[:, :, c0:c0 + block])
+    y, w = (to_numpy(t) for t in sk.sketches())
+    check_sketches(y, w, ref, a, f"f64 with {rnd} test matrices ({emb})", block_cols=block)
+    for kind in ("pseudo_qr", "pseudo_svd"):
+        q, x, _ = sk.finalize(kind)
+        h_o, x_o, _ = onepass.qb_stage(ref, kind)
+        d = rel(qt.hamilton(to_numpy(q), to_numpy(x)), qt.hamilton(h_o, x_o))
+        print(f"  {kind}: |HX - HX_o| / |HX_o| = {d:.2e}", flush=True)
+        assert d < 1e-9
+    sk.close()
