@@ -95,7 +95,7 @@ int64_t rup_i(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
 // Tile shapes of the grouped sketch launches: row tiles of W per block
 // (13 only with bf16 operands) and column tiles of Y per block.
-const int kNmt[3] = {4, 7, 13}, kNj[2] = {4, 7};
+const int kNmt[4] = {4, 7, 8, 13}, kNj[2] = {4, 7};
 // the largest of rup(x, 16 t) over the first n tile counts t
 int64_t max_pad(int64_t x, const int *t, int n) {
   int64_t r = 0;
@@ -890,9 +890,9 @@ qsk_status qsketch_batch_init(int32_t count, const qsk_config *cfgs, void *hip_s
         // staging sized for the largest padding of any tile shape the
         // autotuner may pick
         4 * (size_t)max_pad(q.k, kNj, 2) * q.stage.NP * es,                            // omega staging
-        4 * (size_t)max_pad(q.l, kNmt, c0.sketch_dtype == QSK_BF16 ? 3 : 2) * q.stage.MP * es,  // psi
+        4 * (size_t)max_pad(q.l, kNmt, c0.sketch_dtype == QSK_BF16 ? 4 : 2) * q.stage.MP * es,  // psi
         // W partial sums: up to 8 row chunks of 4 planes x n x the padded l
-        8 * 4 * (size_t)q.n * max_pad(q.l, kNmt, c0.sketch_dtype == QSK_BF16 ? 3 : 2) * 4,
+        8 * 4 * (size_t)q.n * max_pad(q.l, kNmt, c0.sketch_dtype == QSK_BF16 ? 4 : 2) * 4,
     };
     for (size_t s : sizes) {
       off[i].push_back(total);
@@ -941,7 +941,7 @@ qsk_status qsketch_batch_init(int32_t count, const qsk_config *cfgs, void *hip_s
     q.stage.omega = base + o[12];
     q.stage.psi = base + o[13];
     q.wpart = (float *)(base + o[14]);
-    q.wpart_bytes = (int64_t)(8 * 4 * (size_t)q.n * max_pad(q.l, kNmt, c0.sketch_dtype == QSK_BF16 ? 3 : 2) * 4);
+    q.wpart_bytes = (int64_t)(8 * 4 * (size_t)q.n * max_pad(q.l, kNmt, c0.sketch_dtype == QSK_BF16 ? 4 : 2) * 4);
   }
   b->status = (SmallStatus *)(base + st_off);
   b->kstatus = (SmallStatus *)(base + st_off + al(sizeof(SmallStatus) * count));
@@ -1049,7 +1049,7 @@ qsk_status qsketch_batch_autotune(qsk_batch *b, const void *const *planes, const
     BCHK(b, hipEventCreate(&e1));
     float best = -1.0f;
     qsk_status r = QSK_OK;
-    const int n_nmt = b->mode == qsk::MODE_BF16 ? 3 : 2;
+    const int n_nmt = b->mode == qsk::MODE_BF16 ? 4 : 2;
     for (int a = 0; a < n_nmt && r == QSK_OK; ++a) {
       for (int c = 0; c < 2 && r == QSK_OK; ++c) {
         if ((r = restage(b, kNmt[a], kNj[c])) != QSK_OK) break;

@@ -38,6 +38,8 @@ struct SketchArgs {
   double eta = 1.0;      // scale of the products: Y += eta H Omega_J, W[:, J] += eta Psi H
   int skip_w = 0;        // Y only: no Psi staging, no W product
   int emode = -1;        // format of the test-matrix values (MODE_*); -1: that of `mode`
+  int gen_rad = 1;       // matrix-core path: Rademacher tiles generated in the kernels (not staged)
+  int *y_splits = nullptr;  // out (may be null): copies of Y the update added into
   // optional timing: events[2 * kernel] before, [2 * kernel + 1] after (may be null)
   hipEvent_t *events;
 };
@@ -84,6 +86,11 @@ constexpr int Y_COPIES = 4;
 hipError_t launch_y_fold(hipStream_t st, float *y, int64_t n_per_copy, int S);
 // Matrix-core path; returns hipErrorNotSupported for shapes it does not take.
 hipError_t launch_sketch_mfma(const SketchArgs &s, const MfmaStage &g);
+// Whether launch_sketch_mfma generates the update's test-matrix tiles in its
+// kernels (then nothing is staged, and Psi must be regenerated for Psi Q).
+bool gen_in_kernel(const SketchArgs &s);
+// Psi alone into g.psi as a sketch of s.mode uses it.
+hipError_t stage_psi(const SketchArgs &s, const MfmaStage &g);
 
 // ---------------------------------------------------------------------------
 // FP64 finalize building blocks (finalize.hip).  Small k x k quaternion

@@ -69,6 +69,7 @@ struct qsk_ctx {
   // sum is Y (folded into copy 0 before Y is read)
   void *y = nullptr, *w = nullptr;
   int y_copies = 1;
+  int y_dirty = 1;                     // copies 0 .. y_dirty - 1 may be nonzero
   // finalize workspace (FP64)
   double *u[2] = {nullptr, nullptr};   // m x k planar, two alternating buffers
   double *small = nullptr;             // k x k AoS matrices
@@ -97,6 +98,7 @@ struct qsk_ctx {
   double t_ms[4] = {0, 0, 0, 0};
   int64_t t_count[4] = {0, 0, 0, 0};
   int use_mfma = 1;
+  int gen_rad = 1;                     // Rademacher tiles generated in the product kernels
   bool psi_staged = false;             // stage.psi holds Psi as the sketch used it
   void *zero_plane = nullptr;          // zeroed real plane for qsketch_project on pure input
   size_t zero_plane_bytes = 0;
@@ -113,6 +115,9 @@ struct qsk_ctx {
   void *pend = nullptr;
   int64_t pend_col0 = 0, pend_ncols = 0;
   int64_t work_cols = 0;               // widest block the sketch products see
+  // Gram Y^* Y of the current sketch (S_YG), kept between finalize calls
+  // until the sketch changes (both rangefinders start from it)
+  bool gram_valid = false;
 };
 
 namespace {
@@ -229,14 +234,17 @@ bool alloc(void **p, size_t bytes) {
 
 // Offsets of the k x k matrices inside ctx->small.
 enum SmallSlot { S_G1 = 0, S_GU, S_R, S_T, S_RPROD, S_RTMP, S_G0, S_TMP, S_C, S_F, S_GP, S_RP,
-                 S_TP1, S_TP2, S_TPT, S_Z, S_CR, S_CT, S_GI, S_M, S_TMP2, S_GH, S_GK0, S_COUNT };
+                 S_TP1, S_TP2, S_TPT, S_Z, S_CR, S_CT, S_GI, S_M, S_TMP2, S_GH, S_GK0, S_YG, S_COUNT };
 
 double *slot(qsk_ctx *c, int s) { return c->small + (size_t)s * c->cfg.k * c->cfg.k * 4; }
 
 // Sum the split-K copies of Y into copy 0 (stream-ordered).
+// Only the copies an update added into since the last fold are read.
 hipError_t fold_y(qsk_ctx *c) {
-  if (c->y_copies <= 1) return hipSuccess;
-  return qsk::launch_y_fold(c->stream, (float *)c->y, 4 * c->cfg.m * (int64_t)c->cfg.k, c->y_copies);
+  if (c->y_copies <= 1 || c->y_dirty <= 1) return hipSuccess;
+  const hipError_t e = qsk::launch_y_fold(c->stream, (float *)c->y, 4 * c->cfg.m * (int64_t)c->cfg.k, c->y_dirty);
+  if (e == hipSuccess) c->y_dirty = 1;
+  return e;
 }
 
 }  // namespace
@@ -316,6 +324,8 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   ctx->k1 = (uint32_t)(c.seed >> 32);
   const char *env = std::getenv("QSK_NO_MFMA");
   ctx->use_mfma = (env && env[0] == '1') ? 0 : 1;
+  const char *genv = std::getenv("QSK_STAGE_RADEMACHER");
+  ctx->gen_rad = (genv && genv[0] == '1') ? 0 : 1;
   if (hipGetDevice(&ctx->device) != hipSuccess ||
       scratch_address(ctx->device, &ctx->noalloc_scratch) != hipSuccess) {
     (void)hipGetLastError();
@@ -405,6 +415,8 @@ qsk_status qsketch_reset(qsk_ctx *ctx) {
   if (ctx->w) HIPCHK(ctx, hipMemsetAsync(ctx->w, 0, 4 * (size_t)c.l * c.n * ctx->ts, ctx->stream));
   ctx->columns_seen = 0;
   ctx->pend_ncols = 0;
+  ctx->gram_valid = false;
+  ctx->y_dirty = 1;
   return QSK_OK;
 }
 
@@ -424,6 +436,7 @@ static qsk_status check_block(qsk_ctx *ctx, int64_t col0, int64_t ncols, const v
 static qsk_status sketch_block(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void *const planes[4],
                                int64_t ld, double eta) {
   const qsk_config &c = ctx->cfg;
+  ctx->gram_valid = false;
   qsk::SketchArgs s{};
   s.eta = eta;
   s.skip_w = c.y_only;
@@ -449,6 +462,9 @@ static qsk_status sketch_block(qsk_ctx *ctx, int64_t col0, int64_t ncols, const 
   s.fp8_scales = ctx->fp8_scales;
   s.fp8_scale_elems = ctx->fp8_scale_elems;
   s.psi_ready = ctx->psi_staged ? 1 : 0;
+  s.gen_rad = ctx->gen_rad;
+  int splits = 1;
+  s.y_splits = &splits;
   s.events = nullptr;
   if (ctx->timing && ctx->use_mfma && ctx->mode != qsk::MODE_F64) {
     if (ctx->ev_used + 8 > ctx->ev_pool.size()) {
@@ -464,7 +480,8 @@ static qsk_status sketch_block(qsk_ctx *ctx, int64_t col0, int64_t ncols, const 
   hipError_t e = hipErrorNotSupported;
   if (ctx->use_mfma && ctx->mode != qsk::MODE_F64) {
     e = qsk::launch_sketch_mfma(s, ctx->stage);
-    if (e == hipSuccess && !c.y_only) ctx->psi_staged = true;
+    if (e == hipSuccess && !c.y_only && !qsk::gen_in_kernel(s)) ctx->psi_staged = true;
+    if (e == hipSuccess && splits > ctx->y_dirty) ctx->y_dirty = splits;
   }
   if (e == hipErrorNotSupported && ctx->mode == qsk::MODE_FP8) {
     ctx->last_error = "fp8 sketch: block too large for the matrix-core path (32-bit offsets) or "
@@ -576,6 +593,7 @@ qsk_status qsketch_update_block(qsk_ctx *ctx, int64_t row0, int64_t nrows, int64
 // (every split-K copy of Y scales with the sum).
 static qsk_status scale_sketches(qsk_ctx *ctx, double theta) {
   if (theta == 1.0) return QSK_OK;
+  ctx->gram_valid = false;
   const qsk_config &c = ctx->cfg;
   const int t = ctx->mode == qsk::MODE_F64 ? 0 : 1;
   HIPCHK(ctx, qsk::launch_scale(ctx->stream, t, ctx->y, (int64_t)ctx->y_copies * 4 * c.m * (int64_t)c.k, theta));
@@ -624,12 +642,14 @@ qsk_status qsketch_set_sketches(qsk_ctx *ctx, const double *const Y[4], int64_t 
   }
   const int t = ctx->mode == qsk::MODE_F64 ? 0 : 1;
   ctx->pend_ncols = 0;                   // the new state replaces pending columns too
+  ctx->gram_valid = false;
   if (Y) {
     const int64_t per_copy = 4 * c.m * (int64_t)c.k;
     if (ctx->y_copies > 1)
       HIPCHK(ctx, hipMemsetAsync((char *)ctx->y + per_copy * ctx->ts, 0,
                                  (size_t)(ctx->y_copies - 1) * per_copy * ctx->ts, ctx->stream));
     HIPCHK(ctx, qsk::launch_narrow(ctx->stream, t, Y, ldy, ctx->y, c.m, c.m * (int64_t)c.k, c.m, c.k));
+    ctx->y_dirty = 1;
   }
   if (W) HIPCHK(ctx, qsk::launch_narrow(ctx->stream, t, W, ldw, ctx->w, c.l, c.l * (int64_t)c.n, c.l, c.n));
   ctx->columns_seen = columns_seen;
@@ -710,8 +730,17 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
   int passes = 0, need = 2;
   const int max_passes = 8;
   for (;;) {
-    HIPCHK(ctx, qsk::launch_crossprod(st, tz, zsrc, m, tz, zsrc, m, m, k, k, ctx->partials,
-                                      ctx->partial_elems, gz));
+    if (passes == 0 && ctx->gram_valid) {
+      // Y^* Y of this sketch, kept from the previous finalize
+      HIPCHK(ctx, hipMemcpyAsync(gz, slot(ctx, S_YG), kk * 8, hipMemcpyDeviceToDevice, st));
+    } else {
+      HIPCHK(ctx, qsk::launch_crossprod(st, tz, zsrc, m, tz, zsrc, m, m, k, k, ctx->partials,
+                                        ctx->partial_elems, gz));
+      if (passes == 0) {
+        HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_YG), gz, kk * 8, hipMemcpyDeviceToDevice, st));
+        ctx->gram_valid = true;
+      }
+    }
     HIPCHK(ctx, qsk::launch_chol_inv(st, gz, k, complex_only, 0.0, 1e-13, slot(ctx, S_R),
                                      slot(ctx, S_T), ctx->status));
     if (!opt) {
@@ -817,7 +846,16 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
     sp[p] = ctx->sbuf + (size_t)p * l * k;
   }
   // Psi as the sketch used it: the matrix-core path's staging holds exactly
-  // those values (rounded to the operand format); otherwise regenerate
+  // those values (rounded to the operand format); when the update kernels
+  // generated Psi in place, it is regenerated into the staging buffer once
+  // for this product (the FP64 matrix-core product reads it there)
+  if (!ctx->psi_staged && ctx->use_mfma && ctx->stage.psi && ctx->mode != qsk::MODE_F64) {
+    qsk::SketchArgs sa{};
+    sa.stream = st; sa.mode = ctx->mode; sa.l = l; sa.m = m; sa.k = k;
+    sa.rad = c.embedding == QSK_RADEMACHER; sa.k0 = ctx->k0; sa.k1 = ctx->k1;
+    HIPCHK(ctx, qsk::stage_psi(sa, ctx->stage));
+    ctx->psi_staged = true;
+  }
   const int psi_st_type = !ctx->psi_staged ? 0 : (ctx->mode == qsk::MODE_F32 ? 2 : 1);
   HIPCHK(ctx, qsk::launch_psi_apply(st, ctx->emode, c.embedding == QSK_RADEMACHER, ctx->k0, ctx->k1, l,
                                     m, Q, ldq, k, ctx->partials, ctx->partial_elems, pp, l,

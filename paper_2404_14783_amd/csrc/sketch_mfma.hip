@@ -138,6 +138,23 @@ __device__ constexpr int ssel(int p, int q) {      // S(Psi)[p][q]
   return t[p][q];
 }
 
+// The same tables read by test-matrix plane: the data plane q whose product
+// with plane s of Psi (W) or of Omega (Y) lands in output plane p, and
+// whether that term carries a minus sign.  Each output plane takes each
+// test-matrix plane exactly once.
+__device__ constexpr int w_q_of(int p, int s) {
+  for (int q = 0; q < 4; ++q)
+    if (ssel(p, q) == s || (s > 0 && ssel(p, q) == s + 3)) return q;
+  return -1;
+}
+__device__ constexpr bool w_neg(int p, int s) { return ssel(p, w_q_of(p, s)) >= 4; }
+__device__ constexpr int y_q_of(int p, int s) {
+  for (int q = 0; q < 4; ++q)
+    if (rsel(q, p) == s || (s > 0 && rsel(q, p) == s + 3)) return q;
+  return -1;
+}
+__device__ constexpr bool y_neg(int p, int s) { return rsel(y_q_of(p, s), p) >= 4; }
+
 // ---------------------------------------------------------------------------
 // Block-to-tile mapping.  Workgroups are dispatched to the eight XCDs in
 // turn (block b runs on XCD b mod 8), so the linear tile index is taken as
@@ -167,8 +184,6 @@ __device__ __forceinline__ void neg_data(const Frag (&af)[4][3], Frag (&naf)[4][
       for (int tm = 0; tm < TERMS; ++tm) naf[q][tm] = negx(af[q][tm]);
   }
 }
-__device__ __forceinline__ void neg3(FragB (&f)[7]) { f[4] = negB(f[1]); f[5] = negB(f[2]); f[6] = negB(f[3]); }
-__device__ __forceinline__ void neg3(FragF (&f)[7]) { f[4] = negF(f[1]); f[5] = negF(f[2]); f[6] = negF(f[3]); }
 
 // fp8 operand split of 8 data values sharing the tile scale sc (a power of
 // two): term 0 is q * sc with q = e4m3(x / sc) (round to nearest even, as
@@ -336,6 +351,70 @@ template <> __device__ __forceinline__ void dma_frag<FragF>(const char *blk, int
 }
 
 // ---------------------------------------------------------------------------
+// Rademacher test-matrix tiles generated in place of the staged ones.  A
+// step's tile holds rows o0 .. o0 + 16 ntiles - 1 of the test matrix (rows of
+// Psi for W, columns of Omega for Y) at 32 consecutive contraction indices
+// from tb, in the 1 KB LDS blocks [plane][tile] of the fragment layout (lane
+// 16 g + c: row c of the tile, indices 8 g .. 8 g + 7 as bf16 +-1).  One
+// Philox call serves 32 contraction indices of a row, 4 bits per entry (bit
+// p: the sign of plane p), so one thread makes a whole row of the tile: one
+// call when tb is a multiple of 32, two when the step straddles two calls
+// (the entries tb .. tb + 31 are bits 4 (tb mod 32) .. of the two calls'
+// 256 bits).  Rows at or past n_o are zero.  Row r goes to wave r mod 4,
+// lane r / 4, so the four SIMDs share the work (waves 4 .. have none).
+
+// bf16 +-1 pair of entries 2d, 2d + 1 of a plane whose sign bits sit at
+// bits 8d and 8d + 4 of y
+__device__ __forceinline__ uint32_t rad_pair(uint32_t y, int d) {
+  const uint32_t lo = (y >> (8 * d)) & 1u, hi = (y >> (8 * d + 4)) & 1u;
+  return 0x3F803F80u | (lo << 15) | (hi << 31);
+}
+
+__device__ __forceinline__ uint32_t pick_word(int wd, int i, const uint32_t (&z)[8]) {
+  // z[wd + i] for wd in 0 .. 3, i in 0 .. 4, as selects (no indexed registers)
+  const uint32_t a = i < 8 ? z[i] : 0u;
+  const uint32_t b = i + 1 < 8 ? z[i + 1] : 0u;
+  const uint32_t c = i + 2 < 8 ? z[i + 2] : 0u;
+  const uint32_t d = i + 3 < 8 ? z[i + 3] : 0u;
+  return wd == 0 ? a : (wd == 1 ? b : (wd == 2 ? c : d));
+}
+
+template <int NT>
+__device__ __forceinline__ void rad_tile(char *lds, int64_t o0, int64_t n_o, int64_t tb, uint32_t stream,
+                                         uint32_t k0, uint32_t k1, int wave, int lane) {
+  if (wave >= 4) return;
+  const int r = 4 * lane + wave;
+  if (r >= 16 * NT) return;
+  const int64_t o = o0 + r;
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+  if (o < n_o) {
+    const uint32_t c0 = (uint32_t)(tb >> 5), off = (uint32_t)(tb & 31);
+    const u32x4 x = philox(c0, (uint32_t)o, stream, 1u, k0, k1);
+    if (off == 0) {
+      w[0] = x.x0; w[1] = x.x1; w[2] = x.x2; w[3] = x.x3;
+    } else {
+      const u32x4 y = philox(c0 + 1u, (uint32_t)o, stream, 1u, k0, k1);
+      const uint32_t z[8] = {x.x0, x.x1, x.x2, x.x3, y.x0, y.x1, y.x2, y.x3};
+      const int bit = (int)(4 * off), wd = bit >> 5, sh = bit & 31;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const uint32_t lo = pick_word(wd, g, z), hi = pick_word(wd, g + 1, z);
+        w[g] = sh ? (lo >> sh) | (hi << (32 - sh)) : lo;
+      }
+    }
+  }
+  const int tile = r >> 4, c = r & 15;
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+      const uint32_t y = w[g] >> pl;
+      const u32v4 v = {rad_pair(y, 0), rad_pair(y, 1), rad_pair(y, 2), rad_pair(y, 3)};
+      *(QSK_LDS u32v4 *)(lds + (pl * NT + tile) * 1024 + (16 * g + c) * 16) = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // W kernel.  Tiles: 64 columns of the update block x NMT row tiles of W
 // (16 rows each) x one chunk of the rows of A (split K over S chunks).
 // Block = 4H waves, H per SIMD: wave w owns columns 16 (w mod 4) .. + 15 of
@@ -359,9 +438,12 @@ struct WArgs {
   const float *fsc;           // fp8 tile scales [4][RT][CT] (OP_FP8)
   int RT, CT;
   float eta = 1.f;            // W += eta Psi H
+  uint32_t k0 = 0, k1 = 0;    // Philox key (Psi tiles generated in the kernel)
 };
 
-template <int OP, typename TIN, int NMT, int TERMS, bool PURE, int H>
+// GEN: the Rademacher Psi tiles are generated in the kernel (rad_tile)
+// instead of read from the staging buffer
+template <int OP, typename TIN, int NMT, int TERMS, bool PURE, int H, bool GEN>
 __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H))) void w_mfma_kernel(WArgs a0, GroupRef grp) {
   WArgs a;
   int64_t t;
@@ -443,6 +525,10 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
   } while (0)
 #define QSK_W_DMA(I0, B)                                                                        \
   do {                                                                                          \
+    if constexpr (GEN) {                                                                        \
+      rad_tile<NMT>(&s_psi[B][0][0], rbase, a.l, (I0), STREAM_PSI, a.k0, a.k1, wave, lane);     \
+      break;                                                                                    \
+    }                                                                                           \
     _Pragma("unroll") for (int k_ = 0; k_ < (NBLK + NW - 1) / NW; ++k_) {                       \
       const int u_ = wave + k_ * NW;                                                            \
       if (u_ < NBLK) {                                                                          \
@@ -479,28 +565,37 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
     __builtin_amdgcn_sched_barrier(0);
     QSK_W_FETCH_A(i0 + 32);                                // next step (past the end: unused)
     __builtin_amdgcn_sched_barrier(0);
+    // The products of a 16-row tile run grouped by Psi plane s; once group s
+    // is issued the tile's plane-s fragment is dead, and plane s of the next
+    // tile is read from LDS into the same registers while groups s + 1 ..
+    // run, so the LDS latency stays hidden behind the matrix cores.  Tiles
+    // that lie below NMT in every wave carry no branch.
+    Frag pf[4];
+    if ((H - 1) * NH < NMT || rt0 < NMT) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) dma_frag<Frag>(&s_psi[buf][(s * NMT + rt0) * SUB][0], lane, pf[s]);
+    }
 #pragma unroll
     for (int i = 0; i < NH; ++i) {
       const int rt = rt0 + i;
-      // tiles that lie below NMT in every wave carry no branch, so the
-      // fragment reads of the next tile can be issued during the current
-      // tile's products
       if ((H - 1) * NH + i < NMT || rt < NMT) {
-        Frag pf[7];
+        const bool next = i + 1 < NH && ((H - 1) * NH + i + 1 < NMT || rt + 1 < NMT);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) dma_frag<Frag>(&s_psi[buf][(s * NMT + rt) * SUB][0], lane, pf[s]);
-        if constexpr (!neg_on_data<TERMS>()) neg3(pf);
+        for (int s = 0; s < 4; ++s) {
+          Frag nps;
+          if constexpr (!neg_on_data<TERMS>()) nps = negx(pf[s]);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (q == 0 && PURE) continue;
+          for (int p = 0; p < 4; ++p) {
+            const int q = w_q_of(p, s);
+            if (q == 0 && PURE) continue;
+            const bool ng = w_neg(p, s);
 #pragma unroll
-          for (int tm = 0; tm < TERMS; ++tm)
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-              const int sp = ssel(p, q);
-              if constexpr (!neg_on_data<TERMS>()) acc[i][p] = mma(pf[sp], af[q][tm], acc[i][p]);
-              else acc[i][p] = sp < 4 ? mma(pf[sp], af[q][tm], acc[i][p]) : mma(pf[sp - 3], naf[q][tm], acc[i][p]);
+            for (int tm = 0; tm < TERMS; ++tm) {
+              if constexpr (neg_on_data<TERMS>()) acc[i][p] = mma(pf[s], ng ? naf[q][tm] : af[q][tm], acc[i][p]);
+              else acc[i][p] = mma(ng ? nps : pf[s], af[q][tm], acc[i][p]);
             }
+          }
+          if (next) dma_frag<Frag>(&s_psi[buf][(s * NMT + rt + 1) * SUB][0], lane, pf[s]);
         }
       }
     }
@@ -603,9 +698,12 @@ struct YArgs {
   const float *fsc;           // fp8 tile scales [4][RT][CT] (OP_FP8)
   int RT, CT;
   float eta = 1.f;            // Y += eta H Omega
+  int64_t col0 = 0;           // first column of the block (Omega tiles generated in the kernel)
+  uint32_t k0 = 0, k1 = 0;
 };
 
-template <int OP, typename TIN, int NJ, int TERMS, bool PURE, int H>
+// GEN: the Rademacher Omega tiles are generated in the kernel (rad_tile)
+template <int OP, typename TIN, int NJ, int TERMS, bool PURE, int H, bool GEN>
 __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H))) void y_mfma_kernel(YArgs a0, GroupRef grp) {
   YArgs a;
   int64_t t;
@@ -672,6 +770,10 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
   } while (0)
 #define QSK_Y_DMA(T0, B)                                                                        \
   do {                                                                                          \
+    if constexpr (GEN) {                                                                        \
+      rad_tile<NJ>(&s_om[B][0][0], (int64_t)jt0 * 16, a.k, a.col0 + (T0), STREAM_OMEGA, a.k0, a.k1, wave, lane); \
+      break;                                                                                    \
+    }                                                                                           \
     _Pragma("unroll") for (int k_ = 0; k_ < (NBLK + NW - 1) / NW; ++k_) {                       \
       const int u_ = wave + k_ * NW;                                                            \
       if (u_ < NBLK) {                                                                          \
@@ -695,23 +797,29 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
     voff += vstep;
     QSK_Y_FETCH_A(t0 + 32);                                 // next step (past the end: unused)
     if (t0 + 32 < te) QSK_Y_DMA(t0 + 32, buf ^ 1);
+    // grouped by Omega plane, the next column tile's fragments read during
+    // the current tile's products (as in the W kernel)
+    Frag of[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) dma_frag<Frag>(&s_om[buf][(s * NJ) * SUB][0], lane, of[s]);
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
-      Frag of[7];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) dma_frag<Frag>(&s_om[buf][(s * NJ + i) * SUB][0], lane, of[s]);
-      if constexpr (!neg_on_data<TERMS>()) neg3(of);
+      for (int s = 0; s < 4; ++s) {
+        Frag nof;
+        if constexpr (!neg_on_data<TERMS>()) nof = negx(of[s]);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (q == 0 && PURE) continue;
+        for (int p = 0; p < 4; ++p) {
+          const int q = y_q_of(p, s);
+          if (q == 0 && PURE) continue;
+          const bool ng = y_neg(p, s);
 #pragma unroll
-        for (int tm = 0; tm < TERMS; ++tm)
-#pragma unroll
-          for (int p = 0; p < 4; ++p) {
-            const int rs = rsel(q, p);
-            if constexpr (!neg_on_data<TERMS>()) acc[i][p] = mma(af[q][tm], of[rs], acc[i][p]);
-            else acc[i][p] = rs < 4 ? mma(af[q][tm], of[rs], acc[i][p]) : mma(naf[q][tm], of[rs - 3], acc[i][p]);
+          for (int tm = 0; tm < TERMS; ++tm) {
+            if constexpr (neg_on_data<TERMS>()) acc[i][p] = mma(ng ? naf[q][tm] : af[q][tm], of[s], acc[i][p]);
+            else acc[i][p] = mma(af[q][tm], ng ? nof : of[s], acc[i][p]);
           }
+        }
+        if (i + 1 < NJ) dma_frag<Frag>(&s_om[buf][(s * NJ + i + 1) * SUB][0], lane, of[s]);
       }
     }
     wait_vm();
@@ -805,8 +913,8 @@ hipError_t launch_y_fold(hipStream_t st, float *y, int64_t n_per_copy, int S) {
 // ---------------------------------------------------------------------------
 static inline int64_t rup(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
-// Tile choices: NMT row tiles of W per block (from {4, 7, 13}; 13 only for
-// bf16 operands, whose Psi tile is half the size) and NJ column tiles of Y
+// Tile choices: NMT row tiles of W per block (from {4, 7, 8, 13}; 8 and 13
+// only for bf16 operands, whose Psi tile is half the size) and NJ column tiles of Y
 // per block (from {4, 7}), each minimising the padded tile count (ties go to
 // the larger tile).
 static int pick_tiles(int tiles, const int *cand, int nc) {
@@ -819,8 +927,8 @@ static int pick_tiles(int tiles, const int *cand, int nc) {
   return best;
 }
 static int w_nmt(int l, int op_bf16) {
-  static const int cb[3] = {4, 7, 13}, cf[2] = {4, 7};
-  return op_bf16 ? pick_tiles((l + 15) / 16, cb, 3) : pick_tiles((l + 15) / 16, cf, 2);
+  static const int cb[4] = {4, 7, 8, 13}, cf[2] = {4, 7};
+  return op_bf16 ? pick_tiles((l + 15) / 16, cb, 4) : pick_tiles((l + 15) / 16, cf, 2);
 }
 static int y_nj(int k) {
   static const int c[2] = {4, 7};
@@ -863,21 +971,40 @@ template <int OP> constexpr int y_waves() { return !op_f32(OP) ? QSK_Y_WAVES : 1
 
 // `pure` (no real plane) is a template parameter so that the product
 // sequences have no branches
+// gen: Rademacher test-matrix tiles generated in the kernel (bf16 operands)
 template <int OP, typename TIN, int TERMS, int NMT>
-static void launch_w(const WArgs &w, int64_t blocks, hipStream_t st, GroupRef g = GroupRef{}) {
+static void launch_w(const WArgs &w, int64_t blocks, hipStream_t st, GroupRef g = GroupRef{}, bool gen = false) {
   constexpr int H = w_waves<OP>();
+  if constexpr (!op_f32(OP)) {
+    if (gen) {
+      if (w.pure)
+        hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS, true, H, true>), dim3((unsigned)blocks), dim3(256 * H), 0, st, w, g);
+      else
+        hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS, false, H, true>), dim3((unsigned)blocks), dim3(256 * H), 0, st, w, g);
+      return;
+    }
+  }
   if (w.pure)
-    hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS, true, H>), dim3((unsigned)blocks), dim3(256 * H), 0, st, w, g);
+    hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS, true, H, false>), dim3((unsigned)blocks), dim3(256 * H), 0, st, w, g);
   else
-    hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS, false, H>), dim3((unsigned)blocks), dim3(256 * H), 0, st, w, g);
+    hipLaunchKernelGGL((w_mfma_kernel<OP, TIN, NMT, TERMS, false, H, false>), dim3((unsigned)blocks), dim3(256 * H), 0, st, w, g);
 }
 template <int OP, typename TIN, int TERMS, int NJ>
-static void launch_y(const YArgs &y, int64_t blocks, hipStream_t st, GroupRef g = GroupRef{}) {
+static void launch_y(const YArgs &y, int64_t blocks, hipStream_t st, GroupRef g = GroupRef{}, bool gen = false) {
   constexpr int H = y_waves<OP>();
+  if constexpr (!op_f32(OP)) {
+    if (gen) {
+      if (y.pure)
+        hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS, true, H, true>), dim3((unsigned)blocks), dim3(256 * H), 0, st, y, g);
+      else
+        hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS, false, H, true>), dim3((unsigned)blocks), dim3(256 * H), 0, st, y, g);
+      return;
+    }
+  }
   if (y.pure)
-    hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS, true, H>), dim3((unsigned)blocks), dim3(256 * H), 0, st, y, g);
+    hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS, true, H, false>), dim3((unsigned)blocks), dim3(256 * H), 0, st, y, g);
   else
-    hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS, false, H>), dim3((unsigned)blocks), dim3(256 * H), 0, st, y, g);
+    hipLaunchKernelGGL((y_mfma_kernel<OP, TIN, NJ, TERMS, false, H, false>), dim3((unsigned)blocks), dim3(256 * H), 0, st, y, g);
 }
 // Blocks of 4 H waves resident at once on the device: every CU holds two
 // waves per SIMD of these kernels (their register budget).
@@ -929,18 +1056,28 @@ static bool offsets_fit(int64_t m, int64_t ncols, int64_t lda) {
   return (uint64_t)((ncols + 64) * lda + rup(m, 128) + 64) * sizeof(TIN) < (1ull << 32);
 }
 
+// Whether an update's test-matrix tiles are generated inside the product
+// kernels (Rademacher with bf16 operands) rather than staged.
+bool gen_in_kernel(const SketchArgs &s) {
+  return s.rad && s.gen_rad && (s.mode == MODE_BF16 || s.mode == MODE_FP8);
+}
+
 template <int OP, typename TIN, int TERMS>
 static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
   using OPT = typename std::conditional<!op_f32(OP), uint16_t, float>::type;
   if (!offsets_fit<TIN>(s.m, s.ncols, s.lda) || !y_plane_fits(s.m, s.k)) return hipErrorNotSupported;
   hipError_t e;
   mark(s, 0);
-  // regenerate Omega_J in the operand format, and Psi once (it is the same
-  // for every block)
+  // Rademacher test matrices with bf16 operands are generated inside the
+  // product kernels; otherwise regenerate Omega_J in the operand format,
+  // and Psi once (it is the same for every block)
+  const bool gen = gen_in_kernel(s);
   OPT *om = (OPT *)g.omega;
   OPT *ps = (OPT *)g.psi;
   const int64_t NPu = rup(s.ncols, 32);
-  if (s.mode == MODE_BF16) {
+  if (gen) {
+    // nothing staged
+  } else if (s.mode == MODE_BF16) {
     e = gen_stage<MODE_BF16, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
     if (!s.psi_ready && !s.skip_w) e = gen_stage<MODE_BF16, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
@@ -978,6 +1115,7 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     y.lda = s.lda; y.m = s.m; y.ncols = s.ncols;
     y.om = om; y.KP = g.KP; y.NP = NPu;
     y.k = s.k; y.pure = s.pure; y.eta = (float)s.eta;
+    y.col0 = s.col0; y.k0 = s.k0; y.k1 = s.k1;
     y.y = (float *)s.y; y.ldy = s.ldy; y.psy = s.psy; y.pss = s.pss;
     const int nj = y_nj(s.k);
     const int ntiles = (s.k + 15) / 16;
@@ -990,9 +1128,10 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     int64_t tchunk = rup((s.ncols + S - 1) / S, 32);
     S = (s.ncols + tchunk - 1) / tchunk;
     y.S = (int)S; y.tchunk = tchunk;
+    if (s.y_splits) *s.y_splits = (int)S;
     const int64_t blocks = (int64_t)y.rblocks * y.cgroups * S;
-    if (nj == 7) launch_y<OP, TIN, TERMS, 7>(y, blocks, s.stream);
-    else launch_y<OP, TIN, TERMS, 4>(y, blocks, s.stream);
+    if (nj == 7) launch_y<OP, TIN, TERMS, 7>(y, blocks, s.stream, GroupRef{}, gen);
+    else launch_y<OP, TIN, TERMS, 4>(y, blocks, s.stream, GroupRef{}, gen);
     e = hipGetLastError();
     mark(s, 3);
     if (e != hipSuccess) return e;
@@ -1005,6 +1144,7 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     w.lda = s.lda; w.m = s.m; w.ncols = s.ncols; w.col0 = s.col0;
     w.psi = ps; w.LP = g.LP; w.MP = g.MP;
     w.l = s.l; w.pure = s.pure; w.eta = (float)s.eta;
+    w.k0 = s.k0; w.k1 = s.k1;
     w.w = (float *)s.w; w.ldw = s.ldw; w.psw = s.psw;
     const int nmt = w_nmt(s.l, !op_f32(OP));
     w.rgroups = (int)(g.LP / (16 * nmt));
@@ -1024,9 +1164,10 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
     w.S = (int)S; w.kchunk = kchunk; w.part = (float *)s.scratch;
     const int64_t blocks = base * S;
     mark(s, 4);
-    if (nmt == 13) launch_w<OP, TIN, TERMS, (!op_f32(OP) ? 13 : 7)>(w, blocks, s.stream);
-    else if (nmt == 7) launch_w<OP, TIN, TERMS, 7>(w, blocks, s.stream);
-    else launch_w<OP, TIN, TERMS, 4>(w, blocks, s.stream);
+    if (nmt == 13) launch_w<OP, TIN, TERMS, (!op_f32(OP) ? 13 : 7)>(w, blocks, s.stream, GroupRef{}, gen);
+    else if (nmt == 8) launch_w<OP, TIN, TERMS, (!op_f32(OP) ? 8 : 7)>(w, blocks, s.stream, GroupRef{}, gen);
+    else if (nmt == 7) launch_w<OP, TIN, TERMS, 7>(w, blocks, s.stream, GroupRef{}, gen);
+    else launch_w<OP, TIN, TERMS, 4>(w, blocks, s.stream, GroupRef{}, gen);
     e = hipGetLastError();
     mark(s, 5);
     if (e != hipSuccess) return e;
@@ -1051,9 +1192,9 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
 // grouped launch each (no split K: each problem's tiles write its own Y and
 // W directly).
 void batch_tiles(const int *l, const int *k, int count, int op_bf16, int *nmt, int *nj) {
-  static const int cb[3] = {4, 7, 13}, cf[2] = {4, 7}, cy[2] = {4, 7};
+  static const int cb[4] = {4, 7, 8, 13}, cf[2] = {4, 7}, cy[2] = {4, 7};
   const int *cw = op_bf16 ? cb : cf;
-  const int ncw = op_bf16 ? 3 : 2;
+  const int ncw = op_bf16 ? 4 : 2;
   int64_t best = -1;
   for (int i = 0; i < ncw; ++i) {
     int64_t pad = 0;
@@ -1080,6 +1221,21 @@ void stage_geometry_tiles(int64_t m, int l, int k, int64_t maxcols, int nmt, int
   *MP = rup(m, 32);
   *KP = (int)rup(k, 16 * nj);
   *NP = rup(maxcols, 32);
+}
+
+// Psi alone into its staging buffer, with the values a sketch of s.mode uses
+// (P = Psi Q reads it there when the update kernels generated Psi in place).
+hipError_t stage_psi(const SketchArgs &s, const MfmaStage &g) {
+  if (s.mode == MODE_BF16)
+    return gen_stage<MODE_BF16, uint16_t>(s.stream, (uint16_t *)g.psi, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI,
+                                          s.rad, s.k0, s.k1);
+  if (s.mode == MODE_FP8)
+    return gen_stage<MODE_FP8, uint16_t>(s.stream, (uint16_t *)g.psi, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI,
+                                         s.rad, s.k0, s.k1);
+  if (s.mode == MODE_F32)
+    return gen_stage<MODE_F32, float>(s.stream, (float *)g.psi, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad,
+                                      s.k0, s.k1);
+  return hipErrorNotSupported;
 }
 
 hipError_t stage_test_matrices(const SketchArgs &s, const MfmaStage &g) {
@@ -1189,6 +1345,7 @@ static hipError_t launch_batch_t(const SketchArgs *s, const MfmaStage *g, int co
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (nmt == 13) launch_w<OP, TIN, TERMS, (!op_f32(OP) ? 13 : 7)>(ws[0], pw[count], st, gw);
+  else if (nmt == 8) launch_w<OP, TIN, TERMS, (!op_f32(OP) ? 8 : 7)>(ws[0], pw[count], st, gw);
   else if (nmt == 7) launch_w<OP, TIN, TERMS, 7>(ws[0], pw[count], st, gw);
   else launch_w<OP, TIN, TERMS, 4>(ws[0], pw[count], st, gw);
   e = hipGetLastError();

@@ -246,3 +246,36 @@ def test_fp64_sketch_with_rounded_test_matrices(emb, rnd):
         print(f"  {kind}: |HX - HX_o| / |HX_o| = {d:.2e}", flush=True)
         assert d < 1e-9
     sk.close()
+
+
+@pytest.mark.parametrize("dtype,terms,pure,block", [("bf16", 1, True, 50), ("f32", 2, False, 70)])
+def test_rademacher_generated_in_kernel_matches_staged(monkeypatch, dtype, terms, pure, block):
+    """Rademacher test matrices with bf16 operands are generated inside the
+    product kernels (never written to device memory); the staged form
+    (QSK_STAGE_RADEMACHER=1 at context creation) feeds the same operand
+    values in the same order, so both give the same sketches bit for bit,
+    on blocks whose first column is not a multiple of 32 (the Omega tile of
+    a step then straddles two Philox calls).  The QB stage on the two gives
+    the same HX to FP64 rounding."""
+    m, n, k, l = 1300, 333, 40, 81
+    a = synth.lowrank_plus_noise(m, n, torch.tensor(0.85 ** np.arange(20)), 1e-3, 91).numpy()
+    if pure:
+        a[0] = 0.0
+    a = input_values(a, dtype)
+    out = []
+    for staged in ("1", "0"):
+        monkeypatch.setenv("QSK_STAGE_RADEMACHER", staged)
+        sk, _ = run_sketch(a, m, n, k, l, block, dtype=dtype, sketch="bf16", emb="rademacher", seed=17,
+                           terms=terms, pure=pure)
+        out.append([to_numpy(t) for t in sk.sketches()])
+        q, x, _ = sk.finalize("pseudo_qr")
+        out[-1].append(qt.hamilton(to_numpy(q), to_numpy(x)))
+        sk.close()
+    np.testing.assert_array_equal(out[0][0], out[1][0])          # Y
+    np.testing.assert_array_equal(out[0][1], out[1][1])          # W
+    # the QB stage reads Psi from the staging buffer or regenerates it: the
+    # same values, FP64 sums in another order
+    assert rel(out[1][2], out[0][2]) < 1e-9
+    ref = sketch_matrix(a, SketchConfig(m, n, k, l, seed=17, embedding="rademacher", dtype="bf16", terms=terms),
+                        block_cols=block)
+    check_sketches(out[1][0], out[1][1], ref, a, f"generated rademacher {dtype} x{terms}", block_cols=block)
