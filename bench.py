@@ -482,6 +482,45 @@ def bench_image(args, profile_only=False):
     return leg
 
 
+def graph_saving(args, a, m, n, k, l, block, sketch, terms, coalesce):
+    """The stream of column-block updates issued one call per block and as
+    one replayed HIP graph (qsketch_update_many): median update-phase times
+    over the timed passes, and whether the two give bit-identical sketches."""
+    sk = qs.Sketcher(m, n, k, l, seed=0, embedding="gaussian", input_dtype="f32", sketch_dtype=sketch,
+                     split_terms=terms, pure=True, max_block_cols=block, coalesce_cols=coalesce)
+    cols = list(range(0, n, block))
+    blocks = [a[:, :, c0:c0 + block] for c0 in cols]
+    st = torch.cuda.current_stream()
+
+    def once(graph):
+        sk.reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        if graph:
+            sk.update_many(cols, blocks)
+        else:
+            for c0, b in zip(cols, blocks):
+                sk.update(c0, b)
+        sk.sketches()                                  # runs the pending gathered columns
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    out = {}
+    for graph in (False, True):
+        for _ in range(max(1, args.warmup)):
+            once(graph)
+        out["graph_ms" if graph else "eager_ms"] = float(np.median([once(graph) for _ in range(args.steps)]))
+        ys = [t.clone() for t in sk.sketches()]
+        if graph:
+            out["bit_identical"] = bool(all(torch.equal(u, v) for u, v in zip(ys, prev)))
+        prev = ys
+    sk.close()
+    out.update({"updates": len(cols), "coalesce_cols": coalesce,
+                "saving_ms": out["eager_ms"] - out["graph_ms"]})
+    return out
+
+
 def bench_flow(args, profile_only=False):
     """The 128^3 x 300 pure-quaternion FP32 flow snapshots, 30 linear updates
     of 10 columns, e4m3 operands plus the residual terms, Gaussian, k = 60,
@@ -507,6 +546,11 @@ def bench_flow(args, profile_only=False):
                            [("fp8", "fp8", 2), ("fp8_coalesced", "fp8", 2, co),
                             ("bf16", "bf16", 2), ("bf16_coalesced", "bf16", 2, co)],
                            PEAK_BF16, ref_block=n)
+    leg["update_graph"] = {}
+    for name, co_cols in (("fp8", 0), ("fp8_coalesced", co)):
+        g = graph_saving(args, a, m, n, k, l, block, "fp8", 2, co_cols)
+        leg["update_graph"][name] = g
+        log(f"[bench] flow {name} updates as one graph: {g}")
     del a
     torch.cuda.empty_cache()
     f8 = leg["paths"]["fp8_coalesced"]

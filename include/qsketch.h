@@ -164,6 +164,23 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out);
 qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols,
                           const void *const planes[4], int64_t ld);
 
+/* A sequence of column-block updates A[:, col0[i] : col0[i] + ncols[i]) += H_i,
+   i = 0 .. count - 1, in order, with the same result as count calls of
+   qsketch_update (Section 4 opening and Section 5.3: data streamed through
+   linear updates).  The first call with a given argument list (the same
+   count, offsets, sizes, plane pointers and leading dimensions, starting
+   from the same pending-column state when coalescing) captures the whole
+   sequence into one HIP graph on a stream of the context; later calls with
+   the same list replay it with one launch.  planes holds 4 * count device
+   pointers (planes[4 i + p]), the other arrays count host values.  Every
+   block is checked before anything runs (QSK_E_ARG: nothing happened).
+   Stream-ordered with the context stream; the caller keeps the blocks alive
+   until the stream has passed the call, and changes their contents, not
+   their addresses, between replays. */
+qsk_status qsketch_update_many(qsk_ctx *ctx, int32_t count, const int64_t *col0,
+                               const int64_t *ncols, const void *const *planes,
+                               const int64_t *ld);
+
 /* General linear update A <- theta A + eta H (Section 5.3 streams the image
    through linear sketch updates of the kind introduced by Tropp et al.; both
    sketches are linear in A), with H zero outside the columns

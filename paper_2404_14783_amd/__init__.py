@@ -80,6 +80,9 @@ def _load():
     lib.qsketch_init.restype = i32
     lib.qsketch_update.argtypes = [vp, i64, i64, _P4, i64]
     lib.qsketch_update.restype = i32
+    lib.qsketch_update_many.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                        ctypes.POINTER(vp), ctypes.POINTER(i64)]
+    lib.qsketch_update_many.restype = i32
     lib.qsketch_update_linear.argtypes = [vp, ctypes.c_double, ctypes.c_double, i64, i64, _P4, i64]
     lib.qsketch_update_linear.restype = i32
     lib.qsketch_update_block.argtypes = [vp, i64, i64, i64, i64, _P4, i64]
@@ -237,6 +240,28 @@ class Sketcher:
             self._check(self._lib.qsketch_update_linear(self._ctx, float(theta), float(eta), int(col0),
                                                         int(block.shape[2]), ptrs, ld))
         self.columns_seen += int(block.shape[2])
+
+    def update_many(self, col0s, blocks):
+        """The updates A[:, c0 : c0 + ncols] += block for the pairs of col0s
+        and blocks, in order, as one HIP graph (captured on the first call
+        with these arguments, replayed on later calls with the same tensors)."""
+        n = len(blocks)
+        if n != len(col0s) or n < 1:
+            raise ValueError("one column offset per block")
+        c0 = (ctypes.c_int64 * n)(*[int(c) for c in col0s])
+        nc = (ctypes.c_int64 * n)()
+        lds = (ctypes.c_int64 * n)()
+        ptrs = (ctypes.c_void_p * (4 * n))()
+        for i, b in enumerate(blocks):
+            if b.dtype != TORCH_DTYPE[self.input_dtype]:
+                raise TypeError(f"block dtype {b.dtype} != input dtype {self.input_dtype}")
+            p4, ld = _plane_ptrs(b, self.pure)
+            for q in range(4):
+                ptrs[4 * i + q] = p4[q]
+            nc[i] = int(b.shape[2])
+            lds[i] = ld
+        self._check(self._lib.qsketch_update_many(self._ctx, n, c0, nc, ptrs, lds))
+        self.columns_seen += sum(int(b.shape[2]) for b in blocks)
 
     def update_block(self, row0, col0, block):
         """A[row0 : row0 + nrows, col0 : col0 + ncols] += block."""

@@ -118,6 +118,14 @@ struct qsk_ctx {
   // Gram Y^* Y of the current sketch (S_YG), kept between finalize calls
   // until the sketch changes (both rangefinders start from it)
   bool gram_valid = false;
+  // qsketch_update_many: a sequence of updates captured once into a HIP
+  // graph on its own stream and replayed while the arguments repeat
+  hipStream_t gstream = nullptr;
+  hipEvent_t gev_in = nullptr, gev_out = nullptr;
+  hipGraphExec_t uexec = nullptr;
+  std::vector<uint64_t> ukey;
+  int64_t u_pend_col0 = 0, u_pend_ncols = 0, u_cols = 0;   // host state after the sequence
+  int u_y_dirty = 1;
 };
 
 namespace {
@@ -203,6 +211,14 @@ void free_all(qsk_ctx *c) {
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->side) (void)hipStreamDestroy(c->side);
+  if (c->uexec) (void)hipGraphExecDestroy(c->uexec);
+  if (c->gstream) (void)hipStreamSynchronize(c->gstream);
+  if (c->gev_in) (void)hipEventDestroy(c->gev_in);
+  if (c->gev_out) (void)hipEventDestroy(c->gev_out);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
+  c->uexec = nullptr;
+  c->gev_in = c->gev_out = nullptr;
+  c->gstream = nullptr;
   c->ev_fork = c->ev_join = nullptr;
   c->side = nullptr;
   void *ptrs[] = {c->y, c->w, c->u[0], c->u[1], c->small, c->work, c->partials, c->pbuf,
@@ -531,13 +547,11 @@ static qsk_status append_pending(qsk_ctx *ctx, int64_t col0, int64_t ncols, cons
   return QSK_OK;
 }
 
-qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void *const planes[4],
-                          int64_t ld) {
-  if (!ctx) return QSK_E_ARG;
-  if (ctx->poisoned) return QSK_E_STATE;
+// One checked column-block update (qsketch_update without the checks).
+static qsk_status update_body(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void *const planes[4],
+                              int64_t ld) {
   const qsk_config &c = ctx->cfg;
-  qsk_status st = check_block(ctx, col0, ncols, planes, ld);
-  if (st != QSK_OK) return st;
+  qsk_status st = QSK_OK;
   if (c.coalesce_cols > 0 && ncols < c.coalesce_cols) {
     if (ctx->pend_ncols > 0 &&
         (col0 != ctx->pend_col0 + ctx->pend_ncols || ctx->pend_ncols + ncols > c.coalesce_cols))
@@ -550,6 +564,110 @@ qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void 
   }
   if (st == QSK_OK) ctx->columns_seen += ncols;
   return st;
+}
+
+qsk_status qsketch_update(qsk_ctx *ctx, int64_t col0, int64_t ncols, const void *const planes[4],
+                          int64_t ld) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  const qsk_status st = check_block(ctx, col0, ncols, planes, ld);
+  if (st != QSK_OK) return st;
+  return update_body(ctx, col0, ncols, planes, ld);
+}
+
+qsk_status qsketch_update_many(qsk_ctx *ctx, int32_t count, const int64_t *col0, const int64_t *ncols,
+                               const void *const *planes, const int64_t *ld) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  if (count < 1 || !col0 || !ncols || !planes || !ld) return fail_arg(ctx, "bad update_many arguments");
+  for (int32_t i = 0; i < count; ++i) {
+    const qsk_status st = check_block(ctx, col0[i], ncols[i], planes + 4 * (size_t)i, ld[i]);
+    if (st != QSK_OK) return st;
+  }
+  const qsk_config &c = ctx->cfg;
+  if (!ctx->gstream) {
+    HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->gev_in, hipEventDisableTiming));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->gev_out, hipEventDisableTiming));
+  }
+  // Psi is staged (once per context) outside the graph, so that replays do
+  // not stage it again
+  if (ctx->use_mfma && ctx->mode != qsk::MODE_F64 && !c.y_only && !ctx->psi_staged) {
+    qsk::SketchArgs sa{};
+    sa.stream = ctx->stream; sa.mode = ctx->mode; sa.l = c.l; sa.m = c.m; sa.k = c.k;
+    sa.rad = c.embedding == QSK_RADEMACHER; sa.k0 = ctx->k0; sa.k1 = ctx->k1;
+    sa.gen_rad = ctx->gen_rad;
+    if (!qsk::gen_in_kernel(sa)) {
+      HIPCHK(ctx, qsk::stage_psi(sa, ctx->stage));
+      ctx->psi_staged = true;
+    }
+  }
+  // the sequence, with the pending-column state it starts from
+  std::vector<uint64_t> key;
+  key.reserve(8 * (size_t)count + 4);
+  key.push_back((uint64_t)count);
+  key.push_back((uint64_t)ctx->pend_col0);
+  key.push_back((uint64_t)ctx->pend_ncols);
+  key.push_back((uint64_t)ctx->psi_staged);
+  for (int32_t i = 0; i < count; ++i) {
+    key.push_back((uint64_t)col0[i]);
+    key.push_back((uint64_t)ncols[i]);
+    key.push_back((uint64_t)ld[i]);
+    for (int p = 0; p < 4; ++p) key.push_back((uint64_t)(uintptr_t)planes[4 * (size_t)i + p]);
+  }
+  if (!ctx->uexec || key != ctx->ukey) {
+    if (ctx->uexec) {
+      HIPCHK(ctx, hipStreamSynchronize(ctx->gstream));
+      (void)hipGraphExecDestroy(ctx->uexec);
+      ctx->uexec = nullptr;
+    }
+    // capture the updates on the graph stream (the host state they change
+    // is recorded for the replays)
+    hipStream_t user = ctx->stream;
+    const bool timing = ctx->timing;
+    ctx->stream = ctx->gstream;
+    ctx->timing = false;
+    int64_t cols = 0;
+    hipError_t e = hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal);
+    qsk_status r = e == hipSuccess ? QSK_OK : QSK_E_HIP;
+    for (int32_t i = 0; i < count && r == QSK_OK; ++i) {
+      r = update_body(ctx, col0[i], ncols[i], planes + 4 * (size_t)i, ld[i]);
+      cols += ncols[i];
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(ctx->gstream, &graph) : e;
+    ctx->stream = user;
+    ctx->timing = timing;
+    if (r != QSK_OK || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      if (r != QSK_OK) return r;
+      return hip_fail(ctx, e2, "capture of the updates");
+    }
+    const hipError_t e3 = hipGraphInstantiate(&ctx->uexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) {
+      ctx->uexec = nullptr;
+      return hip_fail(ctx, e3, "hipGraphInstantiate");
+    }
+    ctx->ukey = key;
+    ctx->u_pend_col0 = ctx->pend_col0;
+    ctx->u_pend_ncols = ctx->pend_ncols;
+    ctx->u_y_dirty = ctx->y_dirty;
+    ctx->u_cols = cols;
+    // the capture ran nothing: the state it left is what the launch makes
+    ctx->columns_seen -= cols;
+  }
+  HIPCHK(ctx, hipEventRecord(ctx->gev_in, ctx->stream));
+  HIPCHK(ctx, hipStreamWaitEvent(ctx->gstream, ctx->gev_in, 0));
+  HIPCHK(ctx, hipGraphLaunch(ctx->uexec, ctx->gstream));
+  HIPCHK(ctx, hipEventRecord(ctx->gev_out, ctx->gstream));
+  HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->gev_out, 0));
+  ctx->pend_col0 = ctx->u_pend_col0;
+  ctx->pend_ncols = ctx->u_pend_ncols;
+  if (ctx->u_y_dirty > ctx->y_dirty) ctx->y_dirty = ctx->u_y_dirty;
+  ctx->gram_valid = false;
+  ctx->columns_seen += ctx->u_cols;
+  return QSK_OK;
 }
 
 qsk_status qsketch_update_block(qsk_ctx *ctx, int64_t row0, int64_t nrows, int64_t col0, int64_t ncols,
