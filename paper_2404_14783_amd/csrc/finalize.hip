@@ -26,6 +26,13 @@ __device__ __forceinline__ PlanesC<T> mkc_d(const P (&z)[4]) {
   return r;
 }
 
+// A launch given a gate status whose core-solve gate passes does nothing.
+__device__ __forceinline__ bool gate_skip(const SmallStatus *g) {
+  if (!g) return false;
+  const double v = *(const volatile double *)&g->gate;
+  return v > 0.0 && v <= ONE_PASS_KAPPA2;
+}
+
 // The problem and block indices of this block (see GroupRef).
 template <typename A>
 __device__ __forceinline__ bool group_select(const A &a0, const GroupRef &g, A &a, int &bx, int &by,
@@ -125,6 +132,7 @@ __global__ __launch_bounds__(256) void qgemm64_k(Gemm64Args args, GroupRef grp) 
   Gemm64Args A;
   int bx, by, bz;
   if (!group_select(args, grp, A, bx, by, bz)) return;
+  if (gate_skip(A.gate)) return;
   const int lane = threadIdx.x & 63;
   const int tile = bx * 4 + (threadIdx.x >> 6);
   int tm, tn;
@@ -208,6 +216,7 @@ __global__ __launch_bounds__(256) void qgemm64s_k(Gemm64Args args, GroupRef grp)
   Gemm64Args A;
   int bx, by, bz;
   if (!group_select(args, grp, A, bx, by, bz)) return;
+  if (gate_skip(A.gate)) return;
   const int lane = threadIdx.x & 63;
   const int tile = bx * 4 + (threadIdx.x >> 6);
   int tm, tn;
@@ -298,6 +307,7 @@ __global__ void reduce_chunks_k(ReduceArgs args, GroupRef grp) {
   ReduceArgs A;
   int bx, by, bz;
   if (!group_select(args, grp, A, bx, by, bz)) return;
+  if (gate_skip(A.gate)) return;
   const double *partial = A.partial;
   const int nchunks = A.nchunks;
   const int64_t elems = A.elems;
@@ -426,11 +436,13 @@ static Gemm64Args g64_args(const void *const a[4], int64_t sa_i, int64_t sa_t, c
 
 hipError_t launch_crossprod(hipStream_t st, int t1, const void *const z1[4], int64_t ld1, int t2,
                             const void *const z2[4], int64_t ld2, int64_t rows, int k1, int k2,
-                            double *partials, int64_t partial_elems, double *out_aos) {
+                            double *partials, int64_t partial_elems, double *out_aos,
+                            const SmallStatus *gate) {
   // C(i, j) = sum_t conj(Z1(t, i)) Z2(t, j) on the FP64 matrix cores, K split
   const int64_t max_chunks = partial_elems / ((int64_t)k1 * k2 * 4);
   if (max_chunks < 1) return hipErrorInvalidValue;
   Gemm64Args g = g64_args(z1, ld1, 1, z2, 1, ld2, k1, k2, rows);
+  g.gate = gate;
   g64_set_herm(g, t1 == t2 && ld1 == ld2 && k1 == k2 && same_planes(z1, z2));
   int64_t nch;
   g.kchunk = g64_chunk(rows, g64_tiles(g), max_chunks, &nch);
@@ -440,7 +452,7 @@ hipError_t launch_crossprod(hipStream_t st, int t1, const void *const z1[4], int
   if (e != hipSuccess) return e;
   ReduceArgs r{};
   r.partial = partials; r.nchunks = (int)nch; r.elems = (int64_t)k1 * k2 * 4; r.out = out_aos;
-  r.herm = g.herm; r.m = k1;
+  r.herm = g.herm; r.m = k1; r.gate = gate;
   r.gx = (int)((r.elems + 255) / 256); r.gy = 1;
   return launch_reduce_k(st, r, GroupRef{}, r.gx);
 }
@@ -561,11 +573,12 @@ bool g64_plan_psi(const void *psi_st, int es, int64_t psi_ld, int64_t psi_ps, co
 // ---------------------------------------------------------------------------
 hipError_t launch_apply(hipStream_t st, int tz, const void *const z[4], int64_t ldz, int64_t rows,
                         int k, const double *c_aos, int kc, double *const out[4], int64_t ldo,
-                        int c_upper) {
+                        int c_upper, const SmallStatus *gate) {
   // Out(i, j) = sum_t Z(i, t) C(t, j), C AoS with leading dimension k
   const void *cp[4] = {c_aos, c_aos + 1, c_aos + 2, c_aos + 3};
   Gemm64Args g = g64_args(z, 1, ldz, cp, 4, 4 * (int64_t)k, rows, kc, k);
   g.b_upper = c_upper;
+  g.gate = gate;
   for (int p = 0; p < 4; ++p) g.out[p] = out[p];
   g.ldo = ldo;
   return launch_qgemm64_k(st, tz, 0, false, g, GroupRef{}, 0);
@@ -918,6 +931,50 @@ __device__ void sm_gemm(int k, const double *a, int opa, const double *b, int op
 // holds rows 0 .. c), and only the finished rows are written to r.
 constexpr int CHOL_POOL = 4992;       // quaternions of LDS (156 KB)
 __device__ __forceinline__ int chol_pk(int a, int c) { return ((c * (c + 1)) >> 1) + a; }
+
+// Trailing update of sm_chol after a panel of jb pivot rows (rows j0 ..,
+// finished and scaled in `done`, row stride w): G'[a, c] -= sum over the
+// panel rows of conj(done[rr][a]) done[rr][c] for b0 <= a <= c < b0 + nr, in
+// the packed LDS block T (INLDS) or in r.  Thread t takes the entries t,
+// t + nt, t + 2 nt, ... (column by column), CH at a time: their loads are
+// issued together, then the updates and the stores, so that a load never
+// waits for the store of the previous entry (each entry's arithmetic is the
+// same as one at a time).
+template <bool INLDS, int CH>
+__device__ __forceinline__ void chol_trailing(qd *T, int o, double *r, int k, const qd *done, int w, int j0,
+                                              int jb, int b0, int nr) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tot = (nr * (nr + 1)) >> 1;
+  for (int e0 = tid; e0 < tot; e0 += CH * nt) {
+    int ga_[CH], gc_[CH];
+    qd v[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int e = e0 + u * nt;
+      int ga = b0, gc = b0;
+      if (e < tot) {
+        int cc = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while (cc > 0 && ((cc * (cc + 1)) >> 1) > e) --cc;
+        while ((((cc + 1) * (cc + 2)) >> 1) <= e) ++cc;
+        ga = b0 + e - ((cc * (cc + 1)) >> 1);
+        gc = b0 + cc;
+      }
+      ga_[u] = ga;
+      gc_[u] = gc;
+      if (e < tot) v[u] = INLDS ? T[chol_pk(ga - o, gc - o)] : gq(r, ga, gc, k);
+      else v[u] = qzero();
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      if (e0 + u * nt >= tot) break;
+      qd x = v[u];
+      for (int rr = 0; rr < jb; ++rr)
+        x = qsub(x, qmul(qconj(done[rr * w + ga_[u] - j0]), done[rr * w + gc_[u] - j0]));
+      if (INLDS) T[chol_pk(ga_[u] - o, gc_[u] - o)] = x;
+      else sq_(r, ga_[u], gc_[u], k, x);
+    }
+  }
+}
 __device__ void sm_chol(const double *g, double *r, int k, int complex_only, double shift,
                         double tol, int *fail, double *minp, double *trace) {
   // Panels of CB pivot rows live in LDS twice: `panel` holds the rows as
@@ -1006,18 +1063,8 @@ __device__ void sm_chol(const double *g, double *r, int k, int complex_only, dou
     // trailing update of the upper triangle, its entries dealt to the
     // threads in turn (packed by columns)
     const int nr = k - j0 - jb, b0 = j0 + jb;
-    for (int e = tid; e < ((nr * (nr + 1)) >> 1); e += nt) {
-      int cc = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-      while (cc > 0 && ((cc * (cc + 1)) >> 1) > e) --cc;
-      while ((((cc + 1) * (cc + 2)) >> 1) <= e) ++cc;
-      const int aa = e - ((cc * (cc + 1)) >> 1);
-      const int ga = b0 + aa, gc = b0 + cc;
-      qd v = QSK_CHOL_GET(ga, gc);
-      for (int rr = 0; rr < jb; ++rr)
-        v = qsub(v, qmul(qconj(done[rr * w + ga - j0]), done[rr * w + gc - j0]));
-      if (T) T[chol_pk(ga - o, gc - o)] = v;
-      else sq_(r, ga, gc, k, v);
-    }
+    if (T) chol_trailing<true, 4>(T, o, r, k, done, w, j0, jb, b0, nr);
+    else chol_trailing<false, 8>(T, o, r, k, done, w, j0, jb, b0, nr);
     __syncthreads();
   }
 #undef QSK_CHOL_GET
@@ -1133,6 +1180,7 @@ __global__ __launch_bounds__(1024) void chol_kernel(CholArgs args, GroupRef grp)
   CholArgs A;
   int bx, by, bz;
   if (!group_select(args, grp, A, bx, by, bz)) return;
+  if (gate_skip(A.gate)) return;
   const double *g = A.g;
   const int k = A.k, complex_only = A.complex_only;
   const double shift = A.shift, tol = A.tol;
@@ -1159,6 +1207,7 @@ __global__ __launch_bounds__(256) void triinv_kernel(CholArgs args, GroupRef grp
   CholArgs A;
   int bx, by, bz;
   if (!group_select(args, grp, A, bx, by, bz)) return;
+  if (gate_skip(A.gate)) return;
   const double *r = A.r;
   double *t = A.t;
   const int k = A.k;
@@ -1241,10 +1290,10 @@ hipError_t launch_triinv_k(hipStream_t st, const CholArgs &a, GroupRef g, int64_
 
 
 hipError_t launch_chol_inv(hipStream_t st, const double *g, int k, int complex_only, double shift,
-                           double tol, double *r, double *t, SmallStatus *status) {
+                           double tol, double *r, double *t, SmallStatus *status, const SmallStatus *gate) {
   CholArgs a{};
   a.g = g; a.k = k; a.complex_only = complex_only; a.shift = shift; a.tol = tol;
-  a.r = r; a.t = t; a.status = status; a.only_failed = 0;
+  a.r = r; a.t = t; a.status = status; a.only_failed = 0; a.gate = gate;
   a.gx = k; a.gy = 1;
   hipError_t e = launch_chol_k(st, a, GroupRef{}, 1);
   if (e != hipSuccess) return e;
@@ -1257,6 +1306,7 @@ __global__ __launch_bounds__(256) void qgemm_small_kernel(GemmArgs args, GroupRe
   GemmArgs A;
   int bx, by, bz;
   if (!group_select(args, grp, A, bx, by, bz)) return;
+  if (gate_skip(A.gate)) return;
   const int k = A.k, opa = A.opa, opb = A.opb;
   const double *a = A.a, *b = A.b;
   double *c = A.c;
@@ -1296,9 +1346,9 @@ hipError_t launch_gemm_k(hipStream_t st, const GemmArgs &a, GroupRef g, int64_t 
 }
 
 hipError_t launch_small_gemm(hipStream_t st, int k, const double *a, int opa, const double *b,
-                             int opb, double *c) {
+                             int opb, double *c, const SmallStatus *gate) {
   GemmArgs x{};
-  x.k = k; x.a = a; x.opa = opa; x.b = b; x.opb = opb; x.c = c;
+  x.k = k; x.a = a; x.opa = opa; x.b = b; x.opb = opb; x.c = c; x.gate = gate;
   x.gx = (k + 15) / 16; x.gy = (k + 15) / 16;
   return launch_gemm_k(st, x, GroupRef{}, 0);
 }
@@ -1417,6 +1467,30 @@ hipError_t launch_identity_k(hipStream_t st, const GemmArgs &a, GroupRef g, int 
 }
 hipError_t launch_copy_small_k(hipStream_t st, const GemmArgs &a, GroupRef g, int count) {
   hipLaunchKernelGGL(copy_small_kernel, dim3(g.tab ? count : 1), dim3(1024), 0, st, a, g);
+  return hipGetLastError();
+}
+
+// C = T and the core-solve gate: trace(G_P) ||T||_F^2, ||T||_F^2 summed in a
+// fixed order (strided per thread, then over the threads in index order).
+__global__ __launch_bounds__(1024) void core_gate_kernel(int k, const double *t, double *c, SmallStatus *status) {
+  __shared__ double part[1024];
+  const int64_t n = 4 * (int64_t)k * k;
+  double s = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const double v = t[e];
+    c[e] = v;
+    s += v * v;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int i = 0; i < (int)blockDim.x; ++i) tot += part[i];
+    status->gate = status->trace * tot;
+  }
+}
+hipError_t launch_core_gate(hipStream_t st, int k, const double *t, double *c, SmallStatus *status) {
+  hipLaunchKernelGGL(core_gate_kernel, dim3(1), dim3(1024), 0, st, k, t, c, status);
   return hipGetLastError();
 }
 
@@ -1776,19 +1850,40 @@ __device__ __forceinline__ void tri_step(int j, int k, double *g, qd *P, int o0,
     const double sk = 0.5 * beta * wave_sum(kl);
     const int tot = n * (n + 1) / 2;
     const double b2 = 2.0 * n + 1.0;
-    for (int e = tid; e < tot; e += (int)blockDim.x) {
-      int cc = (int)((b2 - sqrt(b2 * b2 - 8.0 * e)) * 0.5);
-      cc = min(max(cc, 0), n - 1);
-      while (cc > 0 && cc * n - ((cc * (cc - 1)) >> 1) > e) --cc;
-      while (cc + 1 < n && (cc + 1) * n - (((cc + 1) * cc) >> 1) <= e) ++cc;
-      const int aa = cc + (e - (cc * n - ((cc * (cc - 1)) >> 1)));
-      const qd va = v[aa], vc = v[cc];
-      const qd wa = qsub(pv[aa], qscale(va, sk));
-      const qd wc = qsub(pv[cc], qscale(vc, sk));
-      qd gv = tri_get<L>(P, g, o + aa, o + cc, o0, n0, k);
-      gv = qsub(gv, qmul(va, qconj(wc)));
-      gv = qsub(gv, qmul(wa, qconj(vc)));
-      tri_set<L>(P, g, o + aa, o + cc, o0, n0, k, gv);
+    // CH entries per thread at a time: their loads go out together, then the
+    // updates and stores (a load never waits for the previous entry's store)
+    constexpr int CH = 4;
+    const int nt = blockDim.x;
+    for (int e0 = tid; e0 < tot; e0 += CH * nt) {
+      int ia[CH], ic[CH];
+      qd gvs[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int e = e0 + u * nt;
+        int cc = 0, aa = 0;
+        if (e < tot) {
+          cc = (int)((b2 - sqrt(b2 * b2 - 8.0 * e)) * 0.5);
+          cc = min(max(cc, 0), n - 1);
+          while (cc > 0 && cc * n - ((cc * (cc - 1)) >> 1) > e) --cc;
+          while (cc + 1 < n && (cc + 1) * n - (((cc + 1) * cc) >> 1) <= e) ++cc;
+          aa = cc + (e - (cc * n - ((cc * (cc - 1)) >> 1)));
+        }
+        ia[u] = aa;
+        ic[u] = cc;
+        gvs[u] = e < tot ? tri_get<L>(P, g, o + aa, o + cc, o0, n0, k) : qzero();
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        if (e0 + u * nt >= tot) break;
+        const int aa = ia[u], cc = ic[u];
+        const qd va = v[aa], vc = v[cc];
+        const qd wa = qsub(pv[aa], qscale(va, sk));
+        const qd wc = qsub(pv[cc], qscale(vc, sk));
+        qd gv = gvs[u];
+        gv = qsub(gv, qmul(va, qconj(wc)));
+        gv = qsub(gv, qmul(wa, qconj(vc)));
+        tri_set<L>(P, g, o + aa, o + cc, o0, n0, k, gv);
+      }
     }
   }
   __syncthreads();
@@ -1915,55 +2010,76 @@ __device__ void sm_bisect_all(const double *d, const double *e, int k, double *l
   sm_bisect_sel(d, e, k, nullptr, k, lam);
 }
 
-// Classical Gram-Schmidt, twice, over the c vectors xs[0..c) (length k,
-// stride k; LDS or global), in order: each vector loses its components along
-// the earlier ones and is normalised.
-template <typename P>
-__device__ __forceinline__ void cgs2_block(P xs, int k, int c, double *coef, double *s_nrm,
-                                           QSK_LDS double *red) {
+// One vector of cgs2_block: x_i (at xi) loses its components along x_0 ..
+// x_{i-1} (in xs) twice, then is normalised.
+template <typename P, typename PI>
+__device__ __forceinline__ void cgs2_vec(P xs, PI xi, int i, int k, double *coef, double *s_nrm,
+                                         QSK_LDS double *red) {
   // inner products: 16 lanes per pair (j, i), 64 pairs at a time; the
   // update x_i -= sum_j coef_j x_j: rows over rb threads, the sum over j
   // split in np partial sums (short serial chains) that meet in red
-  // (blockDim.x doubles of LDS)
+  // (blockDim.x doubles of LDS).  The loops are unrolled so that several
+  // loads are in flight (the sums keep their order).
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nt = blockDim.x, grp = tid >> 4, sl = tid & 15, ngrp = nt >> 4;
   const int rb = k <= 128 ? 128 : 256, np = nt / rb, row = tid % rb, part = tid / rb;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int j = grp; j < i; j += ngrp) {
+      P xj = xs + (int64_t)j * k;
+      double s = 0.0;
+#pragma unroll 4
+      for (int r = sl; r < k; r += 16) s += xj[r] * xi[r];
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (sl == 0) coef[j] = s;
+    }
+    __syncthreads();
+    if (part < np) {
+      double acc = 0.0;
+      if (row < k)
+#pragma unroll 8
+        for (int j = part; j < i; j += np) acc += coef[j] * xs[(int64_t)j * k + row];
+      red[part * rb + row] = acc;
+    }
+    __syncthreads();
+    if (part == 0 && row < k) {
+      double s = 0.0;
+      for (int p = 0; p < np; ++p) s += red[p * rb + row];
+      xi[row] -= s;
+    }
+    __syncthreads();
+  }
+  if (wave == 0) {
+    double s = 0.0;
+    for (int r = lane; r < k; r += 64) s += xi[r] * xi[r];
+    s = wave_sum(s);
+    if (lane == 0) *s_nrm = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  }
+  __syncthreads();
+  const double sc = *s_nrm;
+  for (int r = tid; r < k; r += blockDim.x) xi[r] *= sc;
+  __syncthreads();
+}
+
+// Classical Gram-Schmidt, twice, over the c vectors xs[0..c) (length k,
+// stride k; LDS or global), in order: each vector loses its components along
+// the earlier ones and is normalised.  With xl (k doubles of LDS) the vector
+// being orthogonalised is worked on there and copied back when done.
+template <typename P>
+__device__ __forceinline__ void cgs2_block(P xs, int k, int c, double *coef, double *s_nrm,
+                                           QSK_LDS double *red, QSK_LDS double *xl = nullptr) {
+  const int tid = threadIdx.x;
   for (int i = 1; i < c; ++i) {
     P xi = xs + (int64_t)i * k;
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int j = grp; j < i; j += ngrp) {
-        P xj = xs + (int64_t)j * k;
-        double s = 0.0;
-        for (int r = sl; r < k; r += 16) s += xj[r] * xi[r];
-#pragma unroll
-        for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (sl == 0) coef[j] = s;
-      }
+    if (xl) {
+      for (int r = tid; r < k; r += blockDim.x) xl[r] = xi[r];
       __syncthreads();
-      if (part < np) {
-        double acc = 0.0;
-        if (row < k)
-          for (int j = part; j < i; j += np) acc += coef[j] * xs[(int64_t)j * k + row];
-        red[part * rb + row] = acc;
-      }
+      cgs2_vec(xs, xl, i, k, coef, s_nrm, red);
+      for (int r = tid; r < k; r += blockDim.x) xi[r] = xl[r];
       __syncthreads();
-      if (part == 0 && row < k) {
-        double s = 0.0;
-        for (int p = 0; p < np; ++p) s += red[p * rb + row];
-        xi[row] -= s;
-      }
-      __syncthreads();
+    } else {
+      cgs2_vec(xs, xi, i, k, coef, s_nrm, red);
     }
-    if (wave == 0) {
-      double s = 0.0;
-      for (int r = lane; r < k; r += 64) s += xi[r] * xi[r];
-      s = wave_sum(s);
-      if (lane == 0) *s_nrm = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-    }
-    __syncthreads();
-    const double sc = *s_nrm;
-    for (int r = tid; r < k; r += blockDim.x) xi[r] *= sc;
-    __syncthreads();
   }
 }
 
@@ -2128,7 +2244,7 @@ __global__ __launch_bounds__(1024) void psvd_orth_kernel(PsvdArgs args, GroupRef
         for (int q = tid; q < c * k; q += blockDim.x) xg[q] = xs[q];
         __syncthreads();
       } else {
-        cgs2_block(xg, k, c, coef, &s_nrm, (QSK_LDS double *)pool);
+        cgs2_block(xg, k, c, coef, &s_nrm, (QSK_LDS double *)pool, (QSK_LDS double *)pool + 1024);
       }
     }
     c0 = c1;

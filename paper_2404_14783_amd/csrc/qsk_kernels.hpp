@@ -7,6 +7,8 @@
 
 namespace qsk {
 
+struct SmallStatus;
+
 enum : int { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_FP8 = 3 };
 enum : int { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16 = 2, MODE_FP8 = 3 };
 
@@ -102,7 +104,8 @@ hipError_t stage_psi(const SketchArgs &s, const MfmaStage &g);
 // `partials` (size >= nchunks * k1 * k2 * 4 doubles) when rows > chunk.
 hipError_t launch_crossprod(hipStream_t st, int t1, const void *const z1[4], int64_t ld1,
                             int t2, const void *const z2[4], int64_t ld2, int64_t rows, int k1,
-                            int k2, double *partials, int64_t partial_elems, double *out_aos);
+                            int k2, double *partials, int64_t partial_elems, double *out_aos,
+                            const SmallStatus *gate = nullptr);
 // Same product written to planar FP64 output (used for X = S^* W).
 hipError_t launch_crossprod_planar(hipStream_t st, const double *const z1[4], int64_t ld1,
                                    int t2, const void *const z2[4], int64_t ld2, int64_t rows,
@@ -110,7 +113,7 @@ hipError_t launch_crossprod_planar(hipStream_t st, const double *const z1[4], in
 // Out (rows x kc, planar FP64) = Z (rows x k, planar, type tz) * C (k x kc, AoS, ldc = k).
 hipError_t launch_apply(hipStream_t st, int tz, const void *const z[4], int64_t ldz, int64_t rows,
                         int k, const double *c_aos, int kc, double *const out[4], int64_t ldo,
-                        int c_upper = 0);
+                        int c_upper = 0, const SmallStatus *gate = nullptr);
 // P (l x k, planar FP64) = Psi H with Psi regenerated as the sketch of `mode` used it.
 hipError_t launch_psi_apply(hipStream_t st, int mode, int rad, uint32_t k0, uint32_t k1, int l,
                             int64_t m, const double *const h[4], int64_t ldh, int k,
@@ -163,7 +166,15 @@ struct SmallStatus {
   double orth_defect;
   int good_count;
   int fail_any;        // sticky: some Cholesky since the last full reset failed
+  double gate;         // core solve: trace(G_P) ||R_1^{-1}||_F^2 (0: not formed)
 };
+
+// The core solve's second CholeskyQR pass is skipped when the first factor
+// R_1 of P = Psi Q has kappa_F(R_1)^2 = trace(G_P) ||R_1^{-1}||_F^2 (an upper
+// bound on kappa_2(P)^2) at most this: the normal-form solve with R_1 then
+// has relative error below about 1e6 u.  Kernels given a gate status return
+// at once when its gate lies in (0, ONE_PASS_KAPPA2].
+constexpr double ONE_PASS_KAPPA2 = 1e6;
 
 // ---------------------------------------------------------------------------
 // Argument structs of the FP64 finalize kernels.  Every kernel takes its
@@ -187,11 +198,13 @@ struct Gemm64Args {         // C = opA(A) B, quaternion, FP64 matrix cores (16 x
   double *partial;                        // split K: [chunk][N][M] AoS partial sums
   int herm;                               // C Hermitian (A = B, conj): tiles tm <= tn only
   int b_upper;                            // B upper triangular: t < 16 (tn + 1) only
+  const SmallStatus *gate;                // skip when its gate passes (see ONE_PASS_KAPPA2)
   int gx, gy;
 };
 struct ReduceArgs {
   const double *partial; int nchunks; int64_t elems; double *out;
   int herm, m;              // herm: tiles below the diagonal (16 x 16, m rows) mirror the ones above
+  const SmallStatus *gate;
   int gx, gy;
 };
 struct ReducePlanarArgs {
@@ -232,9 +245,14 @@ struct CholArgs {           // R = chol(G'), T = R^{-1}
   double *r, *t;
   SmallStatus *status;
   int only_failed;          // factor only where status->fail is set (the shifted retry)
+  const SmallStatus *gate;
   int gx, gy;
 };
-struct GemmArgs { int k; const double *a; int opa; const double *b; int opb; double *c; int gx, gy; };
+struct GemmArgs {
+  int k; const double *a; int opa; const double *b; int opb; double *c;
+  const SmallStatus *gate;
+  int gx, gy;
+};
 struct PowerArgs {
   int k; const double *gi; int step, n_power; uint32_t k0, k1; double *m_out; SmallStatus *status;
   int gx, gy;
@@ -253,10 +271,14 @@ struct KappaArgs { int k; const double *gh; double *work; int which; SmallStatus
 // zeroed) when complex_only; plus `shift` * I when shift > 0; T = R^{-1}.
 // A pivot^2 <= tol * max diagonal counts as a failure.
 hipError_t launch_chol_inv(hipStream_t st, const double *g, int k, int complex_only, double shift,
-                           double tol, double *r, double *t, SmallStatus *status);
+                           double tol, double *r, double *t, SmallStatus *status,
+                           const SmallStatus *gate = nullptr);
 // C = opA(A) * opB(B) (k x k AoS; op = 0 none, 1 conjugate transpose).
 hipError_t launch_small_gemm(hipStream_t st, int k, const double *a, int opa, const double *b,
-                             int opb, double *c);
+                             int opb, double *c, const SmallStatus *gate = nullptr);
+// C = T (k x k AoS copy) and status->gate = status->trace * ||T||_F^2 (the
+// core solve's one-pass test, after the Cholesky of G_P wrote the trace).
+hipError_t launch_core_gate(hipStream_t st, int k, const double *t, double *c, SmallStatus *status);
 // One pseudo-QR correction step's eps (power iteration on G^{-1}, recorded
 // in status->eps) and M = (1 - eps) I + eps G^{-1}, given gi = G^{-1}.
 hipError_t launch_power_m(hipStream_t st, int k, const double *gi, int step, int n_power,

@@ -999,21 +999,40 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
     HIPCHK(ctx, qsk::launch_pinv_sstar(st, l, k, pp, l, 1e-13, ctx->pinv_work, sp, l));
     have_sstar = true;
   } else {
-    HIPCHK(ctx, qsk::launch_apply(st, 0, (const void *const *)pp, l, l, k, slot(ctx, S_TP1), k, p1, l, 1));
-    HIPCHK(ctx, qsk::launch_crossprod(st, 0, (const void *const *)p1, l, 0, (const void *const *)p1,
-                                      l, l, k, k, ctx->partials, ctx->partial_elems, slot(ctx, S_GP)));
-    HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GP), k, 0, 0.0, 1e-13, slot(ctx, S_RP),
-                                     slot(ctx, S_TP2), ctx->status));
-    if (!opt) {
+    // R^{-1} = TP1 alone when kappa_F(R_1)^2 = trace(G_P) ||TP1||_F^2 (an
+    // upper bound on kappa_2(P)^2) is small enough for the normal-form
+    // solve below; else a second CholeskyQR pass, R^{-1} = TP1 TP2.  The
+    // optimistic run decides on the device: the second pass's launches are
+    // given the gate status and return at once when the gate passes.
+    HIPCHK(ctx, qsk::launch_core_gate(st, k, slot(ctx, S_TP1), slot(ctx, S_TPT), ctx->status));
+    bool second = true;
+    const SmallStatus *gate = nullptr;
+    if (opt) {
+      gate = ctx->status;
+    } else {
       HIPCHK(ctx, hipMemcpyAsync(&ps, ctx->status, sizeof(ps), hipMemcpyDeviceToHost, st));
       HIPCHK(ctx, hipStreamSynchronize(st));
+      second = !(ps.gate > 0.0 && ps.gate <= qsk::ONE_PASS_KAPPA2);
     }
-    if (ps.fail) {
-      flags |= QSK_FLAG_RANK_DEFICIENT;
-      HIPCHK(ctx, qsk::launch_pinv_sstar(st, l, k, pp, l, 1e-13, ctx->pinv_work, sp, l));
-      have_sstar = true;
-    } else {
-      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_TP1), 0, slot(ctx, S_TP2), 0, slot(ctx, S_TPT)));
+    if (second) {
+      HIPCHK(ctx, qsk::launch_apply(st, 0, (const void *const *)pp, l, l, k, slot(ctx, S_TP1), k, p1, l, 1,
+                                    gate));
+      HIPCHK(ctx, qsk::launch_crossprod(st, 0, (const void *const *)p1, l, 0, (const void *const *)p1,
+                                        l, l, k, k, ctx->partials, ctx->partial_elems, slot(ctx, S_GP), gate));
+      HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GP), k, 0, 0.0, 1e-13, slot(ctx, S_RP),
+                                       slot(ctx, S_TP2), ctx->status, gate));
+      if (!opt) {
+        HIPCHK(ctx, hipMemcpyAsync(&ps, ctx->status, sizeof(ps), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+      }
+      if (ps.fail) {
+        flags |= QSK_FLAG_RANK_DEFICIENT;
+        HIPCHK(ctx, qsk::launch_pinv_sstar(st, l, k, pp, l, 1e-13, ctx->pinv_work, sp, l));
+        have_sstar = true;
+      } else {
+        HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_TP1), 0, slot(ctx, S_TP2), 0, slot(ctx, S_TPT),
+                                           gate));
+      }
     }
   }
   // Z = R^{-1} R^{-*} with R^{-1} = TPT; S^* = P Z; X = S W = (S^*)^* W
