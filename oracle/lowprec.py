@@ -15,7 +15,11 @@ GPU feeds its matrix units, and then does all arithmetic on them in FP64:
   * fp8 block quantisation with power-of-two scales: for each block,
     scale = 2^ceil(log2(amax / 448)) so that a / scale fits e4m3 and
     dequantisation q * scale is exact; the FP32 residual a - q * scale is
-    then exact as well.
+    then exact as well;
+  * the same block quantisation carried on as T e4m3 terms: term t
+    quantises what the earlier terms left, r_t / (scale 16^-t), so that
+    a ~ sum_t q_t scale 16^-t (every term an e4m3 value times a power of
+    two, every r_t exact in FP32).
 
 All rounding here is from the exact (float64) value in a single step.
 """
@@ -111,6 +115,34 @@ def quantize_e4m3_blocks(a, block_rows, block_cols):
     return q * s_full, scales
 
 
+E4M3_TERM_SHIFT = 16.0             # term t of the multi-term split uses scale * 16^-t
+
+
+def quantize_e4m3_terms(a, block_rows, block_cols, terms):
+    """Quantise a 2-D float64 array (FP32-exact values) to ``terms`` e4m3
+    terms with one power-of-two scale s per (block_rows x block_cols) tile:
+    r_0 = a, q_t = e4m3(r_t / (s 16^-t)) (RNE), r_{t+1} = r_t - q_t s 16^-t.
+    After term 0, |r_1| <= 16 s (half a step of e4m3 at 448), so
+    r_1 / (s / 16) <= 256 and no later term saturates.  Returns (the list of
+    dequantised terms q_t s 16^-t, the tile scales)."""
+    a = np.asarray(a, dtype=np.float64)
+    m, n = a.shape
+    gm, gn = -(-m // block_rows), -(-n // block_cols)
+    pad = np.zeros((gm * block_rows, gn * block_cols))
+    pad[:m, :n] = np.abs(a)
+    amax = pad.reshape(gm, block_rows, gn, block_cols).max(axis=(1, 3))
+    scales = pow2_scale(amax)
+    s_full = np.repeat(np.repeat(scales, block_rows, axis=0), block_cols, axis=1)[:m, :n]
+    out = []
+    rem = a.copy()
+    for t in range(terms):
+        st = s_full / E4M3_TERM_SHIFT ** t          # exact: powers of two
+        d = round_e4m3(rem / st) * st
+        out.append(d)
+        rem = rem - d                                # exact in FP32 (and here)
+    return out, scales
+
+
 def round_dtype(x, dtype):
     """Round exact values to the named operand format."""
     if dtype == "f64":
@@ -119,6 +151,6 @@ def round_dtype(x, dtype):
         return round_f32(x)
     if dtype == "bf16":
         return round_bf16(x)
-    if dtype == "fp8":
+    if dtype in ("fp8", "fp8x"):
         return round_e4m3(x)
     raise ValueError(dtype)

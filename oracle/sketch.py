@@ -29,8 +29,10 @@ from . import embeddings, lowprec, quaternion as qt
 class SketchConfig:
     """m, n: A in Q^{m x n}; k, l: sketch sizes (paper s, l), r <= s <= l
     (Section 4.1); embedding 'gaussian' or 'rademacher'; dtype of the sketch
-    operands 'f64' | 'f32' | 'bf16' | 'fp8'; terms: number of bf16 terms of
-    the residual split of the data (bf16 only); fp8_block: tile edge of the
+    operands 'f64' | 'f32' | 'bf16' | 'fp8' | 'fp8x'; terms: number of bf16
+    terms of the residual split of the data (bf16), or of e4m3 terms of the
+    block quantisation ('fp8x': q_t with scales 16^-t times the tile scale,
+    the residual carried on in e4m3); fp8_block: tile edge of the
     power-of-two fp8 scales; fp8_residual: add the exact FP32 residual of
     the fp8 quantisation as a second term; embedding_dtype: the format of the
     test-matrix values when it differs from the operand dtype (an FP64 sketch
@@ -54,7 +56,8 @@ class SketchConfig:
 def data_operand(block, cfg):
     """The value of a block of A that the sketch multiplies, per the operand
     format: FP64/FP32 data as given; bf16: sum of the split terms; fp8: the
-    dequantised block (plus the exact residual when enabled)."""
+    dequantised block (plus the exact residual when enabled); fp8x: the sum
+    of the e4m3 terms."""
     block = qt.as_planes(block)
     if cfg.dtype in ("f64", "f32"):
         return block
@@ -65,6 +68,12 @@ def data_operand(block, cfg):
         for p in range(4):
             deq, _ = lowprec.quantize_e4m3_blocks(block[p], cfg.fp8_block, cfg.fp8_block)
             out[p] = deq + (block[p] - deq if cfg.fp8_residual else 0.0)
+        return out
+    if cfg.dtype == "fp8x":
+        out = np.empty_like(block)
+        for p in range(4):
+            terms, _ = lowprec.quantize_e4m3_terms(block[p], cfg.fp8_block, cfg.fp8_block, cfg.terms)
+            out[p] = sum(terms)
         return out
     raise ValueError(cfg.dtype)
 

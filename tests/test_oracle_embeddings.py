@@ -175,3 +175,58 @@ def test_diag_f_distribution():
     assert ks < 1.95 / np.sqrt(n)
     assert not np.array_equal(embeddings.diag_f(64, 5), embeddings.diag_f(64, 6))
     np.testing.assert_array_equal(embeddings.diag_f(64, 5), f[:64])
+
+
+def _e4m3_terms_torch(a, s, terms):
+    """Independent scalar reference of the multi-term e4m3 split: PyTorch's
+    float8_e4m3fn cast (RNE) one element at a time, float64 arithmetic."""
+    out = np.zeros((terms,) + a.shape)
+    for idx in np.ndindex(a.shape):
+        r = float(a[idx])
+        for t in range(terms):
+            st = float(s[idx]) / 16.0 ** t
+            q = float(torch.tensor(r / st, dtype=torch.float64).to(torch.float8_e4m3fn).double())
+            out[(t,) + idx] = q * st
+            r -= q * st
+    return out
+
+
+def test_e4m3_term_split():
+    """Multi-term e4m3 block quantisation: term 0 is the plain block
+    quantisation; every term is an e4m3 value times scale 16^-t (a PyTorch
+    float8_e4m3fn round trip leaves it unchanged); the terms agree with an
+    element-by-element reference built on PyTorch's cast; what is left after
+    T terms is at most 16 s 16^(1-T) per element; data that are e4m3 values
+    times the tile scale are exact in one term."""
+    rng = np.random.default_rng(5)
+    a = (rng.standard_normal((70, 45)) * np.exp(rng.uniform(-6, 3, (70, 45)))).astype(np.float32).astype(np.float64)
+    a[:32, :32] *= 1e-3                               # tiles of very different scales
+    a[40:, 32:] = 0.0                                 # an all-zero tile
+    deq1, sc1 = lowprec.quantize_e4m3_blocks(a, 32, 32)
+    for terms in (1, 2, 3, 4):
+        parts, sc = lowprec.quantize_e4m3_terms(a, 32, 32, terms)
+        np.testing.assert_array_equal(sc, sc1)
+        np.testing.assert_array_equal(parts[0], deq1)
+        s_full = np.repeat(np.repeat(sc, 32, axis=0), 32, axis=1)[:70, :45]
+        for t, d in enumerate(parts):
+            q = d / (s_full / 16.0 ** t)
+            rt = torch.from_numpy(q.astype(np.float32)).to(torch.float8_e4m3fn).double().numpy()
+            np.testing.assert_array_equal(rt, q)
+            assert np.abs(q).max() <= (448.0 if t == 0 else 256.0)
+        left = a - sum(parts)
+        assert np.all(np.abs(left) <= 16.0 * s_full * 16.0 ** (1 - terms))
+        if terms == 4:
+            # four terms carry about as many bits as two bf16 terms near the tile maximum
+            rel = np.abs(left).max() / np.abs(a).max()
+            assert rel < 2.0 ** -16
+    sub = a[32:64, :32]
+    ref = _e4m3_terms_torch(sub, np.full(sub.shape, lowprec.pow2_scale(np.abs(sub).max())), 3)
+    parts, _ = lowprec.quantize_e4m3_terms(sub, 32, 32, 3)
+    np.testing.assert_array_equal(np.stack(parts), ref)
+    # exact data in one term
+    s = 2.0 ** -5
+    vals = lowprec.round_e4m3(rng.uniform(-448, 448, (32, 32))) * s
+    vals[0, 0] = 448 * s                              # fixes the tile scale at s
+    parts, sc = lowprec.quantize_e4m3_terms(vals, 32, 32, 1)
+    assert sc[0, 0] == s
+    np.testing.assert_array_equal(parts[0], vals)
