@@ -53,6 +53,7 @@ import synth  # noqa: E402
 
 PEAK_BF16 = 2.5e15     # dense bf16 MFMA, MI355X
 PEAK_F32 = 157.3e12    # fp32 MFMA
+PEAK_FP8 = 5.0e15      # dense fp8 MFMA
 PEAK_HBM = 8e12
 CALIB_BYTES = 256 << 20                    # the plain copy used to scale the HBM counters
 KERNEL_SRC = os.path.join(ROOT, "paper_2404_14783_amd", "csrc", "sketch_mfma.hip")
@@ -247,6 +248,55 @@ def summarize_stats(directory, cmd, out_path, workload="c2"):
     print("\n".join(lines[:30]))
 
 
+BUSY_COUNTERS = ("SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_MFMA "
+                 "SQ_INSTS_VALU SQ_WAIT_ANY SQ_INSTS_LDS")
+
+
+def summarize_busy(directory, cmd, out_path, workload="c2"):
+    """Matrix-core busy fraction per library kernel from one rocprofv3 --pmc
+    pass over BUSY_COUNTERS: SQ_VALU_MFMA_BUSY_CYCLES over (1024 SIMDs x the
+    dispatch's duration x 2.4 GHz), averaged over the dispatches."""
+    rows = _pmc_rows(directory)
+    per = {}
+    for r in rows:
+        name = r.get("Kernel_Name", "")
+        if not name.startswith(("qsk::", "void qsk::")):
+            continue
+        d = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        rec = per.setdefault(name, {}).setdefault(d, {"dur": (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9})
+        rec[r["Counter_Name"]] = rec.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    title, _ = STATS_TITLES[workload]
+    lines = [
+        f"# Matrix-core busy time: {title}",
+        "",
+        "One counter pass (from the repository root, on one MI355X):",
+        "",
+        f"    {cmd}",
+        "",
+        "busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x duration x 2.4 GHz): the fraction of the",
+        "kernel's time the matrix cores of the whole chip were busy (duration from the dispatch",
+        "timestamps of the counter pass).  Per dispatch averages, library kernels of 40 us or more.",
+        "",
+        "| kernel | dispatches | avg us | MFMA instr | MFMA busy | VALU instr | LDS instr |",
+        "|---|---:|---:|---:|---:|---:|---:|",
+    ]
+    out = []
+    for name, ds in per.items():
+        recs = list(ds.values())
+        dur = float(np.mean([x["dur"] for x in recs]))
+        if dur < 40e-6:
+            continue
+        busy = float(np.mean([x.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (1024 * x["dur"] * 2.4e9) for x in recs]))
+        mean = lambda c: float(np.mean([x.get(c, 0.0) for x in recs]))
+        out.append((dur * len(recs), f"| `{name.replace('|', '/')[:100]}` | {len(recs)} | {dur * 1e6:.1f} | "
+                    f"{mean('SQ_INSTS_MFMA'):.3g} | {busy:.2f} | {mean('SQ_INSTS_VALU'):.3g} | "
+                    f"{mean('SQ_INSTS_LDS'):.3g} |"))
+    lines += [s for _, s in sorted(out, reverse=True)]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def committed_traffic():
     """Per-launch HBM bytes of the W kernel from the committed counter
     summary, or None when the kernel source changed since it was taken."""
@@ -380,7 +430,7 @@ def kernel_rooflines(timing, m, n, k, l, pure, steps, peak, y_bytes_per_update=N
     return out
 
 
-EMB_ROUND = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}
+EMB_ROUND = {"fp32": "f32", "f32": "f32", "bf16": "bf16", "fp8": "fp8", "fp8x": "fp8"}
 
 
 def fp64_reference(a, m, n, k, l, block, emb, input_dtype, pure, rnd):
@@ -408,8 +458,7 @@ def bench_stream_leg(args, label, a, m, n, k, l, block, emb, input_dtype, pure, 
     for path in paths:
         name, sketch, terms = path[:3]
         coalesce = path[3] if len(path) > 3 else 0
-        base = name.split("_")[0]
-        rnd = "f64" if emb == "rademacher" else EMB_ROUND[base]      # +-1 is exact in every format
+        rnd = "f64" if emb == "rademacher" else EMB_ROUND[sketch]    # +-1 is exact in every format
         if rnd not in refs:
             log(f"[bench] {label}: FP64 reference pass, test matrices rounded to {rnd} (untimed)")
             refs[rnd] = fp64_reference(a, m, n, k, l, ref_block or block, emb, input_dtype, pure, rnd)
@@ -429,7 +478,9 @@ def bench_stream_leg(args, label, a, m, n, k, l, block, emb, input_dtype, pure, 
         if eff < 64:
             # streamed in thin blocks: Y's read-modify-write dominates the traffic
             ybytes = (3 if pure else 4) * m * (n / nupd) * (4 if input_dtype == "f32" else 2) + 2 * 4 * m * k * 4
-        rec["kernels"] = kernel_rooflines(timing, m, n, k, l, pure, args.steps, peak, ybytes, nupd)
+        rec["kernels"] = kernel_rooflines(timing, m, n, k, l, pure, args.steps,
+                                          PEAK_FP8 if sketch == "fp8x" else peak, ybytes, nupd)
+        rec["peak_tflops"] = (PEAK_FP8 if sketch == "fp8x" else peak) / 1e12
         res[name] = rec
         log(f"[bench] {label} {name}: updates {up:.2f} ms, step {tot:.2f} ms, "
             f"{rec['sketch_tflops']:.1f} TFLOP/s, kernels {rec['kernels']}")
@@ -440,7 +491,7 @@ def bench_stream_leg(args, label, a, m, n, k, l, block, emb, input_dtype, pure, 
         eq[kind] = {}
         for path in paths:
             name = path[0]
-            rnd = "f64" if emb == "rademacher" else EMB_ROUND[name.split("_")[0]]
+            rnd = "f64" if emb == "rademacher" else EMB_ROUND[path[1]]
             ref = refs[rnd][0][kind]
             e = errors[(name, kind)]
             eq[kind]["e_fp64_" + rnd] = ref
@@ -544,7 +595,9 @@ def bench_flow(args, profile_only=False):
     co = args.coalesce
     leg = bench_stream_leg(args, "flow", a, m, n, k, l, block, "gaussian", "f32", True,
                            [("fp8", "fp8", 2), ("fp8_coalesced", "fp8", 2, co),
-                            ("bf16", "bf16", 2), ("bf16_coalesced", "bf16", 2, co)],
+                            ("bf16", "bf16", 2), ("bf16_coalesced", "bf16", 2, co),
+                            ("fp8x3_coalesced", "fp8x", 3, args.coalesce_fp8x),
+                            ("fp8x4_coalesced", "fp8x", 4, args.coalesce_fp8x)],
                            PEAK_BF16, ref_block=n)
     leg["update_graph"] = {}
     for name, co_cols in (("fp8", 0), ("fp8_coalesced", co)):
@@ -645,6 +698,9 @@ def main():
                          "within 1e-3 of the FP64 path's)")
     ap.add_argument("--coalesce", type=int, default=150,
                     help="flow workload: columns gathered per sketch product (coalesce_cols)")
+    ap.add_argument("--coalesce-fp8x", type=int, default=128,
+                    help="flow workload, e4m3-term paths: columns gathered per product (the fp8 "
+                         "products take 128 columns per step of Y)")
     ap.add_argument("--profile-only", action="store_true",
                     help="one bf16 pass only (for rocprofv3 runs)")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CMD_FETCH", "CMD_WRITE"),
@@ -654,7 +710,12 @@ def main():
                          "and flow workloads in the same line; or one of them alone")
     ap.add_argument("--summarize-stats", nargs=3, metavar=("DIR", "CMD", "OUT"),
                     help="write a kernel-time summary from a rocprofv3 --stats run")
+    ap.add_argument("--summarize-busy", nargs=3, metavar=("DIR", "CMD", "OUT"),
+                    help="write a matrix-core busy summary from a rocprofv3 --pmc run")
     args = ap.parse_args()
+    if args.summarize_busy:
+        summarize_busy(*args.summarize_busy, workload="c2" if args.workload == "all" else args.workload)
+        return
     if args.summarize_stats:
         summarize_stats(*args.summarize_stats, workload="c2" if args.workload == "all" else args.workload)
         return

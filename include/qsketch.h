@@ -72,8 +72,20 @@ typedef enum {
               value; FP32 accumulation, FP32 Y/W.  The dequantised fp8 values
               are exact in bf16 and all terms run on the bf16 matrix-core
               product.  Update blocks whose planes need byte offsets of 2^32
-              or more return QSK_E_UNSUPPORTED in this format. */
-typedef enum { QSK_F64 = 0, QSK_F32 = 1, QSK_BF16 = 2, QSK_FP8_E4M3 = 3 } qsk_dtype;
+              or more return QSK_E_UNSUPPORTED in this format;
+     QSK_FP8_MFMA the same tile scales, the data carried as split_terms
+              (1..4) e4m3 terms: term t quantises (RNE) what the earlier terms
+              left at scale (tile scale) 16^-t, so the operand is
+              sum_t q_t scale 16^-t (after term 0 the rest is at most 16 scale
+              per value, so no later term saturates; four terms carry about as
+              many bits as two bf16 terms near the tile maximum).  Every term
+              runs on the fp8 matrix cores (e4m3 x e4m3 with the tile
+              exponent as the block scale, FP32 accumulation); the block is
+              quantised once per update into bytes (2 split_terms bytes per
+              value and plane); test matrices rounded to e4m3.  Update blocks
+              whose quantised planes need 2^32 bytes or more return
+              QSK_E_UNSUPPORTED.  Not for batches. */
+typedef enum { QSK_F64 = 0, QSK_F32 = 1, QSK_BF16 = 2, QSK_FP8_E4M3 = 3, QSK_FP8_MFMA = 4 } qsk_dtype;
 
 /* Test-matrix distributions: quaternion standard Gaussian, all four
    components i.i.d. N(0,1) (Def. 4.1); quaternion Rademacher, components
@@ -105,7 +117,8 @@ typedef struct {
   int32_t input_dtype;     /* QSK_F64 | QSK_F32 | QSK_BF16 */
   int32_t sketch_dtype;    /* qsk_dtype, see above */
   int32_t pure;            /* 1: A has no real part; planes[0] is ignored (may be NULL) */
-  int32_t split_terms;     /* BF16: 1..3; FP8: 1 or 2 (2 = add FP32 residual term) */
+  int32_t split_terms;     /* BF16: 1..3; FP8: 1 or 2 (2 = add FP32 residual term);
+                              FP8_MFMA: 1..4 e4m3 terms */
   int32_t n_correction;    /* pseudo-QR correction steps, 0..8 (paper: "often 3") */
   int32_t n_power;         /* power iterates per correction step for eps (paper: 2-3) */
   int64_t max_block_cols;  /* largest ncols of one update; 0 means n */

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libqsketch.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "qsketch.h")
 
 QSK_OK, QSK_E_ARG, QSK_E_STATE, QSK_E_NOMEM, QSK_E_HIP, QSK_E_NUMERIC, QSK_E_UNSUPPORTED = range(7)
-DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3, "fp8x": 4}
 EMBEDDINGS = {"gaussian": 0, "rademacher": 1}
 RANGEFINDERS = {"pseudo_qr": 0, "pseudo_svd": 1, "pseudo_svd_gs": 2}
 FLAG_NAMES = {1: "chol_fallback", 2: "rank_deficient", 4: "nonfinite", 8: "bad_pairs"}

@@ -835,7 +835,7 @@ qsk_status qsketch_batch_init(int32_t count, const qsk_config *cfgs, void *hip_s
     if (c.k < 1 || c.l < c.k || c.l > c.m || c.l > c.n || c.k > 256 || c.l > 1024) return QSK_E_ARG;
     if (c.embedding != QSK_GAUSSIAN && c.embedding != QSK_RADEMACHER) return QSK_E_ARG;
     if (c.input_dtype < QSK_F64 || c.input_dtype > QSK_BF16) return QSK_E_ARG;
-    if (c.sketch_dtype < QSK_F64 || c.sketch_dtype > QSK_FP8_E4M3) return QSK_E_ARG;
+    if (c.sketch_dtype < QSK_F64 || c.sketch_dtype > QSK_FP8_MFMA) return QSK_E_ARG;
     if (c.n_correction < 0 || c.n_correction > 8 || c.n_power < 1 || c.n_power > 64) return QSK_E_ARG;
     if (c.sketch_dtype == QSK_BF16 && (c.split_terms < 1 || c.split_terms > 3)) return QSK_E_ARG;
     if (c.y_only || c.embedding_round != QSK_F64 || c.coalesce_cols != 0) return QSK_E_ARG;

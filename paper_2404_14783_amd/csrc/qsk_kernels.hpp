@@ -8,14 +8,31 @@
 namespace qsk {
 
 struct SmallStatus;
+struct SketchArgs;
 
 enum : int { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_FP8 = 3 };
-enum : int { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16 = 2, MODE_FP8 = 3 };
+enum : int { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16 = 2, MODE_FP8 = 3, MODE_FP8X = 4 };
 
 template <typename T> struct PlanesC { const T *p[4]; };
 template <typename T> struct Planes { T *p[4]; };
 
 // One column-block update of the sketches.
+// Buffers of the FP8X format (e4m3 terms on the fp8 matrix cores): the
+// update block quantised into T e4m3 terms, [q][t][column < CPW][row < RP]
+// (qw, for the W product) and [q][t][row < RP][column < CP] (qy, for the Y
+// product), and the test matrices as e4m3 bytes, Psi [4][LP][MPF] and
+// Omega_J [4][KP][NPF].
+struct Fp8xStage {
+  uint8_t *qw = nullptr, *qy = nullptr, *psi = nullptr, *om = nullptr;
+  int64_t RP = 0, CPW = 0, CP = 0, MPF = 0, NPF = 0;
+  int LP = 0, KP = 0, NMT = 0, NJ = 0, T = 0, planes = 0;
+  int64_t qw_bytes = 0, qy_bytes = 0, psi_bytes = 0, om_bytes = 0;
+};
+void fp8x_geometry(int64_t m, int l, int k, int64_t maxcols, int terms, int pure, Fp8xStage *f);
+// Psi into the e4m3 staging of the FP8X format (done by the first update).
+hipError_t stage_psi8(const SketchArgs &s, const Fp8xStage &f);
+int fp8x_nmt(int l);
+
 struct SketchArgs {
   hipStream_t stream;
   int mode;              // MODE_*
@@ -42,6 +59,7 @@ struct SketchArgs {
   int emode = -1;        // format of the test-matrix values (MODE_*); -1: that of `mode`
   int gen_rad = 1;       // matrix-core path: Rademacher tiles generated in the kernels (not staged)
   int *y_splits = nullptr;  // out (may be null): copies of Y the update added into
+  const Fp8xStage *f8 = nullptr;  // FP8X buffers
   // optional timing: events[2 * kernel] before, [2 * kernel + 1] after (may be null)
   hipEvent_t *events;
 };

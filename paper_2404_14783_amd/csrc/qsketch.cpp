@@ -100,6 +100,8 @@ struct qsk_ctx {
   int use_mfma = 1;
   int gen_rad = 1;                     // Rademacher tiles generated in the product kernels
   bool psi_staged = false;             // stage.psi holds Psi as the sketch used it
+  bool psi8_staged = false;            // f8.psi holds Psi (FP8X)
+  qsk::Fp8xStage f8;                   // FP8X buffers
   void *zero_plane = nullptr;          // zeroed real plane for qsketch_project on pure input
   size_t zero_plane_bytes = 0;
   double *xt = nullptr;                // X^* (n x k planes) for qsketch_truncate
@@ -223,7 +225,8 @@ void free_all(qsk_ctx *c) {
   c->side = nullptr;
   void *ptrs[] = {c->y, c->w, c->u[0], c->u[1], c->small, c->work, c->partials, c->pbuf,
                   c->p1buf, c->sbuf, c->err_acc, c->status, c->w_scratch, c->pinv_work,
-                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus, c->fp8_scales, c->zero_plane, c->xt, c->proj_part, c->pad, c->pend};
+                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus, c->fp8_scales, c->zero_plane, c->xt, c->proj_part, c->pad, c->pend,
+                  c->f8.qw, c->f8.qy, c->f8.psi, c->f8.om};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->y = c->w = nullptr;
@@ -236,6 +239,7 @@ void free_all(qsk_ctx *c) {
   c->kwork = nullptr;
   c->fp8_scales = nullptr;
   c->kstatus = nullptr;
+  c->f8.qw = c->f8.qy = c->f8.psi = c->f8.om = nullptr;
 }
 
 bool alloc(void **p, size_t bytes) {
@@ -315,13 +319,14 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   if (c.k < 1 || c.l < c.k || c.l > c.m || c.l > c.n || c.k > 256 || c.l > 1024) return QSK_E_ARG;
   if (c.embedding != QSK_GAUSSIAN && c.embedding != QSK_RADEMACHER) return QSK_E_ARG;
   if (c.input_dtype < QSK_F64 || c.input_dtype > QSK_BF16) return QSK_E_ARG;
-  if (c.sketch_dtype < QSK_F64 || c.sketch_dtype > QSK_FP8_E4M3) return QSK_E_ARG;
+  if (c.sketch_dtype < QSK_F64 || c.sketch_dtype > QSK_FP8_MFMA) return QSK_E_ARG;
   if (c.n_correction < 0 || c.n_correction > 8 || c.n_power < 1 || c.n_power > 64) return QSK_E_ARG;
   if (c.max_block_cols < 0) return QSK_E_ARG;
   if (c.y_only != 0 && c.y_only != 1) return QSK_E_ARG;
   if (c.coalesce_cols < 0 || c.coalesce_cols > c.n) return QSK_E_ARG;
   if (c.sketch_dtype == QSK_BF16 && (c.split_terms < 1 || c.split_terms > 3)) return QSK_E_ARG;
   if (c.sketch_dtype == QSK_FP8_E4M3 && (c.split_terms < 1 || c.split_terms > 2)) return QSK_E_ARG;
+  if (c.sketch_dtype == QSK_FP8_MFMA && (c.split_terms < 1 || c.split_terms > 4)) return QSK_E_ARG;
   if (c.sketch_dtype != QSK_F64 && c.input_dtype == QSK_F64) return QSK_E_UNSUPPORTED;
   if (c.embedding_round < QSK_F64 || c.embedding_round > QSK_FP8_E4M3) return QSK_E_ARG;
   if (c.embedding_round != QSK_F64 && c.sketch_dtype != QSK_F64) return QSK_E_ARG;
@@ -331,10 +336,13 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   ctx->cfg = c;
   if (ctx->cfg.max_block_cols == 0 || ctx->cfg.max_block_cols > c.n) ctx->cfg.max_block_cols = c.n;
   ctx->work_cols = std::max<int64_t>(ctx->cfg.max_block_cols, c.coalesce_cols);
-  if (ctx->cfg.sketch_dtype != QSK_BF16 && ctx->cfg.sketch_dtype != QSK_FP8_E4M3) ctx->cfg.split_terms = 1;
+  if (ctx->cfg.sketch_dtype != QSK_BF16 && ctx->cfg.sketch_dtype != QSK_FP8_E4M3 &&
+      ctx->cfg.sketch_dtype != QSK_FP8_MFMA)
+    ctx->cfg.split_terms = 1;
   ctx->stream = (hipStream_t)hip_stream;
   ctx->mode = c.sketch_dtype;     // MODE_* and QSK dtypes share the numbering
-  ctx->emode = c.sketch_dtype == QSK_F64 ? c.embedding_round : c.sketch_dtype;
+  ctx->emode = c.sketch_dtype == QSK_F64 ? c.embedding_round
+              : c.sketch_dtype == QSK_FP8_MFMA ? (int)qsk::MODE_FP8 : c.sketch_dtype;
   ctx->ts = c.sketch_dtype == QSK_F64 ? 8 : 4;
   ctx->k0 = (uint32_t)(c.seed & 0xFFFFFFFFull);
   ctx->k1 = (uint32_t)(c.seed >> 32);
@@ -353,7 +361,7 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   const size_t kk = (size_t)k * k * 4;
   bool ok = true;
   const bool mfma_mode = c.sketch_dtype == QSK_BF16 || c.sketch_dtype == QSK_F32 ||
-                         c.sketch_dtype == QSK_FP8_E4M3;
+                         c.sketch_dtype == QSK_FP8_E4M3 || c.sketch_dtype == QSK_FP8_MFMA;
   ctx->y_copies = mfma_mode ? qsk::Y_COPIES : 1;
   ok = ok && alloc(&ctx->y, (size_t)ctx->y_copies * 4 * m * k * ctx->ts);
   if (!c.y_only) ok = ok && alloc(&ctx->w, 4 * (size_t)l * n * ctx->ts);
@@ -381,9 +389,18 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
     const bool op16 = c.sketch_dtype != QSK_F32;     // bf16 operands (BF16, FP8 data)
     qsk::stage_geometry(m, (int)l, (int)k, ctx->work_cols, op16, &g.LP, &g.MP, &g.KP, &g.NP);
     const size_t es = op16 ? 2 : 4;
-    if (c.sketch_dtype == QSK_FP8_E4M3) {
+    if (c.sketch_dtype == QSK_FP8_E4M3 || c.sketch_dtype == QSK_FP8_MFMA) {
       ctx->fp8_scale_elems = 4 * ((m + 31) / 32) * ((ctx->work_cols + 31) / 32);
       ok = ok && alloc((void **)&ctx->fp8_scales, (size_t)ctx->fp8_scale_elems * 4);
+    }
+    if (c.sketch_dtype == QSK_FP8_MFMA) {
+      // the quantised block in both layouts and the e4m3 test matrices (the
+      // bf16 staging below keeps Psi's e4m3 values for the QB stage)
+      qsk::fp8x_geometry(m, (int)l, (int)k, ctx->work_cols, c.split_terms, c.pure, &ctx->f8);
+      ok = ok && alloc((void **)&ctx->f8.qw, (size_t)ctx->f8.qw_bytes);
+      ok = ok && alloc((void **)&ctx->f8.qy, (size_t)ctx->f8.qy_bytes);
+      ok = ok && alloc((void **)&ctx->f8.psi, (size_t)ctx->f8.psi_bytes);
+      ok = ok && alloc((void **)&ctx->f8.om, (size_t)ctx->f8.om_bytes);
     }
     ok = ok && alloc(&g.omega, 4 * (size_t)g.KP * g.NP * es);
     ok = ok && alloc(&g.psi, 4 * (size_t)g.LP * g.MP * es);
@@ -477,8 +494,9 @@ static qsk_status sketch_block(qsk_ctx *ctx, int64_t col0, int64_t ncols, const 
   s.scratch_bytes = ctx->w_scratch_bytes;
   s.fp8_scales = ctx->fp8_scales;
   s.fp8_scale_elems = ctx->fp8_scale_elems;
-  s.psi_ready = ctx->psi_staged ? 1 : 0;
+  s.psi_ready = (ctx->mode == qsk::MODE_FP8X ? ctx->psi8_staged : ctx->psi_staged) ? 1 : 0;
   s.gen_rad = ctx->gen_rad;
+  if (ctx->mode == qsk::MODE_FP8X) s.f8 = &ctx->f8;
   int splits = 1;
   s.y_splits = &splits;
   s.events = nullptr;
@@ -496,10 +514,11 @@ static qsk_status sketch_block(qsk_ctx *ctx, int64_t col0, int64_t ncols, const 
   hipError_t e = hipErrorNotSupported;
   if (ctx->use_mfma && ctx->mode != qsk::MODE_F64) {
     e = qsk::launch_sketch_mfma(s, ctx->stage);
-    if (e == hipSuccess && !c.y_only && !qsk::gen_in_kernel(s)) ctx->psi_staged = true;
+    if (e == hipSuccess && !c.y_only && ctx->mode == qsk::MODE_FP8X) ctx->psi8_staged = true;
+    else if (e == hipSuccess && !c.y_only && !qsk::gen_in_kernel(s)) ctx->psi_staged = true;
     if (e == hipSuccess && splits > ctx->y_dirty) ctx->y_dirty = splits;
   }
-  if (e == hipErrorNotSupported && ctx->mode == qsk::MODE_FP8) {
+  if (e == hipErrorNotSupported && (ctx->mode == qsk::MODE_FP8 || ctx->mode == qsk::MODE_FP8X)) {
     ctx->last_error = "fp8 sketch: block too large for the matrix-core path (32-bit offsets) or "
                       "matrix-core path disabled";
     return QSK_E_UNSUPPORTED;
@@ -592,7 +611,13 @@ qsk_status qsketch_update_many(qsk_ctx *ctx, int32_t count, const int64_t *col0,
   }
   // Psi is staged (once per context) outside the graph, so that replays do
   // not stage it again
-  if (ctx->use_mfma && ctx->mode != qsk::MODE_F64 && !c.y_only && !ctx->psi_staged) {
+  if (ctx->use_mfma && ctx->mode == qsk::MODE_FP8X && !c.y_only && !ctx->psi8_staged) {
+    qsk::SketchArgs sa{};
+    sa.stream = ctx->stream; sa.mode = ctx->mode; sa.l = c.l; sa.m = c.m; sa.k = c.k;
+    sa.rad = c.embedding == QSK_RADEMACHER; sa.k0 = ctx->k0; sa.k1 = ctx->k1;
+    HIPCHK(ctx, qsk::stage_psi8(sa, ctx->f8));
+    ctx->psi8_staged = true;
+  } else if (ctx->use_mfma && ctx->mode != qsk::MODE_F64 && !c.y_only && !ctx->psi_staged) {
     qsk::SketchArgs sa{};
     sa.stream = ctx->stream; sa.mode = ctx->mode; sa.l = c.l; sa.m = c.m; sa.k = c.k;
     sa.rad = c.embedding == QSK_RADEMACHER; sa.k0 = ctx->k0; sa.k1 = ctx->k1;
@@ -608,7 +633,7 @@ qsk_status qsketch_update_many(qsk_ctx *ctx, int32_t count, const int64_t *col0,
   key.push_back((uint64_t)count);
   key.push_back((uint64_t)ctx->pend_col0);
   key.push_back((uint64_t)ctx->pend_ncols);
-  key.push_back((uint64_t)ctx->psi_staged);
+  key.push_back((uint64_t)ctx->psi_staged | ((uint64_t)ctx->psi8_staged << 1));
   for (int32_t i = 0; i < count; ++i) {
     key.push_back((uint64_t)col0[i]);
     key.push_back((uint64_t)ncols[i]);

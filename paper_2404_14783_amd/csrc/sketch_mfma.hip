@@ -1229,7 +1229,7 @@ hipError_t stage_psi(const SketchArgs &s, const MfmaStage &g) {
   if (s.mode == MODE_BF16)
     return gen_stage<MODE_BF16, uint16_t>(s.stream, (uint16_t *)g.psi, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI,
                                           s.rad, s.k0, s.k1);
-  if (s.mode == MODE_FP8)
+  if (s.mode == MODE_FP8 || s.mode == MODE_FP8X)
     return gen_stage<MODE_FP8, uint16_t>(s.stream, (uint16_t *)g.psi, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI,
                                          s.rad, s.k0, s.k1);
   if (s.mode == MODE_F32)
@@ -1377,7 +1377,818 @@ hipError_t launch_sketch_mfma_batch(const SketchArgs *s, const MfmaStage *g, int
   return hipErrorNotSupported;
 }
 
+// ===========================================================================
+// FP8X: the data as T e4m3 terms with the 32 x 32 tile scales, all terms on
+// the fp8 matrix cores (v_mfma_scale_f32_16x16x128_f8f6f4, E8M0 block
+// scales, FP32 accumulation).  Term t of a value x quantises what the
+// earlier terms left at scale sc 16^-t (sc: the tile scale), so the operand
+// is sum_t q_t sc 16^-t with every q_t an e4m3 value.
+//
+// The update block is quantised once per update (fp8x_quant_kernel) into
+// bytes in two layouts: columns of rows (rows contiguous) for the W product,
+// whose contraction runs over the rows of A, and rows of columns (columns
+// contiguous) for the Y product, whose contraction runs over the columns;
+// the products then only move bytes and issue matrix-core instructions.
+// The test matrices are staged as e4m3 bytes.
+//
+// Operand layout of the instruction (16 x 128 A, 128 x 16 B; checked on the
+// device): lane L = r + 16 g (r: row of A, column of B) holds 32 bytes,
+// bytes 0-15 the contraction indices 16 g .. 16 g + 15 and bytes 16-31 the
+// indices 64 + 16 g .. 64 + 16 g + 15; the E8M0 scale of indices
+// 32 b .. 32 b + 31 is byte 0 of the scale operand of lane r + 16 b.  With
+// the 128 indices of a step in order, scale block b is rows (W) or columns
+// (Y) 32 b .. 32 b + 31 of the step: one tile of the data scales, whose
+// exponent lane r + 16 b supplies.
+typedef __attribute__((ext_vector_type(8))) int i32x8;
+
+__device__ __forceinline__ uint32_t e4m3_byte(float e4m3_value) {   // exact for e4m3 values
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(e4m3_value, 0.f, 0, false) & 0xFFu;
+}
+
+struct QuantArgs {
+  const void *a[4];
+  int64_t lda, m, ncols;
+  int pure, RT, CT, T;
+  float *fsc;                 // out: tile scales [4][RT][CT]
+  uint8_t *qw;                // [q][t][column < CPW][row < RP]
+  uint8_t *qy;                // [q][t][row < RP][column < CP]
+  int64_t RP, CPW, CP;
+};
+
+// Value of an e4m3 byte (OCP e4m3fn; the quantisation never produces NaN).
+__device__ __forceinline__ float e4m3_value(uint32_t b) {
+  const uint32_t e = (b >> 3) & 15u, mt = b & 7u;
+  const float v = e ? __uint_as_float(((e + 120u) << 23) | (mt << 20)) : (float)mt * 0x1p-9f;
+  return (b & 0x80u) ? -v : v;
+}
+
+// One block per 128 x 128 piece of one plane of the padded block (4 x 4
+// tiles of 32 x 32): the tile scales (the smallest power of two sc with
+// amax / sc <= 448, 1 for an all-zero tile), then the T e4m3 terms, written
+// column by column (qw: 128 bytes of each column) and, through LDS, row by
+// row (qy: 128 bytes of each row).  Thread (column t / 2, rows 64 (t mod 2)
+// .. + 63).  Values outside the block are zero.  The e4m3 rounding is the
+// hardware's round-to-nearest-even conversion, the inputs are within range
+// (|x / sc| <= 448 for term 0, <= 256 after it).
+template <typename TIN>
+__global__ __launch_bounds__(256) void fp8x_quant_kernel(QuantArgs a) {
+  __shared__ float red[4][128];
+  __shared__ float s_sc[4][4];
+  __shared__ __attribute__((aligned(16))) uint8_t tr[4][128][144];   // [term][row][column], padded rows
+  const int q = blockIdx.z;
+  if (q == 0 && a.pure) return;
+  const int64_t r0 = (int64_t)blockIdx.x * 128, c0 = (int64_t)blockIdx.y * 128;
+  const int tid = threadIdx.x, cc = tid >> 1, hr = 64 * (tid & 1);
+  const int64_t c = c0 + cc, rbeg = r0 + hr;
+  float x[64];
+  {
+    // buffer loads over the plane's extent [0, ((ncols - 1) lda + m)
+    // elements): loads past the end read zero; rows past m of a column read
+    // the next column's values and are masked
+    const bool colok = c < a.ncols;
+    const rsrc_t rs = make_rsrc(a.a[q], (uint32_t)(((a.ncols - 1) * a.lda + a.m) * (int64_t)sizeof(TIN)));
+    const int64_t e0 = (colok ? c : 0) * a.lda + rbeg;          // first element of this thread
+    if constexpr (sizeof(TIN) == 4) {
+      const uint32_t base = (uint32_t)(e0 * 4);
+#pragma unroll
+      for (int i = 0; i < 64; i += 8) {
+        const u32v4 u0 = __builtin_amdgcn_raw_buffer_load_b128(rs, base + 4u * i, 0, 0);
+        const u32v4 u1 = __builtin_amdgcn_raw_buffer_load_b128(rs, base + 4u * i + 16u, 0, 0);
+        const float v[8] = {__uint_as_float(u0.x), __uint_as_float(u0.y), __uint_as_float(u0.z), __uint_as_float(u0.w),
+                            __uint_as_float(u1.x), __uint_as_float(u1.y), __uint_as_float(u1.z), __uint_as_float(u1.w)};
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[i + u] = (colok && rbeg + i + u < a.m) ? v[u] : 0.f;
+      }
+    } else {
+      // dword loads need dword-aligned addresses: with an odd element offset
+      // (odd lda, odd column) the loads start one element early and every
+      // pair is taken across two dwords
+      const uint32_t odd = (uint32_t)(e0 & 1);
+      const uint32_t base = (uint32_t)((e0 - odd) * 2);
+      uint32_t d[33];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const u32v4 u = __builtin_amdgcn_raw_buffer_load_b128(rs, base + 16u * i, 0, 0);
+        d[4 * i] = u.x; d[4 * i + 1] = u.y; d[4 * i + 2] = u.z; d[4 * i + 3] = u.w;
+      }
+      d[32] = odd ? __builtin_amdgcn_raw_buffer_load_b32(rs, base + 128u, 0, 0) : 0u;
+#pragma unroll
+      for (int p = 0; p < 32; ++p) {
+        const uint32_t w = odd ? __builtin_amdgcn_alignbit(d[p + 1], d[p], 16) : d[p];
+        x[2 * p] = (colok && rbeg + 2 * p < a.m) ? __uint_as_float(w << 16) : 0.f;
+        x[2 * p + 1] = (colok && rbeg + 2 * p + 1 < a.m) ? __uint_as_float(w & 0xFFFF0000u) : 0.f;
+      }
+    }
+    // bf16: the range check works per dword, so the dword that holds the
+    // block's last element A[m-1, ncols-1] may reach past the end and read
+    // as zero; that element is loaded on its own
+    if constexpr (sizeof(TIN) == 2) {
+      const uint32_t end = (uint32_t)(((a.ncols - 1) * a.lda + a.m) * 2);
+      const float last = bload1<uint16_t>(rs, end - 2, 0);
+#pragma unroll
+      for (int i = 0; i < 64; ++i)
+        if (c == a.ncols - 1 && rbeg + i == a.m - 1) x[i] = last;
+    }
+  }
+  // tile maxima: this thread's column over its two 32-row tiles
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    float mx = 0.f;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) mx = fmaxf(mx, fabsf(x[32 * h + i]));
+    red[(hr >> 5) + h][cc] = mx;
+  }
+  __syncthreads();
+  if (tid < 16) {
+    const int rt = tid >> 2, ct = tid & 3;
+    float mx = 0.f;
+    for (int i = 0; i < 32; ++i) mx = fmaxf(mx, red[rt][32 * ct + i]);
+    float sc = 1.f;
+    if (mx > 0.f) {
+      // mx = f 2^E with 0.5 <= f < 1 and 448 = 0.875 2^9: the smallest e with
+      // mx <= 448 2^e is E - 9, or E - 8 when f > 0.875
+      int E;
+      const float f = frexpf(mx, &E);
+      sc = ldexpf(1.f, E - 9 + (f > 0.875f ? 1 : 0));
+    }
+    s_sc[rt][ct] = sc;
+    const int64_t grt = r0 / 32 + rt, gct = c0 / 32 + ct;
+    if (grt < a.RT && gct < a.CT) gpw(a.fsc)[((int64_t)q * a.RT + grt) * a.CT + gct] = sc;
+  }
+  __syncthreads();
+  for (int t = 0; t < a.T; ++t) {
+    uint32_t word[16];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const float sc = s_sc[(hr >> 5) + h][cc >> 5];
+      const float st = ldexpf(sc, -4 * t), inv = ldexpf(1.f / sc, 4 * t);   // powers of two
+#pragma unroll
+      for (int i = 0; i < 32; i += 2) {
+        const int k0 = 32 * h + i;
+        const uint32_t pk = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x[k0] * inv, x[k0 + 1] * inv, 0, false);
+        const uint32_t b0 = pk & 0xFFu, b1 = (pk >> 8) & 0xFFu;
+        x[k0] -= e4m3_value(b0) * st;                                  // exact
+        x[k0 + 1] -= e4m3_value(b1) * st;
+        const int wi = k0 >> 2, sh = 8 * (k0 & 3);
+        if (sh == 0) word[wi] = b0 | (b1 << 8);
+        else word[wi] |= (b0 << 16) | (b1 << 24);
+        tr[t][hr + k0][cc] = (uint8_t)b0;
+        tr[t][hr + k0 + 1][cc] = (uint8_t)b1;
+      }
+    }
+    if (c < a.CPW) {
+      QSK_GLOBAL u32v4 *dst = (QSK_GLOBAL u32v4 *)(gpw(a.qw) + (((int64_t)q * a.T + t) * a.CPW + c) * a.RP + rbeg);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dst[v] = u32v4{word[4 * v], word[4 * v + 1], word[4 * v + 2], word[4 * v + 3]};
+    }
+  }
+  __syncthreads();
+  // rows: thread (row t / 2, columns 64 (t mod 2) .. + 63)
+  const int rr = tid >> 1, hc = 64 * (tid & 1);
+  if (c0 + hc < a.CP) {
+    for (int t = 0; t < a.T; ++t) {
+      QSK_GLOBAL u32v4 *dst = (QSK_GLOBAL u32v4 *)(gpw(a.qy) + (((int64_t)q * a.T + t) * a.RP + r0 + rr) * a.CP + c0 + hc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dst[v] = *(const QSK_LDS u32v4 *)&tr[t][rr][hc + 16 * v];
+    }
+  }
+}
+
+// Test-matrix staging as e4m3 bytes: [plane][o][t], t fastest, zero outside
+// (o < n_o, t < n_t); four consecutive t per thread (t_pad is a multiple of 4).
+__global__ __launch_bounds__(256) void gen_stage8_kernel(uint8_t *dst, int n_o, int o_pad, int64_t t0,
+                                                         int64_t n_t, int64_t t_pad, uint32_t stream, int rad,
+                                                         uint32_t k0, uint32_t k1) {
+  const int64_t words = (int64_t)o_pad * (t_pad / 4);
+  const int64_t ps = (int64_t)o_pad * t_pad;
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words;
+       w += (int64_t)gridDim.x * blockDim.x) {
+    const int o = (int)(w / (t_pad / 4));
+    const int64_t t = 4 * (w % (t_pad / 4));
+    uint32_t out[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float v[4] = {0.f, 0.f, 0.f, 0.f};
+      if (o < n_o && t + i < n_t) embed_entry<MODE_FP8>(rad, (uint32_t)(t0 + t + i), (uint32_t)o, stream, k0, k1, v);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) out[p] |= e4m3_byte(v[p]) << (8 * i);
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) *(QSK_GLOBAL uint32_t *)(gpw(dst) + p * ps + (int64_t)o * t_pad + t) = out[p];
+  }
+}
+
+// Negation of the 32 e4m3 values of a fragment (sign bits).
+__device__ __forceinline__ i32x8 neg8(const i32x8 &a) {
+  i32x8 r;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = a[i] ^ (int)0x80808080;
+  return r;
+}
+// The fragment of 16-row tile `tile` of an LDS tile set: lane (c, g) reads
+// chunks g and 4 + g of row c.  A (plane, tile) block holds 128 chunks of
+// 16 bytes, chunk (kc, row) at kc * 16 + row, so that eight consecutive
+// lanes read eight different bank groups.
+__device__ __forceinline__ i32x8 lds_frag8(const char *tile, int c16, int g) {
+  const u32v4 lo = *(const QSK_LDS u32v4 *)(tile + (g * 16 + c16) * 16);
+  const u32v4 hi = *(const QSK_LDS u32v4 *)(tile + ((4 + g) * 16 + c16) * 16);
+  i32x8 r;
+  r[0] = (int)lo.x; r[1] = (int)lo.y; r[2] = (int)lo.z; r[3] = (int)lo.w;
+  r[4] = (int)hi.x; r[5] = (int)hi.y; r[6] = (int)hi.z; r[7] = (int)hi.w;
+  return r;
+}
+__device__ __forceinline__ i32x8 bload_frag8(rsrc_t rs, uint32_t off) {
+  const u32v4 lo = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+  const u32v4 hi = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 64, 0, 0);
+  i32x8 r;
+  r[0] = (int)lo.x; r[1] = (int)lo.y; r[2] = (int)lo.z; r[3] = (int)lo.w;
+  r[4] = (int)hi.x; r[5] = (int)hi.y; r[6] = (int)hi.z; r[7] = (int)hi.w;
+  return r;
+}
+// E8M0 exponent byte of a power-of-two float scale
+__device__ __forceinline__ int e8m0_of(float sc) { return (int)((__float_as_uint(sc) >> 23) & 0xFFu); }
+
+struct W8Args {
+  const uint8_t *qw;
+  int64_t RP, CPW;
+  const uint8_t *psi;         // [4][LP][MPF] e4m3 bytes
+  int LP;
+  int64_t MPF;
+  const float *fsc;
+  int RT, CT;
+  int64_t ncols, col0;
+  int l, S, ctiles, rgroups;
+  int64_t kchunk;
+  float *w;
+  int64_t ldw, psw;
+  float *part;                // [S][4][ncols][LP]
+  float eta;
+};
+
+// W = Psi A on the fp8 matrix cores: a block of 4 waves owns 64 columns of
+// the update block (16 per wave) and NMT 16-row tiles of W, over one chunk
+// of the rows of A; 128 rows per step, the Psi tile HBM -> LDS directly (two
+// buffers), the data fragments (2 x 16 bytes per plane and term) from HBM
+// into registers one step ahead.
+template <int NMT, int T, bool PURE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void w_fp8x_kernel(W8Args a) {
+  constexpr int TB = 2048;                                 // bytes of a (plane, row tile) per step
+  constexpr int NBLK = 4 * NMT * 2;                        // 1 KB DMA blocks per step
+  __shared__ __attribute__((aligned(1024))) char s_psi[2][4 * NMT * TB];
+  const int64_t tl = xcd_tile(blockIdx.x, (int64_t)a.ctiles * a.rgroups * a.S);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c16 = lane & 15, g = lane >> 4;
+  const int bx = (int)(tl % a.ctiles);
+  const int by = (int)((tl / a.ctiles) % a.rgroups);
+  const int bz = (int)(tl / ((int64_t)a.ctiles * a.rgroups));
+  const int64_t j = (int64_t)bx * 64 + wave * 16 + c16;
+  const int rbase = by * NMT * 16;
+  const int64_t ib = (int64_t)bz * a.kchunk;
+  const int64_t ie = min(a.RP, ib + a.kchunk);
+  const int sct = (int)min(j >> 5, (int64_t)a.CT - 1);
+  // data: one resource per (plane, term) over its CPW x RP bytes
+  rsrc_t dr[4][T];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+      dr[q][t] = make_rsrc(a.qw + ((int64_t)(PURE ? (q > 0 ? q : 1) : q) * T + t) * a.CPW * a.RP,
+                           (uint32_t)(a.CPW * a.RP));
+  uint32_t voff = (uint32_t)(j * a.RP + ib + 16 * g);
+  // DMA source of this lane for 1 KB block half hh of a (plane, tile): chunk
+  // c = 64 hh + lane is (kc = c / 16, row c mod 16)
+  floatx4 acc[NMT][4];
+#pragma unroll
+  for (int i = 0; i < NMT; ++i)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) acc[i][p] = {0.f, 0.f, 0.f, 0.f};
+  i32x8 df[4][T];
+  int e8[4] = {127, 127, 127, 127};
+#define QSK_W8_FETCH(I0)                                                                         \
+  do {                                                                                           \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                              \
+      if (q == 0 && PURE) continue;                                                              \
+      _Pragma("unroll") for (int t = 0; t < T; ++t) df[q][t] = bload_frag8(dr[q][t], voff);     \
+      e8[q] = e8m0_of(gp(a.fsc)[((int64_t)q * a.RT + min((int64_t)(I0) / 32 + g, (int64_t)a.RT - 1)) * a.CT + sct]); \
+    }                                                                                            \
+  } while (0)
+#define QSK_W8_DMA(I0, B)                                                                        \
+  do {                                                                                           \
+    _Pragma("unroll") for (int k_ = 0; k_ < NBLK / 4; ++k_) {                                    \
+      const int u_ = wave + 4 * k_;                                                              \
+      const int hh_ = u_ & 1, rt_ = (u_ >> 1) % NMT, pl_ = (u_ >> 1) / NMT;                      \
+      const int ch_ = 64 * hh_ + lane;                                                           \
+      dma16(a.psi + ((int64_t)pl_ * a.LP + rbase + rt_ * 16 + (ch_ & 15)) * a.MPF + (I0) + 16 * (ch_ >> 4), \
+            &s_psi[B][(pl_ * NMT + rt_) * TB + hh_ * 1024]);                                     \
+    }                                                                                            \
+  } while (0)
+  QSK_W8_FETCH(ib);
+  QSK_W8_DMA(ib, 0);
+  wait_vm();
+  __syncthreads();
+  int buf = 0;
+  for (int64_t i0 = ib; i0 < ie; i0 += 128) {
+    i32x8 cur[4][T];
+    int ce[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ce[q] = e8[q];
+#pragma unroll
+      for (int t = 0; t < T; ++t) cur[q][t] = df[q][t];
+    }
+    voff += 128;
+    if (i0 + 128 < ie) {
+      QSK_W8_DMA(i0 + 128, buf ^ 1);
+      __builtin_amdgcn_sched_barrier(0);
+      QSK_W8_FETCH(i0 + 128);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < NMT; ++i) {
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) {
+        const i32x8 pf = lds_frag8(&s_psi[buf][(sp * NMT + i) * TB], c16, g);
+        const i32x8 npf = neg8(pf);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const int q = w_q_of(p, sp);
+          if (q == 0 && PURE) continue;
+          const bool ng = w_neg(p, sp);
+#pragma unroll
+          for (int t = 0; t < T; ++t)
+            acc[i][p] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(ng ? npf : pf, cur[q][t], acc[i][p], 0, 0, 0,
+                                                                          127, 0, max(ce[q] - 4 * t, 0));
+        }
+      }
+    }
+    wait_vm();
+    __syncthreads();
+    buf ^= 1;
+  }
+#undef QSK_W8_FETCH
+#undef QSK_W8_DMA
+  // epilogue: lane holds column j, rows rbase + i * 16 + 4g + (0..3)
+  if (j >= a.ncols) return;
+#pragma unroll
+  for (int i = 0; i < NMT; ++i) {
+    const int r0 = rbase + i * 16 + 4 * g;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      if (a.S == 1) {
+        QSK_GLOBAL float *dst = gpw(a.w + p * a.psw + (a.col0 + j) * a.ldw);
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+          if (r0 + tt < a.l) dst[r0 + tt] += a.eta * acc[i][p][tt];
+      } else {
+        float *dst = a.part + (((int64_t)bz * 4 + p) * a.ncols + j) * a.LP + r0;
+        *(QSK_GLOBAL floatx4 *)dst = acc[i][p];
+      }
+    }
+  }
+}
+
+struct Y8Args {
+  const uint8_t *qy;
+  int64_t RP, CP;
+  const uint8_t *om;          // [4][KP][NPF] e4m3 bytes
+  int KP;
+  int64_t NPF;
+  const float *fsc;
+  int RT, CT;
+  int64_t m, ncols;
+  int k, S, rblocks, cgroups;
+  int64_t tchunk;
+  float *y;
+  int64_t ldy, psy, pss;
+  float eta;
+};
+
+// Y = A Omega on the fp8 matrix cores: a block of 4 waves owns 64 rows of A
+// (16 per wave) and NJ 16-column tiles of Y, over one chunk of the update's
+// columns (copy bz of Y); 128 columns per step, the Omega tile HBM -> LDS
+// directly (two buffers), the data fragments from HBM one step ahead.
+template <int NJ, int T, bool PURE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void y_fp8x_kernel(Y8Args a) {
+  constexpr int TB = 2048;
+  constexpr int NBLK = 4 * NJ * 2;
+  __shared__ __attribute__((aligned(1024))) char s_om[2][4 * NJ * TB];
+  const int64_t tl = xcd_tile(blockIdx.x, (int64_t)a.rblocks * a.cgroups * a.S);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c16 = lane & 15, g = lane >> 4;
+  const int64_t bx = tl % a.rblocks;
+  const int by = (int)((tl / a.rblocks) % a.cgroups);
+  const int bz = (int)(tl / ((int64_t)a.rblocks * a.cgroups));
+  const int64_t rb = bx * 64;
+  const int jt0 = by * NJ;
+  const int64_t tb = (int64_t)bz * a.tchunk;
+  const int64_t te = min(a.CP, tb + a.tchunk);
+  const int64_t row = rb + wave * 16 + c16;
+  const int srt = (int)min(row >> 5, (int64_t)a.RT - 1);
+  rsrc_t dr[4][T];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+      dr[q][t] = make_rsrc(a.qy + ((int64_t)(PURE ? (q > 0 ? q : 1) : q) * T + t) * a.RP * a.CP,
+                           (uint32_t)(a.RP * a.CP));
+  uint32_t voff = (uint32_t)(row * a.CP + tb + 16 * g);
+  floatx4 acc[NJ][4];
+#pragma unroll
+  for (int i = 0; i < NJ; ++i)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) acc[i][p] = {0.f, 0.f, 0.f, 0.f};
+  i32x8 df[4][T];
+  int e8[4] = {127, 127, 127, 127};
+#define QSK_Y8_FETCH(T0)                                                                         \
+  do {                                                                                           \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                              \
+      if (q == 0 && PURE) continue;                                                              \
+      _Pragma("unroll") for (int t = 0; t < T; ++t) df[q][t] = bload_frag8(dr[q][t], voff);     \
+      e8[q] = e8m0_of(gp(a.fsc)[((int64_t)q * a.RT + srt) * a.CT + min((int64_t)(T0) / 32 + g, (int64_t)a.CT - 1)]); \
+    }                                                                                            \
+  } while (0)
+#define QSK_Y8_DMA(T0, B)                                                                        \
+  do {                                                                                           \
+    _Pragma("unroll") for (int k_ = 0; k_ < NBLK / 4; ++k_) {                                    \
+      const int u_ = wave + 4 * k_;                                                              \
+      const int hh_ = u_ & 1, jt_ = (u_ >> 1) % NJ, pl_ = (u_ >> 1) / NJ;                        \
+      const int ch_ = 64 * hh_ + lane;                                                           \
+      dma16(a.om + ((int64_t)pl_ * a.KP + (jt0 + jt_) * 16 + (ch_ & 15)) * a.NPF + (T0) + 16 * (ch_ >> 4), \
+            &s_om[B][(pl_ * NJ + jt_) * TB + hh_ * 1024]);                                       \
+    }                                                                                            \
+  } while (0)
+  QSK_Y8_FETCH(tb);
+  QSK_Y8_DMA(tb, 0);
+  wait_vm();
+  __syncthreads();
+  int buf = 0;
+  for (int64_t t0 = tb; t0 < te; t0 += 128) {
+    i32x8 cur[4][T];
+    int ce[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ce[q] = e8[q];
+#pragma unroll
+      for (int t = 0; t < T; ++t) cur[q][t] = df[q][t];
+    }
+    voff += 128;
+    if (t0 + 128 < te) {
+      QSK_Y8_DMA(t0 + 128, buf ^ 1);
+      __builtin_amdgcn_sched_barrier(0);
+      QSK_Y8_FETCH(t0 + 128);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) {
+        const i32x8 of = lds_frag8(&s_om[buf][(sp * NJ + i) * TB], c16, g);
+        const i32x8 nof = neg8(of);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const int q = y_q_of(p, sp);
+          if (q == 0 && PURE) continue;
+          const bool ng = y_neg(p, sp);
+#pragma unroll
+          for (int t = 0; t < T; ++t)
+            acc[i][p] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(cur[q][t], ng ? nof : of, acc[i][p], 0, 0, 0,
+                                                                          max(ce[q] - 4 * t, 0), 0, 127);
+        }
+      }
+    }
+    wait_vm();
+    __syncthreads();
+    buf ^= 1;
+  }
+#undef QSK_Y8_FETCH
+#undef QSK_Y8_DMA
+  // epilogue: lane holds column (jt0 + i) * 16 + c16 of Y, rows rb + 16 wave + 4g + (0..3)
+  const int64_t r0 = rb + wave * 16 + 4 * g;
+  float *ys = a.y + bz * a.pss;
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    const int jj = (jt0 + i) * 16 + c16;
+    if (jj >= a.k) continue;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      QSK_GLOBAL float *dst = gpw(ys + p * a.psy + (int64_t)jj * a.ldy);
+      if (r0 + 3 < a.m && ((a.ldy | a.psy | a.pss) & 3) == 0) {
+        QSK_GLOBAL floatx4 *d4 = (QSK_GLOBAL floatx4 *)(dst + r0);
+        *d4 = *d4 + a.eta * acc[i][p];
+      } else {
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+          if (r0 + tt < a.m) dst[r0 + tt] += a.eta * acc[i][p][tt];
+      }
+    }
+  }
+}
+
+// Y for a block of at most 128 columns (one step): the Omega tile of the
+// workgroup's column group stays in LDS while the workgroup walks over row
+// blocks of 64 (bx, bx + G, bx + 2 G, ...); the data fragments of the next
+// row block and the old Y values of the current one are fetched before the
+// products, so their latency hides behind the matrix cores.
+template <int NJ, int T, bool PURE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void y_fp8x_rows_kernel(Y8Args a) {
+  constexpr int TB = 2048;
+  constexpr int NBLK = 4 * NJ * 2;
+  __shared__ __attribute__((aligned(1024))) char s_om[4 * NJ * TB];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c16 = lane & 15, g = lane >> 4;
+  const int G = (int)gridDim.x;
+  const int by = (int)blockIdx.y;
+  const int jt0 = by * NJ;
+  rsrc_t dr[4][T];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+      dr[q][t] = make_rsrc(a.qy + ((int64_t)(PURE ? (q > 0 ? q : 1) : q) * T + t) * a.RP * a.CP,
+                           (uint32_t)(a.RP * a.CP));
+  // the Omega tile (128 columns of the block x NJ tiles x 4 planes)
+#pragma unroll
+  for (int k_ = 0; k_ < NBLK / 4; ++k_) {
+    const int u_ = wave + 4 * k_;
+    const int hh_ = u_ & 1, jt_ = (u_ >> 1) % NJ, pl_ = (u_ >> 1) / NJ;
+    const int ch_ = 64 * hh_ + lane;
+    dma16(a.om + ((int64_t)pl_ * a.KP + (jt0 + jt_) * 16 + (ch_ & 15)) * a.NPF + 16 * (ch_ >> 4),
+          &s_om[(pl_ * NJ + jt_) * TB + hh_ * 1024]);
+  }
+  i32x8 df[4][T];
+  int e8[4] = {127, 127, 127, 127};
+  int64_t bx = blockIdx.x;
+#define QSK_YR_FETCH(BX)                                                                         \
+  do {                                                                                           \
+    const int64_t row_ = (BX) * 64 + wave * 16 + c16;                                            \
+    const uint32_t off_ = (uint32_t)(row_ * a.CP + 16 * g);                                      \
+    const int srt_ = (int)min(row_ >> 5, (int64_t)a.RT - 1);                                     \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                              \
+      if (q == 0 && PURE) continue;                                                              \
+      _Pragma("unroll") for (int t = 0; t < T; ++t) df[q][t] = bload_frag8(dr[q][t], off_);      \
+      e8[q] = e8m0_of(gp(a.fsc)[((int64_t)q * a.RT + srt_) * a.CT + min(g, a.CT - 1)]);          \
+    }                                                                                            \
+  } while (0)
+  if (bx * 64 < a.m) QSK_YR_FETCH(bx);
+  wait_vm();
+  __syncthreads();
+  for (; bx * 64 < a.m; bx += G) {
+    i32x8 cur[4][T];
+    int ce[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ce[q] = e8[q];
+#pragma unroll
+      for (int t = 0; t < T; ++t) cur[q][t] = df[q][t];
+    }
+    const int64_t r0 = bx * 64 + wave * 16 + 4 * g;
+    const bool full = r0 + 3 < a.m && ((a.ldy | a.psy) & 3) == 0;
+    // old Y values of this row block
+    floatx4 old[NJ][4];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+      const int jj = (jt0 + i) * 16 + c16;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        old[i][p] = {0.f, 0.f, 0.f, 0.f};
+        if (jj < a.k && full) old[i][p] = *(const QSK_GLOBAL floatx4 *)gp(a.y + p * a.psy + (int64_t)jj * a.ldy + r0);
+      }
+    }
+    if ((bx + G) * 64 < a.m) QSK_YR_FETCH(bx + G);
+    __builtin_amdgcn_sched_barrier(0);
+    floatx4 acc[NJ][4];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) acc[i][p] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) {
+        const i32x8 of = lds_frag8(&s_om[(sp * NJ + i) * TB], c16, g);
+        const i32x8 nof = neg8(of);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const int q = y_q_of(p, sp);
+          if (q == 0 && PURE) continue;
+          const bool ng = y_neg(p, sp);
+#pragma unroll
+          for (int t = 0; t < T; ++t)
+            acc[i][p] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(cur[q][t], ng ? nof : of, acc[i][p], 0, 0, 0,
+                                                                          max(ce[q] - 4 * t, 0), 0, 127);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+      const int jj = (jt0 + i) * 16 + c16;
+      if (jj >= a.k) continue;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        QSK_GLOBAL float *dst = gpw(a.y + p * a.psy + (int64_t)jj * a.ldy);
+        if (full) {
+          *(QSK_GLOBAL floatx4 *)(dst + r0) = old[i][p] + a.eta * acc[i][p];
+        } else {
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt)
+            if (r0 + tt < a.m) dst[r0 + tt] += a.eta * acc[i][p][tt];
+        }
+      }
+    }
+  }
+#undef QSK_YR_FETCH
+}
+
+int fp8x_nmt(int l) {
+  static const int c[3] = {4, 7, 8};        // LDS: 16 KB per tile for the two buffers
+  return pick_tiles((l + 15) / 16, c, 3);
+}
+
+// Geometry of the FP8X buffers (bytes): the quantised block in both layouts
+// and the e4m3 test matrices.
+void fp8x_geometry(int64_t m, int l, int k, int64_t maxcols, int terms, int pure, Fp8xStage *f) {
+  f->RP = rup(m, 128);
+  f->CPW = rup(maxcols, 64);
+  f->CP = rup(maxcols, 128);
+  f->T = terms;
+  f->planes = pure ? 3 : 4;
+  f->NMT = fp8x_nmt(l);
+  f->NJ = y_nj(k);
+  f->LP = (int)rup(l, 16 * f->NMT);
+  f->MPF = rup(m, 128);
+  f->KP = (int)rup(k, 16 * f->NJ);
+  f->NPF = f->CP;
+  f->qw_bytes = (int64_t)4 * terms * f->CPW * f->RP;
+  f->qy_bytes = (int64_t)4 * terms * f->RP * f->CP;
+  f->psi_bytes = (int64_t)4 * f->LP * f->MPF;
+  f->om_bytes = (int64_t)4 * f->KP * f->NPF;
+}
+
+template <int T, bool PURE>
+static void launch_w8(const W8Args &w, int nmt, int64_t blocks, hipStream_t st) {
+  if (nmt == 8) hipLaunchKernelGGL((w_fp8x_kernel<8, T, PURE>), dim3((unsigned)blocks), dim3(256), 0, st, w);
+  else if (nmt == 7) hipLaunchKernelGGL((w_fp8x_kernel<7, T, PURE>), dim3((unsigned)blocks), dim3(256), 0, st, w);
+  else hipLaunchKernelGGL((w_fp8x_kernel<4, T, PURE>), dim3((unsigned)blocks), dim3(256), 0, st, w);
+}
+template <int T, bool PURE>
+static void launch_y8(const Y8Args &y, int nj, int64_t blocks, hipStream_t st) {
+  if (nj == 7) hipLaunchKernelGGL((y_fp8x_kernel<7, T, PURE>), dim3((unsigned)blocks), dim3(256), 0, st, y);
+  else hipLaunchKernelGGL((y_fp8x_kernel<4, T, PURE>), dim3((unsigned)blocks), dim3(256), 0, st, y);
+}
+template <int T>
+static void launch_w8_t(const W8Args &w, int pure, int nmt, int64_t blocks, hipStream_t st) {
+  if (pure) launch_w8<T, true>(w, nmt, blocks, st); else launch_w8<T, false>(w, nmt, blocks, st);
+}
+template <int T>
+static void launch_y8_t(const Y8Args &y, int pure, int nj, int64_t blocks, hipStream_t st) {
+  if (pure) launch_y8<T, true>(y, nj, blocks, st); else launch_y8<T, false>(y, nj, blocks, st);
+}
+template <int T, bool PURE>
+static void launch_y8r(const Y8Args &y, dim3 grid, hipStream_t st) {
+  hipLaunchKernelGGL((y_fp8x_rows_kernel<4, T, PURE>), grid, dim3(256), 0, st, y);
+}
+template <int T>
+static void launch_y8r_t(const Y8Args &y, int pure, dim3 grid, hipStream_t st) {
+  if (pure) launch_y8r<T, true>(y, grid, st); else launch_y8r<T, false>(y, grid, st);
+}
+
+// Psi alone into the e4m3 staging of the FP8X format.
+hipError_t stage_psi8(const SketchArgs &s, const Fp8xStage &f) {
+  if (!f.psi) return hipErrorInvalidValue;
+  const int64_t words = (int64_t)f.LP * (f.MPF / 4);
+  hipLaunchKernelGGL(gen_stage8_kernel, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 65536)), dim3(256), 0,
+                     s.stream, f.psi, s.l, f.LP, (int64_t)0, s.m, f.MPF, STREAM_PSI, s.rad, s.k0, s.k1);
+  return hipGetLastError();
+}
+
+static hipError_t launch_fp8x(const SketchArgs &s, const Fp8xStage &f) {
+  if (!f.qw || !f.qy || !f.psi || !f.om || s.ncols > f.CPW || !s.fp8_scales) return hipErrorInvalidValue;
+  if (s.terms < 1 || s.terms > 4 || s.terms != f.T) return hipErrorInvalidValue;
+  if ((uint64_t)f.CPW * f.RP >= (1ull << 32) || (uint64_t)f.RP * f.CP >= (1ull << 32)) return hipErrorNotSupported;
+  if (s.in_dtype == DT_F32 ? !offsets_fit<float>(s.m, s.ncols, s.lda) : !offsets_fit<uint16_t>(s.m, s.ncols, s.lda))
+    return hipErrorNotSupported;
+  hipError_t e;
+  mark(s, 0);
+  // test matrices as e4m3 bytes: Omega_J per update, Psi once per sketch
+  {
+    const int64_t NPu = rup(s.ncols, 128);
+    int64_t words = (int64_t)f.KP * (NPu / 4);
+    hipLaunchKernelGGL(gen_stage8_kernel, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 65536)), dim3(256), 0,
+                       s.stream, f.om, s.k, f.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!s.psi_ready && !s.skip_w && (e = stage_psi8(s, f)) != hipSuccess) return e;
+  }
+  // tile scales and the e4m3 terms in both layouts, one pass over the block
+  const int RT = (int)((s.m + 31) / 32), CT = (int)((s.ncols + 31) / 32);
+  if (4 * (int64_t)RT * CT > s.fp8_scale_elems) return hipErrorInvalidValue;
+  {
+    QuantArgs qa{};
+    for (int p = 0; p < 4; ++p) qa.a[p] = s.planes[p];
+    qa.lda = s.lda; qa.m = s.m; qa.ncols = s.ncols; qa.pure = s.pure; qa.RT = RT; qa.CT = CT; qa.T = f.T;
+    qa.fsc = s.fp8_scales; qa.qw = f.qw; qa.qy = f.qy; qa.RP = f.RP; qa.CPW = f.CPW;
+    qa.CP = rup(s.ncols, 128);
+    const dim3 grid((unsigned)(f.RP / 128), (unsigned)(qa.CP / 128), 4);
+    if (s.in_dtype == DT_F32) hipLaunchKernelGGL(fp8x_quant_kernel<float>, grid, dim3(256), 0, s.stream, qa);
+    else hipLaunchKernelGGL(fp8x_quant_kernel<uint16_t>, grid, dim3(256), 0, s.stream, qa);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  mark(s, 1);
+  const int64_t CPu = rup(s.ncols, 128);
+  // ---- Y
+  {
+    mark(s, 2);
+    Y8Args y{};
+    y.qy = f.qy; y.RP = f.RP; y.CP = CPu;
+    y.om = f.om; y.KP = f.KP; y.NPF = CPu;
+    y.fsc = s.fp8_scales; y.RT = RT; y.CT = CT;
+    y.m = s.m; y.ncols = s.ncols; y.k = s.k;
+    y.y = (float *)s.y; y.ldy = s.ldy; y.psy = s.psy; y.pss = s.pss; y.eta = (float)s.eta;
+    const int nj = f.NJ;
+    const int ntiles = (s.k + 15) / 16;
+    y.rblocks = (int)((s.m + 63) / 64);
+    y.cgroups = (ntiles + nj - 1) / nj;
+    if (CPu == 128 && nj == 4 && !(f.T == 4 && !s.pure)) {
+      // one 128-column step: row-walking blocks with the Omega tile kept in
+      // LDS, two per CU (four column tiles: the registers of seven do not fit)
+      y.S = 1; y.tchunk = CPu;
+      if (s.y_splits) *s.y_splits = 1;
+      const int64_t G = std::min<int64_t>(y.rblocks, std::max<int64_t>(1, 2 * resident_blocks(2) / y.cgroups));
+      const dim3 grid((unsigned)G, (unsigned)y.cgroups);
+      switch (f.T) {
+        case 1: launch_y8r_t<1>(y, s.pure, grid, s.stream); break;
+        case 2: launch_y8r_t<2>(y, s.pure, grid, s.stream); break;
+        case 3: launch_y8r_t<3>(y, s.pure, grid, s.stream); break;
+        default: launch_y8r_t<4>(y, s.pure, grid, s.stream); break;
+      }
+    } else {
+      int64_t S = pick_split((int64_t)y.rblocks * y.cgroups, std::min<int64_t>(s.y_copies, CPu / 128),
+                             resident_blocks(2));
+      int64_t tchunk = rup((CPu + S - 1) / S, 128);
+      S = (CPu + tchunk - 1) / tchunk;
+      y.S = (int)S; y.tchunk = tchunk;
+      if (s.y_splits) *s.y_splits = (int)S;
+      const int64_t blocks = (int64_t)y.rblocks * y.cgroups * S;
+      switch (f.T) {
+        case 1: launch_y8_t<1>(y, s.pure, nj, blocks, s.stream); break;
+        case 2: launch_y8_t<2>(y, s.pure, nj, blocks, s.stream); break;
+        case 3: launch_y8_t<3>(y, s.pure, nj, blocks, s.stream); break;
+        default: launch_y8_t<4>(y, s.pure, nj, blocks, s.stream); break;
+      }
+    }
+    e = hipGetLastError();
+    mark(s, 3);
+    if (e != hipSuccess) return e;
+  }
+  // ---- W
+  if (!s.skip_w) {
+    W8Args w{};
+    w.qw = f.qw; w.RP = f.RP; w.CPW = f.CPW;
+    w.psi = f.psi; w.LP = f.LP; w.MPF = f.MPF;
+    w.fsc = s.fp8_scales; w.RT = RT; w.CT = CT;
+    w.ncols = s.ncols; w.col0 = s.col0; w.l = s.l; w.eta = (float)s.eta;
+    w.w = (float *)s.w; w.ldw = s.ldw; w.psw = s.psw;
+    const int nmt = f.NMT;
+    w.rgroups = f.LP / (16 * nmt);
+    w.ctiles = (int)((s.ncols + 63) / 64);
+    const int64_t base = (int64_t)w.ctiles * w.rgroups;
+    const int64_t per_split = 4 * s.ncols * (int64_t)f.LP * 4;
+    const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(f.RP / 256, s.scratch_bytes / per_split));
+    int64_t S = pick_split(base, smax, resident_blocks(2));
+    int64_t kchunk = rup((f.RP + S - 1) / S, 128);
+    if (kchunk < 256) kchunk = 256;
+    S = (f.RP + kchunk - 1) / kchunk;
+    if (S > 1 && S * per_split > s.scratch_bytes) { S = 1; kchunk = f.RP; }
+    w.S = (int)S; w.kchunk = kchunk; w.part = (float *)s.scratch;
+    const int64_t blocks = base * S;
+    mark(s, 4);
+    switch (f.T) {
+      case 1: launch_w8_t<1>(w, s.pure, nmt, blocks, s.stream); break;
+      case 2: launch_w8_t<2>(w, s.pure, nmt, blocks, s.stream); break;
+      case 3: launch_w8_t<3>(w, s.pure, nmt, blocks, s.stream); break;
+      default: launch_w8_t<4>(w, s.pure, nmt, blocks, s.stream); break;
+    }
+    e = hipGetLastError();
+    mark(s, 5);
+    if (e != hipSuccess) return e;
+    mark(s, 6);
+    if (S > 1) {
+      const int64_t total = 4 * s.ncols * (int64_t)s.l;
+      int64_t rblocks = (total + 255) / 256;
+      if (rblocks > 65536) rblocks = 65536;
+      hipLaunchKernelGGL(w_reduce_kernel, dim3((unsigned)rblocks), dim3(256), 0, s.stream, (const float *)s.scratch,
+                         (int)S, f.LP, s.ncols, s.l, s.col0, (float *)s.w, s.ldw, s.psw, (float)s.eta);
+      e = hipGetLastError();
+    }
+    mark(s, 7);
+  }
+  return e;
+}
+
 hipError_t launch_sketch_mfma(const SketchArgs &s, const MfmaStage &g) {
+  if (s.mode == MODE_FP8X) return s.f8 ? launch_fp8x(s, *s.f8) : hipErrorInvalidValue;
   if (s.mode != MODE_BF16 && s.mode != MODE_F32 && s.mode != MODE_FP8) return hipErrorNotSupported;
   if (!g.omega || !g.psi) return hipErrorNotSupported;
   if (s.mode == MODE_FP8) {

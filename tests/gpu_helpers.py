@@ -119,7 +119,8 @@ def operand_rel(cfg):
     """Relative error per data value of the device's operands against the
     oracle's (``data_operand``): zero except for the fp8 format with the
     residual, whose residual the device carries as two bf16 terms, i.e. to
-    2^-17 of itself (and the residual is at most the value)."""
+    2^-17 of itself (and the residual is at most the value).  The e4m3-term
+    format ('fp8x') multiplies exactly the oracle's terms."""
     if cfg.dtype == "fp8" and cfg.fp8_residual:
         return 2.0 ** -17
     return 0.0
@@ -139,7 +140,7 @@ def check_sketches(y, w, ref, a, label, block_cols=None):
                            axis=2)
     by, bw = sketch_bounds(a_ops, ref.omega_rows(0, cfg.n), ref.psi())
     u = U64 if cfg.dtype == "f64" else U32
-    terms = cfg.terms if cfg.dtype == "bf16" else (3 if cfg.dtype == "fp8" else 1)
+    terms = cfg.terms if cfg.dtype in ("bf16", "fp8x") else (3 if cfg.dtype == "fp8" else 1)
     orel = operand_rel(cfg)
     my = assert_elementwise(y, ref.Y, by, 4 * cfg.n * terms, label + " Y", u=u, op_rel=orel)
     mw = None
@@ -160,7 +161,7 @@ class BoundTracker:
         c = ref.cfg
         self.by = np.zeros((c.m, c.k))
         self.bw = np.zeros((c.l, c.n))
-        self.terms = c.terms if c.dtype == "bf16" else (3 if c.dtype == "fp8" else 1)
+        self.terms = c.terms if c.dtype in ("bf16", "fp8x") else (3 if c.dtype == "fp8" else 1)
         self.ky = 0
         self.kw = 0
 

@@ -35,6 +35,9 @@ def test_config_default_and_strerror():
     dict(m=0, n=80, k=1, l=1),
     dict(m=100, n=80, k=10, l=21, n_correction=9),
     dict(m=100, n=80, k=10, l=21, sketch_dtype=2, split_terms=4),
+    dict(m=100, n=80, k=10, l=21, input_dtype=1, sketch_dtype=4, split_terms=5),   # e4m3 terms: 1..4
+    dict(m=100, n=80, k=10, l=21, input_dtype=1, sketch_dtype=4, split_terms=0),
+    dict(m=100, n=80, k=10, l=21, input_dtype=1, sketch_dtype=5),
     dict(m=100, n=80, k=10, l=21, embedding=5),
     dict(m=100, n=80, k=10, l=21, y_only=2),
     dict(m=100, n=80, k=10, l=21, embedding_round=4),
@@ -49,6 +52,8 @@ def test_invalid_configs_rejected_before_device_use(bad):
 def test_unsupported_combinations():
     # FP64 data with a low-precision sketch is not accepted
     assert qs.config_status(m=100, n=80, k=10, l=21, input_dtype=0, sketch_dtype=2) == qs.QSK_E_UNSUPPORTED
+    assert qs.config_status(m=100, n=80, k=10, l=21, input_dtype=0, sketch_dtype=4, split_terms=3) == \
+        qs.QSK_E_UNSUPPORTED
 
 
 def test_struct_layouts_match_header():
