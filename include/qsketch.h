@@ -384,21 +384,30 @@ qsk_status qsketch_batch_rel_error(qsk_batch *b, const void *const *planes, cons
                                    double *const *Q, const int64_t *ldq, double *const *X,
                                    const int64_t *ldx, double *err);
 
-/* Autotuner of the batch's tile shapes.  For every candidate (row tiles of
-   W per block: 4, 7 or 13, the last with BF16 operands only; column tiles of
-   Y per block: 4 or 7) it lays the staged test matrices out for that shape,
-   times reps grouped sketch launches (Y and W of every problem, inputs as in
-   qsketch_batch_run) after one untimed launch, and keeps the fastest.  The
-   choice is remembered for the process under the batch's signature (operand
-   format, every problem's m, n, k, l), and a batch with the same signature
-   takes it without timing; reps = 0 only applies a remembered choice.
-   Without a call the shapes come from a padding rule.  Results of runs do
-   not depend on the shapes beyond rounding order.  Leaves the sketch
-   buffers with meaningless values (every run starts from zero).
-   Synchronous.  *nmt_out, *nj_out (each may be NULL) receive the shapes in
-   use.  QSK_E_ARG for a NULL or short input array or reps outside 0..100. */
+/* Autotuner of the batch's launch shapes.  For every candidate (row tiles of
+   W per block: 4, 7, 8 or 13, the last two with BF16 operands only; column
+   tiles of Y per block: 4 or 7; the number of W blocks the row splits of the
+   contraction aim at over all problems: 512, 2048 or 8192) it lays the
+   staged test matrices out for that shape, times reps grouped sketch
+   launches (Y and W of every problem, inputs as in qsketch_batch_run) after
+   one untimed launch, and keeps the fastest.  The choice is remembered for
+   the process under the device (architecture name and compute-unit count)
+   and the batch's signature (operand format, split terms, input format,
+   purity, every problem's m, n, k, l); a batch with the same signature takes
+   it without timing; reps = 0 only applies a remembered choice.  When the
+   environment variable QSK_TUNE_CACHE names a file, its entries are read
+   once per process and every new choice is appended to it, one line each:
+   "<arch> <CUs> <format>,<terms>,<input>,<pure>,<m>,<n>,<k>,<l>,... <W row
+   tiles> <Y column tiles> <W blocks>"; lines that do not parse or hold
+   shapes outside the candidates are ignored, and a file that cannot be
+   opened is not an error.  Without a call the shapes come from a padding
+   rule and 2048 W blocks.  Results of runs do not depend on the shapes
+   beyond rounding order.  Leaves the sketch buffers with meaningless values
+   (every run starts from zero).  Synchronous.  *nmt_out, *nj_out,
+   *wblocks_out (each may be NULL) receive the shapes in use.  QSK_E_ARG for
+   a NULL or short input array or reps outside 0..100. */
 qsk_status qsketch_batch_autotune(qsk_batch *b, const void *const *planes, const int64_t *ld,
-                                  int32_t reps, int32_t *nmt_out, int32_t *nj_out);
+                                  int32_t reps, int32_t *nmt_out, int32_t *nj_out, int32_t *wblocks_out);
 
 /* Execution mode of qsketch_batch_run: 0 careful only (a host check after
    every factorisation), 1 optimistic stream-ordered launches, 2 optimistic

@@ -124,7 +124,8 @@ def _load():
     lib.qsketch_batch_run.restype = i32
     lib.qsketch_batch_rel_error.argtypes = [vp, pp, pi64, pp, pi64, pp, pi64, ctypes.POINTER(ctypes.c_double)]
     lib.qsketch_batch_rel_error.restype = i32
-    lib.qsketch_batch_autotune.argtypes = [vp, pp, pi64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.qsketch_batch_autotune.argtypes = [vp, pp, pi64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                           ctypes.POINTER(i32)]
     lib.qsketch_batch_autotune.restype = i32
     lib.qsketch_batch_set_exec.argtypes = [vp, i32]
     lib.qsketch_batch_set_exec.restype = i32
@@ -497,13 +498,15 @@ class Batch:
         return qs_, xs_, [r.as_dict() for r in reps]
 
     def autotune(self, mats, reps=3):
-        """Time the candidate tile shapes of the grouped sketch launches on
-        ``mats`` and keep the fastest; returns (W row tiles, Y column tiles)."""
+        """Time the candidate launch shapes of the grouped sketch launches on
+        ``mats`` and keep the fastest (remembered per process, and in the
+        file QSK_TUNE_CACHE names); returns (W row tiles, Y column tiles,
+        W blocks of the row splits)."""
         ap, ald = self._ptr_tables(mats)
-        nmt, nj = ctypes.c_int32(), ctypes.c_int32()
+        nmt, nj, wb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         self._check(self._lib.qsketch_batch_autotune(self._b, ap, ald, reps, ctypes.byref(nmt),
-                                                     ctypes.byref(nj)))
-        return nmt.value, nj.value
+                                                     ctypes.byref(nj), ctypes.byref(wb)))
+        return nmt.value, nj.value, wb.value
 
     EXEC_MODES = {"careful": 0, "stream": 1, "graph": 2}
 

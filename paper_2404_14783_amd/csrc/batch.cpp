@@ -8,6 +8,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -70,6 +72,7 @@ struct qsk_batch {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<Prob> p;
   int mode = 0, nmt = 4, nj = 4;       // tile shapes of the grouped sketch launches
+  int wblocks = qsk::BATCH_W_BLOCKS;   // W blocks the row splits aim at
   void *pool = nullptr;
   SmallStatus *status = nullptr, *kstatus = nullptr;
   double *err_acc = nullptr;
@@ -301,7 +304,7 @@ static qsk_status launch_sketches(qsk_batch *b, const void *const *planes, const
     s.scratch = q.wpart; s.scratch_bytes = q.wpart_bytes;
     sg[i] = q.stage;
   }
-  BCHK(b, qsk::launch_sketch_mfma_batch(sa.data(), sg.data(), n_all, b->nmt, b->nj, b->arena));
+  BCHK(b, qsk::launch_sketch_mfma_batch(sa.data(), sg.data(), n_all, b->nmt, b->nj, b->arena, b->wblocks));
   return QSK_OK;
 }
 
@@ -786,6 +789,15 @@ static qsk_status batch_graph(qsk_batch *b, qsk_rangefinder rf, const void *cons
   return QSK_OK;
 }
 
+// The captured graphs hold the launch shapes they were recorded with.
+static void drop_graphs(qsk_batch *b) {
+  for (int r = 0; r < 2; ++r) {
+    if (b->gexec[r]) (void)hipGraphExecDestroy(b->gexec[r]);
+    b->gexec[r] = nullptr;
+    b->gkey[r].clear();
+  }
+}
+
 // Lay the staged test matrices out for tile shapes (nmt, nj) and regenerate
 // them; the captured graphs hold the old layout and are dropped.
 static qsk_status restage(qsk_batch *b, int nmt, int nj) {
@@ -801,25 +813,77 @@ static qsk_status restage(qsk_batch *b, int nmt, int nj) {
   b->nmt = nmt;
   b->nj = nj;
   BCHK(b, hipStreamSynchronize(b->stream));
-  for (int r = 0; r < 2; ++r) {
-    if (b->gexec[r]) (void)hipGraphExecDestroy(b->gexec[r]);
-    b->gexec[r] = nullptr;
-    b->gkey[r].clear();
-  }
+  drop_graphs(b);
   return QSK_OK;
 }
 
-// Tuned tile shapes by batch signature (operand format and every problem's
-// m, n, k, l), shared by the batches of this process.
+// Tuned launch shapes by device and batch signature (operand format and
+// every problem's m, n, k, l), shared by the batches of this process and,
+// when QSK_TUNE_CACHE names a file, kept there across processes: one line
+// per entry, "<arch> <CUs> <key, comma-separated> <nmt> <nj> <wblocks>"
+// (lines that do not parse, or name another device, are ignored).
+struct TuneChoice {
+  int nmt, nj, wblocks;
+};
 static std::mutex g_tune_mu;
-static std::map<std::vector<int64_t>, std::pair<int, int>> g_tuned;
+static std::map<std::string, TuneChoice> g_tuned;
+static bool g_tune_file_read = false;
 
-static std::vector<int64_t> tune_key(const qsk_batch *b) {
-  std::vector<int64_t> key = {b->mode, b->p[0].cfg.split_terms, b->p[0].cfg.input_dtype, b->p[0].cfg.pure};
-  for (const Prob &q : b->p) {
-    key.push_back(q.m); key.push_back(q.n); key.push_back(q.k); key.push_back(q.l);
+static std::string tune_key(const qsk_batch *b) {
+  std::string key;
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    std::string arch = prop.gcnArchName;
+    for (char &ch : arch)
+      if (ch == ' ' || ch == '\t') ch = '_';
+    key = arch + " " + std::to_string(prop.multiProcessorCount) + " ";
+  } else {
+    key = "unknown 0 ";
   }
+  std::vector<int64_t> v = {b->mode, b->p[0].cfg.split_terms, b->p[0].cfg.input_dtype, b->p[0].cfg.pure};
+  for (const Prob &q : b->p) {
+    v.push_back(q.m); v.push_back(q.n); v.push_back(q.k); v.push_back(q.l);
+  }
+  for (size_t i = 0; i < v.size(); ++i) key += (i ? "," : "") + std::to_string(v[i]);
   return key;
+}
+
+static bool valid_choice(const TuneChoice &c, int mode) {
+  const int n_nmt = mode == qsk::MODE_BF16 ? 4 : 2;
+  bool ok_nmt = false, ok_nj = false;
+  for (int a = 0; a < n_nmt; ++a) ok_nmt = ok_nmt || c.nmt == kNmt[a];
+  for (int a = 0; a < 2; ++a) ok_nj = ok_nj || c.nj == kNj[a];
+  return ok_nmt && ok_nj && c.wblocks >= 64 && c.wblocks <= (1 << 16);
+}
+
+// Called with g_tune_mu held: the cache file's entries, once per process.
+static void read_tune_file() {
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const char *path = std::getenv("QSK_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  char line[8192];
+  while (std::fgets(line, sizeof(line), f)) {
+    char arch[256], key[7000];
+    int cus = 0;
+    TuneChoice c{};
+    if (std::sscanf(line, "%255s %d %6999s %d %d %d", arch, &cus, key, &c.nmt, &c.nj, &c.wblocks) != 6) continue;
+    g_tuned[std::string(arch) + " " + std::to_string(cus) + " " + key] = c;
+  }
+  std::fclose(f);
+}
+
+// Called with g_tune_mu held: appends an entry to the cache file.
+static void append_tune_file(const std::string &key, const TuneChoice &c) {
+  const char *path = std::getenv("QSK_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %d\n", key.c_str(), c.nmt, c.nj, c.wblocks);
+  std::fclose(f);
 }
 
 extern "C" {
@@ -1027,7 +1091,7 @@ qsk_status qsketch_batch_run(qsk_batch *b, qsk_rangefinder rf, const void *const
 }
 
 qsk_status qsketch_batch_autotune(qsk_batch *b, const void *const *planes, const int64_t *ld,
-                                  int32_t reps, int32_t *nmt_out, int32_t *nj_out) {
+                                  int32_t reps, int32_t *nmt_out, int32_t *nj_out, int32_t *wblocks_out) {
   if (!b || !planes || !ld || reps < 0 || reps > 100) return QSK_E_ARG;
   if (b->poisoned) return QSK_E_STATE;
   for (int i = 0; i < b->count; ++i) {
@@ -1036,50 +1100,60 @@ qsk_status qsketch_batch_autotune(qsk_batch *b, const void *const *planes, const
     for (int p = q.cfg.pure ? 1 : 0; p < 4; ++p)
       if (!planes[4 * i + p]) return QSK_E_ARG;
   }
-  const std::vector<int64_t> key = tune_key(b);
-  int best_nmt = -1, best_nj = -1;
+  const std::string key = tune_key(b);
+  TuneChoice best_c{-1, -1, -1};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    read_tune_file();
     auto it = g_tuned.find(key);
-    if (it != g_tuned.end()) { best_nmt = it->second.first; best_nj = it->second.second; }
+    if (it != g_tuned.end() && valid_choice(it->second, b->mode)) best_c = it->second;
   }
-  if (best_nmt < 0 && reps > 0) {
+  if (best_c.nmt < 0 && reps > 0) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     BCHK(b, hipEventCreate(&e0));
     BCHK(b, hipEventCreate(&e1));
     float best = -1.0f;
     qsk_status r = QSK_OK;
     const int n_nmt = b->mode == qsk::MODE_BF16 ? 4 : 2;
+    // W row splits: fewer, longer chunks (fewer partial sums to reduce) or
+    // more, shorter ones (more blocks in flight)
+    const int wcand[3] = {qsk::BATCH_W_BLOCKS / 4, qsk::BATCH_W_BLOCKS, qsk::BATCH_W_BLOCKS * 4};
     for (int a = 0; a < n_nmt && r == QSK_OK; ++a) {
       for (int c = 0; c < 2 && r == QSK_OK; ++c) {
         if ((r = restage(b, kNmt[a], kNj[c])) != QSK_OK) break;
-        b->arena.used = 0;
-        // one untimed launch, then reps timed ones; Y and W only accumulate
-        if ((r = launch_sketches(b, planes, ld)) != QSK_OK) break;
-        if (hipEventRecord(e0, b->stream) != hipSuccess) { r = QSK_E_HIP; break; }
-        for (int t = 0; t < reps && r == QSK_OK; ++t) r = launch_sketches(b, planes, ld);
-        if (r != QSK_OK) break;
-        float ms = 0.0f;
-        if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-          r = QSK_E_HIP;
-          break;
+        for (int wb : wcand) {
+          b->wblocks = wb;
+          b->arena.used = 0;
+          // one untimed launch, then reps timed ones; Y and W only accumulate
+          if ((r = launch_sketches(b, planes, ld)) != QSK_OK) break;
+          if (hipEventRecord(e0, b->stream) != hipSuccess) { r = QSK_E_HIP; break; }
+          for (int t = 0; t < reps && r == QSK_OK; ++t) r = launch_sketches(b, planes, ld);
+          if (r != QSK_OK) break;
+          float ms = 0.0f;
+          if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            r = QSK_E_HIP;
+            break;
+          }
+          if (best < 0.0f || ms < best) { best = ms; best_c = {kNmt[a], kNj[c], wb}; }
         }
-        if (best < 0.0f || ms < best) { best = ms; best_nmt = kNmt[a]; best_nj = kNj[c]; }
       }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (r != QSK_OK) return r;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[key] = {best_nmt, best_nj};
+    g_tuned[key] = best_c;
+    append_tune_file(key, best_c);
   }
-  if (best_nmt > 0) {
-    qsk_status r = restage(b, best_nmt, best_nj);
+  if (best_c.nmt > 0) {
+    qsk_status r = restage(b, best_c.nmt, best_c.nj);
     if (r != QSK_OK) return r;
+    b->wblocks = best_c.wblocks;
   }
   if (nmt_out) *nmt_out = b->nmt;
   if (nj_out) *nj_out = b->nj;
+  if (wblocks_out) *wblocks_out = b->wblocks;
   return QSK_OK;
 }
 

@@ -96,9 +96,11 @@ void stage_geometry_tiles(int64_t m, int l, int k, int64_t maxcols, int nmt, int
 // Omega (all s.ncols columns) and Psi of one problem into its staging buffers.
 hipError_t stage_test_matrices(const SketchArgs &s, const MfmaStage &g);
 // Y = A Omega and W = Psi A of `count` problems (s[i].col0 = 0, s[i].ncols = n)
-// in one grouped launch per product.
+// in one grouped launch per product.  wblocks: the number of W blocks the
+// row splits aim at over all problems (more blocks: shorter row chunks).
+constexpr int BATCH_W_BLOCKS = 2048;
 hipError_t launch_sketch_mfma_batch(const SketchArgs *s, const MfmaStage *g, int count, int nmt,
-                                    int nj, ArgArena &ar);
+                                    int nj, ArgArena &ar, int wblocks = BATCH_W_BLOCKS);
 
 // Copies of Y the matrix-core Y kernel splits its columns over; Y is their sum.
 constexpr int Y_COPIES = 4;

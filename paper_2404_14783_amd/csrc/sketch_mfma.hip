@@ -1258,7 +1258,7 @@ hipError_t stage_test_matrices(const SketchArgs &s, const MfmaStage &g) {
 
 template <int OP, typename TIN, int TERMS>
 static hipError_t launch_batch_t(const SketchArgs *s, const MfmaStage *g, int count, int nmt, int nj,
-                                 ArgArena &ar) {
+                                 ArgArena &ar, int wblocks) {
   std::vector<YArgs> ys(count);
   std::vector<WArgs> ws(count);
   std::vector<int64_t> py(count + 1, 0), pw(count + 1, 0);
@@ -1286,11 +1286,11 @@ static hipError_t launch_batch_t(const SketchArgs *s, const MfmaStage *g, int co
     w.S = 1; w.kchunk = rup(q.m, 32); w.part = nullptr;
   }
   // W: the rows of A split so that the blocks of all problems cover about
-  // the same number of rows (about 2048 blocks in all, at least 256 rows,
-  // at most 8 splits, partial sums within the problem's scratch)
+  // the same number of rows (about `wblocks` blocks in all, at least 256
+  // rows, at most 8 splits, partial sums within the problem's scratch)
   int64_t work = 0;
   for (int i = 0; i < count; ++i) work += (int64_t)ws[i].ctiles * ws[i].rgroups * ws[i].m;
-  const int64_t wchunk = std::max<int64_t>(256, rup(work / 2048, 32));
+  const int64_t wchunk = std::max<int64_t>(256, rup(work / std::max(wblocks, 1), 32));
   std::vector<WRedArgs> rs;
   std::vector<int64_t> rb;
   for (int i = 0; i < count; ++i) {
@@ -1360,19 +1360,19 @@ static hipError_t launch_batch_t(const SketchArgs *s, const MfmaStage *g, int co
 }
 
 hipError_t launch_sketch_mfma_batch(const SketchArgs *s, const MfmaStage *g, int count, int nmt,
-                                    int nj, ArgArena &ar) {
+                                    int nj, ArgArena &ar, int wblocks) {
   if (count < 1) return hipSuccess;
   const SketchArgs &a = s[0];
   if (a.mode == MODE_BF16) {
     if (a.in_dtype == DT_F32) {
-      if (a.terms == 1) return launch_batch_t<OP_BF16, float, 1>(s, g, count, nmt, nj, ar);
-      if (a.terms == 2) return launch_batch_t<OP_BF16, float, 2>(s, g, count, nmt, nj, ar);
-      return launch_batch_t<OP_BF16, float, 3>(s, g, count, nmt, nj, ar);
+      if (a.terms == 1) return launch_batch_t<OP_BF16, float, 1>(s, g, count, nmt, nj, ar, wblocks);
+      if (a.terms == 2) return launch_batch_t<OP_BF16, float, 2>(s, g, count, nmt, nj, ar, wblocks);
+      return launch_batch_t<OP_BF16, float, 3>(s, g, count, nmt, nj, ar, wblocks);
     }
-    if (a.in_dtype == DT_BF16) return launch_batch_t<OP_BF16, uint16_t, 1>(s, g, count, nmt, nj, ar);
+    if (a.in_dtype == DT_BF16) return launch_batch_t<OP_BF16, uint16_t, 1>(s, g, count, nmt, nj, ar, wblocks);
   } else if (a.mode == MODE_F32) {
-    if (a.in_dtype == DT_F32) return launch_batch_t<OP_F32, float, 1>(s, g, count, nmt, nj, ar);
-    if (a.in_dtype == DT_BF16) return launch_batch_t<OP_F32, uint16_t, 1>(s, g, count, nmt, nj, ar);
+    if (a.in_dtype == DT_F32) return launch_batch_t<OP_F32, float, 1>(s, g, count, nmt, nj, ar, wblocks);
+    if (a.in_dtype == DT_BF16) return launch_batch_t<OP_F32, uint16_t, 1>(s, g, count, nmt, nj, ar, wblocks);
   }
   return hipErrorNotSupported;
 }

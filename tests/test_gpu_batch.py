@@ -150,17 +150,60 @@ def test_batch_autotune(sketch, terms):
     devs = [to_device(a, "f32") for a in mats]
     b = qs.Batch(SHAPES, input_dtype="f32", sketch_dtype=sketch, split_terms=terms)
     q0, x0, _ = b.run(devs, "pseudo_qr")
-    nmt, nj = b.autotune(devs, reps=2)
+    nmt, nj, wb = b.autotune(devs, reps=2)
     assert nmt in ((4, 7, 8, 13) if sketch == "bf16" else (4, 7)) and nj in (4, 7)
+    assert wb in (512, 2048, 8192)
     q1, x1, _ = b.run(devs, "pseudo_qr")
     for i in range(len(SHAPES)):
         hx0 = qt.hamilton(to_numpy(q0[i]), to_numpy(x0[i]))
         hx1 = qt.hamilton(to_numpy(q1[i]), to_numpy(x1[i]))
         assert rel(hx1, hx0) < 1e-12, (i, rel(hx1, hx0))
     b2 = qs.Batch(SHAPES, input_dtype="f32", sketch_dtype=sketch, split_terms=terms)
-    assert b2.autotune(devs, reps=0) == (nmt, nj)
+    assert b2.autotune(devs, reps=0) == (nmt, nj, wb)
     b2.close()
     b.close()
+
+
+_CACHE_CHILD = r"""
+import sys, torch
+sys.path.insert(0, sys.argv[1])
+import paper_2404_14783_amd as qs
+shapes = [(300, 200, 12, 25, 0), (257, 130, 8, 17, 1)]
+devs = [qs.to_colmajor(torch.randn(4, m, n, device="cuda")) for (m, n, k, l, s) in shapes]
+b = qs.Batch(shapes, input_dtype="f32", sketch_dtype="bf16", split_terms=2)
+print("TILES", *b.autotune(devs, reps=int(sys.argv[2])))
+b.close()
+"""
+
+
+def test_batch_tune_cache_file(tmp_path):
+    """QSK_TUNE_CACHE: a process that tunes appends its choice to the file;
+    a new process takes an entry of the file without timing (reps = 0), also
+    one that no timing would produce, and ignores lines that do not parse."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.txt"
+    env = dict(os.environ, QSK_TUNE_CACHE=str(cache))
+
+    def child(reps):
+        r = subprocess.run([sys.executable, "-c", _CACHE_CHILD, root, str(reps)], env=env,
+                           capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        line = [x for x in r.stdout.splitlines() if x.startswith("TILES")][-1]
+        return tuple(int(v) for v in line.split()[1:])
+
+    first = child(2)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    fields = lines[0].split()
+    assert len(fields) == 6 and tuple(int(v) for v in fields[3:]) == first
+    # the same key with another choice, after a malformed line: taken as is
+    other = (13, 7, 8192) if first != (13, 7, 8192) else (4, 4, 512)
+    cache.write_text("not an entry\n" + " ".join(fields[:3] + [str(v) for v in other]) + "\n")
+    assert child(0) == other
+    assert len(cache.read_text().splitlines()) == 2          # nothing appended
 
 
 # HX of the batch workload against the oracle: the device sketches differ
