@@ -277,6 +277,100 @@ __global__ __launch_bounds__(256) void qgemm64s_k(Gemm64Args args, GroupRef grp)
   }
 }
 
+// Out = Z C for a tall Z (A(i, t) = z[p][i + t sa_t], rows contiguous) and a
+// small C stored AoS (B(t, j) = the four planes at b[0] + t sb_t + j sb_j,
+// consecutive): one wave per 16 rows and up to four 16-wide column tiles,
+// so each value of Z is loaded once per four output tiles; one K step of 4
+// per iteration, the next step's operands loaded while the matrix cores
+// work.  blockIdx.x: four 16-row tiles, blockIdx.y: a group of four column
+// tiles.
+template <typename TA>
+__global__ __launch_bounds__(256) void qgemm64w_k(Gemm64Args A) {
+  if (gate_skip(A.gate)) return;
+  const int lane = threadIdx.x & 63;
+  const int tm = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tm >= A.mt) return;                                // whole wave
+  const int tn0 = blockIdx.y * 4;
+  const int ntl = min(4, A.nt - tn0);
+  const int64_t i = (int64_t)tm * 16 + (lane & 15);
+  const int kq = lane >> 4;
+  const bool iok = i < A.M;
+  const int64_t ai = (iok ? i : 0) * A.sa_i;
+  const int64_t ke = A.b_upper ? min(A.K, (int64_t)(tn0 + ntl) * 16) : A.K;
+  const double *bq = (const double *)A.b[0];
+  int64_t bj[4];
+  bool jok[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t j = (int64_t)(tn0 + u) * 16 + (lane & 15);
+    jok[u] = u < ntl && j < A.N;
+    bj[u] = (jok[u] ? j : 0) * A.sb_j;
+  }
+  v4d acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) acc[u][p] = {0.0, 0.0, 0.0, 0.0};
+  // A (the tall operand, from HBM) is loaded one step ahead; B (small,
+  // cached) when its step comes
+  double na[4];
+  typedef double d2 __attribute__((ext_vector_type(2), aligned(8)));
+#define QSK_G64W_LOAD_A(T0)                                                            \
+  do {                                                                                 \
+    const int64_t t_ = (T0) + kq;                                                      \
+    const bool tin_ = t_ < ke;                                                         \
+    const int64_t tc_ = tin_ ? t_ : 0;                                                 \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                    \
+      const double x_ = ld64<TA>(A.a[q], ai + tc_ * A.sa_t);                          \
+      na[q] = (tin_ && iok) ? x_ : 0.0;                                                \
+    }                                                                                  \
+  } while (0)
+  QSK_G64W_LOAD_A(0);
+  for (int64_t t0 = 0; t0 < ke; t0 += 4) {
+    double xa[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xa[q] = na[q];
+    if (t0 + 4 < ke) QSK_G64W_LOAD_A(t0 + 4);
+    const int64_t t = t0 + kq;
+    const bool tin = t < ke;
+    const int64_t tc = tin ? t : 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      // column tile u takes part while t is inside it (B upper triangular:
+      // rows below 16 (tn + 1) only); wave-uniform
+      if (u >= ntl || (A.b_upper && t0 >= (int64_t)(tn0 + u + 1) * 16)) continue;
+      const QSK_GLOBAL d2 *bp = (const QSK_GLOBAL d2 *)(bq + tc * A.sb_t + bj[u]);
+      const d2 v0 = bp[0], v1 = bp[1];
+      const bool ok = tin && jok[u];
+      const double xb[4] = {ok ? v0.x : 0.0, ok ? v0.y : 0.0, ok ? v1.x : 0.0, ok ? v1.y : 0.0};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double aq = xa[q], naq = -xa[q];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          acc[u][p] = __builtin_amdgcn_mfma_f64_16x16x4f64(hp_s(p, q) > 0 ? aq : naq, xb[hp_b(p, q)],
+                                                          acc[u][p], 0, 0, 0);
+      }
+    }
+  }
+#undef QSK_G64W_LOAD_A
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if (!jok[u]) continue;
+    const int64_t j = (int64_t)(tn0 + u) * 16 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = (int64_t)tm * 16 + kq + 4 * v;
+      if (r >= A.M) continue;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        QSK_GLOBAL double *o = gpw(A.out[p]) + r + j * A.ldo;
+        *o = A.accumulate ? *o + acc[u][p][v] : acc[u][p][v];
+      }
+    }
+  }
+}
+
 hipError_t launch_qgemm64_k(hipStream_t st, int ta, int tb, bool conj_a, const Gemm64Args &a, GroupRef g,
                             int64_t blocks) {
   const dim3 grid = g.tab ? dim3((unsigned)blocks) : dim3((unsigned)a.gx, (unsigned)a.gy);
@@ -326,15 +420,15 @@ __global__ void reduce_chunks_k(ReduceArgs args, GroupRef grp) {
       if (p > 0) sg = -1.0;
     }
   }
-  // four loads in flight at a time, added in chunk order
+  // sixteen loads in flight at a time, added in chunk order
   double s = 0.0;
   int c = 0;
-  for (; c + 4 <= nchunks; c += 4) {
-    const double a0 = gp(partial)[(int64_t)c * elems + src];
-    const double a1 = gp(partial)[(int64_t)(c + 1) * elems + src];
-    const double a2 = gp(partial)[(int64_t)(c + 2) * elems + src];
-    const double a3 = gp(partial)[(int64_t)(c + 3) * elems + src];
-    s += a0; s += a1; s += a2; s += a3;
+  for (; c + 16 <= nchunks; c += 16) {
+    double a[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) a[u] = gp(partial)[(int64_t)(c + u) * elems + src];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += a[u];
   }
   for (; c < nchunks; ++c) s += gp(partial)[(int64_t)c * elems + src];
   gpw(out)[e] = sg * s;
@@ -356,11 +450,15 @@ __global__ void reduce_chunks_planar_k(ReducePlanarArgs args, GroupRef grp) {
   const int i = (int)(e % r), j = (int)(e / r);
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   int ch = 0;
-  for (; ch + 2 <= nchunks; ch += 2) {           // two chunks' loads in flight, added in order
-    double a[2][4];
-    for (int u = 0; u < 2; ++u)
+  for (; ch + 4 <= nchunks; ch += 4) {           // four chunks' loads in flight, added in order
+    double a[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
       for (int p = 0; p < 4; ++p) a[u][p] = gp(partial)[((int64_t)(ch + u) * n + e) * 4 + p];
-    for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
       for (int p = 0; p < 4; ++p) s[p] += a[u][p];
   }
   for (; ch < nchunks; ++ch)
@@ -398,10 +496,10 @@ hipError_t launch_reduce_planar_k(hipStream_t st, const ReducePlanarArgs &a, Gro
   return hipGetLastError();
 }
 
-// Split of K for the matrix-core products: about 2048 waves in all (eight
-// per CU), chunks a multiple of 16, at most max_chunks of them.
+// Split of K for the matrix-core products: about 4096 waves in all (four
+// per SIMD), chunks a multiple of 16, at most max_chunks of them.
 static int64_t g64_chunk(int64_t K, int64_t tiles, int64_t max_chunks, int64_t *nch) {
-  int64_t want = (2048 + tiles - 1) / tiles;
+  int64_t want = (4096 + tiles - 1) / tiles;
   if (want > max_chunks) want = max_chunks;
   if (want < 1) want = 1;
   int64_t chunk = (K + want - 1) / want;
@@ -581,7 +679,12 @@ hipError_t launch_apply(hipStream_t st, int tz, const void *const z[4], int64_t 
   g.gate = gate;
   for (int p = 0; p < 4; ++p) g.out[p] = out[p];
   g.ldo = ldo;
-  return launch_qgemm64_k(st, tz, 0, false, g, GroupRef{}, 0);
+  // the wide kernel: Z read once per four column tiles
+  const dim3 grid((unsigned)((g.mt + 3) / 4), (unsigned)((g.nt + 3) / 4));
+  if (tz == 0) hipLaunchKernelGGL(qgemm64w_k<double>, grid, dim3(256), 0, st, g);
+  else if (tz == 1) hipLaunchKernelGGL(qgemm64w_k<float>, grid, dim3(256), 0, st, g);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

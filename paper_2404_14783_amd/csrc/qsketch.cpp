@@ -370,7 +370,9 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   ok = ok && alloc((void **)&ctx->small, S_COUNT * kk * 8);
   ok = ok && alloc((void **)&ctx->work, (12 * kk + 64 * (size_t)k) * 8);
   const int64_t maxk = l > k ? l : k;
-  ctx->partial_elems = 64 * maxk * k * 4;
+  // split-contraction partial sums: room for 64 chunks of the largest
+  // product and for 4096 chunk tiles (16 x 16, 4 planes) of any product
+  ctx->partial_elems = std::max<int64_t>(64 * maxk * k * 4, 4096 * 1024);
   ok = ok && alloc((void **)&ctx->partials, (size_t)ctx->partial_elems * 8);
   ok = ok && alloc((void **)&ctx->pbuf, 4 * (size_t)l * k * 8);
   ok = ok && alloc((void **)&ctx->p1buf, 4 * (size_t)l * k * 8);
