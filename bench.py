@@ -210,10 +210,10 @@ STATS_TITLES = {
     "image": ("31365x27125 pure quaternion BF16 image, Rademacher, k=200, l=401, BF16 operands, both rangefinders",
               "Whole one-pass approximations (14 column-block updates of 2048 columns, then the QB stage with "
               "pseudo-QR and with pseudo-SVD); input generation kernels are listed too."),
-    "flow": ("2097152x300 pure quaternion FP32 flow snapshots, 30 updates of 10 columns, fp8 + residual, "
-             "k=60, l=121, both rangefinders",
-             "Whole one-pass approximations (30 linear updates of 10 columns, then the QB stage with pseudo-QR "
-             "and with pseudo-SVD); input generation kernels are listed too."),
+    "flow": ("2097152x300 pure quaternion FP32 flow snapshots, 30 updates of 10 columns gathered into "
+             "blocks of up to 256 (250 and 50), 3 e4m3 terms on the fp8 matrix cores, k=60, l=121, both rangefinders",
+             "Whole one-pass approximations (30 linear updates of 10 columns, gathered into two products, "
+             "then the QB stage with pseudo-QR and with pseudo-SVD); input generation kernels are listed too."),
     "batch64": ("64 FP32 quaternion problems, BF16 two-term operands, autotuned tiles",
                 "Batched runs (autotuning, then runs with pseudo-QR and with pseudo-SVD); input generation "
                 "kernels are listed too."),
@@ -473,7 +473,7 @@ def bench_stream_leg(args, label, a, m, n, k, l, block, emb, input_dtype, pure, 
         for kind, (q, x, rep) in r.items():
             errors[(name, kind)] = sk.rel_error(a, q, x)
             rec[kind + "_kappa"] = rep["kappa"]
-        eff = coalesce if coalesce else block          # columns per sketch product
+        eff = (coalesce // block) * block if coalesce else block      # columns per sketch product
         nupd = (n + eff - 1) // eff
         ybytes = None
         if eff < 64:
@@ -482,6 +482,16 @@ def bench_stream_leg(args, label, a, m, n, k, l, block, emb, input_dtype, pure, 
         rec["kernels"] = kernel_rooflines(timing, m, n, k, l, pure, args.steps,
                                           PEAK_FP8 if sketch == "fp8x" else peak, ybytes, nupd)
         rec["peak_tflops"] = (PEAK_FP8 if sketch == "fp8x" else peak) / 1e12
+        if sketch == "fp8x" and timing.get("stage", (0.0, 0))[0] > 0:
+            # the e4m3 term split: reads the block once, writes T bytes per
+            # value in each of its two layouts (algorithmic bytes, no padding)
+            planes = 3 if pure else 4
+            qbytes = m * n * planes * ((4 if input_dtype == "f32" else 2) + 2 * terms) * args.steps
+            qs_ms = timing["stage"][0]
+            rec["kernels"]["quant"] = {"bytes_per_pass": qbytes / args.steps,
+                                       "achieved_gbs": qbytes / (qs_ms * 1e-3) / 1e9,
+                                       "hbm_frac": qbytes / (qs_ms * 1e-3) / PEAK_HBM,
+                                       "launches": timing["stage"][1]}
         res[name] = rec
         log(f"[bench] {label} {name}: updates {up:.2f} ms, step {tot:.2f} ms, "
             f"{rec['sketch_tflops']:.1f} TFLOP/s, kernels {rec['kernels']}")
@@ -597,6 +607,8 @@ def bench_flow(args, profile_only=False):
     leg = bench_stream_leg(args, "flow", a, m, n, k, l, block, "gaussian", "f32", True,
                            [("fp8", "fp8", 2), ("fp8_coalesced", "fp8", 2, co),
                             ("bf16", "bf16", 2), ("bf16_coalesced", "bf16", 2, co),
+                            ("fp8x1_coalesced", "fp8x", 1, args.coalesce_fp8x),
+                            ("fp8x2_coalesced", "fp8x", 2, args.coalesce_fp8x),
                             ("fp8x3_coalesced", "fp8x", 3, args.coalesce_fp8x),
                             ("fp8x4_coalesced", "fp8x", 4, args.coalesce_fp8x)],
                            PEAK_BF16, ref_block=n)
@@ -613,7 +625,7 @@ def bench_flow(args, profile_only=False):
     f8 = leg["paths"]["fp8x3_coalesced"]
     leg.update({
         "workload": f"{m}x{n} pure quaternion FP32 flow snapshots, {n // block} linear updates of {block} "
-                    f"columns gathered into blocks of {args.coalesce_fp8x} before the products, 3 e4m3 "
+                    f"columns gathered into blocks of up to {args.coalesce_fp8x} before the products, 3 e4m3 "
                     f"terms with per-tile scales on the fp8 matrix cores, Gaussian k={k} l={l}, "
                     f"both rangefinders",
         "ms_per_step": f8["total_ms"], "sketch_tflops": f8["sketch_tflops"],
@@ -702,9 +714,9 @@ def main():
                          "within 1e-3 of the FP64 path's)")
     ap.add_argument("--coalesce", type=int, default=150,
                     help="flow workload: columns gathered per sketch product (coalesce_cols)")
-    ap.add_argument("--coalesce-fp8x", type=int, default=128,
-                    help="flow workload, e4m3-term paths: columns gathered per product (the fp8 "
-                         "products take 128 columns per step of Y)")
+    ap.add_argument("--coalesce-fp8x", type=int, default=256,
+                    help="flow workload, e4m3-term paths: columns gathered per product (whole "
+                         "update blocks, so 250 of the 10-column blocks)")
     ap.add_argument("--profile-only", action="store_true",
                     help="one bf16 pass only (for rocprofv3 runs)")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CMD_FETCH", "CMD_WRITE"),
