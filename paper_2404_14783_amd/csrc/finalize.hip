@@ -1078,6 +1078,54 @@ __device__ __forceinline__ void chol_trailing(qd *T, int o, double *r, int k, co
     }
   }
 }
+// The same update dealt out in 2 x 2 blocks of entries (rows a0, a0 + 1,
+// columns c0, c0 + 1 of the trailing triangle, block (A, C) with A <= C
+// packed by columns): the four panel values of a block's rows and columns
+// are loaded once per panel row for up to four entries, half the LDS reads
+// per entry of one entry at a time.  Each entry's arithmetic is the same as
+// one at a time.
+template <bool INLDS>
+__device__ __forceinline__ void chol_trailing2(qd *T, int o, double *r, int k, const qd *done, int w, int j0,
+                                               int jb, int b0, int nr) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int nb = (nr + 1) >> 1;
+  const int tot = (nb * (nb + 1)) >> 1;
+  const int end = b0 + nr;
+  for (int e = tid; e < tot; e += nt) {
+    int cc = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while (cc > 0 && ((cc * (cc + 1)) >> 1) > e) --cc;
+    while ((((cc + 1) * (cc + 2)) >> 1) <= e) ++cc;
+    const int ab = e - ((cc * (cc + 1)) >> 1);
+    const int a0 = b0 + 2 * ab, c0 = b0 + 2 * cc, a1 = a0 + 1, c1 = c0 + 1;
+    // entries of the block inside the upper triangle and the trailing block
+    const bool v01 = c1 < end, v10 = ab < cc && a1 < end, v11 = a1 < end && c1 < end;
+    qd x00 = INLDS ? T[chol_pk(a0 - o, c0 - o)] : gq(r, a0, c0, k);
+    qd x01 = v01 ? (INLDS ? T[chol_pk(a0 - o, c1 - o)] : gq(r, a0, c1, k)) : qzero();
+    qd x10 = v10 ? (INLDS ? T[chol_pk(a1 - o, c0 - o)] : gq(r, a1, c0, k)) : qzero();
+    qd x11 = v11 ? (INLDS ? T[chol_pk(a1 - o, c1 - o)] : gq(r, a1, c1, k)) : qzero();
+    const int ia0 = a0 - j0, ic0 = c0 - j0;
+    const int ia1 = a1 < end ? ia0 + 1 : ia0, ic1 = c1 < end ? ic0 + 1 : ic0;
+    for (int rr = 0; rr < jb; ++rr) {
+      const qd *dr = done + rr * w;
+      const qd da0 = qconj(dr[ia0]), da1 = qconj(dr[ia1]), dc0 = dr[ic0], dc1 = dr[ic1];
+      x00 = qsub(x00, qmul(da0, dc0));
+      x01 = qsub(x01, qmul(da0, dc1));
+      x10 = qsub(x10, qmul(da1, dc0));
+      x11 = qsub(x11, qmul(da1, dc1));
+    }
+    if (INLDS) {
+      T[chol_pk(a0 - o, c0 - o)] = x00;
+      if (v01) T[chol_pk(a0 - o, c1 - o)] = x01;
+      if (v10) T[chol_pk(a1 - o, c0 - o)] = x10;
+      if (v11) T[chol_pk(a1 - o, c1 - o)] = x11;
+    } else {
+      sq_(r, a0, c0, k, x00);
+      if (v01) sq_(r, a0, c1, k, x01);
+      if (v10) sq_(r, a1, c0, k, x10);
+      if (v11) sq_(r, a1, c1, k, x11);
+    }
+  }
+}
 __device__ void sm_chol(const double *g, double *r, int k, int complex_only, double shift,
                         double tol, int *fail, double *minp, double *trace) {
   // Panels of CB pivot rows live in LDS twice: `panel` holds the rows as
@@ -1166,8 +1214,10 @@ __device__ void sm_chol(const double *g, double *r, int k, int complex_only, dou
     // trailing update of the upper triangle, its entries dealt to the
     // threads in turn (packed by columns)
     const int nr = k - j0 - jb, b0 = j0 + jb;
+    // (in LDS one entry at a time; in global memory 2 x 2 blocks, whose
+    // halved panel reads shorten the memory-bound update)
     if (T) chol_trailing<true, 4>(T, o, r, k, done, w, j0, jb, b0, nr);
-    else chol_trailing<false, 8>(T, o, r, k, done, w, j0, jb, b0, nr);
+    else chol_trailing2<false>(T, o, r, k, done, w, j0, jb, b0, nr);
     __syncthreads();
   }
 #undef QSK_CHOL_GET

@@ -365,9 +365,19 @@ template <> __device__ __forceinline__ void dma_frag<FragF>(const char *blk, int
 
 // bf16 +-1 pair of entries 2d, 2d + 1 of a plane whose sign bits sit at
 // bits 8d and 8d + 4 of y
-__device__ __forceinline__ uint32_t rad_pair(uint32_t y, int d) {
-  const uint32_t lo = (y >> (8 * d)) & 1u, hi = (y >> (8 * d + 4)) & 1u;
-  return 0x3F803F80u | (lo << 15) | (hi << 31);
+// The four words of bf16 +-1 pairs of one 32-bit sign word y: word d holds
+// (-1)^bit(8d) in its low half and (-1)^bit(8d + 4) in its high half.  The
+// sign bits are moved to bit 7 of each byte (s, t), then one byte permute
+// per word places byte d of s and of t at the two sign positions.
+__device__ __forceinline__ u32v4 rad_quad(uint32_t y) {
+  const uint32_t s = (y << 7) & 0x80808080u, t = (y << 3) & 0x80808080u;
+  u32v4 v;
+  // selector bytes: 0x0c = zero byte, 0..3 = bytes of s, 4..7 = bytes of t
+  v.x = __builtin_amdgcn_perm(t, s, 0x040c000cu) | 0x3F803F80u;
+  v.y = __builtin_amdgcn_perm(t, s, 0x050c010cu) | 0x3F803F80u;
+  v.z = __builtin_amdgcn_perm(t, s, 0x060c020cu) | 0x3F803F80u;
+  v.w = __builtin_amdgcn_perm(t, s, 0x070c030cu) | 0x3F803F80u;
+  return v;
 }
 
 __device__ __forceinline__ uint32_t pick_word(int wd, int i, const uint32_t (&z)[8]) {
@@ -408,9 +418,7 @@ __device__ __forceinline__ void rad_tile(char *lds, int64_t o0, int64_t n_o, int
   for (int g = 0; g < 4; ++g)
 #pragma unroll
     for (int pl = 0; pl < 4; ++pl) {
-      const uint32_t y = w[g] >> pl;
-      const u32v4 v = {rad_pair(y, 0), rad_pair(y, 1), rad_pair(y, 2), rad_pair(y, 3)};
-      *(QSK_LDS u32v4 *)(lds + (pl * NT + tile) * 1024 + (16 * g + c) * 16) = v;
+      *(QSK_LDS u32v4 *)(lds + (pl * NT + tile) * 1024 + (16 * g + c) * 16) = rad_quad(w[g] >> pl);
     }
 }
 
