@@ -80,11 +80,13 @@ struct qsk_ctx {
   double *err_acc = nullptr;
   double *pinv_work = nullptr;         // (l + k) x k quaternions
   SmallStatus *status = nullptr;
-  // kappa estimates only feed the report, so they run on a side stream that
-  // forks from and joins back into the context stream within each finalize
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  double *kwork = nullptr;             // workspace of the side-stream kappa kernels
+  // kappa estimates only feed the report, so they run on side streams that
+  // fork from and join back into the context stream within each finalize:
+  // kappa of H0 (pseudo-QR) on `side`, kappa of Q on `side2`, so that the
+  // second need not wait for the first
+  hipStream_t side = nullptr, side2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_fork2 = nullptr, ev_join2 = nullptr;
+  double *kwork = nullptr, *kwork2 = nullptr;   // workspaces of the two kappa kernels
   SmallStatus *kstatus = nullptr;
   void *w_scratch = nullptr;           // split-K partials of the matrix-core W kernel
   int64_t w_scratch_bytes = 0;
@@ -210,9 +212,13 @@ void free_events(qsk_ctx *c) {
 void free_all(qsk_ctx *c) {
   free_events(c);
   if (c->side) (void)hipStreamSynchronize(c->side);
+  if (c->side2) (void)hipStreamSynchronize(c->side2);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->ev_fork2) (void)hipEventDestroy(c->ev_fork2);
+  if (c->ev_join2) (void)hipEventDestroy(c->ev_join2);
   if (c->side) (void)hipStreamDestroy(c->side);
+  if (c->side2) (void)hipStreamDestroy(c->side2);
   if (c->uexec) (void)hipGraphExecDestroy(c->uexec);
   if (c->gstream) (void)hipStreamSynchronize(c->gstream);
   if (c->gev_in) (void)hipEventDestroy(c->gev_in);
@@ -221,11 +227,11 @@ void free_all(qsk_ctx *c) {
   c->uexec = nullptr;
   c->gev_in = c->gev_out = nullptr;
   c->gstream = nullptr;
-  c->ev_fork = c->ev_join = nullptr;
-  c->side = nullptr;
+  c->ev_fork = c->ev_join = c->ev_fork2 = c->ev_join2 = nullptr;
+  c->side = c->side2 = nullptr;
   void *ptrs[] = {c->y, c->w, c->u[0], c->u[1], c->small, c->work, c->partials, c->pbuf,
                   c->p1buf, c->sbuf, c->err_acc, c->status, c->w_scratch, c->pinv_work,
-                  c->stage.omega, c->stage.psi, c->kwork, c->kstatus, c->fp8_scales, c->zero_plane, c->xt, c->proj_part, c->pad, c->pend,
+                  c->stage.omega, c->stage.psi, c->kwork, c->kwork2, c->kstatus, c->fp8_scales, c->zero_plane, c->xt, c->proj_part, c->pad, c->pend,
                   c->f8.qw, c->f8.qy, c->f8.psi, c->f8.om};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -236,7 +242,7 @@ void free_all(qsk_ctx *c) {
   c->w_scratch = nullptr;
   c->pinv_work = nullptr;
   c->stage.omega = c->stage.psi = nullptr;
-  c->kwork = nullptr;
+  c->kwork = c->kwork2 = nullptr;
   c->fp8_scales = nullptr;
   c->kstatus = nullptr;
   c->f8.qw = c->f8.qy = c->f8.psi = c->f8.om = nullptr;
@@ -382,9 +388,13 @@ qsk_status qsketch_init(const qsk_config *cfg, void *hip_stream, qsk_ctx **out) 
   ok = ok && alloc((void **)&ctx->status, sizeof(SmallStatus));
   ok = ok && alloc((void **)&ctx->kstatus, sizeof(SmallStatus));
   ok = ok && alloc((void **)&ctx->kwork, kk * 8);
+  ok = ok && alloc((void **)&ctx->kwork2, kk * 8);
   ok = ok && hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&ctx->side2, hipStreamNonBlocking) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&ctx->ev_fork2, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&ctx->ev_join2, hipEventDisableTiming) == hipSuccess;
   // matrix-core path: staging of Omega_J / Psi and the W split-K partials
   if (mfma_mode) {
     qsk::MfmaStage &g = ctx->stage;
@@ -852,6 +862,7 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
   const size_t kk = (size_t)k * k * 4;
   SmallStatus hs{};
   int flags = 0;
+  bool kappa0 = false;                 // kappa of H0 launched on `side`
 
   {
     const qsk_status fs = flush_pending(ctx);
@@ -940,6 +951,8 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
     HIPCHK(ctx, hipEventRecord(ctx->ev_fork, st));
     HIPCHK(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
     HIPCHK(ctx, qsk::launch_kappa(ctx->side, k, slot(ctx, S_GK0), ctx->kwork, 1, ctx->kstatus));
+    HIPCHK(ctx, hipEventRecord(ctx->ev_join, ctx->side));
+    kappa0 = true;
     // correction steps (eq. CondNumReductionIter) in the k x k space: with
     // H_j = H0 C_j and G_j = H_j^* H_j, H_{j+1} = (1 - eps) H_j + eps (H_j^dagger)^*
     // = H_j M_j with M_j = (1 - eps) I + eps G_j^{-1}  ((H^dagger)^* = H G^{-1});
@@ -975,10 +988,10 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
   // kappa(Q) from G_Q = F^* G_Z F
   HIPCHK(ctx, qsk::launch_small_gemm(st, k, gz, 0, slot(ctx, S_F), 0, slot(ctx, S_TMP2)));
   HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_F), 1, slot(ctx, S_TMP2), 0, slot(ctx, S_GH)));
-  HIPCHK(ctx, hipEventRecord(ctx->ev_fork, st));
-  HIPCHK(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
-  HIPCHK(ctx, qsk::launch_kappa(ctx->side, k, slot(ctx, S_GH), ctx->kwork, 0, ctx->kstatus));
-  HIPCHK(ctx, hipEventRecord(ctx->ev_join, ctx->side));
+  HIPCHK(ctx, hipEventRecord(ctx->ev_fork2, st));
+  HIPCHK(ctx, hipStreamWaitEvent(ctx->side2, ctx->ev_fork2, 0));
+  HIPCHK(ctx, qsk::launch_kappa(ctx->side2, k, slot(ctx, S_GH), ctx->kwork2, 0, ctx->kstatus));
+  HIPCHK(ctx, hipEventRecord(ctx->ev_join2, ctx->side2));
   HIPCHK(ctx, qsk::launch_apply(st, tz, zsrc, m, m, k, slot(ctx, S_F), k, Q, ldq));
 
   // ---- core solve X = (Psi Q)^dagger W (Alg. 2 through the normal form of
@@ -1072,8 +1085,10 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
   HIPCHK(ctx, qsk::launch_crossprod_planar(st, sp, l, ty, wp, l, l, k, (int)n, X, ldx));
   }
 
-  // join the side stream (kappa estimates) before reading its results
-  HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_join, 0));
+  // join the side streams (kappa estimates) before reading their results
+  // (the two kernels write different fields of kstatus)
+  if (kappa0) HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_join, 0));
+  HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_join2, 0));
   SmallStatus ks{}, hs2{};
   HIPCHK(ctx, hipMemcpyAsync(&ks, ctx->kstatus, sizeof(ks), hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipMemcpyAsync(&hs2, ctx->status, sizeof(hs2), hipMemcpyDeviceToHost, st));
