@@ -127,7 +127,8 @@ __device__ __forceinline__ bool g64_tile(const Gemm64Args &A, int tile, int *tm,
   return true;
 }
 
-template <typename TA, typename TB, bool CONJ_A, bool ACONT, bool BCONT>
+// ATILE: A is a staged Psi in the step-tile layout (psi_tiled_index)
+template <typename TA, typename TB, bool CONJ_A, bool ACONT, bool BCONT, bool ATILE = false>
 __global__ __launch_bounds__(256) void qgemm64_k(Gemm64Args args, GroupRef grp) {
   Gemm64Args A;
   int bx, by, bz;
@@ -144,6 +145,7 @@ __global__ __launch_bounds__(256) void qgemm64_k(Gemm64Args args, GroupRef grp) 
   const int64_t ke = min(A.b_upper ? min(A.K, (int64_t)tn * 16 + 16) : A.K, kb + A.kchunk);
   const bool iok = i < A.M, jok = j < A.N;
   const int64_t ai = (iok ? i : 0) * A.sa_i, bj = (jok ? j : 0) * A.sb_j;
+#define QSK_G64_AIDX(T_) (ATILE ? psi_tiled_index<(int)sizeof(TA)>(iok ? i : 0, (T_), A.a_lp16) : ai + (T_) * A.sa_t)
   v4d acc[4];
 #pragma unroll
   for (int p = 0; p < 4; ++p) acc[p] = {0.0, 0.0, 0.0, 0.0};
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(256) void qgemm64_k(Gemm64Args args, GroupRef grp) 
     const int64_t t_ = (T0) + 4 * kq;                                                  \
     if ((T0) + 16 <= ke) {                                                             \
       _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                  \
-        ld64x4<TA, ACONT>(A.a[q], ai + t_ * A.sa_t, A.sa_t, na[q]);                    \
+        ld64x4<TA, ACONT>(A.a[q], QSK_G64_AIDX(t_), A.sa_t, na[q]);                    \
         ld64x4<TB, BCONT>(A.b[q], t_ * A.sb_t + bj, A.sb_t, nb[q]);                    \
       }                                                                                \
     } else {                                                                           \
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(256) void qgemm64_k(Gemm64Args args, GroupRef grp) 
         _Pragma("unroll") for (int s = 0; s < 4; ++s) {                                \
           const bool in_ = t_ + s < ke;                                                \
           const int64_t tc_ = in_ ? t_ + s : kb;                                       \
-          const double x_ = ld64<TA>(A.a[q], ai + tc_ * A.sa_t);                       \
+          const double x_ = ld64<TA>(A.a[q], QSK_G64_AIDX(tc_));                       \
           const double y_ = ld64<TB>(A.b[q], tc_ * A.sb_t + bj);                       \
           na[q][s] = in_ ? x_ : 0.0;                                                   \
           nb[q][s] = in_ ? y_ : 0.0;                                                   \
@@ -191,6 +193,7 @@ __global__ __launch_bounds__(256) void qgemm64_k(Gemm64Args args, GroupRef grp) 
       }
   }
 #undef QSK_G64_LOAD
+#undef QSK_G64_AIDX
   if (!jok) return;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -386,6 +389,12 @@ hipError_t launch_qgemm64_k(hipStream_t st, int ta, int tb, bool conj_a, const G
     else if (ta == 0 && tb == 1) QSK_G64(double, float, true);
     else if (ta == 0 && tb == 2) QSK_G64(double, uint16_t, true);
     else if (ta == 1 && tb == 1) QSK_G64(float, float, true);
+    else return hipErrorInvalidValue;
+  } else if (a.a_tiled) {
+    // a staged Psi (contiguous in t within its step tiles) times H
+    if (!bc) return hipErrorInvalidValue;
+    if (ta == 1 && tb == 0) hipLaunchKernelGGL((qgemm64_k<float, double, false, true, true, true>), grid, dim3(256), 0, st, a, g);
+    else if (ta == 2 && tb == 0) hipLaunchKernelGGL((qgemm64_k<uint16_t, double, false, true, true, true>), grid, dim3(256), 0, st, a, g);
     else return hipErrorInvalidValue;
   } else {
     if (ta == 0 && tb == 0) QSK_G64(double, double, false);
@@ -657,6 +666,8 @@ bool g64_plan_psi(const void *psi_st, int es, int64_t psi_ld, int64_t psi_ps, co
   for (int q = 0; q < 4; ++q) pp[q] = (const char *)psi_st + (size_t)q * psi_ps * es;
   const void *hh[4] = {h[0], h[1], h[2], h[3]};
   *g = g64_args(pp, psi_ld, 1, hh, 1, ldh, l, k, m);
+  g->a_tiled = 1;
+  g->a_lp16 = psi_ps / psi_ld / 16;
   int64_t nch;
   g->kchunk = g64_group_chunk(m, chunk_hint, max_chunks, &nch);
   g->gy = (int)nch;
@@ -717,12 +728,12 @@ __global__ __launch_bounds__(256) void psi_apply_k(PsiApplyArgs args, GroupRef g
       const int64_t gi = i0 + ii;
       double v[4] = {0.0, 0.0, 0.0, 0.0};
       if (gi < ie && r0 + q < l) {
-        if (A.psi_st_type == 1) {          // bf16 staging of the sketch
-          const QSK_GLOBAL uint16_t *ps = gp((const uint16_t *)A.psi_st) + (int64_t)(r0 + q) * A.psi_ld + gi;
+        if (A.psi_st_type == 1) {          // bf16 staging of the sketch (step tiles)
+          const QSK_GLOBAL uint16_t *ps = gp((const uint16_t *)A.psi_st) + psi_tiled_index<2>(r0 + q, gi, A.psi_ps / A.psi_ld / 16);
 #pragma unroll
           for (int p = 0; p < 4; ++p) v[p] = (double)__uint_as_float(((uint32_t)ps[p * A.psi_ps]) << 16);
         } else if (A.psi_st_type == 2) {   // fp32 staging
-          const QSK_GLOBAL float *ps = gp((const float *)A.psi_st) + (int64_t)(r0 + q) * A.psi_ld + gi;
+          const QSK_GLOBAL float *ps = gp((const float *)A.psi_st) + psi_tiled_index<4>(r0 + q, gi, A.psi_ps / A.psi_ld / 16);
 #pragma unroll
           for (int p = 0; p < 4; ++p) v[p] = (double)ps[p * A.psi_ps];
         } else {
@@ -793,6 +804,8 @@ hipError_t launch_psi_apply(hipStream_t st, int mode, int rad, uint32_t k0, uint
     for (int q = 0; q < 4; ++q) pp[q] = (const char *)psi_st + (size_t)q * psi_ps * es;
     const void *hh[4] = {h[0], h[1], h[2], h[3]};
     Gemm64Args g = g64_args(pp, psi_ld, 1, hh, 1, ldh, l, k, m);
+    g.a_tiled = 1;                       // the step-tile layout of the staging
+    g.a_lp16 = psi_ps / psi_ld / 16;
     g.kchunk = g64_chunk(m, (int64_t)g.mt * g.nt, max_chunks, &nch);
     g.gy = (int)nch;
     g.partial = partials;

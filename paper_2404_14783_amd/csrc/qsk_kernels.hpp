@@ -209,6 +209,23 @@ struct GroupRef {
   int count;
 };
 
+// Step-tile layout of the staged Psi on the matrix-core path (ES bytes per
+// element): element (o, t) of a plane with 16 lp16 rows (o) and a multiple of
+// 32 columns (t, the contraction index of W = Psi A) lies in the 512-element
+// tile of step t / 32 and row tile o / 16, ordered [sub][g][o mod 16][e] with
+// g = (t mod 32) / 8, CE = 16 / ES elements per 16 bytes, sub = (t mod 8) /
+// CE and e = t mod CE.  A lane L = (o mod 16) + 16 g of the W kernel's
+// direct-to-LDS load takes 16 bytes at 16 L (+ 1 KB per sub), so each load
+// instruction reads 1 KB of consecutive bytes; four consecutive t from a
+// multiple of 4 stay consecutive.
+template <int ES>
+__host__ __device__ __forceinline__ int64_t psi_tiled_index(int64_t o, int64_t t, int64_t lp16) {
+  constexpr int CE = 16 / ES;
+  const int64_t tt = t & 31;
+  return (((t >> 5) * lp16 + (o >> 4)) << 9) + ((tt & 7) / CE) * (64 * CE) + (tt >> 3) * (16 * CE) +
+         (o & 15) * CE + (tt % CE);
+}
+
 struct Gemm64Args {         // C = opA(A) B, quaternion, FP64 matrix cores (16 x 16 tiles)
   const void *a[4]; int64_t sa_i, sa_t;   // A(i, t) of plane p: a[p][i * sa_i + t * sa_t]
   const void *b[4]; int64_t sb_t, sb_j;   // B(t, j): b[p][t * sb_t + j * sb_j]
@@ -219,6 +236,8 @@ struct Gemm64Args {         // C = opA(A) B, quaternion, FP64 matrix cores (16 x
   int herm;                               // C Hermitian (A = B, conj): tiles tm <= tn only
   int b_upper;                            // B upper triangular: t < 16 (tn + 1) only
   const SmallStatus *gate;                // skip when its gate passes (see ONE_PASS_KAPPA2)
+  int a_tiled;                            // A is a staged Psi in the step-tile layout
+  int64_t a_lp16;                         // (its rows / 16; sa_i, sa_t unused)
   int gx, gy;
 };
 struct ReduceArgs {

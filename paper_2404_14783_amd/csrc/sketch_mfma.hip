@@ -49,7 +49,7 @@ constexpr bool op_f32(int op) { return op == OP_F32; }
 template <int MODE, typename OPT>
 __global__ __launch_bounds__(256) void gen_stage_kernel(OPT *dst, int n_o, int o_pad, int64_t t0,
                                                         int64_t n_t, int64_t t_pad, uint32_t stream,
-                                                        int rad, uint32_t k0, uint32_t k1) {
+                                                        int rad, uint32_t k0, uint32_t k1, int tiled) {
   const int64_t total = (int64_t)o_pad * t_pad;
   const int64_t ps = total;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -58,12 +58,13 @@ __global__ __launch_bounds__(256) void gen_stage_kernel(OPT *dst, int n_o, int o
     const int o = (int)(e / t_pad);
     float v[4] = {0.f, 0.f, 0.f, 0.f};
     if (o < n_o && t < n_t) embed_entry<MODE>(rad, (uint32_t)(t0 + t), (uint32_t)o, stream, k0, k1, v);
+    const int64_t d = tiled ? psi_tiled_index<sizeof(OPT)>(o, t, o_pad >> 4) : e;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       if constexpr (sizeof(OPT) == 2) {
-        dst[p * ps + e] = (OPT)(__float_as_uint(v[p]) >> 16);   // exact: v is a bf16 value
+        dst[p * ps + d] = (OPT)(__float_as_uint(v[p]) >> 16);   // exact: v is a bf16 value
       } else {
-        dst[p * ps + e] = v[p];
+        dst[p * ps + d] = v[p];
       }
     }
   }
@@ -493,9 +494,11 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
   // columns' values and are never stored)
   uint32_t voff = (uint32_t)((ib + 8 * g + j * a.lda) * (int64_t)sizeof(TIN));
   const uint32_t vstep = 32u * (uint32_t)sizeof(TIN);
-  // this lane's DMA source: row c16 of a 16-row tile, indices 8g (+4 sb)
-  const OPT *psrc = psi + (int64_t)(rbase + c16) * a.MP + 8 * g;
-  const int64_t tile_st = 16 * a.MP;                       // next row tile
+  // DMA sources: the step tile of row tile rt at step i is 1 KB (2 KB for
+  // FP32) of contiguous staging, lane L takes 16 bytes at 16 L
+  constexpr int CE = 16 / (int)sizeof(OPT);                // elements per lane and load
+  const int lp16 = a.LP >> 4;
+  const OPT *psrc = psi + (int64_t)(rbase >> 4) * 512 + lane * CE;
 
   floatx4 acc[NH][4];
 #pragma unroll
@@ -541,7 +544,7 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
       const int u_ = wave + k_ * NW;                                                            \
       if (u_ < NBLK) {                                                                          \
         const int sb_ = u_ % SUB, rt_ = (u_ / SUB) % NMT, pl_ = u_ / (SUB * NMT);               \
-        dma16(psrc + pl_ * pps + rt_ * tile_st + (I0) + 4 * sb_, &s_psi[B][u_][0]);             \
+        dma16(psrc + pl_ * pps + ((I0) >> 5) * lp16 * 512 + rt_ * 512 + 64 * CE * sb_, &s_psi[B][u_][0]); \
       }                                                                                         \
     }                                                                                           \
   } while (0)
@@ -952,14 +955,17 @@ void stage_geometry(int64_t m, int l, int k, int64_t maxcols, int op_bf16, int *
   *NP = rup(maxcols, 32);
 }
 
+// tiled: the step-tile layout of Psi (psi_tiled_index; t_pad a multiple of
+// 32, o_pad of 16), else [plane][o][t] with t fastest (Omega)
 template <int MODE, typename OPT>
 static hipError_t gen_stage(hipStream_t st, OPT *dst, int n_o, int o_pad, int64_t t0, int64_t n_t,
-                            int64_t t_pad, uint32_t stream, int rad, uint32_t k0, uint32_t k1) {
+                            int64_t t_pad, uint32_t stream, int rad, uint32_t k0, uint32_t k1,
+                            bool tiled = false) {
   const int64_t total = (int64_t)o_pad * t_pad;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL((gen_stage_kernel<MODE, OPT>), dim3((unsigned)blocks), dim3(256), 0, st, dst,
-                     n_o, o_pad, t0, n_t, t_pad, stream, rad, k0, k1);
+                     n_o, o_pad, t0, n_t, t_pad, stream, rad, k0, k1, tiled ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -1088,18 +1094,18 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
   } else if (s.mode == MODE_BF16) {
     e = gen_stage<MODE_BF16, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
-    if (!s.psi_ready && !s.skip_w) e = gen_stage<MODE_BF16, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
+    if (!s.psi_ready && !s.skip_w) e = gen_stage<MODE_BF16, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1, true);
     if (e != hipSuccess) return e;
   } else if (s.mode == MODE_FP8) {
     // e4m3 test-matrix values, staged as (exact) bf16
     e = gen_stage<MODE_FP8, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
-    if (!s.psi_ready && !s.skip_w) e = gen_stage<MODE_FP8, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
+    if (!s.psi_ready && !s.skip_w) e = gen_stage<MODE_FP8, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1, true);
     if (e != hipSuccess) return e;
   } else {
     e = gen_stage<MODE_F32, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
-    if (!s.psi_ready && !s.skip_w) e = gen_stage<MODE_F32, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1);
+    if (!s.psi_ready && !s.skip_w) e = gen_stage<MODE_F32, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1, true);
     if (e != hipSuccess) return e;
   }
   // fp8: the tile scales of this block
@@ -1236,13 +1242,13 @@ void stage_geometry_tiles(int64_t m, int l, int k, int64_t maxcols, int nmt, int
 hipError_t stage_psi(const SketchArgs &s, const MfmaStage &g) {
   if (s.mode == MODE_BF16)
     return gen_stage<MODE_BF16, uint16_t>(s.stream, (uint16_t *)g.psi, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI,
-                                          s.rad, s.k0, s.k1);
+                                          s.rad, s.k0, s.k1, true);
   if (s.mode == MODE_FP8 || s.mode == MODE_FP8X)
     return gen_stage<MODE_FP8, uint16_t>(s.stream, (uint16_t *)g.psi, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI,
-                                         s.rad, s.k0, s.k1);
+                                         s.rad, s.k0, s.k1, true);
   if (s.mode == MODE_F32)
     return gen_stage<MODE_F32, float>(s.stream, (float *)g.psi, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad,
-                                      s.k0, s.k1);
+                                      s.k0, s.k1, true);
   return hipErrorNotSupported;
 }
 
@@ -1252,14 +1258,14 @@ hipError_t stage_test_matrices(const SketchArgs &s, const MfmaStage &g) {
                                                   g.NP, STREAM_OMEGA, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
     return gen_stage<MODE_BF16, uint16_t>(s.stream, (uint16_t *)g.psi, s.l, g.LP, 0, s.m, g.MP,
-                                          STREAM_PSI, s.rad, s.k0, s.k1);
+                                          STREAM_PSI, s.rad, s.k0, s.k1, true);
   }
   if (s.mode == MODE_F32) {
     hipError_t e = gen_stage<MODE_F32, float>(s.stream, (float *)g.omega, s.k, g.KP, 0, s.ncols, g.NP,
                                               STREAM_OMEGA, s.rad, s.k0, s.k1);
     if (e != hipSuccess) return e;
     return gen_stage<MODE_F32, float>(s.stream, (float *)g.psi, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI,
-                                      s.rad, s.k0, s.k1);
+                                      s.rad, s.k0, s.k1, true);
   }
   return hipErrorNotSupported;
 }
