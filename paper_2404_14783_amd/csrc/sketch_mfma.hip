@@ -755,8 +755,11 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
   const uint32_t col_bytes = (uint32_t)(a.lda * (int64_t)sizeof(TIN));
   uint32_t voff = (uint32_t)((row + (tb + 8 * g) * a.lda) * (int64_t)sizeof(TIN));
   const uint32_t vstep = 32u * col_bytes;
-  const OPT *osrc = om + (int64_t)(jt0 * 16 + c16) * a.NP + 8 * g;
-  const int64_t tile_st = 16 * a.NP;
+  // DMA sources: the step tile of column tile jt at step t is 1 KB (2 KB for
+  // FP32) of contiguous staging, lane L takes 16 bytes at 16 L
+  constexpr int CE = 16 / (int)sizeof(OPT);                // elements per lane and load
+  const int kp16 = a.KP >> 4;
+  const OPT *osrc = om + (int64_t)jt0 * 512 + lane * CE;
 
   floatx4 acc[NJ][4];
 #pragma unroll
@@ -789,7 +792,7 @@ __global__ __launch_bounds__(256 * H) __attribute__((amdgpu_waves_per_eu(H, H)))
       const int u_ = wave + k_ * NW;                                                            \
       if (u_ < NBLK) {                                                                          \
         const int sb_ = u_ % SUB, jt_ = (u_ / SUB) % NJ, pl_ = u_ / (SUB * NJ);                 \
-        dma16(osrc + pl_ * ops + jt_ * tile_st + (T0) + 4 * sb_, &s_om[B][u_][0]);              \
+        dma16(osrc + pl_ * ops + ((T0) >> 5) * kp16 * 512 + jt_ * 512 + 64 * CE * sb_, &s_om[B][u_][0]); \
       }                                                                                         \
     }                                                                                           \
   } while (0)
@@ -955,8 +958,9 @@ void stage_geometry(int64_t m, int l, int k, int64_t maxcols, int op_bf16, int *
   *NP = rup(maxcols, 32);
 }
 
-// tiled: the step-tile layout of Psi (psi_tiled_index; t_pad a multiple of
-// 32, o_pad of 16), else [plane][o][t] with t fastest (Omega)
+// tiled: the step-tile layout (psi_tiled_index; t_pad a multiple of 32,
+// o_pad of 16) that the product kernels' direct-to-LDS loads read, else
+// [plane][o][t] with t fastest
 template <int MODE, typename OPT>
 static hipError_t gen_stage(hipStream_t st, OPT *dst, int n_o, int o_pad, int64_t t0, int64_t n_t,
                             int64_t t_pad, uint32_t stream, int rad, uint32_t k0, uint32_t k1,
@@ -1092,18 +1096,18 @@ static hipError_t launch_t(const SketchArgs &s, const MfmaStage &g) {
   if (gen) {
     // nothing staged
   } else if (s.mode == MODE_BF16) {
-    e = gen_stage<MODE_BF16, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
+    e = gen_stage<MODE_BF16, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1, true);
     if (e != hipSuccess) return e;
     if (!s.psi_ready && !s.skip_w) e = gen_stage<MODE_BF16, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1, true);
     if (e != hipSuccess) return e;
   } else if (s.mode == MODE_FP8) {
     // e4m3 test-matrix values, staged as (exact) bf16
-    e = gen_stage<MODE_FP8, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
+    e = gen_stage<MODE_FP8, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1, true);
     if (e != hipSuccess) return e;
     if (!s.psi_ready && !s.skip_w) e = gen_stage<MODE_FP8, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1, true);
     if (e != hipSuccess) return e;
   } else {
-    e = gen_stage<MODE_F32, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1);
+    e = gen_stage<MODE_F32, OPT>(s.stream, om, s.k, g.KP, s.col0, s.ncols, NPu, STREAM_OMEGA, s.rad, s.k0, s.k1, true);
     if (e != hipSuccess) return e;
     if (!s.psi_ready && !s.skip_w) e = gen_stage<MODE_F32, OPT>(s.stream, ps, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI, s.rad, s.k0, s.k1, true);
     if (e != hipSuccess) return e;
@@ -1255,14 +1259,14 @@ hipError_t stage_psi(const SketchArgs &s, const MfmaStage &g) {
 hipError_t stage_test_matrices(const SketchArgs &s, const MfmaStage &g) {
   if (s.mode == MODE_BF16) {
     hipError_t e = gen_stage<MODE_BF16, uint16_t>(s.stream, (uint16_t *)g.omega, s.k, g.KP, 0, s.ncols,
-                                                  g.NP, STREAM_OMEGA, s.rad, s.k0, s.k1);
+                                                  g.NP, STREAM_OMEGA, s.rad, s.k0, s.k1, true);
     if (e != hipSuccess) return e;
     return gen_stage<MODE_BF16, uint16_t>(s.stream, (uint16_t *)g.psi, s.l, g.LP, 0, s.m, g.MP,
                                           STREAM_PSI, s.rad, s.k0, s.k1, true);
   }
   if (s.mode == MODE_F32) {
     hipError_t e = gen_stage<MODE_F32, float>(s.stream, (float *)g.omega, s.k, g.KP, 0, s.ncols, g.NP,
-                                              STREAM_OMEGA, s.rad, s.k0, s.k1);
+                                              STREAM_OMEGA, s.rad, s.k0, s.k1, true);
     if (e != hipSuccess) return e;
     return gen_stage<MODE_F32, float>(s.stream, (float *)g.psi, s.l, g.LP, 0, s.m, g.MP, STREAM_PSI,
                                       s.rad, s.k0, s.k1, true);
