@@ -27,7 +27,8 @@ def oracle_cfg(m, n, k, l, seed, sketch, terms):
     return SketchConfig(m, n, k, l, seed=seed, dtype=sketch, terms=terms)
 
 
-@pytest.mark.parametrize("sketch,terms,pure", [("bf16", 2, False), ("fp8", 2, True), ("f32", 1, False)])
+@pytest.mark.parametrize("sketch,terms,pure", [("bf16", 2, False), ("fp8", 2, True), ("f32", 1, False),
+                                               ("fp8x", 3, True), ("fp8x", 2, False)])
 def test_coalesced_stream_matches_oracle(sketch, terms, pure):
     """300 columns arriving in blocks of 10 with coalesce_cols = 64: the
     context gathers 6 blocks (60 columns) per product; the oracle streams

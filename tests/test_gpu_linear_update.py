@@ -33,6 +33,9 @@ CASES = [
     ("bf16", "f32", "gaussian", 2, 333, 1e-5),
     ("bf16", "f32", "rademacher", 2, 1100, 1e-5),   # W split over row chunks + reduction
     ("fp8", "f32", "gaussian", 2, 333, 1e-5),
+    # e4m3 terms on the fp8 matrix cores: three terms put 1.5x the products of
+    # the two-term bf16 split into each FP32 sum (entry-wise bound as for all)
+    ("fp8x", "f32", "gaussian", 3, 333, 3e-5),
 ]
 
 
@@ -102,7 +105,7 @@ def test_invalid_scalars_leave_sketches_unchanged():
 
 
 @pytest.mark.parametrize("sketch,dtype,terms", [("f64", "f64", 1), ("bf16", "f32", 2),
-                                                ("fp8", "f32", 2)])
+                                                ("fp8", "f32", 2), ("fp8x", "f32", 3)])
 def test_checkpoint_restore_continues_stream(sketch, dtype, terms):
     """Stream half the columns, checkpoint to host memory, restore into a new
     context and stream the rest: the sketches match an uninterrupted stream
@@ -154,7 +157,8 @@ def test_checkpoint_restore_continues_stream(sketch, dtype, terms):
 
 
 @pytest.mark.parametrize("sketch,dtype,emb,terms", [("f64", "f64", "gaussian", 1), ("f32", "f32", "gaussian", 1),
-                                                    ("bf16", "f32", "rademacher", 2), ("fp8", "f32", "gaussian", 2)])
+                                                    ("bf16", "f32", "rademacher", 2), ("fp8", "f32", "gaussian", 2),
+                                                    ("fp8x", "bf16", "rademacher", 3)])
 def test_row_block_updates(sketch, dtype, emb, terms):
     """A[I, J] += H over a ragged 2-D partition of A (row blocks of 1..400
     rows): the device against the oracle's sub-block updates, and the FP64 /
@@ -185,7 +189,7 @@ def test_row_block_updates(sketch, dtype, emb, terms):
     ey, ew = rel(y, ref.Y), rel(w, ref.W)
     print(f"  rel. diff Y {ey:.2e}, W {ew:.2e}", flush=True)
     assert ey < tol and ew < tol
-    if sketch != "fp8":
+    if sketch not in ("fp8", "fp8x"):                # (the e4m3 tile scales follow the sub-blocks)
         one = sketch_matrix(a, oracle_cfg(m, n, k, l, 9, emb, sketch, terms), block_cols=block)
         assert rel(y, one.Y) < tol and rel(w, one.W) < tol
     sk.close()

@@ -24,7 +24,8 @@ def blocks_of(dev, n, block):
 
 
 @pytest.mark.parametrize("sketch,terms,pure,coalesce", [("bf16", 2, False, 0), ("fp8", 2, True, 0),
-                                                        ("bf16", 2, False, 64), ("f32", 1, False, 0)])
+                                                        ("bf16", 2, False, 64), ("f32", 1, False, 0),
+                                                        ("fp8x", 3, True, 0), ("fp8x", 3, False, 128)])
 def test_update_graph_replays_match_single_updates(sketch, terms, pure, coalesce):
     m, n, k, l, block = 3000, 300, 24, 49, 10
     print(f"update graph: {sketch} x{terms} pure={pure} coalesce={coalesce}", flush=True)
