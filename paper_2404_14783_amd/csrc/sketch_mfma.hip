@@ -1442,133 +1442,120 @@ __device__ __forceinline__ float e4m3_value(uint32_t b) {
 
 // One block per 128 x 128 piece of one plane of the padded block (4 x 4
 // tiles of 32 x 32): the tile scales (the smallest power of two sc with
-// amax / sc <= 448, 1 for an all-zero tile), then the T e4m3 terms, written
-// column by column (qw: 128 bytes of each column) and, through LDS, row by
-// row (qy: 128 bytes of each row).  Thread (column t / 2, rows 64 (t mod 2)
-// .. + 63).  Values outside the block are zero.  The e4m3 rounding is the
-// hardware's round-to-nearest-even conversion, the inputs are within range
-// (|x / sc| <= 448 for term 0, <= 256 after it).
+// amax / sc <= 448, 1 for an all-zero tile), then the T e4m3 terms of every
+// value, one term at a time staged in LDS in both byte layouts and written
+// out column by column (qw: 128 bytes of each column) and row by row (qy:
+// 128 bytes of each row).  Every global access instruction covers whole 128-byte runs:
+// thread t loads 4 consecutive rows (16 bytes of FP32) of column
+// (t / 8) + 32 j at rows 32 s + 4 (t mod 8), j, s = 0..3, so 8 lanes read one
+// 32-row run of a column; the stores move 16 bytes per lane, 8 lanes per
+// column (qw) or row (qy).  Values outside the block are zero.  The e4m3
+// rounding is the hardware's round-to-nearest-even conversion; the inputs
+// are within range (|x / sc| <= 448 for term 0, <= 256 after it).
+constexpr int QLD = 144;                 // LDS row of 128 bytes, padded
 template <typename TIN>
 __global__ __launch_bounds__(256) void fp8x_quant_kernel(QuantArgs a) {
-  __shared__ float red[4][128];
-  __shared__ float s_sc[4][4];
-  __shared__ __attribute__((aligned(16))) uint8_t tr[4][128][144];   // [term][row][column], padded rows
+  __shared__ __attribute__((aligned(16))) uint8_t s_qw[128][QLD];      // [column][row]
+  __shared__ __attribute__((aligned(16))) uint8_t s_qy[128][QLD];      // [row][column]
+  __shared__ float s_red[4][16];
+  __shared__ float s_sc[16];
   const int q = blockIdx.z;
   if (q == 0 && a.pure) return;
   const int64_t r0 = (int64_t)blockIdx.x * 128, c0 = (int64_t)blockIdx.y * 128;
-  const int tid = threadIdx.x, cc = tid >> 1, hr = 64 * (tid & 1);
-  const int64_t c = c0 + cc, rbeg = r0 + hr;
-  float x[64];
-  {
-    // buffer loads over the plane's extent [0, ((ncols - 1) lda + m)
-    // elements): loads past the end read zero; rows past m of a column read
-    // the next column's values and are masked
+  const int tid = threadIdx.x, l8 = tid & 7, cg = tid >> 3, lane = tid & 63, wave = tid >> 6;
+  const rsrc_t rs = make_rsrc(a.a[q], (uint32_t)(((a.ncols - 1) * a.lda + a.m) * (int64_t)sizeof(TIN)));
+  // x[j][s][i]: row r0 + 32 s + 4 l8 + i of column c0 + cg + 32 j
+  float x[4][4][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t c = c0 + cg + 32 * j;
     const bool colok = c < a.ncols;
-    const rsrc_t rs = make_rsrc(a.a[q], (uint32_t)(((a.ncols - 1) * a.lda + a.m) * (int64_t)sizeof(TIN)));
-    const int64_t e0 = (colok ? c : 0) * a.lda + rbeg;          // first element of this thread
-    if constexpr (sizeof(TIN) == 4) {
-      const uint32_t base = (uint32_t)(e0 * 4);
 #pragma unroll
-      for (int i = 0; i < 64; i += 8) {
-        const u32v4 u0 = __builtin_amdgcn_raw_buffer_load_b128(rs, base + 4u * i, 0, 0);
-        const u32v4 u1 = __builtin_amdgcn_raw_buffer_load_b128(rs, base + 4u * i + 16u, 0, 0);
-        const float v[8] = {__uint_as_float(u0.x), __uint_as_float(u0.y), __uint_as_float(u0.z), __uint_as_float(u0.w),
-                            __uint_as_float(u1.x), __uint_as_float(u1.y), __uint_as_float(u1.z), __uint_as_float(u1.w)};
+    for (int s = 0; s < 4; ++s) {
+      const int64_t r = r0 + 32 * s + 4 * l8;
+      const uint32_t off = (uint32_t)(((colok ? c : 0) * a.lda + r) * (int64_t)sizeof(TIN));
+      float v[4];
+      if constexpr (sizeof(TIN) == 4) {
+        const u32v4 u = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        v[0] = __uint_as_float(u.x); v[1] = __uint_as_float(u.y); v[2] = __uint_as_float(u.z); v[3] = __uint_as_float(u.w);
+      } else {
+        // 2-byte loads: exact range checks and no alignment requirement
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[i + u] = (colok && rbeg + i + u < a.m) ? v[u] : 0.f;
+        for (int i = 0; i < 4; ++i) v[i] = bload1<uint16_t>(rs, off + 2u * i, 0);
       }
-    } else {
-      // dword loads need dword-aligned addresses: with an odd element offset
-      // (odd lda, odd column) the loads start one element early and every
-      // pair is taken across two dwords
-      const uint32_t odd = (uint32_t)(e0 & 1);
-      const uint32_t base = (uint32_t)((e0 - odd) * 2);
-      uint32_t d[33];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const u32v4 u = __builtin_amdgcn_raw_buffer_load_b128(rs, base + 16u * i, 0, 0);
-        d[4 * i] = u.x; d[4 * i + 1] = u.y; d[4 * i + 2] = u.z; d[4 * i + 3] = u.w;
-      }
-      d[32] = odd ? __builtin_amdgcn_raw_buffer_load_b32(rs, base + 128u, 0, 0) : 0u;
-#pragma unroll
-      for (int p = 0; p < 32; ++p) {
-        const uint32_t w = odd ? __builtin_amdgcn_alignbit(d[p + 1], d[p], 16) : d[p];
-        x[2 * p] = (colok && rbeg + 2 * p < a.m) ? __uint_as_float(w << 16) : 0.f;
-        x[2 * p + 1] = (colok && rbeg + 2 * p + 1 < a.m) ? __uint_as_float(w & 0xFFFF0000u) : 0.f;
-      }
-    }
-    // bf16: the range check works per dword, so the dword that holds the
-    // block's last element A[m-1, ncols-1] may reach past the end and read
-    // as zero; that element is loaded on its own
-    if constexpr (sizeof(TIN) == 2) {
-      const uint32_t end = (uint32_t)(((a.ncols - 1) * a.lda + a.m) * 2);
-      const float last = bload1<uint16_t>(rs, end - 2, 0);
-#pragma unroll
-      for (int i = 0; i < 64; ++i)
-        if (c == a.ncols - 1 && rbeg + i == a.m - 1) x[i] = last;
+      for (int i = 0; i < 4; ++i) x[j][s][i] = (colok && r + i < a.m) ? v[i] : 0.f;
     }
   }
-  // tile maxima: this thread's column over its two 32-row tiles
+  // tile maxima: tile (s, j) over this thread's 4 values, the wave, then the
+  // four waves
+  float mx[16];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    float mx = 0.f;
+  for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int i = 0; i < 32; ++i) mx = fmaxf(mx, fabsf(x[32 * h + i]));
-    red[(hr >> 5) + h][cc] = mx;
+    for (int s = 0; s < 4; ++s)
+      mx[4 * s + j] = fmaxf(fmaxf(fabsf(x[j][s][0]), fabsf(x[j][s][1])), fmaxf(fabsf(x[j][s][2]), fabsf(x[j][s][3])));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) mx[u] = fmaxf(mx[u], __shfl_xor(mx[u], off, 64));
+  if (lane < 16) {
+    float v = mx[0];
+#pragma unroll
+    for (int u = 1; u < 16; ++u) v = lane == u ? mx[u] : v;
+    s_red[wave][lane] = v;
   }
   __syncthreads();
   if (tid < 16) {
-    const int rt = tid >> 2, ct = tid & 3;
-    float mx = 0.f;
-    for (int i = 0; i < 32; ++i) mx = fmaxf(mx, red[rt][32 * ct + i]);
+    const float m4 = fmaxf(fmaxf(s_red[0][tid], s_red[1][tid]), fmaxf(s_red[2][tid], s_red[3][tid]));
     float sc = 1.f;
-    if (mx > 0.f) {
-      // mx = f 2^E with 0.5 <= f < 1 and 448 = 0.875 2^9: the smallest e with
-      // mx <= 448 2^e is E - 9, or E - 8 when f > 0.875
+    if (m4 > 0.f) {
+      // m4 = f 2^E with 0.5 <= f < 1 and 448 = 0.875 2^9: the smallest e with
+      // m4 <= 448 2^e is E - 9, or E - 8 when f > 0.875
       int E;
-      const float f = frexpf(mx, &E);
+      const float f = frexpf(m4, &E);
       sc = ldexpf(1.f, E - 9 + (f > 0.875f ? 1 : 0));
     }
-    s_sc[rt][ct] = sc;
+    s_sc[tid] = sc;
+    const int rt = tid >> 2, ct = tid & 3;
     const int64_t grt = r0 / 32 + rt, gct = c0 / 32 + ct;
     if (grt < a.RT && gct < a.CT) gpw(a.fsc)[((int64_t)q * a.RT + grt) * a.CT + gct] = sc;
   }
   __syncthreads();
+  // terms: 4 bytes per (j, s) and term, one word into the column layout and
+  // four bytes into the row layout; then the stores, 16 bytes per lane,
+  // id = tid + 256 v: line id / 8, piece id mod 8
   for (int t = 0; t < a.T; ++t) {
-    uint32_t word[16];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const float sc = s_sc[(hr >> 5) + h][cc >> 5];
-      const float st = ldexpf(sc, -4 * t), inv = ldexpf(1.f / sc, 4 * t);   // powers of two
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int i = 0; i < 32; i += 2) {
-        const int k0 = 32 * h + i;
-        const uint32_t pk = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x[k0] * inv, x[k0 + 1] * inv, 0, false);
-        const uint32_t b0 = pk & 0xFFu, b1 = (pk >> 8) & 0xFFu;
-        x[k0] -= e4m3_value(b0) * st;                                  // exact
-        x[k0 + 1] -= e4m3_value(b1) * st;
-        const int wi = k0 >> 2, sh = 8 * (k0 & 3);
-        if (sh == 0) word[wi] = b0 | (b1 << 8);
-        else word[wi] |= (b0 << 16) | (b1 << 24);
-        tr[t][hr + k0][cc] = (uint8_t)b0;
-        tr[t][hr + k0 + 1][cc] = (uint8_t)b1;
+      for (int s = 0; s < 4; ++s) {
+        const float sc = s_sc[4 * s + j];
+        const float st = ldexpf(sc, -4 * t), inv = ldexpf(1.f / sc, 4 * t);   // powers of two
+        const uint32_t p01 = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x[j][s][0] * inv, x[j][s][1] * inv, 0, false);
+        const uint32_t p23 = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x[j][s][2] * inv, x[j][s][3] * inv, 0, false);
+        const uint32_t b[4] = {p01 & 0xFFu, (p01 >> 8) & 0xFFu, p23 & 0xFFu, (p23 >> 8) & 0xFFu};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[j][s][i] -= e4m3_value(b[i]) * st;                // exact
+        const int col = cg + 32 * j, row = 32 * s + 4 * l8;
+        *(QSK_LDS uint32_t *)&s_qw[col][row] = b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s_qy[row + i][col] = (uint8_t)b[i];
+      }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int id = tid + 256 * v, ln = id >> 3, pc = id & 7;
+      if (c0 + ln < a.CPW) {
+        QSK_GLOBAL u32v4 *dst = (QSK_GLOBAL u32v4 *)(gpw(a.qw) + (((int64_t)q * a.T + t) * a.CPW + c0 + ln) * a.RP + r0 + 16 * pc);
+        *dst = *(const QSK_LDS u32v4 *)&s_qw[ln][16 * pc];
+      }
+      if (c0 + 16 * pc < a.CP) {
+        QSK_GLOBAL u32v4 *dst = (QSK_GLOBAL u32v4 *)(gpw(a.qy) + (((int64_t)q * a.T + t) * a.RP + r0 + ln) * a.CP + c0 + 16 * pc);
+        *dst = *(const QSK_LDS u32v4 *)&s_qy[ln][16 * pc];
       }
     }
-    if (c < a.CPW) {
-      QSK_GLOBAL u32v4 *dst = (QSK_GLOBAL u32v4 *)(gpw(a.qw) + (((int64_t)q * a.T + t) * a.CPW + c) * a.RP + rbeg);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) dst[v] = u32v4{word[4 * v], word[4 * v + 1], word[4 * v + 2], word[4 * v + 3]};
-    }
-  }
-  __syncthreads();
-  // rows: thread (row t / 2, columns 64 (t mod 2) .. + 63)
-  const int rr = tid >> 1, hc = 64 * (tid & 1);
-  if (c0 + hc < a.CP) {
-    for (int t = 0; t < a.T; ++t) {
-      QSK_GLOBAL u32v4 *dst = (QSK_GLOBAL u32v4 *)(gpw(a.qy) + (((int64_t)q * a.T + t) * a.RP + r0 + rr) * a.CP + c0 + hc);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) dst[v] = *(const QSK_LDS u32v4 *)&tr[t][rr][hc + 16 * v];
-    }
+    __syncthreads();                           // the buffers are written again for the next term
   }
 }
 
