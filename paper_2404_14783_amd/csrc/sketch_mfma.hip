@@ -1423,13 +1423,25 @@ __device__ __forceinline__ uint32_t e4m3_byte(float e4m3_value) {   // exact for
   return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(e4m3_value, 0.f, 0, false) & 0xFFu;
 }
 
+// Fragment-ordered 2 KB blocks of e4m3 bytes (the layout of the quantised
+// data and of the staged test matrices): 16 indices r (rows of an A operand,
+// columns of a B operand) x 128 contraction indices kk, byte (r, kk) at
+// (kk / 64) 1024 + (r + 16 ((kk mod 64) / 16)) 16 + kk mod 16.  Lane
+// L = r + 16 g of the fp8 instruction takes its 32 operand bytes as the 16
+// bytes at 16 L and at 1024 + 16 L, so each load or direct-to-LDS copy of a
+// block moves 1 KB of consecutive bytes; a staged tile keeps this order in
+// LDS.  Blocks follow each other along kk (the contraction) fastest.
+__host__ __device__ constexpr int frag8_off(int r, int kk) {
+  return (kk >> 6) * 1024 + (r + 16 * ((kk & 63) >> 4)) * 16 + (kk & 15);
+}
+
 struct QuantArgs {
   const void *a[4];
   int64_t lda, m, ncols;
   int pure, RT, CT, T;
   float *fsc;                 // out: tile scales [4][RT][CT]
-  uint8_t *qw;                // [q][t][column < CPW][row < RP]
-  uint8_t *qy;                // [q][t][row < RP][column < CP]
+  uint8_t *qw;                // [q][t]: blocks (16 columns, 128 rows), rows fastest
+  uint8_t *qy;                // [q][t]: blocks (16 rows, 128 columns), columns fastest
   int64_t RP, CPW, CP;
 };
 
@@ -1523,8 +1535,10 @@ __global__ __launch_bounds__(256) void fp8x_quant_kernel(QuantArgs a) {
   }
   __syncthreads();
   // terms: 4 bytes per (j, s) and term, one word into the column layout and
-  // four bytes into the row layout; then the stores, 16 bytes per lane,
-  // id = tid + 256 v: line id / 8, piece id mod 8
+  // four bytes into the row layout; then the stores, 16 bytes per lane:
+  // piece id = tid + 256 v of the eight 2 KB blocks of the piece, block
+  // id / 128, 16 bytes w = id mod 128 at (r, kk) = (w mod 16, 64 (w / 64) +
+  // 16 ((w mod 64) / 16))
   for (int t = 0; t < a.T; ++t) {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -1545,22 +1559,25 @@ __global__ __launch_bounds__(256) void fp8x_quant_kernel(QuantArgs a) {
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int id = tid + 256 * v, ln = id >> 3, pc = id & 7;
-      if (c0 + ln < a.CPW) {
-        QSK_GLOBAL u32v4 *dst = (QSK_GLOBAL u32v4 *)(gpw(a.qw) + (((int64_t)q * a.T + t) * a.CPW + c0 + ln) * a.RP + r0 + 16 * pc);
-        *dst = *(const QSK_LDS u32v4 *)&s_qw[ln][16 * pc];
+      const int id = tid + 256 * v, blk = id >> 7, w = id & 127;
+      const int r = w & 15, kk = 64 * (w >> 6) + 16 * ((w & 63) >> 4);
+      if (c0 + 16 * blk < a.CPW) {
+        QSK_GLOBAL u32v4 *dst = (QSK_GLOBAL u32v4 *)(gpw(a.qw) + ((int64_t)q * a.T + t) * a.CPW * a.RP +
+                                                     ((c0 / 16 + blk) * (a.RP / 128) + r0 / 128) * 2048 + 16 * w);
+        *dst = *(const QSK_LDS u32v4 *)&s_qw[16 * blk + r][kk];
       }
-      if (c0 + 16 * pc < a.CP) {
-        QSK_GLOBAL u32v4 *dst = (QSK_GLOBAL u32v4 *)(gpw(a.qy) + (((int64_t)q * a.T + t) * a.RP + r0 + ln) * a.CP + c0 + 16 * pc);
-        *dst = *(const QSK_LDS u32v4 *)&s_qy[ln][16 * pc];
-      }
+      QSK_GLOBAL u32v4 *dst = (QSK_GLOBAL u32v4 *)(gpw(a.qy) + ((int64_t)q * a.T + t) * a.RP * a.CP +
+                                                   ((r0 / 16 + blk) * (a.CP / 128) + c0 / 128) * 2048 + 16 * w);
+      *dst = *(const QSK_LDS u32v4 *)&s_qy[16 * blk + r][kk];
     }
     __syncthreads();                           // the buffers are written again for the next term
   }
 }
 
-// Test-matrix staging as e4m3 bytes: [plane][o][t], t fastest, zero outside
-// (o < n_o, t < n_t); four consecutive t per thread (t_pad is a multiple of 4).
+// Test-matrix staging as e4m3 bytes: per plane, fragment-ordered blocks
+// (16 o x 128 t, frag8_off) with t fastest, zero outside (o < n_o,
+// t < n_t); four consecutive t per thread (o_pad a multiple of 16, t_pad of
+// 128).
 __global__ __launch_bounds__(256) void gen_stage8_kernel(uint8_t *dst, int n_o, int o_pad, int64_t t0,
                                                          int64_t n_t, int64_t t_pad, uint32_t stream, int rad,
                                                          uint32_t k0, uint32_t k1) {
@@ -1578,8 +1595,9 @@ __global__ __launch_bounds__(256) void gen_stage8_kernel(uint8_t *dst, int n_o, 
 #pragma unroll
       for (int p = 0; p < 4; ++p) out[p] |= e4m3_byte(v[p]) << (8 * i);
     }
+    const int64_t d = ((t >> 7) * (o_pad >> 4) + (o >> 4)) * 2048 + frag8_off(o & 15, (int)(t & 127));
 #pragma unroll
-    for (int p = 0; p < 4; ++p) *(QSK_GLOBAL uint32_t *)(gpw(dst) + p * ps + (int64_t)o * t_pad + t) = out[p];
+    for (int p = 0; p < 4; ++p) *(QSK_GLOBAL uint32_t *)(gpw(dst) + p * ps + d) = out[p];
   }
 }
 
@@ -1604,7 +1622,7 @@ __device__ __forceinline__ i32x8 lds_frag8(const char *tile, int c16, int g) {
 }
 __device__ __forceinline__ i32x8 bload_frag8(rsrc_t rs, uint32_t off) {
   const u32v4 lo = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-  const u32v4 hi = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 64, 0, 0);
+  const u32v4 hi = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 1024, 0, 0);
   i32x8 r;
   r[0] = (int)lo.x; r[1] = (int)lo.y; r[2] = (int)lo.z; r[3] = (int)lo.w;
   r[4] = (int)hi.x; r[5] = (int)hi.y; r[6] = (int)hi.z; r[7] = (int)hi.w;
@@ -1660,7 +1678,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     for (int t = 0; t < T; ++t)
       dr[q][t] = make_rsrc(a.qw + ((int64_t)(PURE ? (q > 0 ? q : 1) : q) * T + t) * a.CPW * a.RP,
                            (uint32_t)(a.CPW * a.RP));
-  uint32_t voff = (uint32_t)(j * a.RP + ib + 16 * g);
+  // this lane's data bytes: block (column tile, row step), 16 bytes at 16 lane
+  uint32_t voff = (uint32_t)((((int64_t)bx * 4 + wave) * (a.RP / 128) + ib / 128) * 2048 + 16 * lane);
   // DMA source of this lane for 1 KB block half hh of a (plane, tile): chunk
   // c = 64 hh + lane is (kc = c / 16, row c mod 16)
   floatx4 acc[NMT][4];
@@ -1683,9 +1702,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     _Pragma("unroll") for (int k_ = 0; k_ < NBLK / 4; ++k_) {                                    \
       const int u_ = wave + 4 * k_;                                                              \
       const int hh_ = u_ & 1, rt_ = (u_ >> 1) % NMT, pl_ = (u_ >> 1) / NMT;                      \
-      const int ch_ = 64 * hh_ + lane;                                                           \
-      dma16(a.psi + ((int64_t)pl_ * a.LP + rbase + rt_ * 16 + (ch_ & 15)) * a.MPF + (I0) + 16 * (ch_ >> 4), \
-            &s_psi[B][(pl_ * NMT + rt_) * TB + hh_ * 1024]);                                     \
+      dma16(a.psi + (((int64_t)pl_ * (a.MPF / 128) + (I0) / 128) * (a.LP / 16) + rbase / 16 + rt_) * 2048 + \
+                hh_ * 1024 + 16 * lane, &s_psi[B][(pl_ * NMT + rt_) * TB + hh_ * 1024]);       \
     }                                                                                            \
   } while (0)
   QSK_W8_FETCH(ib);
@@ -1702,7 +1720,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
       for (int t = 0; t < T; ++t) cur[q][t] = df[q][t];
     }
-    voff += 128;
+    voff += 2048;
     if (i0 + 128 < ie) {
       QSK_W8_DMA(i0 + 128, buf ^ 1);
       __builtin_amdgcn_sched_barrier(0);
@@ -1798,7 +1816,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     for (int t = 0; t < T; ++t)
       dr[q][t] = make_rsrc(a.qy + ((int64_t)(PURE ? (q > 0 ? q : 1) : q) * T + t) * a.RP * a.CP,
                            (uint32_t)(a.RP * a.CP));
-  uint32_t voff = (uint32_t)(row * a.CP + tb + 16 * g);
+  // this lane's data bytes: block (row tile, column step), 16 bytes at 16 lane
+  uint32_t voff = (uint32_t)((((rb + wave * 16) / 16) * (a.CP / 128) + tb / 128) * 2048 + 16 * lane);
   floatx4 acc[NJ][4];
 #pragma unroll
   for (int i = 0; i < NJ; ++i)
@@ -1819,9 +1838,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     _Pragma("unroll") for (int k_ = 0; k_ < NBLK / 4; ++k_) {                                    \
       const int u_ = wave + 4 * k_;                                                              \
       const int hh_ = u_ & 1, jt_ = (u_ >> 1) % NJ, pl_ = (u_ >> 1) / NJ;                        \
-      const int ch_ = 64 * hh_ + lane;                                                           \
-      dma16(a.om + ((int64_t)pl_ * a.KP + (jt0 + jt_) * 16 + (ch_ & 15)) * a.NPF + (T0) + 16 * (ch_ >> 4), \
-            &s_om[B][(pl_ * NJ + jt_) * TB + hh_ * 1024]);                                       \
+      dma16(a.om + (((int64_t)pl_ * (a.NPF / 128) + (T0) / 128) * (a.KP / 16) + jt0 + jt_) * 2048 + \
+                hh_ * 1024 + 16 * lane, &s_om[B][(pl_ * NJ + jt_) * TB + hh_ * 1024]);         \
     }                                                                                            \
   } while (0)
   QSK_Y8_FETCH(tb);
@@ -1838,7 +1856,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
       for (int t = 0; t < T; ++t) cur[q][t] = df[q][t];
     }
-    voff += 128;
+    voff += 2048;
     if (t0 + 128 < te) {
       QSK_Y8_DMA(t0 + 128, buf ^ 1);
       __builtin_amdgcn_sched_barrier(0);
@@ -1919,8 +1937,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   for (int k_ = 0; k_ < NBLK / 4; ++k_) {
     const int u_ = wave + 4 * k_;
     const int hh_ = u_ & 1, jt_ = (u_ >> 1) % NJ, pl_ = (u_ >> 1) / NJ;
-    const int ch_ = 64 * hh_ + lane;
-    dma16(a.om + ((int64_t)pl_ * a.KP + (jt0 + jt_) * 16 + (ch_ & 15)) * a.NPF + 16 * (ch_ >> 4),
+    dma16(a.om + ((int64_t)pl_ * (a.NPF / 128) * (a.KP / 16) + jt0 + jt_) * 2048 + hh_ * 1024 + 16 * lane,
           &s_om[(pl_ * NJ + jt_) * TB + hh_ * 1024]);
   }
   i32x8 df[4][T];
@@ -1929,7 +1946,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #define QSK_YR_FETCH(BX)                                                                         \
   do {                                                                                           \
     const int64_t row_ = (BX) * 64 + wave * 16 + c16;                                            \
-    const uint32_t off_ = (uint32_t)(row_ * a.CP + 16 * g);                                      \
+    const uint32_t off_ = (uint32_t)((((BX) * 4 + wave) * (a.CP / 128)) * 2048 + 16 * lane);        \
     const int srt_ = (int)min(row_ >> 5, (int64_t)a.RT - 1);                                     \
     _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                              \
       if (q == 0 && PURE) continue;                                                              \
