@@ -1914,11 +1914,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 // blocks of 64 (bx, bx + G, bx + 2 G, ...); the data fragments of the next
 // row block and the old Y values of the current one are fetched before the
 // products, so their latency hides behind the matrix cores.
-template <int NJ, int T, bool PURE>
+template <int NJ, int T, bool PURE, int NS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void y_fp8x_rows_kernel(Y8Args a) {
+  // NS 128-column steps of the gathered block (CP = 128 NS), their Omega
+  // tiles all resident
   constexpr int TB = 2048;
   constexpr int NBLK = 4 * NJ * 2;
-  __shared__ __attribute__((aligned(1024))) char s_om[4 * NJ * TB];
+  __shared__ __attribute__((aligned(1024))) char s_om[NS][4 * NJ * TB];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c16 = lane & 15, g = lane >> 4;
@@ -1932,32 +1934,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     for (int t = 0; t < T; ++t)
       dr[q][t] = make_rsrc(a.qy + ((int64_t)(PURE ? (q > 0 ? q : 1) : q) * T + t) * a.RP * a.CP,
                            (uint32_t)(a.RP * a.CP));
-  // the Omega tile (128 columns of the block x NJ tiles x 4 planes)
+  // the Omega tiles (128 NS columns of the block x NJ tiles x 4 planes)
 #pragma unroll
-  for (int k_ = 0; k_ < NBLK / 4; ++k_) {
-    const int u_ = wave + 4 * k_;
-    const int hh_ = u_ & 1, jt_ = (u_ >> 1) % NJ, pl_ = (u_ >> 1) / NJ;
-    dma16(a.om + ((int64_t)pl_ * (a.NPF / 128) * (a.KP / 16) + jt0 + jt_) * 2048 + hh_ * 1024 + 16 * lane,
-          &s_om[(pl_ * NJ + jt_) * TB + hh_ * 1024]);
-  }
+  for (int ks = 0; ks < NS; ++ks)
+#pragma unroll
+    for (int k_ = 0; k_ < NBLK / 4; ++k_) {
+      const int u_ = wave + 4 * k_;
+      const int hh_ = u_ & 1, jt_ = (u_ >> 1) % NJ, pl_ = (u_ >> 1) / NJ;
+      dma16(a.om + (((int64_t)pl_ * (a.NPF / 128) + ks) * (a.KP / 16) + jt0 + jt_) * 2048 + hh_ * 1024 + 16 * lane,
+            &s_om[ks][(pl_ * NJ + jt_) * TB + hh_ * 1024]);
+    }
+  // one (row block, column step) at a time: the next one's data terms are
+  // loaded while the matrix cores work on this one; Y is read at the first
+  // step of a row block and written after its last
   i32x8 df[4][T];
   int e8[4] = {127, 127, 127, 127};
   int64_t bx = blockIdx.x;
-#define QSK_YR_FETCH(BX)                                                                         \
+  int ks = 0;
+#define QSK_YR_FETCH(BX, KS)                                                                     \
   do {                                                                                           \
     const int64_t row_ = (BX) * 64 + wave * 16 + c16;                                            \
-    const uint32_t off_ = (uint32_t)((((BX) * 4 + wave) * (a.CP / 128)) * 2048 + 16 * lane);        \
+    const uint32_t off_ = (uint32_t)((((BX) * 4 + wave) * (a.CP / 128) + (KS)) * 2048 + 16 * lane); \
     const int srt_ = (int)min(row_ >> 5, (int64_t)a.RT - 1);                                     \
     _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                              \
       if (q == 0 && PURE) continue;                                                              \
       _Pragma("unroll") for (int t = 0; t < T; ++t) df[q][t] = bload_frag8(dr[q][t], off_);      \
-      e8[q] = e8m0_of(gp(a.fsc)[((int64_t)q * a.RT + srt_) * a.CT + min(g, a.CT - 1)]);          \
+      e8[q] = e8m0_of(gp(a.fsc)[((int64_t)q * a.RT + srt_) * a.CT + min(4 * (KS) + g, a.CT - 1)]); \
     }                                                                                            \
   } while (0)
-  if (bx * 64 < a.m) QSK_YR_FETCH(bx);
+  if (bx * 64 < a.m) QSK_YR_FETCH(bx, 0);
   wait_vm();
   __syncthreads();
-  for (; bx * 64 < a.m; bx += G) {
+  floatx4 acc[NJ][4];
+#pragma unroll
+  for (int i = 0; i < NJ; ++i)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) acc[i][p] = {0.f, 0.f, 0.f, 0.f};
+  floatx4 old[NJ][4];
+  while (bx * 64 < a.m) {
     i32x8 cur[4][T];
     int ce[4];
 #pragma unroll
@@ -1968,29 +1982,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     }
     const int64_t r0 = bx * 64 + wave * 16 + 4 * g;
     const bool full = r0 + 3 < a.m && ((a.ldy | a.psy) & 3) == 0;
-    // old Y values of this row block
-    floatx4 old[NJ][4];
+    if (ks == 0) {
+      // old Y values of this row block
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) {
-      const int jj = (jt0 + i) * 16 + c16;
+      for (int i = 0; i < NJ; ++i) {
+        const int jj = (jt0 + i) * 16 + c16;
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        old[i][p] = {0.f, 0.f, 0.f, 0.f};
-        if (jj < a.k && full) old[i][p] = *(const QSK_GLOBAL floatx4 *)gp(a.y + p * a.psy + (int64_t)jj * a.ldy + r0);
+        for (int p = 0; p < 4; ++p) {
+          old[i][p] = {0.f, 0.f, 0.f, 0.f};
+          if (jj < a.k && full) old[i][p] = *(const QSK_GLOBAL floatx4 *)gp(a.y + p * a.psy + (int64_t)jj * a.ldy + r0);
+        }
       }
     }
-    if ((bx + G) * 64 < a.m) QSK_YR_FETCH(bx + G);
+    const int64_t nbx = ks + 1 < NS ? bx : bx + G;
+    const int nks = ks + 1 < NS ? ks + 1 : 0;
+    if (nbx * 64 < a.m) QSK_YR_FETCH(nbx, nks);
     __builtin_amdgcn_sched_barrier(0);
-    floatx4 acc[NJ][4];
-#pragma unroll
-    for (int i = 0; i < NJ; ++i)
-#pragma unroll
-      for (int p = 0; p < 4; ++p) acc[i][p] = {0.f, 0.f, 0.f, 0.f};
+    const char *om = &s_om[ks][0];
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
 #pragma unroll
       for (int sp = 0; sp < 4; ++sp) {
-        const i32x8 of = lds_frag8(&s_om[(sp * NJ + i) * TB], c16, g);
+        const i32x8 of = lds_frag8(om + (sp * NJ + i) * TB, c16, g);
         const i32x8 nof = neg8(of);
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
@@ -2004,22 +2017,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         }
       }
     }
+    if (ks == NS - 1) {
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) {
-      const int jj = (jt0 + i) * 16 + c16;
-      if (jj >= a.k) continue;
+      for (int i = 0; i < NJ; ++i) {
+        const int jj = (jt0 + i) * 16 + c16;
+        if (jj >= a.k) continue;
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        QSK_GLOBAL float *dst = gpw(a.y + p * a.psy + (int64_t)jj * a.ldy);
-        if (full) {
-          *(QSK_GLOBAL floatx4 *)(dst + r0) = old[i][p] + a.eta * acc[i][p];
-        } else {
+        for (int p = 0; p < 4; ++p) {
+          QSK_GLOBAL float *dst = gpw(a.y + p * a.psy + (int64_t)jj * a.ldy);
+          if (full) {
+            *(QSK_GLOBAL floatx4 *)(dst + r0) = old[i][p] + a.eta * acc[i][p];
+          } else {
 #pragma unroll
-          for (int tt = 0; tt < 4; ++tt)
-            if (r0 + tt < a.m) dst[r0 + tt] += a.eta * acc[i][p][tt];
+            for (int tt = 0; tt < 4; ++tt)
+              if (r0 + tt < a.m) dst[r0 + tt] += a.eta * acc[i][p][tt];
+          }
         }
       }
+#pragma unroll
+      for (int i = 0; i < NJ; ++i)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) acc[i][p] = {0.f, 0.f, 0.f, 0.f};
     }
+    bx = nbx;
+    ks = nks;
   }
 #undef QSK_YR_FETCH
 }
@@ -2070,7 +2091,8 @@ static void launch_y8_t(const Y8Args &y, int pure, int nj, int64_t blocks, hipSt
 }
 template <int T, bool PURE>
 static void launch_y8r(const Y8Args &y, dim3 grid, hipStream_t st) {
-  hipLaunchKernelGGL((y_fp8x_rows_kernel<4, T, PURE>), grid, dim3(256), 0, st, y);
+  if (y.CP == 256) hipLaunchKernelGGL((y_fp8x_rows_kernel<4, T, PURE, 2>), grid, dim3(256), 0, st, y);
+  else hipLaunchKernelGGL((y_fp8x_rows_kernel<4, T, PURE, 1>), grid, dim3(256), 0, st, y);
 }
 template <int T>
 static void launch_y8r_t(const Y8Args &y, int pure, dim3 grid, hipStream_t st) {
@@ -2132,9 +2154,10 @@ static hipError_t launch_fp8x(const SketchArgs &s, const Fp8xStage &f) {
     const int ntiles = (s.k + 15) / 16;
     y.rblocks = (int)((s.m + 63) / 64);
     y.cgroups = (ntiles + nj - 1) / nj;
-    if (CPu == 128 && nj == 4 && !(f.T == 4 && !s.pure)) {
-      // one 128-column step: row-walking blocks with the Omega tile kept in
-      // LDS, two per CU (four column tiles: the registers of seven do not fit)
+    if ((CPu == 128 || CPu == 256) && nj == 4 && !(f.T == 4 && !s.pure)) {
+      // one or two 128-column steps: row-walking blocks with the Omega tiles
+      // kept in LDS and Y read and written once per row block (four column
+      // tiles: the registers of seven do not fit)
       y.S = 1; y.tchunk = CPu;
       if (s.y_splits) *s.y_splits = 1;
       const int64_t G = std::min<int64_t>(y.rblocks, std::max<int64_t>(1, 2 * resident_blocks(2) / y.cgroups));
