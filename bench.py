@@ -204,9 +204,10 @@ def summarize_traffic(fetch_dir, write_dir, cmd_fetch, cmd_write):
 
 STATS_TITLES = {
     "c2": ("20000x15000 FP32 quaternion, BF16 (2-term) sketch, both rangefinders",
-           "Whole one-pass approximations (8 column-block updates of 2048 columns each, then the QB stage "
-           "with pseudo-QR and with pseudo-SVD), after a 256 MiB calibration copy; input generation kernels "
-           "(torch, rocBLAS) are listed too."),
+           "The bench line's own run of this workload (FP32, BF16 two-term and FP8 paths, one warm-up and "
+           "three timed one-pass approximations each: 8 column-block updates of 2048 columns, then the QB "
+           "stage with pseudo-QR and with pseudo-SVD; the FP64 reference, the CPU baseline and the extras "
+           "left out); input generation kernels are listed too."),
     "image": ("31365x27125 pure quaternion BF16 image, Rademacher, k=200, l=401, BF16 operands, both rangefinders",
               "Whole one-pass approximations (14 column-block updates of 2048 columns, then the QB stage with "
               "pseudo-QR and with pseudo-SVD); input generation kernels are listed too."),
