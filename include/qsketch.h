@@ -119,7 +119,7 @@ typedef struct {
   int32_t pure;            /* 1: A has no real part; planes[0] is ignored (may be NULL) */
   int32_t split_terms;     /* BF16: 1..3; FP8: 1 or 2 (2 = add FP32 residual term);
                               FP8_MFMA: 1..4 e4m3 terms */
-  int32_t n_correction;    /* pseudo-QR correction steps, 0..8 (paper: "often 3") */
+  int32_t n_correction;    /* pseudo-QR correction steps, 0..8 (the paper's experiments use 3) */
   int32_t n_power;         /* power iterates per correction step for eps (paper: 2-3) */
   int64_t max_block_cols;  /* largest ncols of one update; 0 means n */
   int32_t y_only;          /* 1: keep Y only (the two-pass variant): W is neither stored nor

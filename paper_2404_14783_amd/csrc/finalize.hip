@@ -1931,7 +1931,7 @@ template <bool L>
 __device__ __forceinline__ void tri_step(int j, int k, double *g, qd *P, int o0, int n0, qd *v, qd *pv,
                                          double *d, double *e, double *hv, double *hbeta, double *halpha,
                                          double *s_beta) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = k - j - 1, o = j + 1;
   // (A) one wave forms the reflector of column j: x = G[o.., j], alpha =
   // -|x| x0 / |x0|, v = x - alpha e_0, beta = 2 / |v|^2
