@@ -249,6 +249,25 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf,
                             double *const X[4], int64_t ldx,
                             qsk_report *report);
 
+/* Two QB stages (Alg. 4) of the current sketches, e.g. with the pseudo-QR
+   (Alg. 1) and the pseudo-SVD (Alg. 3) rangefinder: the same results,
+   reports and errors as qsketch_finalize(ctx, rf_a, Qa, ...) followed by
+   qsketch_finalize(ctx, rf_b, Qb, ...), bit for bit, but the two stages run
+   side by side on the device.  Most of a QB stage is k x k work that keeps
+   a few compute units busy, so the second stage runs on a second stream of
+   the context with a workspace of its own (allocated on the first call and
+   kept: two m x k FP64 quaternion buffers and the k x k and l x k scratch).
+   Each pair (Qa, ldqa, Xa, ldxa) and (Qb, ldqb, Xb, ldxb) is checked as in
+   qsketch_finalize; no plane of one result may be a plane of the other
+   (QSK_E_ARG).  A stage whose factorisation needs the careful path is run
+   again on the context stream, as qsketch_finalize does.  Synchronises the
+   context stream, which continues after both stages; reports may be NULL. */
+qsk_status qsketch_finalize_pair(qsk_ctx *ctx,
+                                 qsk_rangefinder rf_a, double *const Qa[4], int64_t ldqa,
+                                 double *const Xa[4], int64_t ldxa, qsk_report *report_a,
+                                 qsk_rangefinder rf_b, double *const Qb[4], int64_t ldqb,
+                                 double *const Xb[4], int64_t ldxb, qsk_report *report_b);
+
 /* Second pass of the two-pass variant (randomized QSVD: the one-pass
    algorithm with Psi = I, Section 4.1, after eq. reconstructionOfTwoSketch):
        X[:, col0 : col0 + ncols) = Q^* A[:, col0 : col0 + ncols),

@@ -99,6 +99,9 @@ def _load():
     lib.qsketch_project_noalloc.argtypes = [vp, _P4, i64, i64, i64, _P4, i64, _P4, i64]
     lib.qsketch_project_noalloc.restype = i32
     lib.qsketch_finalize.restype = i32
+    lib.qsketch_finalize_pair.argtypes = [vp, i32, _P4, i64, vp, i64, ctypes.POINTER(QskReport),
+                                          i32, _P4, i64, vp, i64, ctypes.POINTER(QskReport)]
+    lib.qsketch_finalize_pair.restype = i32
     lib.qsketch_sketches.argtypes = [vp, _P4, i64, vp, i64]
     lib.qsketch_sketches.restype = i32
     lib.qsketch_reset.argtypes = [vp]
@@ -337,6 +340,35 @@ class Sketcher:
         self._check(self._lib.qsketch_finalize(self._ctx, RANGEFINDERS[rangefinder], qp, ldq, xarg, ldx,
                                                ctypes.byref(rep)))
         return q, x, rep.as_dict()
+
+    def _qb_outputs(self, q, x, solve):
+        if q is None:
+            q = qempty(4, self.m, self.k, torch.float64, self.device)
+        qp, ldq = _plane_ptrs(q, False)
+        xarg, ldx = None, self.k
+        if solve:
+            if x is None:
+                x = qempty(4, self.k, self.n, torch.float64, self.device)
+            xp, ldx = _plane_ptrs(x, False)
+            xarg = ctypes.cast(xp, ctypes.c_void_p)
+        else:
+            x = None
+        return q, x, qp, ldq, xarg, ldx
+
+    def finalize_pair(self, rangefinders=("pseudo_qr", "pseudo_svd"), outputs=None, solve=None):
+        """Two QB stages side by side on the device (qsketch_finalize_pair):
+        the results of finalize(rangefinders[0]) and finalize(rangefinders[1]),
+        as a list of two (Q, X, report); outputs: optional [(q, x), (q, x)]."""
+        if solve is None:
+            solve = not self.y_only
+        outputs = outputs or [(None, None), (None, None)]
+        a = self._qb_outputs(*outputs[0], solve)
+        b = self._qb_outputs(*outputs[1], solve)
+        ra, rb = QskReport(), QskReport()
+        self._check(self._lib.qsketch_finalize_pair(
+            self._ctx, RANGEFINDERS[rangefinders[0]], a[2], a[3], a[4], a[5], ctypes.byref(ra),
+            RANGEFINDERS[rangefinders[1]], b[2], b[3], b[4], b[5], ctypes.byref(rb)))
+        return [(a[0], a[1], ra.as_dict()), (b[0], b[1], rb.as_dict())]
 
     def truncate(self, q, x, r):
         """Truncation stage: (Q U_r (4, m, r), sigma (r,), V_r (4, n, r)) with

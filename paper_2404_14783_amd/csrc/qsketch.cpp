@@ -51,6 +51,26 @@ struct Buf {
   size_t bytes = 0;
 };
 
+// Workspace of one QB stage: the stream it runs on, the two side streams of
+// its kappa estimates with their fork/join events, its device status words
+// and its FP64 scratch.  Lane 0 is a view of the context's own fields; a
+// second lane, allocated on the first paired finalize, lets another QB
+// stage of the same sketch run beside it.
+struct QbLane {
+  hipStream_t stream = nullptr;
+  hipStream_t side = nullptr, side2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_fork2 = nullptr, ev_join2 = nullptr;
+  double *u[2] = {nullptr, nullptr};   // m x k planar, two alternating buffers
+  double *small = nullptr;             // k x k AoS matrices (SmallSlot)
+  double *work = nullptr;              // driver scratch
+  double *partials = nullptr;          // split-contraction partial sums
+  int64_t partial_elems = 0;
+  double *pbuf = nullptr, *p1buf = nullptr, *sbuf = nullptr;   // l x k planar each
+  double *pinv_work = nullptr;         // (l + k) x k quaternions
+  double *kwork = nullptr, *kwork2 = nullptr;
+  SmallStatus *status = nullptr, *kstatus = nullptr;
+};
+
 }  // namespace
 
 struct qsk_ctx {
@@ -122,6 +142,11 @@ struct qsk_ctx {
   // Gram Y^* Y of the current sketch (S_YG), kept between finalize calls
   // until the sketch changes (both rangefinders start from it)
   bool gram_valid = false;
+  // qsketch_finalize_pair: the second QB lane (its own streams and
+  // workspace) and the events that fork it from and join it into `stream`
+  QbLane lane1;
+  bool lane1_ready = false;
+  hipEvent_t ev_pair_fork = nullptr, ev_pair_join = nullptr;
   // qsketch_update_many: a sequence of updates captured once into a HIP
   // graph on its own stream and replayed while the arguments repeat
   hipStream_t gstream = nullptr;
@@ -209,8 +234,28 @@ void free_events(qsk_ctx *c) {
   c->ev_used = 0;
 }
 
+void free_lane(QbLane &L) {
+  if (L.stream) (void)hipStreamSynchronize(L.stream);
+  if (L.side) (void)hipStreamSynchronize(L.side);
+  if (L.side2) (void)hipStreamSynchronize(L.side2);
+  for (hipEvent_t e : {L.ev_fork, L.ev_join, L.ev_fork2, L.ev_join2})
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t t : {L.stream, L.side, L.side2})
+    if (t) (void)hipStreamDestroy(t);
+  void *ptrs[] = {L.u[0], L.u[1], L.small, L.work, L.partials, L.pbuf, L.p1buf, L.sbuf,
+                  L.pinv_work, L.kwork, L.kwork2, L.status, L.kstatus};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  L = QbLane{};
+}
+
 void free_all(qsk_ctx *c) {
   free_events(c);
+  free_lane(c->lane1);
+  c->lane1_ready = false;
+  if (c->ev_pair_fork) (void)hipEventDestroy(c->ev_pair_fork);
+  if (c->ev_pair_join) (void)hipEventDestroy(c->ev_pair_join);
+  c->ev_pair_fork = c->ev_pair_join = nullptr;
   if (c->side) (void)hipStreamSynchronize(c->side);
   if (c->side2) (void)hipStreamSynchronize(c->side2);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
@@ -263,6 +308,22 @@ enum SmallSlot { S_G1 = 0, S_GU, S_R, S_T, S_RPROD, S_RTMP, S_G0, S_TMP, S_C, S_
                  S_TP1, S_TP2, S_TPT, S_Z, S_CR, S_CT, S_GI, S_M, S_TMP2, S_GH, S_GK0, S_YG, S_COUNT };
 
 double *slot(qsk_ctx *c, int s) { return c->small + (size_t)s * c->cfg.k * c->cfg.k * 4; }
+double *slot(const QbLane &L, int k, int s) { return L.small + (size_t)s * k * k * 4; }
+
+// Lane 0: the context's own finalize workspace on the context stream.
+QbLane lane0(qsk_ctx *c) {
+  QbLane L;
+  L.stream = c->stream;
+  L.side = c->side; L.side2 = c->side2;
+  L.ev_fork = c->ev_fork; L.ev_join = c->ev_join; L.ev_fork2 = c->ev_fork2; L.ev_join2 = c->ev_join2;
+  L.u[0] = c->u[0]; L.u[1] = c->u[1];
+  L.small = c->small; L.work = c->work;
+  L.partials = c->partials; L.partial_elems = c->partial_elems;
+  L.pbuf = c->pbuf; L.p1buf = c->p1buf; L.sbuf = c->sbuf; L.pinv_work = c->pinv_work;
+  L.kwork = c->kwork; L.kwork2 = c->kwork2;
+  L.status = c->status; L.kstatus = c->kstatus;
+  return L;
+}
 
 // Sum the split-K copies of Y into copy 0 (stream-ordered).
 // Only the copies an update added into since the last fold are read.
@@ -840,21 +901,74 @@ qsk_status qsketch_sketches(qsk_ctx *ctx, double *const Y[4], int64_t ldy, doubl
 // QSK_RETRY_CAREFUL, after which the caller runs the careful version, which
 // checks each factorisation and takes the fallbacks.
 static const qsk_status QSK_RETRY_CAREFUL = static_cast<qsk_status>(-1);
-static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4], int64_t ldq,
-                                double *const X[4], int64_t ldx, qsk_report *report, bool opt) {
-  if (!ctx) return QSK_E_ARG;
-  if (ctx->poisoned) return QSK_E_STATE;
+
+// What one enqueued QB stage leaves for its collection.
+struct QbRun {
+  qsk_rangefinder rf = QSK_PSEUDO_QR;   // QSK_PSEUDO_SVD_GS folded into QSK_PSEUDO_SVD
+  int passes = 0;
+  int flags = 0;
+  bool kappa0 = false;                  // kappa of H0 launched on the lane's `side`
+};
+
+static qsk_status qb_check(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4], int64_t ldq,
+                           double *const X[4], int64_t ldx) {
   const qsk_config &c = ctx->cfg;
   if (rf != QSK_PSEUDO_QR && rf != QSK_PSEUDO_SVD && rf != QSK_PSEUDO_SVD_GS)
     return fail_arg(ctx, "unknown rangefinder");
-  const int gs = rf == QSK_PSEUDO_SVD_GS;
-  if (gs) rf = QSK_PSEUDO_SVD;
   if (!Q) return fail_arg(ctx, "Q NULL");
   if (X && !ctx->w) return fail_arg(ctx, "the context keeps no W (y_only): call with X = NULL");
   for (int p = 0; p < 4; ++p)
     if (!Q[p] || (X && !X[p])) return fail_arg(ctx, "NULL output plane");
   if (ldq < c.m || (X && ldx < c.k)) return fail_arg(ctx, "leading dimension too small");
-  hipStream_t st = ctx->stream;
+  return QSK_OK;
+}
+
+// Pending columns into the sketches, the split-K copies of Y summed.
+static qsk_status qb_prepare(qsk_ctx *ctx) {
+  const qsk_status fs = flush_pending(ctx);
+  if (fs != QSK_OK) return fs;
+  HIPCHK(ctx, fold_y(ctx));
+  return QSK_OK;
+}
+
+// Y^* Y into dst on the lane's stream (with the lane's partial sums).
+static qsk_status y_gram(qsk_ctx *ctx, const QbLane &L, double *dst) {
+  const qsk_config &c = ctx->cfg;
+  const int ty = ctx->mode == qsk::MODE_F64 ? 0 : 1;
+  const void *yp[4];
+  for (int p = 0; p < 4; ++p) yp[p] = (const char *)ctx->y + (size_t)p * c.m * c.k * ctx->ts;
+  HIPCHK(ctx, qsk::launch_crossprod(L.stream, ty, yp, c.m, ty, yp, c.m, c.m, c.k, c.k, L.partials,
+                                    L.partial_elems, dst));
+  return QSK_OK;
+}
+
+// Psi as the sketch used it, for the core solve: the matrix-core path's
+// staging holds exactly those values (rounded to the operand format); when
+// the update kernels generated Psi in place, it is regenerated into the
+// staging buffer once (the FP64 matrix-core product reads it there).
+static qsk_status stage_psi_for_solve(qsk_ctx *ctx, hipStream_t st) {
+  const qsk_config &c = ctx->cfg;
+  if (!ctx->psi_staged && ctx->use_mfma && ctx->stage.psi && ctx->mode != qsk::MODE_F64) {
+    qsk::SketchArgs sa{};
+    sa.stream = st; sa.mode = ctx->mode; sa.l = c.l; sa.m = c.m; sa.k = c.k;
+    sa.rad = c.embedding == QSK_RADEMACHER; sa.k0 = ctx->k0; sa.k1 = ctx->k1;
+    HIPCHK(ctx, qsk::stage_psi(sa, ctx->stage));
+    ctx->psi_staged = true;
+  }
+  return QSK_OK;
+}
+
+// The QB stage's launches on lane L (arguments checked, sketch prepared).
+// The optimistic run makes no host synchronisation: its results, status
+// and kappa estimates are read by qb_collect.  The careful run reads the
+// status after each factorisation.
+static qsk_status qb_enqueue(qsk_ctx *ctx, const QbLane &L, qsk_rangefinder rf, double *const Q[4],
+                             int64_t ldq, double *const X[4], int64_t ldx, bool opt, QbRun *run) {
+  const qsk_config &c = ctx->cfg;
+  const int gs = rf == QSK_PSEUDO_SVD_GS;
+  if (gs) rf = QSK_PSEUDO_SVD;
+  run->rf = rf;
+  hipStream_t st = L.stream;
   const int k = c.k, l = c.l;
   const int64_t m = c.m, n = c.n;
   const int ty = ctx->mode == qsk::MODE_F64 ? 0 : 1;
@@ -864,12 +978,7 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
   int flags = 0;
   bool kappa0 = false;                 // kappa of H0 launched on `side`
 
-  {
-    const qsk_status fs = flush_pending(ctx);
-    if (fs != QSK_OK) return fs;
-  }
-  HIPCHK(ctx, fold_y(ctx));
-  if (opt) HIPCHK(ctx, qsk::launch_status_reset(st, ctx->status, 0));
+  if (opt) HIPCHK(ctx, qsk::launch_status_reset(st, L.status, 0));
   const void *yp[4];
   for (int p = 0; p < 4; ++p) yp[p] = (const char *)ctx->y + (size_t)p * m * k * ctx->ts;
 
@@ -881,7 +990,7 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
   // whose extra directions are arbitrary.
   const void *zsrc[4] = {yp[0], yp[1], yp[2], yp[3]};
   int tz = ty;
-  double *gz = slot(ctx, S_G1);
+  double *gz = slot(L, k, S_G1);
   const double rows_c = complex_only ? 2.0 * m : 4.0 * m;
   int passes = 0, need = 2;
   const int max_passes = 8;
@@ -890,17 +999,17 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
       // Y^* Y of this sketch, kept from the previous finalize
       HIPCHK(ctx, hipMemcpyAsync(gz, slot(ctx, S_YG), kk * 8, hipMemcpyDeviceToDevice, st));
     } else {
-      HIPCHK(ctx, qsk::launch_crossprod(st, tz, zsrc, m, tz, zsrc, m, m, k, k, ctx->partials,
-                                        ctx->partial_elems, gz));
+      HIPCHK(ctx, qsk::launch_crossprod(st, tz, zsrc, m, tz, zsrc, m, m, k, k, L.partials,
+                                        L.partial_elems, gz));
       if (passes == 0) {
         HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_YG), gz, kk * 8, hipMemcpyDeviceToDevice, st));
         ctx->gram_valid = true;
       }
     }
-    HIPCHK(ctx, qsk::launch_chol_inv(st, gz, k, complex_only, 0.0, 1e-13, slot(ctx, S_R),
-                                     slot(ctx, S_T), ctx->status));
+    HIPCHK(ctx, qsk::launch_chol_inv(st, gz, k, complex_only, 0.0, 1e-13, slot(L, k, S_R),
+                                     slot(L, k, S_T), L.status));
     if (!opt) {
-      HIPCHK(ctx, hipMemcpyAsync(&hs, ctx->status, sizeof(hs), hipMemcpyDeviceToHost, st));
+      HIPCHK(ctx, hipMemcpyAsync(&hs, L.status, sizeof(hs), hipMemcpyDeviceToHost, st));
       HIPCHK(ctx, hipStreamSynchronize(st));
     }
     ++passes;
@@ -910,9 +1019,9 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
         return QSK_E_NUMERIC;
       }
       const double shift = 11.0 * (rows_c * k + (double)k * (k + 1)) * 0x1p-53 * hs.trace;
-      HIPCHK(ctx, qsk::launch_chol_inv(st, gz, k, complex_only, shift, 0.0, slot(ctx, S_R),
-                                       slot(ctx, S_T), ctx->status));
-      HIPCHK(ctx, hipMemcpyAsync(&hs, ctx->status, sizeof(hs), hipMemcpyDeviceToHost, st));
+      HIPCHK(ctx, qsk::launch_chol_inv(st, gz, k, complex_only, shift, 0.0, slot(L, k, S_R),
+                                       slot(L, k, S_T), L.status));
+      HIPCHK(ctx, hipMemcpyAsync(&hs, L.status, sizeof(hs), hipMemcpyDeviceToHost, st));
       HIPCHK(ctx, hipStreamSynchronize(st));
       if (hs.fail) {
         ctx->last_error = "Cholesky of the shifted Gram failed";
@@ -922,112 +1031,105 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
       if (need < passes + 2) need = passes + 2;
     }
     if (passes == 1) {
-      HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_RPROD), slot(ctx, S_R), kk * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(ctx, hipMemcpyAsync(slot(L, k, S_RPROD), slot(L, k, S_R), kk * 8, hipMemcpyDeviceToDevice, st));
     } else {
-      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_R), 0, slot(ctx, S_RPROD), 0, slot(ctx, S_RTMP)));
-      HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_RPROD), slot(ctx, S_RTMP), kk * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(L, k, S_R), 0, slot(L, k, S_RPROD), 0, slot(L, k, S_RTMP)));
+      HIPCHK(ctx, hipMemcpyAsync(slot(L, k, S_RPROD), slot(L, k, S_RTMP), kk * 8, hipMemcpyDeviceToDevice, st));
     }
     if (passes >= need || passes >= max_passes) break;
-    double *ub = ctx->u[(passes - 1) & 1];
+    double *ub = L.u[(passes - 1) & 1];
     double *up[4] = {ub, ub + (size_t)m * k, ub + 2 * (size_t)m * k, ub + 3 * (size_t)m * k};
-    HIPCHK(ctx, qsk::launch_apply(st, tz, zsrc, m, m, k, slot(ctx, S_T), k, up, m, 1));
+    HIPCHK(ctx, qsk::launch_apply(st, tz, zsrc, m, m, k, slot(L, k, S_T), k, up, m, 1));
     for (int p = 0; p < 4; ++p) zsrc[p] = up[p];
     tz = 0;
-    gz = slot(ctx, S_GU);
+    gz = slot(L, k, S_GU);
   }
   // Now H0 (pseudo-QR) or Q_Y (pseudo-SVD) = Z T with G_Z = gz.  (The
   // optimistic run keeps the sticky failure flag of the passes above.)
   if (opt) {
-    HIPCHK(ctx, qsk::launch_status_reset(st, ctx->status, 1));
+    HIPCHK(ctx, qsk::launch_status_reset(st, L.status, 1));
   } else {
-    HIPCHK(ctx, hipMemsetAsync(ctx->status, 0, sizeof(SmallStatus), st));
+    HIPCHK(ctx, hipMemsetAsync(L.status, 0, sizeof(SmallStatus), st));
   }
-  HIPCHK(ctx, hipMemsetAsync(ctx->kstatus, 0, sizeof(SmallStatus), st));
+  HIPCHK(ctx, hipMemsetAsync(L.kstatus, 0, sizeof(SmallStatus), st));
   if (rf == QSK_PSEUDO_QR) {
     // G0 = H0^* H0 = T^* G_Z T; kappa of the raw factor
-    HIPCHK(ctx, qsk::launch_small_gemm(st, k, gz, 0, slot(ctx, S_T), 0, slot(ctx, S_TMP)));
-    HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_T), 1, slot(ctx, S_TMP), 0, slot(ctx, S_G0)));
-    HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_GK0), slot(ctx, S_G0), kk * 8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(ctx, hipEventRecord(ctx->ev_fork, st));
-    HIPCHK(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
-    HIPCHK(ctx, qsk::launch_kappa(ctx->side, k, slot(ctx, S_GK0), ctx->kwork, 1, ctx->kstatus));
-    HIPCHK(ctx, hipEventRecord(ctx->ev_join, ctx->side));
+    HIPCHK(ctx, qsk::launch_small_gemm(st, k, gz, 0, slot(L, k, S_T), 0, slot(L, k, S_TMP)));
+    HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(L, k, S_T), 1, slot(L, k, S_TMP), 0, slot(L, k, S_G0)));
+    HIPCHK(ctx, hipMemcpyAsync(slot(L, k, S_GK0), slot(L, k, S_G0), kk * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(ctx, hipEventRecord(L.ev_fork, st));
+    HIPCHK(ctx, hipStreamWaitEvent(L.side, L.ev_fork, 0));
+    HIPCHK(ctx, qsk::launch_kappa(L.side, k, slot(L, k, S_GK0), L.kwork, 1, L.kstatus));
+    HIPCHK(ctx, hipEventRecord(L.ev_join, L.side));
     kappa0 = true;
     // correction steps (eq. CondNumReductionIter) in the k x k space: with
     // H_j = H0 C_j and G_j = H_j^* H_j, H_{j+1} = (1 - eps) H_j + eps (H_j^dagger)^*
     // = H_j M_j with M_j = (1 - eps) I + eps G_j^{-1}  ((H^dagger)^* = H G^{-1});
     // C_{j+1} = C_j M_j, G_{j+1} = M_j^* G_j M_j.
-    HIPCHK(ctx, qsk::launch_identity(st, k, slot(ctx, S_C)));
+    HIPCHK(ctx, qsk::launch_identity(st, k, slot(L, k, S_C)));
     for (int j = 0; j < c.n_correction; ++j) {
-      HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_G0), k, 0, 0.0, 1e-13, slot(ctx, S_CR),
-                                       slot(ctx, S_CT), ctx->status));
+      HIPCHK(ctx, qsk::launch_chol_inv(st, slot(L, k, S_G0), k, 0, 0.0, 1e-13, slot(L, k, S_CR),
+                                       slot(L, k, S_CT), L.status));
       int fail = 0;
       if (!opt) {
-        HIPCHK(ctx, hipMemcpyAsync(&fail, &ctx->status->fail, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipMemcpyAsync(&fail, &L.status->fail, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(ctx, hipStreamSynchronize(st));
       }
       if (fail) {
         flags |= QSK_FLAG_RANK_DEFICIENT;      // G_j singular: no further correction
         break;
       }
-      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_CT), 0, slot(ctx, S_CT), 1, slot(ctx, S_GI)));
-      HIPCHK(ctx, qsk::launch_power_m(st, k, slot(ctx, S_GI), j, c.n_power, ctx->k0, ctx->k1,
-                                      slot(ctx, S_M), ctx->status));
-      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_C), 0, slot(ctx, S_M), 0, slot(ctx, S_TMP)));
-      HIPCHK(ctx, hipMemcpyAsync(slot(ctx, S_C), slot(ctx, S_TMP), kk * 8, hipMemcpyDeviceToDevice, st));
-      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_G0), 0, slot(ctx, S_M), 0, slot(ctx, S_TMP)));
-      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_M), 1, slot(ctx, S_TMP), 0, slot(ctx, S_G0)));
+      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(L, k, S_CT), 0, slot(L, k, S_CT), 1, slot(L, k, S_GI)));
+      HIPCHK(ctx, qsk::launch_power_m(st, k, slot(L, k, S_GI), j, c.n_power, ctx->k0, ctx->k1,
+                                      slot(L, k, S_M), L.status));
+      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(L, k, S_C), 0, slot(L, k, S_M), 0, slot(L, k, S_TMP)));
+      HIPCHK(ctx, hipMemcpyAsync(slot(L, k, S_C), slot(L, k, S_TMP), kk * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(L, k, S_G0), 0, slot(L, k, S_M), 0, slot(L, k, S_TMP)));
+      HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(L, k, S_M), 1, slot(L, k, S_TMP), 0, slot(L, k, S_G0)));
     }
   } else {
     // G_L = R_Y R_Y^*
-    HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_RPROD), 0, slot(ctx, S_RPROD), 1, slot(ctx, S_TMP)));
-    HIPCHK(ctx, qsk::launch_psvd_select(st, k, slot(ctx, S_TMP), ctx->k0, ctx->k1, slot(ctx, S_C),
-                                        ctx->work, ctx->status, gs));
+    HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(L, k, S_RPROD), 0, slot(L, k, S_RPROD), 1, slot(L, k, S_TMP)));
+    HIPCHK(ctx, qsk::launch_psvd_select(st, k, slot(L, k, S_TMP), ctx->k0, ctx->k1, slot(L, k, S_C),
+                                        L.work, L.status, gs));
   }
-  HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_T), 0, slot(ctx, S_C), 0, slot(ctx, S_F)));
+  HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(L, k, S_T), 0, slot(L, k, S_C), 0, slot(L, k, S_F)));
   // kappa(Q) from G_Q = F^* G_Z F
-  HIPCHK(ctx, qsk::launch_small_gemm(st, k, gz, 0, slot(ctx, S_F), 0, slot(ctx, S_TMP2)));
-  HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_F), 1, slot(ctx, S_TMP2), 0, slot(ctx, S_GH)));
-  HIPCHK(ctx, hipEventRecord(ctx->ev_fork2, st));
-  HIPCHK(ctx, hipStreamWaitEvent(ctx->side2, ctx->ev_fork2, 0));
-  HIPCHK(ctx, qsk::launch_kappa(ctx->side2, k, slot(ctx, S_GH), ctx->kwork2, 0, ctx->kstatus));
-  HIPCHK(ctx, hipEventRecord(ctx->ev_join2, ctx->side2));
-  HIPCHK(ctx, qsk::launch_apply(st, tz, zsrc, m, m, k, slot(ctx, S_F), k, Q, ldq));
+  HIPCHK(ctx, qsk::launch_small_gemm(st, k, gz, 0, slot(L, k, S_F), 0, slot(L, k, S_TMP2)));
+  HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(L, k, S_F), 1, slot(L, k, S_TMP2), 0, slot(L, k, S_GH)));
+  HIPCHK(ctx, hipEventRecord(L.ev_fork2, st));
+  HIPCHK(ctx, hipStreamWaitEvent(L.side2, L.ev_fork2, 0));
+  HIPCHK(ctx, qsk::launch_kappa(L.side2, k, slot(L, k, S_GH), L.kwork2, 0, L.kstatus));
+  HIPCHK(ctx, hipEventRecord(L.ev_join2, L.side2));
+  HIPCHK(ctx, qsk::launch_apply(st, tz, zsrc, m, m, k, slot(L, k, S_F), k, Q, ldq));
 
   // ---- core solve X = (Psi Q)^dagger W (Alg. 2 through the normal form of
   // a CholeskyQR2 factorisation of P = Psi Q); skipped when X is NULL
   if (X) {
   double *pp[4], *p1[4], *sp[4];
   for (int p = 0; p < 4; ++p) {
-    pp[p] = ctx->pbuf + (size_t)p * l * k;
-    p1[p] = ctx->p1buf + (size_t)p * l * k;
-    sp[p] = ctx->sbuf + (size_t)p * l * k;
+    pp[p] = L.pbuf + (size_t)p * l * k;
+    p1[p] = L.p1buf + (size_t)p * l * k;
+    sp[p] = L.sbuf + (size_t)p * l * k;
   }
-  // Psi as the sketch used it: the matrix-core path's staging holds exactly
-  // those values (rounded to the operand format); when the update kernels
-  // generated Psi in place, it is regenerated into the staging buffer once
-  // for this product (the FP64 matrix-core product reads it there)
-  if (!ctx->psi_staged && ctx->use_mfma && ctx->stage.psi && ctx->mode != qsk::MODE_F64) {
-    qsk::SketchArgs sa{};
-    sa.stream = st; sa.mode = ctx->mode; sa.l = l; sa.m = m; sa.k = k;
-    sa.rad = c.embedding == QSK_RADEMACHER; sa.k0 = ctx->k0; sa.k1 = ctx->k1;
-    HIPCHK(ctx, qsk::stage_psi(sa, ctx->stage));
-    ctx->psi_staged = true;
+  {
+    const qsk_status ss = stage_psi_for_solve(ctx, st);
+    if (ss != QSK_OK) return ss;
   }
   const int psi_st_type = !ctx->psi_staged ? 0 : (ctx->mode == qsk::MODE_F32 ? 2 : 1);
   HIPCHK(ctx, qsk::launch_psi_apply(st, ctx->emode, c.embedding == QSK_RADEMACHER, ctx->k0, ctx->k1, l,
-                                    m, Q, ldq, k, ctx->partials, ctx->partial_elems, pp, l,
+                                    m, Q, ldq, k, L.partials, L.partial_elems, pp, l,
                                     ctx->stage.psi, psi_st_type, ctx->stage.MP,
                                     (int64_t)ctx->stage.LP * ctx->stage.MP));
   SmallStatus ps{};
-  SmallStatus *pst = (SmallStatus *)ctx->work;   // not used concurrently with drivers
+  SmallStatus *pst = (SmallStatus *)L.work;   // not used concurrently with drivers
   (void)pst;
   HIPCHK(ctx, qsk::launch_crossprod(st, 0, (const void *const *)pp, l, 0, (const void *const *)pp, l,
-                                    l, k, k, ctx->partials, ctx->partial_elems, slot(ctx, S_GP)));
-  HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GP), k, 0, 0.0, 1e-13, slot(ctx, S_RP),
-                                   slot(ctx, S_TP1), ctx->status));
+                                    l, k, k, L.partials, L.partial_elems, slot(L, k, S_GP)));
+  HIPCHK(ctx, qsk::launch_chol_inv(st, slot(L, k, S_GP), k, 0, 0.0, 1e-13, slot(L, k, S_RP),
+                                   slot(L, k, S_TP1), L.status));
   if (!opt) {
-    HIPCHK(ctx, hipMemcpyAsync(&ps, ctx->status, sizeof(ps), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipMemcpyAsync(&ps, L.status, sizeof(ps), hipMemcpyDeviceToHost, st));
     HIPCHK(ctx, hipStreamSynchronize(st));
   }
   bool have_sstar = false;
@@ -1036,7 +1138,7 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
     // SVD of Psi Q (the reading of Alg. 2's backslash for a rank-deficient
     // system).
     flags |= QSK_FLAG_RANK_DEFICIENT;
-    HIPCHK(ctx, qsk::launch_pinv_sstar(st, l, k, pp, l, 1e-13, ctx->pinv_work, sp, l));
+    HIPCHK(ctx, qsk::launch_pinv_sstar(st, l, k, pp, l, 1e-13, L.pinv_work, sp, l));
     have_sstar = true;
   } else {
     // R^{-1} = TP1 alone when kappa_F(R_1)^2 = trace(G_P) ||TP1||_F^2 (an
@@ -1044,79 +1146,198 @@ static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const 
     // solve below; else a second CholeskyQR pass, R^{-1} = TP1 TP2.  The
     // optimistic run decides on the device: the second pass's launches are
     // given the gate status and return at once when the gate passes.
-    HIPCHK(ctx, qsk::launch_core_gate(st, k, slot(ctx, S_TP1), slot(ctx, S_TPT), ctx->status));
+    HIPCHK(ctx, qsk::launch_core_gate(st, k, slot(L, k, S_TP1), slot(L, k, S_TPT), L.status));
     bool second = true;
     const SmallStatus *gate = nullptr;
     if (opt) {
-      gate = ctx->status;
+      gate = L.status;
     } else {
-      HIPCHK(ctx, hipMemcpyAsync(&ps, ctx->status, sizeof(ps), hipMemcpyDeviceToHost, st));
+      HIPCHK(ctx, hipMemcpyAsync(&ps, L.status, sizeof(ps), hipMemcpyDeviceToHost, st));
       HIPCHK(ctx, hipStreamSynchronize(st));
       second = !(ps.gate > 0.0 && ps.gate <= qsk::ONE_PASS_KAPPA2);
     }
     if (second) {
-      HIPCHK(ctx, qsk::launch_apply(st, 0, (const void *const *)pp, l, l, k, slot(ctx, S_TP1), k, p1, l, 1,
+      HIPCHK(ctx, qsk::launch_apply(st, 0, (const void *const *)pp, l, l, k, slot(L, k, S_TP1), k, p1, l, 1,
                                     gate));
       HIPCHK(ctx, qsk::launch_crossprod(st, 0, (const void *const *)p1, l, 0, (const void *const *)p1,
-                                        l, l, k, k, ctx->partials, ctx->partial_elems, slot(ctx, S_GP), gate));
-      HIPCHK(ctx, qsk::launch_chol_inv(st, slot(ctx, S_GP), k, 0, 0.0, 1e-13, slot(ctx, S_RP),
-                                       slot(ctx, S_TP2), ctx->status, gate));
+                                        l, l, k, k, L.partials, L.partial_elems, slot(L, k, S_GP), gate));
+      HIPCHK(ctx, qsk::launch_chol_inv(st, slot(L, k, S_GP), k, 0, 0.0, 1e-13, slot(L, k, S_RP),
+                                       slot(L, k, S_TP2), L.status, gate));
       if (!opt) {
-        HIPCHK(ctx, hipMemcpyAsync(&ps, ctx->status, sizeof(ps), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipMemcpyAsync(&ps, L.status, sizeof(ps), hipMemcpyDeviceToHost, st));
         HIPCHK(ctx, hipStreamSynchronize(st));
       }
       if (ps.fail) {
         flags |= QSK_FLAG_RANK_DEFICIENT;
-        HIPCHK(ctx, qsk::launch_pinv_sstar(st, l, k, pp, l, 1e-13, ctx->pinv_work, sp, l));
+        HIPCHK(ctx, qsk::launch_pinv_sstar(st, l, k, pp, l, 1e-13, L.pinv_work, sp, l));
         have_sstar = true;
       } else {
-        HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_TP1), 0, slot(ctx, S_TP2), 0, slot(ctx, S_TPT),
+        HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(L, k, S_TP1), 0, slot(L, k, S_TP2), 0, slot(L, k, S_TPT),
                                            gate));
       }
     }
   }
   // Z = R^{-1} R^{-*} with R^{-1} = TPT; S^* = P Z; X = S W = (S^*)^* W
   if (!have_sstar) {
-    HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(ctx, S_TPT), 0, slot(ctx, S_TPT), 1, slot(ctx, S_Z)));
-    HIPCHK(ctx, qsk::launch_apply(st, 0, (const void *const *)pp, l, l, k, slot(ctx, S_Z), k, sp, l));
+    HIPCHK(ctx, qsk::launch_small_gemm(st, k, slot(L, k, S_TPT), 0, slot(L, k, S_TPT), 1, slot(L, k, S_Z)));
+    HIPCHK(ctx, qsk::launch_apply(st, 0, (const void *const *)pp, l, l, k, slot(L, k, S_Z), k, sp, l));
   }
   const void *wp[4];
   for (int p = 0; p < 4; ++p) wp[p] = (const char *)ctx->w + (size_t)p * l * n * ctx->ts;
   HIPCHK(ctx, qsk::launch_crossprod_planar(st, sp, l, ty, wp, l, l, k, (int)n, X, ldx));
   }
 
-  // join the side streams (kappa estimates) before reading their results
-  // (the two kernels write different fields of kstatus)
-  if (kappa0) HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_join, 0));
-  HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_join2, 0));
+  // join the side streams (kappa estimates) into the lane's stream before
+  // their results are read (the two kernels write different fields of kstatus)
+  if (kappa0) HIPCHK(ctx, hipStreamWaitEvent(st, L.ev_join, 0));
+  HIPCHK(ctx, hipStreamWaitEvent(st, L.ev_join2, 0));
+  run->passes = passes;
+  run->flags = flags;
+  run->kappa0 = kappa0;
+  return QSK_OK;
+}
+
+// Status and kappa estimates of an enqueued QB stage, read once its lane
+// has drained; the optimistic run returns QSK_RETRY_CAREFUL when any
+// factorisation failed.
+static qsk_status qb_collect(qsk_ctx *ctx, const QbLane &L, const QbRun &run, qsk_report *report,
+                             bool opt) {
+  hipStream_t st = L.stream;
   SmallStatus ks{}, hs2{};
-  HIPCHK(ctx, hipMemcpyAsync(&ks, ctx->kstatus, sizeof(ks), hipMemcpyDeviceToHost, st));
-  HIPCHK(ctx, hipMemcpyAsync(&hs2, ctx->status, sizeof(hs2), hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipMemcpyAsync(&ks, L.kstatus, sizeof(ks), hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipMemcpyAsync(&hs2, L.status, sizeof(hs2), hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipStreamSynchronize(st));
   if (opt && hs2.fail_any) return QSK_RETRY_CAREFUL;
-  flags |= hs2.flags;
   if (report) {
     qsk_report r{};
     r.kappa = ks.kappa;
-    r.kappa_initial = rf == QSK_PSEUDO_QR ? ks.kappa_initial : ks.kappa;
+    r.kappa_initial = run.rf == QSK_PSEUDO_QR ? ks.kappa_initial : ks.kappa;
     r.n_eps = hs2.n_eps;
     for (int i = 0; i < 8; ++i) r.eps[i] = hs2.eps[i];
     r.t_bad = hs2.t_bad;
-    r.flags = flags;
-    r.passes = passes;
+    r.flags = run.flags | hs2.flags;
+    r.passes = run.passes;
     r.columns_seen = ctx->columns_seen;
-    r.orth_defect = rf == QSK_PSEUDO_SVD ? ks.orth_defect : 0.0;
+    r.orth_defect = run.rf == QSK_PSEUDO_SVD ? ks.orth_defect : 0.0;
     *report = r;
   }
-  HIPCHK(ctx, hipStreamSynchronize(st));
   return QSK_OK;
+}
+
+static qsk_status finalize_impl(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4], int64_t ldq,
+                                double *const X[4], int64_t ldx, qsk_report *report, bool opt) {
+  qsk_status r = qb_check(ctx, rf, Q, ldq, X, ldx);
+  if (r == QSK_OK) r = qb_prepare(ctx);
+  if (r != QSK_OK) return r;
+  const QbLane L = lane0(ctx);
+  QbRun run;
+  r = qb_enqueue(ctx, L, rf, Q, ldq, X, ldx, opt, &run);
+  if (r != QSK_OK) return r;
+  return qb_collect(ctx, L, run, report, opt);
+}
+
+// The second QB lane, with the sizes of the context's own workspace.
+static qsk_status alloc_lane1(qsk_ctx *ctx) {
+  if (ctx->lane1_ready) return QSK_OK;
+  const int64_t m = ctx->cfg.m, k = ctx->cfg.k, l = ctx->cfg.l;
+  const size_t kk = (size_t)k * k * 4;
+  QbLane &L = ctx->lane1;
+  bool ok = true;
+  ok = ok && alloc((void **)&L.u[0], 4 * (size_t)m * k * 8);
+  ok = ok && alloc((void **)&L.u[1], 4 * (size_t)m * k * 8);
+  ok = ok && alloc((void **)&L.small, S_COUNT * kk * 8);
+  ok = ok && alloc((void **)&L.work, (12 * kk + 64 * (size_t)k) * 8);
+  L.partial_elems = ctx->partial_elems;
+  ok = ok && alloc((void **)&L.partials, (size_t)L.partial_elems * 8);
+  ok = ok && alloc((void **)&L.pbuf, 4 * (size_t)l * k * 8);
+  ok = ok && alloc((void **)&L.p1buf, 4 * (size_t)l * k * 8);
+  ok = ok && alloc((void **)&L.sbuf, 4 * (size_t)l * k * 8);
+  ok = ok && alloc((void **)&L.pinv_work, 4 * (size_t)(l + k) * k * 8);
+  ok = ok && alloc((void **)&L.status, sizeof(SmallStatus));
+  ok = ok && alloc((void **)&L.kstatus, sizeof(SmallStatus));
+  ok = ok && alloc((void **)&L.kwork, kk * 8);
+  ok = ok && alloc((void **)&L.kwork2, kk * 8);
+  ok = ok && hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&L.side, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&L.side2, hipStreamNonBlocking) == hipSuccess;
+  for (hipEvent_t *e : {&L.ev_fork, &L.ev_join, &L.ev_fork2, &L.ev_join2, &ctx->ev_pair_fork,
+                        &ctx->ev_pair_join})
+    ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    free_lane(L);
+    if (ctx->ev_pair_fork) (void)hipEventDestroy(ctx->ev_pair_fork);
+    if (ctx->ev_pair_join) (void)hipEventDestroy(ctx->ev_pair_join);
+    ctx->ev_pair_fork = ctx->ev_pair_join = nullptr;
+    ctx->last_error = "out of device memory (or streams) for the second QB lane";
+    return QSK_E_NOMEM;
+  }
+  ctx->lane1_ready = true;
+  return QSK_OK;
+}
+
+static bool planes_overlap(double *const A[4], double *const B[4]) {
+  if (!A || !B) return false;
+  for (int p = 0; p < 4; ++p)
+    for (int q = 0; q < 4; ++q)
+      if (A[p] == B[q]) return true;
+  return false;
 }
 
 qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf, double *const Q[4], int64_t ldq,
                             double *const X[4], int64_t ldx, qsk_report *report) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
   const qsk_status r = finalize_impl(ctx, rf, Q, ldq, X, ldx, report, true);
   if (r != QSK_RETRY_CAREFUL) return r;
   return finalize_impl(ctx, rf, Q, ldq, X, ldx, report, false);
+}
+
+qsk_status qsketch_finalize_pair(qsk_ctx *ctx, qsk_rangefinder rf_a, double *const Qa[4], int64_t ldqa,
+                                 double *const Xa[4], int64_t ldxa, qsk_report *report_a,
+                                 qsk_rangefinder rf_b, double *const Qb[4], int64_t ldqb,
+                                 double *const Xb[4], int64_t ldxb, qsk_report *report_b) {
+  if (!ctx) return QSK_E_ARG;
+  if (ctx->poisoned) return QSK_E_STATE;
+  qsk_status r = qb_check(ctx, rf_a, Qa, ldqa, Xa, ldxa);
+  if (r == QSK_OK) r = qb_check(ctx, rf_b, Qb, ldqb, Xb, ldxb);
+  if (r != QSK_OK) return r;
+  if (planes_overlap(Qa, Qb) || planes_overlap(Xa, Xb) || planes_overlap(Qa, Xb) ||
+      planes_overlap(Xa, Qb))
+    return fail_arg(ctx, "the two results share an output plane");
+  r = alloc_lane1(ctx);
+  if (r == QSK_OK) r = qb_prepare(ctx);
+  if (r != QSK_OK) return r;
+  const QbLane La = lane0(ctx);
+  const QbLane &Lb = ctx->lane1;
+  // what both stages read and would otherwise write first: the Gram of Y
+  // and, for a core solve, the staged Psi (on the context stream, before
+  // the fork)
+  if (!ctx->gram_valid) {
+    r = y_gram(ctx, La, slot(ctx, S_YG));
+    if (r != QSK_OK) return r;
+    ctx->gram_valid = true;
+  }
+  if (Xa || Xb) {
+    r = stage_psi_for_solve(ctx, La.stream);
+    if (r != QSK_OK) return r;
+  }
+  HIPCHK(ctx, hipEventRecord(ctx->ev_pair_fork, La.stream));
+  HIPCHK(ctx, hipStreamWaitEvent(Lb.stream, ctx->ev_pair_fork, 0));
+  QbRun run_a, run_b;
+  r = qb_enqueue(ctx, La, rf_a, Qa, ldqa, Xa, ldxa, true, &run_a);
+  if (r == QSK_OK) r = qb_enqueue(ctx, Lb, rf_b, Qb, ldqb, Xb, ldxb, true, &run_b);
+  // the context stream continues after both stages
+  HIPCHK(ctx, hipEventRecord(ctx->ev_pair_join, Lb.stream));
+  HIPCHK(ctx, hipStreamWaitEvent(La.stream, ctx->ev_pair_join, 0));
+  if (r != QSK_OK) return r;
+  qsk_status ra = qb_collect(ctx, La, run_a, report_a, true);
+  qsk_status rb = qb_collect(ctx, Lb, run_b, report_b, true);
+  // a stage whose optimistic run failed a factorisation is run again, the
+  // careful way, on the context stream
+  if (ra == QSK_RETRY_CAREFUL) ra = finalize_impl(ctx, rf_a, Qa, ldqa, Xa, ldxa, report_a, false);
+  if (rb == QSK_RETRY_CAREFUL) rb = finalize_impl(ctx, rf_b, Qb, ldqb, Xb, ldxb, report_b, false);
+  return ra != QSK_OK ? ra : rb;
 }
 
 qsk_status qsketch_project(qsk_ctx *ctx, double *const Q[4], int64_t ldq, int64_t col0, int64_t ncols,
