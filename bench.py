@@ -7,7 +7,9 @@ l = 201, both rangefinders.  Inputs are synthetic and resident in HBM before
 timing starts.
 
 One step = one whole one-pass approximation: reset, all column-block updates
-of the sketches, then the QB stage with pseudo-QR and with pseudo-SVD.  Paths:
+of the sketches, then the QB stages with pseudo-QR and with pseudo-SVD, side
+by side on two streams (each path also reports the QB stage alone, paired and
+one rangefinder after the other, under `qb_stage`).  Paths:
   fp64   FP64 sketch on the GPU (the FP64 plain method; error reference, not timed)
   fp32   FP32 sketch on the matrix cores (the same-GPU FP32 plain path)
   bf16   BF16 sketch with the data split in `--terms` bf16 terms (timed: `value`)
@@ -69,7 +71,8 @@ def sketch_flops(m, n, k, l, pure=False):
 
 
 def run_pass(sk, a, block, kinds=("pseudo_qr", "pseudo_svd")):
-    """One whole one-pass approximation; returns (update_ms, total_ms, results)."""
+    """One whole one-pass approximation; returns (update_ms, total_ms, results).
+    Two rangefinders run their QB stages side by side (qsketch_finalize_pair)."""
     st = torch.cuda.current_stream()
     sk.reset()
     e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
@@ -78,12 +81,35 @@ def run_pass(sk, a, block, kinds=("pseudo_qr", "pseudo_svd")):
     for c0 in range(0, n, block):
         sk.update(c0, a[:, :, c0:c0 + block])
     e1.record(st)
-    res = {}
-    for kind in kinds:
-        res[kind] = sk.finalize(kind)
+    if len(kinds) == 2:
+        res = dict(zip(kinds, sk.finalize_pair(kinds)))
+    else:
+        res = {kind: sk.finalize(kind) for kind in kinds}
     e2.record(st)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1), e0.elapsed_time(e2), res
+
+
+def qb_stage_times(sk, reps=3, kinds=("pseudo_qr", "pseudo_svd")):
+    """Median time of the QB stage alone on the current sketches: the two
+    rangefinders side by side (qsketch_finalize_pair) and one after the other
+    (two qsketch_finalize calls)."""
+    st = torch.cuda.current_stream()
+    out = {}
+    for name, fn in (("pair", lambda: sk.finalize_pair(kinds)),
+                     ("sequential", lambda: [sk.finalize(kd) for kd in kinds])):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(st)
+            fn()
+            e1.record(st)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        out[name + "_ms"] = float(np.median(ts))
+    return out
 
 
 def cpu_threads():
@@ -206,15 +232,15 @@ STATS_TITLES = {
     "c2": ("20000x15000 FP32 quaternion, BF16 (2-term) sketch, both rangefinders",
            "The bench line's own run of this workload (FP32, BF16 two-term and FP8 paths, one warm-up and "
            "three timed one-pass approximations each: 8 column-block updates of 2048 columns, then the QB "
-           "stage with pseudo-QR and with pseudo-SVD; the FP64 reference, the CPU baseline and the extras "
+           "stages with pseudo-QR and with pseudo-SVD side by side; the FP64 reference, the CPU baseline and the extras "
            "left out); input generation kernels are listed too."),
     "image": ("31365x27125 pure quaternion BF16 image, Rademacher, k=200, l=401, BF16 operands, both rangefinders",
-              "Whole one-pass approximations (14 column-block updates of 2048 columns, then the QB stage with "
-              "pseudo-QR and with pseudo-SVD); input generation kernels are listed too."),
+              "Whole one-pass approximations (14 column-block updates of 2048 columns, then the QB stages with "
+              "pseudo-QR and with pseudo-SVD side by side); input generation kernels are listed too."),
     "flow": ("2097152x300 pure quaternion FP32 flow snapshots, 30 updates of 10 columns gathered into "
              "blocks of up to 256 (250 and 50), 3 e4m3 terms on the fp8 matrix cores, k=60, l=121, both rangefinders",
              "Whole one-pass approximations (30 linear updates of 10 columns, gathered into two products, "
-             "then the QB stage with pseudo-QR and with pseudo-SVD); input generation kernels are listed too."),
+             "then the QB stages with pseudo-QR and with pseudo-SVD side by side); input generation kernels are listed too."),
     "batch64": ("64 FP32 quaternion problems, BF16 two-term operands, autotuned tiles",
                 "Batched runs (autotuning, then runs with pseudo-QR and with pseudo-SVD); input generation "
                 "kernels are listed too."),
@@ -474,6 +500,7 @@ def bench_stream_leg(args, label, a, m, n, k, l, block, emb, input_dtype, pure, 
         for kind, (q, x, rep) in r.items():
             errors[(name, kind)] = sk.rel_error(a, q, x)
             rec[kind + "_kappa"] = rep["kappa"]
+        rec["qb_stage"] = qb_stage_times(sk)
         eff = (coalesce // block) * block if coalesce else block      # columns per sketch product
         nupd = (n + eff - 1) // eff
         ybytes = None
@@ -816,6 +843,7 @@ def main():
         for kind, (q, x, rep) in res.items():
             errors[(name, kind)] = sk.rel_error(a, q, x)
             out_paths.setdefault(name, {})[kind + "_kappa"] = rep["kappa"]
+        out_paths[name]["qb_stage"] = qb_stage_times(sk)
         out_paths.setdefault(name, {}).update({
             "update_ms": float(np.median(ups)), "total_ms": float(np.median(tots)),
             "sketch_tflops": flops / (np.median(ups) * 1e-3) / 1e12, "terms": terms})

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -10,6 +11,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/qsketch.h"
@@ -77,7 +79,8 @@ struct qsk_ctx {
   qsk_config cfg{};
   hipStream_t stream = nullptr;
   int device = 0;
-  bool poisoned = false;
+  std::atomic<bool> poisoned{false};
+  std::mutex err_mu;                   // last_error (a paired finalize launches from two threads)
   std::string last_error;
   int mode = 0;            // qsk::MODE_*
   int emode = 0;           // qsk::MODE_* of the test-matrix values
@@ -173,12 +176,16 @@ const char *status_str(qsk_status s) {
 }
 
 qsk_status fail_arg(qsk_ctx *c, const char *msg) {
-  if (c) c->last_error = msg;
+  if (c) {
+    std::lock_guard<std::mutex> lock(c->err_mu);
+    c->last_error = msg;
+  }
   return QSK_E_ARG;
 }
 
 qsk_status hip_fail(qsk_ctx *c, hipError_t e, const char *where) {
   c->poisoned = true;
+  std::lock_guard<std::mutex> lock(c->err_mu);
   c->last_error = std::string(where) + ": " + hipGetErrorString(e);
   return QSK_E_HIP;
 }
@@ -1257,9 +1264,9 @@ static qsk_status alloc_lane1(qsk_ctx *ctx) {
   ok = ok && alloc((void **)&L.kstatus, sizeof(SmallStatus));
   ok = ok && alloc((void **)&L.kwork, kk * 8);
   ok = ok && alloc((void **)&L.kwork2, kk * 8);
+  // one stream of its own: its kappa estimates run on the first lane's side
+  // streams (see qsketch_finalize_pair)
   ok = ok && hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) == hipSuccess;
-  ok = ok && hipStreamCreateWithFlags(&L.side, hipStreamNonBlocking) == hipSuccess;
-  ok = ok && hipStreamCreateWithFlags(&L.side2, hipStreamNonBlocking) == hipSuccess;
   for (hipEvent_t *e : {&L.ev_fork, &L.ev_join, &L.ev_fork2, &L.ev_join2, &ctx->ev_pair_fork,
                         &ctx->ev_pair_join})
     ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
@@ -1309,7 +1316,15 @@ qsk_status qsketch_finalize_pair(qsk_ctx *ctx, qsk_rangefinder rf_a, double *con
   if (r == QSK_OK) r = qb_prepare(ctx);
   if (r != QSK_OK) return r;
   const QbLane La = lane0(ctx);
-  const QbLane &Lb = ctx->lane1;
+  // The second stage's kappa estimates go to the first stage's side streams,
+  // crosswise: pseudo-QR launches its kappa of H0 early on `side` and its
+  // kappa of Q later on `side2`, pseudo-SVD only a late kappa of Q on `side2`,
+  // so the crossing keeps the two late estimates apart.  Streams beyond the
+  // device's hardware queues would share a queue, where a stream waiting for
+  // the other stage holds back every launch queued behind it.
+  QbLane Lb = ctx->lane1;
+  Lb.side = La.side2;
+  Lb.side2 = La.side;
   // what both stages read and would otherwise write first: the Gram of Y
   // and, for a core solve, the staged Psi (on the context stream, before
   // the fork)
@@ -1324,9 +1339,17 @@ qsk_status qsketch_finalize_pair(qsk_ctx *ctx, qsk_rangefinder rf_a, double *con
   }
   HIPCHK(ctx, hipEventRecord(ctx->ev_pair_fork, La.stream));
   HIPCHK(ctx, hipStreamWaitEvent(Lb.stream, ctx->ev_pair_fork, 0));
+  // The two stages are launched from two host threads: a stage is about a
+  // hundred short launches, and launched one after the other the second
+  // stage would reach the device only when the host has issued the first.
+  // The optimistic launches write no host state of the context (the Gram
+  // and Psi are ready; a launch failure is recorded under err_mu).
   QbRun run_a, run_b;
+  qsk_status rb_launch = QSK_OK;
+  std::thread tb([&] { rb_launch = qb_enqueue(ctx, Lb, rf_b, Qb, ldqb, Xb, ldxb, true, &run_b); });
   r = qb_enqueue(ctx, La, rf_a, Qa, ldqa, Xa, ldxa, true, &run_a);
-  if (r == QSK_OK) r = qb_enqueue(ctx, Lb, rf_b, Qb, ldqb, Xb, ldxb, true, &run_b);
+  tb.join();
+  if (r == QSK_OK) r = rb_launch;
   // the context stream continues after both stages
   HIPCHK(ctx, hipEventRecord(ctx->ev_pair_join, Lb.stream));
   HIPCHK(ctx, hipStreamWaitEvent(La.stream, ctx->ev_pair_join, 0));
