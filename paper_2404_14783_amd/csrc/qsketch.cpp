@@ -1129,8 +1129,6 @@ static qsk_status qb_enqueue(qsk_ctx *ctx, const QbLane &L, qsk_rangefinder rf, 
                                     ctx->stage.psi, psi_st_type, ctx->stage.MP,
                                     (int64_t)ctx->stage.LP * ctx->stage.MP));
   SmallStatus ps{};
-  SmallStatus *pst = (SmallStatus *)L.work;   // not used concurrently with drivers
-  (void)pst;
   HIPCHK(ctx, qsk::launch_crossprod(st, 0, (const void *const *)pp, l, 0, (const void *const *)pp, l,
                                     l, k, k, L.partials, L.partial_elems, slot(L, k, S_GP)));
   HIPCHK(ctx, qsk::launch_chol_inv(st, slot(L, k, S_GP), k, 0, 0.0, 1e-13, slot(L, k, S_RP),
