@@ -1999,10 +1999,10 @@ __device__ __forceinline__ void tri_step(int j, int k, double *g, qd *P, int o0,
   __syncthreads();
   // (C) every wave forms s_k = beta/2 Re(v^* p) itself (same order, same
   // value), then the rank-2 update of the lower triangle with w = p - s_k v:
-  // G'[a, c] -= v_a conj(w_c) + w_a conj(v_c).  The n (n + 1) / 2 entries,
-  // numbered column by column (column c holds rows c .. n - 1, starting at
-  // c n - c (c - 1) / 2), are dealt to the threads in turn, so that no thread
-  // takes more than one more entry than any other.
+  // G'[a, c] -= v_a conj(w_c) + w_a conj(v_c).  The n (n + 1) / 2 entries
+  // are numbered pair of columns by pair of columns and dealt to the threads
+  // in turn, so that no thread takes more than one more entry than any other
+  // and consecutive threads mostly touch consecutive rows of one column.
   {
     double kl = 0.0;
 #pragma unroll
@@ -2014,8 +2014,13 @@ __device__ __forceinline__ void tri_step(int j, int k, double *g, qd *P, int o0,
       }
     }
     const double sk = 0.5 * beta * wave_sum(kl);
-    const int tot = n * (n + 1) / 2;
-    const double b2 = 2.0 * n + 1.0;
+    // entries dealt by column pairs: pair p holds column p (rows p .. n - 1)
+    // and column n - 1 - p (rows n - 1 - p .. n - 1), n + 1 entries in all
+    // (the middle column of an odd n alone); entry E is (pair E / (n + 1),
+    // offset E mod (n + 1)), so no square root is needed
+    const int np1 = n + 1;
+    const int tot = ((n + 1) >> 1) * np1 - ((n & 1) ? (np1 >> 1) : 0);
+    const float inv = 1.0f / (float)np1;
     // CH entries per thread at a time: their loads go out together, then the
     // updates and stores (a load never waits for the previous entry's store)
     constexpr int CH = 4;
@@ -2028,11 +2033,13 @@ __device__ __forceinline__ void tri_step(int j, int k, double *g, qd *P, int o0,
         const int e = e0 + u * nt;
         int cc = 0, aa = 0;
         if (e < tot) {
-          cc = (int)((b2 - sqrt(b2 * b2 - 8.0 * e)) * 0.5);
-          cc = min(max(cc, 0), n - 1);
-          while (cc > 0 && cc * n - ((cc * (cc - 1)) >> 1) > e) --cc;
-          while (cc + 1 < n && (cc + 1) * n - (((cc + 1) * cc) >> 1) <= e) ++cc;
-          aa = cc + (e - (cc * n - ((cc * (cc - 1)) >> 1)));
+          int pq = (int)((float)e * inv);
+          if (pq * np1 > e) --pq;
+          if ((pq + 1) * np1 <= e) ++pq;
+          const int off = e - pq * np1;
+          const int len1 = n - pq;                 // entries of column pq
+          if (off < len1) { cc = pq; aa = pq + off; }
+          else { cc = n - 1 - pq; aa = cc + (off - len1); }
         }
         ia[u] = aa;
         ic[u] = cc;

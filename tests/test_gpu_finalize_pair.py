@@ -110,3 +110,27 @@ def test_pair_rejects_shared_outputs():
     pair, seq = run_both(sk, ("pseudo_qr", "pseudo_svd"))
     assert_same(pair, seq, "after a rejected call")
     sk.close()
+
+
+def test_pair_one_stage_without_solve():
+    """Xb = NULL: the second stage runs its rangefinder only, the first
+    solves; each matches its own qsketch_finalize call."""
+    import ctypes
+    m, n, k, l = 1500, 400, 16, 33
+    sk = qs.Sketcher(m, n, k, l, seed=9, input_dtype="f32", sketch_dtype="bf16", split_terms=2)
+    a = input_values(synth.lowrank_plus_noise(m, n, torch.tensor(0.6 ** np.arange(10)), 1e-3, 17).numpy(), "f32")
+    sk.update(0, to_device(a, "f32"))
+    qa, xa, ra = sk.finalize("pseudo_svd")
+    qb, _, rb = sk.finalize("pseudo_qr", solve=False)
+    outs = [sk._qb_outputs(None, None, True), sk._qb_outputs(None, None, False)]
+    reps = [qs.QskReport(), qs.QskReport()]
+    st = sk._lib.qsketch_finalize_pair(
+        sk._ctx, qs.RANGEFINDERS["pseudo_svd"], outs[0][2], outs[0][3], outs[0][4], outs[0][5],
+        ctypes.byref(reps[0]), qs.RANGEFINDERS["pseudo_qr"], outs[1][2], outs[1][3], outs[1][4], outs[1][5],
+        ctypes.byref(reps[1]))
+    assert st == 0, sk._lib.qsketch_last_error(sk._ctx)
+    assert outs[1][1] is None
+    assert torch.equal(outs[0][0], qa) and torch.equal(outs[0][1], xa)
+    assert torch.equal(outs[1][0], qb)
+    assert reps[0].as_dict() == ra and reps[1].as_dict() == rb
+    sk.close()
