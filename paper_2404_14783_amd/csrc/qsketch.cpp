@@ -1342,11 +1342,26 @@ qsk_status qsketch_finalize_pair(qsk_ctx *ctx, qsk_rangefinder rf_a, double *con
   // stage would reach the device only when the host has issued the first.
   // The optimistic launches write no host state of the context (the Gram
   // and Psi are ready; a launch failure is recorded under err_mu).
+  // The worker makes the context's device current first (HIP's current
+  // device is per thread); if no thread can be started, the second stage is
+  // launched after the first from this thread.
   QbRun run_a, run_b;
   qsk_status rb_launch = QSK_OK;
-  std::thread tb([&] { rb_launch = qb_enqueue(ctx, Lb, rf_b, Qb, ldqb, Xb, ldxb, true, &run_b); });
+  auto launch_b = [&] {
+    const hipError_t e = hipSetDevice(ctx->device);
+    rb_launch = e == hipSuccess ? qb_enqueue(ctx, Lb, rf_b, Qb, ldqb, Xb, ldxb, true, &run_b)
+                                : hip_fail(ctx, e, "hipSetDevice in the second QB lane");
+  };
+  std::thread tb;
+  bool threaded = true;
+  try {
+    tb = std::thread(launch_b);
+  } catch (...) {
+    threaded = false;
+  }
   r = qb_enqueue(ctx, La, rf_a, Qa, ldqa, Xa, ldxa, true, &run_a);
-  tb.join();
+  if (threaded) tb.join();
+  else launch_b();
   if (r == QSK_OK) r = rb_launch;
   // the context stream continues after both stages
   HIPCHK(ctx, hipEventRecord(ctx->ev_pair_join, Lb.stream));
