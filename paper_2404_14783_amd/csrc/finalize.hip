@@ -2179,8 +2179,43 @@ __device__ __forceinline__ void sm_bisect_sel(const double *d, const double *e, 
   __syncthreads();
 }
 
-__device__ void sm_bisect_all(const double *d, const double *e, int k, double *lam) {
-  sm_bisect_sel(d, e, k, nullptr, k, lam);
+// Eigenvalue i (ascending) of the real symmetric tridiagonal (d, e) by one
+// wave: multisection of the Gershgorin bracket with 64 Sturm counts per
+// round (65 times narrower per round), with the stopping rule of
+// sm_bisect_sel.  Every lane returns the value.
+__device__ double wave_bisect(const double *d, const double *e, int k, int i) {
+  const int lane = threadIdx.x & 63;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int j = lane; j < k; j += 64) {
+    const double r = (j > 0 ? fabs(e[j - 1]) : 0.0) + (j + 1 < k ? fabs(e[j]) : 0.0);
+    lo = fmin(lo, d[j] - r);
+    hi = fmax(hi, d[j] + r);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+  }
+  const double pad = 1e-14 * fmax(fabs(lo), fabs(hi)) + 1e-300;
+  lo -= pad;
+  hi += pad;
+  const double floor_w = 0x1p-106 * fmax(fabs(lo), fabs(hi));
+  for (int it = 0; it < 120; ++it) {
+    const double w = hi - lo;                   // the same in every lane
+    if (w <= 4.0 * 0x1p-53 * fmax(fabs(lo), fabs(hi)) || w <= floor_w) break;
+    const double h = w / 65.0;
+    const double x = lo + (double)(lane + 1) * h;
+    const uint64_t bits = __ballot(sturm_count(d, e, k, x) > i);     // lambda_i < x
+    if (bits == 0ull) {
+      lo = lo + 64.0 * h;
+    } else {
+      const int s = __builtin_ctzll(bits);
+      const double nhi = lo + (double)(s + 1) * h;
+      lo = s > 0 ? lo + (double)s * h : lo;
+      hi = nhi;
+    }
+  }
+  return 0.5 * (lo + hi);
 }
 
 // One vector of cgs2_block: x_i (at xi) loses its components along x_0 ..
@@ -2258,10 +2293,10 @@ __device__ __forceinline__ void cgs2_block(P xs, int k, int c, double *coef, dou
 
 // Full eigendecomposition of the k x k quaternion Hermitian G_L for the
 // pseudo-SVD, as a pipeline of kernels (state in the PsvdLayout arrays):
-//   psvd_eig_kernel      tridiagonalisation and all eigenvalues (bisection),
-//                        one workgroup;
-//   psvd_invit_kernel    eigenvectors of T by inverse iteration, eight per
-//                        workgroup, each lane with its LU factors in LDS;
+//   psvd_eig_kernel      tridiagonalisation, one workgroup;
+//   psvd_invit_kernel    eigenvalues of T by multisection, one wave each,
+//                        then their eigenvectors by inverse iteration, eight
+//                        per workgroup, each lane with its LU factors in LDS;
 //   psvd_orth_kernel     Gram-Schmidt twice inside clusters of eigenvalues
 //                        closer than 1e-3 ||T|| and the diagonal unitary
 //                        scaling, one workgroup;
@@ -2275,10 +2310,9 @@ __global__ __launch_bounds__(1024) void psvd_eig_kernel(PsvdArgs args, GroupRef 
   if (!group_select(args, grp, A, bx, by, bz)) return;
   const int k = A.k;
   const PsvdLayout L(A.work, k);
-  __shared__ double dd[256], ee[256], hb[256], lam[256];
+  __shared__ double dd[256], ee[256], hb[256];
   __shared__ double pool[TRI_POOL];
   sm_tridiag(A.gl, k, dd, ee, pool, L.HV, hb, L.HA);
-  sm_bisect_all(dd, ee, k, lam);
   const int tid = threadIdx.x;
   if (tid == 0) {
     double tn = 0.0;
@@ -2288,7 +2322,6 @@ __global__ __launch_bounds__(1024) void psvd_eig_kernel(PsvdArgs args, GroupRef 
   for (int i = tid; i < k; i += blockDim.x) {
     gpw(L.DD)[i] = dd[i];
     gpw(L.EE)[i] = ee[i];
-    gpw(L.LAM)[i] = lam[i];
     gpw(L.HB)[i] = hb[i];
   }
 }
@@ -2367,22 +2400,33 @@ __device__ void invit_lds(const QSK_LDS double *d, const QSK_LDS double *e, int 
   }
 }
 
-constexpr int INVIT_EPB = 8;          // eigenvectors per workgroup
-__global__ __launch_bounds__(64) void psvd_invit_kernel(PsvdArgs args, GroupRef grp) {
+constexpr int INVIT_EPB = 8;          // eigenpairs per workgroup
+// Eigenvalues INVIT_EPB bx .. + INVIT_EPB - 1 of T, one wave each (written
+// to LAM), then their eigenvectors, one lane of the first wave each.
+__global__ __launch_bounds__(64 * INVIT_EPB) void psvd_invit_kernel(PsvdArgs args, GroupRef grp) {
   PsvdArgs A;
   int bx, by, bz;
   if (!group_select(args, grp, A, bx, by, bz)) return;
   const int k = A.k;
   const PsvdLayout L(A.work, k);
-  __shared__ double sd[256], se[256];
+  __shared__ double sd[256], se[256], slam[INVIT_EPB];
   __shared__ double lu[INVIT_EPB][6][258];     // padded: lanes hit different banks
-  const int lane = threadIdx.x;
-  for (int j = lane; j < k; j += 64) { sd[j] = gp(L.DD)[j]; se[j] = gp(L.EE)[j]; }
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = tid; j < k; j += blockDim.x) { sd[j] = gp(L.DD)[j]; se[j] = gp(L.EE)[j]; }
+  __syncthreads();
+  const int iw = bx * INVIT_EPB + wave;
+  if (iw < k) {                                 // the whole wave
+    const double lv = wave_bisect(sd, se, k, iw);
+    if (lane == 0) {
+      slam[wave] = lv;
+      gpw(L.LAM)[iw] = lv;
+    }
+  }
   __syncthreads();
   const int i = bx * INVIT_EPB + lane;
-  if (lane < INVIT_EPB && i < k) {
+  if (wave == 0 && lane < INVIT_EPB && i < k) {
     QSK_LDS double(*b)[258] = (QSK_LDS double(*)[258])lu[lane];
-    invit_lds((const QSK_LDS double *)sd, (const QSK_LDS double *)se, k, gp(L.LAM)[i], gp(L.TN)[0],
+    invit_lds((const QSK_LDS double *)sd, (const QSK_LDS double *)se, k, slam[lane], gp(L.TN)[0],
               (uint32_t)i, b[0], b[1], b[2], b[3], b[4], b[5]);
     QSK_GLOBAL double *xo = gpw(L.X) + (int64_t)i * k;
     for (int j = 0; j < k; ++j) xo[j] = b[0][j];
@@ -2522,7 +2566,7 @@ hipError_t launch_psvd_stage(hipStream_t st, int stage, const PsvdArgs &a, Group
   const dim3 grid((unsigned)(g.tab ? blocks : psvd_blocks(a.k, stage)));
   switch (stage) {
     case 0: hipLaunchKernelGGL(psvd_eig_kernel, grid, dim3(1024), 0, st, a, g); break;
-    case 1: hipLaunchKernelGGL(psvd_invit_kernel, grid, dim3(64), 0, st, a, g); break;
+    case 1: hipLaunchKernelGGL(psvd_invit_kernel, grid, dim3(64 * INVIT_EPB), 0, st, a, g); break;
     case 2: hipLaunchKernelGGL(psvd_orth_kernel, grid, dim3(1024), 0, st, a, g); break;
     case 3: hipLaunchKernelGGL(psvd_bt_kernel, grid, dim3(64 * BT_COLS), 0, st, a, g); break;
     default: hipLaunchKernelGGL(psvd_finish_kernel, grid, dim3(1024), 0, st, a, g); break;
