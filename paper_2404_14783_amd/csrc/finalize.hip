@@ -2179,11 +2179,39 @@ __device__ __forceinline__ void sm_bisect_sel(const double *d, const double *e, 
   __syncthreads();
 }
 
+// Sturm count of sturm_count with (d, e^2) in LDS (e2[i - 1] = e[i - 1]^2,
+// the product the recurrence forms), four steps per loop trip so that the
+// loads run ahead of the dependent pivot chain.
+__device__ __forceinline__ int sturm_count_lds(const QSK_LDS double *d, const QSK_LDS double *e2, int k,
+                                               double x) {
+  int c = 0;
+  double q = d[0] - x;
+  if (q < 0.0) ++c;
+  int i = 1;
+  for (; i + 3 < k; i += 4) {
+    const double d0 = d[i], d1 = d[i + 1], d2 = d[i + 2], d3 = d[i + 3];
+    const double f0 = e2[i - 1], f1 = e2[i], f2 = e2[i + 1], f3 = e2[i + 2];
+#define QSK_STURM_STEP(DI, FI)                                  \
+    {                                                           \
+      if (fabs(q) < 1e-300) q = q < 0.0 ? -1e-300 : 1e-300;     \
+      double r = __builtin_amdgcn_rcp(q);                       \
+      r = fma(r, fma(-q, r, 1.0), r);                           \
+      q = ((DI) - x) - (FI) * r;                                \
+      if (q < 0.0) ++c;                                         \
+    }
+    QSK_STURM_STEP(d0, f0) QSK_STURM_STEP(d1, f1) QSK_STURM_STEP(d2, f2) QSK_STURM_STEP(d3, f3)
+  }
+  for (; i < k; ++i) QSK_STURM_STEP(d[i], e2[i - 1])
+#undef QSK_STURM_STEP
+  return c;
+}
+
 // Eigenvalue i (ascending) of the real symmetric tridiagonal (d, e) by one
 // wave: multisection of the Gershgorin bracket with 64 Sturm counts per
 // round (65 times narrower per round), with the stopping rule of
-// sm_bisect_sel.  Every lane returns the value.
-__device__ double wave_bisect(const double *d, const double *e, int k, int i) {
+// sm_bisect_sel.  e2 holds e^2.  Every lane returns the value.
+__device__ double wave_bisect(const QSK_LDS double *d, const QSK_LDS double *e, const QSK_LDS double *e2,
+                              int k, int i) {
   const int lane = threadIdx.x & 63;
   double lo = INFINITY, hi = -INFINITY;
   for (int j = lane; j < k; j += 64) {
@@ -2205,7 +2233,7 @@ __device__ double wave_bisect(const double *d, const double *e, int k, int i) {
     if (w <= 4.0 * 0x1p-53 * fmax(fabs(lo), fabs(hi)) || w <= floor_w) break;
     const double h = w / 65.0;
     const double x = lo + (double)(lane + 1) * h;
-    const uint64_t bits = __ballot(sturm_count(d, e, k, x) > i);     // lambda_i < x
+    const uint64_t bits = __ballot(sturm_count_lds(d, e2, k, x) > i);     // lambda_i < x
     if (bits == 0ull) {
       lo = lo + 64.0 * h;
     } else {
@@ -2409,14 +2437,20 @@ __global__ __launch_bounds__(64 * INVIT_EPB) void psvd_invit_kernel(PsvdArgs arg
   if (!group_select(args, grp, A, bx, by, bz)) return;
   const int k = A.k;
   const PsvdLayout L(A.work, k);
-  __shared__ double sd[256], se[256], slam[INVIT_EPB];
+  __shared__ double sd[256], se[256], se2[256], slam[INVIT_EPB];
   __shared__ double lu[INVIT_EPB][6][258];     // padded: lanes hit different banks
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j = tid; j < k; j += blockDim.x) { sd[j] = gp(L.DD)[j]; se[j] = gp(L.EE)[j]; }
+  for (int j = tid; j < k; j += blockDim.x) {
+    const double ej = gp(L.EE)[j];
+    sd[j] = gp(L.DD)[j];
+    se[j] = ej;
+    se2[j] = ej * ej;
+  }
   __syncthreads();
   const int iw = bx * INVIT_EPB + wave;
   if (iw < k) {                                 // the whole wave
-    const double lv = wave_bisect(sd, se, k, iw);
+    const double lv = wave_bisect((const QSK_LDS double *)sd, (const QSK_LDS double *)se,
+                                  (const QSK_LDS double *)se2, k, iw);
     if (lane == 0) {
       slam[wave] = lv;
       gpw(L.LAM)[iw] = lv;
