@@ -254,9 +254,12 @@ qsk_status qsketch_finalize(qsk_ctx *ctx, qsk_rangefinder rf,
    reports and errors as qsketch_finalize(ctx, rf_a, Qa, ...) followed by
    qsketch_finalize(ctx, rf_b, Qb, ...), bit for bit, but the two stages run
    side by side on the device.  Most of a QB stage is k x k work that keeps
-   a few compute units busy, so the second stage runs on a second stream of
-   the context with a workspace of its own (allocated on the first call and
-   kept: two m x k FP64 quaternion buffers and the k x k and l x k scratch).
+   a few compute units busy, so one stage runs on the context stream (a
+   pseudo-QR stage if there is one, else the first) and the other on a
+   second stream of the context with a workspace of its own (allocated on
+   the first call and kept: two m x k FP64 quaternion buffers and the k x k
+   and l x k scratch); results and reports go where the caller's arguments
+   say.
    Each pair (Qa, ldqa, Xa, ldxa) and (Qb, ldqb, Xb, ldxb) is checked as in
    qsketch_finalize; no plane of one result may be a plane of the other
    (QSK_E_ARG).  A stage whose factorisation needs the careful path is run

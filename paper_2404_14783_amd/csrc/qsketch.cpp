@@ -1310,6 +1310,18 @@ qsk_status qsketch_finalize_pair(qsk_ctx *ctx, qsk_rangefinder rf_a, double *con
   if (planes_overlap(Qa, Qb) || planes_overlap(Xa, Xb) || planes_overlap(Qa, Xb) ||
       planes_overlap(Xa, Qb))
     return fail_arg(ctx, "the two results share an output plane");
+  // a pseudo-QR stage goes to the context stream and the calling thread:
+  // its early kappa of H0 and later kappa of Q then share the side streams
+  // with a pseudo-SVD stage's late kappa of Q as arranged below (the other
+  // way round the pair took 4.5 instead of 4.0 ms at m = 20000, k = 100)
+  if (rf_a != QSK_PSEUDO_QR && rf_b == QSK_PSEUDO_QR) {
+    std::swap(rf_a, rf_b);
+    std::swap(Qa, Qb);
+    std::swap(ldqa, ldqb);
+    std::swap(Xa, Xb);
+    std::swap(ldxa, ldxb);
+    std::swap(report_a, report_b);
+  }
   r = alloc_lane1(ctx);
   if (r == QSK_OK) r = qb_prepare(ctx);
   if (r != QSK_OK) return r;
