@@ -2323,7 +2323,7 @@ __device__ __forceinline__ void cgs2_block(P xs, int k, int c, double *coef, dou
 // pseudo-SVD, as a pipeline of kernels (state in the PsvdLayout arrays):
 //   psvd_eig_kernel      tridiagonalisation, one workgroup;
 //   psvd_invit_kernel    eigenvalues of T by multisection, one wave each,
-//                        then their eigenvectors by inverse iteration, eight
+//                        then their eigenvectors by inverse iteration, four
 //                        per workgroup, each lane with its LU factors in LDS;
 //   psvd_orth_kernel     Gram-Schmidt twice inside clusters of eigenvalues
 //                        closer than 1e-3 ||T|| and the diagonal unitary
@@ -2428,7 +2428,7 @@ __device__ void invit_lds(const QSK_LDS double *d, const QSK_LDS double *e, int 
   }
 }
 
-constexpr int INVIT_EPB = 8;          // eigenpairs per workgroup
+constexpr int INVIT_EPB = 4;          // eigenpairs per workgroup
 // Eigenvalues INVIT_EPB bx .. + INVIT_EPB - 1 of T, one wave each (written
 // to LAM), then their eigenvectors, one lane of the first wave each.
 __global__ __launch_bounds__(64 * INVIT_EPB) void psvd_invit_kernel(PsvdArgs args, GroupRef grp) {
